@@ -1,0 +1,195 @@
+/* libl0l2 — MI355X (gfx950) library for the node relaxations of the l0-l2
+ * branch-and-bound method of arXiv 2602.04551 ("A GPU-accelerated Nonlinear
+ * Branch-and-Bound Framework for Sparse Linear Models").
+ *
+ * Problem (eq. original, Sec. 1):   min_beta 1/2 ||y - X beta||^2 + lambda0 ||beta||_0
+ *                                              + lambda2 ||beta||_2^2
+ * in its perspective big-M form (eq. perspective, Sec. 2.1) with box |beta_i| <= M.
+ * A BnB node is a pair (F0, F1) of coordinates fixed to z = 0 / z = 1 (Sec. 2.2);
+ * its interval relaxation (eq. relaxnode / relaxnode2, Sec. 3.1) is solved by
+ * ADMM (eq. admm-update), bounded from below by the dual of Prop. 1 (Sec. 3.1.2),
+ * and rounded into an incumbent refined by the fast proximal gradient method of
+ * Sec. 3.3-3.4.
+ *
+ * Conventions for every entry point:
+ *  - Return value: 0 (L0L2_OK) on success, a negative L0L2_E_* code on failure.
+ *    No entry point throws, aborts or exits; l0l2_last_error() gives a message.
+ *  - Matrices are dense.  X is column-major n x p (element (i, j) at X[i + j*n]).
+ *    Per-node arrays are node-major: row k of a K x p array holds node k.
+ *  - Fixing codes are one byte per coordinate: L0L2_FREE, L0L2_FIX0 (z = 0,
+ *    coordinate in F0) or L0L2_FIX1 (z = 1, coordinate in F1).
+ *  - "Device" buffers are caller-owned GPU memory on the context's device; the
+ *    library reads and writes them on the context's stream and never frees them.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef L0L2_H
+#define L0L2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    L0L2_OK = 0,
+    L0L2_E_INVALID = -1,     /* bad argument (shape, NaN/Inf input, out-of-range option) */
+    L0L2_E_NODATA = -2,      /* l0l2_set_data has not been called on this context */
+    L0L2_E_OOM = -3,         /* device memory allocation failed */
+    L0L2_E_DEVICE = -4,      /* a HIP runtime call failed */
+    L0L2_E_NUMERIC = -5,     /* factorisation failed (matrix not positive definite) */
+    L0L2_E_TIMEOUT = -6,     /* time limit reached before certification */
+    L0L2_E_UNSUPPORTED = -8  /* option not available in this build */
+};
+
+/* Precision of the X products inside the ADMM sweep.  FP64: everything in FP64.
+ * FP32: products and node state in FP32.  BF16: the transformed design matrix is
+ * stored in BF16, the node operand is split into two BF16 halves, accumulation
+ * and node state are FP32.  In every mode the dual bound and the incumbent
+ * objective are computed in FP64 with the original X. */
+enum { L0L2_FP64 = 0, L0L2_FP32 = 1, L0L2_BF16 = 2 };
+
+enum { L0L2_FREE = 0, L0L2_FIX0 = 1, L0L2_FIX1 = 2 };
+
+typedef struct l0l2_ctx l0l2_ctx;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t (NULL
+ * = the device's null stream) on which all work of this context is issued. */
+int l0l2_create(int device, void *hip_stream, l0l2_ctx **out);
+void l0l2_destroy(l0l2_ctx *ctx);
+/* Message of the last failed call on ctx (empty string if none); valid until the
+ * next call on ctx.  ctx may be NULL (then: message of the last failed create). */
+const char *l0l2_last_error(const l0l2_ctx *ctx);
+/* Size of the state element for the current precision: 8 (FP64) or 4. */
+int l0l2_state_bytes(const l0l2_ctx *ctx);
+
+/* Load one instance and precompute what the whole tree shares (Sec. 3.1.1:
+ * c = X^T y and the factor behind D = (X^T X + rho I)^{-1}, computed once for
+ * the entire tree).  X (n x p column-major FP64) and y (n FP64) are host
+ * pointers when ptrs_on_device == 0, device pointers otherwise; the library
+ * copies them and the caller keeps ownership.  Requires n, p >= 1, finite
+ * X and y, lambda0 >= 0, lambda2 > 0, M > 0 (INFINITY allowed), rho > 0.
+ * x_precision is one of L0L2_FP64, L0L2_FP32, L0L2_BF16.  Replaces any
+ * previous instance on ctx. */
+int l0l2_set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p,
+                  double lambda0, double lambda2, double M, double rho,
+                  int x_precision, int ptrs_on_device);
+
+typedef struct {
+    double tol_node;   /* stop a node when (P(beta) - LB) / |P(beta)| <= tol_node */
+    int max_iter;      /* ADMM sweeps per node (>= 1) */
+    int check_every;   /* the gap is evaluated every check_every sweeps and at max_iter */
+} l0l2_admm_opts;
+
+/* Run exactly `sweeps` ADMM sweeps (eq. admm-update) on K nodes, without gap
+ * checks.  codes: device, K x p uint8.  beta, v: device, K x p state elements
+ * (double for FP64, float otherwise), read as the start and overwritten with
+ * the result; b_out: device, K x p state elements, receives the last b.  The
+ * F0 fixings are imposed on beta before the first sweep (Sec. 3.1.3). */
+int l0l2_admm_sweeps(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta, void *v,
+                     void *b_out, int sweeps);
+
+/* Rigorous dual lower bound (Prop. 1, eq. dual) of K nodes at r = y - X b:
+ * evaluated in FP64 with the original X and lowered by an a-priori bound on
+ * its rounding error, so that lb[k] <= the exact dual value at that r, which
+ * is <= the node's relaxation value.  codes: device K x p; b: device K x p
+ * state elements; lb: device K doubles. */
+int l0l2_dual_bound(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *b, double *lb);
+
+/* Solve K node relaxations by ADMM from the warm starts (beta, v) (device, K x p
+ * state elements, overwritten with the final iterates).  Outputs (device, K each):
+ * lb = rigorous bound of the last gap check, primal = P(beta) of eq. relaxnode2
+ * in FP64, iters = sweeps done, status = 0 converged / 1 reached max_iter. */
+int l0l2_solve_node_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta, void *v,
+                          const l0l2_admm_opts *opts, double *lb, double *primal,
+                          int32_t *iters, int32_t *status);
+
+/* Rounding and branching for K nodes (Sec. 3.3; branching rule: most fractional
+ * z_j, score floored to a 2^-20 grid, ties to the smallest index; when all free
+ * scores are 0, the free index of largest |beta_j|).  z_j follows App. A.1.
+ * Outputs (device): support (K x p uint8, S = F1 u {free j : z_j >= 1/2}),
+ * support_size (K), branch_j (K, -1 when no coordinate is free), z_up (K,
+ * 1 when z at branch_j >= 1/2). */
+int l0l2_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *beta,
+                      uint8_t *support, int32_t *support_size, int32_t *branch_j,
+                      int32_t *z_up);
+
+typedef struct {
+    double tol;        /* stop when |U(beta+) - U(beta)| <= tol * max(1, U(beta+)) */
+    int max_iter;      /* outer iterations */
+} l0l2_fista_opts;
+
+/* Incumbent refinement (eqs. fpg_extrapolate .. fpg_armijo, batched as in
+ * Sec. 3.4) of K supports in FP64.  support: device K x p uint8 (0/1).
+ * beta_start: device K x p state elements (the node iterates; only entries on
+ * the support are read).  beta_out: device K x p doubles, receives the refined
+ * coefficients, zero off the support (may alias beta_start in FP64 mode).
+ * obj: device K doubles, F(S, beta) = 1/2||y - X_S beta_S||^2 + lambda2
+ * ||beta_S||^2 + lambda0 |S|.  iters: device K int32 (may be NULL). */
+int l0l2_refine_incumbent(l0l2_ctx *ctx, int K, const uint8_t *support, const void *beta_start,
+                          double *beta_out, const l0l2_fista_opts *opts, double *obj, int32_t *iters);
+
+/* Objective of one support solved to full FP64 accuracy (box-constrained ridge
+ * on S; used for the certified value of the final incumbent).  support and
+ * beta_out (p doubles) are host pointers. */
+int l0l2_exact_objective(l0l2_ctx *ctx, const uint8_t *support, double *beta_out, double *obj);
+
+enum { L0L2_BEST_FIRST = 0, L0L2_DFS = 1 };
+
+typedef struct {
+    int64_t id, parent;
+    int32_t depth, branch_j, decision, iters;   /* decision: 0 branched, 1 pruned after its
+                                                   solve, 2 leaf, 3 pruned at selection */
+    int32_t support_size, admm_status;
+    double lb, primal, ub_node, ub_global;
+} l0l2_trace_rec;
+
+typedef struct {
+    int K;                 /* nodes per batch (Alg. 1) */
+    int policy;            /* L0L2_BEST_FIRST or L0L2_DFS */
+    double eps_prune;      /* prune when LB >= UB (1 - eps_prune) */
+    double gap_tol;        /* stop when (UB - LB) / UB <= gap_tol; 0 runs to exhaustion */
+    double time_limit_s;   /* <= 0: none */
+    int64_t max_nodes;     /* node solves budget */
+    int max_iter_root;     /* ADMM sweeps at the root */
+    l0l2_admm_opts admm;
+    l0l2_fista_opts fista;
+    l0l2_trace_rec *trace; /* optional host buffer of trace_cap records (NULL: none) */
+    int64_t trace_cap;
+} l0l2_bnb_opts;
+
+typedef struct {
+    double ub;             /* incumbent objective from the node refinements */
+    double certified;      /* F of the incumbent support solved exactly */
+    double lb;             /* global lower bound at exit (= ub when exhausted) */
+    int64_t nodes_solved, nodes_pruned, trace_len, batches;
+    double seconds;
+    int status;            /* 0 exhausted (certified), 1 node budget, 2 gap_tol, 3 time limit */
+    int64_t support_len;
+    int32_t *support;      /* library-owned until l0l2_result_free */
+    double *beta;          /* p entries, library-owned until l0l2_result_free */
+} l0l2_bnb_result;
+
+/* Branch and bound of Alg. 1 on the instance of ctx, to certification when
+ * gap_tol = 0.  Node relaxations, rounding, branching and refinement run on the
+ * GPU in batches of K; the host keeps the frontier (best-first by (LB, id), or
+ * LIFO), the incumbent and the pruning decisions.  Fills *out. */
+int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *out);
+void l0l2_result_free(l0l2_bnb_result *res);
+
+/* Opt-in timing of the library's kernels with HIP events recorded on the
+ * context stream around each launch (adds one event pair per launch).
+ * l0l2_profile_enable clears the counters and switches timing on (1) or off (0).
+ * l0l2_profile_query returns the number of timed launches and their summed
+ * duration in milliseconds for one kernel family: "gemm_xw" (contraction over
+ * p of a sweep), "admm_xtu" (contraction over n with the prox/V epilogue),
+ * "gap_check" (the FP64 gap evaluation, all of its kernels), "round_branch",
+ * "fista".  Unknown names give L0L2_E_INVALID. */
+int l0l2_profile_enable(l0l2_ctx *ctx, int enable);
+int l0l2_profile_query(l0l2_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,258 @@
+"""ctypes binding of libl0l2 (include/l0l2.h).
+
+Argument marshalling only: every step runs in the HIP library.  torch provides
+device memory (tensors on cuda:N) and the stream; nothing here computes the
+method.  Importing this module raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libl0l2.so")
+
+L0L2_OK, L0L2_E_INVALID, L0L2_E_NODATA, L0L2_E_OOM = 0, -1, -2, -3
+L0L2_E_DEVICE, L0L2_E_NUMERIC, L0L2_E_TIMEOUT, L0L2_E_UNSUPPORTED = -4, -5, -6, -8
+L0L2_FP64, L0L2_FP32, L0L2_BF16 = 0, 1, 2
+L0L2_FREE, L0L2_FIX0, L0L2_FIX1 = 0, 1, 2
+L0L2_BEST_FIRST, L0L2_DFS = 0, 1
+PRECISIONS = {"fp64": L0L2_FP64, "fp32": L0L2_FP32, "bf16": L0L2_BF16}
+
+
+class l0l2_admm_opts(C.Structure):
+    _fields_ = [("tol_node", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int)]
+
+
+class l0l2_fista_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int)]
+
+
+class l0l2_trace_rec(C.Structure):
+    _fields_ = [("id", C.c_int64), ("parent", C.c_int64), ("depth", C.c_int32),
+                ("branch_j", C.c_int32), ("decision", C.c_int32), ("iters", C.c_int32),
+                ("support_size", C.c_int32), ("admm_status", C.c_int32),
+                ("lb", C.c_double), ("primal", C.c_double), ("ub_node", C.c_double),
+                ("ub_global", C.c_double)]
+
+
+class l0l2_bnb_opts(C.Structure):
+    _fields_ = [("K", C.c_int), ("policy", C.c_int), ("eps_prune", C.c_double),
+                ("gap_tol", C.c_double), ("time_limit_s", C.c_double), ("max_nodes", C.c_int64),
+                ("max_iter_root", C.c_int), ("admm", l0l2_admm_opts), ("fista", l0l2_fista_opts),
+                ("trace", C.POINTER(l0l2_trace_rec)), ("trace_cap", C.c_int64)]
+
+
+class l0l2_bnb_result(C.Structure):
+    _fields_ = [("ub", C.c_double), ("certified", C.c_double), ("lb", C.c_double),
+                ("nodes_solved", C.c_int64), ("nodes_pruned", C.c_int64), ("trace_len", C.c_int64),
+                ("batches", C.c_int64), ("seconds", C.c_double), ("status", C.c_int),
+                ("support_len", C.c_int64), ("support", C.POINTER(C.c_int32)),
+                ("beta", C.POINTER(C.c_double))]
+
+
+_vp, _i, _i64, _d = C.c_void_p, C.c_int, C.c_int64, C.c_double
+SIGNATURES = {
+    "l0l2_create": (_i, [_i, _vp, C.POINTER(_vp)]),
+    "l0l2_destroy": (None, [_vp]),
+    "l0l2_last_error": (C.c_char_p, [_vp]),
+    "l0l2_state_bytes": (_i, [_vp]),
+    "l0l2_set_data": (_i, [_vp, _vp, _vp, _i64, _i64, _d, _d, _d, _d, _i, _i]),
+    "l0l2_admm_sweeps": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _i]),
+    "l0l2_dual_bound": (_i, [_vp, _i, _vp, _vp, _vp]),
+    "l0l2_solve_node_batch": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_admm_opts), _vp, _vp, _vp, _vp]),
+    "l0l2_round_branch": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "l0l2_refine_incumbent": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_fista_opts), _vp, _vp]),
+    "l0l2_exact_objective": (_i, [_vp, _vp, _vp, _vp]),
+    "l0l2_bnb_solve": (_i, [_vp, C.POINTER(l0l2_bnb_opts), C.POINTER(l0l2_bnb_result)]),
+    "l0l2_result_free": (None, [C.POINTER(l0l2_bnb_result)]),
+    "l0l2_profile_enable": (_i, [_vp, _i]),
+    "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d)]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libl0l2 is not built ({path} missing): run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = load_library()
+
+
+class L0L2Error(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libl0l2 error {code}: {msg}")
+        self.code = code
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Context:
+    """One l0l2_ctx on one device and stream.  Device buffers are torch tensors."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.device = device
+        self.torch_device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.torch_device)
+        self.stream = stream
+        h = C.c_void_p()
+        rc = lib.l0l2_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, lib.l0l2_last_error(None).decode())
+        self._h = h
+        self.n = self.p = 0
+        self.precision = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.l0l2_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, lib.l0l2_last_error(self._h).decode())
+
+    # -- instance ---------------------------------------------------------
+    def set_data(self, X, y, lambda0, lambda2, M, rho=1.0, precision="fp64"):
+        X = np.asfortranarray(X, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        n, p = X.shape
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self._check(lib.l0l2_set_data(self._h, X.ctypes.data, y.ctypes.data, n, p, float(lambda0),
+                                      float(lambda2), float(M), float(rho), prec, 0))
+        self.n, self.p, self.precision = n, p, prec
+        self.lambda0, self.lambda2, self.M, self.rho = lambda0, lambda2, M, rho
+
+    @property
+    def state_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.precision == L0L2_FP64 else torch.float32
+
+    def _dev(self, a, dtype):
+        torch = _torch()
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(np.ascontiguousarray(a))
+        return a.to(device=self.torch_device, dtype=dtype).contiguous()
+
+    # -- hot-path entry points ---------------------------------------------
+    def admm_sweeps(self, codes, beta, v, sweeps):
+        torch = _torch()
+        codes = self._dev(codes, torch.uint8)
+        K = codes.shape[0]
+        beta = self._dev(beta, self.state_dtype).clone()
+        v = self._dev(v, self.state_dtype).clone()
+        b = torch.empty_like(beta)
+        self._check(lib.l0l2_admm_sweeps(self._h, K, _ptr(codes), _ptr(beta), _ptr(v), _ptr(b), int(sweeps)))
+        return beta, v, b
+
+    def dual_bound(self, codes, b):
+        torch = _torch()
+        codes = self._dev(codes, torch.uint8)
+        K = codes.shape[0]
+        b = self._dev(b, self.state_dtype)
+        lb = torch.empty(K, dtype=torch.float64, device=self.torch_device)
+        self._check(lib.l0l2_dual_bound(self._h, K, _ptr(codes), _ptr(b), _ptr(lb)))
+        return lb
+
+    def solve_node_batch(self, codes, beta=None, v=None, tol_node=1e-6, max_iter=2000, check_every=10):
+        torch = _torch()
+        codes = self._dev(codes, torch.uint8)
+        K = codes.shape[0]
+        dt = self.state_dtype
+        beta = torch.zeros((K, self.p), dtype=dt, device=self.torch_device) if beta is None else self._dev(beta, dt).clone()
+        v = torch.zeros((K, self.p), dtype=dt, device=self.torch_device) if v is None else self._dev(v, dt).clone()
+        lb = torch.empty(K, dtype=torch.float64, device=self.torch_device)
+        primal = torch.empty_like(lb)
+        iters = torch.empty(K, dtype=torch.int32, device=self.torch_device)
+        status = torch.empty_like(iters)
+        o = l0l2_admm_opts(float(tol_node), int(max_iter), int(check_every))
+        self._check(lib.l0l2_solve_node_batch(self._h, K, _ptr(codes), _ptr(beta), _ptr(v), C.byref(o),
+                                              _ptr(lb), _ptr(primal), _ptr(iters), _ptr(status)))
+        return dict(lb=lb, primal=primal, iters=iters, status=status, beta=beta, v=v)
+
+    def round_branch(self, codes, beta):
+        torch = _torch()
+        codes = self._dev(codes, torch.uint8)
+        K = codes.shape[0]
+        beta = self._dev(beta, self.state_dtype)
+        sup = torch.empty((K, self.p), dtype=torch.uint8, device=self.torch_device)
+        ss = torch.empty(K, dtype=torch.int32, device=self.torch_device)
+        bj = torch.empty_like(ss)
+        zu = torch.empty_like(ss)
+        self._check(lib.l0l2_round_branch(self._h, K, _ptr(codes), _ptr(beta), _ptr(sup), _ptr(ss), _ptr(bj), _ptr(zu)))
+        return dict(support=sup, support_size=ss, branch_j=bj, z_up=zu)
+
+    def refine_incumbent(self, support, beta_start, tol=1e-12, max_iter=1000):
+        torch = _torch()
+        support = self._dev(support, torch.uint8)
+        K = support.shape[0]
+        start = self._dev(beta_start, self.state_dtype)
+        beta = torch.empty((K, self.p), dtype=torch.float64, device=self.torch_device)
+        obj = torch.empty(K, dtype=torch.float64, device=self.torch_device)
+        iters = torch.empty(K, dtype=torch.int32, device=self.torch_device)
+        o = l0l2_fista_opts(float(tol), int(max_iter))
+        self._check(lib.l0l2_refine_incumbent(self._h, K, _ptr(support), _ptr(start), _ptr(beta), C.byref(o),
+                                              _ptr(obj), _ptr(iters)))
+        return obj, beta, iters
+
+    def exact_objective(self, mask):
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        beta = np.zeros(self.p)
+        obj = C.c_double()
+        self._check(lib.l0l2_exact_objective(self._h, mask.ctypes.data, beta.ctypes.data, C.byref(obj)))
+        return obj.value, beta
+
+    def profile_enable(self, enable=True):
+        self._check(lib.l0l2_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_query(self, kernel):
+        n, ms = C.c_int64(), C.c_double()
+        self._check(lib.l0l2_profile_query(self._h, kernel.encode(), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    def bnb_solve(self, K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000,
+                  check_every=10, eps_prune=None, gap_tol=0.0, time_limit_s=0.0, max_nodes=10**9,
+                  fista_tol=1e-12, fista_max_iter=1000, trace_cap=0):
+        if eps_prune is None:
+            eps_prune = 2.0 * tol_node
+        tr = (l0l2_trace_rec * max(trace_cap, 1))()
+        o = l0l2_bnb_opts(int(K), L0L2_DFS if policy == "dfs" else L0L2_BEST_FIRST, float(eps_prune),
+                          float(gap_tol), float(time_limit_s), int(max_nodes), int(max_iter_root),
+                          l0l2_admm_opts(float(tol_node), int(max_iter), int(check_every)),
+                          l0l2_fista_opts(float(fista_tol), int(fista_max_iter)),
+                          tr if trace_cap > 0 else None, int(trace_cap))
+        r = l0l2_bnb_result()
+        self._check(lib.l0l2_bnb_solve(self._h, C.byref(o), C.byref(r)))
+        try:
+            support = np.array([r.support[i] for i in range(r.support_len)], dtype=np.int64)
+            beta = np.ctypeslib.as_array(r.beta, shape=(self.p,)).copy()
+        finally:
+            lib.l0l2_result_free(C.byref(r))
+        n_tr = min(r.trace_len, trace_cap)
+        trace = [{f: getattr(tr[i], f) for f, _ in l0l2_trace_rec._fields_} for i in range(n_tr)]
+        return dict(ub=r.ub, certified=r.certified, lb=r.lb, nodes_solved=r.nodes_solved,
+                    nodes_pruned=r.nodes_pruned, batches=r.batches, seconds=r.seconds, status=r.status,
+                    support=support, beta=beta, trace=trace)

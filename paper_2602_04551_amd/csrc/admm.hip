@@ -1,0 +1,633 @@
+// Batched ADMM for the node relaxations (Sec. 3.1 and 3.2).
+//
+// One sweep over K nodes, in the folded Woodbury form with Xh = L^{-1} X:
+//   W  = c + rho beta - V                       (formed by the previous epilogue)
+//   U  = Xh W^T                 (n x K)        contraction over p   [k_gemm_xw]
+//   Q  = Xh^T U                 (p x K)        contraction over n   [k_admm_xtu]
+//   b  = (W - Q^T) / rho        = D w row by row (eq. batched_b_update)
+//   beta = prox(b + V / rho)    (eq. minbetalower / batched_beta_update)
+//   V  = V + rho (b - beta)     (eq. batched_v_update)
+//   W' = c + rho beta - V       for the next sweep
+// The prox/V/W update is the epilogue of the second contraction, so the K x p
+// state is read and written once per sweep.
+//
+// Every check_every sweeps the relative gap (P(beta) - LB) / |P(beta)| is
+// evaluated in FP64 with the original X (Sec. 3.1.2 and the node stopping rule
+// of Sec. 4.1): r = y - X b, g = X^T r, LB = rigorous D(r); P(beta) from X beta.
+#include <algorithm>
+#include <cmath>
+
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace l0l2 {
+
+namespace {
+
+template <class T>
+DevParams<T> dev_params(const MethodParams &m) {
+    DevParams<T> q;
+    q.M = (T)m.M;
+    q.rho = (T)m.rho;
+    q.inv_rho_dummy = T(0);
+    q.a_plus_s = (T)m.a_plus_s;
+    q.ridge = (T)m.ridge;
+    q.thr_free = (T)m.thr_free;
+    q.thr_free_M = (T)m.thr_free_M;
+    q.free_quad = m.free_quad;
+    return q;
+}
+
+// ---------------------------------------------------------------------------
+// batch load / store
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void k_load_state(const T *__restrict__ src, int64_t K, int64_t p, T *__restrict__ dst, int64_t Kp,
+                             int64_t pp) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < Kp * pp; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = idx / pp, j = idx % pp;
+        dst[idx] = (k < K && j < p) ? src[k * p + j] : T(0);
+    }
+}
+
+__global__ void k_load_codes(const uint8_t *__restrict__ src, int64_t K, int64_t p, uint8_t *__restrict__ dst,
+                             int64_t Kp, int64_t pp) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < Kp * pp; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = idx / pp, j = idx % pp;
+        dst[idx] = (k < K && j < p) ? src[k * p + j] : (uint8_t)CODE_FIX0;
+    }
+}
+
+template <class T>
+__global__ void k_store_state(const T *__restrict__ src, int64_t K, int64_t p, int64_t pp, T *__restrict__ dst) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < K * p; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = idx / p, j = idx % p;
+        dst[idx] = src[k * pp + j];
+    }
+}
+
+__global__ void k_set_active(int *active, int *status, int *iters, int64_t K, int64_t Kp) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < Kp) {
+        active[k] = k < K;
+        status[k] = 1;
+        iters[k] = 0;
+    }
+}
+
+// Warm start of Sec. 3.1.3: impose F0 on beta, then W = c + rho beta - V.
+template <class T>
+__global__ void k_init(const uint8_t *__restrict__ codes, T *__restrict__ beta, const T *__restrict__ V,
+                       T *__restrict__ W, const T *__restrict__ c, T rho, int64_t pp, int64_t total) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t j = idx % pp;
+        T b = codes[idx] == CODE_FIX0 ? T(0) : beta[idx];
+        beta[idx] = b;
+        W[idx] = c[j] + rho * b - V[idx];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Cross-wave reduction of a 32 x 32 tile held as 2 x 2 MFMA blocks per wave.
+// red: 4 * 1024 elements of LDS; element (m, n) of wave w at red[w*1024 + n*32 + m].
+// ---------------------------------------------------------------------------
+template <class TC>
+__device__ __forceinline__ void tile_to_lds(const typename Acc<TC>::type acc[2][2], TC *red, int w, int lane) {
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int v = 0; v < 4; ++v) {
+                int m = a * 16 + acc_row<TC>(lane, v);
+                int n = b * 16 + (lane & 15);
+                red[w * 1024 + n * 32 + m] = acc[a][b][v];
+            }
+}
+
+template <class TC>
+__device__ __forceinline__ TC tile_sum(const TC *red, int idx) {
+    return red[idx] + red[1024 + idx] + red[2048 + idx] + red[3072 + idx];
+}
+
+template <class TC> __device__ __forceinline__ TC cvt(float x) { return (TC)x; }
+
+// ---------------------------------------------------------------------------
+// Contraction over p:  U[k][i] = sum_j A[i + j*lda] * B[k*ldb + j]
+// A column-major (np x pp), B node-major, U node-major (ldu).  32 x 32 output
+// tile per workgroup; the 4 waves split the contraction range in quarters.
+// Lane l of a wave reads 4 consecutive j of one node row (one vector load) and
+// the matching 4 columns of A; the 4 MFMAs of a 16-wide chunk take slot l/16 as
+// j = j0 + 4 (l/16) + t for both operands.
+// ---------------------------------------------------------------------------
+template <class TA, class TB, class TC>
+__global__ __launch_bounds__(256) void k_gemm_xw(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B,
+                                                 int64_t ldb, TC *__restrict__ U, int64_t ldu, int64_t kdim) {
+    __shared__ TC red[4 * 1024];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int q = lane >> 4, r = lane & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    typedef typename Acc<TC>::type AccT;
+    AccT acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+    const int64_t kq = kdim / 4;
+    const int64_t kb = w * kq, ke = kb + kq;
+    const TA *Ab = A + m0 + r;
+    const TB *B0 = B + (n0 + r) * ldb + 4 * q;
+    const TB *B1 = B + (n0 + 16 + r) * ldb + 4 * q;
+    for (int64_t j0 = kb; j0 < ke; j0 += 16) {
+        TB bv0[4], bv1[4];
+        load4(B0 + j0, bv0);
+        load4(B1 + j0, bv1);
+        TA av[2][4];
+        for (int t = 0; t < 4; ++t) {
+            const TA *col = Ab + (j0 + 4 * q + t) * lda;
+            av[0][t] = col[0];
+            av[1][t] = col[16];
+        }
+        for (int t = 0; t < 4; ++t) {
+            TC b0 = (TC)bv0[t], b1 = (TC)bv1[t];
+            TC a0 = (TC)av[0][t], a1 = (TC)av[1][t];
+            acc[0][0] = mfma16(a0, b0, acc[0][0]);
+            acc[0][1] = mfma16(a0, b1, acc[0][1]);
+            acc[1][0] = mfma16(a1, b0, acc[1][0]);
+            acc[1][1] = mfma16(a1, b1, acc[1][1]);
+        }
+    }
+    tile_to_lds<TC>(acc, red, w, lane);
+    __syncthreads();
+    for (int e = 0; e < 4; ++e) {
+        int idx = tid + 256 * e;
+        int n = idx >> 5, m = idx & 31;
+        U[(n0 + n) * ldu + m0 + m] = tile_sum<TC>(red, idx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Contraction over n with the ADMM epilogue:
+//   Q[k][j] = sum_i A[i + j*lda] * U[k*ldu + i], then b, beta, V, W of node k,
+//   coordinate j.  Lane l reads 4 consecutive i of column j (A) and of node row k
+//   (U); slot l/16 of the 4 MFMAs is i = i0 + 4 (l/16) + t for both.
+// ---------------------------------------------------------------------------
+template <class TA, class T>
+__global__ __launch_bounds__(256) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
+                                                  int64_t ldu, int64_t kdim, T *__restrict__ W,
+                                                  T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
+                                                  const uint8_t *__restrict__ codes, const T *__restrict__ c,
+                                                  const int *__restrict__ active, DevParams<T> q, int64_t ldp,
+                                                  int store_b) {
+    __shared__ T red[4 * 1024];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int qq = lane >> 4, r = lane & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    typedef typename Acc<T>::type AccT;
+    AccT acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
+    const int64_t kq = kdim / 4;
+    const int64_t ib = w * kq, ie = ib + kq;
+    const TA *A0 = A + (m0 + r) * lda + 4 * qq;
+    const TA *A1 = A + (m0 + 16 + r) * lda + 4 * qq;
+    const T *U0 = U + (n0 + r) * ldu + 4 * qq;
+    const T *U1 = U + (n0 + 16 + r) * ldu + 4 * qq;
+    for (int64_t i0 = ib; i0 < ie; i0 += 16) {
+        TA a0[4], a1[4];
+        T u0[4], u1[4];
+        load4(A0 + i0, a0);
+        load4(A1 + i0, a1);
+        load4(U0 + i0, u0);
+        load4(U1 + i0, u1);
+        for (int t = 0; t < 4; ++t) {
+            T x0 = (T)a0[t], x1 = (T)a1[t];
+            acc[0][0] = mfma16(x0, u0[t], acc[0][0]);
+            acc[0][1] = mfma16(x0, u1[t], acc[0][1]);
+            acc[1][0] = mfma16(x1, u0[t], acc[1][0]);
+            acc[1][1] = mfma16(x1, u1[t], acc[1][1]);
+        }
+    }
+    tile_to_lds<T>(acc, red, w, lane);
+    __syncthreads();
+    for (int e = 0; e < 4; ++e) {
+        int idx = tid + 256 * e;
+        int n = idx >> 5, m = idx & 31;
+        int64_t node = n0 + n, j = m0 + m;
+        if (!active[node]) continue;
+        T Qv = tile_sum<T>(red, idx);
+        int64_t o = node * ldp + j;
+        T wv = W[o];
+        T bb = (wv - Qv) / q.rho;
+        T v = V[o];
+        T bt = bb + v / q.rho;
+        T be = prox_beta(bt, codes[o], q);
+        T vn = v + q.rho * (bb - be);
+        beta[o] = be;
+        V[o] = vn;
+        W[o] = c[j] + q.rho * be - vn;
+        if (store_b) Bst[o] = bb;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Gap check (FP64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = sh[0] + sh[1] + sh[2] + sh[3];
+    return s;
+}
+
+// Per node k (one workgroup): r = y - Ub[k], rb = y - Ubeta[k]; sums
+// ||r||^2, y^T r, |y|^T |r|, ||rb||^2.  R[k] receives r.
+__global__ __launch_bounds__(256) void k_resid(const double *__restrict__ y, const double *__restrict__ Ub,
+                                               const double *__restrict__ Ubeta, double *__restrict__ R, int64_t np,
+                                               double *__restrict__ nodescal, const int *__restrict__ active,
+                                               int with_beta) {
+    __shared__ double sh[4];
+    const int64_t k = blockIdx.x;
+    if (!active[k]) return;
+    double rr = 0, yr = 0, ayr = 0, bb = 0;
+    for (int64_t i = threadIdx.x; i < np; i += 256) {
+        double yi = y[i];
+        double rv = yi - Ub[k * np + i];
+        R[k * np + i] = rv;
+        rr += rv * rv;
+        yr += yi * rv;
+        ayr += fabs(yi) * fabs(rv);
+        if (with_beta) {
+            double rb = yi - Ubeta[k * np + i];
+            bb += rb * rb;
+        }
+    }
+    rr = block_sum(rr, sh);
+    yr = block_sum(yr, sh);
+    ayr = block_sum(ayr, sh);
+    bb = block_sum(bb, sh);
+    if (threadIdx.x == 0) {
+        nodescal[k * 8 + 0] = rr;
+        nodescal[k * 8 + 1] = yr;
+        nodescal[k * 8 + 2] = ayr;
+        nodescal[k * 8 + 3] = bb;
+    }
+}
+
+struct DualArgs {
+    double l0, l2, M, s, two_M_l2, four_l2, l2_M2, psi_lin, gamma_n;
+    int free_quad;
+    int64_t p;
+};
+
+// g = X^T r per (node, coordinate) with the per-tile sums of the upper bounds
+// of nu_i(|g_i|) and of psi_i(beta_i):  part[(k * ntile + tile) * 3 + {0,1,2}] =
+// sum nu+, sum |nu+|, sum psi.
+template <class T>
+__global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, int64_t lda,
+                                                  const double *__restrict__ R, int64_t ldr, int64_t kdim,
+                                                  const uint8_t *__restrict__ codes, const T *__restrict__ beta,
+                                                  const double *__restrict__ colnrm,
+                                                  const double *__restrict__ nodescal, const int *__restrict__ active,
+                                                  double *__restrict__ part, int64_t ldp, DualArgs da) {
+    __shared__ double red[4 * 1024];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int qq = lane >> 4, r = lane & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    f64x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+    const int64_t kq = kdim / 4;
+    const int64_t ib = w * kq, ie = ib + kq;
+    const double *A0 = A + (m0 + r) * lda + 4 * qq;
+    const double *A1 = A + (m0 + 16 + r) * lda + 4 * qq;
+    const double *U0 = R + (n0 + r) * ldr + 4 * qq;
+    const double *U1 = R + (n0 + 16 + r) * ldr + 4 * qq;
+    for (int64_t i0 = ib; i0 < ie; i0 += 16) {
+        double a0[4], a1[4], u0[4], u1[4];
+        load4(A0 + i0, a0);
+        load4(A1 + i0, a1);
+        load4(U0 + i0, u0);
+        load4(U1 + i0, u1);
+        for (int t = 0; t < 4; ++t) {
+            acc[0][0] = mfma16(a0[t], u0[t], acc[0][0]);
+            acc[0][1] = mfma16(a0[t], u1[t], acc[0][1]);
+            acc[1][0] = mfma16(a1[t], u0[t], acc[1][0]);
+            acc[1][1] = mfma16(a1[t], u1[t], acc[1][1]);
+        }
+    }
+    tile_to_lds<double>(acc, red, w, lane);
+    __syncthreads();
+    // thread t: node n = t / 8, coordinates 4 (t % 8) .. +3 of the tile
+    const int n = tid >> 3, jl = (tid & 7) * 4;
+    const int64_t node = n0 + n;
+    double snu = 0, sanu = 0, spsi = 0;
+    const bool act = active[node] != 0;
+    if (act) {
+        double nr = sqrt(nodescal[node * 8 + 0]);
+        for (int e = 0; e < 4; ++e) {
+            int64_t j = m0 + jl + e;
+            if (j >= da.p) continue;
+            double g = red[n * 32 + jl + e] + red[1024 + n * 32 + jl + e] + red[2048 + n * 32 + jl + e] +
+                       red[3072 + n * 32 + jl + e];
+            uint8_t code = codes[node * ldp + j];
+            double ej = 2.0 * da.gamma_n * colnrm[j] * nr;
+            double val = nu_upper(fabs(g), ej, code, da.l0, da.l2, da.M, da.two_M_l2, da.four_l2, da.l2_M2,
+                                  da.free_quad);
+            snu += val;
+            sanu += fabs(val);
+            spsi += psi_val((double)beta[node * ldp + j], code, da.l0, da.l2, da.s, da.free_quad, da.psi_lin);
+        }
+    }
+    for (int off = 1; off < 8; off <<= 1) {
+        snu += __shfl_xor(snu, off);
+        sanu += __shfl_xor(sanu, off);
+        spsi += __shfl_xor(spsi, off);
+    }
+    if ((tid & 7) == 0 && act) {
+        int64_t ntile = gridDim.x;
+        double *pp = part + (node * ntile + blockIdx.x) * 3;
+        pp[0] = snu;
+        pp[1] = sanu;
+        pp[2] = spsi;
+    }
+}
+
+struct FinArgs {
+    double gamma_n2, gamma_p, tol;
+    int64_t K, ntile;
+    int iter, mode;  // mode 0: solve (gap test), 1: bound only
+};
+
+// One workgroup: per active node, LB = (q - sum nu+) - margin (Prop. 1 plus the
+// rounding margin), P(beta) = 1/2 ||y - X beta||^2 + sum psi, gap test.  Writes
+// the number of nodes still active to *counter.
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ nodescal,
+                                                  const double *__restrict__ part, int *__restrict__ active,
+                                                  int *__restrict__ status, int *__restrict__ iters,
+                                                  double *__restrict__ lb, double *__restrict__ primal,
+                                                  int *__restrict__ counter, FinArgs fa) {
+    __shared__ int shc[256];
+    const double u = 1.1102230246251565e-16;
+    int cnt = 0;
+    for (int64_t k = threadIdx.x; k < fa.K; k += 256) {
+        if (!active[k]) continue;
+        double rr = nodescal[k * 8 + 0], yr = nodescal[k * 8 + 1], ayr = nodescal[k * 8 + 2];
+        double rbrb = nodescal[k * 8 + 3];
+        double snu = 0, sanu = 0, spsi = 0;
+        const double *pk = part + k * fa.ntile * 3;
+        for (int64_t t = 0; t < fa.ntile; ++t) {
+            snu += pk[t * 3 + 0];
+            sanu += pk[t * 3 + 1];
+            spsi += pk[t * 3 + 2];
+        }
+        double qv = -0.5 * rr + yr;
+        double margin = 2.0 * fa.gamma_n2 * (0.5 * rr + ayr) + 2.0 * fa.gamma_p * sanu + 4.0 * u * (fabs(qv) + fabs(snu));
+        double LB = (qv - snu) - margin;
+        lb[k] = LB;
+        if (fa.mode == 1) continue;
+        double P = 0.5 * rbrb + spsi;
+        primal[k] = P;
+        iters[k] = fa.iter;
+        double den = fabs(P) > 1e-300 ? fabs(P) : 1e-300;
+        if ((P - LB) / den <= fa.tol) {
+            status[k] = 0;
+            active[k] = 0;
+        } else {
+            status[k] = 1;
+            ++cnt;
+        }
+    }
+    shc[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *counter = shc[0];
+}
+
+template <class T> T *st(const DevBuf &b) { return b.as<T>(); }
+
+unsigned grid1d(int64_t total) { return (unsigned)std::min<int64_t>((total + 255) / 256, 65536); }
+
+// ---------------------------------------------------------------------------
+// Host drivers, templated on the state type T (double for FP64, float otherwise)
+// ---------------------------------------------------------------------------
+template <class T>
+void sweep_once(l0l2_ctx *ctx, int64_t Kp, bool store_b) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    const int64_t np = in.np, pp = in.pp;
+    dim3 g1((unsigned)(np / 32), (unsigned)(Kp / 32));
+    dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
+    DevParams<T> q = dev_params<T>(in.mp);
+    prof_begin(ctx, PROF_GEMM_XW);
+    hipLaunchKernelGGL((k_gemm_xw<T, T, T>), g1, dim3(256), 0, s, in.Xh.as<T>(), np, st<T>(ws.W), pp, st<T>(ws.U), np,
+                       pp);
+    prof_end(ctx, PROF_GEMM_XW);
+    prof_begin(ctx, PROF_ADMM_XTU);
+    hipLaunchKernelGGL((k_admm_xtu<T, T>), g2, dim3(256), 0, s, in.Xh.as<T>(), np, st<T>(ws.U), np, np, st<T>(ws.W),
+                       st<T>(ws.beta), st<T>(ws.V), st<T>(ws.B), ws.codes.as<uint8_t>(), in.cst.as<T>(),
+                       ws.active.as<int>(), q, pp, store_b ? 1 : 0);
+    prof_end(ctx, PROF_ADMM_XTU);
+    HIPCHK(hipGetLastError());
+}
+
+DualArgs dual_args(const Instance &in) {
+    DualArgs d;
+    d.l0 = in.mp.l0; d.l2 = in.mp.l2; d.M = in.mp.M; d.s = in.mp.s;
+    d.two_M_l2 = in.mp.two_M_l2; d.four_l2 = in.mp.four_l2; d.l2_M2 = in.mp.l2_M2; d.psi_lin = in.mp.psi_lin;
+    const double u = 1.1102230246251565e-16;
+    d.gamma_n = (double)in.n * u / (1.0 - (double)in.n * u);
+    d.free_quad = in.mp.free_quad;
+    d.p = in.p;
+    return d;
+}
+
+// FP64 check at the current (B, beta): fills ws.lb / primal / status / active.
+template <class T>
+void check_once(l0l2_ctx *ctx, int64_t K, int64_t Kp, int iter, double tol, int mode) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    const int64_t np = in.np, pp = in.pp;
+    dim3 g1((unsigned)(np / 32), (unsigned)(Kp / 32));
+    dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
+    const double *X64 = in.X64.as<double>();
+    prof_begin(ctx, PROF_CHECK);
+    hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, st<T>(ws.B), pp,
+                       ws.Ub.as<double>(), np, pp);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, st<T>(ws.beta), pp,
+                           ws.Ubeta.as<double>(), np, pp);
+    hipLaunchKernelGGL(k_resid, dim3((unsigned)K), dim3(256), 0, s, in.y64.as<double>(), ws.Ub.as<double>(),
+                       ws.Ubeta.as<double>(), ws.R.as<double>(), np, ws.nodescal.as<double>(), ws.active.as<int>(),
+                       mode == 0 ? 1 : 0);
+    DualArgs da = dual_args(in);
+    hipLaunchKernelGGL((k_dual_xtr<T>), g2, dim3(256), 0, s, X64, np, ws.R.as<double>(), np, np,
+                       ws.codes.as<uint8_t>(), mode == 0 ? st<T>(ws.beta) : st<T>(ws.B), in.colnrm.as<double>(),
+                       ws.nodescal.as<double>(), ws.active.as<int>(), ws.part.as<double>(), pp, da);
+    FinArgs fa;
+    const double u = 1.1102230246251565e-16;
+    fa.gamma_n2 = ((double)in.n + 2.0) * u / (1.0 - ((double)in.n + 2.0) * u);
+    fa.gamma_p = (double)in.p * u / (1.0 - (double)in.p * u);
+    fa.tol = tol;
+    fa.K = K;
+    fa.ntile = pp / 32;
+    fa.iter = iter;
+    fa.mode = mode;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ws.nodescal.as<double>(), ws.part.as<double>(),
+                       ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), ws.lb.as<double>(),
+                       ws.primal.as<double>(), ws.counter.as<int>(), fa);
+    prof_end(ctx, PROF_CHECK);
+    HIPCHK(hipGetLastError());
+}
+
+template <class T>
+void init_batch(l0l2_ctx *ctx, int64_t K, int64_t Kp) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
+                       ws.status.as<int>(), ws.iters.as<int>(), K, Kp);
+    hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), st<T>(ws.beta),
+                       st<T>(ws.V), st<T>(ws.W), in.cst.as<T>(), (T)in.mp.rho, in.pp, Kp * in.pp);
+    HIPCHK(hipGetLastError());
+}
+
+int read_counter(l0l2_ctx *ctx) {
+    Workspace &ws = ctx->ws;
+    HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return *ws.host_counter;
+}
+
+template <class T>
+void solve_t(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
+    const int64_t Kp = round_up(K, kPadNodes);
+    init_batch<T>(ctx, K, Kp);
+    const int m = std::max(1, o.check_every);
+    for (int t = 1; t <= o.max_iter; ++t) {
+        bool chk = (t % m == 0) || (t == o.max_iter);
+        sweep_once<T>(ctx, Kp, chk);
+        if (chk) {
+            check_once<T>(ctx, K, Kp, t, o.tol_node, 0);
+            if (read_counter(ctx) == 0) break;
+        }
+    }
+}
+
+template <class T>
+void sweeps_t(l0l2_ctx *ctx, int K, int sweeps) {
+    const int64_t Kp = round_up(K, kPadNodes);
+    init_batch<T>(ctx, K, Kp);
+    for (int t = 1; t <= sweeps; ++t) sweep_once<T>(ctx, Kp, t == sweeps);
+}
+
+}  // namespace
+
+void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    const int64_t Kp = round_up(std::max<int64_t>(K, 1), kPadNodes);
+    if (Kp <= ws.cap && ws.host_counter) return;
+    const size_t sb = state_bytes(in.prec);
+    const int64_t np = in.np, pp = in.pp;
+    ws.W.ensure(sb * Kp * pp);
+    ws.beta.ensure(sb * Kp * pp);
+    ws.V.ensure(sb * Kp * pp);
+    ws.B.ensure(sb * Kp * pp);
+    ws.U.ensure(sb * Kp * np);
+    ws.Ub.ensure(8 * Kp * np);
+    ws.Ubeta.ensure(8 * Kp * np);
+    ws.R.ensure(8 * Kp * np);
+    ws.codes.ensure((size_t)(Kp * pp));
+    ws.nodescal.ensure(8 * 8 * Kp);
+    ws.part.ensure(8 * 3 * Kp * (pp / 32));
+    ws.active.ensure(4 * Kp);
+    ws.iters.ensure(4 * Kp);
+    ws.status.ensure(4 * Kp);
+    ws.lb.ensure(8 * Kp);
+    ws.primal.ensure(8 * Kp);
+    ws.counter.ensure(sizeof(int));
+    if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, sizeof(int), hipHostMallocDefault));
+    // inactive padded rows must read as zeros on first use
+    HIPCHK(hipMemsetAsync(ws.W.ptr, 0, sb * Kp * pp, ctx->stream));
+    HIPCHK(hipMemsetAsync(ws.B.ptr, 0, sb * Kp * pp, ctx->stream));
+    ws.cap = Kp;
+}
+
+void load_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *beta, const void *v, bool codes_on_host) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    ensure_workspace(ctx, K);
+    const int64_t Kp = round_up(K, kPadNodes);
+    const uint8_t *dcodes = codes;
+    DevBuf tmp;
+    if (codes_on_host) {
+        tmp.ensure((size_t)K * in.p);
+        HIPCHK(hipMemcpyAsync(tmp.ptr, codes, (size_t)K * in.p, hipMemcpyHostToDevice, s));
+        dcodes = tmp.as<uint8_t>();
+    }
+    hipLaunchKernelGGL(k_load_codes, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, dcodes, (int64_t)K, in.p,
+                       ws.codes.as<uint8_t>(), Kp, in.pp);
+    if (in.prec == L0L2_FP64) {
+        hipLaunchKernelGGL(k_load_state<double>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const double *)beta,
+                           (int64_t)K, in.p, ws.beta.as<double>(), Kp, in.pp);
+        hipLaunchKernelGGL(k_load_state<double>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const double *)v,
+                           (int64_t)K, in.p, ws.V.as<double>(), Kp, in.pp);
+    } else {
+        hipLaunchKernelGGL(k_load_state<float>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const float *)beta,
+                           (int64_t)K, in.p, ws.beta.as<float>(), Kp, in.pp);
+        hipLaunchKernelGGL(k_load_state<float>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const float *)v,
+                           (int64_t)K, in.p, ws.V.as<float>(), Kp, in.pp);
+    }
+    HIPCHK(hipGetLastError());
+    if (codes_on_host) HIPCHK(hipStreamSynchronize(s));
+}
+
+void store_batch(l0l2_ctx *ctx, int K, void *beta, void *v, void *b) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    unsigned g = grid1d((int64_t)K * in.p);
+    if (in.prec == L0L2_FP64) {
+        if (beta) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.beta.as<double>(), (int64_t)K, in.p, in.pp, (double *)beta);
+        if (v) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.V.as<double>(), (int64_t)K, in.p, in.pp, (double *)v);
+        if (b) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.B.as<double>(), (int64_t)K, in.p, in.pp, (double *)b);
+    } else {
+        if (beta) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.beta.as<float>(), (int64_t)K, in.p, in.pp, (float *)beta);
+        if (v) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.V.as<float>(), (int64_t)K, in.p, in.pp, (float *)v);
+        if (b) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.B.as<float>(), (int64_t)K, in.p, in.pp, (float *)b);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool) {
+    if (ctx->inst.prec == L0L2_FP64) sweeps_t<double>(ctx, K, sweeps);
+    else if (ctx->inst.prec == L0L2_FP32) sweeps_t<float>(ctx, K, sweeps);
+    else fail(L0L2_E_UNSUPPORTED, "BF16 sweeps are not available in this build");
+}
+
+void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
+    if (ctx->inst.prec == L0L2_FP64) solve_t<double>(ctx, K, o);
+    else if (ctx->inst.prec == L0L2_FP32) solve_t<float>(ctx, K, o);
+    else fail(L0L2_E_UNSUPPORTED, "BF16 node solves are not available in this build");
+}
+
+// Bound at b already loaded in ws.B (codes in ws.codes): fills ws.lb.
+void run_dual_bound(l0l2_ctx *ctx, int K, const void *) {
+    const int64_t Kp = round_up(K, kPadNodes);
+    Workspace &ws = ctx->ws;
+    hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, ctx->stream,
+                       ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), (int64_t)K, Kp);
+    if (ctx->inst.prec == L0L2_FP64) check_once<double>(ctx, K, Kp, 0, 0.0, 1);
+    else check_once<float>(ctx, K, Kp, 0, 0.0, 1);
+}
+
+}  // namespace l0l2

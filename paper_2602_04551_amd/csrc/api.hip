@@ -1,0 +1,283 @@
+// extern "C" entry points of libl0l2 (include/l0l2.h): argument validation,
+// error capture and dispatch.  No exception crosses this boundary.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.hpp"
+
+namespace l0l2 {
+
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) {
+        int code = (e == hipErrorOutOfMemory) ? L0L2_E_OOM : L0L2_E_DEVICE;
+        fail(code, std::string(what) + ": " + hipGetErrorString(e));
+    }
+}
+
+void DevBuf::release() {
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+void DevBuf::ensure(size_t b) {
+    if (b <= bytes && ptr) return;
+    release();
+    if (b == 0) b = 1;
+    hipError_t e = hipMalloc(&ptr, b);
+    if (e != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        fail(L0L2_E_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    bytes = b;
+}
+
+}  // namespace l0l2
+
+using l0l2::Error;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+template <class F>
+int guarded(l0l2_ctx *ctx, F &&f) {
+    if (!ctx) return L0L2_E_INVALID;
+    try {
+        if (hipSetDevice(ctx->device) != hipSuccess) l0l2::fail(L0L2_E_DEVICE, "hipSetDevice failed");
+        f();
+        ctx->err.clear();
+        return L0L2_OK;
+    } catch (const Error &e) {
+        ctx->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return L0L2_E_OOM;
+    } catch (...) {
+        ctx->err = "unexpected internal error";
+        return L0L2_E_DEVICE;
+    }
+}
+
+void need_data(l0l2_ctx *ctx) {
+    if (!ctx->has_data) l0l2::fail(L0L2_E_NODATA, "l0l2_set_data has not been called");
+}
+
+void check_K(int K) {
+    if (K < 0) l0l2::fail(L0L2_E_INVALID, "K must be >= 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+int l0l2_create(int device, void *hip_stream, l0l2_ctx **out) {
+    if (!out) return L0L2_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        g_create_err = "no HIP device available";
+        return L0L2_E_DEVICE;
+    }
+    if (device < 0 || device >= ndev) {
+        g_create_err = "device index out of range";
+        return L0L2_E_INVALID;
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        g_create_err = "hipSetDevice failed";
+        return L0L2_E_DEVICE;
+    }
+    l0l2_ctx *c = new (std::nothrow) l0l2_ctx();
+    if (!c) return L0L2_E_OOM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return L0L2_OK;
+}
+
+void l0l2_destroy(l0l2_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws.host_counter) (void)hipHostFree(ctx->ws.host_counter);
+    l0l2::prof_release(ctx->prof);
+    delete ctx;
+}
+
+const char *l0l2_last_error(const l0l2_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int l0l2_state_bytes(const l0l2_ctx *ctx) {
+    if (!ctx) return L0L2_E_INVALID;
+    return (int)l0l2::state_bytes(ctx->inst.prec);
+}
+
+int l0l2_set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p, double lambda0,
+                  double lambda2, double M, double rho, int x_precision, int ptrs_on_device) {
+    return guarded(ctx, [&] {
+        if (!X || !y) l0l2::fail(L0L2_E_INVALID, "X and y must be non-null");
+        if (n < 1 || p < 1) l0l2::fail(L0L2_E_INVALID, "need n >= 1 and p >= 1");
+        if (!(std::isfinite(lambda0) && lambda0 >= 0)) l0l2::fail(L0L2_E_INVALID, "lambda0 must be finite and >= 0");
+        if (!(std::isfinite(lambda2) && lambda2 > 0)) l0l2::fail(L0L2_E_INVALID, "lambda2 must be finite and > 0");
+        if (!(M > 0) || std::isnan(M)) l0l2::fail(L0L2_E_INVALID, "M must be > 0 (INFINITY allowed)");
+        if (!(std::isfinite(rho) && rho > 0)) l0l2::fail(L0L2_E_INVALID, "rho must be finite and > 0");
+        if (x_precision != L0L2_FP64 && x_precision != L0L2_FP32 && x_precision != L0L2_BF16)
+            l0l2::fail(L0L2_E_INVALID, "unknown x_precision");
+        if (x_precision == L0L2_BF16) l0l2::fail(L0L2_E_UNSUPPORTED, "BF16 products are not available in this build");
+        if (!ptrs_on_device) {
+            for (int64_t e = 0; e < n * p; ++e)
+                if (!std::isfinite(X[e])) l0l2::fail(L0L2_E_INVALID, "X has a non-finite entry");
+            for (int64_t e = 0; e < n; ++e)
+                if (!std::isfinite(y[e])) l0l2::fail(L0L2_E_INVALID, "y has a non-finite entry");
+        }
+        l0l2::set_data(ctx, X, y, n, p, lambda0, lambda2, M, rho, x_precision, ptrs_on_device);
+    });
+}
+
+int l0l2_admm_sweeps(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta, void *v, void *b_out, int sweeps) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        check_K(K);
+        if (sweeps < 1) l0l2::fail(L0L2_E_INVALID, "sweeps must be >= 1");
+        if (K == 0) return;
+        if (!codes || !beta || !v) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        l0l2::load_batch(ctx, K, codes, beta, v, false);
+        l0l2::run_sweeps(ctx, K, sweeps, true);
+        l0l2::store_batch(ctx, K, beta, v, b_out);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int l0l2_dual_bound(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *b, double *lb) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        check_K(K);
+        if (K == 0) return;
+        if (!codes || !b || !lb) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        // b goes into the sweep's b slot through the beta loader, then is moved.
+        l0l2::load_batch(ctx, K, codes, b, b, false);
+        auto &ws = ctx->ws;
+        const int64_t Kp = l0l2::round_up(K, l0l2::kPadNodes);
+        size_t sb = l0l2::state_bytes(ctx->inst.prec);
+        HIPCHK(hipMemcpyAsync(ws.B.ptr, ws.beta.ptr, sb * Kp * ctx->inst.pp, hipMemcpyDeviceToDevice, ctx->stream));
+        l0l2::run_dual_bound(ctx, K, nullptr);
+        HIPCHK(hipMemcpyAsync(lb, ws.lb.ptr, sizeof(double) * K, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int l0l2_solve_node_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta, void *v,
+                          const l0l2_admm_opts *opts, double *lb, double *primal, int32_t *iters, int32_t *status) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        check_K(K);
+        if (!opts) l0l2::fail(L0L2_E_INVALID, "null options");
+        if (opts->max_iter < 1 || opts->check_every < 1 || !(opts->tol_node >= 0))
+            l0l2::fail(L0L2_E_INVALID, "need max_iter >= 1, check_every >= 1, tol_node >= 0");
+        if (K == 0) return;
+        if (!codes || !beta || !v || !lb || !primal || !iters || !status) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        l0l2::load_batch(ctx, K, codes, beta, v, false);
+        l0l2::run_solve(ctx, K, *opts);
+        l0l2::store_batch(ctx, K, beta, v, nullptr);
+        auto &ws = ctx->ws;
+        hipStream_t s = ctx->stream;
+        HIPCHK(hipMemcpyAsync(lb, ws.lb.ptr, sizeof(double) * K, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(primal, ws.primal.ptr, sizeof(double) * K, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(iters, ws.iters.ptr, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipMemcpyAsync(status, ws.status.ptr, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    });
+}
+
+int l0l2_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *beta, uint8_t *support,
+                      int32_t *support_size, int32_t *branch_j, int32_t *z_up) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        check_K(K);
+        if (K == 0) return;
+        if (!codes || !beta || !support || !support_size || !branch_j || !z_up)
+            l0l2::fail(L0L2_E_INVALID, "null buffer");
+        l0l2::DevBuf nfree;
+        nfree.ensure(sizeof(int32_t) * K);
+        l0l2::run_round_branch(ctx, K, codes, ctx->inst.p, beta, ctx->inst.p, support, support_size, branch_j, z_up,
+                               nfree.as<int32_t>());
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int l0l2_refine_incumbent(l0l2_ctx *ctx, int K, const uint8_t *support, const void *beta_start, double *beta_out,
+                          const l0l2_fista_opts *opts, double *obj, int32_t *iters) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        check_K(K);
+        if (!opts || opts->max_iter < 1 || !(opts->tol >= 0)) l0l2::fail(L0L2_E_INVALID, "bad FISTA options");
+        if (K == 0) return;
+        if (!support || !beta_start || !beta_out || !obj) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        const int64_t p = ctx->inst.p;
+        l0l2::state_to_f64(ctx, K, beta_start, p, beta_out, p);
+        l0l2::run_fista(ctx, K, support, p, beta_out, p, *opts, obj, iters);
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int l0l2_exact_objective(l0l2_ctx *ctx, const uint8_t *support, double *beta_out, double *obj) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        if (!support || !beta_out || !obj) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        *obj = l0l2::run_exact_objective(ctx, support, beta_out);
+    });
+}
+
+int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *out) {
+    if (out) std::memset(out, 0, sizeof(*out));
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        if (!opts || !out) l0l2::fail(L0L2_E_INVALID, "null argument");
+        if (opts->K < 1 || opts->admm.max_iter < 1 || opts->admm.check_every < 1 || opts->max_iter_root < 1 ||
+            opts->fista.max_iter < 1 || !(opts->eps_prune >= 0) || !(opts->gap_tol >= 0) || opts->max_nodes < 1 ||
+            (opts->policy != L0L2_BEST_FIRST && opts->policy != L0L2_DFS))
+            l0l2::fail(L0L2_E_INVALID, "bad branch-and-bound options");
+        l0l2::bnb_solve(ctx, *opts, out);
+    });
+}
+
+int l0l2_profile_enable(l0l2_ctx *ctx, int enable) {
+    return guarded(ctx, [&] {
+        l0l2::prof_collect(ctx);
+        ctx->prof.on = enable != 0;
+        for (int i = 0; i < l0l2::kProfCount; ++i) {
+            ctx->prof.total_ms[i] = 0.0;
+            ctx->prof.count[i] = 0;
+        }
+    });
+}
+
+int l0l2_profile_query(l0l2_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms) {
+    return guarded(ctx, [&] {
+        if (!kernel || !launches || !total_ms) l0l2::fail(L0L2_E_INVALID, "null argument");
+        l0l2::prof_collect(ctx);
+        for (int i = 0; i < l0l2::kProfCount; ++i)
+            if (std::strcmp(kernel, l0l2::kProfNames[i]) == 0) {
+                *launches = ctx->prof.count[i];
+                *total_ms = ctx->prof.total_ms[i];
+                return;
+            }
+        l0l2::fail(L0L2_E_INVALID, std::string("unknown kernel name ") + kernel);
+    });
+}
+
+void l0l2_result_free(l0l2_bnb_result *res) {
+    if (!res) return;
+    std::free(res->support);
+    std::free(res->beta);
+    res->support = nullptr;
+    res->beta = nullptr;
+}
+
+}  // extern "C"

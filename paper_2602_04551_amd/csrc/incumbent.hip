@@ -1,0 +1,426 @@
+// Rounding, branching and incumbent refinement (Sec. 3.3 and 3.4), FP64.
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <vector>
+
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace l0l2 {
+
+namespace {
+
+constexpr int kSMax = 1024;   // largest support refined by one workgroup
+
+// Deterministic block sum broadcast to every thread (256 threads).
+__device__ __forceinline__ double bsum(double v, double *sh) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__device__ __forceinline__ double bmax(double v, double *sh) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+struct RoundArgs {
+    double s, M;
+    int free_quad;
+    int64_t p;
+};
+
+// One workgroup per node.  S = F1 u {free j : z_j >= 1/2}; branching index =
+// the free j of largest floor(2^20 min(z_j, 1 - z_j)), ties to the smallest j;
+// if that score is 0 for every free j, the free j of largest |beta_j|.
+template <class T>
+__global__ __launch_bounds__(256) void k_round_branch(const uint8_t *__restrict__ codes, int64_t ldc,
+                                                      const T *__restrict__ beta, int64_t ldb,
+                                                      uint8_t *__restrict__ support, int32_t *__restrict__ ssize,
+                                                      int32_t *__restrict__ bj, int32_t *__restrict__ zup,
+                                                      int32_t *__restrict__ nfree, RoundArgs ra) {
+    __shared__ double shs[256];
+    __shared__ int64_t shj[256];
+    __shared__ double sha[256];
+    __shared__ int64_t shja[256];
+    __shared__ int shc[256], shf[256];
+    const int64_t k = blockIdx.x;
+    const int tid = threadIdx.x;
+    double bsc = -1.0, babs = -1.0;
+    int64_t bjj = INT64_MAX, bja = INT64_MAX;
+    int cnt = 0, nf = 0;
+    for (int64_t j = tid; j < ra.p; j += 256) {
+        uint8_t code = codes[k * ldc + j];
+        double b = (double)beta[k * ldb + j];
+        double z = z_of(b, code, ra.s, ra.M, ra.free_quad);
+        uint8_t sup = (code == CODE_FIX1) || (code == CODE_FREE && z >= 0.5);
+        support[k * ra.p + j] = sup;
+        cnt += sup;
+        if (code == CODE_FREE) {
+            ++nf;
+            double f = z < 1.0 - z ? z : 1.0 - z;
+            double sc = floor(f * 1048576.0);
+            if (sc > bsc) { bsc = sc; bjj = j; }
+            double ab = fabs(b);
+            if (ab > babs) { babs = ab; bja = j; }
+        }
+    }
+    shs[tid] = bsc; shj[tid] = bjj; sha[tid] = babs; shja[tid] = bja; shc[tid] = cnt; shf[tid] = nf;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) {
+            int o = tid + st;
+            if (shs[o] > shs[tid] || (shs[o] == shs[tid] && shj[o] < shj[tid])) { shs[tid] = shs[o]; shj[tid] = shj[o]; }
+            if (sha[o] > sha[tid] || (sha[o] == sha[tid] && shja[o] < shja[tid])) { sha[tid] = sha[o]; shja[tid] = shja[o]; }
+            shc[tid] += shc[o];
+            shf[tid] += shf[o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        ssize[k] = shc[0];
+        nfree[k] = shf[0];
+        int64_t j = -1;
+        if (shf[0] > 0) j = shs[0] <= 0.0 ? shja[0] : shj[0];
+        bj[k] = (int32_t)j;
+        int up = 0;
+        if (j >= 0) up = z_of((double)beta[k * ldb + j], CODE_FREE, ra.s, ra.M, ra.free_quad) >= 0.5;
+        zup[k] = up;
+    }
+}
+
+struct FistaArgs {
+    double l0, l2, M, tol;
+    int max_iter;
+    int64_t n, np, p;
+};
+
+// U_S(v) = 1/2 ||X_S v - y||^2 + l2 ||v||^2; optionally keeps the residual.
+__device__ double U_S(const double *__restrict__ X, int64_t np, const double *__restrict__ y, const int *idx, int k,
+                      const double *v, double *res, bool keep, double *sh, const FistaArgs &fa) {
+    double rr = 0.0;
+    for (int64_t i = threadIdx.x; i < fa.n; i += 256) {
+        double s = 0.0;
+        for (int a = 0; a < k; ++a) s += X[(int64_t)idx[a] * np + i] * v[a];
+        double r = s - y[i];
+        if (keep) res[i] = r;
+        rr += r * r;
+    }
+    double bb = 0.0;
+    for (int a = threadIdx.x; a < k; a += 256) bb += v[a] * v[a];
+    rr = bsum(rr, sh);
+    bb = bsum(bb, sh);
+    return 0.5 * rr + fa.l2 * bb;
+}
+
+// Fast proximal gradient on each support (eqs. fpg_extrapolate .. fpg_armijo):
+// one workgroup per node.  Start at the node iterate on S; alpha_0 =
+// 4 / (||X_S||_F^2 + 2 l2), halved on each Armijo failure (at most 60 times per
+// iteration) and carried over; stop on |dU| <= tol max(1, U) or max|d beta| <=
+// 1e-10.
+__global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, const double *__restrict__ y,
+                                               const double *__restrict__ colnrm, const uint8_t *__restrict__ sup,
+                                               int64_t lds, double *__restrict__ beta, int64_t ldb,
+                                               double *__restrict__ resbuf, double *__restrict__ obj,
+                                               int32_t *__restrict__ iters, FistaArgs fa) {
+    __shared__ int idx[kSMax];
+    __shared__ double cur[kSMax], prev[kSMax], ext[kSMax], nxt[kSMax], grad[kSMax];
+    __shared__ double sh[4];
+    __shared__ int shw[4];
+    const int64_t node = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double *res = resbuf + node * fa.np;
+    // compact the support in index order
+    int k = 0;
+    for (int64_t base = 0; base < fa.p; base += 256) {
+        int64_t j = base + tid;
+        int f = (j < fa.p) ? sup[node * lds + j] != 0 : 0;
+        unsigned long long bal = __ballot(f);
+        int before = __popcll(bal & ((1ull << lane) - 1ull));
+        __syncthreads();
+        if (lane == 0) shw[w] = __popcll(bal);
+        __syncthreads();
+        int off = k;
+        for (int ww = 0; ww < w; ++ww) off += shw[ww];
+        if (f && off + before < kSMax) idx[off + before] = (int)j;
+        k += shw[0] + shw[1] + shw[2] + shw[3];
+    }
+    __syncthreads();
+    if (k > kSMax) {
+        if (tid == 0) {
+            obj[node] = NAN;
+            if (iters) iters[node] = -1;
+        }
+        return;
+    }
+    if (k == 0) {
+        double yy = 0.0;
+        for (int64_t i = tid; i < fa.n; i += 256) yy += y[i] * y[i];
+        yy = bsum(yy, sh);
+        for (int64_t j = tid; j < fa.p; j += 256) beta[node * ldb + j] = 0.0;
+        if (tid == 0) {
+            obj[node] = 0.5 * yy;
+            if (iters) iters[node] = 0;
+        }
+        return;
+    }
+    double fro = 0.0;
+    for (int a = tid; a < k; a += 256) {
+        double b0 = beta[node * ldb + idx[a]];
+        b0 = b0 > fa.M ? fa.M : (b0 < -fa.M ? -fa.M : b0);
+        cur[a] = b0;
+        prev[a] = b0;
+        double cn = colnrm[idx[a]];
+        fro += cn * cn;
+    }
+    fro = bsum(fro, sh);
+    double alpha = 4.0 / (fro + 2.0 * fa.l2);
+    double Ucur = U_S(X, fa.np, y, idx, k, cur, res, false, sh, fa);
+    int it = 0;
+    while (it < fa.max_iter) {
+        double mom = (double)it / ((double)it + 3.0);
+        for (int a = tid; a < k; a += 256) ext[a] = cur[a] + mom * (cur[a] - prev[a]);
+        __syncthreads();
+        double Uext = U_S(X, fa.np, y, idx, k, ext, res, true, sh, fa);
+        __syncthreads();
+        for (int a = w; a < k; a += 4) {
+            const double *col = X + (int64_t)idx[a] * fa.np;
+            double s = 0.0;
+            for (int64_t i = lane; i < fa.n; i += 64) s += col[i] * res[i];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (lane == 0) grad[a] = s + 2.0 * fa.l2 * ext[a];
+        }
+        __syncthreads();
+        double Unxt = 0.0;
+        for (int bt = 0; bt <= 60; ++bt) {
+            double gd = 0.0, dd = 0.0;
+            for (int a = tid; a < k; a += 256) {
+                double v = ext[a] - alpha * grad[a];
+                v = v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v);
+                nxt[a] = v;
+                double d = v - ext[a];
+                gd += grad[a] * d;
+                dd += d * d;
+            }
+            gd = bsum(gd, sh);
+            dd = bsum(dd, sh);
+            Unxt = U_S(X, fa.np, y, idx, k, nxt, res, false, sh, fa);
+            if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
+            alpha *= 0.5;
+        }
+        ++it;
+        double dm = 0.0;
+        for (int a = tid; a < k; a += 256) dm = fmax(dm, fabs(nxt[a] - cur[a]));
+        dm = bmax(dm, sh);
+        double dU = fabs(Unxt - Ucur);
+        for (int a = tid; a < k; a += 256) {
+            prev[a] = cur[a];
+            cur[a] = nxt[a];
+        }
+        __syncthreads();
+        Ucur = Unxt;
+        if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
+    }
+    double f = U_S(X, fa.np, y, idx, k, cur, res, false, sh, fa) + fa.l0 * (double)k;
+    for (int64_t j = tid; j < fa.p; j += 256) beta[node * ldb + j] = 0.0;
+    __syncthreads();
+    for (int a = tid; a < k; a += 256) beta[node * ldb + idx[a]] = cur[a];
+    if (tid == 0) {
+        obj[node] = f;
+        if (iters) iters[node] = it;
+    }
+}
+
+template <class T>
+__global__ void k_state_f64(const T *__restrict__ src, int64_t lds, double *__restrict__ dst, int64_t ldd, int64_t K,
+                            int64_t p) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < K * p; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t k = idx / p, j = idx % p;
+        dst[k * ldd + j] = (double)src[k * lds + j];
+    }
+}
+
+// Exact box-constrained ridge on one support, single workgroup:
+// H = X_S^T X_S + 2 l2 I, g = X_S^T y; Cholesky solve; if the box binds,
+// coordinate descent on 1/2 b^T H b - g^T b over [-M, M]^k.
+__global__ __launch_bounds__(256) void k_exact(const double *__restrict__ X, int64_t np, const double *__restrict__ y,
+                                               const double *__restrict__ c, const int *__restrict__ idx, int k,
+                                               double *__restrict__ H, double *__restrict__ L,
+                                               double *__restrict__ bsol, double *__restrict__ res,
+                                               double *__restrict__ out, FistaArgs fa) {
+    __shared__ double sh[4];
+    __shared__ int flag;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int e = w; e < k * k; e += 4) {
+        int a = e % k, b = e / k;
+        if (b > a) continue;
+        const double *ca = X + (int64_t)idx[a] * np, *cb = X + (int64_t)idx[b] * np;
+        double s = 0.0;
+        for (int64_t i = lane; i < fa.n; i += 64) s += ca[i] * cb[i];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) {
+            double v = s + (a == b ? 2.0 * fa.l2 : 0.0);
+            H[a + b * k] = v;
+            H[b + a * k] = v;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += 256) L[e] = H[e];
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    for (int j = 0; j < k; ++j) {
+        if (tid == 0) {
+            double d = L[j + j * k];
+            if (!(d > 0.0)) { flag = 1; d = 1.0; }
+            L[j + j * k] = sqrt(d);
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < k; i += 256) L[i + j * k] /= L[j + j * k];
+        __syncthreads();
+        int rem = k - j - 1;
+        for (int e = tid; e < rem * rem; e += 256) {
+            int i = j + 1 + e % rem, m = j + 1 + e / rem;
+            if (m <= i) L[i + m * k] -= L[i + j * k] * L[m + j * k];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        for (int a = 0; a < k; ++a) bsol[a] = c[idx[a]];
+        if (!flag) {
+            for (int i = 0; i < k; ++i) {
+                double s = bsol[i];
+                for (int m = 0; m < i; ++m) s -= L[i + m * k] * bsol[m];
+                bsol[i] = s / L[i + i * k];
+            }
+            for (int i = k - 1; i >= 0; --i) {
+                double s = bsol[i];
+                for (int m = i + 1; m < k; ++m) s -= L[m + i * k] * bsol[m];
+                bsol[i] = s / L[i + i * k];
+            }
+        }
+        int boxed = flag;
+        for (int a = 0; a < k; ++a) if (fabs(bsol[a]) > fa.M) boxed = 1;
+        if (flag) for (int a = 0; a < k; ++a) bsol[a] = 0.0;
+        flag = boxed;
+    }
+    __syncthreads();
+    if (flag) {
+        for (int a = tid; a < k; a += 256) bsol[a] = fmin(fa.M, fmax(-fa.M, bsol[a]));
+        __syncthreads();
+        for (int sweep = 0; sweep < 200000; ++sweep) {
+            double dmax = 0.0, bm = 0.0;
+            for (int a = 0; a < k; ++a) {
+                double part = 0.0;
+                for (int b = tid; b < k; b += 256) if (b != a) part += H[b * k + a] * bsol[b];
+                part = bsum(part, sh);
+                double nv = (c[idx[a]] - part) / H[a * k + a];
+                nv = fmin(fa.M, fmax(-fa.M, nv));
+                dmax = fmax(dmax, fabs(nv - bsol[a]));
+                bm = fmax(bm, fabs(nv));
+                __syncthreads();
+                if (tid == 0) bsol[a] = nv;
+                __syncthreads();
+            }
+            if (dmax <= 1e-16 * (bm > 1.0 ? bm : 1.0)) break;
+        }
+    }
+    __syncthreads();
+    double rr = 0.0;
+    for (int64_t i = tid; i < fa.n; i += 256) {
+        double s = 0.0;
+        for (int a = 0; a < k; ++a) s += X[(int64_t)idx[a] * np + i] * bsol[a];
+        double r = s - y[i];
+        rr += r * r;
+    }
+    double bb = 0.0;
+    for (int a = tid; a < k; a += 256) bb += bsol[a] * bsol[a];
+    rr = bsum(rr, sh);
+    bb = bsum(bb, sh);
+    if (tid == 0) *out = 0.5 * rr + fa.l2 * bb + fa.l0 * (double)k;
+    (void)res;
+}
+
+}  // namespace
+
+void run_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, int64_t ld_codes, const void *beta,
+                      int64_t ld_beta, uint8_t *support, int32_t *support_size, int32_t *branch_j, int32_t *z_up, int32_t *nfree) {
+    Instance &in = ctx->inst;
+    RoundArgs ra{in.mp.s, in.mp.M, in.mp.free_quad, in.p};
+    if (K <= 0) return;
+    prof_begin(ctx, PROF_ROUND);
+    if (in.prec == L0L2_FP64)
+        hipLaunchKernelGGL(k_round_branch<double>, dim3((unsigned)K), dim3(256), 0, ctx->stream, codes, ld_codes,
+                           (const double *)beta, ld_beta, support, support_size, branch_j, z_up, nfree, ra);
+    else
+        hipLaunchKernelGGL(k_round_branch<float>, dim3((unsigned)K), dim3(256), 0, ctx->stream, codes, ld_codes,
+                           (const float *)beta, ld_beta, support, support_size, branch_j, z_up, nfree, ra);
+    prof_end(ctx, PROF_ROUND);
+    HIPCHK(hipGetLastError());
+}
+
+void run_fista(l0l2_ctx *ctx, int K, const uint8_t *support, int64_t ld_support, double *beta, int64_t ld_beta,
+               const l0l2_fista_opts &o, double *obj, int32_t *iters) {
+    Instance &in = ctx->inst;
+    if (K <= 0) return;
+    ctx->ws.fista.ensure(sizeof(double) * (size_t)K * in.np);
+    FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, o.tol, o.max_iter, in.n, in.np, in.p};
+    prof_begin(ctx, PROF_FISTA);
+    hipLaunchKernelGGL(k_fista, dim3((unsigned)K), dim3(256), 0, ctx->stream, in.X64.as<double>(), in.y64.as<double>(),
+                       in.colnrm.as<double>(), support, ld_support, beta, ld_beta, ctx->ws.fista.as<double>(), obj,
+                       iters, fa);
+    prof_end(ctx, PROF_FISTA);
+    HIPCHK(hipGetLastError());
+}
+
+double run_exact_objective(l0l2_ctx *ctx, const uint8_t *support_host, double *beta_host) {
+    Instance &in = ctx->inst;
+    hipStream_t s = ctx->stream;
+    std::vector<int> idx;
+    for (int64_t j = 0; j < in.p; ++j)
+        if (support_host[j]) idx.push_back((int)j);
+    const int k = (int)idx.size();
+    for (int64_t j = 0; j < in.p; ++j) beta_host[j] = 0.0;
+    DevBuf didx, H, L, b, out;
+    didx.ensure(sizeof(int) * (size_t)std::max(k, 1));
+    H.ensure(sizeof(double) * (size_t)std::max(k * k, 1));
+    L.ensure(sizeof(double) * (size_t)std::max(k * k, 1));
+    b.ensure(sizeof(double) * (size_t)std::max(k, 1));
+    out.ensure(sizeof(double));
+    if (k) HIPCHK(hipMemcpyAsync(didx.ptr, idx.data(), sizeof(int) * k, hipMemcpyHostToDevice, s));
+    FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, 0.0, 0, in.n, in.np, in.p};
+    hipLaunchKernelGGL(k_exact, dim3(1), dim3(256), 0, s, in.X64.as<double>(), in.np, in.y64.as<double>(),
+                       in.c64.as<double>(), didx.as<int>(), k, H.as<double>(), L.as<double>(), b.as<double>(),
+                       (double *)nullptr, out.as<double>(), fa);
+    HIPCHK(hipGetLastError());
+    double f = 0.0;
+    std::vector<double> hb((size_t)std::max(k, 1));
+    HIPCHK(hipMemcpyAsync(&f, out.ptr, sizeof(double), hipMemcpyDeviceToHost, s));
+    if (k) HIPCHK(hipMemcpyAsync(hb.data(), b.ptr, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int a = 0; a < k; ++a) beta_host[idx[a]] = hb[a];
+    return f;
+}
+
+void state_to_f64(l0l2_ctx *ctx, int K, const void *src, int64_t ld_src, double *dst, int64_t ld_dst) {
+    Instance &in = ctx->inst;
+    unsigned g = (unsigned)std::min<int64_t>(((int64_t)K * in.p + 255) / 256, 65536);
+    if (K <= 0) return;
+    if (in.prec == L0L2_FP64)
+        hipLaunchKernelGGL(k_state_f64<double>, dim3(g), dim3(256), 0, ctx->stream, (const double *)src, ld_src, dst,
+                           ld_dst, (int64_t)K, in.p);
+    else
+        hipLaunchKernelGGL(k_state_f64<float>, dim3(g), dim3(256), 0, ctx->stream, (const float *)src, ld_src, dst,
+                           ld_dst, (int64_t)K, in.p);
+    HIPCHK(hipGetLastError());
+}
+
+}  // namespace l0l2

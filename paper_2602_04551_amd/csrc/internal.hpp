@@ -1,0 +1,155 @@
+// Internal declarations of libl0l2 (host side).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/l0l2.h"
+
+namespace l0l2 {
+
+constexpr int kPadRows = 64;    // n and p are padded to multiples of this
+constexpr int kPadNodes = 32;   // K is padded to multiples of this (one GEMM tile)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+// Error carrying a status code; caught at the C ABI boundary.
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string &msg);
+void hip_check(hipError_t e, const char *what);
+#define HIPCHK(x) ::l0l2::hip_check((x), #x)
+
+// Device buffer owned by the library.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release();
+    // grow to at least `b` bytes (contents not preserved)
+    void ensure(size_t b);
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Scalars of the closed forms, evaluated once per instance with the same
+// expressions in every precision (the float copies are rounded from these).
+struct MethodParams {
+    double l0, l2, M, rho;
+    double s;           // sqrt(l0 / l2)
+    int free_quad;      // s <= M: free coordinates use the 3-piece psi
+    double a;           // 2 sqrt(l0 l2) / rho
+    double a_plus_s;    // a + s
+    double ridge;       // rho / (rho + 2 l2)
+    double thr_lin;     // l0 / (M rho) + l2 M / rho
+    double thr_free;    // a if free_quad else thr_lin
+    double thr_free_M;  // thr_free + M
+    double two_M_l2;    // 2 M l2
+    double four_l2;     // 4 l2
+    double l2_M2;       // l2 M M
+    double psi_lin;     // 2 sqrt(l0 l2) if free_quad else l0 / M + l2 M
+};
+
+struct Instance {
+    int64_t n = 0, p = 0, np = 0, pp = 0;   // true and padded sizes
+    int prec = L0L2_FP64;
+    MethodParams mp{};
+    double yy = 0.0;                         // ||y||^2
+    DevBuf X64;       // np x pp column-major FP64, zero padded
+    DevBuf y64;       // np
+    DevBuf c64;       // pp, X^T y
+    DevBuf colnrm;    // pp, ||X_j||
+    DevBuf cst;       // pp, c in state precision
+    DevBuf Xh;        // np x pp column-major, L^{-1} X in working precision (f64 / f32 / bf16)
+    DevBuf XhR;       // bf16 only: row-major copy (row i contiguous over pp)
+    DevBuf codes_pad; // scratch
+};
+
+// Per-batch workspace, grown on demand (capacity in padded nodes).
+struct Workspace {
+    int64_t cap = 0;
+    DevBuf W, beta, V, B;          // Kp x pp state precision
+    DevBuf U;                      // Kp x np state precision (ADMM product)
+    DevBuf Ub, Ubeta, R;           // Kp x np FP64
+    DevBuf codes;                  // Kp x pp uint8
+    DevBuf nodescal;               // Kp x 8 doubles: rr, yr, ayr, rbrb, ...
+    DevBuf part;                   // Kp x (pp/32) x 3 doubles
+    DevBuf active, iters, status;  // Kp int32
+    DevBuf lb, primal;             // Kp doubles
+    DevBuf counter;                // int32 number of active nodes
+    DevBuf fista;                  // FP64 residual scratch for the incumbent kernels
+    int *host_counter = nullptr;   // pinned
+};
+
+enum { PROF_GEMM_XW = 0, PROF_ADMM_XTU, PROF_CHECK, PROF_ROUND, PROF_FISTA, kProfCount };
+extern const char *const kProfNames[kProfCount];
+
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;
+    std::vector<std::pair<int, hipEvent_t>> open;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pairs;
+    double total_ms[kProfCount] = {0, 0, 0, 0, 0};
+    int64_t count[kProfCount] = {0, 0, 0, 0, 0};
+};
+
+}  // namespace l0l2
+
+struct l0l2_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    bool has_data = false;
+    l0l2::Instance inst;
+    l0l2::Workspace ws;
+    l0l2::Profiler prof;
+};
+
+namespace l0l2 {
+
+// precompute.hip
+void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p, double l0,
+              double l2, double M, double rho, int prec, int on_device);
+MethodParams make_params(double l0, double l2, double M, double rho);
+
+// admm.hip
+void ensure_workspace(l0l2_ctx *ctx, int64_t K);
+void load_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *beta, const void *v,
+                bool codes_on_host);
+void store_batch(l0l2_ctx *ctx, int K, void *beta, void *v, void *b);
+void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool store_b_last);
+void run_dual_bound(l0l2_ctx *ctx, int K, const void *b_internal_or_null);
+// Solve the K nodes loaded in the workspace; results stay in ws.lb/primal/iters/status.
+void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o);
+
+// incumbent.hip
+void run_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, int64_t ld_codes, const void *beta, int64_t ld_beta,
+                      uint8_t *support, int32_t *support_size, int32_t *branch_j, int32_t *z_up,
+                      int32_t *nfree);
+void run_fista(l0l2_ctx *ctx, int K, const uint8_t *support, int64_t ld_support, double *beta,
+               int64_t ld_beta, const l0l2_fista_opts &o, double *obj, int32_t *iters);
+double run_exact_objective(l0l2_ctx *ctx, const uint8_t *support_host, double *beta_host);
+// state (f32 or f64, ld_src) -> f64 (ld_dst) copy of K rows of length p
+void state_to_f64(l0l2_ctx *ctx, int K, const void *src, int64_t ld_src, double *dst, int64_t ld_dst);
+
+// bnb.cpp
+void bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out);
+
+// prof.hip
+void prof_begin(l0l2_ctx *ctx, int id);
+void prof_end(l0l2_ctx *ctx, int id);
+void prof_collect(l0l2_ctx *ctx);
+void prof_release(Profiler &p);
+
+inline size_t state_bytes(int prec) { return prec == L0L2_FP64 ? 8 : 4; }
+
+}  // namespace l0l2

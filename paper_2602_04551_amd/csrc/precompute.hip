@@ -1,0 +1,353 @@
+// Once-per-instance precompute (Sec. 3.1.1, update for b): c = X^T y, column
+// norms, S = X X^T + rho I, its Cholesky factor L, and the folded operand
+// Xh = L^{-1} X so that D w = (w - Xh^T (Xh w)) / rho for D = (X^T X + rho I)^{-1}
+// (the Woodbury identity with the 1/rho factor; Xh^T Xh = X^T S^{-1} X).
+#include <cmath>
+#include <cstring>
+
+#include "device_math.hpp"
+#include "internal.hpp"
+
+namespace l0l2 {
+
+namespace {
+
+// dst (np x pp, ld = np) <- src (n x p, ld = n), zero padding.
+__global__ void k_pad_copy(const double *__restrict__ src, int64_t n, int64_t p, double *__restrict__ dst,
+                           int64_t np, int64_t pp) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = np * pp;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx % np, j = idx / np;
+        dst[idx] = (i < n && j < p) ? src[i + j * n] : 0.0;
+    }
+}
+
+// One wave per column: c_j = X_j^T y and ||X_j||.
+__global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ X, const double *__restrict__ y,
+                                                  int64_t np, int64_t pp, double *__restrict__ c,
+                                                  double *__restrict__ nrm) {
+    int lane = threadIdx.x & 63;
+    int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= pp) return;
+    const double *col = X + j * np;
+    double s = 0.0, q = 0.0;
+    for (int64_t i = lane; i < np; i += 64) {
+        double x = col[i];
+        s += x * y[i];
+        q += x * x;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        s += __shfl_xor(s, off);
+        q += __shfl_xor(q, off);
+    }
+    if (lane == 0) {
+        c[j] = s;
+        nrm[j] = sqrt(q);
+    }
+}
+
+// C[i + j*ldc] = alpha * sum_k A(i,k) B(k,j) + beta * C[i + j*ldc] for i < M, j < N,
+// A(i,k) = A[i*sai + k*sak], B(k,j) = B[k*sbk + j*sbj].  64x64 tiles, FP64 MFMA.
+__global__ __launch_bounds__(256) void k_dgemm(int64_t M, int64_t N, int64_t K, double alpha,
+                                               const double *__restrict__ A, int64_t sai, int64_t sak,
+                                               const double *__restrict__ B, int64_t sbk, int64_t sbj,
+                                               double beta, double *__restrict__ C, int64_t ldc) {
+    __shared__ double As[16][64 + 1];
+    __shared__ double Bs[16][64 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int64_t m0 = (int64_t)blockIdx.x * 64, n0 = (int64_t)blockIdx.y * 64;
+    f64x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+    const bool a_i_fast = (sai == 1);
+    const bool b_j_fast = (sbj == 1);
+    for (int64_t k0 = 0; k0 < K; k0 += 16) {
+        for (int r = 0; r < 4; ++r) {
+            int e = tid + 256 * r;
+            int il, kl;
+            if (a_i_fast) { il = e & 63; kl = e >> 6; } else { kl = e & 15; il = e >> 4; }
+            int64_t gi = m0 + il, gk = k0 + kl;
+            As[kl][il] = (gi < M && gk < K) ? A[gi * sai + gk * sak] : 0.0;
+            int jl, kl2;
+            if (b_j_fast) { jl = e & 63; kl2 = e >> 6; } else { kl2 = e & 15; jl = e >> 4; }
+            int64_t gj = n0 + jl, gk2 = k0 + kl2;
+            Bs[kl2][jl] = (gj < N && gk2 < K) ? B[gk2 * sbk + gj * sbj] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < 4; ++kk) {
+            int krow = kk * 4 + (lane >> 4);
+            double av[2], bv[2];
+            for (int a = 0; a < 2; ++a) av[a] = As[krow][wm * 32 + a * 16 + (lane & 15)];
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[krow][wn * 32 + b * 16 + (lane & 15)];
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) acc[a][b] = mfma16(av[a], bv[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int v = 0; v < 4; ++v) {
+                int64_t gi = m0 + wm * 32 + a * 16 + acc_row<double>(lane, v);
+                int64_t gj = n0 + wn * 32 + b * 16 + (lane & 15);
+                if (gi < M && gj < N) {
+                    double old = beta != 0.0 ? C[gi + gj * ldc] : 0.0;
+                    C[gi + gj * ldc] = alpha * acc[a][b][v] + beta * old;
+                }
+            }
+}
+
+// In-place lower Cholesky of the nb x nb diagonal block at S + kb*(ld+1).
+__global__ __launch_bounds__(256) void k_potrf_diag(double *S, int64_t ld, int64_t kb, int nb, int *fail_flag) {
+    __shared__ double L[64][65];
+    const int tid = threadIdx.x;
+    double *blk = S + kb * ld + kb;
+    for (int e = tid; e < nb * nb; e += 256) {
+        int i = e % nb, j = e / nb;
+        L[i][j] = blk[i + j * ld];
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+            double d = L[j][j];
+            if (!(d > 0.0)) {
+                *fail_flag = 1;
+                d = 1.0;
+            }
+            L[j][j] = sqrt(d);
+        }
+        __syncthreads();
+        for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] /= L[j][j];
+        __syncthreads();
+        int rem = nb - j - 1;
+        for (int e = tid; e < rem * rem; e += 256) {
+            int i = j + 1 + e % rem, k = j + 1 + e / rem;
+            if (k <= i) L[i][k] -= L[i][j] * L[k][j];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < nb * nb; e += 256) {
+        int i = e % nb, j = e / nb;
+        blk[i + j * ld] = (i >= j) ? L[i][j] : 0.0;
+    }
+}
+
+// Rows [r0, r0 + nrows) of the panel S[:, kb:kb+nb] <- panel * L_kk^{-T}: one
+// thread per row, row data in LDS.
+__global__ __launch_bounds__(64) void k_trsm_panel(double *S, int64_t ld, int64_t kb, int nb, int64_t r0,
+                                                   int64_t nrows) {
+    __shared__ double L[64][65];
+    __shared__ double Xr[64][65];
+    const int t = threadIdx.x;
+    const double *Lkk = S + kb * ld + kb;
+    for (int e = t; e < nb * nb; e += 64) {
+        int i = e % nb, j = e / nb;
+        L[i][j] = Lkk[i + j * ld];
+    }
+    int64_t row = r0 + (int64_t)blockIdx.x * 64 + t;
+    bool ok = (row - r0) < nrows;
+    for (int j = 0; j < nb; ++j) Xr[t][j] = ok ? S[row + (kb + j) * ld] : 0.0;
+    __syncthreads();
+    if (!ok) return;
+    for (int j = 0; j < nb; ++j) {
+        double s = Xr[t][j];
+        for (int k = 0; k < j; ++k) s -= Xr[t][k] * L[j][k];
+        Xr[t][j] = s / L[j][j];
+    }
+    for (int j = 0; j < nb; ++j) S[row + (kb + j) * ld] = Xr[t][j];
+}
+
+// Columns of the row block X[kb:kb+nb, :] <- L_kk^{-1} X[kb:kb+nb, :] (forward
+// substitution, one thread per column).
+__global__ __launch_bounds__(64) void k_trsv_rows(const double *S, int64_t lds, double *X, int64_t ldx,
+                                                  int64_t kb, int nb, int64_t ncols) {
+    __shared__ double L[64][65];
+    __shared__ double Xc[64][65];
+    const int t = threadIdx.x;
+    const double *Lkk = S + kb * lds + kb;
+    for (int e = t; e < nb * nb; e += 64) {
+        int i = e % nb, j = e / nb;
+        L[i][j] = Lkk[i + j * lds];
+    }
+    int64_t col = (int64_t)blockIdx.x * 64 + t;
+    bool ok = col < ncols;
+    for (int i = 0; i < nb; ++i) Xc[t][i] = ok ? X[kb + i + col * ldx] : 0.0;
+    __syncthreads();
+    if (!ok) return;
+    for (int i = 0; i < nb; ++i) {
+        double s = Xc[t][i];
+        for (int k = 0; k < i; ++k) s -= L[i][k] * Xc[t][k];
+        Xc[t][i] = s / L[i][i];
+    }
+    for (int i = 0; i < nb; ++i) X[kb + i + col * ldx] = Xc[t][i];
+}
+
+__global__ void k_add_diag(double *S, int64_t ld, int64_t n, double r) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) S[i + i * ld] += r;
+}
+
+__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, int64_t total) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) dst[idx] = (float)src[idx];
+}
+
+// bf16 column-major copy and row-major copy of the np x pp column-major src.
+__global__ void k_to_bf16(const double *__restrict__ src, __bf16 *__restrict__ colmaj, __bf16 *__restrict__ rowmaj,
+                          int64_t np, int64_t pp) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = np * pp;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx % np, j = idx / np;
+        __bf16 v = (__bf16)(float)src[idx];
+        colmaj[idx] = v;
+        rowmaj[i * pp + j] = v;
+    }
+}
+
+void dgemm(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t sai,
+           int64_t sak, const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc) {
+    if (M <= 0 || N <= 0) return;
+    dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
+    hipLaunchKernelGGL(k_dgemm, grid, dim3(256), 0, st, M, N, K, alpha, A, sai, sak, B, sbk, sbj, beta, C, ldc);
+    HIPCHK(hipGetLastError());
+}
+
+}  // namespace
+
+MethodParams make_params(double l0, double l2, double M, double rho) {
+    MethodParams q{};
+    q.l0 = l0; q.l2 = l2; q.M = M; q.rho = rho;
+    q.s = sqrt(l0 / l2);
+    q.free_quad = q.s <= M;
+    q.a = 2.0 * sqrt(l0 * l2) / rho;
+    q.a_plus_s = q.a + q.s;
+    q.ridge = rho / (rho + 2.0 * l2);
+    q.thr_lin = l0 / (M * rho) + l2 * M / rho;
+    q.thr_free = q.free_quad ? q.a : q.thr_lin;
+    q.thr_free_M = q.thr_free + M;
+    q.two_M_l2 = 2.0 * M * l2;
+    q.four_l2 = 4.0 * l2;
+    q.l2_M2 = l2 * M * M;
+    q.psi_lin = q.free_quad ? 2.0 * sqrt(l0 * l2) : (l0 / M + l2 * M);
+    return q;
+}
+
+void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p, double l0, double l2,
+              double M, double rho, int prec, int on_device) {
+    Instance &in = ctx->inst;
+    hipStream_t st = ctx->stream;
+    ctx->has_data = false;
+    // the per-batch workspace is sized for the previous instance: drop it
+    ctx->ws.cap = 0;
+    in.n = n;
+    in.p = p;
+    in.np = round_up(n, kPadRows);
+    in.pp = round_up(p, kPadRows);
+    in.prec = prec;
+    in.mp = make_params(l0, l2, M, rho);
+    const int64_t np = in.np, pp = in.pp;
+
+    // Stage X and y on the device unpadded, then pad.
+    DevBuf Xraw, yraw;
+    const double *dX = X, *dy = y;
+    if (!on_device) {
+        Xraw.ensure(sizeof(double) * (size_t)(n * p));
+        yraw.ensure(sizeof(double) * (size_t)n);
+        HIPCHK(hipMemcpyAsync(Xraw.ptr, X, sizeof(double) * (size_t)(n * p), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(yraw.ptr, y, sizeof(double) * (size_t)n, hipMemcpyHostToDevice, st));
+        dX = Xraw.as<double>();
+        dy = yraw.as<double>();
+    }
+    in.X64.ensure(sizeof(double) * (size_t)(np * pp));
+    in.y64.ensure(sizeof(double) * (size_t)np);
+    in.c64.ensure(sizeof(double) * (size_t)pp);
+    in.colnrm.ensure(sizeof(double) * (size_t)pp);
+    hipLaunchKernelGGL(k_pad_copy, dim3(2048), dim3(256), 0, st, dX, n, p, in.X64.as<double>(), np, pp);
+    hipLaunchKernelGGL(k_pad_copy, dim3(64), dim3(256), 0, st, dy, n, (int64_t)1, in.y64.as<double>(), np,
+                       (int64_t)1);
+    hipLaunchKernelGGL(k_colstats, dim3((unsigned)((pp + 3) / 4)), dim3(256), 0, st, in.X64.as<double>(),
+                       in.y64.as<double>(), np, pp, in.c64.as<double>(), in.colnrm.as<double>());
+    HIPCHK(hipGetLastError());
+
+    // S = X X^T + rho I (n x n, ld = np), then its Cholesky factor in place.
+    DevBuf S, flag;
+    S.ensure(sizeof(double) * (size_t)(np * np));
+    flag.ensure(sizeof(int));
+    HIPCHK(hipMemsetAsync(S.ptr, 0, sizeof(double) * (size_t)(np * np), st));
+    HIPCHK(hipMemsetAsync(flag.ptr, 0, sizeof(int), st));
+    const double *X64 = in.X64.as<double>();
+    dgemm(st, n, n, p, 1.0, X64, 1, np, X64, np, 1, 0.0, S.as<double>(), np);
+    hipLaunchKernelGGL(k_add_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S.as<double>(), np, n,
+                       rho);
+    HIPCHK(hipGetLastError());
+    double *Sd = S.as<double>();
+    for (int64_t kb = 0; kb < n; kb += 64) {
+        int nb = (int)std::min<int64_t>(64, n - kb);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, Sd, np, kb, nb, flag.as<int>());
+        int64_t r0 = kb + nb, rem = n - r0;
+        if (rem > 0) {
+            hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)((rem + 63) / 64)), dim3(64), 0, st, Sd, np, kb, nb,
+                               r0, rem);
+            // trailing update S[r0:, r0:] -= P P^T, P = S[r0:, kb:kb+nb]
+            const double *P = Sd + r0 + kb * np;
+            dgemm(st, rem, rem, nb, -1.0, P, 1, np, P, np, 1, 1.0, Sd + r0 + r0 * np, np);
+        }
+        HIPCHK(hipGetLastError());
+    }
+    int hflag = 0;
+    HIPCHK(hipMemcpyAsync(&hflag, flag.ptr, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hflag) fail(L0L2_E_NUMERIC, "Cholesky of X X^T + rho I failed (not positive definite)");
+
+    // Xh = L^{-1} X, blocked forward substitution over row blocks of 64.
+    DevBuf Xh64;
+    double *Xh;
+    if (prec == L0L2_FP64) {
+        in.Xh.ensure(sizeof(double) * (size_t)(np * pp));
+        Xh = in.Xh.as<double>();
+    } else {
+        Xh64.ensure(sizeof(double) * (size_t)(np * pp));
+        Xh = Xh64.as<double>();
+    }
+    HIPCHK(hipMemcpyAsync(Xh, X64, sizeof(double) * (size_t)(np * pp), hipMemcpyDeviceToDevice, st));
+    for (int64_t kb = 0; kb < n; kb += 64) {
+        int nb = (int)std::min<int64_t>(64, n - kb);
+        hipLaunchKernelGGL(k_trsv_rows, dim3((unsigned)((p + 63) / 64)), dim3(64), 0, st, Sd, np, Xh, np, kb, nb,
+                           p);
+        int64_t r0 = kb + nb, rem = n - r0;
+        if (rem > 0) {
+            // X[r0:, :] -= L[r0:, kb:kb+nb] * Xh[kb:kb+nb, :]
+            dgemm(st, rem, p, nb, -1.0, Sd + r0 + kb * np, 1, np, Xh + kb, 1, np, 1.0, Xh + r0, np);
+        }
+        HIPCHK(hipGetLastError());
+    }
+    if (prec == L0L2_FP32) {
+        in.Xh.ensure(sizeof(float) * (size_t)(np * pp));
+        hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, st, Xh, in.Xh.as<float>(), np * pp);
+        in.cst.ensure(sizeof(float) * (size_t)pp);
+        hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), pp);
+    } else if (prec == L0L2_BF16) {
+        in.Xh.ensure(sizeof(__bf16) * (size_t)(np * pp));
+        in.XhR.ensure(sizeof(__bf16) * (size_t)(np * pp));
+        hipLaunchKernelGGL(k_to_bf16, dim3(4096), dim3(256), 0, st, Xh, in.Xh.as<__bf16>(), in.XhR.as<__bf16>(),
+                           np, pp);
+        in.cst.ensure(sizeof(float) * (size_t)pp);
+        hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), pp);
+    } else {
+        in.cst.ensure(sizeof(double) * (size_t)pp);
+        HIPCHK(hipMemcpyAsync(in.cst.ptr, in.c64.ptr, sizeof(double) * (size_t)pp, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipGetLastError());
+    // ||y||^2 on the host (one small copy)
+    std::vector<double> hy((size_t)n);
+    HIPCHK(hipMemcpyAsync(hy.data(), in.y64.ptr, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double yy = 0.0;
+    for (double v : hy) yy += v * v;
+    in.yy = yy;
+    ctx->has_data = true;
+}
+
+}  // namespace l0l2

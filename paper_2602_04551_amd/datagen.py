@@ -27,7 +27,7 @@ from __future__ import annotations
 import dataclasses
 import numpy as np
 
-__all__ = ["Instance", "make_instance", "CONFIGS", "config_instance", "node_batch_codes",
+__all__ = ["Instance", "make_instance", "CONFIGS", "config_instance", "node_batch_codes", "frontier_codes",
            "FREE", "FIX0", "FIX1"]
 
 FREE, FIX0, FIX1 = 0, 1, 2
@@ -153,4 +153,21 @@ def node_batch_codes(p: int, K: int, *, seed: int = 0, free_min: int = 50, free_
         n1 = int(rng.integers(0, min(fix1_max, len(rest)) + 1)) if len(rest) else 0
         codes[k, free] = FREE
         codes[k, rest[:n1]] = FIX1
+    return codes
+
+
+def frontier_codes(p: int, K: int, candidates, *, seed: int = 0, depth_min: int = 1,
+                   depth_max: int = 16) -> np.ndarray:
+    """K synthetic best-first frontier nodes as a (K, p) uint8 array of codes.
+
+    Node k fixes d ~ U{depth_min..depth_max} distinct coordinates drawn from
+    `candidates` (the coordinates a tree near the root branches on), each to
+    z = 0 or z = 1 with probability 1/2; every other coordinate is free."""
+    rng = np.random.default_rng(seed)
+    cand = np.asarray(candidates, dtype=np.int64)
+    codes = np.zeros((K, p), dtype=np.uint8)
+    for k in range(K):
+        d = int(rng.integers(depth_min, min(depth_max, len(cand)) + 1))
+        idx = rng.choice(cand, size=d, replace=False)
+        codes[k, idx] = rng.choice([FIX0, FIX1], size=d)
     return codes

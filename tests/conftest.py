@@ -19,3 +19,11 @@ def orc():
     if not os.path.exists(oracle.LIB_PATH):
         oracle.build()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    """Name each GPU test (and flush) before it touches the device."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[case] {request.node.nodeid}", flush=True)
+    yield
