@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"fp32": 157.3, "fp64": 78.6}          # dense MFMA TFLOP/s, MI355X
+PEAK = {"f32": 157.3, "f64": 78.6}          # dense MFMA TFLOP/s, MI355X
 METRIC = "node relaxations/s + time-to-certified-optimum, mixed vs FP64 GPU path"
 
 
@@ -112,6 +112,24 @@ def cpu_baseline(path, seconds):
                        f"starts), single-threaded FP64 oracle, {dt:.1f} s")
 
 
+def roofline(prof, n, p):
+    """Dominant sweep contraction by measured time; achieved = algorithmic flops
+    (2 n p per active node-iteration) over its summed launch durations."""
+    sweep = [k for k in prof if k.startswith(("gemm_xw", "admm_xtu")) and prof[k][0] > 0]
+    kname = max(sweep, key=lambda k: prof[k][1])
+    launches, ms, units = prof[kname]
+    prec = kname.split(".")[1]
+    achieved = 2.0 * n * p * units / (ms * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[prec], 4), "traffic": None, "kernel": kname,
+            "launches": launches, "avg_us": round(1e3 * ms / max(launches, 1), 3),
+            "flops_per_launch": round(2.0 * n * p * units / max(launches, 1)),
+            "node_iterations": units}
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 3), "node_iterations": v[2]} for k, v in prof.items()
+               if v[0] > 0}
+    return roof, kernels
+
+
 def run_path(path, steps, warmup):
     torch = path.torch
     for _ in range(warmup):
@@ -126,7 +144,7 @@ def run_path(path, steps, warmup):
         its += i
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    prof = {k: path.ctx.profile_query(k) for k in ("gemm_xw", "admm_xtu", "gap_check", "round_branch", "fista")}
+    prof = {k: path.ctx.profile_query(k) for k in path.ctx.KERNELS}
     path.ctx.profile_enable(False)
     return dt, its, prof
 
@@ -147,23 +165,12 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = K * args.steps / dt
 
-    # dominant kernel of the sweep and its roofline (algorithmic flops of the
-    # active node-iterations: 2 n p per node-iteration per contraction)
-    kname = max(("gemm_xw", "admm_xtu"), key=lambda k: prof[k][1])
-    launches, kms = prof[kname]
-    flops = 2.0 * n * p * its
-    achieved = flops / (kms * 1e-3) / 1e12
-    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp32"], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK["fp32"], 4), "traffic": None, "kernel": kname,
-            "launches": launches, "avg_us": round(1e3 * kms / max(launches, 1), 3),
-            "node_iterations": its}
-    kernels_ms = {k: round(v[1], 3) for k, v in prof.items()}
-
+    roof, kernels = roofline(prof, n, p)
     fp64 = Path(inst, "fp64", K)
-    dt64, its64, prof64 = run_path(fp64, max(2, args.steps // 2), 1)
-    value64 = K * max(2, args.steps // 2) / dt64
-    k64 = max(("gemm_xw", "admm_xtu"), key=lambda k: prof64[k][1])
-    ach64 = 2.0 * n * p * its64 / (prof64[k64][1] * 1e-3) / 1e12
+    steps64 = max(2, args.steps // 2)
+    dt64, its64, prof64 = run_path(fp64, steps64, 1)
+    value64 = K * steps64 / dt64
+    roof64, kernels64 = roofline(prof64, n, p)
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "node relaxations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -175,10 +182,9 @@ def main():
                       "batch": "frontier nodes: 1-16 fixings among the 64 largest root coordinates, "
                                "warm-started from the root"},
            "roofline": roof,
-           "kernels_ms": kernels_ms,
+           "kernels": kernels,
            "fp64_path": {"value": round(value64, 2), "unit": "node relaxations/s",
-                         "roofline": {"kernel": k64, "achieved": round(ach64, 3), "peak": PEAK["fp64"],
-                                      "frac": round(ach64 / PEAK["fp64"], 4)}},
+                         "ms_per_step": round(1e3 * dt64 / steps64, 3), "roofline": roof64, "kernels": kernels64},
            "set_data_s": {"fp32": round(mixed.set_data_s, 4), "fp64": round(fp64.set_data_s, 4)}}
 
     if not args.no_ttco:

@@ -44,7 +44,9 @@ enum {
 };
 
 /* Precision of the X products inside the ADMM sweep.  FP64: everything in FP64.
- * FP32: products and node state in FP32.  BF16: the transformed design matrix is
+ * FP32 (mixed): sweeps in FP32 while a batch converges, then FP64 sweeps from the
+ * FP32 iterates until each node meets its tolerance (the FP32 iterates alone
+ * stall near a relative gap of 1e-6 .. 1e-5); node state returned in FP32.  BF16: the transformed design matrix is
  * stored in BF16, the node operand is split into two BF16 halves, accumulation
  * and node state are FP32.  In every mode the dual bound and the incumbent
  * objective are computed in FP64 with the original X. */
@@ -182,12 +184,17 @@ void l0l2_result_free(l0l2_bnb_result *res);
  * context stream around each launch (adds one event pair per launch).
  * l0l2_profile_enable clears the counters and switches timing on (1) or off (0).
  * l0l2_profile_query returns the number of timed launches and their summed
- * duration in milliseconds for one kernel family: "gemm_xw" (contraction over
- * p of a sweep), "admm_xtu" (contraction over n with the prox/V epilogue),
- * "gap_check" (the FP64 gap evaluation, all of its kernels), "round_branch",
- * "fista".  Unknown names give L0L2_E_INVALID. */
+ * duration in milliseconds for one kernel family: "gemm_xw.f32" / "gemm_xw.f64"
+ * (contraction over p of a sweep in FP32 / FP64), "admm_xtu.f32" /
+ * "admm_xtu.f64" (contraction over n with the prox/V epilogue), "gap_check"
+ * (the FP64 gap evaluation, all of its kernels), "round_branch", "fista".
+ * units (may be NULL) receives the work the timed launches did: for the sweep
+ * families the number of node-iterations of nodes that were still active
+ * (columns of converged nodes are not counted).  Unknown names give
+ * L0L2_E_INVALID. */
 int l0l2_profile_enable(l0l2_ctx *ctx, int enable);
-int l0l2_profile_query(l0l2_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms);
+int l0l2_profile_query(l0l2_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms,
+                       int64_t *units);
 
 #ifdef __cplusplus
 }

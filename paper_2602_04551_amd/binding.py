@@ -69,7 +69,7 @@ SIGNATURES = {
     "l0l2_bnb_solve": (_i, [_vp, C.POINTER(l0l2_bnb_opts), C.POINTER(l0l2_bnb_result)]),
     "l0l2_result_free": (None, [C.POINTER(l0l2_bnb_result)]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
-    "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d)]),
+    "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
 }
 
 
@@ -228,10 +228,13 @@ class Context:
     def profile_enable(self, enable=True):
         self._check(lib.l0l2_profile_enable(self._h, 1 if enable else 0))
 
+    KERNELS = ("gemm_xw.f32", "admm_xtu.f32", "gemm_xw.f64", "admm_xtu.f64", "gap_check", "round_branch", "fista")
+
     def profile_query(self, kernel):
-        n, ms = C.c_int64(), C.c_double()
-        self._check(lib.l0l2_profile_query(self._h, kernel.encode(), C.byref(n), C.byref(ms)))
-        return n.value, ms.value
+        """(launches, total milliseconds, work units) of one timed kernel family."""
+        n, ms, u = C.c_int64(), C.c_double(), C.c_int64()
+        self._check(lib.l0l2_profile_query(self._h, kernel.encode(), C.byref(n), C.byref(ms), C.byref(u)))
+        return n.value, ms.value, u.value
 
     def bnb_solve(self, K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000,
                   check_every=10, eps_prune=None, gap_tol=0.0, time_limit_s=0.0, max_nodes=10**9,

@@ -356,7 +356,7 @@ __global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, 
 }
 
 struct FinArgs {
-    double gamma_n2, gamma_p, tol;
+    double gamma_n2, gamma_p, tol, switch_tol;
     int64_t K, ntile;
     int iter, mode;  // mode 0: solve (gap test), 1: bound only
 };
@@ -369,9 +369,9 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ nod
                                                   int *__restrict__ status, int *__restrict__ iters,
                                                   double *__restrict__ lb, double *__restrict__ primal,
                                                   int *__restrict__ counter, FinArgs fa) {
-    __shared__ int shc[256];
+    __shared__ int shc[256], shc2[256];
     const double u = 1.1102230246251565e-16;
-    int cnt = 0;
+    int cnt = 0, cnt2 = 0;
     for (int64_t k = threadIdx.x; k < fa.K; k += 256) {
         if (!active[k]) continue;
         double rr = nodescal[k * 8 + 0], yr = nodescal[k * 8 + 1], ayr = nodescal[k * 8 + 2];
@@ -398,26 +398,86 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ nod
         } else {
             status[k] = 1;
             ++cnt;
+            if ((P - LB) / den > fa.switch_tol) ++cnt2;
         }
     }
     shc[threadIdx.x] = cnt;
+    shc2[threadIdx.x] = cnt2;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) shc[threadIdx.x] += shc[threadIdx.x + s];
+        if ((int)threadIdx.x < s) {
+            shc[threadIdx.x] += shc[threadIdx.x + s];
+            shc2[threadIdx.x] += shc2[threadIdx.x + s];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) *counter = shc[0];
+    if (threadIdx.x == 0) {
+        counter[0] = shc[0];
+        counter[1] = shc2[0];
+    }
 }
 
-template <class T> T *st(const DevBuf &b) { return b.as<T>(); }
+// Ladder step: FP64 copies of the FP32 node state, W64 = c + rho beta - V.
+__global__ void k_promote(const float *__restrict__ beta, const float *__restrict__ V, double *__restrict__ beta64,
+                          double *__restrict__ V64, double *__restrict__ W64, const double *__restrict__ c,
+                          double rho, int64_t pp, int64_t total) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        double b = (double)beta[idx], v = (double)V[idx];
+        beta64[idx] = b;
+        V64[idx] = v;
+        W64[idx] = c[idx % pp] + rho * b - v;
+    }
+}
+
+__global__ void k_demote(const double *__restrict__ beta64, const double *__restrict__ V64, float *__restrict__ beta,
+                         float *__restrict__ V, int64_t total) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        beta[idx] = (float)beta64[idx];
+        V[idx] = (float)V64[idx];
+    }
+}
 
 unsigned grid1d(int64_t total) { return (unsigned)std::min<int64_t>((total + 255) / 256, 65536); }
 
+// The arrays one sweep works on, in the arithmetic type T of the sweep.
+template <class T>
+struct Sweep {
+    const T *Xh;   // np x pp folded operand
+    const T *c;    // pp
+    T *W, *beta, *V, *B, *U;
+};
+
+Sweep<double> sweep64(l0l2_ctx *ctx) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    if (in.prec == L0L2_FP64)
+        return {in.Xh.as<double>(), in.c64.as<double>(), ws.W.as<double>(), ws.beta.as<double>(), ws.V.as<double>(),
+                ws.B.as<double>(), ws.U.as<double>()};
+    return {in.Xh64.as<double>(), in.c64.as<double>(), ws.W64.as<double>(), ws.beta64.as<double>(),
+            ws.V64.as<double>(), ws.B64.as<double>(), ws.U64.as<double>()};
+}
+
+Sweep<float> sweep32(l0l2_ctx *ctx) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    return {in.Xh.as<float>(), in.cst.as<float>(), ws.W.as<float>(), ws.beta.as<float>(), ws.V.as<float>(),
+            ws.B.as<float>(), ws.U.as<float>()};
+}
+
+template <class T> constexpr int prof_xw();
+template <> constexpr int prof_xw<float>() { return PROF_GEMM_XW_F32; }
+template <> constexpr int prof_xw<double>() { return PROF_GEMM_XW_F64; }
+template <class T> constexpr int prof_xtu();
+template <> constexpr int prof_xtu<float>() { return PROF_ADMM_XTU_F32; }
+template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
+
 // ---------------------------------------------------------------------------
-// Host drivers, templated on the state type T (double for FP64, float otherwise)
+// Host drivers
 // ---------------------------------------------------------------------------
 template <class T>
-void sweep_once(l0l2_ctx *ctx, int64_t Kp, bool store_b) {
+void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int64_t active) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
@@ -425,15 +485,13 @@ void sweep_once(l0l2_ctx *ctx, int64_t Kp, bool store_b) {
     dim3 g1((unsigned)(np / 32), (unsigned)(Kp / 32));
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     DevParams<T> q = dev_params<T>(in.mp);
-    prof_begin(ctx, PROF_GEMM_XW);
-    hipLaunchKernelGGL((k_gemm_xw<T, T, T>), g1, dim3(256), 0, s, in.Xh.as<T>(), np, st<T>(ws.W), pp, st<T>(ws.U), np,
-                       pp);
-    prof_end(ctx, PROF_GEMM_XW);
-    prof_begin(ctx, PROF_ADMM_XTU);
-    hipLaunchKernelGGL((k_admm_xtu<T, T>), g2, dim3(256), 0, s, in.Xh.as<T>(), np, st<T>(ws.U), np, np, st<T>(ws.W),
-                       st<T>(ws.beta), st<T>(ws.V), st<T>(ws.B), ws.codes.as<uint8_t>(), in.cst.as<T>(),
-                       ws.active.as<int>(), q, pp, store_b ? 1 : 0);
-    prof_end(ctx, PROF_ADMM_XTU);
+    prof_begin(ctx, prof_xw<T>());
+    hipLaunchKernelGGL((k_gemm_xw<T, T, T>), g1, dim3(256), 0, s, sw.Xh, np, sw.W, pp, sw.U, np, pp);
+    prof_end(ctx, prof_xw<T>(), active);
+    prof_begin(ctx, prof_xtu<T>());
+    hipLaunchKernelGGL((k_admm_xtu<T, T>), g2, dim3(256), 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, sw.B,
+                       ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp, store_b ? 1 : 0);
+    prof_end(ctx, prof_xtu<T>(), active);
     HIPCHK(hipGetLastError());
 }
 
@@ -448,9 +506,11 @@ DualArgs dual_args(const Instance &in) {
     return d;
 }
 
-// FP64 check at the current (B, beta): fills ws.lb / primal / status / active.
+// FP64 check at (B, beta) of type T: fills ws.lb / primal / status / active and
+// the two counters (active nodes; active nodes above switch_tol).
 template <class T>
-void check_once(l0l2_ctx *ctx, int64_t K, int64_t Kp, int iter, double tol, int mode) {
+void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t K, int64_t Kp, int iter, double tol,
+                double switch_tol, int mode) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
@@ -459,23 +519,24 @@ void check_once(l0l2_ctx *ctx, int64_t K, int64_t Kp, int iter, double tol, int 
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     const double *X64 = in.X64.as<double>();
     prof_begin(ctx, PROF_CHECK);
-    hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, st<T>(ws.B), pp,
-                       ws.Ub.as<double>(), np, pp);
+    hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, B, pp, ws.Ub.as<double>(), np,
+                       pp);
     if (mode == 0)
-        hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, st<T>(ws.beta), pp,
+        hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, beta, pp,
                            ws.Ubeta.as<double>(), np, pp);
     hipLaunchKernelGGL(k_resid, dim3((unsigned)K), dim3(256), 0, s, in.y64.as<double>(), ws.Ub.as<double>(),
                        ws.Ubeta.as<double>(), ws.R.as<double>(), np, ws.nodescal.as<double>(), ws.active.as<int>(),
                        mode == 0 ? 1 : 0);
     DualArgs da = dual_args(in);
     hipLaunchKernelGGL((k_dual_xtr<T>), g2, dim3(256), 0, s, X64, np, ws.R.as<double>(), np, np,
-                       ws.codes.as<uint8_t>(), mode == 0 ? st<T>(ws.beta) : st<T>(ws.B), in.colnrm.as<double>(),
-                       ws.nodescal.as<double>(), ws.active.as<int>(), ws.part.as<double>(), pp, da);
+                       ws.codes.as<uint8_t>(), mode == 0 ? beta : B, in.colnrm.as<double>(), ws.nodescal.as<double>(),
+                       ws.active.as<int>(), ws.part.as<double>(), pp, da);
     FinArgs fa;
     const double u = 1.1102230246251565e-16;
     fa.gamma_n2 = ((double)in.n + 2.0) * u / (1.0 - ((double)in.n + 2.0) * u);
     fa.gamma_p = (double)in.p * u / (1.0 - (double)in.p * u);
     fa.tol = tol;
+    fa.switch_tol = switch_tol;
     fa.K = K;
     fa.ntile = pp / 32;
     fa.iter = iter;
@@ -488,44 +549,95 @@ void check_once(l0l2_ctx *ctx, int64_t K, int64_t Kp, int iter, double tol, int 
 }
 
 template <class T>
-void init_batch(l0l2_ctx *ctx, int64_t K, int64_t Kp) {
+void init_batch(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t K, int64_t Kp) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
                        ws.status.as<int>(), ws.iters.as<int>(), K, Kp);
-    hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), st<T>(ws.beta),
-                       st<T>(ws.V), st<T>(ws.W), in.cst.as<T>(), (T)in.mp.rho, in.pp, Kp * in.pp);
+    hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta, sw.V,
+                       sw.W, sw.c, (T)in.mp.rho, in.pp, Kp * in.pp);
     HIPCHK(hipGetLastError());
 }
 
-int read_counter(l0l2_ctx *ctx) {
+void read_counters(l0l2_ctx *ctx, int out[2]) {
     Workspace &ws = ctx->ws;
-    HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    return *ws.host_counter;
+    out[0] = ws.host_counter[0];
+    out[1] = ws.host_counter[1];
 }
 
+// Single-precision-type solve (FP64 mode, or an FP32 run without the ladder).
 template <class T>
-void solve_t(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
+void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts &o) {
     const int64_t Kp = round_up(K, kPadNodes);
-    init_batch<T>(ctx, K, Kp);
+    init_batch<T>(ctx, sw, K, Kp);
     const int m = std::max(1, o.check_every);
+    int cnt[2];
+    int64_t active = K;
     for (int t = 1; t <= o.max_iter; ++t) {
         bool chk = (t % m == 0) || (t == o.max_iter);
-        sweep_once<T>(ctx, Kp, chk);
+        sweep_once<T>(ctx, sw, Kp, chk, active);
         if (chk) {
-            check_once<T>(ctx, K, Kp, t, o.tol_node, 0);
-            if (read_counter(ctx) == 0) break;
+            check_once<T>(ctx, sw.B, sw.beta, K, Kp, t, o.tol_node, o.tol_node, 0);
+            read_counters(ctx, cnt);
+            active = cnt[0];
+            if (cnt[0] == 0) break;
         }
     }
 }
 
-template <class T>
-void sweeps_t(l0l2_ctx *ctx, int K, int sweeps) {
+// Mixed precision (FP32 state): FP32 sweeps while the batch converges, then the
+// remaining active nodes continue in FP64 from their FP32 iterates.  FP32
+// sweeps stop for the batch once every active node's gap is below
+// switch_tol = 50 tol_node, or the number of nodes above it has not dropped
+// for 5 checks, or half the sweep budget is spent.  Bounds are FP64 in both
+// phases; the final iterates are returned in FP32.
+void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
+    Instance &in = ctx->inst;
     const int64_t Kp = round_up(K, kPadNodes);
-    init_batch<T>(ctx, K, Kp);
-    for (int t = 1; t <= sweeps; ++t) sweep_once<T>(ctx, Kp, t == sweeps);
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    init_batch<float>(ctx, s32, K, Kp);
+    const int m = std::max(1, o.check_every);
+    const double switch_tol = 50.0 * o.tol_node;
+    bool fp64 = false;
+    int cnt[2], best_above = 1 << 30, flat = 0;
+    int64_t active = K;
+    for (int t = 1; t <= o.max_iter; ++t) {
+        bool chk = (t % m == 0) || (t == o.max_iter);
+        if (!fp64) sweep_once<float>(ctx, s32, Kp, chk, active);
+        else sweep_once<double>(ctx, s64, Kp, chk, active);
+        if (!chk) continue;
+        if (!fp64) check_once<float>(ctx, s32.B, s32.beta, K, Kp, t, o.tol_node, switch_tol, 0);
+        else check_once<double>(ctx, s64.B, s64.beta, K, Kp, t, o.tol_node, switch_tol, 0);
+        read_counters(ctx, cnt);
+        active = cnt[0];
+        if (cnt[0] == 0) break;
+        if (!fp64) {
+            if (cnt[1] < best_above) { best_above = cnt[1]; flat = 0; }
+            else ++flat;
+            if (cnt[1] == 0 || flat >= 5 || 2 * t >= o.max_iter) {
+                hipLaunchKernelGGL(k_promote, dim3(grid1d(Kp * in.pp)), dim3(256), 0, ctx->stream, s32.beta, s32.V,
+                                   s64.beta, s64.V, s64.W, s64.c, in.mp.rho, in.pp, Kp * in.pp);
+                HIPCHK(hipGetLastError());
+                fp64 = true;
+            }
+        }
+    }
+    if (fp64) {
+        hipLaunchKernelGGL(k_demote, dim3(grid1d(Kp * in.pp)), dim3(256), 0, ctx->stream, s64.beta, s64.V, s32.beta,
+                           s32.V, Kp * in.pp);
+        HIPCHK(hipGetLastError());
+    }
+}
+
+template <class T>
+void sweeps_t(l0l2_ctx *ctx, const Sweep<T> &sw, int K, int sweeps) {
+    const int64_t Kp = round_up(K, kPadNodes);
+    init_batch<T>(ctx, sw, K, Kp);
+    for (int t = 1; t <= sweeps; ++t) sweep_once<T>(ctx, sw, Kp, t == sweeps, K);
 }
 
 }  // namespace
@@ -553,8 +665,16 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.status.ensure(4 * Kp);
     ws.lb.ensure(8 * Kp);
     ws.primal.ensure(8 * Kp);
-    ws.counter.ensure(sizeof(int));
-    if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, sizeof(int), hipHostMallocDefault));
+    ws.counter.ensure(2 * sizeof(int));
+    if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 2 * sizeof(int), hipHostMallocDefault));
+    if (in.prec == L0L2_FP32) {
+        ws.W64.ensure(8 * Kp * pp);
+        ws.beta64.ensure(8 * Kp * pp);
+        ws.V64.ensure(8 * Kp * pp);
+        ws.B64.ensure(8 * Kp * pp);
+        ws.U64.ensure(8 * Kp * np);
+        HIPCHK(hipMemsetAsync(ws.B64.ptr, 0, 8 * Kp * pp, ctx->stream));
+    }
     // inactive padded rows must read as zeros on first use
     HIPCHK(hipMemsetAsync(ws.W.ptr, 0, sb * Kp * pp, ctx->stream));
     HIPCHK(hipMemsetAsync(ws.B.ptr, 0, sb * Kp * pp, ctx->stream));
@@ -609,14 +729,14 @@ void store_batch(l0l2_ctx *ctx, int K, void *beta, void *v, void *b) {
 }
 
 void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool) {
-    if (ctx->inst.prec == L0L2_FP64) sweeps_t<double>(ctx, K, sweeps);
-    else if (ctx->inst.prec == L0L2_FP32) sweeps_t<float>(ctx, K, sweeps);
+    if (ctx->inst.prec == L0L2_FP64) sweeps_t<double>(ctx, sweep64(ctx), K, sweeps);
+    else if (ctx->inst.prec == L0L2_FP32) sweeps_t<float>(ctx, sweep32(ctx), K, sweeps);
     else fail(L0L2_E_UNSUPPORTED, "BF16 sweeps are not available in this build");
 }
 
 void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
-    if (ctx->inst.prec == L0L2_FP64) solve_t<double>(ctx, K, o);
-    else if (ctx->inst.prec == L0L2_FP32) solve_t<float>(ctx, K, o);
+    if (ctx->inst.prec == L0L2_FP64) solve_plain<double>(ctx, sweep64(ctx), K, o);
+    else if (ctx->inst.prec == L0L2_FP32) solve_mixed(ctx, K, o);
     else fail(L0L2_E_UNSUPPORTED, "BF16 node solves are not available in this build");
 }
 
@@ -626,8 +746,10 @@ void run_dual_bound(l0l2_ctx *ctx, int K, const void *) {
     Workspace &ws = ctx->ws;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, ctx->stream,
                        ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), (int64_t)K, Kp);
-    if (ctx->inst.prec == L0L2_FP64) check_once<double>(ctx, K, Kp, 0, 0.0, 1);
-    else check_once<float>(ctx, K, Kp, 0, 0.0, 1);
+    if (ctx->inst.prec == L0L2_FP64)
+        check_once<double>(ctx, ws.B.as<double>(), ws.B.as<double>(), K, Kp, 0, 0.0, 0.0, 1);
+    else
+        check_once<float>(ctx, ws.B.as<float>(), ws.B.as<float>(), K, Kp, 0, 0.0, 0.0, 1);
 }
 
 }  // namespace l0l2

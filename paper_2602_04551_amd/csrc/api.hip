@@ -254,11 +254,12 @@ int l0l2_profile_enable(l0l2_ctx *ctx, int enable) {
         for (int i = 0; i < l0l2::kProfCount; ++i) {
             ctx->prof.total_ms[i] = 0.0;
             ctx->prof.count[i] = 0;
+            ctx->prof.units[i] = 0;
         }
     });
 }
 
-int l0l2_profile_query(l0l2_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms) {
+int l0l2_profile_query(l0l2_ctx *ctx, const char *kernel, int64_t *launches, double *total_ms, int64_t *units) {
     return guarded(ctx, [&] {
         if (!kernel || !launches || !total_ms) l0l2::fail(L0L2_E_INVALID, "null argument");
         l0l2::prof_collect(ctx);
@@ -266,6 +267,7 @@ int l0l2_profile_query(l0l2_ctx *ctx, const char *kernel, int64_t *launches, dou
             if (std::strcmp(kernel, l0l2::kProfNames[i]) == 0) {
                 *launches = ctx->prof.count[i];
                 *total_ms = ctx->prof.total_ms[i];
+                if (units) *units = ctx->prof.units[i];
                 return;
             }
         l0l2::fail(L0L2_E_INVALID, std::string("unknown kernel name ") + kernel);

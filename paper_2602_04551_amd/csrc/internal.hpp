@@ -70,6 +70,7 @@ struct Instance {
     DevBuf cst;       // pp, c in state precision
     DevBuf Xh;        // np x pp column-major, L^{-1} X in working precision (f64 / f32 / bf16)
     DevBuf XhR;       // bf16 only: row-major copy (row i contiguous over pp)
+    DevBuf Xh64;      // FP32 mode: FP64 folded operand for the final sweeps of a node
     DevBuf codes_pad; // scratch
 };
 
@@ -78,6 +79,8 @@ struct Workspace {
     int64_t cap = 0;
     DevBuf W, beta, V, B;          // Kp x pp state precision
     DevBuf U;                      // Kp x np state precision (ADMM product)
+    DevBuf W64, beta64, V64, B64;  // FP32 mode: FP64 state of the final sweeps (Kp x pp)
+    DevBuf U64;                    // FP32 mode: Kp x np
     DevBuf Ub, Ubeta, R;           // Kp x np FP64
     DevBuf codes;                  // Kp x pp uint8
     DevBuf nodescal;               // Kp x 8 doubles: rr, yr, ayr, rbrb, ...
@@ -89,7 +92,8 @@ struct Workspace {
     int *host_counter = nullptr;   // pinned
 };
 
-enum { PROF_GEMM_XW = 0, PROF_ADMM_XTU, PROF_CHECK, PROF_ROUND, PROF_FISTA, kProfCount };
+enum { PROF_GEMM_XW_F32 = 0, PROF_ADMM_XTU_F32, PROF_GEMM_XW_F64, PROF_ADMM_XTU_F64, PROF_CHECK, PROF_ROUND,
+       PROF_FISTA, kProfCount };
 extern const char *const kProfNames[kProfCount];
 
 struct Profiler {
@@ -98,8 +102,9 @@ struct Profiler {
     size_t next = 0;
     std::vector<std::pair<int, hipEvent_t>> open;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pairs;
-    double total_ms[kProfCount] = {0, 0, 0, 0, 0};
-    int64_t count[kProfCount] = {0, 0, 0, 0, 0};
+    double total_ms[kProfCount] = {};
+    int64_t count[kProfCount] = {};
+    int64_t units[kProfCount] = {};   // work units (active node-iterations for the sweeps)
 };
 
 }  // namespace l0l2
@@ -146,7 +151,7 @@ void bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out);
 
 // prof.hip
 void prof_begin(l0l2_ctx *ctx, int id);
-void prof_end(l0l2_ctx *ctx, int id);
+void prof_end(l0l2_ctx *ctx, int id, int64_t units = 0);
 void prof_collect(l0l2_ctx *ctx);
 void prof_release(Profiler &p);
 

@@ -302,14 +302,15 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     if (hflag) fail(L0L2_E_NUMERIC, "Cholesky of X X^T + rho I failed (not positive definite)");
 
     // Xh = L^{-1} X, blocked forward substitution over row blocks of 64.
-    DevBuf Xh64;
+    // FP64 mode keeps it as the sweep operand; the reduced-precision modes keep
+    // it for the FP64 sweeps that finish each node.
     double *Xh;
     if (prec == L0L2_FP64) {
         in.Xh.ensure(sizeof(double) * (size_t)(np * pp));
         Xh = in.Xh.as<double>();
     } else {
-        Xh64.ensure(sizeof(double) * (size_t)(np * pp));
-        Xh = Xh64.as<double>();
+        in.Xh64.ensure(sizeof(double) * (size_t)(np * pp));
+        Xh = in.Xh64.as<double>();
     }
     HIPCHK(hipMemcpyAsync(Xh, X64, sizeof(double) * (size_t)(np * pp), hipMemcpyDeviceToDevice, st));
     for (int64_t kb = 0; kb < n; kb += 64) {

@@ -6,7 +6,8 @@
 
 namespace l0l2 {
 
-const char *const kProfNames[kProfCount] = {"gemm_xw", "admm_xtu", "gap_check", "round_branch", "fista"};
+const char *const kProfNames[kProfCount] = {"gemm_xw.f32", "admm_xtu.f32", "gemm_xw.f64", "admm_xtu.f64",
+                                             "gap_check", "round_branch", "fista"};
 
 static hipEvent_t pool_event(Profiler &p) {
     if (p.next < p.pool.size()) return p.pool[p.next++];
@@ -25,9 +26,10 @@ void prof_begin(l0l2_ctx *ctx, int id) {
     p.open.push_back({id, e});
 }
 
-void prof_end(l0l2_ctx *ctx, int id) {
+void prof_end(l0l2_ctx *ctx, int id, int64_t units) {
     Profiler &p = ctx->prof;
     if (!p.on) return;
+    p.units[id] += units;
     hipEvent_t e = pool_event(p);
     HIPCHK(hipEventRecord(e, ctx->stream));
     for (size_t i = p.open.size(); i-- > 0;) {

@@ -133,12 +133,18 @@ def test_node_solve_fp64_matches_oracle(torch_cuda, cases, name):
         assert rel(gb[k], ref["beta"]) < 1e-9
 
 
-def test_node_solve_fp32_bounds_within_1e5(torch_cuda, cases):
-    inst, o, root = cases["C1"]
+@pytest.mark.parametrize("name", ["C1", "wide"])
+def test_node_solve_mixed_bounds_within_1e5(torch_cuda, cases, name):
+    """Mixed path: FP32 sweeps, then FP64 sweeps from the FP32 iterates; every
+    node reaches the 1e-6 gap and its FP64 bound is within 1e-5 of the oracle's."""
+    inst, o, root = cases[name]
     K = 40
     codes, beta0, v0 = random_nodes(inst.p, K, 5, root["beta"], root["v"])
     ctx = ctx_for(inst, "fp32")
+    ctx.profile_enable(True)
     res = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-6, max_iter=4000, check_every=10)
+    n32 = ctx.profile_query("admm_xtu.f32")[0]
+    assert n32 > 0
     lb, stt = res["lb"].cpu().numpy(), res["status"].cpu().numpy()
     for k in range(K):
         ref = o.node_admm(codes[k], beta0[k], v0[k], tol=1e-6, max_iter=4000, check_every=10)
