@@ -19,6 +19,7 @@
 #include <queue>
 #include <vector>
 
+#include "bnb_core.hpp"
 #include "device_math.hpp"
 #include "internal.hpp"
 
@@ -71,63 +72,21 @@ __global__ void k_scatter(const T *__restrict__ beta, const T *__restrict__ V, i
     pool[(2 * s + 1) * pp + j] = V[k * pp + j];
 }
 
-struct TreeNode {
-    int64_t parent;   // arena index of the parent (-1 root)
-    int32_t j;        // fixed coordinate (-1 root)
-    int32_t fix;      // CODE_FIX0 / CODE_FIX1
-};
-
-struct OpenNode {
-    double lb;        // inherited bound
-    int64_t id;       // arena index = creation order
-    int64_t slot;     // warm-start pool slot (-1: zero start)
-    int32_t depth;
-};
-
-struct HeapCmp {
-    bool operator()(const OpenNode &a, const OpenNode &b) const {
-        if (a.lb != b.lb) return a.lb > b.lb;
-        return a.id > b.id;
-    }
-};
-
-// Device pool of (beta, V) rows, one slot per branched node until both
-// children have been gathered.
-struct StatePool {
+// Device pool of (beta, V) rows indexed by the core's warm-start slots.
+struct DevicePool {
     DevBuf buf;
     int64_t cap = 0, pp = 0;
     size_t sb = 8;
-    std::vector<int64_t> free_list;
-    std::vector<int32_t> refs;
-    int64_t used = 0, high = 0;
-
-    void init(int64_t pp_, size_t sb_) { pp = pp_; sb = sb_; }
-    int64_t alloc(hipStream_t st) {
-        if (free_list.empty()) {
-            int64_t ncap = std::max<int64_t>(64, cap * 2);
-            DevBuf nb;
-            nb.ensure(sb * 2 * pp * (size_t)ncap);
-            if (cap) HIPCHK(hipMemcpyAsync(nb.ptr, buf.ptr, sb * 2 * pp * (size_t)cap, hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipStreamSynchronize(st));
-            std::swap(buf.ptr, nb.ptr);
-            std::swap(buf.bytes, nb.bytes);
-            for (int64_t s = ncap - 1; s >= cap; --s) free_list.push_back(s);
-            refs.resize((size_t)ncap, 0);
-            cap = ncap;
-        }
-        int64_t s = free_list.back();
-        free_list.pop_back();
-        refs[(size_t)s] = 2;
-        ++used;
-        high = std::max(high, used);
-        return s;
-    }
-    void release(int64_t s) {
-        if (s < 0) return;
-        if (--refs[(size_t)s] == 0) {
-            free_list.push_back(s);
-            --used;
-        }
+    void ensure(int64_t slots, hipStream_t st) {
+        if (slots <= cap) return;
+        int64_t ncap = std::max<int64_t>({64, cap * 2, slots});
+        DevBuf nb;
+        nb.ensure(sb * 2 * pp * (size_t)ncap);
+        if (cap) HIPCHK(hipMemcpyAsync(nb.ptr, buf.ptr, sb * 2 * pp * (size_t)cap, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::swap(buf.ptr, nb.ptr);
+        std::swap(buf.bytes, nb.bytes);
+        cap = ncap;
     }
 };
 
@@ -141,11 +100,10 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     const int64_t p = in.p, pp = in.pp;
     const int K = std::max(1, o.K);
     ensure_workspace(ctx, K);
+    DevicePool pool;
+    pool.pp = pp;
+    pool.sb = state_bytes(in.prec);
 
-    StatePool pool;
-    pool.init(pp, state_bytes(in.prec));
-
-    // per-batch device arrays
     DevBuf d_off, d_fix, d_slot, d_row, d_sslot, d_sup, d_ssize, d_bj, d_zup, d_nfree, d_fbeta, d_obj, d_fit;
     d_off.ensure(sizeof(int32_t) * (K + 1));
     d_slot.ensure(sizeof(int64_t) * K);
@@ -160,78 +118,34 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     d_obj.ensure(sizeof(double) * K);
     d_fit.ensure(sizeof(int32_t) * K);
 
-    std::vector<TreeNode> arena;
-    arena.push_back({-1, -1, 0});
-    std::priority_queue<OpenNode, std::vector<OpenNode>, HeapCmp> heap;
-    std::vector<OpenNode> stack;
-    const bool dfs = o.policy == L0L2_DFS;
-    auto push = [&](const OpenNode &u) {
-        if (dfs) stack.push_back(u);
-        else heap.push(u);
-    };
-    auto empty = [&]() { return dfs ? stack.empty() : heap.empty(); };
-    auto pop = [&]() {
-        OpenNode u;
-        if (dfs) { u = stack.back(); stack.pop_back(); }
-        else { u = heap.top(); heap.pop(); }
-        return u;
-    };
-    push({-INFINITY, 0, -1, 0});
-
-    double UB = INFINITY;
-    bool have_inc = false;
+    BnbCore core(o);
     std::vector<uint8_t> inc_mask((size_t)p, 0);
-    std::vector<double> inc_beta((size_t)p, 0.0);
-    int64_t solved = 0, pruned = 0, tl = 0, batches = 0;
+    int64_t batches = 0;
     int status = 0;
-    auto trace_put = [&](const l0l2_trace_rec &r) {
-        if (o.trace && tl < o.trace_cap) o.trace[tl] = r;
-        ++tl;
-    };
-    const double eps = o.eps_prune;
-
     std::vector<OpenNode> batch;
     std::vector<int32_t> h_off, h_fix;
     std::vector<int64_t> h_slot, h_row, h_sslot;
     std::vector<double> h_lb(K), h_primal(K), h_obj(K);
-    std::vector<int32_t> h_iters(K), h_status(K), h_ssize(K), h_bj(K), h_zup(K), h_nfree(K);
+    std::vector<int32_t> h_iters(K), h_status(K), h_ssize(K), h_bj(K), h_zup(K);
+    std::vector<NodeOutcome> res(K);
+    std::vector<std::pair<int, int64_t>> saves;
 
-    while (!empty()) {
-        if (o.gap_tol > 0.0 && have_inc) {
-            double lbg = INFINITY;
-            if (dfs) { for (auto &u : stack) lbg = std::min(lbg, u.lb); }
-            else lbg = heap.top().lb;
-            if (UB - lbg <= o.gap_tol * std::fabs(UB)) { status = 2; break; }
+    while (!core.frontier_empty()) {
+        if ((status = core.gap_reached()) != 0) break;
+        if (o.time_limit_s > 0 && std::chrono::duration<double>(clock::now() - t0).count() > o.time_limit_s) {
+            status = 3;
+            break;
         }
-        if (o.time_limit_s > 0 &&
-            std::chrono::duration<double>(clock::now() - t0).count() > o.time_limit_s) { status = 3; break; }
-        if (solved >= o.max_nodes) { status = 1; break; }
-        // select the batch, discarding nodes already pruned by their inherited bound
-        batch.clear();
-        while (!empty() && (int)batch.size() < K && solved + (int64_t)batch.size() < o.max_nodes) {
-            OpenNode u = pop();
-            if (have_inc && u.lb >= UB * (1.0 - eps)) {
-                ++pruned;
-                l0l2_trace_rec r{};
-                r.id = u.id; r.parent = arena[(size_t)u.id].parent; r.depth = u.depth; r.branch_j = -1;
-                r.decision = 3; r.lb = u.lb; r.ub_global = UB;
-                trace_put(r);
-                pool.release(u.slot);
-                continue;
-            }
-            batch.push_back(u);
-            if (u.id == 0) break;   // the root is solved alone with its own sweep budget
-        }
+        if (core.solved() >= o.max_nodes) { status = 1; break; }
+        core.select(K, batch);
         const int B = (int)batch.size();
         if (B == 0) continue;
         ++batches;
-        // fixing lists (walk each node's chain to the root)
         h_off.assign((size_t)B + 1, 0);
         h_fix.clear();
         h_slot.assign((size_t)B, -1);
         for (int k = 0; k < B; ++k) {
-            for (int64_t a = batch[k].id; a > 0; a = arena[(size_t)a].parent)
-                h_fix.push_back(arena[(size_t)a].j * 4 + arena[(size_t)a].fix);
+            core.fixings(batch[k].id, h_fix);
             h_off[(size_t)k + 1] = (int32_t)h_fix.size();
             h_slot[(size_t)k] = batch[k].slot;
         }
@@ -247,12 +161,10 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
                            ws.beta.as<T>(), ws.V.as<T>(), pp, (const T *)pool.buf.ptr, d_slot.as<int64_t>(), Bp,
                            (int64_t)B);
         HIPCHK(hipGetLastError());
-        for (int k = 0; k < B; ++k) pool.release(batch[k].slot);
-        // node relaxations
+        core.gathered(batch);
         l0l2_admm_opts ao = o.admm;
         if (batch[0].id == 0) ao.max_iter = o.max_iter_root;
         run_solve(ctx, B, ao);
-        // rounding, branching, refinement
         run_round_branch(ctx, B, ws.codes.as<uint8_t>(), pp, ws.beta.ptr, pp, d_sup.as<uint8_t>(),
                          d_ssize.as<int32_t>(), d_bj.as<int32_t>(), d_zup.as<int32_t>(), d_nfree.as<int32_t>());
         state_to_f64(ctx, B, ws.beta.ptr, pp, d_fbeta.as<double>(), p);
@@ -265,63 +177,26 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
         HIPCHK(hipMemcpyAsync(h_ssize.data(), d_ssize.ptr, 4 * B, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(h_bj.data(), d_bj.ptr, 4 * B, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(h_zup.data(), d_zup.ptr, 4 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_nfree.data(), d_nfree.ptr, 4 * B, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(h_obj.data(), d_obj.ptr, 8 * B, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        solved += B;
-        // decisions in selection order
-        h_row.clear();
-        h_sslot.clear();
-        int best_k = -1;
-        double best_ub = UB;
         for (int k = 0; k < B; ++k) {
-            const OpenNode &u = batch[k];
-            l0l2_trace_rec r{};
-            r.id = u.id; r.parent = arena[(size_t)u.id].parent; r.depth = u.depth; r.branch_j = -1;
-            r.iters = h_iters[k]; r.admm_status = h_status[k]; r.primal = h_primal[k];
             if (!std::isfinite(h_obj[k])) fail(L0L2_E_UNSUPPORTED, "support larger than the refinement kernel allows");
-            double lb_eff = std::max(h_lb[k], u.lb);
-            r.lb = lb_eff;
-            if (have_inc && lb_eff >= UB * (1.0 - eps)) {
-                ++pruned;
-                r.decision = 1; r.ub_global = UB;
-                trace_put(r);
-                continue;
-            }
-            r.ub_node = h_obj[k]; r.support_size = h_ssize[k];
-            if (h_obj[k] < UB) {
-                UB = h_obj[k];
-                have_inc = true;
-                best_k = k;
-                best_ub = UB;
-            }
-            r.ub_global = UB;
-            if (h_bj[k] < 0) {
-                r.decision = 2;
-                trace_put(r);
-                continue;
-            }
-            r.decision = 0; r.branch_j = h_bj[k];
-            trace_put(r);
-            int64_t slot = pool.alloc(st);
-            h_row.push_back(k);
-            h_sslot.push_back(slot);
-            int64_t id0 = (int64_t)arena.size();
-            arena.push_back({u.id, h_bj[k], CODE_FIX0});
-            int64_t id1 = (int64_t)arena.size();
-            arena.push_back({u.id, h_bj[k], CODE_FIX1});
-            OpenNode c0{lb_eff, id0, slot, u.depth + 1}, c1{lb_eff, id1, slot, u.depth + 1};
-            if (h_zup[k]) { push(c0); push(c1); }
-            else { push(c1); push(c0); }
+            res[k] = NodeOutcome{h_lb[k], h_primal[k], h_iters[k], h_status[k], h_obj[k], h_ssize[k], h_bj[k],
+                                 h_zup[k]};
         }
-        (void)best_ub;
-        if (best_k >= 0) {
+        int best_k;
+        core.process(batch, res.data(), saves, best_k);
+        if (best_k >= 0)
             HIPCHK(hipMemcpyAsync(inc_mask.data(), d_sup.as<uint8_t>() + (size_t)best_k * p, (size_t)p,
                                   hipMemcpyDeviceToHost, st));
-            HIPCHK(hipMemcpyAsync(inc_beta.data(), d_fbeta.as<double>() + (size_t)best_k * p, 8 * (size_t)p,
-                                  hipMemcpyDeviceToHost, st));
-        }
-        if (!h_row.empty()) {
+        if (!saves.empty()) {
+            pool.ensure(core.slot_high_water(), st);
+            h_row.clear();
+            h_sslot.clear();
+            for (auto &sv : saves) {
+                h_row.push_back(sv.first);
+                h_sslot.push_back(sv.second);
+            }
             HIPCHK(hipMemcpyAsync(d_row.ptr, h_row.data(), 8 * h_row.size(), hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(d_sslot.ptr, h_sslot.data(), 8 * h_sslot.size(), hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)((pp + 255) / 256), (unsigned)h_row.size()), dim3(256),
@@ -331,21 +206,16 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
         }
         HIPCHK(hipStreamSynchronize(st));
     }
-    double lbg = UB;
-    if (status != 0) {
-        if (dfs) { for (auto &u : stack) lbg = std::min(lbg, u.lb); }
-        else if (!heap.empty()) lbg = std::min(lbg, heap.top().lb);
-        for (auto &u : batch) (void)u;
-    }
+    const double UB = core.ub();
     out->ub = UB;
-    out->lb = status == 0 ? UB : lbg;
-    out->nodes_solved = solved;
-    out->nodes_pruned = pruned;
-    out->trace_len = tl;
+    out->lb = status == 0 ? UB : std::min(UB, core.frontier_lb());
+    out->nodes_solved = core.solved();
+    out->nodes_pruned = core.pruned();
+    out->trace_len = core.trace_len();
     out->batches = batches;
     out->status = status;
     std::vector<double> bex((size_t)p, 0.0);
-    out->certified = have_inc ? run_exact_objective(ctx, inc_mask.data(), bex.data()) : INFINITY;
+    out->certified = core.have_incumbent() ? run_exact_objective(ctx, inc_mask.data(), bex.data()) : INFINITY;
     int64_t ns = 0;
     for (int64_t j = 0; j < p; ++j) ns += inc_mask[(size_t)j] != 0;
     out->support_len = ns;
