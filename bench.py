@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"f32": 157.3, "f64": 78.6}          # dense MFMA TFLOP/s, MI355X
+PEAK = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}   # dense MFMA TFLOP/s, MI355X
 METRIC = "node relaxations/s + time-to-certified-optimum, mixed vs FP64 GPU path"
 
 
@@ -177,14 +177,14 @@ def main():
     value = K * args.steps / dt
 
     roof, kernels = roofline(prof, n, p)
-    fp64 = None
+    others = {}
     if not args.only_mixed:
-        fp64 = Path(inst, "fp64", K)
-        steps64 = max(2, args.steps // 2)
-        dt64, its64, prof64 = run_path(fp64, steps64, 1)
-        value64 = K * steps64 / dt64
-        roof64, kernels64 = roofline(prof64, n, p)
-
+        for prec in ("fp64", "bf16"):
+            path = Path(inst, prec, K)
+            steps_o = max(2, args.steps // 2)
+            dt_o, _, prof_o = run_path(path, steps_o, 1)
+            roof_o, kernels_o = roofline(prof_o, n, p)
+            others[prec] = (path, dt_o, steps_o, roof_o, kernels_o)
     out = {"metric": METRIC, "value": round(value, 2), "unit": "node relaxations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -197,16 +197,15 @@ def main():
            "roofline": roof,
            "kernels": kernels,
            "set_data_s": {"fp32": round(mixed.set_data_s, 4)}}
-    if fp64 is not None:
-        out["fp64_path"] = {"value": round(value64, 2), "unit": "node relaxations/s",
-                            "ms_per_step": round(1e3 * dt64 / steps64, 3), "roofline": roof64, "kernels": kernels64}
-        out["set_data_s"]["fp64"] = round(fp64.set_data_s, 4)
+    for prec, (path, dt_o, steps_o, roof_o, kernels_o) in others.items():
+        out[prec + "_path"] = {"value": round(K * steps_o / dt_o, 2), "unit": "node relaxations/s",
+                               "ms_per_step": round(1e3 * dt_o / steps_o, 3), "roofline": roof_o,
+                               "kernels": kernels_o}
+        out["set_data_s"][prec] = round(path.set_data_s, 4)
 
     if not args.no_ttco:
         tt = {}
-        for name, path in (("mixed_fp32", mixed), ("fp64", fp64)):
-            if path is None:
-                continue
+        for name, path in [("mixed_fp32", mixed)] + [(k, v[0]) for k, v in others.items()]:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = path.ctx.bnb_solve(K=K, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000)

@@ -228,7 +228,8 @@ class Context:
     def profile_enable(self, enable=True):
         self._check(lib.l0l2_profile_enable(self._h, 1 if enable else 0))
 
-    KERNELS = ("gemm_xw.f32", "admm_xtu.f32", "gemm_xw.f64", "admm_xtu.f64", "gap_check", "round_branch", "fista")
+    KERNELS = ("gemm_xw.f32", "admm_xtu.f32", "gemm_xw.f64", "admm_xtu.f64", "gemm_xw.bf16", "admm_xtu.bf16",
+               "gap_check", "round_branch", "fista")
 
     def profile_query(self, kernel):
         """(launches, total milliseconds, work units) of one timed kernel family."""

@@ -230,6 +230,128 @@ __global__ __launch_bounds__(256) void k_admm_xtu(const TA *__restrict__ A, int6
 }
 
 // ---------------------------------------------------------------------------
+// BF16 form of the two contractions: the folded operand is stored as two BF16
+// terms (hi + lo), the FP32 node operand is split into two BF16 terms on load,
+// and each 16 x 16 block accumulates hi*hi + hi*lo + lo*hi in FP32 (the lo*lo
+// term is below FP32 resolution).  Lane l supplies 8 consecutive k of row l%16
+// (16x16x32 MFMA); the contraction over p reads the row-major copy, the
+// contraction over n the column-major copy.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split8(const float w[8], bf16x8 &hi, bf16x8 &lo) {
+    for (int t = 0; t < 8; ++t) {
+        __bf16 h = (__bf16)w[t];
+        hi[t] = h;
+        lo[t] = (__bf16)(w[t] - (float)h);
+    }
+}
+
+__device__ __forceinline__ void load8f(const float *p, float out[8]) {
+    float4 a = *reinterpret_cast<const float4 *>(p);
+    float4 b = *reinterpret_cast<const float4 *>(p + 4);
+    out[0] = a.x; out[1] = a.y; out[2] = a.z; out[3] = a.w;
+    out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
+}
+
+// U[k][i] = sum_j Xh[i][j] W[k][j] with Xh row-major (row i at A + i*lda).
+__global__ __launch_bounds__(256) void k_gemm_xw_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+                                                      int64_t lda, const float *__restrict__ B, int64_t ldb,
+                                                      float *__restrict__ U, int64_t ldu, int64_t kdim) {
+    __shared__ float red[4 * 1024];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int q = lane >> 4, r = lane & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    f32x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+    const int64_t kq = kdim / 4;
+    const int64_t kb = w * kq, ke = kb + kq;
+    for (int64_t j0 = kb; j0 < ke; j0 += 32) {
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+        for (int a = 0; a < 2; ++a) {
+            const int64_t o = (m0 + 16 * a + r) * lda + j0 + 8 * q;
+            ah[a] = *reinterpret_cast<const bf16x8 *>(Ahi + o);
+            al[a] = *reinterpret_cast<const bf16x8 *>(Alo + o);
+        }
+        for (int b = 0; b < 2; ++b) {
+            float wv[8];
+            load8f(B + (n0 + 16 * b + r) * ldb + j0 + 8 * q, wv);
+            split8(wv, bh[b], bl[b]);
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                acc[a][b] = mfma16_bf16(ah[a], bh[b], acc[a][b]);
+                acc[a][b] = mfma16_bf16(ah[a], bl[b], acc[a][b]);
+                acc[a][b] = mfma16_bf16(al[a], bh[b], acc[a][b]);
+            }
+    }
+    tile_to_lds<float>(acc, red, w, lane);
+    __syncthreads();
+    for (int e = 0; e < 4; ++e) {
+        int idx = tid + 256 * e;
+        int n = idx >> 5, m = idx & 31;
+        U[(n0 + n) * ldu + m0 + m] = tile_sum<float>(red, idx);
+    }
+}
+
+// Q[k][j] = sum_i Xh[i][j] U[k][i] (Xh column-major) with the ADMM epilogue.
+__global__ __launch_bounds__(256) void k_admm_xtu_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+                                                       int64_t lda, const float *__restrict__ U, int64_t ldu,
+                                                       int64_t kdim, float *__restrict__ W, float *__restrict__ beta,
+                                                       float *__restrict__ V, float *__restrict__ Bst,
+                                                       const uint8_t *__restrict__ codes, const float *__restrict__ c,
+                                                       const int *__restrict__ active, DevParams<float> q,
+                                                       int64_t ldp, int store_b) {
+    __shared__ float red[4 * 1024];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int qq = lane >> 4, r = lane & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    f32x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+    const int64_t kq = kdim / 4;
+    const int64_t ib = w * kq, ie = ib + kq;
+    for (int64_t i0 = ib; i0 < ie; i0 += 32) {
+        bf16x8 ah[2], al[2], uh[2], ul[2];
+        for (int a = 0; a < 2; ++a) {
+            const int64_t o = (m0 + 16 * a + r) * lda + i0 + 8 * qq;
+            ah[a] = *reinterpret_cast<const bf16x8 *>(Ahi + o);
+            al[a] = *reinterpret_cast<const bf16x8 *>(Alo + o);
+        }
+        for (int b = 0; b < 2; ++b) {
+            float uv[8];
+            load8f(U + (n0 + 16 * b + r) * ldu + i0 + 8 * qq, uv);
+            split8(uv, uh[b], ul[b]);
+        }
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                acc[a][b] = mfma16_bf16(ah[a], uh[b], acc[a][b]);
+                acc[a][b] = mfma16_bf16(ah[a], ul[b], acc[a][b]);
+                acc[a][b] = mfma16_bf16(al[a], uh[b], acc[a][b]);
+            }
+    }
+    tile_to_lds<float>(acc, red, w, lane);
+    __syncthreads();
+    for (int e = 0; e < 4; ++e) {
+        int idx = tid + 256 * e;
+        int n = idx >> 5, m = idx & 31;
+        int64_t node = n0 + n, j = m0 + m;
+        if (!active[node]) continue;
+        float Qv = tile_sum<float>(red, idx);
+        int64_t o = node * ldp + j;
+        float wv = W[o];
+        float bb = (wv - Qv) / q.rho;
+        float v = V[o];
+        float bt = bb + v / q.rho;
+        float be = prox_beta(bt, codes[o], q);
+        float vn = v + q.rho * (bb - be);
+        beta[o] = be;
+        V[o] = vn;
+        W[o] = c[j] + q.rho * be - vn;
+        if (store_b) Bst[o] = bb;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Gap check (FP64)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -459,11 +581,13 @@ Sweep<double> sweep64(l0l2_ctx *ctx) {
             ws.V64.as<double>(), ws.B64.as<double>(), ws.U64.as<double>()};
 }
 
+// FP32 state arrays (the FP32 mode's operand; in BF16 mode Xh is the BF16 pair
+// and is not read through this struct).
 Sweep<float> sweep32(l0l2_ctx *ctx) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
-    return {in.Xh.as<float>(), in.cst.as<float>(), ws.W.as<float>(), ws.beta.as<float>(), ws.V.as<float>(),
-            ws.B.as<float>(), ws.U.as<float>()};
+    return {in.prec == L0L2_FP32 ? in.Xh.as<float>() : nullptr, in.cst.as<float>(), ws.W.as<float>(),
+            ws.beta.as<float>(), ws.V.as<float>(), ws.B.as<float>(), ws.U.as<float>()};
 }
 
 template <class T> constexpr int prof_xw();
@@ -492,6 +616,27 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
     hipLaunchKernelGGL((k_admm_xtu<T, T>), g2, dim3(256), 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, sw.B,
                        ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp, store_b ? 1 : 0);
     prof_end(ctx, prof_xtu<T>(), active);
+    HIPCHK(hipGetLastError());
+}
+
+// One sweep of the BF16 form on the FP32 state of sw.
+void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool store_b, int64_t active) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    const int64_t np = in.np, pp = in.pp;
+    dim3 g1((unsigned)(np / 32), (unsigned)(Kp / 32));
+    dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
+    DevParams<float> q = dev_params<float>(in.mp);
+    prof_begin(ctx, PROF_GEMM_XW_BF16);
+    hipLaunchKernelGGL(k_gemm_xw_bf16, g1, dim3(256), 0, s, in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), pp, sw.W, pp,
+                       sw.U, np, pp);
+    prof_end(ctx, PROF_GEMM_XW_BF16, active);
+    prof_begin(ctx, PROF_ADMM_XTU_BF16);
+    hipLaunchKernelGGL(k_admm_xtu_bf16, g2, dim3(256), 0, s, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(), np, sw.U, np,
+                       np, sw.W, sw.beta, sw.V, sw.B, ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp,
+                       store_b ? 1 : 0);
+    prof_end(ctx, PROF_ADMM_XTU_BF16, active);
     HIPCHK(hipGetLastError());
 }
 
@@ -588,12 +733,14 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
     }
 }
 
-// Mixed precision (FP32 state): FP32 sweeps while the batch converges, then the
-// remaining active nodes continue in FP64 from their FP32 iterates.  FP32
-// sweeps stop for the batch once every active node's gap is below
-// switch_tol = 50 tol_node, or the number of nodes above it has not dropped
-// for 5 checks, or half the sweep budget is spent.  Bounds are FP64 in both
-// phases; the final iterates are returned in FP32.
+// Mixed precision (FP32 state): reduced-precision sweeps (FP32, or the BF16
+// form) while the batch converges, then the remaining active nodes continue in
+// FP64 from their FP32 iterates.  The reduced sweeps stop for the batch once
+// every active node's gap is below switch_tol (50 tol_node for FP32, 200
+// tol_node for BF16: the measured floors are about 1e-6..5e-6 and 1e-4), or the
+// number of nodes above it has not dropped for 5 checks, or half the sweep
+// budget is spent.  Bounds are FP64 in both phases; the final iterates are
+// returned in FP32.
 void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     Instance &in = ctx->inst;
     const int64_t Kp = round_up(K, kPadNodes);
@@ -601,14 +748,16 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     Sweep<double> s64 = sweep64(ctx);
     init_batch<float>(ctx, s32, K, Kp);
     const int m = std::max(1, o.check_every);
-    const double switch_tol = 50.0 * o.tol_node;
+    const bool bf16 = in.prec == L0L2_BF16;
+    const double switch_tol = (bf16 ? 200.0 : 50.0) * o.tol_node;
     bool fp64 = false;
     int cnt[2], best_above = 1 << 30, flat = 0;
     int64_t active = K;
     for (int t = 1; t <= o.max_iter; ++t) {
         bool chk = (t % m == 0) || (t == o.max_iter);
-        if (!fp64) sweep_once<float>(ctx, s32, Kp, chk, active);
-        else sweep_once<double>(ctx, s64, Kp, chk, active);
+        if (fp64) sweep_once<double>(ctx, s64, Kp, chk, active);
+        else if (bf16) sweep_once_bf16(ctx, s32, Kp, chk, active);
+        else sweep_once<float>(ctx, s32, Kp, chk, active);
         if (!chk) continue;
         if (!fp64) check_once<float>(ctx, s32.B, s32.beta, K, Kp, t, o.tol_node, switch_tol, 0);
         else check_once<double>(ctx, s64.B, s64.beta, K, Kp, t, o.tol_node, switch_tol, 0);
@@ -667,7 +816,7 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.primal.ensure(8 * Kp);
     ws.counter.ensure(2 * sizeof(int));
     if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 2 * sizeof(int), hipHostMallocDefault));
-    if (in.prec == L0L2_FP32) {
+    if (in.prec != L0L2_FP64) {
         ws.W64.ensure(8 * Kp * pp);
         ws.beta64.ensure(8 * Kp * pp);
         ws.V64.ensure(8 * Kp * pp);
@@ -729,15 +878,21 @@ void store_batch(l0l2_ctx *ctx, int K, void *beta, void *v, void *b) {
 }
 
 void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool) {
-    if (ctx->inst.prec == L0L2_FP64) sweeps_t<double>(ctx, sweep64(ctx), K, sweeps);
-    else if (ctx->inst.prec == L0L2_FP32) sweeps_t<float>(ctx, sweep32(ctx), K, sweeps);
-    else fail(L0L2_E_UNSUPPORTED, "BF16 sweeps are not available in this build");
+    if (ctx->inst.prec == L0L2_FP64) {
+        sweeps_t<double>(ctx, sweep64(ctx), K, sweeps);
+    } else if (ctx->inst.prec == L0L2_FP32) {
+        sweeps_t<float>(ctx, sweep32(ctx), K, sweeps);
+    } else {
+        const int64_t Kp = round_up(K, kPadNodes);
+        Sweep<float> s32 = sweep32(ctx);
+        init_batch<float>(ctx, s32, K, Kp);
+        for (int t = 1; t <= sweeps; ++t) sweep_once_bf16(ctx, s32, Kp, t == sweeps, K);
+    }
 }
 
 void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     if (ctx->inst.prec == L0L2_FP64) solve_plain<double>(ctx, sweep64(ctx), K, o);
-    else if (ctx->inst.prec == L0L2_FP32) solve_mixed(ctx, K, o);
-    else fail(L0L2_E_UNSUPPORTED, "BF16 node solves are not available in this build");
+    else solve_mixed(ctx, K, o);
 }
 
 // Bound at b already loaded in ws.B (codes in ws.codes): fills ws.lb.

@@ -129,7 +129,6 @@ int l0l2_set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, in
         if (!(std::isfinite(rho) && rho > 0)) l0l2::fail(L0L2_E_INVALID, "rho must be finite and > 0");
         if (x_precision != L0L2_FP64 && x_precision != L0L2_FP32 && x_precision != L0L2_BF16)
             l0l2::fail(L0L2_E_INVALID, "unknown x_precision");
-        if (x_precision == L0L2_BF16) l0l2::fail(L0L2_E_UNSUPPORTED, "BF16 products are not available in this build");
         if (!ptrs_on_device) {
             for (int64_t e = 0; e < n * p; ++e)
                 if (!std::isfinite(X[e])) l0l2::fail(L0L2_E_INVALID, "X has a non-finite entry");

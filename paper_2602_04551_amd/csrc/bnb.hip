@@ -232,8 +232,7 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
 
 void bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     if (ctx->inst.prec == L0L2_FP64) bnb_t<double>(ctx, o, out);
-    else if (ctx->inst.prec == L0L2_FP32) bnb_t<float>(ctx, o, out);
-    else fail(L0L2_E_UNSUPPORTED, "BF16 branch and bound is not available in this build");
+    else bnb_t<float>(ctx, o, out);
 }
 
 }  // namespace l0l2

@@ -11,7 +11,7 @@
 
 namespace l0l2 {
 
-constexpr int kPadRows = 64;    // n and p are padded to multiples of this
+constexpr int kPadRows = 128;   // n and p are padded to multiples of this
 constexpr int kPadNodes = 32;   // K is padded to multiples of this (one GEMM tile)
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
@@ -68,8 +68,10 @@ struct Instance {
     DevBuf c64;       // pp, X^T y
     DevBuf colnrm;    // pp, ||X_j||
     DevBuf cst;       // pp, c in state precision
-    DevBuf Xh;        // np x pp column-major, L^{-1} X in working precision (f64 / f32 / bf16)
-    DevBuf XhR;       // bf16 only: row-major copy (row i contiguous over pp)
+    DevBuf Xh;        // np x pp column-major, L^{-1} X in working precision (f64 / f32); BF16 mode: high half
+    DevBuf XhLo;      // BF16 mode: column-major low half (Xh - bf16(Xh))
+    DevBuf XhR;       // BF16 mode: row-major high half (row i contiguous over pp)
+    DevBuf XhRLo;     // BF16 mode: row-major low half
     DevBuf Xh64;      // FP32 mode: FP64 folded operand for the final sweeps of a node
     DevBuf codes_pad; // scratch
 };
@@ -92,8 +94,8 @@ struct Workspace {
     int *host_counter = nullptr;   // pinned
 };
 
-enum { PROF_GEMM_XW_F32 = 0, PROF_ADMM_XTU_F32, PROF_GEMM_XW_F64, PROF_ADMM_XTU_F64, PROF_CHECK, PROF_ROUND,
-       PROF_FISTA, kProfCount };
+enum { PROF_GEMM_XW_F32 = 0, PROF_ADMM_XTU_F32, PROF_GEMM_XW_F64, PROF_ADMM_XTU_F64, PROF_GEMM_XW_BF16,
+       PROF_ADMM_XTU_BF16, PROF_CHECK, PROF_ROUND, PROF_FISTA, kProfCount };
 extern const char *const kProfNames[kProfCount];
 
 struct Profiler {

@@ -193,16 +193,21 @@ __global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst
     for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) dst[idx] = (float)src[idx];
 }
 
-// bf16 column-major copy and row-major copy of the np x pp column-major src.
-__global__ void k_to_bf16(const double *__restrict__ src, __bf16 *__restrict__ colmaj, __bf16 *__restrict__ rowmaj,
-                          int64_t np, int64_t pp) {
+// Two-term BF16 split x = hi + lo of the np x pp column-major src, stored
+// column-major and row-major.
+__global__ void k_to_bf16x2(const double *__restrict__ src, __bf16 *__restrict__ col_hi, __bf16 *__restrict__ col_lo,
+                            __bf16 *__restrict__ row_hi, __bf16 *__restrict__ row_lo, int64_t np, int64_t pp) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = np * pp;
     for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
         int64_t i = idx % np, j = idx / np;
-        __bf16 v = (__bf16)(float)src[idx];
-        colmaj[idx] = v;
-        rowmaj[i * pp + j] = v;
+        double x = src[idx];
+        __bf16 hi = (__bf16)(float)x;
+        __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
+        col_hi[idx] = hi;
+        col_lo[idx] = lo;
+        row_hi[i * pp + j] = hi;
+        row_lo[i * pp + j] = lo;
     }
 }
 
@@ -330,10 +335,13 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
         in.cst.ensure(sizeof(float) * (size_t)pp);
         hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), pp);
     } else if (prec == L0L2_BF16) {
-        in.Xh.ensure(sizeof(__bf16) * (size_t)(np * pp));
-        in.XhR.ensure(sizeof(__bf16) * (size_t)(np * pp));
-        hipLaunchKernelGGL(k_to_bf16, dim3(4096), dim3(256), 0, st, Xh, in.Xh.as<__bf16>(), in.XhR.as<__bf16>(),
-                           np, pp);
+        const size_t nb = sizeof(__bf16) * (size_t)(np * pp);
+        in.Xh.ensure(nb);
+        in.XhLo.ensure(nb);
+        in.XhR.ensure(nb);
+        in.XhRLo.ensure(nb);
+        hipLaunchKernelGGL(k_to_bf16x2, dim3(4096), dim3(256), 0, st, Xh, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(),
+                           in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), np, pp);
         in.cst.ensure(sizeof(float) * (size_t)pp);
         hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), pp);
     } else {
