@@ -180,6 +180,45 @@ typedef struct {
 int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *out);
 void l0l2_result_free(l0l2_bnb_result *res);
 
+/* ---- Serving: branch and bound for many instances on one device ---------- */
+
+/* Estimated device bytes one instance of n x p needs at batch size K in the
+ * given precision (instance copies, precompute peak, batch workspace, a
+ * warm-start reserve of 16 K slots).  Used for admission; the pool of parent
+ * states can outgrow its reserve on large trees. */
+size_t l0l2_footprint_bytes(int64_t n, int64_t p, int precision, int K);
+
+typedef struct l0l2_server l0l2_server;
+
+typedef struct {
+    double submit_s, admit_s, done_s;   /* seconds since the server was created */
+    size_t footprint_bytes;             /* reserved from the HBM budget while running */
+} l0l2_request_stats;
+
+/* Create a server on `device`.  hbm_budget_bytes bounds the summed footprints
+ * of the instances running at once (0 = 80% of the free device memory now);
+ * at most max_concurrent instances run at once, each on its own context and
+ * HIP stream.  opts (copied; its trace buffer is ignored) applies to every
+ * request.  Requests are admitted in arrival order as workers and budget free
+ * up ("continuous batching": arrivals join while others are on the GPU). */
+int l0l2_server_create(int device, size_t hbm_budget_bytes, int max_concurrent, const l0l2_bnb_opts *opts,
+                       l0l2_server **out);
+/* Queue one instance (host X column-major n x p, host y; copied before return).
+ * Returns L0L2_E_OOM when its footprint alone exceeds the budget. */
+int l0l2_server_submit(l0l2_server *srv, const double *X, const double *y, int64_t n, int64_t p,
+                       double lambda0, double lambda2, double M, double rho, int precision,
+                       int64_t *req_id);
+/* Wait up to timeout_s seconds (< 0: no limit) for request req_id.  On success
+ * *out holds its certified result (arrays owned by the caller from then on:
+ * release with l0l2_result_free) and *stats (may be NULL) its timing.  A request
+ * can be collected once.  L0L2_E_TIMEOUT if it is not finished in time; the
+ * request's own error code if its solve failed. */
+int l0l2_server_wait(l0l2_server *srv, int64_t req_id, double timeout_s, l0l2_bnb_result *out,
+                     l0l2_request_stats *stats);
+const char *l0l2_server_last_error(const l0l2_server *srv);
+/* Stop admitting, drop queued requests, wait for running ones, free all. */
+int l0l2_server_destroy(l0l2_server *srv);
+
 /* Opt-in timing of the library's kernels with HIP events recorded on the
  * context stream around each launch (adds one event pair per launch).
  * l0l2_profile_enable clears the counters and switches timing on (1) or off (0).

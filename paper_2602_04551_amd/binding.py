@@ -53,6 +53,11 @@ class l0l2_bnb_result(C.Structure):
                 ("beta", C.POINTER(C.c_double))]
 
 
+class l0l2_request_stats(C.Structure):
+    _fields_ = [("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("footprint_bytes", C.c_size_t)]
+
+
 _vp, _i, _i64, _d = C.c_void_p, C.c_int, C.c_int64, C.c_double
 SIGNATURES = {
     "l0l2_create": (_i, [_i, _vp, C.POINTER(_vp)]),
@@ -68,6 +73,12 @@ SIGNATURES = {
     "l0l2_exact_objective": (_i, [_vp, _vp, _vp, _vp]),
     "l0l2_bnb_solve": (_i, [_vp, C.POINTER(l0l2_bnb_opts), C.POINTER(l0l2_bnb_result)]),
     "l0l2_result_free": (None, [C.POINTER(l0l2_bnb_result)]),
+    "l0l2_footprint_bytes": (C.c_size_t, [_i64, _i64, _i, _i]),
+    "l0l2_server_create": (_i, [_i, C.c_size_t, _i, C.POINTER(l0l2_bnb_opts), C.POINTER(_vp)]),
+    "l0l2_server_submit": (_i, [_vp, _vp, _vp, _i64, _i64, _d, _d, _d, _d, _i, C.POINTER(_i64)]),
+    "l0l2_server_wait": (_i, [_vp, _i64, _d, C.POINTER(l0l2_bnb_result), C.POINTER(l0l2_request_stats)]),
+    "l0l2_server_last_error": (C.c_char_p, [_vp]),
+    "l0l2_server_destroy": (_i, [_vp]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
     "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
 }
@@ -260,3 +271,73 @@ class Context:
         return dict(ub=r.ub, certified=r.certified, lb=r.lb, nodes_solved=r.nodes_solved,
                     nodes_pruned=r.nodes_pruned, batches=r.batches, seconds=r.seconds, status=r.status,
                     support=support, beta=beta, trace=trace)
+
+
+def bnb_options(K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000, check_every=10,
+                eps_prune=None, gap_tol=0.0, time_limit_s=0.0, max_nodes=10**9, fista_tol=1e-12,
+                fista_max_iter=1000):
+    if eps_prune is None:
+        eps_prune = 2.0 * tol_node
+    return l0l2_bnb_opts(int(K), L0L2_DFS if policy == "dfs" else L0L2_BEST_FIRST, float(eps_prune),
+                         float(gap_tol), float(time_limit_s), int(max_nodes), int(max_iter_root),
+                         l0l2_admm_opts(float(tol_node), int(max_iter), int(check_every)),
+                         l0l2_fista_opts(float(fista_tol), int(fista_max_iter)), None, 0)
+
+
+def _result_dict(r, p):
+    support = np.array([r.support[i] for i in range(r.support_len)], dtype=np.int64)
+    beta = np.ctypeslib.as_array(r.beta, shape=(p,)).copy() if r.beta else np.zeros(p)
+    return dict(ub=r.ub, certified=r.certified, lb=r.lb, nodes_solved=r.nodes_solved,
+                nodes_pruned=r.nodes_pruned, batches=r.batches, seconds=r.seconds, status=r.status,
+                support=support, beta=beta)
+
+
+class Server:
+    """l0l2_server: continuous batching of whole branch-and-bound solves."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0, max_concurrent=4, **bnb_kw):
+        h = C.c_void_p()
+        self.opts = bnb_options(**bnb_kw)
+        rc = lib.l0l2_server_create(device, int(hbm_budget_bytes), int(max_concurrent), C.byref(self.opts),
+                                    C.byref(h))
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, "server creation failed")
+        self._h = h
+        self._p = {}
+
+    def submit(self, X, y, lambda0, lambda2, M, rho=1.0, precision="fp32"):
+        X = np.asfortranarray(X, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        n, p = X.shape
+        rid = C.c_int64()
+        rc = lib.l0l2_server_submit(self._h, X.ctypes.data, y.ctypes.data, n, p, float(lambda0), float(lambda2),
+                                    float(M), float(rho), PRECISIONS[precision], C.byref(rid))
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, lib.l0l2_server_last_error(self._h).decode())
+        self._p[rid.value] = p
+        return rid.value
+
+    def wait(self, rid, timeout_s=-1.0):
+        r = l0l2_bnb_result()
+        st = l0l2_request_stats()
+        rc = lib.l0l2_server_wait(self._h, int(rid), float(timeout_s), C.byref(r), C.byref(st))
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, lib.l0l2_server_last_error(self._h).decode())
+        try:
+            out = _result_dict(r, self._p.pop(rid))
+        finally:
+            lib.l0l2_result_free(C.byref(r))
+        out.update(submit_s=st.submit_s, admit_s=st.admit_s, done_s=st.done_s,
+                   footprint_bytes=st.footprint_bytes)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.l0l2_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

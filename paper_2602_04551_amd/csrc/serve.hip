@@ -1,0 +1,229 @@
+// Serving: branch and bound for many independent instances on one device.
+//
+// Requests (X, y, lambda0, lambda2, M, rho, precision) arrive at any time.  A
+// request is admitted, in arrival order, as soon as a worker slot is free and
+// its estimated device footprint fits in what the HBM budget has left; it then
+// runs on its own context and HIP stream (default priority), so the kernels of
+// all admitted instances overlap on the device, and its footprint returns to
+// the budget when it finishes.  Each instance's computation is the same
+// deterministic sequence of kernels whether it runs alone or beside others.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace l0l2 {
+
+size_t footprint_bytes(int64_t n, int64_t p, int prec, int K) {
+    const double np = (double)round_up(n, kPadRows), pp = (double)round_up(p, kPadRows);
+    const double Kp = (double)round_up(std::max(K, 1), kPadNodes);
+    const double sb = prec == L0L2_FP64 ? 8.0 : 4.0;
+    double inst = 8.0 * np * pp + 32.0 * (np + pp);
+    if (prec == L0L2_FP64) inst += 8.0 * np * pp;
+    else if (prec == L0L2_FP32) inst += 12.0 * np * pp;
+    else inst += 16.0 * np * pp;
+    double transient = 8.0 * np * np + 8.0 * (double)n * (double)p;
+    double ws = 4.0 * sb * Kp * pp + sb * Kp * np + 24.0 * Kp * np + Kp * pp + 1.0 * Kp * pp / 4.0 + 128.0 * Kp;
+    if (prec != L0L2_FP64) ws += 32.0 * Kp * pp + 8.0 * Kp * np;
+    ws += 8.0 * Kp * np;                                   // refinement residuals
+    double bnb = 9.0 * Kp * (double)p + 2.0 * sb * pp * 16.0 * Kp;   // supports, starts, pool reserve
+    return (size_t)(inst + std::max(transient, ws + bnb));
+}
+
+}  // namespace l0l2
+
+struct l0l2_server {
+    struct Request {
+        int64_t id;
+        std::vector<double> X, y;
+        int64_t n, p;
+        double l0, l2, M, rho;
+        int prec;
+        size_t bytes;
+        double t_submit = 0, t_admit = 0, t_done = 0;
+        bool done = false, taken = false;
+        int rc = L0L2_OK;
+        std::string err;
+        l0l2_bnb_result res{};
+    };
+
+    int device = 0;
+    size_t budget = 0, reserved = 0;
+    int max_concurrent = 1, running = 0;
+    l0l2_bnb_opts opts{};
+    std::string err;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> pending;
+    std::map<int64_t, std::shared_ptr<Request>> all;
+    std::vector<std::thread> workers;
+    int64_t next_id = 1;
+    bool stopping = false;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    // Next admissible request, in arrival order (the head blocks later ones so
+    // that large instances are not starved).
+    std::shared_ptr<Request> admit_locked() {
+        if (pending.empty() || running >= max_concurrent) return nullptr;
+        auto r = pending.front();
+        if (reserved + r->bytes > budget && running > 0) return nullptr;
+        pending.pop_front();
+        reserved += r->bytes;
+        ++running;
+        r->t_admit = now();
+        return r;
+    }
+
+    void worker() {
+        (void)hipSetDevice(device);
+        hipStream_t stream = nullptr;
+        if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+        for (;;) {
+            std::shared_ptr<Request> r;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] { return stopping || (r = admit_locked()) != nullptr; });
+                if (!r) break;
+            }
+            run(*r, stream);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                reserved -= r->bytes;
+                --running;
+                r->t_done = now();
+                r->done = true;
+                r->X.clear();
+                r->X.shrink_to_fit();
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    void run(Request &r, hipStream_t stream) {
+        l0l2_ctx *ctx = nullptr;
+        int rc = l0l2_create(device, stream, &ctx);
+        if (rc == L0L2_OK)
+            rc = l0l2_set_data(ctx, r.X.data(), r.y.data(), r.n, r.p, r.l0, r.l2, r.M, r.rho, r.prec, 0);
+        if (rc == L0L2_OK) rc = l0l2_bnb_solve(ctx, &opts, &r.res);
+        r.rc = rc;
+        if (rc != L0L2_OK) r.err = ctx ? l0l2_last_error(ctx) : l0l2_last_error(nullptr);
+        if (ctx) l0l2_destroy(ctx);
+    }
+};
+
+extern "C" {
+
+size_t l0l2_footprint_bytes(int64_t n, int64_t p, int precision, int K) {
+    return l0l2::footprint_bytes(n, p, precision, K);
+}
+
+int l0l2_server_create(int device, size_t hbm_budget_bytes, int max_concurrent, const l0l2_bnb_opts *opts,
+                       l0l2_server **out) {
+    if (!out || !opts || max_concurrent < 1 || opts->K < 1) return L0L2_E_INVALID;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return L0L2_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return L0L2_E_DEVICE;
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return L0L2_E_DEVICE;
+    l0l2_server *s = new (std::nothrow) l0l2_server();
+    if (!s) return L0L2_E_OOM;
+    s->device = device;
+    s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)freeb);
+    s->max_concurrent = max_concurrent;
+    s->opts = *opts;
+    s->opts.trace = nullptr;
+    s->opts.trace_cap = 0;
+    for (int i = 0; i < max_concurrent; ++i) s->workers.emplace_back([s] { s->worker(); });
+    *out = s;
+    return L0L2_OK;
+}
+
+int l0l2_server_submit(l0l2_server *s, const double *X, const double *y, int64_t n, int64_t p, double lambda0,
+                       double lambda2, double M, double rho, int precision, int64_t *req_id) {
+    if (!s || !X || !y || !req_id || n < 1 || p < 1) return L0L2_E_INVALID;
+    if (precision != L0L2_FP64 && precision != L0L2_FP32 && precision != L0L2_BF16) return L0L2_E_INVALID;
+    auto r = std::make_shared<l0l2_server::Request>();
+    try {
+        r->X.assign(X, X + n * p);
+        r->y.assign(y, y + n);
+    } catch (...) {
+        return L0L2_E_OOM;
+    }
+    r->n = n; r->p = p; r->l0 = lambda0; r->l2 = lambda2; r->M = M; r->rho = rho; r->prec = precision;
+    r->bytes = l0l2::footprint_bytes(n, p, precision, s->opts.K);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) return L0L2_E_INVALID;
+        if (r->bytes > s->budget) {
+            s->err = "request footprint exceeds the server's HBM budget";
+            return L0L2_E_OOM;
+        }
+        r->id = s->next_id++;
+        r->t_submit = s->now();
+        s->pending.push_back(r);
+        s->all[r->id] = r;
+        *req_id = r->id;
+    }
+    s->cv_work.notify_all();
+    return L0L2_OK;
+}
+
+int l0l2_server_wait(l0l2_server *s, int64_t req_id, double timeout_s, l0l2_bnb_result *out,
+                     l0l2_request_stats *stats) {
+    if (!s || !out) return L0L2_E_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(req_id);
+    if (it == s->all.end() || it->second->taken) return L0L2_E_INVALID;
+    auto r = it->second;
+    auto pred = [&] { return r->done; };
+    if (timeout_s < 0) s->cv_done.wait(lk, pred);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return L0L2_E_TIMEOUT;
+    *out = r->res;
+    r->res.support = nullptr;
+    r->res.beta = nullptr;
+    r->taken = true;
+    if (stats) {
+        stats->submit_s = r->t_submit;
+        stats->admit_s = r->t_admit;
+        stats->done_s = r->t_done;
+        stats->footprint_bytes = r->bytes;
+    }
+    int rc = r->rc;
+    if (rc != L0L2_OK) s->err = r->err;
+    s->all.erase(it);
+    return rc;
+}
+
+const char *l0l2_server_last_error(const l0l2_server *s) { return s ? s->err.c_str() : ""; }
+
+int l0l2_server_destroy(l0l2_server *s) {
+    if (!s) return L0L2_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+        s->pending.clear();
+    }
+    s->cv_work.notify_all();
+    for (auto &t : s->workers) t.join();
+    for (auto &kv : s->all) l0l2_result_free(&kv.second->res);
+    delete s;
+    return L0L2_OK;
+}
+
+}  // extern "C"

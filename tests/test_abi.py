@@ -48,3 +48,14 @@ def test_binding_names_match_the_abi():
     from paper_2602_04551_amd import binding
     for name in declared_functions():
         assert hasattr(binding.lib, name)
+
+
+def test_footprint_estimate_grows_with_size_and_batch():
+    from paper_2602_04551_amd.binding import lib
+    f = lib.l0l2_footprint_bytes
+    assert f(1000, 1000, 1, 256) > f(1000, 1000, 1, 32) > 0
+    assert f(2000, 1000, 1, 256) > f(1000, 1000, 1, 256)
+    assert f(1000, 2000, 1, 256) > f(1000, 1000, 1, 256)
+    assert f(1000, 1000, 0, 256) > f(1000, 1000, 1, 256)  # FP64 state is twice as wide
+    # dominated by the instance copies for a wide design
+    assert f(1000, 50000, 2, 256) > 8 * 1000 * 50000

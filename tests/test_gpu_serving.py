@@ -1,0 +1,92 @@
+"""Serving: whole branch-and-bound solves of several instances of different
+sizes admitted under an HBM budget and run concurrently.  Each result is the
+same alone and in the mix (the per-instance kernel sequence is deterministic),
+admitted instances overlap in time, and the budget caps the concurrent
+footprint."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2602_04551_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(K=32, policy="best", tol_node=1e-6, max_iter=3000, max_iter_root=10000)
+SIZES = [(60, 30, 0), (120, 45, 1), (90, 60, 2), (200, 40, 3), (150, 70, 4), (80, 35, 5)]
+
+
+@pytest.fixture(scope="module")
+def instances():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return [datagen.make_instance(n, p, rho=0.3, k=3, snr=3.0, seed=s, lambda0=0.02, lambda2=0.01)
+            for n, p, s in SIZES]
+
+
+@pytest.fixture(scope="module")
+def alone(instances):
+    from paper_2602_04551_amd.binding import Context
+    out = []
+    for inst in instances:
+        c = Context(0)
+        c.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp32")
+        out.append(c.bnb_solve(**KW))
+        c.close()
+    return out
+
+
+def overlaps(res):
+    iv = sorted((r["admit_s"], r["done_s"]) for r in res)
+    return any(iv[i + 1][0] < iv[i][1] for i in range(len(iv) - 1))
+
+
+def test_results_identical_alone_and_in_the_mix(instances, alone, orc):
+    from paper_2602_04551_amd.binding import Server
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=3, **KW)
+    ids = []
+    for i, inst in enumerate(instances):
+        ids.append(srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp32"))
+        if i == 2:
+            time.sleep(0.05)     # later arrivals join while the first ones run
+    res = [srv.wait(r, timeout_s=600) for r in ids]
+    srv.close()
+    for a, b in zip(res, alone):
+        assert a["status"] == 0
+        assert a["certified"] == b["certified"]
+        assert list(a["support"]) == list(b["support"])
+        assert a["nodes_solved"] == b["nodes_solved"]
+    assert overlaps(res)
+    ref = orc.Oracle.from_instance(instances[1]).bnb(tol_node=1e-6, max_iter=3000, max_iter_root=10000)
+    assert abs(res[1]["certified"] - ref["certified"]) <= 1e-8 * ref["certified"]
+    assert list(res[1]["support"]) == list(ref["support"])
+
+
+def test_budget_caps_concurrent_footprint(instances, alone):
+    from paper_2602_04551_amd.binding import Server, lib
+    fp = [lib.l0l2_footprint_bytes(i.n, i.p, 1, KW["K"]) for i in instances]
+    budget = int(max(fp) * 1.5)
+    srv = Server(0, hbm_budget_bytes=budget, max_concurrent=4, **KW)
+    ids = [srv.submit(i.X, i.y, i.lambda0, i.lambda2, i.M, precision="fp32") for i in instances]
+    res = [srv.wait(r, timeout_s=600) for r in ids]
+    srv.close()
+    for a, b in zip(res, alone):
+        assert a["certified"] == b["certified"]
+    # at every admission instant the running footprints fit in the budget
+    for r in res:
+        t = r["admit_s"]
+        running = sum(x["footprint_bytes"] for x in res if x["admit_s"] <= t < x["done_s"])
+        assert running <= budget
+    # arrival order is kept
+    admits = [r["admit_s"] for r in res]
+    assert admits == sorted(admits)
+
+
+def test_oversized_request_is_rejected(instances):
+    from paper_2602_04551_amd.binding import L0L2Error, Server
+    srv = Server(0, hbm_budget_bytes=1 << 20, max_concurrent=1, **KW)
+    inst = instances[0]
+    with pytest.raises(L0L2Error):
+        srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M)
+    srv.close()
