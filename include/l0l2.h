@@ -219,6 +219,13 @@ const char *l0l2_server_last_error(const l0l2_server *srv);
 /* Stop admitting, drop queued requests, wait for running ones, free all. */
 int l0l2_server_destroy(l0l2_server *srv);
 
+/* Tile shapes of the two sweep contractions (each a 32x32, 16x32, 32x16 or 16x16
+ * output tile per workgroup: 0, 1, 2, 3).  By default (both -1) each new batch
+ * size is timed once with every shape on the live batch and the fastest kept
+ * per instance; fixed shapes serve tests and tuning studies.  Results do not
+ * depend on the shape beyond rounding of the summation order. */
+int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
+
 /* Opt-in timing of the library's kernels with HIP events recorded on the
  * context stream around each launch (adds one event pair per launch).
  * l0l2_profile_enable clears the counters and switches timing on (1) or off (0).

@@ -79,6 +79,7 @@ SIGNATURES = {
     "l0l2_server_wait": (_i, [_vp, _i64, _d, C.POINTER(l0l2_bnb_result), C.POINTER(l0l2_request_stats)]),
     "l0l2_server_last_error": (C.c_char_p, [_vp]),
     "l0l2_server_destroy": (_i, [_vp]),
+    "l0l2_set_tiles": (_i, [_vp, _i, _i]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
     "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
 }
@@ -235,6 +236,9 @@ class Context:
         obj = C.c_double()
         self._check(lib.l0l2_exact_objective(self._h, mask.ctypes.data, beta.ctypes.data, C.byref(obj)))
         return obj.value, beta
+
+    def set_tiles(self, xw_shape=-1, xtu_shape=-1):
+        self._check(lib.l0l2_set_tiles(self._h, int(xw_shape), int(xtu_shape)))
 
     def profile_enable(self, enable=True):
         self._check(lib.l0l2_profile_enable(self._h, 1 if enable else 0))

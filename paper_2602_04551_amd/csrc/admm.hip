@@ -92,8 +92,9 @@ __global__ void k_init(const uint8_t *__restrict__ codes, T *__restrict__ beta, 
 }
 
 // ---------------------------------------------------------------------------
-// Cross-wave reduction of a 32 x 32 tile held as 2 x 2 MFMA blocks per wave.
-// red: 4 * 1024 elements of LDS; element (m, n) of wave w at red[w*1024 + n*32 + m].
+// Cross-wave reduction of a 32 x 32 tile held as 2 x 2 MFMA blocks per wave
+// (used by the BF16 kernels).  red: 4 * 1024 elements of LDS; element (m, n) of
+// wave w at red[w*1024 + n*32 + m].
 // ---------------------------------------------------------------------------
 template <class TC>
 __device__ __forceinline__ void tile_to_lds(const typename Acc<TC>::type acc[2][2], TC *red, int w, int lane) {
@@ -111,110 +112,105 @@ __device__ __forceinline__ TC tile_sum(const TC *red, int idx) {
     return red[idx] + red[1024 + idx] + red[2048 + idx] + red[3072 + idx];
 }
 
-template <class TC> __device__ __forceinline__ TC cvt(float x) { return (TC)x; }
+// ---------------------------------------------------------------------------
+// One TM x TN output tile (TM = 16 BM, TN = 16 BN) of C[m][n] = sum_k A[m][k] B[n][k]
+// with A rows (lda) and B rows (ldb) contiguous in k.  Both contractions of a
+// sweep have this shape: over p with A = the row-major copy of Xh and B = the
+// node operand W; over n with A = Xh column-major (a column of Xh is a row of
+// Xh^T) and B = U.  The 4 waves of the workgroup split the k range; lane l
+// loads 4 consecutive k of row l%16 with one vector load per fragment and the
+// 4 MFMAs of a 16-wide chunk map their k slot to those 4 values for both
+// operands.  Two register stages: the next chunk's loads are issued before the
+// current chunk's MFMAs.  On return red[w*TM*TN + n*TM + m] holds wave w's
+// partial sums and the workgroup is synchronised.  kdim / 4 must be a multiple
+// of 32.
+// ---------------------------------------------------------------------------
+template <class TC, int BM, int BN, class TA, class TB>
+__device__ __forceinline__ void mma_chunk(typename Acc<TC>::type (&acc)[BM][BN], const TA (&a)[BM][4],
+                                          const TB (&b)[BN][4]) {
+    for (int t = 0; t < 4; ++t)
+        for (int i = 0; i < BM; ++i)
+            for (int j = 0; j < BN; ++j) acc[i][j] = mfma16((TC)a[i][t], (TC)b[j][t], acc[i][j]);
+}
 
-// ---------------------------------------------------------------------------
-// Contraction over p:  U[k][i] = sum_j A[i + j*lda] * B[k*ldb + j]
-// A column-major (np x pp), B node-major, U node-major (ldu).  32 x 32 output
-// tile per workgroup; the 4 waves split the contraction range in quarters.
-// Lane l of a wave reads 4 consecutive j of one node row (one vector load) and
-// the matching 4 columns of A; the 4 MFMAs of a 16-wide chunk take slot l/16 as
-// j = j0 + 4 (l/16) + t for both operands.
-// ---------------------------------------------------------------------------
-template <class TA, class TB, class TC>
-__global__ __launch_bounds__(256) void k_gemm_xw(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B,
-                                                 int64_t ldb, TC *__restrict__ U, int64_t ldu, int64_t kdim) {
-    __shared__ TC red[4 * 1024];
+template <class TA, class TB, class TC, int BM, int BN>
+__device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B, int64_t ldb,
+                                        int64_t kdim, int64_t m0, int64_t n0, TC *red) {
+    constexpr int TM = 16 * BM, TN = 16 * BN;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
     typedef typename Acc<TC>::type AccT;
-    AccT acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
-    const int64_t kq = kdim / 4;
-    const int64_t kb = w * kq, ke = kb + kq;
-    const TA *Ab = A + m0 + r;
-    const TB *B0 = B + (n0 + r) * ldb + 4 * q;
-    const TB *B1 = B + (n0 + 16 + r) * ldb + 4 * q;
-    for (int64_t j0 = kb; j0 < ke; j0 += 16) {
-        TB bv0[4], bv1[4];
-        load4(B0 + j0, bv0);
-        load4(B1 + j0, bv1);
-        TA av[2][4];
-        for (int t = 0; t < 4; ++t) {
-            const TA *col = Ab + (j0 + 4 * q + t) * lda;
-            av[0][t] = col[0];
-            av[1][t] = col[16];
+    AccT acc[BM][BN];
+    for (int i = 0; i < BM; ++i)
+        for (int j = 0; j < BN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
+    const int64_t kq = kdim / 4, kb = w * kq, ke = kb + kq;
+    const TA *Ap[BM];
+    const TB *Bp[BN];
+    for (int i = 0; i < BM; ++i) Ap[i] = A + (m0 + 16 * i + r) * lda + 4 * q;
+    for (int j = 0; j < BN; ++j) Bp[j] = B + (n0 + 16 * j + r) * ldb + 4 * q;
+    TA a0[BM][4], a1[BM][4];
+    TB b0[BN][4], b1[BN][4];
+    for (int i = 0; i < BM; ++i) load4(Ap[i] + kb, a0[i]);
+    for (int j = 0; j < BN; ++j) load4(Bp[j] + kb, b0[j]);
+    for (int64_t k0 = kb; k0 < ke; k0 += 32) {
+        for (int i = 0; i < BM; ++i) load4(Ap[i] + k0 + 16, a1[i]);
+        for (int j = 0; j < BN; ++j) load4(Bp[j] + k0 + 16, b1[j]);
+        mma_chunk<TC, BM, BN>(acc, a0, b0);
+        if (k0 + 32 < ke) {
+            for (int i = 0; i < BM; ++i) load4(Ap[i] + k0 + 32, a0[i]);
+            for (int j = 0; j < BN; ++j) load4(Bp[j] + k0 + 32, b0[j]);
         }
-        for (int t = 0; t < 4; ++t) {
-            TC b0 = (TC)bv0[t], b1 = (TC)bv1[t];
-            TC a0 = (TC)av[0][t], a1 = (TC)av[1][t];
-            acc[0][0] = mfma16(a0, b0, acc[0][0]);
-            acc[0][1] = mfma16(a0, b1, acc[0][1]);
-            acc[1][0] = mfma16(a1, b0, acc[1][0]);
-            acc[1][1] = mfma16(a1, b1, acc[1][1]);
-        }
+        mma_chunk<TC, BM, BN>(acc, a1, b1);
     }
-    tile_to_lds<TC>(acc, red, w, lane);
+    for (int i = 0; i < BM; ++i)
+        for (int j = 0; j < BN; ++j)
+            for (int v = 0; v < 4; ++v) {
+                int m = 16 * i + acc_row<TC>(lane, v);
+                int n = 16 * j + r;
+                red[w * TM * TN + n * TM + m] = acc[i][j][v];
+            }
     __syncthreads();
-    for (int e = 0; e < 4; ++e) {
-        int idx = tid + 256 * e;
-        int n = idx >> 5, m = idx & 31;
-        U[(n0 + n) * ldu + m0 + m] = tile_sum<TC>(red, idx);
+}
+
+template <class TC, int TMTN>
+__device__ __forceinline__ TC sum_waves(const TC *red, int idx) {
+    return red[idx] + red[TMTN + idx] + red[2 * TMTN + idx] + red[3 * TMTN + idx];
+}
+
+// Contraction over p: U[k][i] = sum_j Xh[i][j] W[k][j] (A = row-major Xh).
+template <class TA, class TB, class TC, int BM, int BN>
+__global__ __launch_bounds__(256) void k_gemm_xw(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B,
+                                                 int64_t ldb, TC *__restrict__ U, int64_t ldu, int64_t kdim) {
+    constexpr int TM = 16 * BM, TN = 16 * BN;
+    __shared__ TC red[4 * TM * TN];
+    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    nt_tile<TA, TB, TC, BM, BN>(A, lda, B, ldb, kdim, m0, n0, red);
+    for (int idx = threadIdx.x; idx < TM * TN; idx += 256) {
+        int n = idx / TM, m = idx % TM;
+        U[(n0 + n) * ldu + m0 + m] = sum_waves<TC, TM * TN>(red, idx);
     }
 }
 
-// ---------------------------------------------------------------------------
 // Contraction over n with the ADMM epilogue:
-//   Q[k][j] = sum_i A[i + j*lda] * U[k*ldu + i], then b, beta, V, W of node k,
-//   coordinate j.  Lane l reads 4 consecutive i of column j (A) and of node row k
-//   (U); slot l/16 of the 4 MFMAs is i = i0 + 4 (l/16) + t for both.
-// ---------------------------------------------------------------------------
-template <class TA, class T>
+//   Q[k][j] = sum_i Xh[i][j] U[k][i], then for node k and coordinate j:
+//   b = (W - Q) / rho, beta = prox(b + V / rho), V += rho (b - beta),
+//   W = c + rho beta - V.
+template <class TA, class T, int BM, int BN>
 __global__ __launch_bounds__(256) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
                                                   int64_t ldu, int64_t kdim, T *__restrict__ W,
                                                   T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
                                                   const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                                   const int *__restrict__ active, DevParams<T> q, int64_t ldp,
                                                   int store_b) {
-    __shared__ T red[4 * 1024];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int qq = lane >> 4, r = lane & 15;
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    typedef typename Acc<T>::type AccT;
-    AccT acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = AccT{0, 0, 0, 0};
-    const int64_t kq = kdim / 4;
-    const int64_t ib = w * kq, ie = ib + kq;
-    const TA *A0 = A + (m0 + r) * lda + 4 * qq;
-    const TA *A1 = A + (m0 + 16 + r) * lda + 4 * qq;
-    const T *U0 = U + (n0 + r) * ldu + 4 * qq;
-    const T *U1 = U + (n0 + 16 + r) * ldu + 4 * qq;
-    for (int64_t i0 = ib; i0 < ie; i0 += 16) {
-        TA a0[4], a1[4];
-        T u0[4], u1[4];
-        load4(A0 + i0, a0);
-        load4(A1 + i0, a1);
-        load4(U0 + i0, u0);
-        load4(U1 + i0, u1);
-        for (int t = 0; t < 4; ++t) {
-            T x0 = (T)a0[t], x1 = (T)a1[t];
-            acc[0][0] = mfma16(x0, u0[t], acc[0][0]);
-            acc[0][1] = mfma16(x0, u1[t], acc[0][1]);
-            acc[1][0] = mfma16(x1, u0[t], acc[1][0]);
-            acc[1][1] = mfma16(x1, u1[t], acc[1][1]);
-        }
-    }
-    tile_to_lds<T>(acc, red, w, lane);
-    __syncthreads();
-    for (int e = 0; e < 4; ++e) {
-        int idx = tid + 256 * e;
-        int n = idx >> 5, m = idx & 31;
+    constexpr int TM = 16 * BM, TN = 16 * BN;
+    __shared__ T red[4 * TM * TN];
+    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    nt_tile<TA, T, T, BM, BN>(A, lda, U, ldu, kdim, m0, n0, red);
+    for (int idx = threadIdx.x; idx < TM * TN; idx += 256) {
+        int n = idx / TM, m = idx % TM;
         int64_t node = n0 + n, j = m0 + m;
         if (!active[node]) continue;
-        T Qv = tile_sum<T>(red, idx);
+        T Qv = sum_waves<T, TM * TN>(red, idx);
         int64_t o = node * ldp + j;
         T wv = W[o];
         T bb = (wv - Qv) / q.rho;
@@ -415,33 +411,9 @@ __global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, 
                                                   const double *__restrict__ nodescal, const int *__restrict__ active,
                                                   double *__restrict__ part, int64_t ldp, DualArgs da) {
     __shared__ double red[4 * 1024];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int qq = lane >> 4, r = lane & 15;
+    const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    f64x4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
-    const int64_t kq = kdim / 4;
-    const int64_t ib = w * kq, ie = ib + kq;
-    const double *A0 = A + (m0 + r) * lda + 4 * qq;
-    const double *A1 = A + (m0 + 16 + r) * lda + 4 * qq;
-    const double *U0 = R + (n0 + r) * ldr + 4 * qq;
-    const double *U1 = R + (n0 + 16 + r) * ldr + 4 * qq;
-    for (int64_t i0 = ib; i0 < ie; i0 += 16) {
-        double a0[4], a1[4], u0[4], u1[4];
-        load4(A0 + i0, a0);
-        load4(A1 + i0, a1);
-        load4(U0 + i0, u0);
-        load4(U1 + i0, u1);
-        for (int t = 0; t < 4; ++t) {
-            acc[0][0] = mfma16(a0[t], u0[t], acc[0][0]);
-            acc[0][1] = mfma16(a0[t], u1[t], acc[0][1]);
-            acc[1][0] = mfma16(a1[t], u0[t], acc[1][0]);
-            acc[1][1] = mfma16(a1[t], u1[t], acc[1][1]);
-        }
-    }
-    tile_to_lds<double>(acc, red, w, lane);
-    __syncthreads();
+    nt_tile<double, double, double, 2, 2>(A, lda, R, ldr, kdim, m0, n0, red);
     // thread t: node n = t / 8, coordinates 4 (t % 8) .. +3 of the tile
     const int n = tid >> 3, jl = (tid & 7) * 4;
     const int64_t node = n0 + n;
@@ -566,7 +538,8 @@ unsigned grid1d(int64_t total) { return (unsigned)std::min<int64_t>((total + 255
 // The arrays one sweep works on, in the arithmetic type T of the sweep.
 template <class T>
 struct Sweep {
-    const T *Xh;   // np x pp folded operand
+    const T *Xh;   // np x pp folded operand, column-major
+    const T *XhR;  // the same, row-major
     const T *c;    // pp
     T *W, *beta, *V, *B, *U;
 };
@@ -575,10 +548,10 @@ Sweep<double> sweep64(l0l2_ctx *ctx) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     if (in.prec == L0L2_FP64)
-        return {in.Xh.as<double>(), in.c64.as<double>(), ws.W.as<double>(), ws.beta.as<double>(), ws.V.as<double>(),
-                ws.B.as<double>(), ws.U.as<double>()};
-    return {in.Xh64.as<double>(), in.c64.as<double>(), ws.W64.as<double>(), ws.beta64.as<double>(),
-            ws.V64.as<double>(), ws.B64.as<double>(), ws.U64.as<double>()};
+        return {in.Xh.as<double>(), in.XhRw.as<double>(), in.c64.as<double>(), ws.W.as<double>(),
+                ws.beta.as<double>(), ws.V.as<double>(), ws.B.as<double>(), ws.U.as<double>()};
+    return {in.Xh64.as<double>(), in.Xh64R.as<double>(), in.c64.as<double>(), ws.W64.as<double>(),
+            ws.beta64.as<double>(), ws.V64.as<double>(), ws.B64.as<double>(), ws.U64.as<double>()};
 }
 
 // FP32 state arrays (the FP32 mode's operand; in BF16 mode Xh is the BF16 pair
@@ -586,8 +559,9 @@ Sweep<double> sweep64(l0l2_ctx *ctx) {
 Sweep<float> sweep32(l0l2_ctx *ctx) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
-    return {in.prec == L0L2_FP32 ? in.Xh.as<float>() : nullptr, in.cst.as<float>(), ws.W.as<float>(),
-            ws.beta.as<float>(), ws.V.as<float>(), ws.B.as<float>(), ws.U.as<float>()};
+    const bool f32 = in.prec == L0L2_FP32;
+    return {f32 ? in.Xh.as<float>() : nullptr, f32 ? in.XhRw.as<float>() : nullptr, in.cst.as<float>(),
+            ws.W.as<float>(), ws.beta.as<float>(), ws.V.as<float>(), ws.B.as<float>(), ws.U.as<float>()};
 }
 
 template <class T> constexpr int prof_xw();
@@ -600,21 +574,109 @@ template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
 // ---------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------
+// Tile shapes (BM, BN) of the sweep contractions, in 16-row blocks.
+constexpr int kTileBM[4] = {2, 1, 2, 1};
+constexpr int kTileBN[4] = {2, 2, 1, 1};
+
+template <class TA, class TB, class TC>
+void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int64_t ldb, TC *U, int64_t ldu,
+               int64_t rows, int64_t Kp, int64_t kdim) {
+    dim3 g((unsigned)(rows / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
+    switch (v) {
+        case 0: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 2, 2>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
+        case 1: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 1, 2>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
+        case 2: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 2, 1>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
+        default: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 1, 1>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
+    }
+}
+
+template <class T>
+void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes,
+                const int *active, const DevParams<T> &q, int store_b) {
+    dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
+#define L0L2_XTU(BM, BN)                                                                                           \
+    hipLaunchKernelGGL((k_admm_xtu<T, T, BM, BN>), g, dim3(256), 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, \
+                       sw.B, codes, sw.c, active, q, pp, store_b)
+    switch (v) {
+        case 0: L0L2_XTU(2, 2); break;
+        case 1: L0L2_XTU(1, 2); break;
+        case 2: L0L2_XTU(2, 1); break;
+        default: L0L2_XTU(1, 1); break;
+    }
+#undef L0L2_XTU
+}
+
+// Tile shapes chosen for (arithmetic type, padded batch): each shape is timed
+// on the live batch (every node masked inactive, so the epilogue writes
+// nothing) and the fastest kept for this instance.
+template <class T>
+TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    if (ctx->force_xw >= 0) {
+        static thread_local TileChoice forced;
+        forced.xw = ctx->force_xw;
+        forced.xtu = ctx->force_xtu;
+        return forced;
+    }
+    const int kind = sizeof(T) == 8 ? 1 : 0;
+    auto key = std::make_pair(kind, Kp);
+    auto it = in.tiles.find(key);
+    if (it != in.tiles.end()) return it->second;
+    TileChoice tc;
+    if (ctx->tune) {
+        hipStream_t s = ctx->stream;
+        const int64_t np = in.np, pp = in.pp;
+        DevBuf inactive;
+        inactive.ensure(sizeof(int) * Kp);
+        HIPCHK(hipMemsetAsync(inactive.ptr, 0, sizeof(int) * Kp, s));
+        DevParams<T> q = dev_params<T>(in.mp);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        float best_xw = 1e30f, best_xtu = 1e30f;
+        for (int v = 0; v < 4; ++v) {
+            for (int rep = 0; rep < 2; ++rep) {
+                float ms[2];
+                for (int which = 0; which < 2; ++which) {
+                    HIPCHK(hipEventRecord(e0, s));
+                    for (int t = 0; t < 3; ++t) {
+                        if (which == 0) launch_xw<T, T, T>(v, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp);
+                        else launch_xtu<T>(v, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), inactive.as<int>(), q, 0);
+                    }
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    HIPCHK(hipEventElapsedTime(&ms[which], e0, e1));
+                }
+                if (rep == 1) {
+                    if (ms[0] < best_xw) { best_xw = ms[0]; tc.xw = v; }
+                    if (ms[1] < best_xtu) { best_xtu = ms[1]; tc.xtu = v; }
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(hipGetLastError());
+    }
+    return in.tiles[key] = tc;
+}
+
+// ---------------------------------------------------------------------------
+// Host drivers
+// ---------------------------------------------------------------------------
 template <class T>
 void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int64_t active) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     const int64_t np = in.np, pp = in.pp;
-    dim3 g1((unsigned)(np / 32), (unsigned)(Kp / 32));
-    dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     DevParams<T> q = dev_params<T>(in.mp);
+    const TileChoice &tc = tile_choice<T>(ctx, sw, Kp);
     prof_begin(ctx, prof_xw<T>());
-    hipLaunchKernelGGL((k_gemm_xw<T, T, T>), g1, dim3(256), 0, s, sw.Xh, np, sw.W, pp, sw.U, np, pp);
+    launch_xw<T, T, T>(tc.xw, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp);
     prof_end(ctx, prof_xw<T>(), active);
     prof_begin(ctx, prof_xtu<T>());
-    hipLaunchKernelGGL((k_admm_xtu<T, T>), g2, dim3(256), 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, sw.B,
-                       ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp, store_b ? 1 : 0);
+    launch_xtu<T>(tc.xtu, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), ws.active.as<int>(), q, store_b ? 1 : 0);
     prof_end(ctx, prof_xtu<T>(), active);
     HIPCHK(hipGetLastError());
 }
@@ -664,11 +726,9 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t K, int64_t Kp,
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     const double *X64 = in.X64.as<double>();
     prof_begin(ctx, PROF_CHECK);
-    hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, B, pp, ws.Ub.as<double>(), np,
-                       pp);
-    if (mode == 0)
-        hipLaunchKernelGGL((k_gemm_xw<double, T, double>), g1, dim3(256), 0, s, X64, np, beta, pp,
-                           ws.Ubeta.as<double>(), np, pp);
+    const double *X64R = in.X64R.as<double>();
+    launch_xw<double, T, double>(0, s, X64R, pp, B, pp, ws.Ub.as<double>(), np, np, Kp, pp);
+    if (mode == 0) launch_xw<double, T, double>(0, s, X64R, pp, beta, pp, ws.Ubeta.as<double>(), np, np, Kp, pp);
     hipLaunchKernelGGL(k_resid, dim3((unsigned)K), dim3(256), 0, s, in.y64.as<double>(), ws.Ub.as<double>(),
                        ws.Ubeta.as<double>(), ws.R.as<double>(), np, ws.nodescal.as<double>(), ws.active.as<int>(),
                        mode == 0 ? 1 : 0);

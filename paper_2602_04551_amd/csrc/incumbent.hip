@@ -121,20 +121,51 @@ __device__ double U_S(const double *__restrict__ X, int64_t np, const double *__
     return 0.5 * rr + fa.l2 * bb;
 }
 
-// Fast proximal gradient on each support (eqs. fpg_extrapolate .. fpg_armijo):
+// Fast proximal gradient on each support (eqs. fpg_extrapolate .. fpg_armijo),
 // one workgroup per node.  Start at the node iterate on S; alpha_0 =
 // 4 / (||X_S||_F^2 + 2 l2), halved on each Armijo failure (at most 60 times per
 // iteration) and carried over; stop on |dU| <= tol max(1, U) or max|d beta| <=
-// 1e-10.
+// 1e-10; at most max_iter iterations.
+//
+// Supports of up to kGramMax coordinates keep G = X_S^T X_S and g = X_S^T y in
+// LDS (built in one pass over X_S), so an iteration costs O(|S|^2) on chip:
+// U(b) = 1/2 ||y||^2 - g^T b + 1/2 b^T G b + l2 ||b||^2 and grad = G b - g + 2 l2 b.
+// Larger supports stream X_S once per evaluation.  Either way the returned
+// objective F(S, beta) is evaluated from the residual y - X_S beta in FP64.
+constexpr int kGramMax = 96;
+constexpr int kGramRows = 32;
+
+struct FistaShared {
+    int idx[kSMax];
+    double cur[kSMax], prev[kSMax], ext[kSMax], nxt[kSMax], grad[kSMax];
+    double G[kGramMax * kGramMax];
+    double tile[kGramRows * kGramMax];
+    double g[kGramMax], Gv[kGramMax];
+    double sh[4];
+    int shw[4];
+};
+
+// v -> (1/2 v^T G v - g^T v + l2 ||v||^2 + yy/2), and Gv into sm.Gv (Gram form).
+__device__ double U_gram(FistaShared &sm, const double *v, int k, double yy, double l2) {
+    const int tid = threadIdx.x;
+    double part = 0.0;
+    if (tid < k) {
+        double s = 0.0;
+        const double *row = sm.G + tid * k;
+        for (int b = 0; b < k; ++b) s += row[b] * v[b];
+        sm.Gv[tid] = s;
+        part = 0.5 * v[tid] * s - sm.g[tid] * v[tid] + l2 * v[tid] * v[tid];
+    }
+    part = bsum(part, sm.sh);
+    return 0.5 * yy + part;
+}
+
 __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, const double *__restrict__ y,
-                                               const double *__restrict__ colnrm, const uint8_t *__restrict__ sup,
-                                               int64_t lds, double *__restrict__ beta, int64_t ldb,
-                                               double *__restrict__ resbuf, double *__restrict__ obj,
-                                               int32_t *__restrict__ iters, FistaArgs fa) {
-    __shared__ int idx[kSMax];
-    __shared__ double cur[kSMax], prev[kSMax], ext[kSMax], nxt[kSMax], grad[kSMax];
-    __shared__ double sh[4];
-    __shared__ int shw[4];
+                                               const double *__restrict__ colnrm, const double *__restrict__ c,
+                                               double yy, const uint8_t *__restrict__ sup, int64_t lds,
+                                               double *__restrict__ beta, int64_t ldb, double *__restrict__ resbuf,
+                                               double *__restrict__ obj, int32_t *__restrict__ iters, FistaArgs fa) {
+    __shared__ FistaShared sm;
     const int64_t node = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     double *res = resbuf + node * fa.np;
@@ -146,14 +177,15 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         unsigned long long bal = __ballot(f);
         int before = __popcll(bal & ((1ull << lane) - 1ull));
         __syncthreads();
-        if (lane == 0) shw[w] = __popcll(bal);
+        if (lane == 0) sm.shw[w] = __popcll(bal);
         __syncthreads();
         int off = k;
-        for (int ww = 0; ww < w; ++ww) off += shw[ww];
-        if (f && off + before < kSMax) idx[off + before] = (int)j;
-        k += shw[0] + shw[1] + shw[2] + shw[3];
+        for (int ww = 0; ww < w; ++ww) off += sm.shw[ww];
+        if (f && off + before < kSMax) sm.idx[off + before] = (int)j;
+        k += sm.shw[0] + sm.shw[1] + sm.shw[2] + sm.shw[3];
     }
     __syncthreads();
+    const int *idx = sm.idx;
     if (k > kSMax) {
         if (tid == 0) {
             obj[node] = NAN;
@@ -162,77 +194,107 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         return;
     }
     if (k == 0) {
-        double yy = 0.0;
-        for (int64_t i = tid; i < fa.n; i += 256) yy += y[i] * y[i];
-        yy = bsum(yy, sh);
+        double s = 0.0;
+        for (int64_t i = tid; i < fa.n; i += 256) s += y[i] * y[i];
+        s = bsum(s, sm.sh);
         for (int64_t j = tid; j < fa.p; j += 256) beta[node * ldb + j] = 0.0;
         if (tid == 0) {
-            obj[node] = 0.5 * yy;
+            obj[node] = 0.5 * s;
             if (iters) iters[node] = 0;
         }
         return;
+    }
+    const bool gram = k <= kGramMax;
+    if (gram) {
+        // G = X_S^T X_S by row tiles of X_S staged in LDS; thread t accumulates
+        // entries t, t + 256, ... of G in place.
+        for (int e = tid; e < k * k; e += 256) sm.G[e] = 0.0;
+        for (int64_t i0 = 0; i0 < fa.n; i0 += kGramRows) {
+            __syncthreads();
+            for (int e = tid; e < kGramRows * k; e += 256) {
+                int r = e % kGramRows, a = e / kGramRows;
+                int64_t i = i0 + r;
+                sm.tile[r * k + a] = i < fa.n ? X[(int64_t)idx[a] * fa.np + i] : 0.0;
+            }
+            __syncthreads();
+            for (int e = tid; e < k * k; e += 256) {
+                int a = e / k, b = e % k;
+                double s = 0.0;
+                for (int r = 0; r < kGramRows; ++r) s += sm.tile[r * k + a] * sm.tile[r * k + b];
+                sm.G[e] += s;
+            }
+        }
+        __syncthreads();
+        if (tid < k) sm.g[tid] = c[idx[tid]];
+        __syncthreads();
     }
     double fro = 0.0;
     for (int a = tid; a < k; a += 256) {
         double b0 = beta[node * ldb + idx[a]];
         b0 = b0 > fa.M ? fa.M : (b0 < -fa.M ? -fa.M : b0);
-        cur[a] = b0;
-        prev[a] = b0;
+        sm.cur[a] = b0;
+        sm.prev[a] = b0;
         double cn = colnrm[idx[a]];
         fro += cn * cn;
     }
-    fro = bsum(fro, sh);
+    fro = bsum(fro, sm.sh);
     double alpha = 4.0 / (fro + 2.0 * fa.l2);
-    double Ucur = U_S(X, fa.np, y, idx, k, cur, res, false, sh, fa);
+    double Ucur = gram ? U_gram(sm, sm.cur, k, yy, fa.l2) : U_S(X, fa.np, y, idx, k, sm.cur, res, false, sm.sh, fa);
     int it = 0;
     while (it < fa.max_iter) {
         double mom = (double)it / ((double)it + 3.0);
-        for (int a = tid; a < k; a += 256) ext[a] = cur[a] + mom * (cur[a] - prev[a]);
+        for (int a = tid; a < k; a += 256) sm.ext[a] = sm.cur[a] + mom * (sm.cur[a] - sm.prev[a]);
         __syncthreads();
-        double Uext = U_S(X, fa.np, y, idx, k, ext, res, true, sh, fa);
-        __syncthreads();
-        for (int a = w; a < k; a += 4) {
-            const double *col = X + (int64_t)idx[a] * fa.np;
-            double s = 0.0;
-            for (int64_t i = lane; i < fa.n; i += 64) s += col[i] * res[i];
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-            if (lane == 0) grad[a] = s + 2.0 * fa.l2 * ext[a];
+        double Uext;
+        if (gram) {
+            Uext = U_gram(sm, sm.ext, k, yy, fa.l2);
+            if (tid < k) sm.grad[tid] = sm.Gv[tid] - sm.g[tid] + 2.0 * fa.l2 * sm.ext[tid];
+        } else {
+            Uext = U_S(X, fa.np, y, idx, k, sm.ext, res, true, sm.sh, fa);
+            __syncthreads();
+            for (int a = w; a < k; a += 4) {
+                const double *col = X + (int64_t)idx[a] * fa.np;
+                double s = 0.0;
+                for (int64_t i = lane; i < fa.n; i += 64) s += col[i] * res[i];
+                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+                if (lane == 0) sm.grad[a] = s + 2.0 * fa.l2 * sm.ext[a];
+            }
         }
         __syncthreads();
         double Unxt = 0.0;
         for (int bt = 0; bt <= 60; ++bt) {
             double gd = 0.0, dd = 0.0;
             for (int a = tid; a < k; a += 256) {
-                double v = ext[a] - alpha * grad[a];
+                double v = sm.ext[a] - alpha * sm.grad[a];
                 v = v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v);
-                nxt[a] = v;
-                double d = v - ext[a];
-                gd += grad[a] * d;
+                sm.nxt[a] = v;
+                double d = v - sm.ext[a];
+                gd += sm.grad[a] * d;
                 dd += d * d;
             }
-            gd = bsum(gd, sh);
-            dd = bsum(dd, sh);
-            Unxt = U_S(X, fa.np, y, idx, k, nxt, res, false, sh, fa);
+            gd = bsum(gd, sm.sh);
+            dd = bsum(dd, sm.sh);
+            Unxt = gram ? U_gram(sm, sm.nxt, k, yy, fa.l2) : U_S(X, fa.np, y, idx, k, sm.nxt, res, false, sm.sh, fa);
             if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
             alpha *= 0.5;
         }
         ++it;
         double dm = 0.0;
-        for (int a = tid; a < k; a += 256) dm = fmax(dm, fabs(nxt[a] - cur[a]));
-        dm = bmax(dm, sh);
+        for (int a = tid; a < k; a += 256) dm = fmax(dm, fabs(sm.nxt[a] - sm.cur[a]));
+        dm = bmax(dm, sm.sh);
         double dU = fabs(Unxt - Ucur);
         for (int a = tid; a < k; a += 256) {
-            prev[a] = cur[a];
-            cur[a] = nxt[a];
+            sm.prev[a] = sm.cur[a];
+            sm.cur[a] = sm.nxt[a];
         }
         __syncthreads();
         Ucur = Unxt;
         if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
     }
-    double f = U_S(X, fa.np, y, idx, k, cur, res, false, sh, fa) + fa.l0 * (double)k;
+    double f = U_S(X, fa.np, y, idx, k, sm.cur, res, false, sm.sh, fa) + fa.l0 * (double)k;
     for (int64_t j = tid; j < fa.p; j += 256) beta[node * ldb + j] = 0.0;
     __syncthreads();
-    for (int a = tid; a < k; a += 256) beta[node * ldb + idx[a]] = cur[a];
+    for (int a = tid; a < k; a += 256) beta[node * ldb + idx[a]] = sm.cur[a];
     if (tid == 0) {
         obj[node] = f;
         if (iters) iters[node] = it;
@@ -375,8 +437,8 @@ void run_fista(l0l2_ctx *ctx, int K, const uint8_t *support, int64_t ld_support,
     FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, o.tol, o.max_iter, in.n, in.np, in.p};
     prof_begin(ctx, PROF_FISTA);
     hipLaunchKernelGGL(k_fista, dim3((unsigned)K), dim3(256), 0, ctx->stream, in.X64.as<double>(), in.y64.as<double>(),
-                       in.colnrm.as<double>(), support, ld_support, beta, ld_beta, ctx->ws.fista.as<double>(), obj,
-                       iters, fa);
+                       in.colnrm.as<double>(), in.c64.as<double>(), in.yy, support, ld_support, beta, ld_beta,
+                       ctx->ws.fista.as<double>(), obj, iters, fa);
     prof_end(ctx, PROF_FISTA);
     HIPCHK(hipGetLastError());
 }

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/l0l2.h"
@@ -58,6 +60,11 @@ struct MethodParams {
     double psi_lin;     // 2 sqrt(l0 l2) if free_quad else l0 / M + l2 M
 };
 
+// Tile shapes (index into the sweep kernels' shape table) of the two contractions.
+struct TileChoice {
+    int xw = 0, xtu = 0;
+};
+
 struct Instance {
     int64_t n = 0, p = 0, np = 0, pp = 0;   // true and padded sizes
     int prec = L0L2_FP64;
@@ -72,8 +79,12 @@ struct Instance {
     DevBuf XhLo;      // BF16 mode: column-major low half (Xh - bf16(Xh))
     DevBuf XhR;       // BF16 mode: row-major high half (row i contiguous over pp)
     DevBuf XhRLo;     // BF16 mode: row-major low half
-    DevBuf Xh64;      // FP32 mode: FP64 folded operand for the final sweeps of a node
+    DevBuf Xh64;      // FP32 / BF16 mode: FP64 folded operand for the final sweeps of a node
+    DevBuf XhRw;      // FP64 / FP32 mode: row-major copy of Xh in the working precision
+    DevBuf Xh64R;     // FP32 / BF16 mode: row-major copy of Xh64
+    DevBuf X64R;      // row-major copy of X64 (contraction over p of the gap check)
     DevBuf codes_pad; // scratch
+    std::map<std::pair<int, int64_t>, TileChoice> tiles;   // autotuned per (type, padded K)
 };
 
 // Per-batch workspace, grown on demand (capacity in padded nodes).
@@ -116,6 +127,8 @@ struct l0l2_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     bool has_data = false;
+    bool tune = true;          // time the tile shapes of each new batch size
+    int force_xw = -1, force_xtu = -1;   // fixed tile shapes (-1: autotune)
     l0l2::Instance inst;
     l0l2::Workspace ws;
     l0l2::Profiler prof;

@@ -183,6 +183,26 @@ __global__ __launch_bounds__(64) void k_trsv_rows(const double *S, int64_t lds, 
     for (int i = 0; i < nb; ++i) X[kb + i + col * ldx] = Xc[t][i];
 }
 
+// dst (row-major, row i of length pp) <- src (np x pp column-major), by 32 x 32
+// tiles through LDS so both sides are coalesced.
+template <class TS, class TD>
+__global__ __launch_bounds__(256) void k_transpose(const TS *__restrict__ src, TD *__restrict__ dst, int64_t np,
+                                                   int64_t pp) {
+    __shared__ TD t[32][33];
+    const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int r = ty; r < 32; r += 8) t[r][tx] = (TD)src[(j0 + r) * np + i0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) dst[(i0 + r) * pp + j0 + tx] = t[tx][r];
+}
+
+template <class TS, class TD>
+void transpose(hipStream_t st, const TS *src, TD *dst, int64_t np, int64_t pp) {
+    hipLaunchKernelGGL((k_transpose<TS, TD>), dim3((unsigned)(np / 32), (unsigned)(pp / 32)), dim3(256), 0, st, src,
+                       dst, np, pp);
+    HIPCHK(hipGetLastError());
+}
+
 __global__ void k_add_diag(double *S, int64_t ld, int64_t n, double r) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) S[i + i * ld] += r;
@@ -246,6 +266,7 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     ctx->has_data = false;
     // the per-batch workspace is sized for the previous instance: drop it
     ctx->ws.cap = 0;
+    in.tiles.clear();
     in.n = n;
     in.p = p;
     in.np = round_up(n, kPadRows);
@@ -329,7 +350,19 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
         }
         HIPCHK(hipGetLastError());
     }
+    // row-major copies for the contractions over p
+    in.X64R.ensure(sizeof(double) * (size_t)(np * pp));
+    transpose<double, double>(st, X64, in.X64R.as<double>(), np, pp);
+    if (prec == L0L2_FP64) {
+        in.XhRw.ensure(sizeof(double) * (size_t)(np * pp));
+        transpose<double, double>(st, Xh, in.XhRw.as<double>(), np, pp);
+    } else {
+        in.Xh64R.ensure(sizeof(double) * (size_t)(np * pp));
+        transpose<double, double>(st, Xh, in.Xh64R.as<double>(), np, pp);
+    }
     if (prec == L0L2_FP32) {
+        in.XhRw.ensure(sizeof(float) * (size_t)(np * pp));
+        transpose<double, float>(st, Xh, in.XhRw.as<float>(), np, pp);
         in.Xh.ensure(sizeof(float) * (size_t)(np * pp));
         hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, st, Xh, in.Xh.as<float>(), np * pp);
         in.cst.ensure(sizeof(float) * (size_t)pp);
