@@ -69,14 +69,18 @@ __global__ void k_store_state(const T *__restrict__ src, int64_t K, int64_t p, i
     }
 }
 
-__global__ void k_set_active(int *active, int *status, int *iters, int64_t K, int64_t Kp) {
+__global__ void k_set_active(int *active, int *status, int *iters, int64_t K, int64_t Kp, int *sweep_no) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < Kp) {
         active[k] = k < K;
         status[k] = 1;
         iters[k] = 0;
     }
+    if (k == 0) *sweep_no = 0;
 }
+
+// Sweep counter of the batch, advanced at the start of each block of sweeps.
+__global__ void k_sweep_add(int *sweep_no, int n) { *sweep_no += n; }
 
 // Warm start of Sec. 3.1.3: impose F0 on beta, then W = c + rho beta - V.
 template <class T>
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, 
 struct FinArgs {
     double gamma_n2, gamma_p, tol, switch_tol;
     int64_t K, ntile;
-    int iter, mode;  // mode 0: solve (gap test), 1: bound only
+    int mode;  // mode 0: solve (gap test), 1: bound only
 };
 
 // One workgroup: per active node, LB = (q - sum nu+) - margin (Prop. 1 plus the
@@ -462,8 +466,10 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ nod
                                                   const double *__restrict__ part, int *__restrict__ active,
                                                   int *__restrict__ status, int *__restrict__ iters,
                                                   double *__restrict__ lb, double *__restrict__ primal,
-                                                  int *__restrict__ counter, FinArgs fa) {
+                                                  int *__restrict__ counter, const int *__restrict__ sweep_no,
+                                                  FinArgs fa) {
     __shared__ int shc[256], shc2[256];
+    const int iter = *sweep_no;
     const double u = 1.1102230246251565e-16;
     int cnt = 0, cnt2 = 0;
     for (int64_t k = threadIdx.x; k < fa.K; k += 256) {
@@ -484,7 +490,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ nod
         if (fa.mode == 1) continue;
         double P = 0.5 * rbrb + spsi;
         primal[k] = P;
-        iters[k] = fa.iter;
+        iters[k] = iter;
         double den = fabs(P) > 1e-300 ? fabs(P) : 1e-300;
         if ((P - LB) / den <= fa.tol) {
             status[k] = 0;
@@ -716,8 +722,7 @@ DualArgs dual_args(const Instance &in) {
 // FP64 check at (B, beta) of type T: fills ws.lb / primal / status / active and
 // the two counters (active nodes; active nodes above switch_tol).
 template <class T>
-void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t K, int64_t Kp, int iter, double tol,
-                double switch_tol, int mode) {
+void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol, double switch_tol, int mode) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
@@ -729,7 +734,7 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t K, int64_t Kp,
     const double *X64R = in.X64R.as<double>();
     launch_xw<double, T, double>(0, s, X64R, pp, B, pp, ws.Ub.as<double>(), np, np, Kp, pp);
     if (mode == 0) launch_xw<double, T, double>(0, s, X64R, pp, beta, pp, ws.Ubeta.as<double>(), np, np, Kp, pp);
-    hipLaunchKernelGGL(k_resid, dim3((unsigned)K), dim3(256), 0, s, in.y64.as<double>(), ws.Ub.as<double>(),
+    hipLaunchKernelGGL(k_resid, dim3((unsigned)Kp), dim3(256), 0, s, in.y64.as<double>(), ws.Ub.as<double>(),
                        ws.Ubeta.as<double>(), ws.R.as<double>(), np, ws.nodescal.as<double>(), ws.active.as<int>(),
                        mode == 0 ? 1 : 0);
     DualArgs da = dual_args(in);
@@ -742,13 +747,12 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t K, int64_t Kp,
     fa.gamma_p = (double)in.p * u / (1.0 - (double)in.p * u);
     fa.tol = tol;
     fa.switch_tol = switch_tol;
-    fa.K = K;
+    fa.K = Kp;
     fa.ntile = pp / 32;
-    fa.iter = iter;
     fa.mode = mode;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ws.nodescal.as<double>(), ws.part.as<double>(),
                        ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), ws.lb.as<double>(),
-                       ws.primal.as<double>(), ws.counter.as<int>(), fa);
+                       ws.primal.as<double>(), ws.counter.as<int>(), ws.sweep_no.as<int>(), fa);
     prof_end(ctx, PROF_CHECK);
     HIPCHK(hipGetLastError());
 }
@@ -759,7 +763,7 @@ void init_batch(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t K, int64_t Kp) {
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
-                       ws.status.as<int>(), ws.iters.as<int>(), K, Kp);
+                       ws.status.as<int>(), ws.iters.as<int>(), K, Kp, ws.sweep_no.as<int>());
     hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta, sw.V,
                        sw.W, sw.c, (T)in.mp.rho, in.pp, Kp * in.pp);
     HIPCHK(hipGetLastError());
@@ -773,7 +777,64 @@ void read_counters(l0l2_ctx *ctx, int out[2]) {
     out[1] = ws.host_counter[1];
 }
 
-// Single-precision-type solve (FP64 mode, or an FP32 run without the ladder).
+enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2 };
+
+// One block: `n` sweeps of the given kind, then the FP64 gap check and the
+// read-back of the two counters into pinned host memory.  Issued eagerly.
+void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active) {
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n);
+    for (int t = 1; t <= n; ++t) {
+        const bool last = t == n;
+        if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), Kp, last, active);
+        else if (kind == SK_BF16) sweep_once_bf16(ctx, sweep32(ctx), Kp, last, active);
+        else sweep_once<float>(ctx, sweep32(ctx), Kp, last, active);
+    }
+    if (kind == SK_F64) {
+        Sweep<double> sw = sweep64(ctx);
+        check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0);
+    } else {
+        Sweep<float> sw = sweep32(ctx);
+        check_once<float>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0);
+    }
+    HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+}
+
+// Run one block and return the counters.  Blocks are captured once into a HIP
+// graph per (kind, padded batch, block length, tolerances) and replayed; with
+// the profiler on they are issued eagerly so each launch can be timed.
+void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
+               int out[2]) {
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    if (!ctx->use_graphs || ctx->prof.on) {
+        issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
+    } else {
+        GraphKey key{kind, Kp, n, tol, switch_tol, ws.gen};
+        auto it = ctx->graphs.find(key);
+        if (it == ctx->graphs.end()) {
+            // settle the tile shapes (the autotuner synchronises) before capturing
+            if (kind == SK_F64) (void)tile_choice<double>(ctx, sweep64(ctx), Kp);
+            else if (kind == SK_F32) (void)tile_choice<float>(ctx, sweep32(ctx), Kp);
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
+            HIPCHK(hipStreamEndCapture(s, &g));
+            hipGraphExec_t ex = nullptr;
+            hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHK(e);
+            it = ctx->graphs.emplace(key, ex).first;
+        }
+        HIPCHK(hipGraphLaunch(it->second, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    out[0] = ws.host_counter[0];
+    out[1] = ws.host_counter[1];
+}
+
+// Single-precision-type solve (FP64 mode).
 template <class T>
 void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts &o) {
     const int64_t Kp = round_up(K, kPadNodes);
@@ -781,15 +842,12 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
     const int m = std::max(1, o.check_every);
     int cnt[2];
     int64_t active = K;
-    for (int t = 1; t <= o.max_iter; ++t) {
-        bool chk = (t % m == 0) || (t == o.max_iter);
-        sweep_once<T>(ctx, sw, Kp, chk, active);
-        if (chk) {
-            check_once<T>(ctx, sw.B, sw.beta, K, Kp, t, o.tol_node, o.tol_node, 0);
-            read_counters(ctx, cnt);
-            active = cnt[0];
-            if (cnt[0] == 0) break;
-        }
+    for (int t = 0; t < o.max_iter;) {
+        const int n = std::min(m, o.max_iter - t);
+        run_block(ctx, sizeof(T) == 8 ? SK_F64 : SK_F32, Kp, n, o.tol_node, o.tol_node, active, cnt);
+        t += n;
+        active = cnt[0];
+        if (cnt[0] == 0) break;
     }
 }
 
@@ -813,15 +871,11 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     bool fp64 = false;
     int cnt[2], best_above = 1 << 30, flat = 0;
     int64_t active = K;
-    for (int t = 1; t <= o.max_iter; ++t) {
-        bool chk = (t % m == 0) || (t == o.max_iter);
-        if (fp64) sweep_once<double>(ctx, s64, Kp, chk, active);
-        else if (bf16) sweep_once_bf16(ctx, s32, Kp, chk, active);
-        else sweep_once<float>(ctx, s32, Kp, chk, active);
-        if (!chk) continue;
-        if (!fp64) check_once<float>(ctx, s32.B, s32.beta, K, Kp, t, o.tol_node, switch_tol, 0);
-        else check_once<double>(ctx, s64.B, s64.beta, K, Kp, t, o.tol_node, switch_tol, 0);
-        read_counters(ctx, cnt);
+    for (int t = 0; t < o.max_iter;) {
+        const int n = std::min(m, o.max_iter - t);
+        const int kind = fp64 ? SK_F64 : (bf16 ? SK_BF16 : SK_F32);
+        run_block(ctx, kind, Kp, n, o.tol_node, switch_tol, active, cnt);
+        t += n;
         active = cnt[0];
         if (cnt[0] == 0) break;
         if (!fp64) {
@@ -875,6 +929,9 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.lb.ensure(8 * Kp);
     ws.primal.ensure(8 * Kp);
     ws.counter.ensure(2 * sizeof(int));
+    ws.sweep_no.ensure(sizeof(int));
+    drop_graphs(ctx);
+    ++ws.gen;
     if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 2 * sizeof(int), hipHostMallocDefault));
     if (in.prec != L0L2_FP64) {
         ws.W64.ensure(8 * Kp * pp);
@@ -960,11 +1017,12 @@ void run_dual_bound(l0l2_ctx *ctx, int K, const void *) {
     const int64_t Kp = round_up(K, kPadNodes);
     Workspace &ws = ctx->ws;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, ctx->stream,
-                       ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), (int64_t)K, Kp);
+                       ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), (int64_t)K, Kp,
+                       ws.sweep_no.as<int>());
     if (ctx->inst.prec == L0L2_FP64)
-        check_once<double>(ctx, ws.B.as<double>(), ws.B.as<double>(), K, Kp, 0, 0.0, 0.0, 1);
+        check_once<double>(ctx, ws.B.as<double>(), ws.B.as<double>(), Kp, 0.0, 0.0, 1);
     else
-        check_once<float>(ctx, ws.B.as<float>(), ws.B.as<float>(), K, Kp, 0, 0.0, 0.0, 1);
+        check_once<float>(ctx, ws.B.as<float>(), ws.B.as<float>(), Kp, 0.0, 0.0, 1);
 }
 
 }  // namespace l0l2

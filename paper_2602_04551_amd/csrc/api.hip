@@ -19,6 +19,11 @@ void hip_check(hipError_t e, const char *what) {
     }
 }
 
+void drop_graphs(l0l2_ctx *ctx) {
+    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+}
+
 void DevBuf::release() {
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
@@ -106,6 +111,7 @@ void l0l2_destroy(l0l2_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    l0l2::drop_graphs(ctx);
     if (ctx->ws.host_counter) (void)hipHostFree(ctx->ws.host_counter);
     l0l2::prof_release(ctx->prof);
     delete ctx;

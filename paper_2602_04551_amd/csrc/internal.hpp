@@ -100,7 +100,9 @@ struct Workspace {
     DevBuf part;                   // Kp x (pp/32) x 3 doubles
     DevBuf active, iters, status;  // Kp int32
     DevBuf lb, primal;             // Kp doubles
-    DevBuf counter;                // int32 number of active nodes
+    DevBuf counter;                // int32 x 2: active nodes, active nodes above the switch tolerance
+    DevBuf sweep_no;               // int32 sweep counter of the batch
+    int64_t gen = 0;               // bumped whenever the buffers above move
     DevBuf fista;                  // FP64 residual scratch for the incumbent kernels
     int *host_counter = nullptr;   // pinned
 };
@@ -120,6 +122,23 @@ struct Profiler {
     int64_t units[kProfCount] = {};   // work units (active node-iterations for the sweeps)
 };
 
+// A captured block of sweeps + gap check.
+struct GraphKey {
+    int kind;
+    int64_t Kp;
+    int n;
+    double tol, switch_tol;
+    int64_t gen;
+    bool operator<(const GraphKey &o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (Kp != o.Kp) return Kp < o.Kp;
+        if (n != o.n) return n < o.n;
+        if (tol != o.tol) return tol < o.tol;
+        if (switch_tol != o.switch_tol) return switch_tol < o.switch_tol;
+        return gen < o.gen;
+    }
+};
+
 }  // namespace l0l2
 
 struct l0l2_ctx {
@@ -129,6 +148,8 @@ struct l0l2_ctx {
     bool has_data = false;
     bool tune = true;          // time the tile shapes of each new batch size
     int force_xw = -1, force_xtu = -1;   // fixed tile shapes (-1: autotune)
+    bool use_graphs = true;              // replay captured blocks of sweeps
+    std::map<l0l2::GraphKey, hipGraphExec_t> graphs;
     l0l2::Instance inst;
     l0l2::Workspace ws;
     l0l2::Profiler prof;
@@ -163,6 +184,8 @@ void state_to_f64(l0l2_ctx *ctx, int K, const void *src, int64_t ld_src, double 
 
 // bnb.cpp
 void bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out);
+
+void drop_graphs(l0l2_ctx *ctx);
 
 // prof.hip
 void prof_begin(l0l2_ctx *ctx, int id);

@@ -266,6 +266,7 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     ctx->has_data = false;
     // the per-batch workspace is sized for the previous instance: drop it
     ctx->ws.cap = 0;
+    drop_graphs(ctx);
     in.tiles.clear();
     in.n = n;
     in.p = p;
