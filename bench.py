@@ -134,11 +134,12 @@ def roofline(prof, n, p):
 
 
 def run_path(path, steps, warmup):
+    """Timed steps with the library in its default mode (blocks of sweeps
+    replayed from HIP graphs), then a separate pass with per-launch HIP-event
+    timing (launches issued one by one) for the kernel durations."""
     torch = path.torch
     for _ in range(warmup):
         path.step()
-    torch.cuda.synchronize()
-    path.ctx.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     its = 0
@@ -147,6 +148,10 @@ def run_path(path, steps, warmup):
         its += i
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    path.ctx.profile_enable(True)
+    for _ in range(max(1, min(steps, 3))):
+        path.step()
+    torch.cuda.synchronize()
     prof = {k: path.ctx.profile_query(k) for k in path.ctx.KERNELS}
     path.ctx.profile_enable(False)
     return dt, its, prof
