@@ -818,13 +818,29 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
             if (kind == SK_F64) (void)tile_choice<double>(ctx, sweep64(ctx), Kp);
             else if (kind == SK_F32) (void)tile_choice<float>(ctx, sweep32(ctx), Kp);
             hipGraph_t g = nullptr;
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
-            HIPCHK(hipStreamEndCapture(s, &g));
             hipGraphExec_t ex = nullptr;
-            hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            HIPCHK(e);
+            if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                bool ok = true;
+                try {
+                    issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
+                } catch (...) {
+                    ok = false;
+                }
+                hipError_t e = hipStreamEndCapture(s, &g);
+                if (ok && e == hipSuccess && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess)
+                    ex = nullptr;
+                if (g) (void)hipGraphDestroy(g);
+            }
+            (void)hipGetLastError();
+            if (!ex) {
+                // capture is not available here: issue blocks launch by launch from now on
+                ctx->use_graphs = false;
+                issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
+                HIPCHK(hipStreamSynchronize(s));
+                out[0] = ws.host_counter[0];
+                out[1] = ws.host_counter[1];
+                return;
+            }
             it = ctx->graphs.emplace(key, ex).first;
         }
         HIPCHK(hipGraphLaunch(it->second, s));

@@ -54,18 +54,30 @@ thread_local std::string g_create_err;
 template <class F>
 int guarded(l0l2_ctx *ctx, F &&f) {
     if (!ctx) return L0L2_E_INVALID;
+    // work of the call runs on the context's stream after everything already
+    // queued on the caller's stream, and the caller's stream waits for it
+    auto order_out = [&] {
+        if (hipEventRecord(ctx->ev_out, ctx->stream) == hipSuccess)
+            (void)hipStreamWaitEvent(ctx->user_stream, ctx->ev_out, 0);
+    };
     try {
         if (hipSetDevice(ctx->device) != hipSuccess) l0l2::fail(L0L2_E_DEVICE, "hipSetDevice failed");
+        HIPCHK(hipEventRecord(ctx->ev_in, ctx->user_stream));
+        HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_in, 0));
         f();
+        order_out();
         ctx->err.clear();
         return L0L2_OK;
     } catch (const Error &e) {
+        order_out();
         ctx->err = e.msg;
         return e.code;
     } catch (const std::bad_alloc &) {
+        order_out();
         ctx->err = "host allocation failed";
         return L0L2_E_OOM;
     } catch (...) {
+        order_out();
         ctx->err = "unexpected internal error";
         return L0L2_E_DEVICE;
     }
@@ -102,7 +114,16 @@ int l0l2_create(int device, void *hip_stream, l0l2_ctx **out) {
     l0l2_ctx *c = new (std::nothrow) l0l2_ctx();
     if (!c) return L0L2_E_OOM;
     c->device = device;
-    c->stream = (hipStream_t)hip_stream;
+    c->user_stream = (hipStream_t)hip_stream;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+        g_create_err = "stream or event creation failed";
+        if (c->stream) (void)hipStreamDestroy(c->stream);
+        if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+        delete c;
+        return L0L2_E_DEVICE;
+    }
     *out = c;
     return L0L2_OK;
 }
@@ -114,6 +135,10 @@ void l0l2_destroy(l0l2_ctx *ctx) {
     l0l2::drop_graphs(ctx);
     if (ctx->ws.host_counter) (void)hipHostFree(ctx->ws.host_counter);
     l0l2::prof_release(ctx->prof);
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipStreamDestroy(ctx->stream);
+    (void)hipEventDestroy(ctx->ev_in);
+    (void)hipEventDestroy(ctx->ev_out);
     delete ctx;
 }
 

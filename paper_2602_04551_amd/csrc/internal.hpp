@@ -143,7 +143,9 @@ struct GraphKey {
 
 struct l0l2_ctx {
     int device = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // the context's own stream (non-blocking, default priority)
+    hipStream_t user_stream = nullptr;  // the caller's stream, ordered with `stream` by events
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::string err;
     bool has_data = false;
     bool tune = true;          // time the tile shapes of each new batch size
