@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--only-mixed", action="store_true", help="skip the FP64 path (short profiled runs)")
+    ap.add_argument("--batching", action="store_true",
+                    help="n = p = 5000 node batches of 512..4096 (free sets U[50, p]), BF16 split vs FP32")
+    ap.add_argument("--serve", action="store_true",
+                    help="Poisson stream of independent instances through the server: p50/p99 TTCO")
+    ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="first dispatch one device copy of 256 MiB, the reference for HBM counter scaling")
     return ap.parse_args()
@@ -157,8 +162,97 @@ def run_path(path, steps, warmup):
     return dt, its, prof
 
 
+def batching_main(args):
+    """Node-batch throughput at n = p = 5000 for K in {512, 1024, 2048, 4096}: each node keeps
+    f ~ U{50..p} free coordinates, |F1| ~ U{0..20}, the rest fixed to zero, warm-started from
+    the root.  BF16 split sweeps (then FP64) against FP32 sweeps (then FP64)."""
+    import torch
+    from paper_2602_04551_amd import datagen
+    from paper_2602_04551_amd.binding import Context
+    inst = datagen.config_instance("C3", seed=0)
+    n, p = inst.n, inst.p
+    out = {"metric": "node relaxations/s (batching workload)", "unit": "node relaxations/s",
+           "config": {"workload": "n=p=5000 Toeplitz rho=0.3 k=20 SNR=3 lambda0=0.005 lambda2=0.01, node "
+                                  "batches with free sets U{50..p}, |F1| U{0..20}", "node_tol": 1e-6}, "runs": {}}
+    for prec in ("bf16", "fp32"):
+        ctx = Context(0)
+        t0 = time.perf_counter()
+        ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
+        torch.cuda.synchronize()
+        sd = time.perf_counter() - t0
+        root = ctx.solve_node_batch(np.zeros((1, p), np.uint8), tol_node=1e-6, max_iter=10000)
+        for K in (512, 1024, 2048, 4096):
+            codes = torch.from_numpy(datagen.node_batch_codes(p, K, seed=K)).to(ctx.torch_device)
+            b0 = root["beta"].expand(K, p).contiguous()
+            v0 = root["v"].expand(K, p).contiguous()
+            ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)     # warm-up, tiles, graphs
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ctx.profile_enable(True)
+            ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
+            prof = {k: ctx.profile_query(k) for k in ctx.KERNELS}
+            ctx.profile_enable(False)
+            roof, kernels = roofline(prof, n, p)
+            it = r["iters"].cpu().numpy()
+            out["runs"][f"{prec}_K{K}"] = {"value": round(K / dt, 2), "seconds": round(dt, 4),
+                                           "iters_mean": float(it.mean()), "iters_max": int(it.max()),
+                                           "converged": int((r["status"] == 0).sum().item()),
+                                           "roofline": roof, "kernels": kernels, "set_data_s": round(sd, 3)}
+            print(json.dumps({f"{prec}_K{K}": out["runs"][f"{prec}_K{K}"]["value"]}), file=sys.stderr, flush=True)
+        ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def serve_main(args):
+    """A Poisson stream of independent instances (n ~ U{500..2000}, p ~ U{1000..4000}, Toeplitz
+    rho ~ U[0, 0.7], k ~ U{5..12}, SNR ~ U[2, 10], lambda0 = 0.005, lambda2 = 0.01) through the
+    server (continuous admission under an HBM budget); per-request time to certified optimum
+    (submit to done) and admission wait, p50 / p99, beside the throughput."""
+    from paper_2602_04551_amd import datagen
+    from paper_2602_04551_amd.binding import Server
+    rng = np.random.default_rng(0)
+    reqs = []
+    for i in range(args.serve_requests):
+        n = int(rng.integers(500, 2001))
+        p = int(rng.integers(1000, 4001))
+        reqs.append(datagen.make_instance(n, p, corr="toeplitz", rho=float(rng.uniform(0, 0.7)),
+                                          k=int(rng.integers(5, 13)), snr=float(rng.uniform(2, 10)),
+                                          lambda0=0.005, lambda2=0.01, seed=1000 + i))
+    gaps = rng.exponential(0.05, size=len(reqs))
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=4, K=64, tol_node=1e-6, max_iter=2000,
+                 max_iter_root=10000, time_limit_s=30.0)
+    t0 = time.perf_counter()
+    ids = []
+    for inst, g in zip(reqs, gaps):
+        time.sleep(float(g))
+        ids.append(srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp32"))
+    res = [srv.wait(r) for r in ids]
+    wall = time.perf_counter() - t0
+    srv.close()
+    tt = np.array([r["done_s"] - r["submit_s"] for r in res])
+    wait = np.array([r["admit_s"] - r["submit_s"] for r in res])
+    nodes = sum(r["nodes_solved"] for r in res)
+    out = {"metric": "time-to-certified-optimum under serving", "unit": "s",
+           "requests": len(res), "certified": int(sum(r["status"] == 0 for r in res)),
+           "ttco_p50": round(float(np.percentile(tt, 50)), 4), "ttco_p99": round(float(np.percentile(tt, 99)), 4),
+           "admit_wait_p50": round(float(np.percentile(wait, 50)), 4),
+           "throughput_requests_per_s": round(len(res) / wall, 3), "node_relaxations_per_s": round(nodes / wall, 1),
+           "wall_s": round(wall, 3), "mean_interarrival_s": 0.05, "max_concurrent": 4,
+           "per_request": [{"n": i.n, "p": i.p, "ttco": round(float(t), 4), "nodes": r["nodes_solved"],
+                            "status": r["status"]} for i, t, r in zip(reqs, tt, res)]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.batching or args.serve:
+        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+            print("bench.py: this build runs on exactly one GPU", file=sys.stderr)
+            sys.exit(2)
+        return batching_main(args) if args.batching else serve_main(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)

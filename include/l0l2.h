@@ -219,8 +219,9 @@ const char *l0l2_server_last_error(const l0l2_server *srv);
 /* Stop admitting, drop queued requests, wait for running ones, free all. */
 int l0l2_server_destroy(l0l2_server *srv);
 
-/* Tile shapes of the two sweep contractions (each a 32x32, 16x32, 32x16 or 16x16
- * output tile per workgroup: 0, 1, 2, 3).  By default (both -1) each new batch
+/* Tile shapes of the two sweep contractions: 0..5 = 32x32 output tile with 4, 8
+ * or 16 waves splitting the contraction (16 falls back to 8 in FP64), 16x32 and
+ * 32x16 with 8 waves, 16x16 with 4 waves.  By default (both -1) each new batch
  * size is timed once with every shape on the live batch and the fastest kept
  * per instance; fixed shapes serve tests and tuning studies.  Results do not
  * depend on the shape beyond rounding of the summation order. */

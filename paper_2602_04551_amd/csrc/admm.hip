@@ -137,7 +137,7 @@ __device__ __forceinline__ void mma_chunk(typename Acc<TC>::type (&acc)[BM][BN],
             for (int j = 0; j < BN; ++j) acc[i][j] = mfma16((TC)a[i][t], (TC)b[j][t], acc[i][j]);
 }
 
-template <class TA, class TB, class TC, int BM, int BN>
+template <class TA, class TB, class TC, int BM, int BN, int WAVES>
 __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B, int64_t ldb,
                                         int64_t kdim, int64_t m0, int64_t n0, TC *red) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
@@ -147,25 +147,31 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     AccT acc[BM][BN];
     for (int i = 0; i < BM; ++i)
         for (int j = 0; j < BN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
-    const int64_t kq = kdim / 4, kb = w * kq, ke = kb + kq;
+    // chunks of 16 k split evenly over the waves (a wave may get none)
+    const int64_t nch = kdim / 16;
+    const int64_t c0 = nch * w / WAVES, c1 = nch * (w + 1) / WAVES;
     const TA *Ap[BM];
     const TB *Bp[BN];
     for (int i = 0; i < BM; ++i) Ap[i] = A + (m0 + 16 * i + r) * lda + 4 * q;
     for (int j = 0; j < BN; ++j) Bp[j] = B + (n0 + 16 * j + r) * ldb + 4 * q;
     TA a0[BM][4], a1[BM][4];
     TB b0[BN][4], b1[BN][4];
-    for (int i = 0; i < BM; ++i) load4(Ap[i] + kb, a0[i]);
-    for (int j = 0; j < BN; ++j) load4(Bp[j] + kb, b0[j]);
-    for (int64_t k0 = kb; k0 < ke; k0 += 32) {
-        for (int i = 0; i < BM; ++i) load4(Ap[i] + k0 + 16, a1[i]);
-        for (int j = 0; j < BN; ++j) load4(Bp[j] + k0 + 16, b1[j]);
+    int64_t c = c0;
+    if (c < c1) {
+        for (int i = 0; i < BM; ++i) load4(Ap[i] + 16 * c, a0[i]);
+        for (int j = 0; j < BN; ++j) load4(Bp[j] + 16 * c, b0[j]);
+    }
+    for (; c + 1 < c1; c += 2) {
+        for (int i = 0; i < BM; ++i) load4(Ap[i] + 16 * (c + 1), a1[i]);
+        for (int j = 0; j < BN; ++j) load4(Bp[j] + 16 * (c + 1), b1[j]);
         mma_chunk<TC, BM, BN>(acc, a0, b0);
-        if (k0 + 32 < ke) {
-            for (int i = 0; i < BM; ++i) load4(Ap[i] + k0 + 32, a0[i]);
-            for (int j = 0; j < BN; ++j) load4(Bp[j] + k0 + 32, b0[j]);
+        if (c + 2 < c1) {
+            for (int i = 0; i < BM; ++i) load4(Ap[i] + 16 * (c + 2), a0[i]);
+            for (int j = 0; j < BN; ++j) load4(Bp[j] + 16 * (c + 2), b0[j]);
         }
         mma_chunk<TC, BM, BN>(acc, a1, b1);
     }
+    if (c < c1) mma_chunk<TC, BM, BN>(acc, a0, b0);
     for (int i = 0; i < BM; ++i)
         for (int j = 0; j < BN; ++j)
             for (int v = 0; v < 4; ++v) {
@@ -176,22 +182,25 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     __syncthreads();
 }
 
-template <class TC, int TMTN>
+template <class TC, int TMTN, int WAVES>
 __device__ __forceinline__ TC sum_waves(const TC *red, int idx) {
-    return red[idx] + red[TMTN + idx] + red[2 * TMTN + idx] + red[3 * TMTN + idx];
+    TC s = red[idx];
+    for (int w = 1; w < WAVES; ++w) s += red[w * TMTN + idx];
+    return s;
 }
 
 // Contraction over p: U[k][i] = sum_j Xh[i][j] W[k][j] (A = row-major Xh).
-template <class TA, class TB, class TC, int BM, int BN>
-__global__ __launch_bounds__(256) void k_gemm_xw(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B,
-                                                 int64_t ldb, TC *__restrict__ U, int64_t ldu, int64_t kdim) {
+template <class TA, class TB, class TC, int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A, int64_t lda,
+                                                        const TB *__restrict__ B, int64_t ldb, TC *__restrict__ U,
+                                                        int64_t ldu, int64_t kdim) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
-    __shared__ TC red[4 * TM * TN];
+    __shared__ TC red[WAVES * TM * TN];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    nt_tile<TA, TB, TC, BM, BN>(A, lda, B, ldb, kdim, m0, n0, red);
-    for (int idx = threadIdx.x; idx < TM * TN; idx += 256) {
+    nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, red);
+    for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
         int n = idx / TM, m = idx % TM;
-        U[(n0 + n) * ldu + m0 + m] = sum_waves<TC, TM * TN>(red, idx);
+        U[(n0 + n) * ldu + m0 + m] = sum_waves<TC, TM * TN, WAVES>(red, idx);
     }
 }
 
@@ -199,22 +208,22 @@ __global__ __launch_bounds__(256) void k_gemm_xw(const TA *__restrict__ A, int64
 //   Q[k][j] = sum_i Xh[i][j] U[k][i], then for node k and coordinate j:
 //   b = (W - Q) / rho, beta = prox(b + V / rho), V += rho (b - beta),
 //   W = c + rho beta - V.
-template <class TA, class T, int BM, int BN>
-__global__ __launch_bounds__(256) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
+template <class TA, class T, int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
                                                   int64_t ldu, int64_t kdim, T *__restrict__ W,
                                                   T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
                                                   const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                                   const int *__restrict__ active, DevParams<T> q, int64_t ldp,
                                                   int store_b) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
-    __shared__ T red[4 * TM * TN];
+    __shared__ T red[WAVES * TM * TN];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    nt_tile<TA, T, T, BM, BN>(A, lda, U, ldu, kdim, m0, n0, red);
-    for (int idx = threadIdx.x; idx < TM * TN; idx += 256) {
+    nt_tile<TA, T, T, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, red);
+    for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
         int n = idx / TM, m = idx % TM;
         int64_t node = n0 + n, j = m0 + m;
         if (!active[node]) continue;
-        T Qv = sum_waves<T, TM * TN>(red, idx);
+        T Qv = sum_waves<T, TM * TN, WAVES>(red, idx);
         int64_t o = node * ldp + j;
         T wv = W[o];
         T bb = (wv - Qv) / q.rho;
@@ -252,91 +261,89 @@ __device__ __forceinline__ void load8f(const float *p, float out[8]) {
     out[4] = b.x; out[5] = b.y; out[6] = b.z; out[7] = b.w;
 }
 
-// U[k][i] = sum_j Xh[i][j] W[k][j] with Xh row-major (row i at A + i*lda).
-__global__ __launch_bounds__(256) void k_gemm_xw_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
-                                                      int64_t lda, const float *__restrict__ B, int64_t ldb,
-                                                      float *__restrict__ U, int64_t ldu, int64_t kdim) {
-    __shared__ float red[4 * 1024];
+// 32 x 32 tile of C[m][n] = sum_k (Ahi + Alo)[m][k] B[n][k] with A rows in BF16
+// (hi, lo) and B rows in FP32 (split into hi, lo on load), k chunks of 32 split
+// over WAVES waves, next chunk's loads issued before the current chunk's MFMAs.
+template <int WAVES>
+__device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+                                             int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
+                                             int64_t m0, int64_t n0, float *red) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
-    const int64_t kq = kdim / 4;
-    const int64_t kb = w * kq, ke = kb + kq;
-    for (int64_t j0 = kb; j0 < ke; j0 += 32) {
-        bf16x8 ah[2], al[2], bh[2], bl[2];
+    const int64_t nch = kdim / 32;
+    const int64_t c0 = nch * w / WAVES, c1 = nch * (w + 1) / WAVES;
+    bf16x8 ah[2][2], al[2][2];
+    float bv[2][2][8];
+    auto load = [&](int st, int64_t c) {
         for (int a = 0; a < 2; ++a) {
-            const int64_t o = (m0 + 16 * a + r) * lda + j0 + 8 * q;
-            ah[a] = *reinterpret_cast<const bf16x8 *>(Ahi + o);
-            al[a] = *reinterpret_cast<const bf16x8 *>(Alo + o);
+            const int64_t o = (m0 + 16 * a + r) * lda + 32 * c + 8 * q;
+            ah[st][a] = *reinterpret_cast<const bf16x8 *>(Ahi + o);
+            al[st][a] = *reinterpret_cast<const bf16x8 *>(Alo + o);
         }
-        for (int b = 0; b < 2; ++b) {
-            float wv[8];
-            load8f(B + (n0 + 16 * b + r) * ldb + j0 + 8 * q, wv);
-            split8(wv, bh[b], bl[b]);
-        }
+        for (int b = 0; b < 2; ++b) load8f(B + (n0 + 16 * b + r) * ldb + 32 * c + 8 * q, bv[st][b]);
+    };
+    auto compute = [&](int st) {
+        bf16x8 bh[2], bl[2];
+        for (int b = 0; b < 2; ++b) split8(bv[st][b], bh[b], bl[b]);
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) {
-                acc[a][b] = mfma16_bf16(ah[a], bh[b], acc[a][b]);
-                acc[a][b] = mfma16_bf16(ah[a], bl[b], acc[a][b]);
-                acc[a][b] = mfma16_bf16(al[a], bh[b], acc[a][b]);
+                acc[a][b] = mfma16_bf16(ah[st][a], bh[b], acc[a][b]);
+                acc[a][b] = mfma16_bf16(ah[st][a], bl[b], acc[a][b]);
+                acc[a][b] = mfma16_bf16(al[st][a], bh[b], acc[a][b]);
             }
+    };
+    int64_t c = c0;
+    if (c < c1) load(0, c);
+    for (; c + 1 < c1; c += 2) {
+        load(1, c + 1);
+        compute(0);
+        if (c + 2 < c1) load(0, c + 2);
+        compute(1);
     }
-    tile_to_lds<float>(acc, red, w, lane);
+    if (c < c1) compute(0);
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int v = 0; v < 4; ++v) {
+                int m = a * 16 + acc_row<float>(lane, v);
+                int n = b * 16 + r;
+                red[w * 1024 + n * 32 + m] = acc[a][b][v];
+            }
     __syncthreads();
-    for (int e = 0; e < 4; ++e) {
-        int idx = tid + 256 * e;
+}
+
+constexpr int kWavesBf16 = 8;
+
+// U[k][i] = sum_j Xh[i][j] W[k][j] with Xh row-major (row i at A + i*lda).
+__global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *__restrict__ Ahi,
+                                                                  const __bf16 *__restrict__ Alo, int64_t lda,
+                                                                  const float *__restrict__ B, int64_t ldb,
+                                                                  float *__restrict__ U, int64_t ldu, int64_t kdim) {
+    __shared__ float red[kWavesBf16 * 1024];
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, red);
+    for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
         int n = idx >> 5, m = idx & 31;
-        U[(n0 + n) * ldu + m0 + m] = tile_sum<float>(red, idx);
+        U[(n0 + n) * ldu + m0 + m] = sum_waves<float, 1024, kWavesBf16>(red, idx);
     }
 }
 
 // Q[k][j] = sum_i Xh[i][j] U[k][i] (Xh column-major) with the ADMM epilogue.
-__global__ __launch_bounds__(256) void k_admm_xtu_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
-                                                       int64_t lda, const float *__restrict__ U, int64_t ldu,
-                                                       int64_t kdim, float *__restrict__ W, float *__restrict__ beta,
-                                                       float *__restrict__ V, float *__restrict__ Bst,
-                                                       const uint8_t *__restrict__ codes, const float *__restrict__ c,
-                                                       const int *__restrict__ active, DevParams<float> q,
-                                                       int64_t ldp, int store_b) {
-    __shared__ float red[4 * 1024];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int qq = lane >> 4, r = lane & 15;
+__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
+    const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
+    int64_t ldu, int64_t kdim, float *__restrict__ W, float *__restrict__ beta, float *__restrict__ V,
+    float *__restrict__ Bst, const uint8_t *__restrict__ codes, const float *__restrict__ c,
+    const int *__restrict__ active, DevParams<float> q, int64_t ldp, int store_b) {
+    __shared__ float red[kWavesBf16 * 1024];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    f32x4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
-    const int64_t kq = kdim / 4;
-    const int64_t ib = w * kq, ie = ib + kq;
-    for (int64_t i0 = ib; i0 < ie; i0 += 32) {
-        bf16x8 ah[2], al[2], uh[2], ul[2];
-        for (int a = 0; a < 2; ++a) {
-            const int64_t o = (m0 + 16 * a + r) * lda + i0 + 8 * qq;
-            ah[a] = *reinterpret_cast<const bf16x8 *>(Ahi + o);
-            al[a] = *reinterpret_cast<const bf16x8 *>(Alo + o);
-        }
-        for (int b = 0; b < 2; ++b) {
-            float uv[8];
-            load8f(U + (n0 + 16 * b + r) * ldu + i0 + 8 * qq, uv);
-            split8(uv, uh[b], ul[b]);
-        }
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                acc[a][b] = mfma16_bf16(ah[a], uh[b], acc[a][b]);
-                acc[a][b] = mfma16_bf16(ah[a], ul[b], acc[a][b]);
-                acc[a][b] = mfma16_bf16(al[a], uh[b], acc[a][b]);
-            }
-    }
-    tile_to_lds<float>(acc, red, w, lane);
-    __syncthreads();
-    for (int e = 0; e < 4; ++e) {
-        int idx = tid + 256 * e;
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, red);
+    for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
         int n = idx >> 5, m = idx & 31;
         int64_t node = n0 + n, j = m0 + m;
         if (!active[node]) continue;
-        float Qv = tile_sum<float>(red, idx);
+        float Qv = sum_waves<float, 1024, kWavesBf16>(red, idx);
         int64_t o = node * ldp + j;
         float wv = W[o];
         float bb = (wv - Qv) / q.rho;
@@ -417,7 +424,7 @@ __global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, 
     __shared__ double red[4 * 1024];
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    nt_tile<double, double, double, 2, 2>(A, lda, R, ldr, kdim, m0, n0, red);
+    nt_tile<double, double, double, 2, 2, 4>(A, lda, R, ldr, kdim, m0, n0, red);
     // thread t: node n = t / 8, coordinates 4 (t % 8) .. +3 of the tile
     const int n = tid >> 3, jl = (tid & 7) * 4;
     const int64_t node = n0 + n;
@@ -580,34 +587,49 @@ template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
 // ---------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------
-// Tile shapes (BM, BN) of the sweep contractions, in 16-row blocks.
-constexpr int kTileBM[4] = {2, 1, 2, 1};
-constexpr int kTileBN[4] = {2, 2, 1, 1};
+// Tile shapes of the sweep contractions: (BM, BN) 16-row blocks per output tile
+// and the number of waves splitting the contraction range.  FP64 keeps at most
+// 8 waves on the 32 x 32 tile (LDS for the cross-wave reduction).
+constexpr int kShapes = 6;
+constexpr int kTileBM[kShapes] = {2, 2, 2, 1, 2, 1};
+constexpr int kTileBN[kShapes] = {2, 2, 2, 2, 1, 1};
+constexpr int kTileW[kShapes] = {4, 8, 16, 8, 8, 4};
 
 template <class TA, class TB, class TC>
 void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int64_t ldb, TC *U, int64_t ldu,
                int64_t rows, int64_t Kp, int64_t kdim) {
+    if (sizeof(TC) == 8 && v == 2) v = 1;
     dim3 g((unsigned)(rows / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
+    dim3 b((unsigned)(64 * kTileW[v]));
+#define L0L2_XW(PBM, PBN, PW) \
+    hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, PBM, PBN, PW>), g, b, 0, s, A, lda, B, ldb, U, ldu, kdim)
     switch (v) {
-        case 0: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 2, 2>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
-        case 1: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 1, 2>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
-        case 2: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 2, 1>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
-        default: hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 1, 1>), g, dim3(256), 0, s, A, lda, B, ldb, U, ldu, kdim); break;
+        case 0: L0L2_XW(2, 2, 4); break;
+        case 1: L0L2_XW(2, 2, 8); break;
+        case 2: L0L2_XW(2, 2, (sizeof(TC) == 8 ? 8 : 16)); break;
+        case 3: L0L2_XW(1, 2, 8); break;
+        case 4: L0L2_XW(2, 1, 8); break;
+        default: L0L2_XW(1, 1, 4); break;
     }
+#undef L0L2_XW
 }
 
 template <class T>
 void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes,
                 const int *active, const DevParams<T> &q, int store_b) {
+    if (sizeof(T) == 8 && v == 2) v = 1;
     dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
-#define L0L2_XTU(BM, BN)                                                                                           \
-    hipLaunchKernelGGL((k_admm_xtu<T, T, BM, BN>), g, dim3(256), 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, \
+    dim3 b((unsigned)(64 * kTileW[v]));
+#define L0L2_XTU(PBM, PBN, PW)                                                                                  \
+    hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, \
                        sw.B, codes, sw.c, active, q, pp, store_b)
     switch (v) {
-        case 0: L0L2_XTU(2, 2); break;
-        case 1: L0L2_XTU(1, 2); break;
-        case 2: L0L2_XTU(2, 1); break;
-        default: L0L2_XTU(1, 1); break;
+        case 0: L0L2_XTU(2, 2, 4); break;
+        case 1: L0L2_XTU(2, 2, 8); break;
+        case 2: L0L2_XTU(2, 2, (sizeof(T) == 8 ? 8 : 16)); break;
+        case 3: L0L2_XTU(1, 2, 8); break;
+        case 4: L0L2_XTU(2, 1, 8); break;
+        default: L0L2_XTU(1, 1, 4); break;
     }
 #undef L0L2_XTU
 }
@@ -641,7 +663,7 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         float best_xw = 1e30f, best_xtu = 1e30f;
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < kShapes; ++v) {
             for (int rep = 0; rep < 2; ++rep) {
                 float ms[2];
                 for (int which = 0; which < 2; ++which) {
@@ -697,11 +719,11 @@ void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool sto
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     DevParams<float> q = dev_params<float>(in.mp);
     prof_begin(ctx, PROF_GEMM_XW_BF16);
-    hipLaunchKernelGGL(k_gemm_xw_bf16, g1, dim3(256), 0, s, in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), pp, sw.W, pp,
+    hipLaunchKernelGGL(k_gemm_xw_bf16, g1, dim3(64 * kWavesBf16), 0, s, in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), pp, sw.W, pp,
                        sw.U, np, pp);
     prof_end(ctx, PROF_GEMM_XW_BF16, active);
     prof_begin(ctx, PROF_ADMM_XTU_BF16);
-    hipLaunchKernelGGL(k_admm_xtu_bf16, g2, dim3(256), 0, s, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(), np, sw.U, np,
+    hipLaunchKernelGGL(k_admm_xtu_bf16, g2, dim3(64 * kWavesBf16), 0, s, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(), np, sw.U, np,
                        np, sw.W, sw.beta, sw.V, sw.B, ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp,
                        store_b ? 1 : 0);
     prof_end(ctx, PROF_ADMM_XTU_BF16, active);

@@ -83,13 +83,13 @@ def test_sweeps_fp64_match_oracle(torch_cuda, cases, name):
             assert rel(gbb[k], bb) < 1e-11, (S, k)
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3])
+@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
 def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
     inst, o, root = cases["ragged"]
     K = 48
     codes, beta0, v0 = random_nodes(inst.p, K, 11, root["beta"], root["v"])
     ctx = ctx_for(inst, "fp64")
-    ctx.set_tiles(shape, 3 - shape)
+    ctx.set_tiles(shape, 5 - shape)
     gb, gv, gbb = ctx.admm_sweeps(codes, beta0, v0, 7)
     gb, gbb = gb.cpu().numpy(), gbb.cpu().numpy()
     for k in range(K):
