@@ -219,12 +219,15 @@ const char *l0l2_server_last_error(const l0l2_server *srv);
 /* Stop admitting, drop queued requests, wait for running ones, free all. */
 int l0l2_server_destroy(l0l2_server *srv);
 
-/* Tile shapes of the two sweep contractions: 0..5 = 32x32 output tile with 4, 8
- * or 16 waves splitting the contraction (16 falls back to 8 in FP64), 16x32 and
- * 32x16 with 8 waves, 16x16 with 4 waves.  By default (both -1) each new batch
- * size is timed once with every shape on the live batch and the fastest kept
- * per instance; fixed shapes serve tests and tuning studies.  Results do not
- * depend on the shape beyond rounding of the summation order. */
+/* Tile shapes of the two sweep contractions (output rows x nodes, waves that
+ * split the contraction): 0 = 32x32/4, 1 = 32x32/8, 2 = 32x32/16 (8 in FP64),
+ * 3 = 16x32/8, 4 = 32x16/8, 5 = 16x16/4, 6 = 64x32/8, 7 = 32x64/8, 8 = 64x32/4.
+ * By default (both -1) each new padded batch size is timed once with every
+ * shape whose node tile divides it, on the live batch, and the fastest kept per
+ * instance; fixed shapes serve tests and tuning studies (a fixed shape whose
+ * node tile does not divide the padded batch makes the solve calls fail with
+ * L0L2_E_INVALID).  Results do not depend on the shape beyond rounding of the
+ * summation order. */
 int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
 
 /* Opt-in timing of the library's kernels with HIP events recorded on the

@@ -79,8 +79,13 @@ __global__ void k_set_active(int *active, int *status, int *iters, int64_t K, in
     if (k == 0) *sweep_no = 0;
 }
 
-// Sweep counter of the batch, advanced at the start of each block of sweeps.
-__global__ void k_sweep_add(int *sweep_no, int n) { *sweep_no += n; }
+// Sweep counter of the batch, advanced at the start of each block of sweeps;
+// the gate counters of the block start at zero.
+__global__ void k_sweep_add(int *sweep_no, int n, int *gate) {
+    *sweep_no += n;
+    gate[0] = 0;
+    gate[1] = 0;
+}
 
 // Warm start of Sec. 3.1.3: impose F0 on beta, then W = c + rho beta - V.
 template <class T>
@@ -96,24 +101,21 @@ __global__ void k_init(const uint8_t *__restrict__ codes, T *__restrict__ beta, 
 }
 
 // ---------------------------------------------------------------------------
-// Cross-wave reduction of a 32 x 32 tile held as 2 x 2 MFMA blocks per wave
-// (used by the BF16 kernels).  red: 4 * 1024 elements of LDS; element (m, n) of
-// wave w at red[w*1024 + n*32 + m].
+// Cross-wave partial sums of a TM x TN output tile in LDS: wave w's element
+// (m, n) sits at red[w * WS + n * LD + m] with LD = TM + 1 (the pad element
+// spreads the 16 lanes that hold one row of an MFMA block over different banks).
 // ---------------------------------------------------------------------------
-template <class TC>
-__device__ __forceinline__ void tile_to_lds(const typename Acc<TC>::type acc[2][2], TC *red, int w, int lane) {
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-            for (int v = 0; v < 4; ++v) {
-                int m = a * 16 + acc_row<TC>(lane, v);
-                int n = b * 16 + (lane & 15);
-                red[w * 1024 + n * 32 + m] = acc[a][b][v];
-            }
-}
+template <int TM, int TN>
+struct Red {
+    static constexpr int LD = TM + 1, WS = TN * LD;
+};
 
-template <class TC>
-__device__ __forceinline__ TC tile_sum(const TC *red, int idx) {
-    return red[idx] + red[1024 + idx] + red[2048 + idx] + red[3072 + idx];
+template <class TC, int TM, int TN, int WAVES>
+__device__ __forceinline__ TC sum_waves(const TC *red, int n, int m) {
+    const int o = n * Red<TM, TN>::LD + m;
+    TC s = red[o];
+    for (int w = 1; w < WAVES; ++w) s += red[w * Red<TM, TN>::WS + o];
+    return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -121,13 +123,14 @@ __device__ __forceinline__ TC tile_sum(const TC *red, int idx) {
 // with A rows (lda) and B rows (ldb) contiguous in k.  Both contractions of a
 // sweep have this shape: over p with A = the row-major copy of Xh and B = the
 // node operand W; over n with A = Xh column-major (a column of Xh is a row of
-// Xh^T) and B = U.  The 4 waves of the workgroup split the k range; lane l
-// loads 4 consecutive k of row l%16 with one vector load per fragment and the
-// 4 MFMAs of a 16-wide chunk map their k slot to those 4 values for both
-// operands.  Two register stages: the next chunk's loads are issued before the
-// current chunk's MFMAs.  On return red[w*TM*TN + n*TM + m] holds wave w's
-// partial sums and the workgroup is synchronised.  kdim / 4 must be a multiple
-// of 32.
+// Xh^T) and B = U.  The WAVES waves of the workgroup split the chunks of 16 k
+// (wave w takes chunks [nch w / WAVES, nch (w + 1) / WAVES)); lane l loads 4
+// consecutive k of row l%16 with one vector load per fragment and the 4 MFMAs
+// of a chunk map their k slot to those 4 values for both operands.  Two
+// register stages: the next chunk's loads are issued before the current
+// chunk's MFMAs (deeper rings measured slower on these shapes).  On return red
+// holds every wave's partial sums (layout Red<TM, TN>) and the workgroup is
+// synchronised.  kdim must be a multiple of 16.
 // ---------------------------------------------------------------------------
 template <class TC, int BM, int BN, class TA, class TB>
 __device__ __forceinline__ void mma_chunk(typename Acc<TC>::type (&acc)[BM][BN], const TA (&a)[BM][4],
@@ -147,7 +150,6 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     AccT acc[BM][BN];
     for (int i = 0; i < BM; ++i)
         for (int j = 0; j < BN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
-    // chunks of 16 k split evenly over the waves (a wave may get none)
     const int64_t nch = kdim / 16;
     const int64_t c0 = nch * w / WAVES, c1 = nch * (w + 1) / WAVES;
     const TA *Ap[BM];
@@ -177,16 +179,9 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
             for (int v = 0; v < 4; ++v) {
                 int m = 16 * i + acc_row<TC>(lane, v);
                 int n = 16 * j + r;
-                red[w * TM * TN + n * TM + m] = acc[i][j][v];
+                red[w * Red<TM, TN>::WS + n * Red<TM, TN>::LD + m] = acc[i][j][v];
             }
     __syncthreads();
-}
-
-template <class TC, int TMTN, int WAVES>
-__device__ __forceinline__ TC sum_waves(const TC *red, int idx) {
-    TC s = red[idx];
-    for (int w = 1; w < WAVES; ++w) s += red[w * TMTN + idx];
-    return s;
 }
 
 // Contraction over p: U[k][i] = sum_j Xh[i][j] W[k][j] (A = row-major Xh).
@@ -195,46 +190,94 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A
                                                         const TB *__restrict__ B, int64_t ldb, TC *__restrict__ U,
                                                         int64_t ldu, int64_t kdim) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
-    __shared__ TC red[WAVES * TM * TN];
+    __shared__ TC red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
     nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, red);
     for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
         int n = idx / TM, m = idx % TM;
-        U[(n0 + n) * ldu + m0 + m] = sum_waves<TC, TM * TN, WAVES>(red, idx);
+        U[(n0 + n) * ldu + m0 + m] = sum_waves<TC, TM, TN, WAVES>(red, n, m);
     }
 }
 
-// Contraction over n with the ADMM epilogue:
-//   Q[k][j] = sum_i Xh[i][j] U[k][i], then for node k and coordinate j:
+// Scalars of the gap estimate (FP64).
+struct GateArgs {
+    double l0, l2, M, s, two_M_l2, four_l2, l2_M2, psi_lin;
+    int free_quad;
+};
+
+// The ADMM update of one (node, coordinate) from Q = (Xh^T Xh w)_j:
 //   b = (W - Q) / rho, beta = prox(b + V / rho), V += rho (b - beta),
 //   W = c + rho beta - V.
+// With est set it also returns the five terms of the gap estimate.  Since b
+// solves (X^T X + rho I) b = w, the residual r = y - X b satisfies
+// X^T r = c - w + rho b and ||r||^2 = ||y||^2 - 2 c^T b + b^T (w - rho b), so the
+// dual value D(r) of Prop. 1 and the lower bound
+//   P(beta) >= 1/2 ||r||^2 - (X^T r)^T (beta - b) + sum psi(beta)
+// (from ||r - X (beta - b)||^2 >= ||r||^2 - 2 r^T X (beta - b)) follow from the
+// per-node sums of c b, b (w - rho b), nu(|X^T r|), (X^T r) (beta - b), psi(beta).
+template <class T>
+__device__ __forceinline__ void admm_update(T Qv, int64_t o, int64_t j, T *__restrict__ W, T *__restrict__ beta,
+                                            T *__restrict__ V, T *__restrict__ Bst, const uint8_t *__restrict__ codes,
+                                            const T *__restrict__ c, const DevParams<T> &q, int store_b, bool est,
+                                            const GateArgs &ga, double e[5]) {
+    const uint8_t code = codes[o];
+    const T wv = W[o];
+    const T bb = (wv - Qv) / q.rho;
+    const T v = V[o];
+    const T bt = bb + v / q.rho;
+    const T be = prox_beta(bt, code, q);
+    const T vn = v + q.rho * (bb - be);
+    const T cj = c[j];
+    beta[o] = be;
+    V[o] = vn;
+    W[o] = cj + q.rho * be - vn;
+    if (store_b) Bst[o] = bb;
+    if (est) {
+        const double b = (double)bb, w = (double)wv, cd = (double)cj, rho = (double)q.rho, bn = (double)be;
+        const double g = cd - w + rho * b;
+        e[0] = cd * b;
+        e[1] = b * (w - rho * b);
+        e[2] = nu_plain(fabs(g), code, ga.l0, ga.l2, ga.M, ga.two_M_l2, ga.four_l2, ga.l2_M2, ga.free_quad);
+        e[3] = g * (bn - b);
+        e[4] = psi_val(bn, code, ga.l0, ga.l2, ga.s, ga.free_quad, ga.psi_lin);
+    }
+}
+
+// Sums the five estimate terms over the TM consecutive threads that hold one
+// node's coordinates of the tile and stores them at gpart[(node * ntile + tile) * 5].
+template <int TM>
+__device__ __forceinline__ void store_estimate(double e[5], int m, int64_t node, double *__restrict__ gpart) {
+    for (int t = 0; t < 5; ++t)
+        for (int off = 1; off < TM; off <<= 1) e[t] += __shfl_xor(e[t], off);
+    if (m == 0) {
+        double *d = gpart + (node * (int64_t)gridDim.x + blockIdx.x) * 5;
+        for (int t = 0; t < 5; ++t) d[t] = e[t];
+    }
+}
+
+// Contraction over n with the ADMM epilogue: Q[k][j] = sum_i Xh[i][j] U[k][i],
+// then admm_update for node k and coordinate j.  gpart != nullptr adds the
+// per-tile sums of the gap estimate.
 template <class TA, class T, int BM, int BN, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
                                                   int64_t ldu, int64_t kdim, T *__restrict__ W,
                                                   T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
                                                   const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                                   const int *__restrict__ active, DevParams<T> q, int64_t ldp,
-                                                  int store_b) {
+                                                  int store_b, double *__restrict__ gpart, GateArgs ga) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
-    __shared__ T red[WAVES * TM * TN];
+    __shared__ T red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
     nt_tile<TA, T, T, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, red);
+    const bool est = gpart != nullptr;
     for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
-        int n = idx / TM, m = idx % TM;
-        int64_t node = n0 + n, j = m0 + m;
-        if (!active[node]) continue;
-        T Qv = sum_waves<T, TM * TN, WAVES>(red, idx);
-        int64_t o = node * ldp + j;
-        T wv = W[o];
-        T bb = (wv - Qv) / q.rho;
-        T v = V[o];
-        T bt = bb + v / q.rho;
-        T be = prox_beta(bt, codes[o], q);
-        T vn = v + q.rho * (bb - be);
-        beta[o] = be;
-        V[o] = vn;
-        W[o] = c[j] + q.rho * be - vn;
-        if (store_b) Bst[o] = bb;
+        const int n = idx / TM, m = idx % TM;
+        const int64_t node = n0 + n, j = m0 + m;
+        double e[5] = {0, 0, 0, 0, 0};
+        if (active[node])
+            admm_update<T>(sum_waves<T, TM, TN, WAVES>(red, n, m), node * ldp + j, j, W, beta, V, Bst, codes, c, q,
+                           store_b, est, ga, e);
+        if (est) store_estimate<TM>(e, m, node, gpart);
     }
 }
 
@@ -262,8 +305,9 @@ __device__ __forceinline__ void load8f(const float *p, float out[8]) {
 }
 
 // 32 x 32 tile of C[m][n] = sum_k (Ahi + Alo)[m][k] B[n][k] with A rows in BF16
-// (hi, lo) and B rows in FP32 (split into hi, lo on load), k chunks of 32 split
-// over WAVES waves, next chunk's loads issued before the current chunk's MFMAs.
+// (hi, lo) and B rows in FP32 (split into hi, lo on load); chunks of 32 k split
+// over WAVES waves as in nt_tile, next chunk's loads issued before the current
+// chunk's MFMAs.
 template <int WAVES>
 __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
                                              int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
@@ -309,7 +353,7 @@ __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, con
             for (int v = 0; v < 4; ++v) {
                 int m = a * 16 + acc_row<float>(lane, v);
                 int n = b * 16 + r;
-                red[w * 1024 + n * 32 + m] = acc[a][b][v];
+                red[w * Red<32, 32>::WS + n * Red<32, 32>::LD + m] = acc[a][b][v];
             }
     __syncthreads();
 }
@@ -321,12 +365,12 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *
                                                                   const __bf16 *__restrict__ Alo, int64_t lda,
                                                                   const float *__restrict__ B, int64_t ldb,
                                                                   float *__restrict__ U, int64_t ldu, int64_t kdim) {
-    __shared__ float red[kWavesBf16 * 1024];
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
     nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, red);
     for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
         int n = idx >> 5, m = idx & 31;
-        U[(n0 + n) * ldu + m0 + m] = sum_waves<float, 1024, kWavesBf16>(red, idx);
+        U[(n0 + n) * ldu + m0 + m] = sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
     }
 }
 
@@ -335,73 +379,88 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
     const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
     int64_t ldu, int64_t kdim, float *__restrict__ W, float *__restrict__ beta, float *__restrict__ V,
     float *__restrict__ Bst, const uint8_t *__restrict__ codes, const float *__restrict__ c,
-    const int *__restrict__ active, DevParams<float> q, int64_t ldp, int store_b) {
-    __shared__ float red[kWavesBf16 * 1024];
+    const int *__restrict__ active, DevParams<float> q, int64_t ldp, int store_b, double *__restrict__ gpart,
+    GateArgs ga) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
     nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, red);
+    const bool est = gpart != nullptr;
     for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
-        int n = idx >> 5, m = idx & 31;
-        int64_t node = n0 + n, j = m0 + m;
-        if (!active[node]) continue;
-        float Qv = sum_waves<float, 1024, kWavesBf16>(red, idx);
-        int64_t o = node * ldp + j;
-        float wv = W[o];
-        float bb = (wv - Qv) / q.rho;
-        float v = V[o];
-        float bt = bb + v / q.rho;
-        float be = prox_beta(bt, codes[o], q);
-        float vn = v + q.rho * (bb - be);
-        beta[o] = be;
-        V[o] = vn;
-        W[o] = c[j] + q.rho * be - vn;
-        if (store_b) Bst[o] = bb;
+        const int n = idx >> 5, m = idx & 31;
+        const int64_t node = n0 + n, j = m0 + m;
+        double e[5] = {0, 0, 0, 0, 0};
+        if (active[node])
+            admm_update<float>(sum_waves<float, 32, 32, kWavesBf16>(red, n, m), node * ldp + j, j, W, beta, V, Bst,
+                               codes, c, q, store_b, est, ga, e);
+        if (est) store_estimate<32>(e, m, node, gpart);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Gap check (FP64)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double block_sum(double v, double *sh) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+// Sum over the 64 lanes of a wave (xor butterfly: every lane gets the same value).
+__device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    __syncthreads();
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    double s = sh[0] + sh[1] + sh[2] + sh[3];
-    return s;
+    return v;
 }
 
-// Per node k (one workgroup): r = y - Ub[k], rb = y - Ubeta[k]; sums
-// ||r||^2, y^T r, |y|^T |r|, ||rb||^2.  R[k] receives r.
-__global__ __launch_bounds__(256) void k_resid(const double *__restrict__ y, const double *__restrict__ Ub,
-                                               const double *__restrict__ Ubeta, double *__restrict__ R, int64_t np,
-                                               double *__restrict__ nodescal, const int *__restrict__ active,
-                                               int with_beta) {
-    __shared__ double sh[4];
-    const int64_t k = blockIdx.x;
-    if (!active[k]) return;
-    double rr = 0, yr = 0, ayr = 0, bb = 0;
-    for (int64_t i = threadIdx.x; i < np; i += 256) {
-        double yi = y[i];
-        double rv = yi - Ub[k * np + i];
-        R[k * np + i] = rv;
-        rr += rv * rv;
-        yr += yi * rv;
-        ayr += fabs(yi) * fabs(rv);
-        if (with_beta) {
-            double rb = yi - Ubeta[k * np + i];
-            bb += rb * rb;
-        }
+// Number of nodes of the last gap estimate that may pass the check (nullptr:
+// no estimate, the check always runs).
+__device__ __forceinline__ bool check_skipped(const int *gate) { return gate && gate[0] == 0; }
+
+// First kernel of the gap check: with the original X (row-major copy, FP64)
+// and the node iterates b (grid z = 0) and beta (z = 1) of type T, forms the
+// 32 x 32 tile of X b^T (X beta^T) and, in the epilogue, r = y - X b (stored in
+// R) with the per-(node, row tile) sums of ||r||^2, y^T r, |y|^T |r| (z = 0) or
+// ||y - X beta||^2 (z = 1) in rpart[(node * ntr + tile) * 4 + {0, 1, 2 | 3}].
+// Also clears the two result counters (mode 0) for the finalize kernel.
+template <class T>
+__global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR, int64_t ldx,
+                                                  const T *__restrict__ B, const T *__restrict__ beta, int64_t ldb,
+                                                  int64_t kdim, const double *__restrict__ y, double *__restrict__ R,
+                                                  int64_t np, double *__restrict__ rpart, int *__restrict__ counter,
+                                                  const int *__restrict__ gate) {
+    constexpr int WAVES = 8;
+    __shared__ double red[WAVES * Red<32, 32>::WS];
+    if (check_skipped(gate)) return;
+    if (counter && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+        counter[0] = 0;
+        counter[1] = 0;
     }
-    rr = block_sum(rr, sh);
-    yr = block_sum(yr, sh);
-    ayr = block_sum(ayr, sh);
-    bb = block_sum(bb, sh);
-    if (threadIdx.x == 0) {
-        nodescal[k * 8 + 0] = rr;
-        nodescal[k * 8 + 1] = yr;
-        nodescal[k * 8 + 2] = ayr;
-        nodescal[k * 8 + 3] = bb;
+    const bool with_b = blockIdx.z == 0;
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    nt_tile<double, T, double, 2, 2, WAVES>(XR, ldx, with_b ? B : beta, ldb, kdim, m0, n0, red);
+    const int64_t ntr = gridDim.x;
+    for (int idx = threadIdx.x; idx < 1024; idx += 64 * WAVES) {
+        const int n = idx >> 5, m = idx & 31;
+        const int64_t node = n0 + n, i = m0 + m;
+        const double yi = y[i];
+        const double rv = yi - sum_waves<double, 32, 32, WAVES>(red, n, m);
+        double e0, e1 = 0.0, e2 = 0.0;
+        if (with_b) {
+            R[node * np + i] = rv;
+            e0 = rv * rv;
+            e1 = yi * rv;
+            e2 = fabs(yi) * fabs(rv);
+        } else {
+            e0 = rv * rv;
+        }
+        for (int off = 1; off < 32; off <<= 1) {
+            e0 += __shfl_xor(e0, off);
+            e1 += __shfl_xor(e1, off);
+            e2 += __shfl_xor(e2, off);
+        }
+        if (m == 0) {
+            double *d = rpart + (node * ntr + blockIdx.x) * 4;
+            if (with_b) {
+                d[0] = e0;
+                d[1] = e1;
+                d[2] = e2;
+            } else {
+                d[3] = e0;
+            }
+        }
     }
 }
 
@@ -414,29 +473,35 @@ struct DualArgs {
 // g = X^T r per (node, coordinate) with the per-tile sums of the upper bounds
 // of nu_i(|g_i|) and of psi_i(beta_i):  part[(k * ntile + tile) * 3 + {0,1,2}] =
 // sum nu+, sum |nu+|, sum psi.
+constexpr int kWavesDual = 8;
+
 template <class T>
-__global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, int64_t lda,
-                                                  const double *__restrict__ R, int64_t ldr, int64_t kdim,
-                                                  const uint8_t *__restrict__ codes, const T *__restrict__ beta,
-                                                  const double *__restrict__ colnrm,
-                                                  const double *__restrict__ nodescal, const int *__restrict__ active,
-                                                  double *__restrict__ part, int64_t ldp, DualArgs da) {
-    __shared__ double red[4 * 1024];
+__global__ __launch_bounds__(64 * kWavesDual) void k_dual_xtr(
+    const double *__restrict__ A, int64_t lda, const double *__restrict__ R, int64_t ldr, int64_t kdim,
+    const uint8_t *__restrict__ codes, const T *__restrict__ beta, const double *__restrict__ colnrm,
+    const double *__restrict__ rpart, int64_t ntr, const int *__restrict__ active, double *__restrict__ part,
+    int64_t ldp, DualArgs da, const int *__restrict__ gate) {
+    __shared__ double red[kWavesDual * Red<32, 32>::WS];
+    if (check_skipped(gate)) return;
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    nt_tile<double, double, double, 2, 2, 4>(A, lda, R, ldr, kdim, m0, n0, red);
-    // thread t: node n = t / 8, coordinates 4 (t % 8) .. +3 of the tile
-    const int n = tid >> 3, jl = (tid & 7) * 4;
+    nt_tile<double, double, double, 2, 2, kWavesDual>(A, lda, R, ldr, kdim, m0, n0, red);
+    // 16 threads per node: thread t takes node t / 16, coordinates 2 (t % 16) and
+    // 2 (t % 16) + 1 of the tile
+    const int n = tid >> 4, jl = (tid & 15) * 2;
     const int64_t node = n0 + n;
+    // ||r||^2 of the node from the row-tile sums of the first check kernel
+    double rr = 0.0;
+    for (int64_t t = tid & 15; t < ntr; t += 16) rr += rpart[(node * ntr + t) * 4];
+    for (int off = 1; off < 16; off <<= 1) rr += __shfl_xor(rr, off);
     double snu = 0, sanu = 0, spsi = 0;
     const bool act = active[node] != 0;
     if (act) {
-        double nr = sqrt(nodescal[node * 8 + 0]);
-        for (int e = 0; e < 4; ++e) {
+        const double nr = sqrt(rr);
+        for (int e = 0; e < 2; ++e) {
             int64_t j = m0 + jl + e;
             if (j >= da.p) continue;
-            double g = red[n * 32 + jl + e] + red[1024 + n * 32 + jl + e] + red[2048 + n * 32 + jl + e] +
-                       red[3072 + n * 32 + jl + e];
+            double g = sum_waves<double, 32, 32, kWavesDual>(red, n, jl + e);
             uint8_t code = codes[node * ldp + j];
             double ej = 2.0 * da.gamma_n * colnrm[j] * nr;
             double val = nu_upper(fabs(g), ej, code, da.l0, da.l2, da.M, da.two_M_l2, da.four_l2, da.l2_M2,
@@ -446,12 +511,12 @@ __global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, 
             spsi += psi_val((double)beta[node * ldp + j], code, da.l0, da.l2, da.s, da.free_quad, da.psi_lin);
         }
     }
-    for (int off = 1; off < 8; off <<= 1) {
+    for (int off = 1; off < 16; off <<= 1) {
         snu += __shfl_xor(snu, off);
         sanu += __shfl_xor(sanu, off);
         spsi += __shfl_xor(spsi, off);
     }
-    if ((tid & 7) == 0 && act) {
+    if ((tid & 15) == 0 && act) {
         int64_t ntile = gridDim.x;
         double *pp = part + (node * ntile + blockIdx.x) * 3;
         pp[0] = snu;
@@ -462,65 +527,104 @@ __global__ __launch_bounds__(256) void k_dual_xtr(const double *__restrict__ A, 
 
 struct FinArgs {
     double gamma_n2, gamma_p, tol, switch_tol;
-    int64_t K, ntile;
+    int64_t K, ntile, ntr;
     int mode;  // mode 0: solve (gap test), 1: bound only
 };
 
-// One workgroup: per active node, LB = (q - sum nu+) - margin (Prop. 1 plus the
-// rounding margin), P(beta) = 1/2 ||y - X beta||^2 + sum psi, gap test.  Writes
-// the number of nodes still active to *counter.
-__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ nodescal,
-                                                  const double *__restrict__ part, int *__restrict__ active,
-                                                  int *__restrict__ status, int *__restrict__ iters,
-                                                  double *__restrict__ lb, double *__restrict__ primal,
-                                                  int *__restrict__ counter, const int *__restrict__ sweep_no,
-                                                  FinArgs fa) {
-    __shared__ int shc[256], shc2[256];
-    const int iter = *sweep_no;
+// One wave per node: LB = (q - sum nu+) - margin (Prop. 1 plus the rounding
+// margin) and, in mode 0, P(beta) = 1/2 ||y - X beta||^2 + sum psi and the gap
+// test; the nodes still active (and those above switch_tol) are added to the
+// two counters with integer atomics (exact in any order).  When the gap
+// estimate skipped the check, every active node stays active: both counters
+// become the active count gate[1].
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpart, const double *__restrict__ part,
+                                                  int *__restrict__ active, int *__restrict__ status,
+                                                  int *__restrict__ iters, double *__restrict__ lb,
+                                                  double *__restrict__ primal, int *__restrict__ counter,
+                                                  const int *__restrict__ sweep_no, FinArgs fa,
+                                                  const int *__restrict__ gate) {
+    const int lane = threadIdx.x & 63;
+    if (check_skipped(gate)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            counter[0] = gate[1];
+            counter[1] = gate[1];
+        }
+        return;
+    }
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= fa.K || !active[k]) return;
     const double u = 1.1102230246251565e-16;
-    int cnt = 0, cnt2 = 0;
-    for (int64_t k = threadIdx.x; k < fa.K; k += 256) {
-        if (!active[k]) continue;
-        double rr = nodescal[k * 8 + 0], yr = nodescal[k * 8 + 1], ayr = nodescal[k * 8 + 2];
-        double rbrb = nodescal[k * 8 + 3];
-        double snu = 0, sanu = 0, spsi = 0;
-        const double *pk = part + k * fa.ntile * 3;
-        for (int64_t t = 0; t < fa.ntile; ++t) {
-            snu += pk[t * 3 + 0];
-            sanu += pk[t * 3 + 1];
-            spsi += pk[t * 3 + 2];
-        }
-        double qv = -0.5 * rr + yr;
-        double margin = 2.0 * fa.gamma_n2 * (0.5 * rr + ayr) + 2.0 * fa.gamma_p * sanu + 4.0 * u * (fabs(qv) + fabs(snu));
-        double LB = (qv - snu) - margin;
-        lb[k] = LB;
-        if (fa.mode == 1) continue;
-        double P = 0.5 * rbrb + spsi;
-        primal[k] = P;
-        iters[k] = iter;
-        double den = fabs(P) > 1e-300 ? fabs(P) : 1e-300;
-        if ((P - LB) / den <= fa.tol) {
-            status[k] = 0;
-            active[k] = 0;
-        } else {
-            status[k] = 1;
-            ++cnt;
-            if ((P - LB) / den > fa.switch_tol) ++cnt2;
-        }
+    double rr = 0, yr = 0, ayr = 0, rbrb = 0, snu = 0, sanu = 0, spsi = 0;
+    const double *rk = rpart + k * fa.ntr * 4;
+    for (int64_t t = lane; t < fa.ntr; t += 64) {
+        rr += rk[t * 4 + 0];
+        yr += rk[t * 4 + 1];
+        ayr += rk[t * 4 + 2];
+        if (fa.mode == 0) rbrb += rk[t * 4 + 3];
     }
-    shc[threadIdx.x] = cnt;
-    shc2[threadIdx.x] = cnt2;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            shc[threadIdx.x] += shc[threadIdx.x + s];
-            shc2[threadIdx.x] += shc2[threadIdx.x + s];
-        }
-        __syncthreads();
+    const double *pk = part + k * fa.ntile * 3;
+    for (int64_t t = lane; t < fa.ntile; t += 64) {
+        snu += pk[t * 3 + 0];
+        sanu += pk[t * 3 + 1];
+        spsi += pk[t * 3 + 2];
     }
-    if (threadIdx.x == 0) {
-        counter[0] = shc[0];
-        counter[1] = shc2[0];
+    rr = wave_sum(rr);
+    yr = wave_sum(yr);
+    ayr = wave_sum(ayr);
+    rbrb = wave_sum(rbrb);
+    snu = wave_sum(snu);
+    sanu = wave_sum(sanu);
+    spsi = wave_sum(spsi);
+    if (lane != 0) return;
+    const double qv = -0.5 * rr + yr;
+    const double margin =
+        2.0 * fa.gamma_n2 * (0.5 * rr + ayr) + 2.0 * fa.gamma_p * sanu + 4.0 * u * (fabs(qv) + fabs(snu));
+    const double LB = (qv - snu) - margin;
+    lb[k] = LB;
+    if (fa.mode == 1) return;
+    const double P = 0.5 * rbrb + spsi;
+    primal[k] = P;
+    iters[k] = *sweep_no;
+    const double den = fabs(P) > 1e-300 ? fabs(P) : 1e-300;
+    if ((P - LB) / den <= fa.tol) {
+        status[k] = 0;
+        active[k] = 0;
+    } else {
+        status[k] = 1;
+        atomicAdd(&counter[0], 1);
+        if ((P - LB) / den > fa.switch_tol) atomicAdd(&counter[1], 1);
+    }
+}
+
+struct GateFin {
+    double yy, tol_eff;
+    int64_t K, ntile;
+};
+
+// Gap estimate per node (one wave each) from the per-tile sums of the last
+// sweep's epilogue.  A node needs the exact check unless P_low > 0 and
+// P_low - D > 2 tol_eff P_low: then its P(beta) is at least P_low and its
+// rigorous LB at most D (up to rounding), so the check's relative gap
+// 1 - LB / P(beta) is at least 1 - D / P_low and the check cannot accept it.
+// gate[0] counts the nodes that need the check, gate[1] the active nodes (both
+// cleared at the start of the block; integer atomics, exact in any order).
+__global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, const int *__restrict__ active,
+                                              int *__restrict__ gate, GateFin gf) {
+    const int lane = threadIdx.x & 63;
+    const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= gf.K || !active[k]) return;
+    double e[5] = {0, 0, 0, 0, 0};
+    const double *pk = gpart + k * gf.ntile * 5;
+    for (int64_t t = lane; t < gf.ntile; t += 64)
+        for (int i = 0; i < 5; ++i) e[i] += pk[t * 5 + i];
+    for (int i = 0; i < 5; ++i) e[i] = wave_sum(e[i]);
+    if (lane == 0) {
+        const double rr = gf.yy - 2.0 * e[0] + e[1];
+        const double D = -0.5 * rr + (gf.yy - e[0]) - e[2];
+        const double Pl = 0.5 * rr - e[3] + e[4];
+        const bool far = Pl > 0.0 && (Pl - D) > 2.0 * gf.tol_eff * Pl;
+        if (!far) atomicAdd(&gate[0], 1);
+        atomicAdd(&gate[1], 1);
     }
 }
 
@@ -590,15 +694,19 @@ template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
 // Tile shapes of the sweep contractions: (BM, BN) 16-row blocks per output tile
 // and the number of waves splitting the contraction range.  FP64 keeps at most
 // 8 waves on the 32 x 32 tile (LDS for the cross-wave reduction).
-constexpr int kShapes = 6;
-constexpr int kTileBM[kShapes] = {2, 2, 2, 1, 2, 1};
-constexpr int kTileBN[kShapes] = {2, 2, 2, 2, 1, 1};
-constexpr int kTileW[kShapes] = {4, 8, 16, 8, 8, 4};
+constexpr int kShapes = 9;
+constexpr int kTileBM[kShapes] = {2, 2, 2, 1, 2, 1, 4, 2, 4};
+constexpr int kTileBN[kShapes] = {2, 2, 2, 2, 1, 1, 2, 4, 2};
+constexpr int kTileW[kShapes] = {4, 8, 16, 8, 8, 4, 8, 8, 4};
+
+// A shape fits a padded batch when its node tile divides it.
+bool shape_fits(int v, int64_t Kp) { return Kp % (16 * kTileBN[v]) == 0; }
 
 template <class TA, class TB, class TC>
 void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int64_t ldb, TC *U, int64_t ldu,
                int64_t rows, int64_t Kp, int64_t kdim) {
     if (sizeof(TC) == 8 && v == 2) v = 1;
+    if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(rows / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XW(PBM, PBN, PW) \
@@ -609,27 +717,35 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
         case 2: L0L2_XW(2, 2, (sizeof(TC) == 8 ? 8 : 16)); break;
         case 3: L0L2_XW(1, 2, 8); break;
         case 4: L0L2_XW(2, 1, 8); break;
-        default: L0L2_XW(1, 1, 4); break;
+        case 5: L0L2_XW(1, 1, 4); break;
+        case 6: L0L2_XW(4, 2, 8); break;
+        case 7: L0L2_XW(2, 4, 8); break;
+        default: L0L2_XW(4, 2, 4); break;
     }
 #undef L0L2_XW
 }
 
 template <class T>
 void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes,
-                const int *active, const DevParams<T> &q, int store_b) {
+                const int *active, const DevParams<T> &q, int store_b, double *gpart = nullptr,
+                const GateArgs &ga = GateArgs{}) {
     if (sizeof(T) == 8 && v == 2) v = 1;
+    if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XTU(PBM, PBN, PW)                                                                                  \
     hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, \
-                       sw.B, codes, sw.c, active, q, pp, store_b)
+                       sw.B, codes, sw.c, active, q, pp, store_b, gpart, ga)
     switch (v) {
         case 0: L0L2_XTU(2, 2, 4); break;
         case 1: L0L2_XTU(2, 2, 8); break;
         case 2: L0L2_XTU(2, 2, (sizeof(T) == 8 ? 8 : 16)); break;
         case 3: L0L2_XTU(1, 2, 8); break;
         case 4: L0L2_XTU(2, 1, 8); break;
-        default: L0L2_XTU(1, 1, 4); break;
+        case 5: L0L2_XTU(1, 1, 4); break;
+        case 6: L0L2_XTU(4, 2, 8); break;
+        case 7: L0L2_XTU(2, 4, 8); break;
+        default: L0L2_XTU(4, 2, 4); break;
     }
 #undef L0L2_XTU
 }
@@ -664,6 +780,7 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         HIPCHK(hipEventCreate(&e1));
         float best_xw = 1e30f, best_xtu = 1e30f;
         for (int v = 0; v < kShapes; ++v) {
+            if (!shape_fits(v, Kp)) continue;
             for (int rep = 0; rep < 2; ++rep) {
                 float ms[2];
                 for (int which = 0; which < 2; ++which) {
@@ -692,8 +809,18 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
 // ---------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------
+GateArgs gate_args(const Instance &in) {
+    GateArgs g;
+    g.l0 = in.mp.l0; g.l2 = in.mp.l2; g.M = in.mp.M; g.s = in.mp.s;
+    g.two_M_l2 = in.mp.two_M_l2; g.four_l2 = in.mp.four_l2; g.l2_M2 = in.mp.l2_M2; g.psi_lin = in.mp.psi_lin;
+    g.free_quad = in.mp.free_quad;
+    return g;
+}
+
+// One sweep; with gate set the epilogue also leaves the per-tile sums of the
+// gap estimate in ws.gpart.
 template <class T>
-void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int64_t active) {
+void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int64_t active, bool gate = false) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
@@ -704,13 +831,15 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
     launch_xw<T, T, T>(tc.xw, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp);
     prof_end(ctx, prof_xw<T>(), active);
     prof_begin(ctx, prof_xtu<T>());
-    launch_xtu<T>(tc.xtu, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), ws.active.as<int>(), q, store_b ? 1 : 0);
+    launch_xtu<T>(tc.xtu, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), ws.active.as<int>(), q, store_b ? 1 : 0,
+                  gate ? ws.gpart.as<double>() : nullptr, gate_args(in));
     prof_end(ctx, prof_xtu<T>(), active);
     HIPCHK(hipGetLastError());
 }
 
 // One sweep of the BF16 form on the FP32 state of sw.
-void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool store_b, int64_t active) {
+void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool store_b, int64_t active,
+                     bool gate = false) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
@@ -725,7 +854,7 @@ void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool sto
     prof_begin(ctx, PROF_ADMM_XTU_BF16);
     hipLaunchKernelGGL(k_admm_xtu_bf16, g2, dim3(64 * kWavesBf16), 0, s, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(), np, sw.U, np,
                        np, sw.W, sw.beta, sw.V, sw.B, ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp,
-                       store_b ? 1 : 0);
+                       store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, gate_args(in));
     prof_end(ctx, PROF_ADMM_XTU_BF16, active);
     HIPCHK(hipGetLastError());
 }
@@ -742,27 +871,26 @@ DualArgs dual_args(const Instance &in) {
 }
 
 // FP64 check at (B, beta) of type T: fills ws.lb / primal / status / active and
-// the two counters (active nodes; active nodes above switch_tol).
+// the two counters (active nodes; active nodes above switch_tol).  gate: the
+// counters of the last gap estimate (nullptr: the check always runs).
 template <class T>
-void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol, double switch_tol, int mode) {
+void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol, double switch_tol, int mode,
+                const int *gate = nullptr) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     const int64_t np = in.np, pp = in.pp;
-    dim3 g1((unsigned)(np / 32), (unsigned)(Kp / 32));
+    const int64_t ntr = np / 32;
+    dim3 g1((unsigned)ntr, (unsigned)(Kp / 32), mode == 0 ? 2u : 1u);
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
-    const double *X64 = in.X64.as<double>();
     prof_begin(ctx, PROF_CHECK);
-    const double *X64R = in.X64R.as<double>();
-    launch_xw<double, T, double>(0, s, X64R, pp, B, pp, ws.Ub.as<double>(), np, np, Kp, pp);
-    if (mode == 0) launch_xw<double, T, double>(0, s, X64R, pp, beta, pp, ws.Ubeta.as<double>(), np, np, Kp, pp);
-    hipLaunchKernelGGL(k_resid, dim3((unsigned)Kp), dim3(256), 0, s, in.y64.as<double>(), ws.Ub.as<double>(),
-                       ws.Ubeta.as<double>(), ws.R.as<double>(), np, ws.nodescal.as<double>(), ws.active.as<int>(),
-                       mode == 0 ? 1 : 0);
+    hipLaunchKernelGGL((k_check_xr<T>), g1, dim3(512), 0, s, in.X64R.as<double>(), pp, B, beta, pp, pp,
+                       in.y64.as<double>(), ws.R.as<double>(), np, ws.rpart.as<double>(),
+                       mode == 0 ? ws.counter.as<int>() : nullptr, gate);
     DualArgs da = dual_args(in);
-    hipLaunchKernelGGL((k_dual_xtr<T>), g2, dim3(256), 0, s, X64, np, ws.R.as<double>(), np, np,
-                       ws.codes.as<uint8_t>(), mode == 0 ? beta : B, in.colnrm.as<double>(), ws.nodescal.as<double>(),
-                       ws.active.as<int>(), ws.part.as<double>(), pp, da);
+    hipLaunchKernelGGL((k_dual_xtr<T>), g2, dim3(64 * kWavesDual), 0, s, in.X64.as<double>(), np, ws.R.as<double>(),
+                       np, np, ws.codes.as<uint8_t>(), mode == 0 ? beta : B, in.colnrm.as<double>(),
+                       ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), pp, da, gate);
     FinArgs fa;
     const double u = 1.1102230246251565e-16;
     fa.gamma_n2 = ((double)in.n + 2.0) * u / (1.0 - ((double)in.n + 2.0) * u);
@@ -771,10 +899,12 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     fa.switch_tol = switch_tol;
     fa.K = Kp;
     fa.ntile = pp / 32;
+    fa.ntr = ntr;
     fa.mode = mode;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, ws.nodescal.as<double>(), ws.part.as<double>(),
-                       ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), ws.lb.as<double>(),
-                       ws.primal.as<double>(), ws.counter.as<int>(), ws.sweep_no.as<int>(), fa);
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.rpart.as<double>(),
+                       ws.part.as<double>(), ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(),
+                       ws.lb.as<double>(), ws.primal.as<double>(), ws.counter.as<int>(), ws.sweep_no.as<int>(), fa,
+                       gate);
     prof_end(ctx, PROF_CHECK);
     HIPCHK(hipGetLastError());
 }
@@ -803,22 +933,41 @@ enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2 };
 
 // One block: `n` sweeps of the given kind, then the FP64 gap check and the
 // read-back of the two counters into pinned host memory.  Issued eagerly.
-void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active) {
+// Unless force is set, the last sweep also forms the gap estimate and the check
+// kernels run only when some active node may pass it (tolerance tol for FP64
+// sweeps, switch_tol for reduced ones, where the host also reads the second
+// counter); a skipped check leaves every node active.
+void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
+                 bool force) {
+    Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
-    hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n);
+    hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>());
     for (int t = 1; t <= n; ++t) {
-        const bool last = t == n;
-        if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), Kp, last, active);
-        else if (kind == SK_BF16) sweep_once_bf16(ctx, sweep32(ctx), Kp, last, active);
-        else sweep_once<float>(ctx, sweep32(ctx), Kp, last, active);
+        const bool last = t == n, gate = last && !force;
+        if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), Kp, last, active, gate);
+        else if (kind == SK_BF16) sweep_once_bf16(ctx, sweep32(ctx), Kp, last, active, gate);
+        else sweep_once<float>(ctx, sweep32(ctx), Kp, last, active, gate);
+    }
+    const int *skip = nullptr;
+    if (!force) {
+        int rows = 32;
+        if (kind == SK_F64) rows = 16 * kTileBM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
+        else if (kind == SK_F32) rows = 16 * kTileBM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
+        GateFin gf{in.yy, kind == SK_F64 ? tol : switch_tol, Kp, in.pp / rows};
+        prof_begin(ctx, PROF_CHECK);
+        hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
+                           ws.active.as<int>(), ws.gate.as<int>(), gf);
+        prof_end(ctx, PROF_CHECK);
+        HIPCHK(hipGetLastError());
+        skip = ws.gate.as<int>();
     }
     if (kind == SK_F64) {
         Sweep<double> sw = sweep64(ctx);
-        check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0);
+        check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, skip);
     } else {
         Sweep<float> sw = sweep32(ctx);
-        check_once<float>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0);
+        check_once<float>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, skip);
     }
     HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
 }
@@ -827,13 +976,13 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
 // graph per (kind, padded batch, block length, tolerances) and replayed; with
 // the profiler on they are issued eagerly so each launch can be timed.
 void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
-               int out[2]) {
+               bool force, int out[2]) {
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     if (!ctx->use_graphs || ctx->prof.on) {
-        issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
+        issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
     } else {
-        GraphKey key{kind, Kp, n, tol, switch_tol, ws.gen};
+        GraphKey key{kind, Kp, n, force ? 1 : 0, tol, switch_tol, ws.gen};
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
             // settle the tile shapes (the autotuner synchronises) before capturing
@@ -844,7 +993,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                 bool ok = true;
                 try {
-                    issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
+                    issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
                 } catch (...) {
                     ok = false;
                 }
@@ -857,7 +1006,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
             if (!ex) {
                 // capture is not available here: issue blocks launch by launch from now on
                 ctx->use_graphs = false;
-                issue_block(ctx, kind, Kp, n, tol, switch_tol, active);
+                issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
                 HIPCHK(hipStreamSynchronize(s));
                 out[0] = ws.host_counter[0];
                 out[1] = ws.host_counter[1];
@@ -882,7 +1031,8 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
         const int n = std::min(m, o.max_iter - t);
-        run_block(ctx, sizeof(T) == 8 ? SK_F64 : SK_F32, Kp, n, o.tol_node, o.tol_node, active, cnt);
+        run_block(ctx, sizeof(T) == 8 ? SK_F64 : SK_F32, Kp, n, o.tol_node, o.tol_node, active,
+                  t + n >= o.max_iter, cnt);
         t += n;
         active = cnt[0];
         if (cnt[0] == 0) break;
@@ -912,7 +1062,7 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     for (int t = 0; t < o.max_iter;) {
         const int n = std::min(m, o.max_iter - t);
         const int kind = fp64 ? SK_F64 : (bf16 ? SK_BF16 : SK_F32);
-        run_block(ctx, kind, Kp, n, o.tol_node, switch_tol, active, cnt);
+        run_block(ctx, kind, Kp, n, o.tol_node, switch_tol, active, t + n >= o.max_iter, cnt);
         t += n;
         active = cnt[0];
         if (cnt[0] == 0) break;
@@ -955,12 +1105,12 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.V.ensure(sb * Kp * pp);
     ws.B.ensure(sb * Kp * pp);
     ws.U.ensure(sb * Kp * np);
-    ws.Ub.ensure(8 * Kp * np);
-    ws.Ubeta.ensure(8 * Kp * np);
     ws.R.ensure(8 * Kp * np);
     ws.codes.ensure((size_t)(Kp * pp));
-    ws.nodescal.ensure(8 * 8 * Kp);
+    ws.rpart.ensure(8 * 4 * Kp * (np / 32));
     ws.part.ensure(8 * 3 * Kp * (pp / 32));
+    ws.gpart.ensure(8 * 5 * Kp * (pp / 16));
+    ws.gate.ensure(2 * sizeof(int));
     ws.active.ensure(4 * Kp);
     ws.iters.ensure(4 * Kp);
     ws.status.ensure(4 * Kp);

@@ -87,6 +87,18 @@ __device__ __forceinline__ double nu_upper(double absg, double e, uint8_t code, 
     return val;
 }
 
+// nu_i(|g|) of eq. (nudef) in plain FP64 (no rounding allowance): the value the
+// gap estimate uses to decide whether a node can have converged.
+__device__ __forceinline__ double nu_plain(double absg, uint8_t code, double l0, double l2, double M,
+                                           double two_M_l2, double four_l2, double l2_M2, int free_quad) {
+    if (code == CODE_FIX0) return 0.0;
+    double val;
+    if ((code == CODE_FIX1 || free_quad) && absg <= two_M_l2) val = absg * absg / four_l2 - l0;
+    else val = M * absg - l0 - l2_M2;
+    if (code == CODE_FREE && val < 0.0) val = 0.0;
+    return val;
+}
+
 __device__ __forceinline__ double gamma_k(double k) {
     const double u = 1.1102230246251565e-16;
     return k * u / (1.0 - k * u);

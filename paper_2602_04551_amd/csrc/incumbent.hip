@@ -122,42 +122,140 @@ __device__ double U_S(const double *__restrict__ X, int64_t np, const double *__
 }
 
 // Fast proximal gradient on each support (eqs. fpg_extrapolate .. fpg_armijo),
-// one workgroup per node.  Start at the node iterate on S; alpha_0 =
+// one workgroup of 4 waves per node.  Start at the node iterate on S; alpha_0 =
 // 4 / (||X_S||_F^2 + 2 l2), halved on each Armijo failure (at most 60 times per
 // iteration) and carried over; stop on |dU| <= tol max(1, U) or max|d beta| <=
 // 1e-10; at most max_iter iterations.
 //
-// Supports of up to kGramMax coordinates keep G = X_S^T X_S and g = X_S^T y in
-// LDS (built in one pass over X_S), so an iteration costs O(|S|^2) on chip:
-// U(b) = 1/2 ||y||^2 - g^T b + 1/2 b^T G b + l2 ||b||^2 and grad = G b - g + 2 l2 b.
-// Larger supports stream X_S once per evaluation.  Either way the returned
-// objective F(S, beta) is evaluated from the residual y - X_S beta in FP64.
-constexpr int kGramMax = 96;
-constexpr int kGramRows = 32;
+// Supports of up to kGramMax = 64 coordinates build G = X_S^T X_S once with FP64
+// MFMA (the 4 waves split the rows of X_S, lower block triangle only) and keep it
+// in LDS with g = X_S^T y; one wave then runs the iterations with coordinate a
+// on lane a: U(b) = 1/2 ||y||^2 - g^T b + 1/2 b^T G b + l2 ||b||^2 and
+// grad = G b - g + 2 l2 b, every sum a wave reduction (no workgroup barrier).
+// Larger supports stream X_S once per evaluation with all 4 waves.  Either way
+// the returned objective F(S, beta) is evaluated from the residual y - X_S beta
+// in FP64.
+constexpr int kGramMax = 64;
+constexpr int kGramBlocks = kGramMax / 16;
+constexpr int kGramTri = kGramBlocks * (kGramBlocks + 1) / 2;
 
 struct FistaShared {
     int idx[kSMax];
     double cur[kSMax], prev[kSMax], ext[kSMax], nxt[kSMax], grad[kSMax];
-    double G[kGramMax * kGramMax];
-    double tile[kGramRows * kGramMax];
-    double g[kGramMax], Gv[kGramMax];
+    double G[kGramMax * kGramMax];   // column-major, leading dimension kGramMax
+    double vb[kGramMax];
     double sh[4];
     int shw[4];
+    int it;
 };
 
-// v -> (1/2 v^T G v - g^T v + l2 ||v||^2 + yy/2), and Gv into sm.Gv (Gram form).
-__device__ double U_gram(FistaShared &sm, const double *v, int k, double yy, double l2) {
-    const int tid = threadIdx.x;
-    double part = 0.0;
-    if (tid < k) {
-        double s = 0.0;
-        const double *row = sm.G + tid * k;
-        for (int b = 0; b < k; ++b) s += row[b] * v[b];
-        sm.Gv[tid] = s;
-        part = 0.5 * v[tid] * s - sm.g[tid] * v[tid] + l2 * v[tid] * v[tid];
+// Sum (max) over the 64 lanes of a wave; every lane receives the same value.
+__device__ __forceinline__ double wsum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    return v;
+}
+
+// Lane a < k: (G v)_a for v held one coordinate per lane (wave-local LDS
+// broadcast through sm.vb); returns the lane's share of U(v) - yy/2 in *part.
+__device__ __forceinline__ double gram_mv(FistaShared &sm, double v, int k, int lane) {
+    __builtin_amdgcn_wave_barrier();
+    sm.vb[lane] = v;
+    __builtin_amdgcn_wave_barrier();
+    double s = 0.0;
+    if (lane < k)
+        for (int b = 0; b < k; ++b) s += sm.G[b * kGramMax + lane] * sm.vb[b];
+    __builtin_amdgcn_wave_barrier();
+    return s;
+}
+
+// G = X_S^T X_S into sm.G (k <= 16 NB).  Lane l of a wave loads rows
+// i0 + 4 (l / 16) .. + 3 of column S[16 bi + l % 16] with one vector load, and
+// the 4 MFMAs of a 16-row chunk map their k slot to those rows for both
+// operands (both are X_S).  Rows beyond n are zero in X; lanes past the support
+// load a valid column and contribute zeros.  The 4 waves split the rows and
+// only the lower block triangle is formed.
+template <int NB>
+__device__ void gram_build_nb(FistaShared &sm, const double *__restrict__ X, int64_t np, int k) {
+    constexpr int TRI = NB * (NB + 1) / 2;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int q = lane >> 4, r = lane & 15;
+    f64x4 acc[TRI];
+    for (int t = 0; t < TRI; ++t) acc[t] = f64x4{0, 0, 0, 0};
+    const double *col[NB];
+    bool valid[NB];
+    for (int bi = 0; bi < NB; ++bi) {
+        const int a = 16 * bi + r;
+        valid[bi] = a < k;
+        col[bi] = X + (int64_t)sm.idx[valid[bi] ? a : 0] * np + 4 * q;
     }
-    part = bsum(part, sm.sh);
-    return 0.5 * yy + part;
+    const int64_t nch = np / 16;
+    const int64_t c0 = nch * w / 4, c1 = nch * (w + 1) / 4;
+    // two register stages; every load is unconditional (chunk index clamped to
+    // the wave's last chunk), so each chunk waits only for its own loads
+    double f[2][NB][4];
+    auto load = [&](int st, int64_t c) {
+#pragma unroll
+        for (int bi = 0; bi < NB; ++bi) load4(col[bi] + 16 * c, f[st][bi]);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto compute = [&](int st) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            double x[NB];
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi) x[bi] = valid[bi] ? f[st][bi][t] : 0.0;
+#pragma unroll
+            for (int bi = 0; bi < NB; ++bi)
+#pragma unroll
+                for (int bj = 0; bj <= bi; ++bj) {
+                    const int o = bi * (bi + 1) / 2 + bj;
+                    acc[o] = mfma16(x[bi], x[bj], acc[o]);
+                }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    if (c0 < c1) {
+        load(0, c0);
+        for (int64_t c = c0; c < c1; c += 2) {
+            load(1, c + 1 < c1 ? c + 1 : c1 - 1);
+            compute(0);
+            load(0, c + 2 < c1 ? c + 2 : c1 - 1);
+            if (c + 1 < c1) compute(1);
+        }
+    }
+    // cross-wave sum in a fixed order: wave 0 stores, waves 1..3 add in turn
+    for (int ww = 0; ww < 4; ++ww) {
+        if (w == ww)
+            for (int bi = 0; bi < NB; ++bi)
+                for (int bj = 0; bj <= bi; ++bj) {
+                    const int o = bi * (bi + 1) / 2 + bj;
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = 16 * bi + acc_row<double>(lane, v), cl = 16 * bj + r;
+                        if (row >= k || cl >= k) continue;
+                        double x = acc[o][v];
+                        double *g1 = &sm.G[cl * kGramMax + row];
+                        *g1 = ww == 0 ? x : *g1 + x;
+                        if (bi != bj) {
+                            double *g2 = &sm.G[row * kGramMax + cl];
+                            *g2 = ww == 0 ? x : *g2 + x;
+                        }
+                    }
+                }
+        __syncthreads();
+    }
+}
+
+__device__ void gram_build(FistaShared &sm, const double *__restrict__ X, int64_t np, int k) {
+    switch ((k + 15) / 16) {
+        case 1: gram_build_nb<1>(sm, X, np, k); break;
+        case 2: gram_build_nb<2>(sm, X, np, k); break;
+        case 3: gram_build_nb<3>(sm, X, np, k); break;
+        default: gram_build_nb<4>(sm, X, np, k); break;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, const double *__restrict__ y,
@@ -204,53 +302,73 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         }
         return;
     }
-    const bool gram = k <= kGramMax;
-    if (gram) {
-        // G = X_S^T X_S by row tiles of X_S staged in LDS; thread t accumulates
-        // entries t, t + 256, ... of G in place.
-        for (int e = tid; e < k * k; e += 256) sm.G[e] = 0.0;
-        for (int64_t i0 = 0; i0 < fa.n; i0 += kGramRows) {
-            __syncthreads();
-            for (int e = tid; e < kGramRows * k; e += 256) {
-                int r = e % kGramRows, a = e / kGramRows;
-                int64_t i = i0 + r;
-                sm.tile[r * k + a] = i < fa.n ? X[(int64_t)idx[a] * fa.np + i] : 0.0;
+    if (k <= kGramMax) {
+        gram_build(sm, X, fa.np, k);
+        if (w == 0) {
+            const bool on = lane < k;
+            const double g = on ? c[idx[lane]] : 0.0;
+            double cur = 0.0, cn = 0.0;
+            if (on) {
+                cur = beta[node * ldb + idx[lane]];
+                cur = cur > fa.M ? fa.M : (cur < -fa.M ? -fa.M : cur);
+                cn = colnrm[idx[lane]];
             }
-            __syncthreads();
-            for (int e = tid; e < k * k; e += 256) {
-                int a = e / k, b = e % k;
-                double s = 0.0;
-                for (int r = 0; r < kGramRows; ++r) s += sm.tile[r * k + a] * sm.tile[r * k + b];
-                sm.G[e] += s;
+            double prev = cur;
+            double alpha = 4.0 / (wsum(cn * cn) + 2.0 * fa.l2);
+            auto U = [&](double v, double &Gv) {
+                Gv = gram_mv(sm, v, k, lane);
+                double part = on ? 0.5 * v * Gv - g * v + fa.l2 * v * v : 0.0;
+                return 0.5 * yy + wsum(part);
+            };
+            double Gv;
+            double Ucur = U(cur, Gv);
+            int it = 0;
+            while (it < fa.max_iter) {
+                const double mom = (double)it / ((double)it + 3.0);
+                const double ext = cur + mom * (cur - prev);
+                const double Uext = U(ext, Gv);
+                const double grad = on ? Gv - g + 2.0 * fa.l2 * ext : 0.0;
+                double Unxt = 0.0, nxt = 0.0;
+                for (int bt = 0; bt <= 60; ++bt) {
+                    double v = ext - alpha * grad;
+                    nxt = on ? (v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v)) : 0.0;
+                    const double d = nxt - ext;
+                    const double gd = wsum(grad * d), dd = wsum(d * d);
+                    Unxt = U(nxt, Gv);
+                    if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
+                    alpha *= 0.5;
+                }
+                ++it;
+                const double dm = wmax(fabs(nxt - cur));
+                const double dU = fabs(Unxt - Ucur);
+                prev = cur;
+                cur = nxt;
+                Ucur = Unxt;
+                if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
             }
+            if (on) sm.cur[lane] = cur;
+            if (lane == 0) sm.it = it;
         }
         __syncthreads();
-        if (tid < k) sm.g[tid] = c[idx[tid]];
-        __syncthreads();
-    }
-    double fro = 0.0;
-    for (int a = tid; a < k; a += 256) {
-        double b0 = beta[node * ldb + idx[a]];
-        b0 = b0 > fa.M ? fa.M : (b0 < -fa.M ? -fa.M : b0);
-        sm.cur[a] = b0;
-        sm.prev[a] = b0;
-        double cn = colnrm[idx[a]];
-        fro += cn * cn;
-    }
-    fro = bsum(fro, sm.sh);
-    double alpha = 4.0 / (fro + 2.0 * fa.l2);
-    double Ucur = gram ? U_gram(sm, sm.cur, k, yy, fa.l2) : U_S(X, fa.np, y, idx, k, sm.cur, res, false, sm.sh, fa);
-    int it = 0;
-    while (it < fa.max_iter) {
-        double mom = (double)it / ((double)it + 3.0);
-        for (int a = tid; a < k; a += 256) sm.ext[a] = sm.cur[a] + mom * (sm.cur[a] - sm.prev[a]);
-        __syncthreads();
-        double Uext;
-        if (gram) {
-            Uext = U_gram(sm, sm.ext, k, yy, fa.l2);
-            if (tid < k) sm.grad[tid] = sm.Gv[tid] - sm.g[tid] + 2.0 * fa.l2 * sm.ext[tid];
-        } else {
-            Uext = U_S(X, fa.np, y, idx, k, sm.ext, res, true, sm.sh, fa);
+    } else {
+        double fro = 0.0;
+        for (int a = tid; a < k; a += 256) {
+            double b0 = beta[node * ldb + idx[a]];
+            b0 = b0 > fa.M ? fa.M : (b0 < -fa.M ? -fa.M : b0);
+            sm.cur[a] = b0;
+            sm.prev[a] = b0;
+            double cn = colnrm[idx[a]];
+            fro += cn * cn;
+        }
+        fro = bsum(fro, sm.sh);
+        double alpha = 4.0 / (fro + 2.0 * fa.l2);
+        double Ucur = U_S(X, fa.np, y, idx, k, sm.cur, res, false, sm.sh, fa);
+        int it = 0;
+        while (it < fa.max_iter) {
+            double mom = (double)it / ((double)it + 3.0);
+            for (int a = tid; a < k; a += 256) sm.ext[a] = sm.cur[a] + mom * (sm.cur[a] - sm.prev[a]);
+            __syncthreads();
+            double Uext = U_S(X, fa.np, y, idx, k, sm.ext, res, true, sm.sh, fa);
             __syncthreads();
             for (int a = w; a < k; a += 4) {
                 const double *col = X + (int64_t)idx[a] * fa.np;
@@ -259,37 +377,39 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
                 for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
                 if (lane == 0) sm.grad[a] = s + 2.0 * fa.l2 * sm.ext[a];
             }
-        }
-        __syncthreads();
-        double Unxt = 0.0;
-        for (int bt = 0; bt <= 60; ++bt) {
-            double gd = 0.0, dd = 0.0;
-            for (int a = tid; a < k; a += 256) {
-                double v = sm.ext[a] - alpha * sm.grad[a];
-                v = v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v);
-                sm.nxt[a] = v;
-                double d = v - sm.ext[a];
-                gd += sm.grad[a] * d;
-                dd += d * d;
+            __syncthreads();
+            double Unxt = 0.0;
+            for (int bt = 0; bt <= 60; ++bt) {
+                double gd = 0.0, dd = 0.0;
+                for (int a = tid; a < k; a += 256) {
+                    double v = sm.ext[a] - alpha * sm.grad[a];
+                    v = v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v);
+                    sm.nxt[a] = v;
+                    double d = v - sm.ext[a];
+                    gd += sm.grad[a] * d;
+                    dd += d * d;
+                }
+                gd = bsum(gd, sm.sh);
+                dd = bsum(dd, sm.sh);
+                Unxt = U_S(X, fa.np, y, idx, k, sm.nxt, res, false, sm.sh, fa);
+                if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
+                alpha *= 0.5;
             }
-            gd = bsum(gd, sm.sh);
-            dd = bsum(dd, sm.sh);
-            Unxt = gram ? U_gram(sm, sm.nxt, k, yy, fa.l2) : U_S(X, fa.np, y, idx, k, sm.nxt, res, false, sm.sh, fa);
-            if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
-            alpha *= 0.5;
+            ++it;
+            double dm = 0.0;
+            for (int a = tid; a < k; a += 256) dm = fmax(dm, fabs(sm.nxt[a] - sm.cur[a]));
+            dm = bmax(dm, sm.sh);
+            double dU = fabs(Unxt - Ucur);
+            for (int a = tid; a < k; a += 256) {
+                sm.prev[a] = sm.cur[a];
+                sm.cur[a] = sm.nxt[a];
+            }
+            __syncthreads();
+            Ucur = Unxt;
+            if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
         }
-        ++it;
-        double dm = 0.0;
-        for (int a = tid; a < k; a += 256) dm = fmax(dm, fabs(sm.nxt[a] - sm.cur[a]));
-        dm = bmax(dm, sm.sh);
-        double dU = fabs(Unxt - Ucur);
-        for (int a = tid; a < k; a += 256) {
-            sm.prev[a] = sm.cur[a];
-            sm.cur[a] = sm.nxt[a];
-        }
+        if (tid == 0) sm.it = it;
         __syncthreads();
-        Ucur = Unxt;
-        if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
     }
     double f = U_S(X, fa.np, y, idx, k, sm.cur, res, false, sm.sh, fa) + fa.l0 * (double)k;
     for (int64_t j = tid; j < fa.p; j += 256) beta[node * ldb + j] = 0.0;
@@ -297,7 +417,7 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
     for (int a = tid; a < k; a += 256) beta[node * ldb + idx[a]] = sm.cur[a];
     if (tid == 0) {
         obj[node] = f;
-        if (iters) iters[node] = it;
+        if (iters) iters[node] = sm.it;
     }
 }
 

@@ -94,10 +94,12 @@ struct Workspace {
     DevBuf U;                      // Kp x np state precision (ADMM product)
     DevBuf W64, beta64, V64, B64;  // FP32 mode: FP64 state of the final sweeps (Kp x pp)
     DevBuf U64;                    // FP32 mode: Kp x np
-    DevBuf Ub, Ubeta, R;           // Kp x np FP64
+    DevBuf R;                      // Kp x np FP64 residuals of the gap check
     DevBuf codes;                  // Kp x pp uint8
-    DevBuf nodescal;               // Kp x 8 doubles: rr, yr, ayr, rbrb, ...
+    DevBuf rpart;                  // Kp x (np/32) x 4 doubles: row-tile sums of the gap check
     DevBuf part;                   // Kp x (pp/32) x 3 doubles
+    DevBuf gpart;                  // Kp x (pp/16) x 5 doubles: per-tile sums of the gap estimate
+    DevBuf gate;                   // int32 x 2: nodes that need the exact check, active nodes
     DevBuf active, iters, status;  // Kp int32
     DevBuf lb, primal;             // Kp doubles
     DevBuf counter;                // int32 x 2: active nodes, active nodes above the switch tolerance
@@ -127,12 +129,14 @@ struct GraphKey {
     int kind;
     int64_t Kp;
     int n;
+    int force;
     double tol, switch_tol;
     int64_t gen;
     bool operator<(const GraphKey &o) const {
         if (kind != o.kind) return kind < o.kind;
         if (Kp != o.Kp) return Kp < o.Kp;
         if (n != o.n) return n < o.n;
+        if (force != o.force) return force < o.force;
         if (tol != o.tol) return tol < o.tol;
         if (switch_tol != o.switch_tol) return switch_tol < o.switch_tol;
         return gen < o.gen;

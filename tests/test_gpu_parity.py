@@ -83,13 +83,13 @@ def test_sweeps_fp64_match_oracle(torch_cuda, cases, name):
             assert rel(gbb[k], bb) < 1e-11, (S, k)
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("shape", list(range(9)))
 def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
     inst, o, root = cases["ragged"]
     K = 48
     codes, beta0, v0 = random_nodes(inst.p, K, 11, root["beta"], root["v"])
     ctx = ctx_for(inst, "fp64")
-    ctx.set_tiles(shape, 5 - shape)
+    ctx.set_tiles(shape, 8 - shape)
     gb, gv, gbb = ctx.admm_sweeps(codes, beta0, v0, 7)
     gb, gbb = gb.cpu().numpy(), gbb.cpu().numpy()
     for k in range(K):
@@ -99,6 +99,19 @@ def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
         for _ in range(7):
             b, v, bb = o.sweep(codes[k], b, v)
         assert rel(gb[k], b) < 1e-11 and rel(gbb[k], bb) < 1e-11
+
+
+def test_fixed_shape_that_does_not_fit_the_batch_is_rejected(torch_cuda, cases):
+    """Shape 7 tiles 64 nodes; a batch padded to 32 nodes cannot use it."""
+    from paper_2602_04551_amd.binding import L0L2Error
+    inst, o, root = cases["ragged"]
+    codes, beta0, v0 = random_nodes(inst.p, 20, 12, root["beta"], root["v"])
+    ctx = ctx_for(inst, "fp64")
+    ctx.set_tiles(7, 1)
+    with pytest.raises(L0L2Error):
+        ctx.admm_sweeps(codes, beta0, v0, 2)
+    ctx.set_tiles(-1, -1)
+    ctx.admm_sweeps(codes, beta0, v0, 2)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp32", 2e-5), ("bf16", 5e-4)])

@@ -65,3 +65,55 @@ def test_best_first_batches_certify_the_optimum(orc, harness, tmp_path, K):
     assert {t["decision"] for t in trace} <= {0, 1, 2, 3}
     ids = [t["id"] for t in trace]
     assert len(ids) == len(set(ids))
+
+
+def test_gap_estimate_never_exceeds_the_exact_gap():
+    """The check gate of the sweep kernels skips the exact FP64 gap check when
+    the estimate formed in the last sweep's epilogue exceeds twice the
+    tolerance.  The estimate rests on two facts about the b-update (Sec. 3.1.2):
+    b solves (X^T X + rho I) b = w, so r = y - X b has X^T r = c - w + rho b and
+    ||r||^2 = ||y||^2 - 2 c^T b + b^T (w - rho b); and ||y - X beta||^2 >=
+    ||r||^2 - 2 (X^T r)^T (beta - b).  Restated here in numpy and run along
+    the oracle's sweeps, it must never exceed the relative gap of the oracle's
+    rigorous bound (Prop. 1) and primal value."""
+    from oracle import Oracle, nu as onu
+    inst = datagen.config_instance("C1")
+    orc = Oracle.from_instance(inst)
+    X, y = inst.X, inst.y
+    l0, l2, M, rho = inst.lambda0, inst.lambda2, inst.M, 1.0
+    c, yy = X.T @ y, float(y @ y)
+    s = np.sqrt(l0 / l2)
+
+    def psi(b, code):                     # eq. (psi) on |b| <= M
+        if code == datagen.FIX0:
+            return 0.0 if b == 0.0 else np.inf
+        if code == datagen.FIX1 or (s <= M and abs(b) >= s):
+            return l0 + l2 * b * b
+        if s <= M:
+            return 2.0 * np.sqrt(l0 * l2) * abs(b)
+        return (l0 / M + l2 * M) * abs(b)
+
+    codes_all = datagen.node_batch_codes(inst.p, 4, seed=3, free_min=10)
+    worst, checked = np.inf, 0
+    for codes in codes_all:
+        beta, v = np.zeros(inst.p), np.zeros(inst.p)
+        for it in range(1, 121):
+            w = c + rho * beta - v
+            beta2, v2, b = orc.sweep(codes, beta, v)
+            if it % 10 == 0:
+                g = c - w + rho * b
+                s_cb, s_bq = c @ b, b @ (w - rho * b)
+                s_nu = sum(onu(abs(g[j]), int(codes[j]), l0, l2, M) for j in range(inst.p))
+                s_gd = g @ (beta2 - b)
+                s_psi = sum(psi(beta2[j], codes[j]) for j in range(inst.p))
+                rr = yy - 2.0 * s_cb + s_bq
+                D = -0.5 * rr + (yy - s_cb) - s_nu
+                P_low = 0.5 * rr - s_gd + s_psi
+                P = orc.primal(codes, beta2)
+                LB = orc.dual_bound(codes, y - X @ b)
+                assert P_low <= P * (1 + 1e-12)
+                worst = min(worst, (P - LB) / abs(P) - (P_low - D) / P_low)
+                checked += 1
+            beta, v = beta2, v2
+    assert checked == 48
+    assert worst >= -1e-12
