@@ -237,7 +237,9 @@ int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
  * duration in milliseconds for one kernel family: "gemm_xw.f32" / "gemm_xw.f64"
  * (contraction over p of a sweep in FP32 / FP64), "admm_xtu.f32" /
  * "admm_xtu.f64" (contraction over n with the prox/V epilogue), "gap_check"
- * (the FP64 gap evaluation, all of its kernels), "round_branch", "fista".
+ * (the FP64 gap evaluation, all of its kernels), "round_branch", "fista",
+ * "anchor.f64" (the two FP64 products that start each block of anchored
+ * sweeps in FP32 mode; those sweeps themselves count as the FP32 families).
  * units (may be NULL) receives the work the timed launches did: for the sweep
  * families the number of node-iterations of nodes that were still active
  * (columns of converged nodes are not counted).  Unknown names give

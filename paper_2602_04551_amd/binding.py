@@ -244,7 +244,7 @@ class Context:
         self._check(lib.l0l2_profile_enable(self._h, 1 if enable else 0))
 
     KERNELS = ("gemm_xw.f32", "admm_xtu.f32", "gemm_xw.f64", "admm_xtu.f64", "gemm_xw.bf16", "admm_xtu.bf16",
-               "gap_check", "round_branch", "fista")
+               "gap_check", "round_branch", "fista", "anchor.f64")
 
     def profile_query(self, kernel):
         """(launches, total milliseconds, work units) of one timed kernel family."""

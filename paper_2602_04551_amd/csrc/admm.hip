@@ -282,6 +282,51 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
+// Anchored FP64 sweeps (FP32 mode, after the reduced-precision phase).  At the
+// start of a block the FP64 iterate w_a = W and its product z_a = Xh^T Xh w_a
+// are formed in FP64; each sweep then multiplies only the difference
+// d = fl32(W - w_a) in FP32 and takes Xh^T Xh W = z_a + Xh^T Xh d, so the
+// product's rounding error scales with |d| (the movement within the block)
+// rather than with |W|, while the state and the update stay FP64.
+// ---------------------------------------------------------------------------
+__global__ void k_anchor_init(const double *__restrict__ W, double *__restrict__ Wa, float *__restrict__ d,
+                              int64_t total) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        Wa[idx] = W[idx];
+        d[idx] = 0.0f;
+    }
+}
+
+// Contraction over n of an anchored sweep: Q32 = Xh^T U32 (FP32 MFMA), then
+// admm_update<double> with Q = z_a + Q32 and d = fl32(W_new - w_a).
+template <int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_admm_xtu_anch(
+    const float *__restrict__ A, int64_t lda, const float *__restrict__ U, int64_t ldu, int64_t kdim,
+    const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W, double *__restrict__ beta,
+    double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d, const uint8_t *__restrict__ codes,
+    const double *__restrict__ c, const int *__restrict__ active, DevParams<double> q, int64_t ldp, int store_b,
+    double *__restrict__ gpart, GateArgs ga) {
+    constexpr int TM = 16 * BM, TN = 16 * BN;
+    __shared__ float red[WAVES * Red<TM, TN>::WS];
+    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    nt_tile<float, float, float, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, red);
+    const bool est = gpart != nullptr;
+    for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
+        const int n = idx / TM, m = idx % TM;
+        const int64_t node = n0 + n, j = m0 + m;
+        double e[5] = {0, 0, 0, 0, 0};
+        if (active[node]) {
+            const int64_t o = node * ldp + j;
+            const double Qv = Za[o] + (double)sum_waves<float, TM, TN, WAVES>(red, n, m);
+            admm_update<double>(Qv, o, j, W, beta, V, Bst, codes, c, q, store_b, est, ga, e);
+            d[o] = (float)(W[o] - Wa[o]);
+        }
+        if (est) store_estimate<TM>(e, m, node, gpart);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // BF16 form of the two contractions: the folded operand is stored as two BF16
 // terms (hi + lo), the FP32 node operand is split into two BF16 terms on load,
 // and each 16 x 16 block accumulates hi*hi + hi*lo + lo*hi in FP32 (the lo*lo
@@ -750,9 +795,34 @@ void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp
 #undef L0L2_XTU
 }
 
-// Tile shapes chosen for (arithmetic type, padded batch): each shape is timed
-// on the live batch (every node masked inactive, so the epilogue writes
-// nothing) and the fastest kept for this instance.
+// The anchored sweep's contraction over n (FP32 operands, FP64 update).
+void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<double> &s64, const double *Za,
+                     const double *Wa, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes, const int *active,
+                     const DevParams<double> &q, int store_b, double *gpart, const GateArgs &ga) {
+    if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
+    dim3 b((unsigned)(64 * kTileW[v]));
+#define L0L2_XTUA(PBM, PBN, PW)                                                                                \
+    hipLaunchKernelGGL((k_admm_xtu_anch<PBM, PBN, PW>), g, b, 0, s, s32.Xh, np, s32.U, np, np, Za, Wa, s64.W,     \
+                       s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, pp, store_b, gpart, ga)
+    switch (v) {
+        case 0: L0L2_XTUA(2, 2, 4); break;
+        case 1: L0L2_XTUA(2, 2, 8); break;
+        case 2: L0L2_XTUA(2, 2, 16); break;
+        case 3: L0L2_XTUA(1, 2, 8); break;
+        case 4: L0L2_XTUA(2, 1, 8); break;
+        case 5: L0L2_XTUA(1, 1, 4); break;
+        case 6: L0L2_XTUA(4, 2, 8); break;
+        case 7: L0L2_XTUA(2, 4, 8); break;
+        default: L0L2_XTUA(4, 2, 4); break;
+    }
+#undef L0L2_XTUA
+}
+
+// Tile shapes chosen for (arithmetic type, padded batch): each shape that fits
+// is timed on the live batch (every node masked inactive, so the epilogue
+// writes nothing), the best of several interleaved samples per shape, and the
+// fastest kept for this instance.
 template <class T>
 TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
     Instance &in = ctx->inst;
@@ -778,26 +848,40 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
+        // time `reps` back-to-back launches of shape v (which = 0: contraction
+        // over p, 1: contraction over n with its masked epilogue)
+        auto time_shape = [&](int v, int which, int reps) {
+            HIPCHK(hipEventRecord(e0, s));
+            for (int t = 0; t < reps; ++t) {
+                if (which == 0) launch_xw<T, T, T>(v, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp);
+                else launch_xtu<T>(v, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), inactive.as<int>(), q, 0);
+            }
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return ms / (float)reps;
+        };
+        // warm-up round, which also sizes the measurement: about 0.2 ms of work
+        // per sample, and fewer rounds for launches longer than 1 ms
+        float t0 = 0.f;
+        for (int v = 0; v < kShapes; ++v)
+            if (shape_fits(v, Kp)) t0 = std::max(t0, std::max(time_shape(v, 0, 1), time_shape(v, 1, 1)));
+        const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
+        const int rounds = t0 > 1.0f ? 2 : 4;
+        float best[kShapes][2];
+        for (int v = 0; v < kShapes; ++v) best[v][0] = best[v][1] = 1e30f;
+        for (int r = 0; r < rounds; ++r)
+            for (int v = 0; v < kShapes; ++v) {
+                if (!shape_fits(v, Kp)) continue;
+                for (int which = 0; which < 2; ++which)
+                    best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
+            }
         float best_xw = 1e30f, best_xtu = 1e30f;
         for (int v = 0; v < kShapes; ++v) {
             if (!shape_fits(v, Kp)) continue;
-            for (int rep = 0; rep < 2; ++rep) {
-                float ms[2];
-                for (int which = 0; which < 2; ++which) {
-                    HIPCHK(hipEventRecord(e0, s));
-                    for (int t = 0; t < 3; ++t) {
-                        if (which == 0) launch_xw<T, T, T>(v, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp);
-                        else launch_xtu<T>(v, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), inactive.as<int>(), q, 0);
-                    }
-                    HIPCHK(hipEventRecord(e1, s));
-                    HIPCHK(hipEventSynchronize(e1));
-                    HIPCHK(hipEventElapsedTime(&ms[which], e0, e1));
-                }
-                if (rep == 1) {
-                    if (ms[0] < best_xw) { best_xw = ms[0]; tc.xw = v; }
-                    if (ms[1] < best_xtu) { best_xtu = ms[1]; tc.xtu = v; }
-                }
-            }
+            if (best[v][0] < best_xw) { best_xw = best[v][0]; tc.xw = v; }
+            if (best[v][1] < best_xtu) { best_xtu = best[v][1]; tc.xtu = v; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -856,6 +940,44 @@ void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool sto
                        np, sw.W, sw.beta, sw.V, sw.B, ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp,
                        store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, gate_args(in));
     prof_end(ctx, PROF_ADMM_XTU_BF16, active);
+    HIPCHK(hipGetLastError());
+}
+
+// Start of an anchored block: w_a = W (FP64), d = 0, z_a = Xh^T (Xh w_a) in FP64.
+void anchor_start(l0l2_ctx *ctx, int64_t Kp) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    const int64_t np = in.np, pp = in.pp;
+    Sweep<double> s64 = sweep64(ctx);
+    Sweep<float> s32 = sweep32(ctx);
+    const TileChoice &tc = tile_choice<double>(ctx, s64, Kp);
+    prof_begin(ctx, PROF_ANCHOR);
+    hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * pp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
+                       Kp * pp);
+    launch_xw<double, double, double>(tc.xw, s, s64.XhR, pp, ws.Wa.as<double>(), pp, s64.U, np, np, Kp, pp);
+    launch_xw<double, double, double>(tc.xw, s, s64.Xh, np, s64.U, np, ws.Za.as<double>(), pp, pp, Kp, np);
+    prof_end(ctx, PROF_ANCHOR);
+    HIPCHK(hipGetLastError());
+}
+
+// One anchored sweep: U = Xh d (FP32), then the FP64 update from z_a + Xh^T U.
+void sweep_once_anch(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    const int64_t np = in.np, pp = in.pp;
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    const TileChoice &tc = tile_choice<float>(ctx, s32, Kp);
+    prof_begin(ctx, PROF_GEMM_XW_F32);
+    launch_xw<float, float, float>(tc.xw, s, s32.XhR, pp, s32.W, pp, s32.U, np, np, Kp, pp);
+    prof_end(ctx, PROF_GEMM_XW_F32, active);
+    prof_begin(ctx, PROF_ADMM_XTU_F32);
+    launch_xtu_anch(tc.xtu, s, s32, s64, ws.Za.as<double>(), ws.Wa.as<double>(), np, pp, Kp,
+                    ws.codes.as<uint8_t>(), ws.active.as<int>(), dev_params<double>(in.mp), store_b ? 1 : 0,
+                    gate ? ws.gpart.as<double>() : nullptr, gate_args(in));
+    prof_end(ctx, PROF_ADMM_XTU_F32, active);
     HIPCHK(hipGetLastError());
 }
 
@@ -929,7 +1051,7 @@ void read_counters(l0l2_ctx *ctx, int out[2]) {
     out[1] = ws.host_counter[1];
 }
 
-enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2 };
+enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2, SK_ANCH = 3 };
 
 // One block: `n` sweeps of the given kind, then the FP64 gap check and the
 // read-back of the two counters into pinned host memory.  Issued eagerly.
@@ -943,18 +1065,21 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>());
+    if (kind == SK_ANCH) anchor_start(ctx, Kp);
     for (int t = 1; t <= n; ++t) {
         const bool last = t == n, gate = last && !force;
         if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), Kp, last, active, gate);
         else if (kind == SK_BF16) sweep_once_bf16(ctx, sweep32(ctx), Kp, last, active, gate);
+        else if (kind == SK_ANCH) sweep_once_anch(ctx, Kp, last, active, gate);
         else sweep_once<float>(ctx, sweep32(ctx), Kp, last, active, gate);
     }
     const int *skip = nullptr;
     if (!force) {
         int rows = 32;
         if (kind == SK_F64) rows = 16 * kTileBM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
-        else if (kind == SK_F32) rows = 16 * kTileBM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
-        GateFin gf{in.yy, kind == SK_F64 ? tol : switch_tol, Kp, in.pp / rows};
+        else if (kind == SK_F32 || kind == SK_ANCH) rows = 16 * kTileBM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
+        const bool full = kind == SK_F64 || kind == SK_ANCH;
+        GateFin gf{in.yy, full ? tol : switch_tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
                            ws.active.as<int>(), ws.gate.as<int>(), gf);
@@ -962,7 +1087,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         HIPCHK(hipGetLastError());
         skip = ws.gate.as<int>();
     }
-    if (kind == SK_F64) {
+    if (kind == SK_F64 || kind == SK_ANCH) {
         Sweep<double> sw = sweep64(ctx);
         check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, skip);
     } else {
@@ -986,8 +1111,8 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
             // settle the tile shapes (the autotuner synchronises) before capturing
-            if (kind == SK_F64) (void)tile_choice<double>(ctx, sweep64(ctx), Kp);
-            else if (kind == SK_F32) (void)tile_choice<float>(ctx, sweep32(ctx), Kp);
+            if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), Kp);
+            if (kind == SK_F32 || kind == SK_ANCH) (void)tile_choice<float>(ctx, sweep32(ctx), Kp);
             hipGraph_t g = nullptr;
             hipGraphExec_t ex = nullptr;
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
@@ -1061,7 +1186,7 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
         const int n = std::min(m, o.max_iter - t);
-        const int kind = fp64 ? SK_F64 : (bf16 ? SK_BF16 : SK_F32);
+        const int kind = fp64 ? (bf16 ? SK_F64 : SK_ANCH) : (bf16 ? SK_BF16 : SK_F32);
         run_block(ctx, kind, Kp, n, o.tol_node, switch_tol, active, t + n >= o.max_iter, cnt);
         t += n;
         active = cnt[0];
@@ -1122,6 +1247,8 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ++ws.gen;
     if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 2 * sizeof(int), hipHostMallocDefault));
     if (in.prec != L0L2_FP64) {
+        ws.Wa.ensure(8 * Kp * pp);
+        ws.Za.ensure(8 * Kp * pp);
         ws.W64.ensure(8 * Kp * pp);
         ws.beta64.ensure(8 * Kp * pp);
         ws.V64.ensure(8 * Kp * pp);

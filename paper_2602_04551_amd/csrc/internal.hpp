@@ -94,6 +94,7 @@ struct Workspace {
     DevBuf U;                      // Kp x np state precision (ADMM product)
     DevBuf W64, beta64, V64, B64;  // FP32 mode: FP64 state of the final sweeps (Kp x pp)
     DevBuf U64;                    // FP32 mode: Kp x np
+    DevBuf Wa, Za;                 // FP32 mode: anchor w_a and Xh^T Xh w_a of the anchored sweeps (Kp x pp FP64)
     DevBuf R;                      // Kp x np FP64 residuals of the gap check
     DevBuf codes;                  // Kp x pp uint8
     DevBuf rpart;                  // Kp x (np/32) x 4 doubles: row-tile sums of the gap check
@@ -110,7 +111,7 @@ struct Workspace {
 };
 
 enum { PROF_GEMM_XW_F32 = 0, PROF_ADMM_XTU_F32, PROF_GEMM_XW_F64, PROF_ADMM_XTU_F64, PROF_GEMM_XW_BF16,
-       PROF_ADMM_XTU_BF16, PROF_CHECK, PROF_ROUND, PROF_FISTA, kProfCount };
+       PROF_ADMM_XTU_BF16, PROF_CHECK, PROF_ROUND, PROF_FISTA, PROF_ANCHOR, kProfCount };
 extern const char *const kProfNames[kProfCount];
 
 struct Profiler {
