@@ -69,22 +69,31 @@ __global__ void k_store_state(const T *__restrict__ src, int64_t K, int64_t p, i
     }
 }
 
-__global__ void k_set_active(int *active, int *status, int *iters, int64_t K, int64_t Kp, int *sweep_no) {
+// Batch start: nodes 0..K-1 active (the active list is 0..K-1), padding inactive.
+__global__ void k_set_active(int *active, int *status, int *iters, int *list, int *count, int64_t K, int64_t Kp,
+                             int *sweep_no) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < Kp) {
         active[k] = k < K;
         status[k] = 1;
         iters[k] = 0;
+        list[k] = (int)k;
     }
-    if (k == 0) *sweep_no = 0;
+    if (k == 0) {
+        *sweep_no = 0;
+        *count = (int)K;
+    }
 }
 
 // Sweep counter of the batch, advanced at the start of each block of sweeps;
-// the gate counters of the block start at zero.
-__global__ void k_sweep_add(int *sweep_no, int n, int *gate) {
+// the check list, the next active list and the result counters of the block
+// start empty.
+__global__ void k_sweep_add(int *sweep_no, int n, int *gate, int *ncount, int *counter) {
     *sweep_no += n;
     gate[0] = 0;
-    gate[1] = 0;
+    *ncount = 0;
+    counter[0] = 0;
+    counter[1] = 0;
 }
 
 // Warm start of Sec. 3.1.3: impose F0 on beta, then W = c + rho beta - V.
@@ -132,6 +141,23 @@ __device__ __forceinline__ TC sum_waves(const TC *red, int n, int m) {
 // holds every wave's partial sums (layout Red<TM, TN>) and the workgroup is
 // synchronised.  kdim must be a multiple of 16.
 // ---------------------------------------------------------------------------
+// Node columns of a launch.  Column c of the grid's node range is node slot
+// cols[c] for c < count; columns at or past count are idle (their workgroups
+// return at once, or their lanes load a valid row and store nothing).  cols ==
+// nullptr: column c is slot c and every column of the grid is live.  Converged
+// nodes thus cost nothing: the list holds the nodes still active.
+struct NodeCols {
+    const int *cols;
+    const int *count;
+};
+
+__device__ __forceinline__ int live_cols(const NodeCols &nc, int grid_cols) {
+    return nc.cols ? *nc.count : grid_cols;
+}
+__device__ __forceinline__ int64_t col_slot(const NodeCols &nc, int64_t c, int cnt) {
+    return nc.cols ? (int64_t)nc.cols[c < cnt ? c : cnt - 1] : c;
+}
+
 template <class TC, int BM, int BN, class TA, class TB>
 __device__ __forceinline__ void mma_chunk(typename Acc<TC>::type (&acc)[BM][BN], const TA (&a)[BM][4],
                                           const TB (&b)[BN][4]) {
@@ -142,7 +168,8 @@ __device__ __forceinline__ void mma_chunk(typename Acc<TC>::type (&acc)[BM][BN],
 
 template <class TA, class TB, class TC, int BM, int BN, int WAVES>
 __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B, int64_t ldb,
-                                        int64_t kdim, int64_t m0, int64_t n0, TC *red) {
+                                        int64_t kdim, int64_t m0, int64_t n0, const NodeCols &ncl, int cnt,
+                                        TC *red) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
@@ -155,7 +182,7 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     const TA *Ap[BM];
     const TB *Bp[BN];
     for (int i = 0; i < BM; ++i) Ap[i] = A + (m0 + 16 * i + r) * lda + 4 * q;
-    for (int j = 0; j < BN; ++j) Bp[j] = B + (n0 + 16 * j + r) * ldb + 4 * q;
+    for (int j = 0; j < BN; ++j) Bp[j] = B + col_slot(ncl, n0 + 16 * j + r, cnt) * ldb + 4 * q;
     TA a0[BM][4], a1[BM][4];
     TB b0[BN][4], b1[BN][4];
     int64_t c = c0;
@@ -184,18 +211,22 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     __syncthreads();
 }
 
-// Contraction over p: U[k][i] = sum_j Xh[i][j] W[k][j] (A = row-major Xh).
+// Contraction over p: U[k][i] = sum_j Xh[i][j] W[k][j] (A = row-major Xh), for
+// the node slots k of the live columns.
 template <class TA, class TB, class TC, int BM, int BN, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A, int64_t lda,
                                                         const TB *__restrict__ B, int64_t ldb, TC *__restrict__ U,
-                                                        int64_t ldu, int64_t kdim) {
+                                                        int64_t ldu, int64_t kdim, NodeCols ncl) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
     __shared__ TC red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, red);
+    const int cnt = live_cols(ncl, (int)(gridDim.y * TN));
+    if (n0 >= cnt) return;
+    nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, ncl, cnt, red);
     for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
         int n = idx / TM, m = idx % TM;
-        U[(n0 + n) * ldu + m0 + m] = sum_waves<TC, TM, TN, WAVES>(red, n, m);
+        if (n0 + n >= cnt) continue;
+        U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = sum_waves<TC, TM, TN, WAVES>(red, n, m);
     }
 }
 
@@ -249,7 +280,7 @@ template <int TM>
 __device__ __forceinline__ void store_estimate(double e[5], int m, int64_t node, double *__restrict__ gpart) {
     for (int t = 0; t < 5; ++t)
         for (int off = 1; off < TM; off <<= 1) e[t] += __shfl_xor(e[t], off);
-    if (m == 0) {
+    if (m == 0 && node >= 0) {
         double *d = gpart + (node * (int64_t)gridDim.x + blockIdx.x) * 5;
         for (int t = 0; t < 5; ++t) d[t] = e[t];
     }
@@ -264,20 +295,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ 
                                                   T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
                                                   const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                                   const int *__restrict__ active, DevParams<T> q, int64_t ldp,
-                                                  int store_b, double *__restrict__ gpart, GateArgs ga) {
+                                                  int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
     __shared__ T red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    nt_tile<TA, T, T, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, red);
+    const int cnt = live_cols(ncl, (int)(gridDim.y * TN));
+    if (n0 >= cnt) return;
+    nt_tile<TA, T, T, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
     const bool est = gpart != nullptr;
     for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
         const int n = idx / TM, m = idx % TM;
-        const int64_t node = n0 + n, j = m0 + m;
+        const bool live = n0 + n < cnt;
+        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
         double e[5] = {0, 0, 0, 0, 0};
-        if (active[node])
+        if (live && active[node])
             admm_update<T>(sum_waves<T, TM, TN, WAVES>(red, n, m), node * ldp + j, j, W, beta, V, Bst, codes, c, q,
                            store_b, est, ga, e);
-        if (est) store_estimate<TM>(e, m, node, gpart);
+        if (est) store_estimate<TM>(e, m, live ? node : -1, gpart);
     }
 }
 
@@ -306,23 +340,26 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu_anch(
     const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W, double *__restrict__ beta,
     double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d, const uint8_t *__restrict__ codes,
     const double *__restrict__ c, const int *__restrict__ active, DevParams<double> q, int64_t ldp, int store_b,
-    double *__restrict__ gpart, GateArgs ga) {
+    double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
     __shared__ float red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    nt_tile<float, float, float, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, red);
+    const int cnt = live_cols(ncl, (int)(gridDim.y * TN));
+    if (n0 >= cnt) return;
+    nt_tile<float, float, float, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
     const bool est = gpart != nullptr;
     for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
         const int n = idx / TM, m = idx % TM;
-        const int64_t node = n0 + n, j = m0 + m;
+        const bool live = n0 + n < cnt;
+        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
         double e[5] = {0, 0, 0, 0, 0};
-        if (active[node]) {
+        if (live && active[node]) {
             const int64_t o = node * ldp + j;
             const double Qv = Za[o] + (double)sum_waves<float, TM, TN, WAVES>(red, n, m);
             admm_update<double>(Qv, o, j, W, beta, V, Bst, codes, c, q, store_b, est, ga, e);
             d[o] = (float)(W[o] - Wa[o]);
         }
-        if (est) store_estimate<TM>(e, m, node, gpart);
+        if (est) store_estimate<TM>(e, m, live ? node : -1, gpart);
     }
 }
 
@@ -356,9 +393,10 @@ __device__ __forceinline__ void load8f(const float *p, float out[8]) {
 template <int WAVES>
 __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
                                              int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
-                                             int64_t m0, int64_t n0, float *red) {
+                                             int64_t m0, int64_t n0, const NodeCols &ncl, int cnt, float *red) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
+    const int64_t brow[2] = {col_slot(ncl, n0 + r, cnt), col_slot(ncl, n0 + 16 + r, cnt)};
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
@@ -372,7 +410,7 @@ __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, con
             ah[st][a] = *reinterpret_cast<const bf16x8 *>(Ahi + o);
             al[st][a] = *reinterpret_cast<const bf16x8 *>(Alo + o);
         }
-        for (int b = 0; b < 2; ++b) load8f(B + (n0 + 16 * b + r) * ldb + 32 * c + 8 * q, bv[st][b]);
+        for (int b = 0; b < 2; ++b) load8f(B + brow[b] * ldb + 32 * c + 8 * q, bv[st][b]);
     };
     auto compute = [&](int st) {
         bf16x8 bh[2], bl[2];
@@ -409,13 +447,17 @@ constexpr int kWavesBf16 = 8;
 __global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *__restrict__ Ahi,
                                                                   const __bf16 *__restrict__ Alo, int64_t lda,
                                                                   const float *__restrict__ B, int64_t ldb,
-                                                                  float *__restrict__ U, int64_t ldu, int64_t kdim) {
+                                                                  float *__restrict__ U, int64_t ldu, int64_t kdim,
+                                                                  NodeCols ncl) {
     __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, red);
+    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
+    if (n0 >= cnt) return;
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, ncl, cnt, red);
     for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
         int n = idx >> 5, m = idx & 31;
-        U[(n0 + n) * ldu + m0 + m] = sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
+        if (n0 + n >= cnt) continue;
+        U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
     }
 }
 
@@ -425,19 +467,22 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
     int64_t ldu, int64_t kdim, float *__restrict__ W, float *__restrict__ beta, float *__restrict__ V,
     float *__restrict__ Bst, const uint8_t *__restrict__ codes, const float *__restrict__ c,
     const int *__restrict__ active, DevParams<float> q, int64_t ldp, int store_b, double *__restrict__ gpart,
-    GateArgs ga) {
+    GateArgs ga, NodeCols ncl) {
     __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, red);
+    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
+    if (n0 >= cnt) return;
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
     const bool est = gpart != nullptr;
     for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
         const int n = idx >> 5, m = idx & 31;
-        const int64_t node = n0 + n, j = m0 + m;
+        const bool live = n0 + n < cnt;
+        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
         double e[5] = {0, 0, 0, 0, 0};
-        if (active[node])
+        if (live && active[node])
             admm_update<float>(sum_waves<float, 32, 32, kWavesBf16>(red, n, m), node * ldp + j, j, W, beta, V, Bst,
                                codes, c, q, store_b, est, ga, e);
-        if (est) store_estimate<32>(e, m, node, gpart);
+        if (est) store_estimate<32>(e, m, live ? node : -1, gpart);
     }
 }
 
@@ -450,41 +495,34 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Number of nodes of the last gap estimate that may pass the check (nullptr:
-// no estimate, the check always runs).
-__device__ __forceinline__ bool check_skipped(const int *gate) { return gate && gate[0] == 0; }
-
 // First kernel of the gap check: with the original X (row-major copy, FP64)
 // and the node iterates b (grid z = 0) and beta (z = 1) of type T, forms the
-// 32 x 32 tile of X b^T (X beta^T) and, in the epilogue, r = y - X b (stored in
-// R) with the per-(node, row tile) sums of ||r||^2, y^T r, |y|^T |r| (z = 0) or
-// ||y - X beta||^2 (z = 1) in rpart[(node * ntr + tile) * 4 + {0, 1, 2 | 3}].
-// Also clears the two result counters (mode 0) for the finalize kernel.
+// 32 x 32 tile of X b^T (X beta^T) for the nodes of the check list and, in the
+// epilogue, r = y - X b (stored in R) with the per-(node, row tile) sums of
+// ||r||^2, y^T r, |y|^T |r| (z = 0) or ||y - X beta||^2 (z = 1) in
+// rpart[(node * ntr + tile) * 4 + {0, 1, 2 | 3}].
 template <class T>
 __global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR, int64_t ldx,
                                                   const T *__restrict__ B, const T *__restrict__ beta, int64_t ldb,
                                                   int64_t kdim, const double *__restrict__ y, double *__restrict__ R,
-                                                  int64_t np, double *__restrict__ rpart, int *__restrict__ counter,
-                                                  const int *__restrict__ gate) {
+                                                  int64_t np, double *__restrict__ rpart, NodeCols ncl) {
     constexpr int WAVES = 8;
     __shared__ double red[WAVES * Red<32, 32>::WS];
-    if (check_skipped(gate)) return;
-    if (counter && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
-        counter[0] = 0;
-        counter[1] = 0;
-    }
     const bool with_b = blockIdx.z == 0;
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    nt_tile<double, T, double, 2, 2, WAVES>(XR, ldx, with_b ? B : beta, ldb, kdim, m0, n0, red);
+    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
+    if (n0 >= cnt) return;
+    nt_tile<double, T, double, 2, 2, WAVES>(XR, ldx, with_b ? B : beta, ldb, kdim, m0, n0, ncl, cnt, red);
     const int64_t ntr = gridDim.x;
     for (int idx = threadIdx.x; idx < 1024; idx += 64 * WAVES) {
         const int n = idx >> 5, m = idx & 31;
-        const int64_t node = n0 + n, i = m0 + m;
+        const bool live = n0 + n < cnt;
+        const int64_t node = col_slot(ncl, n0 + n, cnt), i = m0 + m;
         const double yi = y[i];
         const double rv = yi - sum_waves<double, 32, 32, WAVES>(red, n, m);
         double e0, e1 = 0.0, e2 = 0.0;
         if (with_b) {
-            R[node * np + i] = rv;
+            if (live) R[node * np + i] = rv;
             e0 = rv * rv;
             e1 = yi * rv;
             e2 = fabs(yi) * fabs(rv);
@@ -496,7 +534,7 @@ __global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR,
             e1 += __shfl_xor(e1, off);
             e2 += __shfl_xor(e2, off);
         }
-        if (m == 0) {
+        if (m == 0 && live) {
             double *d = rpart + (node * ntr + blockIdx.x) * 4;
             if (with_b) {
                 d[0] = e0;
@@ -525,22 +563,24 @@ __global__ __launch_bounds__(64 * kWavesDual) void k_dual_xtr(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ R, int64_t ldr, int64_t kdim,
     const uint8_t *__restrict__ codes, const T *__restrict__ beta, const double *__restrict__ colnrm,
     const double *__restrict__ rpart, int64_t ntr, const int *__restrict__ active, double *__restrict__ part,
-    int64_t ldp, DualArgs da, const int *__restrict__ gate) {
+    int64_t ldp, DualArgs da, NodeCols ncl) {
     __shared__ double red[kWavesDual * Red<32, 32>::WS];
-    if (check_skipped(gate)) return;
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    nt_tile<double, double, double, 2, 2, kWavesDual>(A, lda, R, ldr, kdim, m0, n0, red);
+    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
+    if (n0 >= cnt) return;
+    nt_tile<double, double, double, 2, 2, kWavesDual>(A, lda, R, ldr, kdim, m0, n0, ncl, cnt, red);
     // 16 threads per node: thread t takes node t / 16, coordinates 2 (t % 16) and
     // 2 (t % 16) + 1 of the tile
     const int n = tid >> 4, jl = (tid & 15) * 2;
-    const int64_t node = n0 + n;
+    const bool live = n0 + n < cnt;
+    const int64_t node = col_slot(ncl, n0 + n, cnt);
     // ||r||^2 of the node from the row-tile sums of the first check kernel
     double rr = 0.0;
     for (int64_t t = tid & 15; t < ntr; t += 16) rr += rpart[(node * ntr + t) * 4];
     for (int off = 1; off < 16; off <<= 1) rr += __shfl_xor(rr, off);
     double snu = 0, sanu = 0, spsi = 0;
-    const bool act = active[node] != 0;
+    const bool act = live && active[node] != 0;
     if (act) {
         const double nr = sqrt(rr);
         for (int e = 0; e < 2; ++e) {
@@ -576,28 +616,34 @@ struct FinArgs {
     int mode;  // mode 0: solve (gap test), 1: bound only
 };
 
-// One wave per node: LB = (q - sum nu+) - margin (Prop. 1 plus the rounding
-// margin) and, in mode 0, P(beta) = 1/2 ||y - X beta||^2 + sum psi and the gap
-// test; the nodes still active (and those above switch_tol) are added to the
-// two counters with integer atomics (exact in any order).  When the gap
-// estimate skipped the check, every active node stays active: both counters
-// become the active count gate[1].
+// One wave per node slot: LB = (q - sum nu+) - margin (Prop. 1 plus the
+// rounding margin) and, in mode 0, P(beta) = 1/2 ||y - X beta||^2 + sum psi
+// and the gap test, for the active nodes that were checked (all of them, or
+// those the gap estimate flagged in needs).  In mode 0 every node that stays
+// active is appended to the next active list (nlist, *ncount) and counted in
+// counter[0] (and in counter[1] when above switch_tol); nodes the estimate
+// left out are above twice the tolerance, so they count in both.  Appends and
+// counts are integer atomics: the counts are exact in any order, and the order
+// of the list does not change any node's arithmetic.
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpart, const double *__restrict__ part,
                                                   int *__restrict__ active, int *__restrict__ status,
                                                   int *__restrict__ iters, double *__restrict__ lb,
                                                   double *__restrict__ primal, int *__restrict__ counter,
+                                                  int *__restrict__ nlist, int *__restrict__ ncount,
                                                   const int *__restrict__ sweep_no, FinArgs fa,
-                                                  const int *__restrict__ gate) {
+                                                  const int *__restrict__ needs) {
     const int lane = threadIdx.x & 63;
-    if (check_skipped(gate)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            counter[0] = gate[1];
-            counter[1] = gate[1];
-        }
-        return;
-    }
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= fa.K || !active[k]) return;
+    auto keep = [&](bool above) {
+        nlist[atomicAdd(ncount, 1)] = (int)k;
+        atomicAdd(&counter[0], 1);
+        if (above) atomicAdd(&counter[1], 1);
+    };
+    if (needs && !needs[k]) {
+        if (lane == 0 && fa.mode == 0) keep(true);
+        return;
+    }
     const double u = 1.1102230246251565e-16;
     double rr = 0, yr = 0, ayr = 0, rbrb = 0, snu = 0, sanu = 0, spsi = 0;
     const double *rk = rpart + k * fa.ntr * 4;
@@ -636,9 +682,16 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpa
         active[k] = 0;
     } else {
         status[k] = 1;
-        atomicAdd(&counter[0], 1);
-        if ((P - LB) / den > fa.switch_tol) atomicAdd(&counter[1], 1);
+        keep((P - LB) / den > fa.switch_tol);
     }
+}
+
+// The next active list becomes the current one (one workgroup).
+__global__ __launch_bounds__(256) void k_list_commit(const int *__restrict__ nlist, const int *__restrict__ ncount,
+                                                     int *__restrict__ list, int *__restrict__ count) {
+    const int n = *ncount;
+    for (int i = threadIdx.x; i < n; i += 256) list[i] = nlist[i];
+    if (threadIdx.x == 0) *count = n;
 }
 
 struct GateFin {
@@ -651,9 +704,10 @@ struct GateFin {
 // P_low - D > 2 tol_eff P_low: then its P(beta) is at least P_low and its
 // rigorous LB at most D (up to rounding), so the check's relative gap
 // 1 - LB / P(beta) is at least 1 - D / P_low and the check cannot accept it.
-// gate[0] counts the nodes that need the check, gate[1] the active nodes (both
-// cleared at the start of the block; integer atomics, exact in any order).
+// needs[k] flags the node; the nodes that need the check are appended to the
+// check list (clist, gate[0]) with integer atomics.
 __global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, const int *__restrict__ active,
+                                              int *__restrict__ needs, int *__restrict__ clist,
                                               int *__restrict__ gate, GateFin gf) {
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -668,8 +722,8 @@ __global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, 
         const double D = -0.5 * rr + (gf.yy - e[0]) - e[2];
         const double Pl = 0.5 * rr - e[3] + e[4];
         const bool far = Pl > 0.0 && (Pl - D) > 2.0 * gf.tol_eff * Pl;
-        if (!far) atomicAdd(&gate[0], 1);
-        atomicAdd(&gate[1], 1);
+        needs[k] = far ? 0 : 1;
+        if (!far) clist[atomicAdd(&gate[0], 1)] = (int)k;
     }
 }
 
@@ -749,13 +803,13 @@ bool shape_fits(int v, int64_t Kp) { return Kp % (16 * kTileBN[v]) == 0; }
 
 template <class TA, class TB, class TC>
 void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int64_t ldb, TC *U, int64_t ldu,
-               int64_t rows, int64_t Kp, int64_t kdim) {
+               int64_t rows, int64_t Kp, int64_t kdim, NodeCols ncl = NodeCols{nullptr, nullptr}) {
     if (sizeof(TC) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(rows / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XW(PBM, PBN, PW) \
-    hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, PBM, PBN, PW>), g, b, 0, s, A, lda, B, ldb, U, ldu, kdim)
+    hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, PBM, PBN, PW>), g, b, 0, s, A, lda, B, ldb, U, ldu, kdim, ncl)
     switch (v) {
         case 0: L0L2_XW(2, 2, 4); break;
         case 1: L0L2_XW(2, 2, 8); break;
@@ -773,14 +827,14 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
 template <class T>
 void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes,
                 const int *active, const DevParams<T> &q, int store_b, double *gpart = nullptr,
-                const GateArgs &ga = GateArgs{}) {
+                const GateArgs &ga = GateArgs{}, NodeCols ncl = NodeCols{nullptr, nullptr}) {
     if (sizeof(T) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XTU(PBM, PBN, PW)                                                                                  \
     hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, \
-                       sw.B, codes, sw.c, active, q, pp, store_b, gpart, ga)
+                       sw.B, codes, sw.c, active, q, pp, store_b, gpart, ga, ncl)
     switch (v) {
         case 0: L0L2_XTU(2, 2, 4); break;
         case 1: L0L2_XTU(2, 2, 8); break;
@@ -798,13 +852,13 @@ void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp
 // The anchored sweep's contraction over n (FP32 operands, FP64 update).
 void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<double> &s64, const double *Za,
                      const double *Wa, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes, const int *active,
-                     const DevParams<double> &q, int store_b, double *gpart, const GateArgs &ga) {
+                     const DevParams<double> &q, int store_b, double *gpart, const GateArgs &ga, NodeCols ncl) {
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XTUA(PBM, PBN, PW)                                                                                \
     hipLaunchKernelGGL((k_admm_xtu_anch<PBM, PBN, PW>), g, b, 0, s, s32.Xh, np, s32.U, np, np, Za, Wa, s64.W,     \
-                       s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, pp, store_b, gpart, ga)
+                       s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, pp, store_b, gpart, ga, ncl)
     switch (v) {
         case 0: L0L2_XTUA(2, 2, 4); break;
         case 1: L0L2_XTUA(2, 2, 8); break;
@@ -893,6 +947,9 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
 // ---------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------
+// The active list of the current batch.
+NodeCols active_cols(l0l2_ctx *ctx) { return NodeCols{ctx->ws.list.as<int>(), ctx->ws.count.as<int>()}; }
+
 GateArgs gate_args(const Instance &in) {
     GateArgs g;
     g.l0 = in.mp.l0; g.l2 = in.mp.l2; g.M = in.mp.M; g.s = in.mp.s;
@@ -912,11 +969,11 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
     DevParams<T> q = dev_params<T>(in.mp);
     const TileChoice &tc = tile_choice<T>(ctx, sw, Kp);
     prof_begin(ctx, prof_xw<T>());
-    launch_xw<T, T, T>(tc.xw, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp);
+    launch_xw<T, T, T>(tc.xw, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp, active_cols(ctx));
     prof_end(ctx, prof_xw<T>(), active);
     prof_begin(ctx, prof_xtu<T>());
     launch_xtu<T>(tc.xtu, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), ws.active.as<int>(), q, store_b ? 1 : 0,
-                  gate ? ws.gpart.as<double>() : nullptr, gate_args(in));
+                  gate ? ws.gpart.as<double>() : nullptr, gate_args(in), active_cols(ctx));
     prof_end(ctx, prof_xtu<T>(), active);
     HIPCHK(hipGetLastError());
 }
@@ -933,12 +990,12 @@ void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool sto
     DevParams<float> q = dev_params<float>(in.mp);
     prof_begin(ctx, PROF_GEMM_XW_BF16);
     hipLaunchKernelGGL(k_gemm_xw_bf16, g1, dim3(64 * kWavesBf16), 0, s, in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), pp, sw.W, pp,
-                       sw.U, np, pp);
+                       sw.U, np, pp, active_cols(ctx));
     prof_end(ctx, PROF_GEMM_XW_BF16, active);
     prof_begin(ctx, PROF_ADMM_XTU_BF16);
     hipLaunchKernelGGL(k_admm_xtu_bf16, g2, dim3(64 * kWavesBf16), 0, s, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(), np, sw.U, np,
                        np, sw.W, sw.beta, sw.V, sw.B, ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp,
-                       store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, gate_args(in));
+                       store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, gate_args(in), active_cols(ctx));
     prof_end(ctx, PROF_ADMM_XTU_BF16, active);
     HIPCHK(hipGetLastError());
 }
@@ -955,8 +1012,10 @@ void anchor_start(l0l2_ctx *ctx, int64_t Kp) {
     prof_begin(ctx, PROF_ANCHOR);
     hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * pp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
                        Kp * pp);
-    launch_xw<double, double, double>(tc.xw, s, s64.XhR, pp, ws.Wa.as<double>(), pp, s64.U, np, np, Kp, pp);
-    launch_xw<double, double, double>(tc.xw, s, s64.Xh, np, s64.U, np, ws.Za.as<double>(), pp, pp, Kp, np);
+    launch_xw<double, double, double>(tc.xw, s, s64.XhR, pp, ws.Wa.as<double>(), pp, s64.U, np, np, Kp, pp,
+                                      active_cols(ctx));
+    launch_xw<double, double, double>(tc.xw, s, s64.Xh, np, s64.U, np, ws.Za.as<double>(), pp, pp, Kp, np,
+                                      active_cols(ctx));
     prof_end(ctx, PROF_ANCHOR);
     HIPCHK(hipGetLastError());
 }
@@ -971,12 +1030,12 @@ void sweep_once_anch(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
     Sweep<double> s64 = sweep64(ctx);
     const TileChoice &tc = tile_choice<float>(ctx, s32, Kp);
     prof_begin(ctx, PROF_GEMM_XW_F32);
-    launch_xw<float, float, float>(tc.xw, s, s32.XhR, pp, s32.W, pp, s32.U, np, np, Kp, pp);
+    launch_xw<float, float, float>(tc.xw, s, s32.XhR, pp, s32.W, pp, s32.U, np, np, Kp, pp, active_cols(ctx));
     prof_end(ctx, PROF_GEMM_XW_F32, active);
     prof_begin(ctx, PROF_ADMM_XTU_F32);
     launch_xtu_anch(tc.xtu, s, s32, s64, ws.Za.as<double>(), ws.Wa.as<double>(), np, pp, Kp,
                     ws.codes.as<uint8_t>(), ws.active.as<int>(), dev_params<double>(in.mp), store_b ? 1 : 0,
-                    gate ? ws.gpart.as<double>() : nullptr, gate_args(in));
+                    gate ? ws.gpart.as<double>() : nullptr, gate_args(in), active_cols(ctx));
     prof_end(ctx, PROF_ADMM_XTU_F32, active);
     HIPCHK(hipGetLastError());
 }
@@ -993,26 +1052,29 @@ DualArgs dual_args(const Instance &in) {
 }
 
 // FP64 check at (B, beta) of type T: fills ws.lb / primal / status / active and
-// the two counters (active nodes; active nodes above switch_tol).  gate: the
-// counters of the last gap estimate (nullptr: the check always runs).
+// the two counters (active nodes; active nodes above switch_tol), and in mode 0
+// rebuilds the active list.  gated: only the nodes of the last gap estimate's
+// check list are evaluated (the others stay active); otherwise every active
+// node (mode 0) or every node of the padded batch (mode 1, bound only).
 template <class T>
 void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol, double switch_tol, int mode,
-                const int *gate = nullptr) {
+                bool gated = false) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     const int64_t np = in.np, pp = in.pp;
     const int64_t ntr = np / 32;
+    NodeCols ncl{nullptr, nullptr};
+    if (mode == 0) ncl = gated ? NodeCols{ws.clist.as<int>(), ws.gate.as<int>()} : active_cols(ctx);
     dim3 g1((unsigned)ntr, (unsigned)(Kp / 32), mode == 0 ? 2u : 1u);
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     prof_begin(ctx, PROF_CHECK);
     hipLaunchKernelGGL((k_check_xr<T>), g1, dim3(512), 0, s, in.X64R.as<double>(), pp, B, beta, pp, pp,
-                       in.y64.as<double>(), ws.R.as<double>(), np, ws.rpart.as<double>(),
-                       mode == 0 ? ws.counter.as<int>() : nullptr, gate);
+                       in.y64.as<double>(), ws.R.as<double>(), np, ws.rpart.as<double>(), ncl);
     DualArgs da = dual_args(in);
     hipLaunchKernelGGL((k_dual_xtr<T>), g2, dim3(64 * kWavesDual), 0, s, in.X64.as<double>(), np, ws.R.as<double>(),
                        np, np, ws.codes.as<uint8_t>(), mode == 0 ? beta : B, in.colnrm.as<double>(),
-                       ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), pp, da, gate);
+                       ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), pp, da, ncl);
     FinArgs fa;
     const double u = 1.1102230246251565e-16;
     fa.gamma_n2 = ((double)in.n + 2.0) * u / (1.0 - ((double)in.n + 2.0) * u);
@@ -1025,8 +1087,11 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     fa.mode = mode;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.rpart.as<double>(),
                        ws.part.as<double>(), ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(),
-                       ws.lb.as<double>(), ws.primal.as<double>(), ws.counter.as<int>(), ws.sweep_no.as<int>(), fa,
-                       gate);
+                       ws.lb.as<double>(), ws.primal.as<double>(), ws.counter.as<int>(), ws.nlist.as<int>(),
+                       ws.ncount.as<int>(), ws.sweep_no.as<int>(), fa, gated ? ws.needs.as<int>() : nullptr);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_list_commit, dim3(1), dim3(256), 0, s, ws.nlist.as<int>(), ws.ncount.as<int>(),
+                           ws.list.as<int>(), ws.count.as<int>());
     prof_end(ctx, PROF_CHECK);
     HIPCHK(hipGetLastError());
 }
@@ -1037,7 +1102,8 @@ void init_batch(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t K, int64_t Kp) {
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
-                       ws.status.as<int>(), ws.iters.as<int>(), K, Kp, ws.sweep_no.as<int>());
+                       ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(), ws.count.as<int>(), K, Kp,
+                       ws.sweep_no.as<int>());
     hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta, sw.V,
                        sw.W, sw.c, (T)in.mp.rho, in.pp, Kp * in.pp);
     HIPCHK(hipGetLastError());
@@ -1064,7 +1130,8 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
-    hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>());
+    hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>(),
+                       ws.ncount.as<int>(), ws.counter.as<int>());
     if (kind == SK_ANCH) anchor_start(ctx, Kp);
     for (int t = 1; t <= n; ++t) {
         const bool last = t == n, gate = last && !force;
@@ -1073,7 +1140,6 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         else if (kind == SK_ANCH) sweep_once_anch(ctx, Kp, last, active, gate);
         else sweep_once<float>(ctx, sweep32(ctx), Kp, last, active, gate);
     }
-    const int *skip = nullptr;
     if (!force) {
         int rows = 32;
         if (kind == SK_F64) rows = 16 * kTileBM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
@@ -1082,17 +1148,16 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         GateFin gf{in.yy, full ? tol : switch_tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
-                           ws.active.as<int>(), ws.gate.as<int>(), gf);
+                           ws.active.as<int>(), ws.needs.as<int>(), ws.clist.as<int>(), ws.gate.as<int>(), gf);
         prof_end(ctx, PROF_CHECK);
         HIPCHK(hipGetLastError());
-        skip = ws.gate.as<int>();
     }
     if (kind == SK_F64 || kind == SK_ANCH) {
         Sweep<double> sw = sweep64(ctx);
-        check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, skip);
+        check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, !force);
     } else {
         Sweep<float> sw = sweep32(ctx);
-        check_once<float>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, skip);
+        check_once<float>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, !force);
     }
     HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
 }
@@ -1235,7 +1300,13 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.rpart.ensure(8 * 4 * Kp * (np / 32));
     ws.part.ensure(8 * 3 * Kp * (pp / 32));
     ws.gpart.ensure(8 * 5 * Kp * (pp / 16));
-    ws.gate.ensure(2 * sizeof(int));
+    ws.gate.ensure(sizeof(int));
+    ws.needs.ensure(4 * Kp);
+    ws.clist.ensure(4 * Kp);
+    ws.list.ensure(4 * Kp);
+    ws.nlist.ensure(4 * Kp);
+    ws.count.ensure(sizeof(int));
+    ws.ncount.ensure(sizeof(int));
     ws.active.ensure(4 * Kp);
     ws.iters.ensure(4 * Kp);
     ws.status.ensure(4 * Kp);
@@ -1332,8 +1403,8 @@ void run_dual_bound(l0l2_ctx *ctx, int K, const void *) {
     const int64_t Kp = round_up(K, kPadNodes);
     Workspace &ws = ctx->ws;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, ctx->stream,
-                       ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), (int64_t)K, Kp,
-                       ws.sweep_no.as<int>());
+                       ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(),
+                       ws.count.as<int>(), (int64_t)K, Kp, ws.sweep_no.as<int>());
     if (ctx->inst.prec == L0L2_FP64)
         check_once<double>(ctx, ws.B.as<double>(), ws.B.as<double>(), Kp, 0.0, 0.0, 1);
     else

@@ -100,7 +100,11 @@ struct Workspace {
     DevBuf rpart;                  // Kp x (np/32) x 4 doubles: row-tile sums of the gap check
     DevBuf part;                   // Kp x (pp/32) x 3 doubles
     DevBuf gpart;                  // Kp x (pp/16) x 5 doubles: per-tile sums of the gap estimate
-    DevBuf gate;                   // int32 x 2: nodes that need the exact check, active nodes
+    DevBuf gate;                   // int32: length of the check list
+    DevBuf needs;                  // Kp int32: the gap estimate leaves the node to the exact check
+    DevBuf clist;                  // Kp int32: node slots the exact check evaluates
+    DevBuf list, count;            // active node slots of the batch and their number
+    DevBuf nlist, ncount;          // the active list being rebuilt by the check
     DevBuf active, iters, status;  // Kp int32
     DevBuf lb, primal;             // Kp doubles
     DevBuf counter;                // int32 x 2: active nodes, active nodes above the switch tolerance
