@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="Poisson stream of independent instances through the server: p50/p99 TTCO")
     ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-concurrent", type=int, default=8, help="instances in flight at once")
+    ap.add_argument("--highdim", action="store_true",
+                    help="n = 1000, p = 50000 node batches of 256 and 1024: FP32 and BF16 split vs FP64")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="first dispatch one device copy of 256 MiB, the reference for HBM counter scaling")
     return ap.parse_args()
@@ -162,26 +165,25 @@ def run_path(path, steps, warmup):
     return dt, its, prof
 
 
-def batching_main(args):
-    """Node-batch throughput at n = p = 5000 for K in {512, 1024, 2048, 4096}: each node keeps
-    f ~ U{50..p} free coordinates, |F1| ~ U{0..20}, the rest fixed to zero, warm-started from
-    the root.  BF16 split sweeps (then FP64) against FP32 sweeps (then FP64)."""
+def node_batch_runs(inst, Ks, precs, workload, label):
+    """Node-batch throughput on one instance: each node keeps f ~ U{50..p} free coordinates,
+    |F1| ~ U{0..20}, the rest fixed to zero, warm-started from the root; one batch per K and
+    precision, timed after a warm-up solve of the same batch (tiles and graphs settled)."""
     import torch
     from paper_2602_04551_amd import datagen
     from paper_2602_04551_amd.binding import Context
-    inst = datagen.config_instance("C3", seed=0)
     n, p = inst.n, inst.p
-    out = {"metric": "node relaxations/s (batching workload)", "unit": "node relaxations/s",
-           "config": {"workload": "n=p=5000 Toeplitz rho=0.3 k=20 SNR=3 lambda0=0.005 lambda2=0.01, node "
-                                  "batches with free sets U{50..p}, |F1| U{0..20}", "node_tol": 1e-6}, "runs": {}}
-    for prec in ("bf16", "fp32"):
+    out = {"metric": f"node relaxations/s ({label} workload)", "unit": "node relaxations/s",
+           "config": {"workload": workload, "node_tol": 1e-6}, "runs": {}}
+    for prec in precs:
         ctx = Context(0)
         t0 = time.perf_counter()
         ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
         torch.cuda.synchronize()
         sd = time.perf_counter() - t0
+        print(json.dumps({"set_data": prec, "seconds": round(sd, 3)}), file=sys.stderr, flush=True)
         root = ctx.solve_node_batch(np.zeros((1, p), np.uint8), tol_node=1e-6, max_iter=10000)
-        for K in (512, 1024, 2048, 4096):
+        for K in Ks:
             codes = torch.from_numpy(datagen.node_batch_codes(p, K, seed=K)).to(ctx.torch_device)
             b0 = root["beta"].expand(K, p).contiguous()
             v0 = root["v"].expand(K, p).contiguous()
@@ -206,6 +208,25 @@ def batching_main(args):
     print(json.dumps(out), flush=True)
 
 
+def batching_main(args):
+    """n = p = 5000 batches, K in {512, 1024, 2048, 4096}: BF16 split sweeps against FP32."""
+    from paper_2602_04551_amd import datagen
+    inst = datagen.config_instance("C3", seed=0)
+    node_batch_runs(inst, (512, 1024, 2048, 4096), ("bf16", "fp32"),
+                    "n=p=5000 Toeplitz rho=0.3 k=20 SNR=3 lambda0=0.005 lambda2=0.01, node batches with free sets "
+                    "U{50..p}, |F1| U{0..20}", "batching")
+
+
+def highdim_main(args):
+    """n = 1000, p = 50000 (constant correlation 0.2), K in {256, 1024}: FP32 and BF16 split
+    sweeps against the FP64 path."""
+    from paper_2602_04551_amd import datagen
+    inst = datagen.config_instance("C5", seed=0)
+    node_batch_runs(inst, (256, 1024), ("fp32", "bf16", "fp64"),
+                    "n=1000 p=50000 constant correlation 0.2 k=25 SNR=3 lambda0=0.002 lambda2=0.005, node batches "
+                    "with free sets U{50..p}, |F1| U{0..20}", "high-dimensional")
+
+
 def serve_main(args):
     """A Poisson stream of independent instances (n ~ U{500..2000}, p ~ U{1000..4000}, Toeplitz
     rho ~ U[0, 0.7], k ~ U{5..12}, SNR ~ U[2, 10], lambda0 = 0.005, lambda2 = 0.01) through the
@@ -222,7 +243,7 @@ def serve_main(args):
                                           k=int(rng.integers(5, 13)), snr=float(rng.uniform(2, 10)),
                                           lambda0=0.005, lambda2=0.01, seed=1000 + i))
     gaps = rng.exponential(0.05, size=len(reqs))
-    srv = Server(0, hbm_budget_bytes=0, max_concurrent=4, K=64, tol_node=1e-6, max_iter=2000,
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=args.serve_concurrent, K=64, tol_node=1e-6, max_iter=2000,
                  max_iter_root=10000, time_limit_s=30.0)
     t0 = time.perf_counter()
     ids = []
@@ -240,7 +261,7 @@ def serve_main(args):
            "ttco_p50": round(float(np.percentile(tt, 50)), 4), "ttco_p99": round(float(np.percentile(tt, 99)), 4),
            "admit_wait_p50": round(float(np.percentile(wait, 50)), 4),
            "throughput_requests_per_s": round(len(res) / wall, 3), "node_relaxations_per_s": round(nodes / wall, 1),
-           "wall_s": round(wall, 3), "mean_interarrival_s": 0.05, "max_concurrent": 4,
+           "wall_s": round(wall, 3), "mean_interarrival_s": 0.05, "max_concurrent": args.serve_concurrent,
            "per_request": [{"n": i.n, "p": i.p, "ttco": round(float(t), 4), "nodes": r["nodes_solved"],
                             "status": r["status"]} for i, t, r in zip(reqs, tt, res)]}
     print(json.dumps(out), flush=True)
@@ -248,11 +269,13 @@ def serve_main(args):
 
 def main():
     args = parse()
-    if args.batching or args.serve:
+    if args.batching or args.serve or args.highdim:
         if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
             print("bench.py: this build runs on exactly one GPU", file=sys.stderr)
             sys.exit(2)
-        return batching_main(args) if args.batching else serve_main(args)
+        if args.batching:
+            return batching_main(args)
+        return highdim_main(args) if args.highdim else serve_main(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)
