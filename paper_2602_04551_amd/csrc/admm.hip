@@ -621,17 +621,17 @@ struct FinArgs {
 // and the gap test, for the active nodes that were checked (all of them, or
 // those the gap estimate flagged in needs).  In mode 0 every node that stays
 // active is appended to the next active list (nlist, *ncount) and counted in
-// counter[0] (and in counter[1] when above switch_tol); nodes the estimate
-// left out are above twice the tolerance, so they count in both.  Appends and
-// counts are integer atomics: the counts are exact in any order, and the order
-// of the list does not change any node's arithmetic.
+// counter[0], and in counter[1] when its gap is above switch_tol (the exact
+// gap, or the estimate gest, a lower bound of it, for the nodes left out of
+// the check).  Appends and counts are integer atomics: the counts are exact in
+// any order, and the order of the list does not change any node's arithmetic.
 __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpart, const double *__restrict__ part,
                                                   int *__restrict__ active, int *__restrict__ status,
                                                   int *__restrict__ iters, double *__restrict__ lb,
                                                   double *__restrict__ primal, int *__restrict__ counter,
                                                   int *__restrict__ nlist, int *__restrict__ ncount,
                                                   const int *__restrict__ sweep_no, FinArgs fa,
-                                                  const int *__restrict__ needs) {
+                                                  const int *__restrict__ needs, const double *__restrict__ gest) {
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= fa.K || !active[k]) return;
@@ -641,7 +641,7 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpa
         if (above) atomicAdd(&counter[1], 1);
     };
     if (needs && !needs[k]) {
-        if (lane == 0 && fa.mode == 0) keep(true);
+        if (lane == 0 && fa.mode == 0) keep(gest[k] > fa.switch_tol);
         return;
     }
     const double u = 1.1102230246251565e-16;
@@ -695,20 +695,20 @@ __global__ __launch_bounds__(256) void k_list_commit(const int *__restrict__ nli
 }
 
 struct GateFin {
-    double yy, tol_eff;
+    double yy, tol;
     int64_t K, ntile;
 };
 
 // Gap estimate per node (one wave each) from the per-tile sums of the last
-// sweep's epilogue.  A node needs the exact check unless P_low > 0 and
-// P_low - D > 2 tol_eff P_low: then its P(beta) is at least P_low and its
-// rigorous LB at most D (up to rounding), so the check's relative gap
-// 1 - LB / P(beta) is at least 1 - D / P_low and the check cannot accept it.
-// needs[k] flags the node; the nodes that need the check are appended to the
-// check list (clist, gate[0]) with integer atomics.
+// sweep's epilogue: gest[k] = 1 - D / P_low.  A node needs the exact check
+// unless P_low > 0 and P_low - D > 2 tol P_low: then its P(beta) is at least
+// P_low and its rigorous LB at most D (up to rounding), so the check's
+// relative gap 1 - LB / P(beta) is at least gest[k] and the check cannot accept
+// it.  needs[k] flags the node; the nodes that need the check are appended to
+// the check list (clist, gate[0]) with integer atomics.
 __global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, const int *__restrict__ active,
-                                              int *__restrict__ needs, int *__restrict__ clist,
-                                              int *__restrict__ gate, GateFin gf) {
+                                              int *__restrict__ needs, double *__restrict__ gest,
+                                              int *__restrict__ clist, int *__restrict__ gate, GateFin gf) {
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= gf.K || !active[k]) return;
@@ -721,8 +721,9 @@ __global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, 
         const double rr = gf.yy - 2.0 * e[0] + e[1];
         const double D = -0.5 * rr + (gf.yy - e[0]) - e[2];
         const double Pl = 0.5 * rr - e[3] + e[4];
-        const bool far = Pl > 0.0 && (Pl - D) > 2.0 * gf.tol_eff * Pl;
+        const bool far = Pl > 0.0 && (Pl - D) > 2.0 * gf.tol * Pl;
         needs[k] = far ? 0 : 1;
+        gest[k] = Pl > 0.0 ? (Pl - D) / Pl : INFINITY;
         if (!far) clist[atomicAdd(&gate[0], 1)] = (int)k;
     }
 }
@@ -1088,7 +1089,8 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.rpart.as<double>(),
                        ws.part.as<double>(), ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(),
                        ws.lb.as<double>(), ws.primal.as<double>(), ws.counter.as<int>(), ws.nlist.as<int>(),
-                       ws.ncount.as<int>(), ws.sweep_no.as<int>(), fa, gated ? ws.needs.as<int>() : nullptr);
+                       ws.ncount.as<int>(), ws.sweep_no.as<int>(), fa, gated ? ws.needs.as<int>() : nullptr,
+                       ws.gest.as<double>());
     if (mode == 0)
         hipLaunchKernelGGL(k_list_commit, dim3(1), dim3(256), 0, s, ws.nlist.as<int>(), ws.ncount.as<int>(),
                            ws.list.as<int>(), ws.count.as<int>());
@@ -1121,10 +1123,9 @@ enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2, SK_ANCH = 3 };
 
 // One block: `n` sweeps of the given kind, then the FP64 gap check and the
 // read-back of the two counters into pinned host memory.  Issued eagerly.
-// Unless force is set, the last sweep also forms the gap estimate and the check
-// kernels run only when some active node may pass it (tolerance tol for FP64
-// sweeps, switch_tol for reduced ones, where the host also reads the second
-// counter); a skipped check leaves every node active.
+// Unless force is set, the last sweep also forms the gap estimate and the exact
+// check evaluates only the nodes that may pass the tolerance; the others stay
+// active and are counted above switch_tol by their estimate.
 void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
                  bool force) {
     Instance &in = ctx->inst;
@@ -1144,11 +1145,11 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         int rows = 32;
         if (kind == SK_F64) rows = 16 * kTileBM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
         else if (kind == SK_F32 || kind == SK_ANCH) rows = 16 * kTileBM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
-        const bool full = kind == SK_F64 || kind == SK_ANCH;
-        GateFin gf{in.yy, full ? tol : switch_tol, Kp, in.pp / rows};
+        GateFin gf{in.yy, tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
-                           ws.active.as<int>(), ws.needs.as<int>(), ws.clist.as<int>(), ws.gate.as<int>(), gf);
+                           ws.active.as<int>(), ws.needs.as<int>(), ws.gest.as<double>(), ws.clist.as<int>(),
+                           ws.gate.as<int>(), gf);
         prof_end(ctx, PROF_CHECK);
         HIPCHK(hipGetLastError());
     }
@@ -1302,6 +1303,7 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.gpart.ensure(8 * 5 * Kp * (pp / 16));
     ws.gate.ensure(sizeof(int));
     ws.needs.ensure(4 * Kp);
+    ws.gest.ensure(8 * Kp);
     ws.clist.ensure(4 * Kp);
     ws.list.ensure(4 * Kp);
     ws.nlist.ensure(4 * Kp);

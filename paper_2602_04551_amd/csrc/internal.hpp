@@ -102,6 +102,7 @@ struct Workspace {
     DevBuf gpart;                  // Kp x (pp/16) x 5 doubles: per-tile sums of the gap estimate
     DevBuf gate;                   // int32: length of the check list
     DevBuf needs;                  // Kp int32: the gap estimate leaves the node to the exact check
+    DevBuf gest;                   // Kp FP64: the gap estimate (a lower bound of the exact relative gap)
     DevBuf clist;                  // Kp int32: node slots the exact check evaluates
     DevBuf list, count;            // active node slots of the batch and their number
     DevBuf nlist, ncount;          // the active list being rebuilt by the check
