@@ -89,7 +89,8 @@ class Path:
         c = self.ctx
         res = c.solve_node_batch(self.codes, self.beta0, self.v0, tol_node=1e-6, max_iter=2000, check_every=10)
         rb = c.round_branch(self.codes, res["beta"])
-        obj, _, _ = c.refine_incumbent(rb["support"], res["beta"])
+        obj, _, fit = c.refine_incumbent(rb["support"], res["beta"])
+        self.detail = (res["iters"], rb["support_size"], fit)
         lb = res["lb"].cpu().numpy()
         ub = obj.cpu().numpy()
         bj = rb["branch_j"].cpu().numpy()
@@ -144,6 +145,14 @@ def cpu_baseline(path, seconds):
                 sample=f"{done} of the {path.K} nodes of the timed batch (same codes and warm starts), "
                        f"split over {workers} single-threaded FP64 oracle processes, {busy:.1f} s of work "
                        f"each at most ({wall:.1f} s wall with process start-up)")
+
+
+def batch_detail(path):
+    """Per-node work of the last step: ADMM sweeps, support sizes and FISTA iterations."""
+    sw, ss, fi = (t.cpu().numpy().astype(np.float64) for t in path.detail)
+    return {"admm_sweeps_mean": round(float(sw.mean()), 2), "admm_sweeps_max": int(sw.max()),
+            "support_mean": round(float(ss.mean()), 2), "support_max": int(ss.max()),
+            "fista_iters_mean": round(float(fi.mean()), 2), "fista_iters_max": int(fi.max())}
 
 
 def roofline(prof, n, p):
@@ -341,6 +350,7 @@ def main():
                                "warm-started from the root"},
            "roofline": roof,
            "kernels": kernels,
+           "batch_detail": batch_detail(mixed),
            "set_data_s": {"fp32": round(mixed.set_data_s, 4)}}
     for prec, (path, dt_o, steps_o, roof_o, kernels_o) in others.items():
         out[prec + "_path"] = {"value": round(K * steps_o / dt_o, 2), "unit": "node relaxations/s",

@@ -72,6 +72,40 @@ __global__ void k_scatter(const T *__restrict__ beta, const T *__restrict__ V, i
     pool[(2 * s + 1) * pp + j] = V[k * pp + j];
 }
 
+// Per-node results of a batch, gathered into one array for a single read-back.
+struct NodeOut {
+    double lb, primal, obj;
+    int32_t iters, status, ssize, bj, zup, pad;
+};
+
+__global__ void k_pack_out(const double *__restrict__ lb, const double *__restrict__ primal,
+                           const double *__restrict__ obj, const int32_t *__restrict__ iters,
+                           const int32_t *__restrict__ status, const int32_t *__restrict__ ssize,
+                           const int32_t *__restrict__ bj, const int32_t *__restrict__ zup, NodeOut *__restrict__ out,
+                           int64_t K) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    out[k] = NodeOut{lb[k], primal[k], obj[k], iters[k], status[k], ssize[k], bj[k], zup[k], 0};
+}
+
+// Pinned host staging memory, grown on demand (only between synchronised batches).
+struct PinnedBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    void ensure(size_t n) {
+        if (n <= bytes) return;
+        if (ptr) (void)hipHostFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+        HIPCHK(hipHostMalloc(&ptr, n, hipHostMallocDefault));
+        bytes = n;
+    }
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+    ~PinnedBuf() {
+        if (ptr) (void)hipHostFree(ptr);
+    }
+};
+
 // Device pool of (beta, V) rows indexed by the core's warm-start slots.
 struct DevicePool {
     DevBuf buf;
@@ -104,11 +138,14 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     pool.pp = pp;
     pool.sb = state_bytes(in.prec);
 
-    DevBuf d_off, d_fix, d_slot, d_row, d_sslot, d_sup, d_ssize, d_bj, d_zup, d_nfree, d_fbeta, d_obj, d_fit;
-    d_off.ensure(sizeof(int32_t) * (K + 1));
-    d_slot.ensure(sizeof(int64_t) * K);
-    d_row.ensure(sizeof(int64_t) * K);
-    d_sslot.ensure(sizeof(int64_t) * K);
+    // per batch: one host-to-device copy of [slots | fixing offsets | fixings], one
+    // device-to-host copy of the packed results, one copy of the scatter pairs
+    DevBuf d_in, d_sc, d_out, d_sup, d_ssize, d_bj, d_zup, d_nfree, d_fbeta, d_obj, d_fit;
+    PinnedBuf h_in, h_sc, h_out;
+    d_sc.ensure(sizeof(int64_t) * 2 * K);
+    d_out.ensure(sizeof(NodeOut) * K);
+    h_sc.ensure(sizeof(int64_t) * 2 * K);
+    h_out.ensure(sizeof(NodeOut) * K);
     d_sup.ensure((size_t)K * p);
     d_ssize.ensure(sizeof(int32_t) * K);
     d_bj.ensure(sizeof(int32_t) * K);
@@ -123,10 +160,7 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     int64_t batches = 0;
     int status = 0;
     std::vector<OpenNode> batch;
-    std::vector<int32_t> h_off, h_fix;
-    std::vector<int64_t> h_slot, h_row, h_sslot;
-    std::vector<double> h_lb(K), h_primal(K), h_obj(K);
-    std::vector<int32_t> h_iters(K), h_status(K), h_ssize(K), h_bj(K), h_zup(K);
+    std::vector<int32_t> h_fix;
     std::vector<NodeOutcome> res(K);
     std::vector<std::pair<int, int64_t>> saves;
 
@@ -141,25 +175,30 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
         const int B = (int)batch.size();
         if (B == 0) continue;
         ++batches;
-        h_off.assign((size_t)B + 1, 0);
+        // input layout: B slots (int64), B + 1 fixing offsets (int32), the fixings (int32)
         h_fix.clear();
-        h_slot.assign((size_t)B, -1);
+        std::vector<int32_t> offs((size_t)B + 1, 0);
         for (int k = 0; k < B; ++k) {
             core.fixings(batch[k].id, h_fix);
-            h_off[(size_t)k + 1] = (int32_t)h_fix.size();
-            h_slot[(size_t)k] = batch[k].slot;
+            offs[(size_t)k + 1] = (int32_t)h_fix.size();
         }
-        d_fix.ensure(sizeof(int32_t) * std::max<size_t>(h_fix.size(), 1));
-        HIPCHK(hipMemcpyAsync(d_off.ptr, h_off.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, st));
-        if (!h_fix.empty())
-            HIPCHK(hipMemcpyAsync(d_fix.ptr, h_fix.data(), sizeof(int32_t) * h_fix.size(), hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(d_slot.ptr, h_slot.data(), sizeof(int64_t) * B, hipMemcpyHostToDevice, st));
+        const size_t in_bytes = sizeof(int64_t) * B + sizeof(int32_t) * ((size_t)B + 1 + h_fix.size());
+        h_in.ensure(in_bytes);
+        d_in.ensure(in_bytes);
+        int64_t *hs = h_in.as<int64_t>();
+        for (int k = 0; k < B; ++k) hs[k] = batch[k].slot;
+        int32_t *ho = reinterpret_cast<int32_t *>(hs + B);
+        std::memcpy(ho, offs.data(), sizeof(int32_t) * ((size_t)B + 1));
+        if (!h_fix.empty()) std::memcpy(ho + B + 1, h_fix.data(), sizeof(int32_t) * h_fix.size());
+        HIPCHK(hipMemcpyAsync(d_in.ptr, h_in.ptr, in_bytes, hipMemcpyHostToDevice, st));
+        const int64_t *d_slot = d_in.as<int64_t>();
+        const int32_t *d_off = reinterpret_cast<const int32_t *>(d_slot + B);
+        const int32_t *d_fix = d_off + B + 1;
         const int64_t Bp = round_up(B, kPadNodes);
         hipLaunchKernelGGL(k_build_codes, dim3((unsigned)Bp), dim3(256), 0, st, ws.codes.as<uint8_t>(), pp, p,
-                           (int64_t)B, Bp, d_off.as<int32_t>(), d_fix.as<int32_t>());
+                           (int64_t)B, Bp, d_off, d_fix);
         hipLaunchKernelGGL((k_gather<T>), dim3((unsigned)((pp + 255) / 256), (unsigned)Bp), dim3(256), 0, st,
-                           ws.beta.as<T>(), ws.V.as<T>(), pp, (const T *)pool.buf.ptr, d_slot.as<int64_t>(), Bp,
-                           (int64_t)B);
+                           ws.beta.as<T>(), ws.V.as<T>(), pp, (const T *)pool.buf.ptr, d_slot, Bp, (int64_t)B);
         HIPCHK(hipGetLastError());
         core.gathered(batch);
         l0l2_admm_opts ao = o.admm;
@@ -170,19 +209,18 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
         state_to_f64(ctx, B, ws.beta.ptr, pp, d_fbeta.as<double>(), p);
         run_fista(ctx, B, d_sup.as<uint8_t>(), p, d_fbeta.as<double>(), p, o.fista, d_obj.as<double>(),
                   d_fit.as<int32_t>());
-        HIPCHK(hipMemcpyAsync(h_lb.data(), ws.lb.ptr, 8 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_primal.data(), ws.primal.ptr, 8 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_iters.data(), ws.iters.ptr, 4 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_status.data(), ws.status.ptr, 4 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_ssize.data(), d_ssize.ptr, 4 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_bj.data(), d_bj.ptr, 4 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_zup.data(), d_zup.ptr, 4 * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(h_obj.data(), d_obj.ptr, 8 * B, hipMemcpyDeviceToHost, st));
+        hipLaunchKernelGGL(k_pack_out, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, st, ws.lb.as<double>(),
+                           ws.primal.as<double>(), d_obj.as<double>(), ws.iters.as<int32_t>(), ws.status.as<int32_t>(),
+                           d_ssize.as<int32_t>(), d_bj.as<int32_t>(), d_zup.as<int32_t>(), d_out.as<NodeOut>(),
+                           (int64_t)B);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(h_out.ptr, d_out.ptr, sizeof(NodeOut) * B, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        const NodeOut *ho_res = h_out.as<NodeOut>();
         for (int k = 0; k < B; ++k) {
-            if (!std::isfinite(h_obj[k])) fail(L0L2_E_UNSUPPORTED, "support larger than the refinement kernel allows");
-            res[k] = NodeOutcome{h_lb[k], h_primal[k], h_iters[k], h_status[k], h_obj[k], h_ssize[k], h_bj[k],
-                                 h_zup[k]};
+            const NodeOut &r = ho_res[k];
+            if (!std::isfinite(r.obj)) fail(L0L2_E_UNSUPPORTED, "support larger than the refinement kernel allows");
+            res[k] = NodeOutcome{r.lb, r.primal, r.iters, r.status, r.obj, r.ssize, r.bj, r.zup};
         }
         int best_k;
         core.process(batch, res.data(), saves, best_k);
@@ -191,21 +229,22 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
                                   hipMemcpyDeviceToHost, st));
         if (!saves.empty()) {
             pool.ensure(core.slot_high_water(), st);
-            h_row.clear();
-            h_sslot.clear();
-            for (auto &sv : saves) {
-                h_row.push_back(sv.first);
-                h_sslot.push_back(sv.second);
+            const int64_t ns = (int64_t)saves.size();
+            int64_t *hr = h_sc.as<int64_t>();
+            for (int64_t e = 0; e < ns; ++e) {
+                hr[e] = saves[(size_t)e].first;
+                hr[ns + e] = saves[(size_t)e].second;
             }
-            HIPCHK(hipMemcpyAsync(d_row.ptr, h_row.data(), 8 * h_row.size(), hipMemcpyHostToDevice, st));
-            HIPCHK(hipMemcpyAsync(d_sslot.ptr, h_sslot.data(), 8 * h_sslot.size(), hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)((pp + 255) / 256), (unsigned)h_row.size()), dim3(256),
-                               0, st, ws.beta.as<T>(), ws.V.as<T>(), pp, (T *)pool.buf.ptr, d_row.as<int64_t>(),
-                               d_sslot.as<int64_t>(), (int64_t)h_row.size());
+            HIPCHK(hipMemcpyAsync(d_sc.ptr, h_sc.ptr, sizeof(int64_t) * 2 * ns, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL((k_scatter<T>), dim3((unsigned)((pp + 255) / 256), (unsigned)ns), dim3(256), 0, st,
+                               ws.beta.as<T>(), ws.V.as<T>(), pp, (T *)pool.buf.ptr, d_sc.as<int64_t>(),
+                               d_sc.as<int64_t>() + ns, ns);
             HIPCHK(hipGetLastError());
         }
-        HIPCHK(hipStreamSynchronize(st));
+        // no wait here: the next batch's copies and kernels follow in stream order,
+        // and the staging buffers are rewritten only after its results are read
     }
+    HIPCHK(hipStreamSynchronize(st));
     const double UB = core.ub();
     out->ub = UB;
     out->lb = status == 0 ? UB : std::min(UB, core.frontier_lb());

@@ -149,13 +149,9 @@ struct FistaShared {
     int it;
 };
 
-// Sum (max) over the 64 lanes of a wave; every lane receives the same value.
+// Sum over the 64 lanes of a wave; every lane receives the same value.
 __device__ __forceinline__ double wsum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-__device__ __forceinline__ double wmax(double v) {
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
     return v;
 }
 
@@ -166,8 +162,19 @@ __device__ __forceinline__ double gram_mv(FistaShared &sm, double v, int k, int 
     sm.vb[lane] = v;
     __builtin_amdgcn_wave_barrier();
     double s = 0.0;
-    if (lane < k)
-        for (int b = 0; b < k; ++b) s += sm.G[b * kGramMax + lane] * sm.vb[b];
+    if (lane < k) {
+        // four independent partial sums keep several LDS reads in flight
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = 0;
+        for (; b + 4 <= k; b += 4) {
+            s0 += sm.G[b * kGramMax + lane] * sm.vb[b];
+            s1 += sm.G[(b + 1) * kGramMax + lane] * sm.vb[b + 1];
+            s2 += sm.G[(b + 2) * kGramMax + lane] * sm.vb[b + 2];
+            s3 += sm.G[(b + 3) * kGramMax + lane] * sm.vb[b + 3];
+        }
+        for (; b < k; ++b) s0 += sm.G[b * kGramMax + lane] * sm.vb[b];
+        s = (s0 + s1) + (s2 + s3);
+    }
     __builtin_amdgcn_wave_barrier();
     return s;
 }
@@ -315,31 +322,35 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
             }
             double prev = cur;
             double alpha = 4.0 / (wsum(cn * cn) + 2.0 * fa.l2);
-            auto U = [&](double v, double &Gv) {
-                Gv = gram_mv(sm, v, k, lane);
-                double part = on ? 0.5 * v * Gv - g * v + fa.l2 * v * v : 0.0;
-                return 0.5 * yy + wsum(part);
-            };
-            double Gv;
-            double Ucur = U(cur, Gv);
+            // lane share of U(v) - yy/2 given (G v)_lane
+            auto upart = [&](double v, double Gv) { return on ? 0.5 * v * Gv - g * v + fa.l2 * v * v : 0.0; };
+            double Ucur = 0.5 * yy + wsum(upart(cur, gram_mv(sm, cur, k, lane)));
             int it = 0;
             while (it < fa.max_iter) {
                 const double mom = (double)it / ((double)it + 3.0);
                 const double ext = cur + mom * (cur - prev);
-                const double Uext = U(ext, Gv);
-                const double grad = on ? Gv - g + 2.0 * fa.l2 * ext : 0.0;
-                double Unxt = 0.0, nxt = 0.0;
+                const double Gve = gram_mv(sm, ext, k, lane);
+                const double grad = on ? Gve - g + 2.0 * fa.l2 * ext : 0.0;
+                const double ue = upart(ext, Gve);
+                double Uext = 0.0, Unxt = 0.0, nxt = 0.0, dm = 0.0;
                 for (int bt = 0; bt <= 60; ++bt) {
                     double v = ext - alpha * grad;
                     nxt = on ? (v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v)) : 0.0;
                     const double d = nxt - ext;
-                    const double gd = wsum(grad * d), dd = wsum(d * d);
-                    Unxt = U(nxt, Gv);
-                    if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
+                    // one fused pass of independent butterflies: U(ext) (first trial
+                    // only), <grad, d>, |d|^2, U(nxt) and max |nxt - cur|
+                    double r[5] = {ue, grad * d, d * d, upart(nxt, gram_mv(sm, nxt, k, lane)), fabs(nxt - cur)};
+                    for (int off = 32; off > 0; off >>= 1) {
+                        for (int i = 0; i < 4; ++i) r[i] += __shfl_xor(r[i], off);
+                        r[4] = fmax(r[4], __shfl_xor(r[4], off));
+                    }
+                    if (bt == 0) Uext = 0.5 * yy + r[0];
+                    Unxt = 0.5 * yy + r[3];
+                    dm = r[4];
+                    if (Unxt <= Uext + r[1] + r[2] / (2.0 * alpha) || bt == 60) break;
                     alpha *= 0.5;
                 }
                 ++it;
-                const double dm = wmax(fabs(nxt - cur));
                 const double dU = fabs(Unxt - Ucur);
                 prev = cur;
                 cur = nxt;
