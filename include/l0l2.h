@@ -219,15 +219,16 @@ const char *l0l2_server_last_error(const l0l2_server *srv);
 /* Stop admitting, drop queued requests, wait for running ones, free all. */
 int l0l2_server_destroy(l0l2_server *srv);
 
-/* Tile shapes of the two sweep contractions (output rows x nodes, waves that
- * split the contraction): 0 = 32x32/4, 1 = 32x32/8, 2 = 32x32/16 (8 in FP64),
- * 3 = 16x32/8, 4 = 32x16/8, 5 = 16x16/4, 6 = 64x32/8, 7 = 32x64/8, 8 = 64x32/4.
- * By default (both -1) each new padded batch size is timed once with every
- * shape whose node tile divides it, on the live batch, and the fastest kept per
- * instance; fixed shapes serve tests and tuning studies (a fixed shape whose
- * node tile does not divide the padded batch makes the solve calls fail with
- * L0L2_E_INVALID).  Results do not depend on the shape beyond rounding of the
- * summation order. */
+/* Tile shapes of the two sweep contractions (output rows x nodes / waves):
+ * register tiles whose waves split the contraction range, 0 = 32x32/4,
+ * 1 = 32x32/8, 2 = 32x32/16 (8 in FP64), 3 = 16x32/8, 4 = 32x16/8, 5 = 16x16/4,
+ * 6 = 64x32/8, 7 = 32x64/8, 8 = 64x32/4; LDS-staged tiles (4 waves), 9 = 64x64,
+ * 10 = 128x64, 11 = 128x128.  By default (both -1) each new padded batch size
+ * is timed once with every shape whose node tile divides it, on the live batch,
+ * and the fastest kept per instance; fixed shapes serve tests and tuning
+ * studies (a fixed shape whose node tile does not divide the padded batch makes
+ * the solve calls fail with L0L2_E_INVALID).  Results do not depend on the
+ * shape beyond rounding of the summation order. */
 int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
 
 /* Opt-in timing of the library's kernels with HIP events recorded on the

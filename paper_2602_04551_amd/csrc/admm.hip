@@ -16,6 +16,7 @@
 // of Sec. 4.1): r = y - X b, g = X^T r, LB = rigorous D(r); P(beta) from X beta.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "device_math.hpp"
 #include "internal.hpp"
@@ -361,6 +362,243 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu_anch(
         }
         if (est) store_estimate<TM>(e, m, live ? node : -1, gpart);
     }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged tiles for large grids.  A workgroup of 4 waves (2 x 2) owns a
+// TM x TN output tile (TM = 32 WM, TN = 32 WN); every k chunk of 16 of the A
+// slab (TM rows) and the B slab (TN node rows) is loaded once from global memory
+// into LDS (two buffers: the next chunk's global loads are issued before the
+// current chunk's MFMAs and stored after them) and each wave reads its
+// (16 WM) x (16 WN) sub-tile's fragments from LDS, so a loaded element feeds
+// 2 waves instead of 1 and the tile is 4-16 times larger than the register
+// tiles' (far less L2 traffic per flop).  Each output element is owned by one
+// lane (no cross-wave reduction).  Lane l reads 4 consecutive k of row l%16 for
+// the 4 MFMAs of a chunk, as in nt_tile.  LDS rows hold 16 + pad elements
+// (80 B for FP32, 144 B for FP64: 16 lanes' 16-byte reads spread over the banks).
+// ---------------------------------------------------------------------------
+template <class T> struct LdsRow;
+template <> struct LdsRow<float> { static constexpr int LD = 20; };
+template <> struct LdsRow<double> { static constexpr int LD = 18; };
+
+template <class T, int WM, int WN>
+struct LdsTile {
+    static constexpr int TM = 32 * WM, TN = 32 * WN, LD = LdsRow<T>::LD;
+    static constexpr int VPR = (int)sizeof(T);              // 16-byte vectors per 16-element row
+    static constexpr int NA = TM * VPR / 256, NB = TN * VPR / 256;
+    static constexpr int STAGE = (TM + TN) * LD;            // elements per buffer
+};
+
+template <class T, int WM, int WN>
+__device__ __forceinline__ void lds_tile(const T *__restrict__ A, int64_t lda, const T *__restrict__ B, int64_t ldb,
+                                         int64_t kdim, int64_t m0, int64_t n0, const NodeCols &ncl, int cnt, T *smem,
+                                         typename Acc<T>::type (&acc)[WM][WN]) {
+    typedef LdsTile<T, WM, WN> L;
+    constexpr int EPV = 16 / (int)sizeof(T);                 // elements per 16-byte vector
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int q = lane >> 4, r = lane & 15;
+    typedef typename Acc<T>::type AccT;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
+    // global source of each staged vector of this thread (row, 16-byte part)
+    const T *ga[L::NA];
+    const T *gb[L::NB];
+    int la[L::NA], lb[L::NB];
+#pragma unroll
+    for (int e = 0; e < L::NA; ++e) {
+        const int idx = tid + 256 * e, row = idx / L::VPR, part = idx % L::VPR;
+        ga[e] = A + (m0 + row) * lda + EPV * part;
+        la[e] = row * L::LD + EPV * part;
+    }
+#pragma unroll
+    for (int e = 0; e < L::NB; ++e) {
+        const int idx = tid + 256 * e, row = idx / L::VPR, part = idx % L::VPR;
+        gb[e] = B + col_slot(ncl, n0 + row, cnt) * ldb + EPV * part;
+        lb[e] = (L::TM + row) * L::LD + EPV * part;
+    }
+    float4 va[L::NA], vb[L::NB];
+#define L0L2_GLOAD(c)                                                                                          \
+    _Pragma("unroll") for (int e = 0; e < L::NA; ++e) va[e] = *reinterpret_cast<const float4 *>(ga[e] + 16 * (c)); \
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) vb[e] = *reinterpret_cast<const float4 *>(gb[e] + 16 * (c));
+#define L0L2_SSTORE(st)                                                                                        \
+    _Pragma("unroll") for (int e = 0; e < L::NA; ++e)                                                          \
+        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + la[e]) = va[e];                                    \
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e)                                                          \
+        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + lb[e]) = vb[e];
+    const int64_t nch = kdim / 16;
+    L0L2_GLOAD(0)
+    L0L2_SSTORE(0)
+    __syncthreads();
+    for (int64_t c = 0; c < nch; ++c) {
+        const int st = (int)(c & 1);
+        // next chunk (the last chunk reloads itself; its copy lands in the idle buffer)
+        const int64_t cn = c + 1 < nch ? c + 1 : c;
+        L0L2_GLOAD(cn)
+        const T *sa = smem + st * L::STAGE;
+        T a[WM][4], b[WN][4];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) load4(sa + (wm * 16 * WM + 16 * i + r) * L::LD + 4 * q, a[i]);
+#pragma unroll
+        for (int j = 0; j < WN; ++j) load4(sa + (L::TM + wn * 16 * WN + 16 * j + r) * L::LD + 4 * q, b[j]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j) acc[i][j] = mfma16(a[i][t], b[j][t], acc[i][j]);
+        L0L2_SSTORE(st ^ 1)
+        __syncthreads();
+    }
+#undef L0L2_GLOAD
+#undef L0L2_SSTORE
+}
+
+// Output position of accumulator v of block (i, j) held by this lane.
+template <class T, int WM, int WN>
+__device__ __forceinline__ void lds_pos(int i, int j, int v, int &m, int &n) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    m = (w >> 1) * 16 * WM + 16 * i + acc_row<T>(lane, v);
+    n = (w & 1) * 16 * WN + 16 * j + (lane & 15);
+}
+
+// Contraction over p (U = Xh W^T) with an LDS-staged tile.
+template <class T, int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
+                                                     int64_t ldb, T *__restrict__ U, int64_t ldu, int64_t kdim,
+                                                     NodeCols ncl) {
+    typedef LdsTile<T, WM, WN> L;
+    __shared__ __align__(16) T smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
+    if (n0 >= cnt) return;
+    typename Acc<T>::type acc[WM][WN];
+    lds_tile<T, WM, WN>(A, lda, B, ldb, kdim, m0, n0, ncl, cnt, smem, acc);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int m, n;
+                lds_pos<T, WM, WN>(i, j, v, m, n);
+                if (n0 + n < cnt) U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = acc[i][j][v];
+            }
+}
+
+// Per-(node, tile) sums of the gap estimate over the TM rows of an LDS tile:
+// each lane adds its 4 rows of every block row, the 4 lanes of a column add
+// up (xor 16, 32), the two wave rows meet in LDS.  e[i][j][t]: term t of
+// block (i, j)'s 4 rows of this lane.
+template <int WM, int WN>
+__device__ __forceinline__ void lds_store_estimate(double (&e)[WN][5], const NodeCols &ncl, int64_t n0, int cnt,
+                                                   double *__restrict__ gpart, double *red) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+#pragma unroll
+    for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            e[j][t] += __shfl_xor(e[j][t], 16);
+            e[j][t] += __shfl_xor(e[j][t], 32);
+        }
+    __syncthreads();
+    if (wm == 1 && lane < 16)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int t = 0; t < 5; ++t) red[((wn * WN + j) * 16 + lane) * 5 + t] = e[j][t];
+    __syncthreads();
+    if (wm == 0 && lane < 16)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const int n = wn * 16 * WN + 16 * j + lane;
+            if (n0 + n >= cnt) continue;
+            double *d = gpart + (col_slot(ncl, n0 + n, cnt) * (int64_t)gridDim.x + blockIdx.x) * 5;
+#pragma unroll
+            for (int t = 0; t < 5; ++t) d[t] = e[j][t] + red[((wn * WN + j) * 16 + lane) * 5 + t];
+        }
+}
+
+// Contraction over n with the ADMM epilogue, LDS-staged tile.
+template <class T, int WM, int WN>
+__global__ __launch_bounds__(256) void k_admm_xtu_lds(const T *__restrict__ A, int64_t lda, const T *__restrict__ U,
+                                                      int64_t ldu, int64_t kdim, T *__restrict__ W,
+                                                      T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
+                                                      const uint8_t *__restrict__ codes, const T *__restrict__ c,
+                                                      const int *__restrict__ active, DevParams<T> q, int64_t ldp,
+                                                      int store_b, double *__restrict__ gpart, GateArgs ga,
+                                                      NodeCols ncl) {
+    typedef LdsTile<T, WM, WN> L;
+    __shared__ __align__(16) T smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
+    if (n0 >= cnt) return;
+    typename Acc<T>::type acc[WM][WN];
+    lds_tile<T, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, smem, acc);
+    const bool est = gpart != nullptr;
+    double e[WN][5] = {};
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int m, n;
+                lds_pos<T, WM, WN>(i, j, v, m, n);
+                const bool live = n0 + n < cnt;
+                const int64_t node = col_slot(ncl, n0 + n, cnt), jj = m0 + m;
+                if (live && active[node]) {
+                    double ev[5] = {0, 0, 0, 0, 0};
+                    admm_update<T>(acc[i][j][v], node * ldp + jj, jj, W, beta, V, Bst, codes, c, q, store_b, est,
+                                   ga, ev);
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
+                }
+            }
+    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, cnt, gpart, reinterpret_cast<double *>(smem));
+}
+
+// Contraction over n of an anchored sweep, LDS-staged tile.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_admm_xtu_anch_lds(
+    const float *__restrict__ A, int64_t lda, const float *__restrict__ U, int64_t ldu, int64_t kdim,
+    const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W, double *__restrict__ beta,
+    double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d, const uint8_t *__restrict__ codes,
+    const double *__restrict__ c, const int *__restrict__ active, DevParams<double> q, int64_t ldp, int store_b,
+    double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    typedef LdsTile<float, WM, WN> L;
+    __shared__ __align__(16) float smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
+    if (n0 >= cnt) return;
+    f32x4 acc[WM][WN];
+    lds_tile<float, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, smem, acc);
+    const bool est = gpart != nullptr;
+    double e[WN][5] = {};
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int m, n;
+                lds_pos<float, WM, WN>(i, j, v, m, n);
+                const bool live = n0 + n < cnt;
+                const int64_t node = col_slot(ncl, n0 + n, cnt), jj = m0 + m;
+                if (live && active[node]) {
+                    const int64_t o = node * ldp + jj;
+                    double ev[5] = {0, 0, 0, 0, 0};
+                    admm_update<double>(Za[o] + (double)acc[i][j][v], o, jj, W, beta, V, Bst, codes, c, q, store_b,
+                                        est, ga, ev);
+                    d[o] = (float)(W[o] - Wa[o]);
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
+                }
+            }
+    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, cnt, gpart, reinterpret_cast<double *>(smem));
 }
 
 // ---------------------------------------------------------------------------
@@ -791,26 +1029,40 @@ template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
 // ---------------------------------------------------------------------------
 // Host drivers
 // ---------------------------------------------------------------------------
-// Tile shapes of the sweep contractions: (BM, BN) 16-row blocks per output tile
-// and the number of waves splitting the contraction range.  FP64 keeps at most
-// 8 waves on the 32 x 32 tile (LDS for the cross-wave reduction).
-constexpr int kShapes = 9;
-constexpr int kTileBM[kShapes] = {2, 2, 2, 1, 2, 1, 4, 2, 4};
-constexpr int kTileBN[kShapes] = {2, 2, 2, 2, 1, 1, 2, 4, 2};
-constexpr int kTileW[kShapes] = {4, 8, 16, 8, 8, 4, 8, 8, 4};
+// Tile shapes of the sweep contractions: output tile TM x TN (rows x nodes) and
+// waves per workgroup.  Shapes 0-8 are register tiles whose waves split the
+// contraction range (FP64 keeps at most 8 waves on the 32 x 32 tile: LDS for
+// the cross-wave reduction); shapes 9-11 are LDS-staged tiles (4 waves, 2 x 2).
+constexpr int kShapes = 12;
+constexpr int kTileTM[kShapes] = {32, 32, 32, 16, 32, 16, 64, 32, 64, 64, 128, 128};
+constexpr int kTileTN[kShapes] = {32, 32, 32, 32, 16, 16, 32, 64, 32, 64, 64, 128};
+constexpr int kTileW[kShapes] = {4, 8, 16, 8, 8, 4, 8, 8, 4, 4, 4, 4};
 
-// A shape fits a padded batch when its node tile divides it.
-bool shape_fits(int v, int64_t Kp) { return Kp % (16 * kTileBN[v]) == 0; }
+// A shape fits a padded batch when its node tile divides it (rows are padded to
+// multiples of 128).
+bool shape_fits(int v, int64_t Kp) { return Kp % kTileTN[v] == 0; }
 
 template <class TA, class TB, class TC>
 void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int64_t ldb, TC *U, int64_t ldu,
                int64_t rows, int64_t Kp, int64_t kdim, NodeCols ncl = NodeCols{nullptr, nullptr}) {
     if (sizeof(TC) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
-    dim3 g((unsigned)(rows / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
+    dim3 g((unsigned)(rows / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XW(PBM, PBN, PW) \
     hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, PBM, PBN, PW>), g, b, 0, s, A, lda, B, ldb, U, ldu, kdim, ncl)
+#define L0L2_XWL(WM, WN) \
+    hipLaunchKernelGGL((k_gemm_xw_lds<TC, WM, WN>), g, b, 0, s, (const TC *)A, lda, (const TC *)B, ldb, U, ldu, kdim, ncl)
+    if (v >= 9) {
+        if (!std::is_same<TA, TC>::value || !std::is_same<TB, TC>::value)
+            fail(L0L2_E_INVALID, "LDS-staged tiles take one operand type");
+        switch (v) {
+            case 9: L0L2_XWL(2, 2); break;
+            case 10: L0L2_XWL(4, 2); break;
+            default: L0L2_XWL(4, 4); break;
+        }
+        return;
+    }
     switch (v) {
         case 0: L0L2_XW(2, 2, 4); break;
         case 1: L0L2_XW(2, 2, 8); break;
@@ -823,6 +1075,7 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
         default: L0L2_XW(4, 2, 4); break;
     }
 #undef L0L2_XW
+#undef L0L2_XWL
 }
 
 template <class T>
@@ -831,11 +1084,22 @@ void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp
                 const GateArgs &ga = GateArgs{}, NodeCols ncl = NodeCols{nullptr, nullptr}) {
     if (sizeof(T) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
-    dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
+    dim3 g((unsigned)(pp / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XTU(PBM, PBN, PW)                                                                                  \
     hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, \
                        sw.B, codes, sw.c, active, q, pp, store_b, gpart, ga, ncl)
+#define L0L2_XTUL(WM, WN)                                                                                       \
+    hipLaunchKernelGGL((k_admm_xtu_lds<T, WM, WN>), g, b, 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V,     \
+                       sw.B, codes, sw.c, active, q, pp, store_b, gpart, ga, ncl)
+    if (v >= 9) {
+        switch (v) {
+            case 9: L0L2_XTUL(2, 2); break;
+            case 10: L0L2_XTUL(4, 2); break;
+            default: L0L2_XTUL(4, 4); break;
+        }
+        return;
+    }
     switch (v) {
         case 0: L0L2_XTU(2, 2, 4); break;
         case 1: L0L2_XTU(2, 2, 8); break;
@@ -848,6 +1112,7 @@ void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp
         default: L0L2_XTU(4, 2, 4); break;
     }
 #undef L0L2_XTU
+#undef L0L2_XTUL
 }
 
 // The anchored sweep's contraction over n (FP32 operands, FP64 update).
@@ -855,11 +1120,22 @@ void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<
                      const double *Wa, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes, const int *active,
                      const DevParams<double> &q, int store_b, double *gpart, const GateArgs &ga, NodeCols ncl) {
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
-    dim3 g((unsigned)(pp / (16 * kTileBM[v])), (unsigned)(Kp / (16 * kTileBN[v])));
+    dim3 g((unsigned)(pp / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XTUA(PBM, PBN, PW)                                                                                \
     hipLaunchKernelGGL((k_admm_xtu_anch<PBM, PBN, PW>), g, b, 0, s, s32.Xh, np, s32.U, np, np, Za, Wa, s64.W,     \
                        s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, pp, store_b, gpart, ga, ncl)
+#define L0L2_XTUAL(WM, WN)                                                                                     \
+    hipLaunchKernelGGL((k_admm_xtu_anch_lds<WM, WN>), g, b, 0, s, s32.Xh, np, s32.U, np, np, Za, Wa, s64.W,       \
+                       s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, pp, store_b, gpart, ga, ncl)
+    if (v >= 9) {
+        switch (v) {
+            case 9: L0L2_XTUAL(2, 2); break;
+            case 10: L0L2_XTUAL(4, 2); break;
+            default: L0L2_XTUAL(4, 4); break;
+        }
+        return;
+    }
     switch (v) {
         case 0: L0L2_XTUA(2, 2, 4); break;
         case 1: L0L2_XTUA(2, 2, 8); break;
@@ -872,6 +1148,7 @@ void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<
         default: L0L2_XTUA(4, 2, 4); break;
     }
 #undef L0L2_XTUA
+#undef L0L2_XTUAL
 }
 
 // Tile shapes chosen for (arithmetic type, padded batch): each shape that fits
@@ -1143,8 +1420,8 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     }
     if (!force) {
         int rows = 32;
-        if (kind == SK_F64) rows = 16 * kTileBM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
-        else if (kind == SK_F32 || kind == SK_ANCH) rows = 16 * kTileBM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
+        if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
+        else if (kind == SK_F32 || kind == SK_ANCH) rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
         GateFin gf{in.yy, tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),

@@ -83,13 +83,13 @@ def test_sweeps_fp64_match_oracle(torch_cuda, cases, name):
             assert rel(gbb[k], bb) < 1e-11, (S, k)
 
 
-@pytest.mark.parametrize("shape", list(range(9)))
+@pytest.mark.parametrize("shape", list(range(12)))
 def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
     inst, o, root = cases["ragged"]
-    K = 48
+    K = 100
     codes, beta0, v0 = random_nodes(inst.p, K, 11, root["beta"], root["v"])
     ctx = ctx_for(inst, "fp64")
-    ctx.set_tiles(shape, 8 - shape)
+    ctx.set_tiles(shape, 11 - shape)
     gb, gv, gbb = ctx.admm_sweeps(codes, beta0, v0, 7)
     gb, gbb = gb.cpu().numpy(), gbb.cpu().numpy()
     for k in range(K):
@@ -99,6 +99,26 @@ def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
         for _ in range(7):
             b, v, bb = o.sweep(codes[k], b, v)
         assert rel(gb[k], b) < 1e-11 and rel(gbb[k], bb) < 1e-11
+
+
+@pytest.mark.parametrize("shape", [9, 10, 11])
+def test_lds_tiles_fp32_and_anchored_match(torch_cuda, cases, shape):
+    """The LDS-staged tiles in FP32 mode (plain and anchored sweeps, with the gap
+    estimate's epilogue) give the same node solves as the register tiles, to
+    FP32 rounding of the summation order."""
+    inst, o, root = cases["wide"]
+    K = 128
+    codes, beta0, v0 = random_nodes(inst.p, K, 13, root["beta"], root["v"])
+    ref = ctx_for(inst, "fp32")
+    ref.set_tiles(1, 1)
+    r0 = ref.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
+    ctx = ctx_for(inst, "fp32")
+    ctx.set_tiles(shape, shape)
+    r1 = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
+    lb0, lb1 = r0["lb"].cpu().numpy(), r1["lb"].cpu().numpy()
+    pr = r0["primal"].cpu().numpy()
+    assert (r1["status"].cpu().numpy() == 0).all()
+    assert np.max(np.abs(lb0 - lb1) / np.abs(pr)) < 1e-7
 
 
 def test_fixed_shape_that_does_not_fit_the_batch_is_rejected(torch_cuda, cases):
