@@ -679,6 +679,173 @@ __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, con
     __syncthreads();
 }
 
+// LDS-staged tile of the BF16 split form (4 waves, 2 x 2; TM = 32 WM, TN = 32 WN).
+// A k chunk of 32 stages, per row, the BF16 hi and lo terms of A (2 x 64 B) or the
+// FP32 values of B (128 B), each row padded to 144 B; lane l reads 8
+// consecutive k of row l%16 (one 16-byte read per BF16 term, two for FP32) and
+// the B fragment is split into BF16 hi / lo in registers.
+template <int WM, int WN>
+struct LdsTileBf {
+    static constexpr int TM = 32 * WM, TN = 32 * WN;
+    static constexpr int ROWB = 144;                         // bytes per staged row
+    static constexpr int NA = TM * 8 / 256, NB = TN * 8 / 256;   // 16-byte vectors per thread
+    static constexpr int STAGE = (TM + TN) * ROWB;           // bytes per buffer
+};
+
+template <int WM, int WN>
+__device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+                                              int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
+                                              int64_t m0, int64_t n0, const NodeCols &ncl, int cnt,
+                                              unsigned char *smem, f32x4 (&acc)[WM][WN]) {
+    typedef LdsTileBf<WM, WN> L;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int q = lane >> 4, r = lane & 15;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    // staged vector e of this thread: row idx / 8, part idx % 8 (A: parts 0-3 hi,
+    // 4-7 lo; B: parts 0-7 of the FP32 row)
+    const unsigned char *ga[L::NA];
+    const unsigned char *gb[L::NB];
+    int la[L::NA], lb[L::NB];
+#pragma unroll
+    for (int e = 0; e < L::NA; ++e) {
+        const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
+        const __bf16 *src = (part < 4 ? Ahi : Alo) + (m0 + row) * lda;
+        ga[e] = reinterpret_cast<const unsigned char *>(src) + 16 * (part & 3);
+        la[e] = row * L::ROWB + 16 * part;
+    }
+#pragma unroll
+    for (int e = 0; e < L::NB; ++e) {
+        const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
+        gb[e] = reinterpret_cast<const unsigned char *>(B + col_slot(ncl, n0 + row, cnt) * ldb) + 16 * part;
+        lb[e] = (L::TM + row) * L::ROWB + 16 * part;
+    }
+    float4 va[L::NA], vb[L::NB];
+    // chunk c covers 32 k: 64 bytes of each BF16 term, 128 bytes of FP32
+#define L0L2_GLOADB(c)                                                                                      \
+    _Pragma("unroll") for (int e = 0; e < L::NA; ++e) va[e] = *reinterpret_cast<const float4 *>(ga[e] + 64 * (c)); \
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) vb[e] = *reinterpret_cast<const float4 *>(gb[e] + 128 * (c));
+#define L0L2_SSTOREB(st)                                                                                    \
+    _Pragma("unroll") for (int e = 0; e < L::NA; ++e)                                                       \
+        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + la[e]) = va[e];                                 \
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e)                                                       \
+        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + lb[e]) = vb[e];
+    const int64_t nch = kdim / 32;
+    L0L2_GLOADB(0)
+    L0L2_SSTOREB(0)
+    __syncthreads();
+    for (int64_t c = 0; c < nch; ++c) {
+        const int st = (int)(c & 1);
+        const int64_t cn = c + 1 < nch ? c + 1 : c;
+        L0L2_GLOADB(cn)
+        const unsigned char *sa = smem + st * L::STAGE;
+        bf16x8 ah[WM], al[WM], bh[WN], bl[WN];
+#pragma unroll
+        for (int i = 0; i < WM; ++i) {
+            const unsigned char *row = sa + (wm * 16 * WM + 16 * i + r) * L::ROWB;
+            ah[i] = *reinterpret_cast<const bf16x8 *>(row + 16 * q);
+            al[i] = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);
+        }
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const float *row = reinterpret_cast<const float *>(sa + (L::TM + wn * 16 * WN + 16 * j + r) * L::ROWB);
+            float bv[8];
+            load8f(row + 8 * q, bv);
+            split8(bv, bh[j], bl[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                acc[i][j] = mfma16_bf16(ah[i], bh[j], acc[i][j]);
+                acc[i][j] = mfma16_bf16(ah[i], bl[j], acc[i][j]);
+                acc[i][j] = mfma16_bf16(al[i], bh[j], acc[i][j]);
+            }
+        L0L2_SSTOREB(st ^ 1)
+        __syncthreads();
+    }
+#undef L0L2_GLOADB
+#undef L0L2_SSTOREB
+}
+
+// BF16 split form, contraction over p, LDS-staged tile.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restrict__ Ahi,
+                                                          const __bf16 *__restrict__ Alo, int64_t lda,
+                                                          const float *__restrict__ B, int64_t ldb,
+                                                          float *__restrict__ U, int64_t ldu, int64_t kdim,
+                                                          NodeCols ncl) {
+    typedef LdsTileBf<WM, WN> L;
+    __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
+    if (n0 >= cnt) return;
+    f32x4 acc[WM][WN];
+    lds_tile_bf16<WM, WN>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, ncl, cnt, smem, acc);
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int m, n;
+                lds_pos<float, WM, WN>(i, j, v, m, n);
+                if (n0 + n < cnt) U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = acc[i][j][v];
+            }
+}
+
+// BF16 split form, contraction over n with the FP32 ADMM epilogue (anch == 0)
+// or the anchored FP64 epilogue (anch == 1: Q = z_a + Q_bf16, FP64 state,
+// d = fl32(W - w_a) into dst32), LDS-staged tile.
+template <int WM, int WN, int ANCH>
+__global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
+    const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
+    int64_t ldu, int64_t kdim, float *__restrict__ W32, float *__restrict__ beta32, float *__restrict__ V32,
+    float *__restrict__ B32, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W64,
+    double *__restrict__ beta64, double *__restrict__ V64, double *__restrict__ B64, const uint8_t *__restrict__ codes,
+    const float *__restrict__ c32, const double *__restrict__ c64, const int *__restrict__ active,
+    DevParams<float> q32, DevParams<double> q64, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga,
+    NodeCols ncl) {
+    typedef LdsTileBf<WM, WN> L;
+    __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
+    if (n0 >= cnt) return;
+    f32x4 acc[WM][WN];
+    lds_tile_bf16<WM, WN>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, cnt, smem, acc);
+    const bool est = gpart != nullptr;
+    double e[WN][5] = {};
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int m, n;
+                lds_pos<float, WM, WN>(i, j, v, m, n);
+                const bool live = n0 + n < cnt;
+                const int64_t node = col_slot(ncl, n0 + n, cnt), jj = m0 + m;
+                if (live && active[node]) {
+                    const int64_t o = node * ldp + jj;
+                    double ev[5] = {0, 0, 0, 0, 0};
+                    if (ANCH) {
+                        admm_update<double>(Za[o] + (double)acc[i][j][v], o, jj, W64, beta64, V64, B64, codes, c64,
+                                            q64, store_b, est, ga, ev);
+                        W32[o] = (float)(W64[o] - Wa[o]);
+                    } else {
+                        admm_update<float>(acc[i][j][v], o, jj, W32, beta32, V32, B32, codes, c32, q32, store_b, est,
+                                           ga, ev);
+                    }
+#pragma unroll
+                    for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
+                }
+            }
+    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, cnt, gpart, reinterpret_cast<double *>(smem));
+}
+
 constexpr int kWavesBf16 = 8;
 
 // U[k][i] = sum_j Xh[i][j] W[k][j] with Xh row-major (row i at A + i*lda).
@@ -720,6 +887,35 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
         if (live && active[node])
             admm_update<float>(sum_waves<float, 32, 32, kWavesBf16>(red, n, m), node * ldp + j, j, W, beta, V, Bst,
                                codes, c, q, store_b, est, ga, e);
+        if (est) store_estimate<32>(e, m, live ? node : -1, gpart);
+    }
+}
+
+// Contraction over n of an anchored sweep in the BF16 split form (register
+// tile): Q = z_a + Xh^T U with the BF16 pair, FP64 update, d = fl32(W - w_a).
+__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_anch_bf16(
+    const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
+    int64_t ldu, int64_t kdim, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W,
+    double *__restrict__ beta, double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d,
+    const uint8_t *__restrict__ codes, const double *__restrict__ c, const int *__restrict__ active,
+    DevParams<double> q, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
+    if (n0 >= cnt) return;
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
+    const bool est = gpart != nullptr;
+    for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
+        const int n = idx >> 5, m = idx & 31;
+        const bool live = n0 + n < cnt;
+        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
+        double e[5] = {0, 0, 0, 0, 0};
+        if (live && active[node]) {
+            const int64_t o = node * ldp + j;
+            const double Qv = Za[o] + (double)sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
+            admm_update<double>(Qv, o, j, W, beta, V, Bst, codes, c, q, store_b, est, ga, e);
+            d[o] = (float)(W[o] - Wa[o]);
+        }
         if (est) store_estimate<32>(e, m, live ? node : -1, gpart);
     }
 }
@@ -1256,24 +1452,142 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
     HIPCHK(hipGetLastError());
 }
 
-// One sweep of the BF16 form on the FP32 state of sw.
-void sweep_once_bf16(l0l2_ctx *ctx, const Sweep<float> &sw, int64_t Kp, bool store_b, int64_t active,
-                     bool gate = false) {
+// Tile shapes of the BF16 split form: 0 = register tile 32 x 32 (8 waves split
+// the contraction), 1 = LDS-staged 64 x 64, 2 = LDS-staged 128 x 128.
+constexpr int kShapesBf16 = 3;
+constexpr int kBfTM[kShapesBf16] = {32, 64, 128};
+constexpr int kBfTN[kShapesBf16] = {32, 64, 128};
+
+void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, NodeCols ncl) {
+    Instance &in = ctx->inst;
+    const int64_t np = in.np, pp = in.pp;
+    if (v < 0 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    dim3 g((unsigned)(np / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
+    const __bf16 *hi = in.XhR.as<__bf16>(), *lo = in.XhRLo.as<__bf16>();
+    if (v == 0)
+        hipLaunchKernelGGL(k_gemm_xw_bf16, g, dim3(64 * kWavesBf16), 0, ctx->stream, hi, lo, pp, B, pp, U, np, pp, ncl);
+    else if (v == 1)
+        hipLaunchKernelGGL((k_gemm_xw_bf16_lds<2, 2>), g, dim3(256), 0, ctx->stream, hi, lo, pp, B, pp, U, np, pp, ncl);
+    else
+        hipLaunchKernelGGL((k_gemm_xw_bf16_lds<4, 4>), g, dim3(256), 0, ctx->stream, hi, lo, pp, B, pp, U, np, pp, ncl);
+}
+
+// Contraction over n in the BF16 split form: FP32 update (anch = false, on the
+// FP32 state) or the anchored FP64 update (anch = true).
+void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *active, int store_b, double *gpart,
+                     NodeCols ncl) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
-    hipStream_t s = ctx->stream;
     const int64_t np = in.np, pp = in.pp;
-    dim3 g1((unsigned)(np / 32), (unsigned)(Kp / 32));
-    dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
-    DevParams<float> q = dev_params<float>(in.mp);
+    if (v < 0 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    dim3 g((unsigned)(pp / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
+    const __bf16 *hi = in.Xh.as<__bf16>(), *lo = in.XhLo.as<__bf16>();
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    const DevParams<float> q32 = dev_params<float>(in.mp);
+    const DevParams<double> q64 = dev_params<double>(in.mp);
+    const GateArgs ga = gate_args(in);
+    const double *Za = ws.Za.as<double>(), *Wa = ws.Wa.as<double>();
+    const uint8_t *codes = ws.codes.as<uint8_t>();
+    hipStream_t s = ctx->stream;
+    if (v == 0) {
+        if (anch)
+            hipLaunchKernelGGL(k_admm_xtu_anch_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, np, s32.U, np, np, Za, Wa,
+                               s64.W, s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q64, pp, store_b, gpart, ga,
+                               ncl);
+        else
+            hipLaunchKernelGGL(k_admm_xtu_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, np, s32.U, np, np, s32.W,
+                               s32.beta, s32.V, s32.B, codes, s32.c, active, q32, pp, store_b, gpart, ga, ncl);
+        return;
+    }
+#define L0L2_XTUB(WM, WN, A)                                                                                    \
+    hipLaunchKernelGGL((k_admm_xtu_bf16_lds<WM, WN, A>), g, dim3(256), 0, s, hi, lo, np, s32.U, np, np, s32.W,      \
+                       s32.beta, s32.V, s32.B, Za, Wa, s64.W, s64.beta, s64.V, s64.B, codes, s32.c, s64.c, active, \
+                       q32, q64, pp, store_b, gpart, ga, ncl)
+    if (v == 1) {
+        if (anch) L0L2_XTUB(2, 2, 1);
+        else L0L2_XTUB(2, 2, 0);
+    } else {
+        if (anch) L0L2_XTUB(4, 4, 1);
+        else L0L2_XTUB(4, 4, 0);
+    }
+#undef L0L2_XTUB
+}
+
+// BF16 shapes chosen per padded batch, timed like tile_choice (kind 2).
+TileChoice &tile_choice_bf16(l0l2_ctx *ctx, int64_t Kp) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    if (ctx->force_xw >= 0) {
+        static thread_local TileChoice forced;
+        forced.xw = std::min(ctx->force_xw, kShapesBf16 - 1);
+        forced.xtu = std::min(ctx->force_xtu, kShapesBf16 - 1);
+        return forced;
+    }
+    auto key = std::make_pair(2, Kp);
+    auto it = in.tiles.find(key);
+    if (it != in.tiles.end()) return it->second;
+    TileChoice tc;
+    tc.xw = tc.xtu = 0;
+    if (ctx->tune) {
+        hipStream_t s = ctx->stream;
+        DevBuf inactive;
+        inactive.ensure(sizeof(int) * Kp);
+        HIPCHK(hipMemsetAsync(inactive.ptr, 0, sizeof(int) * Kp, s));
+        Sweep<float> s32 = sweep32(ctx);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto time_shape = [&](int v, int which, int reps) {
+            HIPCHK(hipEventRecord(e0, s));
+            for (int t = 0; t < reps; ++t) {
+                if (which == 0) launch_xw_bf16(v, ctx, s32.W, s32.U, Kp, NodeCols{nullptr, nullptr});
+                else launch_xtu_bf16(v, ctx, false, Kp, inactive.as<int>(), 0, nullptr, NodeCols{nullptr, nullptr});
+            }
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return ms / (float)reps;
+        };
+        float t0 = 0.f;
+        for (int v = 0; v < kShapesBf16; ++v)
+            if (Kp % kBfTN[v] == 0) t0 = std::max(t0, std::max(time_shape(v, 0, 1), time_shape(v, 1, 1)));
+        const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
+        const int rounds = t0 > 1.0f ? 2 : 4;
+        float best[kShapesBf16][2];
+        for (int v = 0; v < kShapesBf16; ++v) best[v][0] = best[v][1] = 1e30f;
+        for (int r = 0; r < rounds; ++r)
+            for (int v = 0; v < kShapesBf16; ++v) {
+                if (Kp % kBfTN[v] != 0) continue;
+                for (int which = 0; which < 2; ++which)
+                    best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
+            }
+        float bx = 1e30f, bt = 1e30f;
+        for (int v = 0; v < kShapesBf16; ++v) {
+            if (Kp % kBfTN[v] != 0) continue;
+            if (best[v][0] < bx) { bx = best[v][0]; tc.xw = v; }
+            if (best[v][1] < bt) { bt = best[v][1]; tc.xtu = v; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(hipGetLastError());
+    }
+    return in.tiles[key] = tc;
+}
+
+// One sweep of the BF16 form on the FP32 state (anch = false), or an anchored
+// sweep in BF16 mode (anch = true: products of d = W - w_a, FP64 update).
+void sweep_once_bf16(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate, bool anch) {
+    Workspace &ws = ctx->ws;
+    Sweep<float> s32 = sweep32(ctx);
+    const TileChoice &tc = tile_choice_bf16(ctx, Kp);
     prof_begin(ctx, PROF_GEMM_XW_BF16);
-    hipLaunchKernelGGL(k_gemm_xw_bf16, g1, dim3(64 * kWavesBf16), 0, s, in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), pp, sw.W, pp,
-                       sw.U, np, pp, active_cols(ctx));
+    launch_xw_bf16(tc.xw, ctx, s32.W, s32.U, Kp, active_cols(ctx));
     prof_end(ctx, PROF_GEMM_XW_BF16, active);
     prof_begin(ctx, PROF_ADMM_XTU_BF16);
-    hipLaunchKernelGGL(k_admm_xtu_bf16, g2, dim3(64 * kWavesBf16), 0, s, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(), np, sw.U, np,
-                       np, sw.W, sw.beta, sw.V, sw.B, ws.codes.as<uint8_t>(), sw.c, ws.active.as<int>(), q, pp,
-                       store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, gate_args(in), active_cols(ctx));
+    launch_xtu_bf16(tc.xtu, ctx, anch, Kp, ws.active.as<int>(), store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr,
+                    active_cols(ctx));
     prof_end(ctx, PROF_ADMM_XTU_BF16, active);
     HIPCHK(hipGetLastError());
 }
@@ -1414,14 +1728,17 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     for (int t = 1; t <= n; ++t) {
         const bool last = t == n, gate = last && !force;
         if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), Kp, last, active, gate);
-        else if (kind == SK_BF16) sweep_once_bf16(ctx, sweep32(ctx), Kp, last, active, gate);
+        else if (kind == SK_BF16) sweep_once_bf16(ctx, Kp, last, active, gate, false);
+        else if (kind == SK_ANCH && in.prec == L0L2_BF16) sweep_once_bf16(ctx, Kp, last, active, gate, true);
         else if (kind == SK_ANCH) sweep_once_anch(ctx, Kp, last, active, gate);
         else sweep_once<float>(ctx, sweep32(ctx), Kp, last, active, gate);
     }
     if (!force) {
         int rows = 32;
         if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
-        else if (kind == SK_F32 || kind == SK_ANCH) rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
+        else if (kind == SK_BF16 || (kind == SK_ANCH && in.prec == L0L2_BF16))
+            rows = kBfTM[tile_choice_bf16(ctx, Kp).xtu];
+        else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
         GateFin gf{in.yy, tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
@@ -1454,8 +1771,10 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
             // settle the tile shapes (the autotuner synchronises) before capturing
+            const bool bf = ctx->inst.prec == L0L2_BF16;
             if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), Kp);
-            if (kind == SK_F32 || kind == SK_ANCH) (void)tile_choice<float>(ctx, sweep32(ctx), Kp);
+            if (kind == SK_F32 || (kind == SK_ANCH && !bf)) (void)tile_choice<float>(ctx, sweep32(ctx), Kp);
+            if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, Kp);
             hipGraph_t g = nullptr;
             hipGraphExec_t ex = nullptr;
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
@@ -1529,7 +1848,7 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
         const int n = std::min(m, o.max_iter - t);
-        const int kind = fp64 ? (bf16 ? SK_F64 : SK_ANCH) : (bf16 ? SK_BF16 : SK_F32);
+        const int kind = fp64 ? SK_ANCH : (bf16 ? SK_BF16 : SK_F32);
         run_block(ctx, kind, Kp, n, o.tol_node, switch_tol, active, t + n >= o.max_iter, cnt);
         t += n;
         active = cnt[0];
@@ -1668,7 +1987,7 @@ void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool) {
         const int64_t Kp = round_up(K, kPadNodes);
         Sweep<float> s32 = sweep32(ctx);
         init_batch<float>(ctx, s32, K, Kp);
-        for (int t = 1; t <= sweeps; ++t) sweep_once_bf16(ctx, s32, Kp, t == sweeps, K);
+        for (int t = 1; t <= sweeps; ++t) sweep_once_bf16(ctx, Kp, t == sweeps, K, false, false);
     }
 }
 

@@ -209,16 +209,17 @@ def test_node_solve_mixed_bounds_within_1e5(torch_cuda, cases, name, precision):
         assert lb[k] <= ref["primal"] + 1e-12
 
 
-@pytest.mark.parametrize("name", ["C1", "wide"])
-def test_fp32_mode_reaches_fp64_tolerances(torch_cuda, cases, name):
-    """FP32 mode below its own rounding floor: the anchored FP64 sweeps that
-    follow the FP32 phase multiply only the movement since the block's FP64
-    anchor in FP32, so a 1e-9 gap is reached and the FP64 bound agrees with the
-    oracle's to 1e-8 of the primal value."""
+@pytest.mark.parametrize("name,precision", [("C1", "fp32"), ("wide", "fp32"), ("C1", "bf16"), ("wide", "bf16")])
+def test_reduced_modes_reach_fp64_tolerances(torch_cuda, cases, name, precision):
+    """FP32 and BF16 modes below their own rounding floors: the anchored FP64
+    sweeps that follow the reduced phase multiply only the movement since the
+    block's FP64 anchor (in FP32, or in the BF16 split form), so a 1e-9 gap is
+    reached and the FP64 bound agrees with the oracle's to 1e-8 of the primal
+    value."""
     inst, o, root = cases[name]
     K = 24
     codes, beta0, v0 = random_nodes(inst.p, K, 8, root["beta"], root["v"])
-    ctx = ctx_for(inst, "fp32")
+    ctx = ctx_for(inst, precision)
     ctx.profile_enable(True)
     res = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-9, max_iter=6000, check_every=10)
     assert ctx.profile_query("anchor.f64")[0] > 0
