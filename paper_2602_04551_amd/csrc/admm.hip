@@ -1593,20 +1593,20 @@ void sweep_once_bf16(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
 }
 
 // Start of an anchored block: w_a = W (FP64), d = 0, z_a = Xh^T (Xh w_a) in FP64.
-void anchor_start(l0l2_ctx *ctx, int64_t Kp) {
+void anchor_start(l0l2_ctx *ctx, int64_t Kp, int64_t cols) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     const int64_t np = in.np, pp = in.pp;
     Sweep<double> s64 = sweep64(ctx);
     Sweep<float> s32 = sweep32(ctx);
-    const TileChoice &tc = tile_choice<double>(ctx, s64, Kp);
+    const TileChoice &tc = tile_choice<double>(ctx, s64, cols);
     prof_begin(ctx, PROF_ANCHOR);
     hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * pp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
                        Kp * pp);
-    launch_xw<double, double, double>(tc.xw, s, s64.XhR, pp, ws.Wa.as<double>(), pp, s64.U, np, np, Kp, pp,
+    launch_xw<double, double, double>(tc.xw, s, s64.XhR, pp, ws.Wa.as<double>(), pp, s64.U, np, np, cols, pp,
                                       active_cols(ctx));
-    launch_xw<double, double, double>(tc.xw, s, s64.Xh, np, s64.U, np, ws.Za.as<double>(), pp, pp, Kp, np,
+    launch_xw<double, double, double>(tc.xw, s, s64.Xh, np, s64.U, np, ws.Za.as<double>(), pp, pp, cols, np,
                                       active_cols(ctx));
     prof_end(ctx, PROF_ANCHOR);
     HIPCHK(hipGetLastError());
@@ -1717,28 +1717,40 @@ enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2, SK_ANCH = 3 };
 // Unless force is set, the last sweep also forms the gap estimate and the exact
 // check evaluates only the nodes that may pass the tolerance; the others stay
 // active and are counted above switch_tol by their estimate.
+// Node columns a block's sweep launches cover: the active count rounded up to a
+// power of two (at least 32, at most the padded batch).  Tile shapes are tuned
+// per such bucket, since the best shape for a few live nodes is not the best
+// for a full batch.  Fixed shapes (l0l2_set_tiles) always cover the whole batch.
+int64_t live_bucket(const l0l2_ctx *ctx, int64_t active, int64_t Kp) {
+    if (ctx->force_xw >= 0) return Kp;
+    int64_t b = kPadNodes;
+    while (b < active) b *= 2;
+    return std::min(b, Kp);
+}
+
 void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
                  bool force) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
+    const int64_t cols = live_bucket(ctx, active, Kp);
     hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>(),
                        ws.ncount.as<int>(), ws.counter.as<int>());
-    if (kind == SK_ANCH) anchor_start(ctx, Kp);
+    if (kind == SK_ANCH) anchor_start(ctx, Kp, cols);
     for (int t = 1; t <= n; ++t) {
         const bool last = t == n, gate = last && !force;
-        if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), Kp, last, active, gate);
-        else if (kind == SK_BF16) sweep_once_bf16(ctx, Kp, last, active, gate, false);
-        else if (kind == SK_ANCH && in.prec == L0L2_BF16) sweep_once_bf16(ctx, Kp, last, active, gate, true);
-        else if (kind == SK_ANCH) sweep_once_anch(ctx, Kp, last, active, gate);
-        else sweep_once<float>(ctx, sweep32(ctx), Kp, last, active, gate);
+        if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), cols, last, active, gate);
+        else if (kind == SK_BF16) sweep_once_bf16(ctx, cols, last, active, gate, false);
+        else if (kind == SK_ANCH && in.prec == L0L2_BF16) sweep_once_bf16(ctx, cols, last, active, gate, true);
+        else if (kind == SK_ANCH) sweep_once_anch(ctx, cols, last, active, gate);
+        else sweep_once<float>(ctx, sweep32(ctx), cols, last, active, gate);
     }
     if (!force) {
         int rows = 32;
-        if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), Kp).xtu];
+        if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), cols).xtu];
         else if (kind == SK_BF16 || (kind == SK_ANCH && in.prec == L0L2_BF16))
-            rows = kBfTM[tile_choice_bf16(ctx, Kp).xtu];
-        else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), Kp).xtu];
+            rows = kBfTM[tile_choice_bf16(ctx, cols).xtu];
+        else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), cols).xtu];
         GateFin gf{in.yy, tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
@@ -1767,14 +1779,15 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
     if (!ctx->use_graphs || ctx->prof.on) {
         issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
     } else {
-        GraphKey key{kind, Kp, n, force ? 1 : 0, tol, switch_tol, ws.gen};
+        const int64_t cols = live_bucket(ctx, active, Kp);
+        GraphKey key{kind, Kp, cols, n, force ? 1 : 0, tol, switch_tol, ws.gen};
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
             // settle the tile shapes (the autotuner synchronises) before capturing
             const bool bf = ctx->inst.prec == L0L2_BF16;
-            if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), Kp);
-            if (kind == SK_F32 || (kind == SK_ANCH && !bf)) (void)tile_choice<float>(ctx, sweep32(ctx), Kp);
-            if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, Kp);
+            if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), cols);
+            if (kind == SK_F32 || (kind == SK_ANCH && !bf)) (void)tile_choice<float>(ctx, sweep32(ctx), cols);
+            if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);
             hipGraph_t g = nullptr;
             hipGraphExec_t ex = nullptr;
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {

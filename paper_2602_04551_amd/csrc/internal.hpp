@@ -133,7 +133,7 @@ struct Profiler {
 // A captured block of sweeps + gap check.
 struct GraphKey {
     int kind;
-    int64_t Kp;
+    int64_t Kp, cols;
     int n;
     int force;
     double tol, switch_tol;
@@ -141,6 +141,7 @@ struct GraphKey {
     bool operator<(const GraphKey &o) const {
         if (kind != o.kind) return kind < o.kind;
         if (Kp != o.Kp) return Kp < o.Kp;
+        if (cols != o.cols) return cols < o.cols;
         if (n != o.n) return n < o.n;
         if (force != o.force) return force < o.force;
         if (tol != o.tol) return tol < o.tol;
