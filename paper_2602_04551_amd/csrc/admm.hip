@@ -134,13 +134,17 @@ __device__ __forceinline__ TC sum_waves(const TC *red, int n, int m) {
 // sweep have this shape: over p with A = the row-major copy of Xh and B = the
 // node operand W; over n with A = Xh column-major (a column of Xh is a row of
 // Xh^T) and B = U.  The WAVES waves of the workgroup split the chunks of 16 k
-// (wave w takes chunks [nch w / WAVES, nch (w + 1) / WAVES)); lane l loads 4
-// consecutive k of row l%16 with one vector load per fragment and the 4 MFMAs
-// of a chunk map their k slot to those 4 values for both operands.  Two
-// register stages: the next chunk's loads are issued before the current
-// chunk's MFMAs (deeper rings measured slower on these shapes).  On return red
-// holds every wave's partial sums (layout Red<TM, TN>) and the workgroup is
-// synchronised.  kdim must be a multiple of 16.
+// in pairs (wave w takes pairs [npr w / WAVES, npr (w + 1) / WAVES), npr =
+// kdim / 32); lane l loads 4 consecutive k of row l%16 with one vector load per
+// fragment and the 4 MFMAs of a chunk map their k slot to those 4 values for
+// both operands.  Two register stages: the next chunk's loads are issued before
+// the current chunk's MFMAs.  The loop body has no branch and scheduling
+// barriers keep each load group ahead of the MFMAs that do not need it, so the
+// wait before a chunk's MFMAs covers only that chunk's loads (a conditional
+// load, or a load the scheduler sinks below the MFMAs, makes that wait cover
+// the next chunk's loads too).  On return red holds every wave's partial sums
+// (layout Red<TM, TN>) and the workgroup is synchronised.  kdim must be a
+// multiple of 32.
 // ---------------------------------------------------------------------------
 // Node columns of a launch.  Column c of the grid's node range is node slot
 // cols[c] for c < count; columns at or past count are idle (their workgroups
@@ -178,30 +182,35 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     AccT acc[BM][BN];
     for (int i = 0; i < BM; ++i)
         for (int j = 0; j < BN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
-    const int64_t nch = kdim / 16;
-    const int64_t c0 = nch * w / WAVES, c1 = nch * (w + 1) / WAVES;
+    const int64_t npr = kdim / 32;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int64_t c0 = 2 * (npr * wu / WAVES), c1 = 2 * (npr * (wu + 1) / WAVES);
     const TA *Ap[BM];
     const TB *Bp[BN];
     for (int i = 0; i < BM; ++i) Ap[i] = A + (m0 + 16 * i + r) * lda + 4 * q;
     for (int j = 0; j < BN; ++j) Bp[j] = B + col_slot(ncl, n0 + 16 * j + r, cnt) * ldb + 4 * q;
     TA a0[BM][4], a1[BM][4];
     TB b0[BN][4], b1[BN][4];
-    int64_t c = c0;
-    if (c < c1) {
-        for (int i = 0; i < BM; ++i) load4(Ap[i] + 16 * c, a0[i]);
-        for (int j = 0; j < BN; ++j) load4(Bp[j] + 16 * c, b0[j]);
-    }
-    for (; c + 1 < c1; c += 2) {
-        for (int i = 0; i < BM; ++i) load4(Ap[i] + 16 * (c + 1), a1[i]);
-        for (int j = 0; j < BN; ++j) load4(Bp[j] + 16 * (c + 1), b1[j]);
-        mma_chunk<TC, BM, BN>(acc, a0, b0);
-        if (c + 2 < c1) {
-            for (int i = 0; i < BM; ++i) load4(Ap[i] + 16 * (c + 2), a0[i]);
-            for (int j = 0; j < BN; ++j) load4(Bp[j] + 16 * (c + 2), b0[j]);
+#define L0L2_LD(a, b, c)                                                  \
+    for (int i = 0; i < BM; ++i) load4(Ap[i] + 16 * (c), a[i]);          \
+    for (int j = 0; j < BN; ++j) load4(Bp[j] + 16 * (c), b[j]);          \
+    __builtin_amdgcn_sched_barrier(0);
+    if (c0 < c1) {
+        L0L2_LD(a0, b0, c0)
+        int64_t c = c0;
+        for (; c + 2 < c1; c += 2) {
+            L0L2_LD(a1, b1, c + 1)
+            mma_chunk<TC, BM, BN>(acc, a0, b0);
+            __builtin_amdgcn_sched_barrier(0);
+            L0L2_LD(a0, b0, c + 2)
+            mma_chunk<TC, BM, BN>(acc, a1, b1);
+            __builtin_amdgcn_sched_barrier(0);
         }
+        L0L2_LD(a1, b1, c + 1)
+        mma_chunk<TC, BM, BN>(acc, a0, b0);
         mma_chunk<TC, BM, BN>(acc, a1, b1);
     }
-    if (c < c1) mma_chunk<TC, BM, BN>(acc, a0, b0);
+#undef L0L2_LD
     for (int i = 0; i < BM; ++i)
         for (int j = 0; j < BN; ++j)
             for (int v = 0; v < 4; ++v) {
@@ -626,8 +635,9 @@ __device__ __forceinline__ void load8f(const float *p, float out[8]) {
 
 // 32 x 32 tile of C[m][n] = sum_k (Ahi + Alo)[m][k] B[n][k] with A rows in BF16
 // (hi, lo) and B rows in FP32 (split into hi, lo on load); chunks of 32 k split
-// over WAVES waves as in nt_tile, next chunk's loads issued before the current
-// chunk's MFMAs.
+// in pairs over WAVES waves, next chunk's loads issued before the current
+// chunk's MFMAs with the branch-free loop of nt_tile.  kdim must be a multiple
+// of 64.
 template <int WAVES>
 __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
                                              int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
@@ -638,8 +648,9 @@ __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, con
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
-    const int64_t nch = kdim / 32;
-    const int64_t c0 = nch * w / WAVES, c1 = nch * (w + 1) / WAVES;
+    const int64_t npr = kdim / 64;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int64_t c0 = 2 * (npr * wu / WAVES), c1 = 2 * (npr * (wu + 1) / WAVES);
     bf16x8 ah[2][2], al[2][2];
     float bv[2][2][8];
     auto load = [&](int st, int64_t c) {
@@ -649,6 +660,7 @@ __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, con
             al[st][a] = *reinterpret_cast<const bf16x8 *>(Alo + o);
         }
         for (int b = 0; b < 2; ++b) load8f(B + brow[b] * ldb + 32 * c + 8 * q, bv[st][b]);
+        __builtin_amdgcn_sched_barrier(0);
     };
     auto compute = [&](int st) {
         bf16x8 bh[2], bl[2];
@@ -660,15 +672,21 @@ __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, con
                 acc[a][b] = mfma16_bf16(al[st][a], bh[b], acc[a][b]);
             }
     };
-    int64_t c = c0;
-    if (c < c1) load(0, c);
-    for (; c + 1 < c1; c += 2) {
+    if (c0 < c1) {
+        load(0, c0);
+        int64_t c = c0;
+        for (; c + 2 < c1; c += 2) {
+            load(1, c + 1);
+            compute(0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(0, c + 2);
+            compute(1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         load(1, c + 1);
         compute(0);
-        if (c + 2 < c1) load(0, c + 2);
         compute(1);
     }
-    if (c < c1) compute(0);
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
             for (int v = 0; v < 4; ++v) {
@@ -939,7 +957,7 @@ template <class T>
 __global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR, int64_t ldx,
                                                   const T *__restrict__ B, const T *__restrict__ beta, int64_t ldb,
                                                   int64_t kdim, const double *__restrict__ y, double *__restrict__ R,
-                                                  int64_t np, double *__restrict__ rpart, NodeCols ncl) {
+                                                  int64_t ldr, double *__restrict__ rpart, NodeCols ncl) {
     constexpr int WAVES = 8;
     __shared__ double red[WAVES * Red<32, 32>::WS];
     const bool with_b = blockIdx.z == 0;
@@ -956,7 +974,7 @@ __global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR,
         const double rv = yi - sum_waves<double, 32, 32, WAVES>(red, n, m);
         double e0, e1 = 0.0, e2 = 0.0;
         if (with_b) {
-            if (live) R[node * np + i] = rv;
+            if (live) R[node * ldr + i] = rv;
             e0 = rv * rv;
             e1 = yi * rv;
             e2 = fabs(yi) * fabs(rv);
@@ -1189,10 +1207,12 @@ unsigned grid1d(int64_t total) { return (unsigned)std::min<int64_t>((total + 255
 // The arrays one sweep works on, in the arithmetic type T of the sweep.
 template <class T>
 struct Sweep {
-    const T *Xh;   // np x pp folded operand, column-major
-    const T *XhR;  // the same, row-major
-    const T *c;    // pp
-    T *W, *beta, *V, *B, *U;
+    const T *Xh;   // np x pp folded operand, column-major (column stride ldc)
+    const T *XhR;  // the same, row-major (row stride ldr)
+    const T *c;    // ldp entries
+    T *W, *beta, *V, *B;   // node-state rows of stride ldp
+    T *U;          // ADMM product rows of stride ldu
+    int64_t ldc, ldr, ldu, ldp;
 };
 
 Sweep<double> sweep64(l0l2_ctx *ctx) {
@@ -1200,9 +1220,11 @@ Sweep<double> sweep64(l0l2_ctx *ctx) {
     Workspace &ws = ctx->ws;
     if (in.prec == L0L2_FP64)
         return {in.Xh.as<double>(), in.XhRw.as<double>(), in.c64.as<double>(), ws.W.as<double>(),
-                ws.beta.as<double>(), ws.V.as<double>(), ws.B.as<double>(), ws.U.as<double>()};
+                ws.beta.as<double>(), ws.V.as<double>(), ws.B.as<double>(), ws.U.as<double>(),
+                in.ldx, in.ldxr, in.ldu, in.ldp};
     return {in.Xh64.as<double>(), in.Xh64R.as<double>(), in.c64.as<double>(), ws.W64.as<double>(),
-            ws.beta64.as<double>(), ws.V64.as<double>(), ws.B64.as<double>(), ws.U64.as<double>()};
+            ws.beta64.as<double>(), ws.V64.as<double>(), ws.B64.as<double>(), ws.U64.as<double>(),
+            in.ldx, in.ldxr, in.ldu64, in.ldp};
 }
 
 // FP32 state arrays (the FP32 mode's operand; in BF16 mode Xh is the BF16 pair
@@ -1212,7 +1234,8 @@ Sweep<float> sweep32(l0l2_ctx *ctx) {
     Workspace &ws = ctx->ws;
     const bool f32 = in.prec == L0L2_FP32;
     return {f32 ? in.Xh.as<float>() : nullptr, f32 ? in.XhRw.as<float>() : nullptr, in.cst.as<float>(),
-            ws.W.as<float>(), ws.beta.as<float>(), ws.V.as<float>(), ws.B.as<float>(), ws.U.as<float>()};
+            ws.W.as<float>(), ws.beta.as<float>(), ws.V.as<float>(), ws.B.as<float>(), ws.U.as<float>(),
+            in.ldw, in.ldwr, in.ldu, in.ldp};
 }
 
 template <class T> constexpr int prof_xw();
@@ -1278,16 +1301,17 @@ template <class T>
 void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes,
                 const int *active, const DevParams<T> &q, int store_b, double *gpart = nullptr,
                 const GateArgs &ga = GateArgs{}, NodeCols ncl = NodeCols{nullptr, nullptr}) {
+    const int64_t ldp = sw.ldp;
     if (sizeof(T) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XTU(PBM, PBN, PW)                                                                                  \
-    hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V, \
-                       sw.B, codes, sw.c, active, q, pp, store_b, gpart, ga, ncl)
+    hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, sw.ldc, sw.U, sw.ldu, np, sw.W,      \
+                       sw.beta, sw.V, sw.B, codes, sw.c, active, q, ldp, store_b, gpart, ga, ncl)
 #define L0L2_XTUL(WM, WN)                                                                                       \
-    hipLaunchKernelGGL((k_admm_xtu_lds<T, WM, WN>), g, b, 0, s, sw.Xh, np, sw.U, np, np, sw.W, sw.beta, sw.V,     \
-                       sw.B, codes, sw.c, active, q, pp, store_b, gpart, ga, ncl)
+    hipLaunchKernelGGL((k_admm_xtu_lds<T, WM, WN>), g, b, 0, s, sw.Xh, sw.ldc, sw.U, sw.ldu, np, sw.W, sw.beta,  \
+                       sw.V, sw.B, codes, sw.c, active, q, ldp, store_b, gpart, ga, ncl)
     if (v >= 9) {
         switch (v) {
             case 9: L0L2_XTUL(2, 2); break;
@@ -1318,12 +1342,13 @@ void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
     dim3 b((unsigned)(64 * kTileW[v]));
+    const int64_t ldp = s32.ldp;
 #define L0L2_XTUA(PBM, PBN, PW)                                                                                \
-    hipLaunchKernelGGL((k_admm_xtu_anch<PBM, PBN, PW>), g, b, 0, s, s32.Xh, np, s32.U, np, np, Za, Wa, s64.W,     \
-                       s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, pp, store_b, gpart, ga, ncl)
+    hipLaunchKernelGGL((k_admm_xtu_anch<PBM, PBN, PW>), g, b, 0, s, s32.Xh, s32.ldc, s32.U, s32.ldu, np, Za, Wa,  \
+                       s64.W, s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, ldp, store_b, gpart, ga, ncl)
 #define L0L2_XTUAL(WM, WN)                                                                                     \
-    hipLaunchKernelGGL((k_admm_xtu_anch_lds<WM, WN>), g, b, 0, s, s32.Xh, np, s32.U, np, np, Za, Wa, s64.W,       \
-                       s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, pp, store_b, gpart, ga, ncl)
+    hipLaunchKernelGGL((k_admm_xtu_anch_lds<WM, WN>), g, b, 0, s, s32.Xh, s32.ldc, s32.U, s32.ldu, np, Za, Wa,    \
+                       s64.W, s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q, ldp, store_b, gpart, ga, ncl)
     if (v >= 9) {
         switch (v) {
             case 9: L0L2_XTUAL(2, 2); break;
@@ -1381,7 +1406,7 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         auto time_shape = [&](int v, int which, int reps) {
             HIPCHK(hipEventRecord(e0, s));
             for (int t = 0; t < reps; ++t) {
-                if (which == 0) launch_xw<T, T, T>(v, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp);
+                if (which == 0) launch_xw<T, T, T>(v, s, sw.XhR, sw.ldr, sw.W, sw.ldp, sw.U, sw.ldu, np, Kp, pp);
                 else launch_xtu<T>(v, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), inactive.as<int>(), q, 0);
             }
             HIPCHK(hipEventRecord(e1, s));
@@ -1443,7 +1468,7 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
     DevParams<T> q = dev_params<T>(in.mp);
     const TileChoice &tc = tile_choice<T>(ctx, sw, Kp);
     prof_begin(ctx, prof_xw<T>());
-    launch_xw<T, T, T>(tc.xw, s, sw.XhR, pp, sw.W, pp, sw.U, np, np, Kp, pp, active_cols(ctx));
+    launch_xw<T, T, T>(tc.xw, s, sw.XhR, sw.ldr, sw.W, sw.ldp, sw.U, sw.ldu, np, Kp, pp, active_cols(ctx));
     prof_end(ctx, prof_xw<T>(), active);
     prof_begin(ctx, prof_xtu<T>());
     launch_xtu<T>(tc.xtu, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), ws.active.as<int>(), q, store_b ? 1 : 0,
@@ -1464,12 +1489,16 @@ void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, 
     if (v < 0 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(np / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
     const __bf16 *hi = in.XhR.as<__bf16>(), *lo = in.XhRLo.as<__bf16>();
+    const int64_t lda = in.ldwr, ldb = in.ldp, ldu = in.ldu;
     if (v == 0)
-        hipLaunchKernelGGL(k_gemm_xw_bf16, g, dim3(64 * kWavesBf16), 0, ctx->stream, hi, lo, pp, B, pp, U, np, pp, ncl);
+        hipLaunchKernelGGL(k_gemm_xw_bf16, g, dim3(64 * kWavesBf16), 0, ctx->stream, hi, lo, lda, B, ldb, U, ldu, pp,
+                           ncl);
     else if (v == 1)
-        hipLaunchKernelGGL((k_gemm_xw_bf16_lds<2, 2>), g, dim3(256), 0, ctx->stream, hi, lo, pp, B, pp, U, np, pp, ncl);
+        hipLaunchKernelGGL((k_gemm_xw_bf16_lds<2, 2>), g, dim3(256), 0, ctx->stream, hi, lo, lda, B, ldb, U, ldu, pp,
+                           ncl);
     else
-        hipLaunchKernelGGL((k_gemm_xw_bf16_lds<4, 4>), g, dim3(256), 0, ctx->stream, hi, lo, pp, B, pp, U, np, pp, ncl);
+        hipLaunchKernelGGL((k_gemm_xw_bf16_lds<4, 4>), g, dim3(256), 0, ctx->stream, hi, lo, lda, B, ldb, U, ldu, pp,
+                           ncl);
 }
 
 // Contraction over n in the BF16 split form: FP32 update (anch = false, on the
@@ -1482,6 +1511,7 @@ void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *act
     if (v < 0 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
     const __bf16 *hi = in.Xh.as<__bf16>(), *lo = in.XhLo.as<__bf16>();
+    const int64_t lda = in.ldw, ldu = in.ldu, ldp = in.ldp;
     Sweep<float> s32 = sweep32(ctx);
     Sweep<double> s64 = sweep64(ctx);
     const DevParams<float> q32 = dev_params<float>(in.mp);
@@ -1492,18 +1522,18 @@ void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *act
     hipStream_t s = ctx->stream;
     if (v == 0) {
         if (anch)
-            hipLaunchKernelGGL(k_admm_xtu_anch_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, np, s32.U, np, np, Za, Wa,
-                               s64.W, s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q64, pp, store_b, gpart, ga,
-                               ncl);
+            hipLaunchKernelGGL(k_admm_xtu_anch_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, lda, s32.U, ldu, np, Za,
+                               Wa, s64.W, s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q64, ldp, store_b,
+                               gpart, ga, ncl);
         else
-            hipLaunchKernelGGL(k_admm_xtu_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, np, s32.U, np, np, s32.W,
-                               s32.beta, s32.V, s32.B, codes, s32.c, active, q32, pp, store_b, gpart, ga, ncl);
+            hipLaunchKernelGGL(k_admm_xtu_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, lda, s32.U, ldu, np, s32.W,
+                               s32.beta, s32.V, s32.B, codes, s32.c, active, q32, ldp, store_b, gpart, ga, ncl);
         return;
     }
 #define L0L2_XTUB(WM, WN, A)                                                                                    \
-    hipLaunchKernelGGL((k_admm_xtu_bf16_lds<WM, WN, A>), g, dim3(256), 0, s, hi, lo, np, s32.U, np, np, s32.W,      \
+    hipLaunchKernelGGL((k_admm_xtu_bf16_lds<WM, WN, A>), g, dim3(256), 0, s, hi, lo, lda, s32.U, ldu, np, s32.W,   \
                        s32.beta, s32.V, s32.B, Za, Wa, s64.W, s64.beta, s64.V, s64.B, codes, s32.c, s64.c, active, \
-                       q32, q64, pp, store_b, gpart, ga, ncl)
+                       q32, q64, ldp, store_b, gpart, ga, ncl)
     if (v == 1) {
         if (anch) L0L2_XTUB(2, 2, 1);
         else L0L2_XTUB(2, 2, 0);
@@ -1602,12 +1632,13 @@ void anchor_start(l0l2_ctx *ctx, int64_t Kp, int64_t cols) {
     Sweep<float> s32 = sweep32(ctx);
     const TileChoice &tc = tile_choice<double>(ctx, s64, cols);
     prof_begin(ctx, PROF_ANCHOR);
-    hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * pp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
-                       Kp * pp);
-    launch_xw<double, double, double>(tc.xw, s, s64.XhR, pp, ws.Wa.as<double>(), pp, s64.U, np, np, cols, pp,
-                                      active_cols(ctx));
-    launch_xw<double, double, double>(tc.xw, s, s64.Xh, np, s64.U, np, ws.Za.as<double>(), pp, pp, cols, np,
-                                      active_cols(ctx));
+    const int64_t ldp = in.ldp;
+    hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
+                       Kp * ldp);
+    launch_xw<double, double, double>(tc.xw, s, s64.XhR, s64.ldr, ws.Wa.as<double>(), ldp, s64.U, s64.ldu, np, cols,
+                                      pp, active_cols(ctx));
+    launch_xw<double, double, double>(tc.xw, s, s64.Xh, s64.ldc, s64.U, s64.ldu, ws.Za.as<double>(), ldp, pp, cols,
+                                      np, active_cols(ctx));
     prof_end(ctx, PROF_ANCHOR);
     HIPCHK(hipGetLastError());
 }
@@ -1622,7 +1653,8 @@ void sweep_once_anch(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
     Sweep<double> s64 = sweep64(ctx);
     const TileChoice &tc = tile_choice<float>(ctx, s32, Kp);
     prof_begin(ctx, PROF_GEMM_XW_F32);
-    launch_xw<float, float, float>(tc.xw, s, s32.XhR, pp, s32.W, pp, s32.U, np, np, Kp, pp, active_cols(ctx));
+    launch_xw<float, float, float>(tc.xw, s, s32.XhR, s32.ldr, s32.W, s32.ldp, s32.U, s32.ldu, np, Kp, pp,
+                                   active_cols(ctx));
     prof_end(ctx, PROF_GEMM_XW_F32, active);
     prof_begin(ctx, PROF_ADMM_XTU_F32);
     launch_xtu_anch(tc.xtu, s, s32, s64, ws.Za.as<double>(), ws.Wa.as<double>(), np, pp, Kp,
@@ -1661,12 +1693,13 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     dim3 g1((unsigned)ntr, (unsigned)(Kp / 32), mode == 0 ? 2u : 1u);
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     prof_begin(ctx, PROF_CHECK);
-    hipLaunchKernelGGL((k_check_xr<T>), g1, dim3(512), 0, s, in.X64R.as<double>(), pp, B, beta, pp, pp,
-                       in.y64.as<double>(), ws.R.as<double>(), np, ws.rpart.as<double>(), ncl);
+    hipLaunchKernelGGL((k_check_xr<T>), g1, dim3(512), 0, s, in.X64R.as<double>(), in.ldxr, B, beta, in.ldp, pp,
+                       in.y64.as<double>(), ws.R.as<double>(), in.ldu64, ws.rpart.as<double>(), ncl);
     DualArgs da = dual_args(in);
-    hipLaunchKernelGGL((k_dual_xtr<T>), g2, dim3(64 * kWavesDual), 0, s, in.X64.as<double>(), np, ws.R.as<double>(),
-                       np, np, ws.codes.as<uint8_t>(), mode == 0 ? beta : B, in.colnrm.as<double>(),
-                       ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), pp, da, ncl);
+    hipLaunchKernelGGL((k_dual_xtr<T>), g2, dim3(64 * kWavesDual), 0, s, in.X64.as<double>(), in.ldx,
+                       ws.R.as<double>(), in.ldu64, np, ws.codes.as<uint8_t>(), mode == 0 ? beta : B,
+                       in.colnrm.as<double>(), ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(),
+                       in.ldp, da, ncl);
     FinArgs fa;
     const double u = 1.1102230246251565e-16;
     fa.gamma_n2 = ((double)in.n + 2.0) * u / (1.0 - ((double)in.n + 2.0) * u);
@@ -1697,8 +1730,8 @@ void init_batch(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t K, int64_t Kp) {
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
                        ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(), ws.count.as<int>(), K, Kp,
                        ws.sweep_no.as<int>());
-    hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta, sw.V,
-                       sw.W, sw.c, (T)in.mp.rho, in.pp, Kp * in.pp);
+    hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.ldp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta,
+                       sw.V, sw.W, sw.c, (T)in.mp.rho, in.ldp, Kp * in.ldp);
     HIPCHK(hipGetLastError());
 }
 
@@ -1870,16 +1903,16 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
             if (cnt[1] < best_above) { best_above = cnt[1]; flat = 0; }
             else ++flat;
             if (cnt[1] == 0 || flat >= 5 || 2 * t >= o.max_iter) {
-                hipLaunchKernelGGL(k_promote, dim3(grid1d(Kp * in.pp)), dim3(256), 0, ctx->stream, s32.beta, s32.V,
-                                   s64.beta, s64.V, s64.W, s64.c, in.mp.rho, in.pp, Kp * in.pp);
+                hipLaunchKernelGGL(k_promote, dim3(grid1d(Kp * in.ldp)), dim3(256), 0, ctx->stream, s32.beta, s32.V,
+                                   s64.beta, s64.V, s64.W, s64.c, in.mp.rho, in.ldp, Kp * in.ldp);
                 HIPCHK(hipGetLastError());
                 fp64 = true;
             }
         }
     }
     if (fp64) {
-        hipLaunchKernelGGL(k_demote, dim3(grid1d(Kp * in.pp)), dim3(256), 0, ctx->stream, s64.beta, s64.V, s32.beta,
-                           s32.V, Kp * in.pp);
+        hipLaunchKernelGGL(k_demote, dim3(grid1d(Kp * in.ldp)), dim3(256), 0, ctx->stream, s64.beta, s64.V, s32.beta,
+                           s32.V, Kp * in.ldp);
         HIPCHK(hipGetLastError());
     }
 }
@@ -1899,14 +1932,14 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     const int64_t Kp = round_up(std::max<int64_t>(K, 1), kPadNodes);
     if (Kp <= ws.cap && ws.host_counter) return;
     const size_t sb = state_bytes(in.prec);
-    const int64_t np = in.np, pp = in.pp;
-    ws.W.ensure(sb * Kp * pp);
-    ws.beta.ensure(sb * Kp * pp);
-    ws.V.ensure(sb * Kp * pp);
-    ws.B.ensure(sb * Kp * pp);
-    ws.U.ensure(sb * Kp * np);
-    ws.R.ensure(8 * Kp * np);
-    ws.codes.ensure((size_t)(Kp * pp));
+    const int64_t np = in.np, pp = in.pp, ldp = in.ldp;
+    ws.W.ensure(sb * Kp * ldp);
+    ws.beta.ensure(sb * Kp * ldp);
+    ws.V.ensure(sb * Kp * ldp);
+    ws.B.ensure(sb * Kp * ldp);
+    ws.U.ensure(sb * Kp * in.ldu);
+    ws.R.ensure(8 * Kp * in.ldu64);
+    ws.codes.ensure((size_t)(Kp * ldp));
     ws.rpart.ensure(8 * 4 * Kp * (np / 32));
     ws.part.ensure(8 * 3 * Kp * (pp / 32));
     ws.gpart.ensure(8 * 5 * Kp * (pp / 16));
@@ -1929,18 +1962,18 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ++ws.gen;
     if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 2 * sizeof(int), hipHostMallocDefault));
     if (in.prec != L0L2_FP64) {
-        ws.Wa.ensure(8 * Kp * pp);
-        ws.Za.ensure(8 * Kp * pp);
-        ws.W64.ensure(8 * Kp * pp);
-        ws.beta64.ensure(8 * Kp * pp);
-        ws.V64.ensure(8 * Kp * pp);
-        ws.B64.ensure(8 * Kp * pp);
-        ws.U64.ensure(8 * Kp * np);
-        HIPCHK(hipMemsetAsync(ws.B64.ptr, 0, 8 * Kp * pp, ctx->stream));
+        ws.Wa.ensure(8 * Kp * ldp);
+        ws.Za.ensure(8 * Kp * ldp);
+        ws.W64.ensure(8 * Kp * ldp);
+        ws.beta64.ensure(8 * Kp * ldp);
+        ws.V64.ensure(8 * Kp * ldp);
+        ws.B64.ensure(8 * Kp * ldp);
+        ws.U64.ensure(8 * Kp * in.ldu64);
+        HIPCHK(hipMemsetAsync(ws.B64.ptr, 0, 8 * Kp * ldp, ctx->stream));
     }
     // inactive padded rows must read as zeros on first use
-    HIPCHK(hipMemsetAsync(ws.W.ptr, 0, sb * Kp * pp, ctx->stream));
-    HIPCHK(hipMemsetAsync(ws.B.ptr, 0, sb * Kp * pp, ctx->stream));
+    HIPCHK(hipMemsetAsync(ws.W.ptr, 0, sb * Kp * ldp, ctx->stream));
+    HIPCHK(hipMemsetAsync(ws.B.ptr, 0, sb * Kp * ldp, ctx->stream));
     ws.cap = Kp;
 }
 
@@ -1957,18 +1990,19 @@ void load_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *beta, co
         HIPCHK(hipMemcpyAsync(tmp.ptr, codes, (size_t)K * in.p, hipMemcpyHostToDevice, s));
         dcodes = tmp.as<uint8_t>();
     }
-    hipLaunchKernelGGL(k_load_codes, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, dcodes, (int64_t)K, in.p,
-                       ws.codes.as<uint8_t>(), Kp, in.pp);
+    const int64_t ldp = in.ldp;
+    hipLaunchKernelGGL(k_load_codes, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, dcodes, (int64_t)K, in.p,
+                       ws.codes.as<uint8_t>(), Kp, ldp);
     if (in.prec == L0L2_FP64) {
-        hipLaunchKernelGGL(k_load_state<double>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const double *)beta,
-                           (int64_t)K, in.p, ws.beta.as<double>(), Kp, in.pp);
-        hipLaunchKernelGGL(k_load_state<double>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const double *)v,
-                           (int64_t)K, in.p, ws.V.as<double>(), Kp, in.pp);
+        hipLaunchKernelGGL(k_load_state<double>, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, (const double *)beta,
+                           (int64_t)K, in.p, ws.beta.as<double>(), Kp, ldp);
+        hipLaunchKernelGGL(k_load_state<double>, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, (const double *)v,
+                           (int64_t)K, in.p, ws.V.as<double>(), Kp, ldp);
     } else {
-        hipLaunchKernelGGL(k_load_state<float>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const float *)beta,
-                           (int64_t)K, in.p, ws.beta.as<float>(), Kp, in.pp);
-        hipLaunchKernelGGL(k_load_state<float>, dim3(grid1d(Kp * in.pp)), dim3(256), 0, s, (const float *)v,
-                           (int64_t)K, in.p, ws.V.as<float>(), Kp, in.pp);
+        hipLaunchKernelGGL(k_load_state<float>, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, (const float *)beta,
+                           (int64_t)K, in.p, ws.beta.as<float>(), Kp, ldp);
+        hipLaunchKernelGGL(k_load_state<float>, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, (const float *)v,
+                           (int64_t)K, in.p, ws.V.as<float>(), Kp, ldp);
     }
     HIPCHK(hipGetLastError());
     if (codes_on_host) HIPCHK(hipStreamSynchronize(s));
@@ -1980,13 +2014,13 @@ void store_batch(l0l2_ctx *ctx, int K, void *beta, void *v, void *b) {
     hipStream_t s = ctx->stream;
     unsigned g = grid1d((int64_t)K * in.p);
     if (in.prec == L0L2_FP64) {
-        if (beta) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.beta.as<double>(), (int64_t)K, in.p, in.pp, (double *)beta);
-        if (v) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.V.as<double>(), (int64_t)K, in.p, in.pp, (double *)v);
-        if (b) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.B.as<double>(), (int64_t)K, in.p, in.pp, (double *)b);
+        if (beta) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.beta.as<double>(), (int64_t)K, in.p, in.ldp, (double *)beta);
+        if (v) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.V.as<double>(), (int64_t)K, in.p, in.ldp, (double *)v);
+        if (b) hipLaunchKernelGGL(k_store_state<double>, dim3(g), dim3(256), 0, s, ws.B.as<double>(), (int64_t)K, in.p, in.ldp, (double *)b);
     } else {
-        if (beta) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.beta.as<float>(), (int64_t)K, in.p, in.pp, (float *)beta);
-        if (v) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.V.as<float>(), (int64_t)K, in.p, in.pp, (float *)v);
-        if (b) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.B.as<float>(), (int64_t)K, in.p, in.pp, (float *)b);
+        if (beta) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.beta.as<float>(), (int64_t)K, in.p, in.ldp, (float *)beta);
+        if (v) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.V.as<float>(), (int64_t)K, in.p, in.ldp, (float *)v);
+        if (b) hipLaunchKernelGGL(k_store_state<float>, dim3(g), dim3(256), 0, s, ws.B.as<float>(), (int64_t)K, in.p, in.ldp, (float *)b);
     }
     HIPCHK(hipGetLastError());
 }

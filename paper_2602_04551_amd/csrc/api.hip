@@ -195,7 +195,7 @@ int l0l2_dual_bound(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *b, d
         auto &ws = ctx->ws;
         const int64_t Kp = l0l2::round_up(K, l0l2::kPadNodes);
         size_t sb = l0l2::state_bytes(ctx->inst.prec);
-        HIPCHK(hipMemcpyAsync(ws.B.ptr, ws.beta.ptr, sb * Kp * ctx->inst.pp, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(ws.B.ptr, ws.beta.ptr, sb * Kp * ctx->inst.ldp, hipMemcpyDeviceToDevice, ctx->stream));
         l0l2::run_dual_bound(ctx, K, nullptr);
         HIPCHK(hipMemcpyAsync(lb, ws.lb.ptr, sizeof(double) * K, hipMemcpyDeviceToDevice, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));

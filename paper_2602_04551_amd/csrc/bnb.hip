@@ -131,7 +131,8 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t st = ctx->stream;
-    const int64_t p = in.p, pp = in.pp;
+    // state and code rows (and the warm-start pool's rows) have stride ldp
+    const int64_t p = in.p, pp = in.ldp;
     const int K = std::max(1, o.K);
     ensure_workspace(ctx, K);
     DevicePool pool;

@@ -101,15 +101,16 @@ struct FistaArgs {
     double l0, l2, M, tol;
     int max_iter;
     int64_t n, np, p;
+    int64_t ldx;   // column stride of X
 };
 
 // U_S(v) = 1/2 ||X_S v - y||^2 + l2 ||v||^2; optionally keeps the residual.
-__device__ double U_S(const double *__restrict__ X, int64_t np, const double *__restrict__ y, const int *idx, int k,
+__device__ double U_S(const double *__restrict__ X, int64_t ldx, const double *__restrict__ y, const int *idx, int k,
                       const double *v, double *res, bool keep, double *sh, const FistaArgs &fa) {
     double rr = 0.0;
     for (int64_t i = threadIdx.x; i < fa.n; i += 256) {
         double s = 0.0;
-        for (int a = 0; a < k; ++a) s += X[(int64_t)idx[a] * np + i] * v[a];
+        for (int a = 0; a < k; ++a) s += X[(int64_t)idx[a] * ldx + i] * v[a];
         double r = s - y[i];
         if (keep) res[i] = r;
         rr += r * r;
@@ -186,7 +187,7 @@ __device__ __forceinline__ double gram_mv(FistaShared &sm, double v, int k, int 
 // load a valid column and contribute zeros.  The 4 waves split the rows and
 // only the lower block triangle is formed.
 template <int NB>
-__device__ void gram_build_nb(FistaShared &sm, const double *__restrict__ X, int64_t np, int k) {
+__device__ void gram_build_nb(FistaShared &sm, const double *__restrict__ X, int64_t ldx, int64_t np, int k) {
     constexpr int TRI = NB * (NB + 1) / 2;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int q = lane >> 4, r = lane & 15;
@@ -197,7 +198,7 @@ __device__ void gram_build_nb(FistaShared &sm, const double *__restrict__ X, int
     for (int bi = 0; bi < NB; ++bi) {
         const int a = 16 * bi + r;
         valid[bi] = a < k;
-        col[bi] = X + (int64_t)sm.idx[valid[bi] ? a : 0] * np + 4 * q;
+        col[bi] = X + (int64_t)sm.idx[valid[bi] ? a : 0] * ldx + 4 * q;
     }
     const int64_t nch = np / 16;
     const int64_t c0 = nch * w / 4, c1 = nch * (w + 1) / 4;
@@ -256,12 +257,12 @@ __device__ void gram_build_nb(FistaShared &sm, const double *__restrict__ X, int
     }
 }
 
-__device__ void gram_build(FistaShared &sm, const double *__restrict__ X, int64_t np, int k) {
+__device__ void gram_build(FistaShared &sm, const double *__restrict__ X, int64_t ldx, int64_t np, int k) {
     switch ((k + 15) / 16) {
-        case 1: gram_build_nb<1>(sm, X, np, k); break;
-        case 2: gram_build_nb<2>(sm, X, np, k); break;
-        case 3: gram_build_nb<3>(sm, X, np, k); break;
-        default: gram_build_nb<4>(sm, X, np, k); break;
+        case 1: gram_build_nb<1>(sm, X, ldx, np, k); break;
+        case 2: gram_build_nb<2>(sm, X, ldx, np, k); break;
+        case 3: gram_build_nb<3>(sm, X, ldx, np, k); break;
+        default: gram_build_nb<4>(sm, X, ldx, np, k); break;
     }
 }
 
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         return;
     }
     if (k <= kGramMax) {
-        gram_build(sm, X, fa.np, k);
+        gram_build(sm, X, fa.ldx, fa.np, k);
         if (w == 0) {
             const bool on = lane < k;
             const double g = on ? c[idx[lane]] : 0.0;
@@ -373,16 +374,16 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         }
         fro = bsum(fro, sm.sh);
         double alpha = 4.0 / (fro + 2.0 * fa.l2);
-        double Ucur = U_S(X, fa.np, y, idx, k, sm.cur, res, false, sm.sh, fa);
+        double Ucur = U_S(X, fa.ldx, y, idx, k, sm.cur, res, false, sm.sh, fa);
         int it = 0;
         while (it < fa.max_iter) {
             double mom = (double)it / ((double)it + 3.0);
             for (int a = tid; a < k; a += 256) sm.ext[a] = sm.cur[a] + mom * (sm.cur[a] - sm.prev[a]);
             __syncthreads();
-            double Uext = U_S(X, fa.np, y, idx, k, sm.ext, res, true, sm.sh, fa);
+            double Uext = U_S(X, fa.ldx, y, idx, k, sm.ext, res, true, sm.sh, fa);
             __syncthreads();
             for (int a = w; a < k; a += 4) {
-                const double *col = X + (int64_t)idx[a] * fa.np;
+                const double *col = X + (int64_t)idx[a] * fa.ldx;
                 double s = 0.0;
                 for (int64_t i = lane; i < fa.n; i += 64) s += col[i] * res[i];
                 for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
                 }
                 gd = bsum(gd, sm.sh);
                 dd = bsum(dd, sm.sh);
-                Unxt = U_S(X, fa.np, y, idx, k, sm.nxt, res, false, sm.sh, fa);
+                Unxt = U_S(X, fa.ldx, y, idx, k, sm.nxt, res, false, sm.sh, fa);
                 if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
                 alpha *= 0.5;
             }
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         if (tid == 0) sm.it = it;
         __syncthreads();
     }
-    double f = U_S(X, fa.np, y, idx, k, sm.cur, res, false, sm.sh, fa) + fa.l0 * (double)k;
+    double f = U_S(X, fa.ldx, y, idx, k, sm.cur, res, false, sm.sh, fa) + fa.l0 * (double)k;
     for (int64_t j = tid; j < fa.p; j += 256) beta[node * ldb + j] = 0.0;
     __syncthreads();
     for (int a = tid; a < k; a += 256) beta[node * ldb + idx[a]] = sm.cur[a];
@@ -445,7 +446,7 @@ __global__ void k_state_f64(const T *__restrict__ src, int64_t lds, double *__re
 // Exact box-constrained ridge on one support, single workgroup:
 // H = X_S^T X_S + 2 l2 I, g = X_S^T y; Cholesky solve; if the box binds,
 // coordinate descent on 1/2 b^T H b - g^T b over [-M, M]^k.
-__global__ __launch_bounds__(256) void k_exact(const double *__restrict__ X, int64_t np, const double *__restrict__ y,
+__global__ __launch_bounds__(256) void k_exact(const double *__restrict__ X, int64_t ldx, const double *__restrict__ y,
                                                const double *__restrict__ c, const int *__restrict__ idx, int k,
                                                double *__restrict__ H, double *__restrict__ L,
                                                double *__restrict__ bsol, double *__restrict__ res,
@@ -456,7 +457,7 @@ __global__ __launch_bounds__(256) void k_exact(const double *__restrict__ X, int
     for (int e = w; e < k * k; e += 4) {
         int a = e % k, b = e / k;
         if (b > a) continue;
-        const double *ca = X + (int64_t)idx[a] * np, *cb = X + (int64_t)idx[b] * np;
+        const double *ca = X + (int64_t)idx[a] * ldx, *cb = X + (int64_t)idx[b] * ldx;
         double s = 0.0;
         for (int64_t i = lane; i < fa.n; i += 64) s += ca[i] * cb[i];
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -530,7 +531,7 @@ __global__ __launch_bounds__(256) void k_exact(const double *__restrict__ X, int
     double rr = 0.0;
     for (int64_t i = tid; i < fa.n; i += 256) {
         double s = 0.0;
-        for (int a = 0; a < k; ++a) s += X[(int64_t)idx[a] * np + i] * bsol[a];
+        for (int a = 0; a < k; ++a) s += X[(int64_t)idx[a] * ldx + i] * bsol[a];
         double r = s - y[i];
         rr += r * r;
     }
@@ -565,7 +566,7 @@ void run_fista(l0l2_ctx *ctx, int K, const uint8_t *support, int64_t ld_support,
     Instance &in = ctx->inst;
     if (K <= 0) return;
     ctx->ws.fista.ensure(sizeof(double) * (size_t)K * in.np);
-    FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, o.tol, o.max_iter, in.n, in.np, in.p};
+    FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, o.tol, o.max_iter, in.n, in.np, in.p, in.ldx};
     prof_begin(ctx, PROF_FISTA);
     hipLaunchKernelGGL(k_fista, dim3((unsigned)K), dim3(256), 0, ctx->stream, in.X64.as<double>(), in.y64.as<double>(),
                        in.colnrm.as<double>(), in.c64.as<double>(), in.yy, support, ld_support, beta, ld_beta,
@@ -589,8 +590,8 @@ double run_exact_objective(l0l2_ctx *ctx, const uint8_t *support_host, double *b
     b.ensure(sizeof(double) * (size_t)std::max(k, 1));
     out.ensure(sizeof(double));
     if (k) HIPCHK(hipMemcpyAsync(didx.ptr, idx.data(), sizeof(int) * k, hipMemcpyHostToDevice, s));
-    FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, 0.0, 0, in.n, in.np, in.p};
-    hipLaunchKernelGGL(k_exact, dim3(1), dim3(256), 0, s, in.X64.as<double>(), in.np, in.y64.as<double>(),
+    FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, 0.0, 0, in.n, in.np, in.p, in.ldx};
+    hipLaunchKernelGGL(k_exact, dim3(1), dim3(256), 0, s, in.X64.as<double>(), in.ldx, in.y64.as<double>(),
                        in.c64.as<double>(), didx.as<int>(), k, H.as<double>(), L.as<double>(), b.as<double>(),
                        (double *)nullptr, out.as<double>(), fa);
     HIPCHK(hipGetLastError());

@@ -18,6 +18,14 @@ constexpr int kPadNodes = 32;   // K is padded to multiples of this (one GEMM ti
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
+// Leading dimension of a matrix whose rows (or columns) hold `extent` elements
+// of `elem` bytes: the extent plus 64 bytes.  The contraction tiles load a
+// fragment as 64-byte pieces of 16 consecutive rows; with rows a whole number
+// of 128-byte lines apart those loads took up to 35 % longer than with rows
+// offset by half a line (measured at n = p = 1024 and 5120 and at p = 50048,
+// FP32 and FP64).
+inline int64_t ld_pad(int64_t extent, int64_t elem) { return extent + 64 / elem; }
+
 // Error carrying a status code; caught at the C ABI boundary.
 struct Error {
     int code;
@@ -67,22 +75,30 @@ struct TileChoice {
 
 struct Instance {
     int64_t n = 0, p = 0, np = 0, pp = 0;   // true and padded sizes
+    // leading dimensions (elements, ld_pad of the padded extents)
+    int64_t ldx = 0;    // FP64 column-major X64 and FP64 Xh / Xh64 (np + 8)
+    int64_t ldxr = 0;   // FP64 row-major X64R, XhRw (FP64 mode), Xh64R (pp + 8)
+    int64_t ldw = 0;    // working-precision column-major Xh / XhLo (FP32 np + 16, BF16 np + 32)
+    int64_t ldwr = 0;   // working-precision row-major XhRw / XhR / XhRLo (FP32 pp + 16, BF16 pp + 32)
+    int64_t ldp = 0;    // node-state rows (W, beta, V, B, codes and the FP64 copies): pp + 64 bytes of the state type
+    int64_t ldu = 0;    // rows of the ADMM product U in the state type (np + 64 bytes)
+    int64_t ldu64 = 0;  // rows of the FP64 U64 and of the residuals R (np + 8)
     int prec = L0L2_FP64;
     MethodParams mp{};
     double yy = 0.0;                         // ||y||^2
-    DevBuf X64;       // np x pp column-major FP64, zero padded
+    DevBuf X64;       // np x pp column-major FP64 (ld ldx), zero padded
     DevBuf y64;       // np
-    DevBuf c64;       // pp, X^T y
-    DevBuf colnrm;    // pp, ||X_j||
-    DevBuf cst;       // pp, c in state precision
-    DevBuf Xh;        // np x pp column-major, L^{-1} X in working precision (f64 / f32); BF16 mode: high half
-    DevBuf XhLo;      // BF16 mode: column-major low half (Xh - bf16(Xh))
-    DevBuf XhR;       // BF16 mode: row-major high half (row i contiguous over pp)
-    DevBuf XhRLo;     // BF16 mode: row-major low half
-    DevBuf Xh64;      // FP32 / BF16 mode: FP64 folded operand for the final sweeps of a node
-    DevBuf XhRw;      // FP64 / FP32 mode: row-major copy of Xh in the working precision
-    DevBuf Xh64R;     // FP32 / BF16 mode: row-major copy of Xh64
-    DevBuf X64R;      // row-major copy of X64 (contraction over p of the gap check)
+    DevBuf c64;       // ldp, X^T y (zero past p)
+    DevBuf colnrm;    // ldp, ||X_j||
+    DevBuf cst;       // ldp, c in state precision
+    DevBuf Xh;        // np x pp column-major, L^{-1} X in working precision (f64: ld ldx, f32: ld ldw); BF16 mode: high half (ld ldw)
+    DevBuf XhLo;      // BF16 mode: column-major low half (Xh - bf16(Xh)), ld ldw
+    DevBuf XhR;       // BF16 mode: row-major high half (row i contiguous over pp), ld ldwr
+    DevBuf XhRLo;     // BF16 mode: row-major low half, ld ldwr
+    DevBuf Xh64;      // FP32 / BF16 mode: FP64 folded operand of the anchored sweeps (ld ldx)
+    DevBuf XhRw;      // FP64 / FP32 mode: row-major copy of Xh in the working precision (ld ldxr / ldwr)
+    DevBuf Xh64R;     // FP32 / BF16 mode: row-major copy of Xh64 (ld ldxr)
+    DevBuf X64R;      // row-major copy of X64 (contraction over p of the gap check), ld ldxr
     DevBuf codes_pad; // scratch
     std::map<std::pair<int, int64_t>, TileChoice> tiles;   // autotuned per (type, padded K)
 };
@@ -90,13 +106,13 @@ struct Instance {
 // Per-batch workspace, grown on demand (capacity in padded nodes).
 struct Workspace {
     int64_t cap = 0;
-    DevBuf W, beta, V, B;          // Kp x pp state precision
-    DevBuf U;                      // Kp x np state precision (ADMM product)
-    DevBuf W64, beta64, V64, B64;  // FP32 mode: FP64 state of the final sweeps (Kp x pp)
-    DevBuf U64;                    // FP32 mode: Kp x np
-    DevBuf Wa, Za;                 // FP32 mode: anchor w_a and Xh^T Xh w_a of the anchored sweeps (Kp x pp FP64)
-    DevBuf R;                      // Kp x np FP64 residuals of the gap check
-    DevBuf codes;                  // Kp x pp uint8
+    DevBuf W, beta, V, B;          // Kp rows of ldp, state precision
+    DevBuf U;                      // Kp rows of ldu, state precision (ADMM product)
+    DevBuf W64, beta64, V64, B64;  // FP32 / BF16 mode: FP64 state of the anchored sweeps (Kp rows of ldp)
+    DevBuf U64;                    // FP32 / BF16 mode: Kp rows of ldu64
+    DevBuf Wa, Za;                 // FP32 / BF16 mode: anchor w_a and Xh^T Xh w_a (Kp rows of ldp, FP64)
+    DevBuf R;                      // Kp rows of ldu64: FP64 residuals of the gap check
+    DevBuf codes;                  // Kp rows of ldp, uint8
     DevBuf rpart;                  // Kp x (np/32) x 4 doubles: row-tile sums of the gap check
     DevBuf part;                   // Kp x (pp/32) x 3 doubles
     DevBuf gpart;                  // Kp x (pp/16) x 5 doubles: per-tile sums of the gap estimate

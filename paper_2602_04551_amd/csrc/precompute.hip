@@ -12,25 +12,25 @@ namespace l0l2 {
 
 namespace {
 
-// dst (np x pp, ld = np) <- src (n x p, ld = n), zero padding.
+// dst (np x pp, column stride ld) <- src (n x p, ld = n), zero padding.
 __global__ void k_pad_copy(const double *__restrict__ src, int64_t n, int64_t p, double *__restrict__ dst,
-                           int64_t np, int64_t pp) {
+                           int64_t np, int64_t pp, int64_t ld) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = np * pp;
     for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
         int64_t i = idx % np, j = idx / np;
-        dst[idx] = (i < n && j < p) ? src[i + j * n] : 0.0;
+        dst[i + j * ld] = (i < n && j < p) ? src[i + j * n] : 0.0;
     }
 }
 
 // One wave per column: c_j = X_j^T y and ||X_j||.
-__global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ X, const double *__restrict__ y,
-                                                  int64_t np, int64_t pp, double *__restrict__ c,
-                                                  double *__restrict__ nrm) {
+__global__ __launch_bounds__(256) void k_colstats(const double *__restrict__ X, int64_t ldx,
+                                                  const double *__restrict__ y, int64_t np, int64_t pp,
+                                                  double *__restrict__ c, double *__restrict__ nrm) {
     int lane = threadIdx.x & 63;
     int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= pp) return;
-    const double *col = X + j * np;
+    const double *col = X + j * ldx;
     double s = 0.0, q = 0.0;
     for (int64_t i = lane; i < np; i += 64) {
         double x = col[i];
@@ -183,23 +183,23 @@ __global__ __launch_bounds__(64) void k_trsv_rows(const double *S, int64_t lds, 
     for (int i = 0; i < nb; ++i) X[kb + i + col * ldx] = Xc[t][i];
 }
 
-// dst (row-major, row i of length pp) <- src (np x pp column-major), by 32 x 32
-// tiles through LDS so both sides are coalesced.
+// dst (row-major, rows of stride ldd) <- src (np x pp column-major, column
+// stride lds), by 32 x 32 tiles through LDS so both sides are coalesced.
 template <class TS, class TD>
-__global__ __launch_bounds__(256) void k_transpose(const TS *__restrict__ src, TD *__restrict__ dst, int64_t np,
-                                                   int64_t pp) {
+__global__ __launch_bounds__(256) void k_transpose(const TS *__restrict__ src, int64_t lds, TD *__restrict__ dst,
+                                                   int64_t ldd) {
     __shared__ TD t[32][33];
     const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-    for (int r = ty; r < 32; r += 8) t[r][tx] = (TD)src[(j0 + r) * np + i0 + tx];
+    for (int r = ty; r < 32; r += 8) t[r][tx] = (TD)src[(j0 + r) * lds + i0 + tx];
     __syncthreads();
-    for (int r = ty; r < 32; r += 8) dst[(i0 + r) * pp + j0 + tx] = t[tx][r];
+    for (int r = ty; r < 32; r += 8) dst[(i0 + r) * ldd + j0 + tx] = t[tx][r];
 }
 
 template <class TS, class TD>
-void transpose(hipStream_t st, const TS *src, TD *dst, int64_t np, int64_t pp) {
+void transpose(hipStream_t st, const TS *src, int64_t lds, TD *dst, int64_t ldd, int64_t np, int64_t pp) {
     hipLaunchKernelGGL((k_transpose<TS, TD>), dim3((unsigned)(np / 32), (unsigned)(pp / 32)), dim3(256), 0, st, src,
-                       dst, np, pp);
+                       lds, dst, ldd);
     HIPCHK(hipGetLastError());
 }
 
@@ -213,21 +213,33 @@ __global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst
     for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) dst[idx] = (float)src[idx];
 }
 
-// Two-term BF16 split x = hi + lo of the np x pp column-major src, stored
-// column-major and row-major.
-__global__ void k_to_bf16x2(const double *__restrict__ src, __bf16 *__restrict__ col_hi, __bf16 *__restrict__ col_lo,
-                            __bf16 *__restrict__ row_hi, __bf16 *__restrict__ row_lo, int64_t np, int64_t pp) {
+// FP32 rounding of the np x pp column-major src (column stride lds) into dst
+// (column stride ldd).
+__global__ void k_to_f32_cols(const double *__restrict__ src, int64_t lds, float *__restrict__ dst, int64_t ldd,
+                              int64_t np, int64_t pp) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < np * pp; idx += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = idx % np, j = idx / np;
+        dst[i + j * ldd] = (float)src[i + j * lds];
+    }
+}
+
+// Two-term BF16 split x = hi + lo of the np x pp column-major src (column
+// stride lds), stored column-major (stride ldc) and row-major (stride ldr).
+__global__ void k_to_bf16x2(const double *__restrict__ src, int64_t lds, __bf16 *__restrict__ col_hi,
+                            __bf16 *__restrict__ col_lo, int64_t ldc, __bf16 *__restrict__ row_hi,
+                            __bf16 *__restrict__ row_lo, int64_t ldr, int64_t np, int64_t pp) {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t total = np * pp;
     for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
         int64_t i = idx % np, j = idx / np;
-        double x = src[idx];
+        double x = src[i + j * lds];
         __bf16 hi = (__bf16)(float)x;
         __bf16 lo = (__bf16)(float)(x - (double)(float)hi);
-        col_hi[idx] = hi;
-        col_lo[idx] = lo;
-        row_hi[i * pp + j] = hi;
-        row_lo[i * pp + j] = lo;
+        col_hi[i + j * ldc] = hi;
+        col_lo[i + j * ldc] = lo;
+        row_hi[i * ldr + j] = hi;
+        row_lo[i * ldr + j] = lo;
     }
 }
 
@@ -275,6 +287,15 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     in.prec = prec;
     in.mp = make_params(l0, l2, M, rho);
     const int64_t np = in.np, pp = in.pp;
+    const int64_t ws_elem = prec == L0L2_FP64 ? 8 : (prec == L0L2_FP32 ? 4 : 2);   // working-precision bytes
+    in.ldx = ld_pad(np, 8);
+    in.ldxr = ld_pad(pp, 8);
+    in.ldw = prec == L0L2_FP64 ? in.ldx : ld_pad(np, ws_elem);
+    in.ldwr = prec == L0L2_FP64 ? in.ldxr : ld_pad(pp, ws_elem);
+    in.ldp = ld_pad(pp, prec == L0L2_FP64 ? 8 : 4);
+    in.ldu = ld_pad(np, prec == L0L2_FP64 ? 8 : 4);
+    in.ldu64 = ld_pad(np, 8);
+    const int64_t ldx = in.ldx, ldxr = in.ldxr, ldp = in.ldp;
 
     // Stage X and y on the device unpadded, then pad.
     DevBuf Xraw, yraw;
@@ -287,14 +308,19 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
         dX = Xraw.as<double>();
         dy = yraw.as<double>();
     }
-    in.X64.ensure(sizeof(double) * (size_t)(np * pp));
+    // every buffer is cleared first: the gaps between the padded extent and the
+    // leading dimension hold zeros
+    in.X64.ensure(sizeof(double) * (size_t)(ldx * pp));
     in.y64.ensure(sizeof(double) * (size_t)np);
-    in.c64.ensure(sizeof(double) * (size_t)pp);
-    in.colnrm.ensure(sizeof(double) * (size_t)pp);
-    hipLaunchKernelGGL(k_pad_copy, dim3(2048), dim3(256), 0, st, dX, n, p, in.X64.as<double>(), np, pp);
+    in.c64.ensure(sizeof(double) * (size_t)ldp);
+    in.colnrm.ensure(sizeof(double) * (size_t)ldp);
+    HIPCHK(hipMemsetAsync(in.X64.ptr, 0, sizeof(double) * (size_t)(ldx * pp), st));
+    HIPCHK(hipMemsetAsync(in.c64.ptr, 0, sizeof(double) * (size_t)ldp, st));
+    HIPCHK(hipMemsetAsync(in.colnrm.ptr, 0, sizeof(double) * (size_t)ldp, st));
+    hipLaunchKernelGGL(k_pad_copy, dim3(2048), dim3(256), 0, st, dX, n, p, in.X64.as<double>(), np, pp, ldx);
     hipLaunchKernelGGL(k_pad_copy, dim3(64), dim3(256), 0, st, dy, n, (int64_t)1, in.y64.as<double>(), np,
-                       (int64_t)1);
-    hipLaunchKernelGGL(k_colstats, dim3((unsigned)((pp + 3) / 4)), dim3(256), 0, st, in.X64.as<double>(),
+                       (int64_t)1, np);
+    hipLaunchKernelGGL(k_colstats, dim3((unsigned)((pp + 3) / 4)), dim3(256), 0, st, in.X64.as<double>(), ldx,
                        in.y64.as<double>(), np, pp, in.c64.as<double>(), in.colnrm.as<double>());
     HIPCHK(hipGetLastError());
 
@@ -305,7 +331,7 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     HIPCHK(hipMemsetAsync(S.ptr, 0, sizeof(double) * (size_t)(np * np), st));
     HIPCHK(hipMemsetAsync(flag.ptr, 0, sizeof(int), st));
     const double *X64 = in.X64.as<double>();
-    dgemm(st, n, n, p, 1.0, X64, 1, np, X64, np, 1, 0.0, S.as<double>(), np);
+    dgemm(st, n, n, p, 1.0, X64, 1, ldx, X64, ldx, 1, 0.0, S.as<double>(), np);
     hipLaunchKernelGGL(k_add_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, S.as<double>(), np, n,
                        rho);
     HIPCHK(hipGetLastError());
@@ -330,57 +356,67 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
 
     // Xh = L^{-1} X, blocked forward substitution over row blocks of 64.
     // FP64 mode keeps it as the sweep operand; the reduced-precision modes keep
-    // it for the FP64 sweeps that finish each node.
+    // it for the anchored sweeps.  Column stride ldx, as X64.
     double *Xh;
     if (prec == L0L2_FP64) {
-        in.Xh.ensure(sizeof(double) * (size_t)(np * pp));
+        in.Xh.ensure(sizeof(double) * (size_t)(ldx * pp));
         Xh = in.Xh.as<double>();
     } else {
-        in.Xh64.ensure(sizeof(double) * (size_t)(np * pp));
+        in.Xh64.ensure(sizeof(double) * (size_t)(ldx * pp));
         Xh = in.Xh64.as<double>();
     }
-    HIPCHK(hipMemcpyAsync(Xh, X64, sizeof(double) * (size_t)(np * pp), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(Xh, X64, sizeof(double) * (size_t)(ldx * pp), hipMemcpyDeviceToDevice, st));
     for (int64_t kb = 0; kb < n; kb += 64) {
         int nb = (int)std::min<int64_t>(64, n - kb);
-        hipLaunchKernelGGL(k_trsv_rows, dim3((unsigned)((p + 63) / 64)), dim3(64), 0, st, Sd, np, Xh, np, kb, nb,
+        hipLaunchKernelGGL(k_trsv_rows, dim3((unsigned)((p + 63) / 64)), dim3(64), 0, st, Sd, np, Xh, ldx, kb, nb,
                            p);
         int64_t r0 = kb + nb, rem = n - r0;
         if (rem > 0) {
             // X[r0:, :] -= L[r0:, kb:kb+nb] * Xh[kb:kb+nb, :]
-            dgemm(st, rem, p, nb, -1.0, Sd + r0 + kb * np, 1, np, Xh + kb, 1, np, 1.0, Xh + r0, np);
+            dgemm(st, rem, p, nb, -1.0, Sd + r0 + kb * np, 1, np, Xh + kb, 1, ldx, 1.0, Xh + r0, ldx);
         }
         HIPCHK(hipGetLastError());
     }
-    // row-major copies for the contractions over p
-    in.X64R.ensure(sizeof(double) * (size_t)(np * pp));
-    transpose<double, double>(st, X64, in.X64R.as<double>(), np, pp);
+    // row-major copies for the contractions over p (gaps past pp cleared)
+    in.X64R.ensure(sizeof(double) * (size_t)(np * ldxr));
+    HIPCHK(hipMemsetAsync(in.X64R.ptr, 0, sizeof(double) * (size_t)(np * ldxr), st));
+    transpose<double, double>(st, X64, ldx, in.X64R.as<double>(), ldxr, np, pp);
     if (prec == L0L2_FP64) {
-        in.XhRw.ensure(sizeof(double) * (size_t)(np * pp));
-        transpose<double, double>(st, Xh, in.XhRw.as<double>(), np, pp);
+        in.XhRw.ensure(sizeof(double) * (size_t)(np * ldxr));
+        HIPCHK(hipMemsetAsync(in.XhRw.ptr, 0, sizeof(double) * (size_t)(np * ldxr), st));
+        transpose<double, double>(st, Xh, ldx, in.XhRw.as<double>(), ldxr, np, pp);
     } else {
-        in.Xh64R.ensure(sizeof(double) * (size_t)(np * pp));
-        transpose<double, double>(st, Xh, in.Xh64R.as<double>(), np, pp);
+        in.Xh64R.ensure(sizeof(double) * (size_t)(np * ldxr));
+        HIPCHK(hipMemsetAsync(in.Xh64R.ptr, 0, sizeof(double) * (size_t)(np * ldxr), st));
+        transpose<double, double>(st, Xh, ldx, in.Xh64R.as<double>(), ldxr, np, pp);
     }
+    const int64_t ldw = in.ldw, ldwr = in.ldwr;
     if (prec == L0L2_FP32) {
-        in.XhRw.ensure(sizeof(float) * (size_t)(np * pp));
-        transpose<double, float>(st, Xh, in.XhRw.as<float>(), np, pp);
-        in.Xh.ensure(sizeof(float) * (size_t)(np * pp));
-        hipLaunchKernelGGL(k_to_f32, dim3(4096), dim3(256), 0, st, Xh, in.Xh.as<float>(), np * pp);
-        in.cst.ensure(sizeof(float) * (size_t)pp);
-        hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), pp);
+        in.XhRw.ensure(sizeof(float) * (size_t)(np * ldwr));
+        HIPCHK(hipMemsetAsync(in.XhRw.ptr, 0, sizeof(float) * (size_t)(np * ldwr), st));
+        transpose<double, float>(st, Xh, ldx, in.XhRw.as<float>(), ldwr, np, pp);
+        in.Xh.ensure(sizeof(float) * (size_t)(ldw * pp));
+        HIPCHK(hipMemsetAsync(in.Xh.ptr, 0, sizeof(float) * (size_t)(ldw * pp), st));
+        hipLaunchKernelGGL(k_to_f32_cols, dim3(4096), dim3(256), 0, st, Xh, ldx, in.Xh.as<float>(), ldw, np, pp);
+        in.cst.ensure(sizeof(float) * (size_t)ldp);
+        hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), ldp);
     } else if (prec == L0L2_BF16) {
-        const size_t nb = sizeof(__bf16) * (size_t)(np * pp);
-        in.Xh.ensure(nb);
-        in.XhLo.ensure(nb);
-        in.XhR.ensure(nb);
-        in.XhRLo.ensure(nb);
-        hipLaunchKernelGGL(k_to_bf16x2, dim3(4096), dim3(256), 0, st, Xh, in.Xh.as<__bf16>(), in.XhLo.as<__bf16>(),
-                           in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), np, pp);
-        in.cst.ensure(sizeof(float) * (size_t)pp);
-        hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), pp);
+        const size_t nbc = sizeof(__bf16) * (size_t)(ldw * pp), nbr = sizeof(__bf16) * (size_t)(np * ldwr);
+        in.Xh.ensure(nbc);
+        in.XhLo.ensure(nbc);
+        in.XhR.ensure(nbr);
+        in.XhRLo.ensure(nbr);
+        HIPCHK(hipMemsetAsync(in.Xh.ptr, 0, nbc, st));
+        HIPCHK(hipMemsetAsync(in.XhLo.ptr, 0, nbc, st));
+        HIPCHK(hipMemsetAsync(in.XhR.ptr, 0, nbr, st));
+        HIPCHK(hipMemsetAsync(in.XhRLo.ptr, 0, nbr, st));
+        hipLaunchKernelGGL(k_to_bf16x2, dim3(4096), dim3(256), 0, st, Xh, ldx, in.Xh.as<__bf16>(),
+                           in.XhLo.as<__bf16>(), ldw, in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), ldwr, np, pp);
+        in.cst.ensure(sizeof(float) * (size_t)ldp);
+        hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), ldp);
     } else {
-        in.cst.ensure(sizeof(double) * (size_t)pp);
-        HIPCHK(hipMemcpyAsync(in.cst.ptr, in.c64.ptr, sizeof(double) * (size_t)pp, hipMemcpyDeviceToDevice, st));
+        in.cst.ensure(sizeof(double) * (size_t)ldp);
+        HIPCHK(hipMemcpyAsync(in.cst.ptr, in.c64.ptr, sizeof(double) * (size_t)ldp, hipMemcpyDeviceToDevice, st));
     }
     HIPCHK(hipGetLastError());
     // ||y||^2 on the host (one small copy)

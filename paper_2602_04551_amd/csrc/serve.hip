@@ -24,7 +24,8 @@
 namespace l0l2 {
 
 size_t footprint_bytes(int64_t n, int64_t p, int prec, int K) {
-    const double np = (double)round_up(n, kPadRows), pp = (double)round_up(p, kPadRows);
+    // padded extents plus the largest leading-dimension gap (64 bytes of BF16)
+    const double np = (double)ld_pad(round_up(n, kPadRows), 2), pp = (double)ld_pad(round_up(p, kPadRows), 2);
     const double Kp = (double)round_up(std::max(K, 1), kPadNodes);
     const double sb = prec == L0L2_FP64 ? 8.0 : 4.0;
     double inst = 8.0 * np * pp + 32.0 * (np + pp);
