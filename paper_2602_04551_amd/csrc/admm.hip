@@ -71,19 +71,17 @@ __global__ void k_store_state(const T *__restrict__ src, int64_t K, int64_t p, i
 }
 
 // Batch start: nodes 0..K-1 active (the active list is 0..K-1), padding inactive.
-__global__ void k_set_active(int *active, int *status, int *iters, int *list, int *count, int64_t K, int64_t Kp,
+__global__ void k_set_active(int *active, int *status, int *iters, int *list, int *clist, int64_t K, int64_t Kp,
                              int *sweep_no) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < Kp) {
         active[k] = k < K;
         status[k] = 1;
         iters[k] = 0;
-        list[k] = (int)k;
+        list[k] = k < K ? (int)k : -1;
+        clist[k] = -1;
     }
-    if (k == 0) {
-        *sweep_no = 0;
-        *count = (int)K;
-    }
+    if (k == 0) *sweep_no = 0;
 }
 
 // Sweep counter of the batch, advanced at the start of each block of sweeps;
@@ -147,20 +145,35 @@ __device__ __forceinline__ TC sum_waves(const TC *red, int n, int m) {
 // multiple of 32.
 // ---------------------------------------------------------------------------
 // Node columns of a launch.  Column c of the grid's node range is node slot
-// cols[c] for c < count; columns at or past count are idle (their workgroups
-// return at once, or their lanes load a valid row and store nothing).  cols ==
-// nullptr: column c is slot c and every column of the grid is live.  Converged
-// nodes thus cost nothing: the list holds the nodes still active.
+// cols[c]; the list holds the live nodes first and -1 in every entry past them
+// (up to the padded batch), so a column is idle when its entry is negative and
+// a workgroup whose first column is idle has no live column (its workgroup
+// returns at once; an idle column of a live workgroup loads a valid row and
+// stores nothing).  cols == nullptr: column c is slot c and every column of the
+// grid is live.  Converged nodes thus cost nothing: the list holds the nodes
+// still active.  A kernel reads the entries of all its columns first, in one
+// round trip, before it loads anything that depends on them.
 struct NodeCols {
     const int *cols;
-    const int *count;
 };
 
-__device__ __forceinline__ int live_cols(const NodeCols &nc, int grid_cols) {
-    return nc.cols ? *nc.count : grid_cols;
-}
-__device__ __forceinline__ int64_t col_slot(const NodeCols &nc, int64_t c, int cnt) {
-    return nc.cols ? (int64_t)nc.cols[c < cnt ? c : cnt - 1] : c;
+__device__ __forceinline__ int col_slot(const NodeCols &nc, int64_t c) { return nc.cols ? nc.cols[c] : (int)c; }
+// Row of the node arrays read for a column: its slot, or row c (a valid padded
+// row, read but never written) when the column is idle.
+__device__ __forceinline__ int64_t col_row(int slot, int64_t c) { return slot >= 0 ? (int64_t)slot : c; }
+
+// Slots of the BN fragment rows of this lane (rows n0 + 16 j + lane % 16) and of
+// the E epilogue columns of this thread (thread t owns elements t + i 64 WAVES of
+// the TM x TN tile, column = element / TM).  Returns false for an idle tile.
+template <int TM, int BN, int E, int WAVES>
+__device__ __forceinline__ bool tile_slots(const NodeCols &ncl, int64_t n0, int (&sb)[BN], int (&se)[E]) {
+    const int r = threadIdx.x & 15;
+#pragma unroll
+    for (int j = 0; j < BN; ++j) sb[j] = col_slot(ncl, n0 + 16 * j + r);
+#pragma unroll
+    for (int t = 0; t < E; ++t) se[t] = col_slot(ncl, n0 + (threadIdx.x + t * 64 * WAVES) / TM);
+    // lane 0 holds column n0, the first column of the tile
+    return __builtin_amdgcn_readfirstlane(sb[0]) >= 0;
 }
 
 template <class TC, int BM, int BN, class TA, class TB>
@@ -173,8 +186,7 @@ __device__ __forceinline__ void mma_chunk(typename Acc<TC>::type (&acc)[BM][BN],
 
 template <class TA, class TB, class TC, int BM, int BN, int WAVES>
 __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B, int64_t ldb,
-                                        int64_t kdim, int64_t m0, int64_t n0, const NodeCols &ncl, int cnt,
-                                        TC *red) {
+                                        int64_t kdim, int64_t m0, int64_t n0, const int (&sb)[BN], TC *red) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
@@ -188,7 +200,7 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     const TA *Ap[BM];
     const TB *Bp[BN];
     for (int i = 0; i < BM; ++i) Ap[i] = A + (m0 + 16 * i + r) * lda + 4 * q;
-    for (int j = 0; j < BN; ++j) Bp[j] = B + col_slot(ncl, n0 + 16 * j + r, cnt) * ldb + 4 * q;
+    for (int j = 0; j < BN; ++j) Bp[j] = B + col_row(sb[j], n0 + 16 * j + r) * ldb + 4 * q;
     TA a0[BM][4], a1[BM][4];
     TB b0[BN][4], b1[BN][4];
 #define L0L2_LD(a, b, c)                                                  \
@@ -227,16 +239,17 @@ template <class TA, class TB, class TC, int BM, int BN, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A, int64_t lda,
                                                         const TB *__restrict__ B, int64_t ldb, TC *__restrict__ U,
                                                         int64_t ldu, int64_t kdim, NodeCols ncl) {
-    constexpr int TM = 16 * BM, TN = 16 * BN;
+    constexpr int TM = 16 * BM, TN = 16 * BN, E = TM * TN / (64 * WAVES);
+    static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
     __shared__ TC red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * TN));
-    if (n0 >= cnt) return;
-    nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, ncl, cnt, red);
-    for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
-        int n = idx / TM, m = idx % TM;
-        if (n0 + n >= cnt) continue;
-        U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = sum_waves<TC, TM, TN, WAVES>(red, n, m);
+    int sb[BN], se[E];
+    if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
+    nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, sb, red);
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * WAVES, n = idx / TM, m = idx % TM;
+        if (se[t] >= 0) U[(int64_t)se[t] * ldu + m0 + m] = sum_waves<TC, TM, TN, WAVES>(red, n, m);
     }
 }
 
@@ -245,6 +258,29 @@ struct GateArgs {
     double l0, l2, M, s, two_M_l2, four_l2, l2_M2, psi_lin;
     int free_quad;
 };
+
+// Operands of the ADMM update of one (node, coordinate), loaded before the
+// contraction so that their latency overlaps it.  on: live column and active node.
+template <class T>
+struct EpiIn {
+    T w, v, c;
+    uint8_t code;
+    bool on;
+};
+
+template <class T>
+__device__ __forceinline__ void epi_load(EpiIn<T> &ei, int slot, int64_t col, int64_t j, int64_t ldp,
+                                         const T *__restrict__ W, const T *__restrict__ V,
+                                         const uint8_t *__restrict__ codes, const T *__restrict__ c,
+                                         const int *__restrict__ active) {
+    const int64_t row = col_row(slot, col), o = row * ldp + j;
+    ei.w = W[o];
+    ei.v = V[o];
+    ei.c = c[j];
+    ei.code = codes[o];
+    const int act = active[row];   // loaded unconditionally: no wait before the other loads
+    ei.on = (slot >= 0) & (act != 0);
+}
 
 // The ADMM update of one (node, coordinate) from Q = (Xh^T Xh w)_j:
 //   b = (W - Q) / rho, beta = prox(b + V / rho), V += rho (b - beta),
@@ -256,22 +292,24 @@ struct GateArgs {
 //   P(beta) >= 1/2 ||r||^2 - (X^T r)^T (beta - b) + sum psi(beta)
 // (from ||r - X (beta - b)||^2 >= ||r||^2 - 2 r^T X (beta - b)) follow from the
 // per-node sums of c b, b (w - rho b), nu(|X^T r|), (X^T r) (beta - b), psi(beta).
+// Returns the new W.
 template <class T>
-__device__ __forceinline__ void admm_update(T Qv, int64_t o, int64_t j, T *__restrict__ W, T *__restrict__ beta,
-                                            T *__restrict__ V, T *__restrict__ Bst, const uint8_t *__restrict__ codes,
-                                            const T *__restrict__ c, const DevParams<T> &q, int store_b, bool est,
-                                            const GateArgs &ga, double e[5]) {
-    const uint8_t code = codes[o];
-    const T wv = W[o];
+__device__ __forceinline__ T admm_update(T Qv, const EpiIn<T> &ei, int64_t o, T *__restrict__ W,
+                                         T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
+                                         const DevParams<T> &q, int store_b, bool est, const GateArgs &ga,
+                                         double e[5]) {
+    const uint8_t code = ei.code;
+    const T wv = ei.w;
     const T bb = (wv - Qv) / q.rho;
-    const T v = V[o];
+    const T v = ei.v;
     const T bt = bb + v / q.rho;
     const T be = prox_beta(bt, code, q);
     const T vn = v + q.rho * (bb - be);
-    const T cj = c[j];
+    const T cj = ei.c;
+    const T wn = cj + q.rho * be - vn;
     beta[o] = be;
     V[o] = vn;
-    W[o] = cj + q.rho * be - vn;
+    W[o] = wn;
     if (store_b) Bst[o] = bb;
     if (est) {
         const double b = (double)bb, w = (double)wv, cd = (double)cj, rho = (double)q.rho, bn = (double)be;
@@ -282,6 +320,23 @@ __device__ __forceinline__ void admm_update(T Qv, int64_t o, int64_t j, T *__res
         e[3] = g * (bn - b);
         e[4] = psi_val(bn, code, ga.l0, ga.l2, ga.s, ga.free_quad, ga.psi_lin);
     }
+    return wn;
+}
+
+// The same with the operands loaded here (LDS-staged tiles, whose lanes own too
+// many elements to load them ahead).
+template <class T>
+__device__ __forceinline__ T admm_update(T Qv, int64_t o, int64_t j, T *__restrict__ W, T *__restrict__ beta,
+                                         T *__restrict__ V, T *__restrict__ Bst, const uint8_t *__restrict__ codes,
+                                         const T *__restrict__ c, const DevParams<T> &q, int store_b, bool est,
+                                         const GateArgs &ga, double e[5]) {
+    EpiIn<T> ei;
+    ei.w = W[o];
+    ei.v = V[o];
+    ei.c = c[j];
+    ei.code = codes[o];
+    ei.on = true;
+    return admm_update<T>(Qv, ei, o, W, beta, V, Bst, q, store_b, est, ga, e);
 }
 
 // Sums the five estimate terms over the TM consecutive threads that hold one
@@ -306,22 +361,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ 
                                                   const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                                   const int *__restrict__ active, DevParams<T> q, int64_t ldp,
                                                   int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
-    constexpr int TM = 16 * BM, TN = 16 * BN;
+    constexpr int TM = 16 * BM, TN = 16 * BN, E = TM * TN / (64 * WAVES);
+    static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
     __shared__ T red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * TN));
-    if (n0 >= cnt) return;
-    nt_tile<TA, T, T, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
+    int sb[BN], se[E];
+    if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
+    EpiIn<T> ei[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * WAVES;
+        epi_load<T>(ei[t], se[t], n0 + idx / TM, m0 + idx % TM, ldp, W, V, codes, c, active);
+    }
+    nt_tile<TA, T, T, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, sb, red);
     const bool est = gpart != nullptr;
-    for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
-        const int n = idx / TM, m = idx % TM;
-        const bool live = n0 + n < cnt;
-        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * WAVES, n = idx / TM, m = idx % TM;
         double e[5] = {0, 0, 0, 0, 0};
-        if (live && active[node])
-            admm_update<T>(sum_waves<T, TM, TN, WAVES>(red, n, m), node * ldp + j, j, W, beta, V, Bst, codes, c, q,
-                           store_b, est, ga, e);
-        if (est) store_estimate<TM>(e, m, live ? node : -1, gpart);
+        if (ei[t].on)
+            admm_update<T>(sum_waves<T, TM, TN, WAVES>(red, n, m), ei[t], (int64_t)se[t] * ldp + m0 + m, W, beta, V,
+                           Bst, q, store_b, est, ga, e);
+        if (est) store_estimate<TM>(e, m, se[t], gpart);
     }
 }
 
@@ -351,25 +412,35 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu_anch(
     double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d, const uint8_t *__restrict__ codes,
     const double *__restrict__ c, const int *__restrict__ active, DevParams<double> q, int64_t ldp, int store_b,
     double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
-    constexpr int TM = 16 * BM, TN = 16 * BN;
+    constexpr int TM = 16 * BM, TN = 16 * BN, E = TM * TN / (64 * WAVES);
+    static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
     __shared__ float red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * TN));
-    if (n0 >= cnt) return;
-    nt_tile<float, float, float, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
+    int sb[BN], se[E];
+    if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
+    EpiIn<double> ei[E];
+    double za[E], wa[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * WAVES;
+        const int64_t col = n0 + idx / TM, j = m0 + idx % TM, o = col_row(se[t], col) * ldp + j;
+        epi_load<double>(ei[t], se[t], col, j, ldp, W, V, codes, c, active);
+        za[t] = Za[o];
+        wa[t] = Wa[o];
+    }
+    nt_tile<float, float, float, BM, BN, WAVES>(A, lda, U, ldu, kdim, m0, n0, sb, red);
     const bool est = gpart != nullptr;
-    for (int idx = threadIdx.x; idx < TM * TN; idx += 64 * WAVES) {
-        const int n = idx / TM, m = idx % TM;
-        const bool live = n0 + n < cnt;
-        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * WAVES, n = idx / TM, m = idx % TM;
         double e[5] = {0, 0, 0, 0, 0};
-        if (live && active[node]) {
-            const int64_t o = node * ldp + j;
-            const double Qv = Za[o] + (double)sum_waves<float, TM, TN, WAVES>(red, n, m);
-            admm_update<double>(Qv, o, j, W, beta, V, Bst, codes, c, q, store_b, est, ga, e);
-            d[o] = (float)(W[o] - Wa[o]);
+        if (ei[t].on) {
+            const int64_t o = (int64_t)se[t] * ldp + m0 + m;
+            const double Qv = za[t] + (double)sum_waves<float, TM, TN, WAVES>(red, n, m);
+            const double wn = admm_update<double>(Qv, ei[t], o, W, beta, V, Bst, q, store_b, est, ga, e);
+            d[o] = (float)(wn - wa[t]);
         }
-        if (est) store_estimate<TM>(e, m, live ? node : -1, gpart);
+        if (est) store_estimate<TM>(e, m, se[t], gpart);
     }
 }
 
@@ -400,7 +471,7 @@ struct LdsTile {
 
 template <class T, int WM, int WN>
 __device__ __forceinline__ void lds_tile(const T *__restrict__ A, int64_t lda, const T *__restrict__ B, int64_t ldb,
-                                         int64_t kdim, int64_t m0, int64_t n0, const NodeCols &ncl, int cnt, T *smem,
+                                         int64_t kdim, int64_t m0, int64_t n0, const NodeCols &ncl, T *smem,
                                          typename Acc<T>::type (&acc)[WM][WN]) {
     typedef LdsTile<T, WM, WN> L;
     constexpr int EPV = 16 / (int)sizeof(T);                 // elements per 16-byte vector
@@ -425,7 +496,7 @@ __device__ __forceinline__ void lds_tile(const T *__restrict__ A, int64_t lda, c
 #pragma unroll
     for (int e = 0; e < L::NB; ++e) {
         const int idx = tid + 256 * e, row = idx / L::VPR, part = idx % L::VPR;
-        gb[e] = B + col_slot(ncl, n0 + row, cnt) * ldb + EPV * part;
+        gb[e] = B + col_row(col_slot(ncl, n0 + row), n0 + row) * ldb + EPV * part;
         lb[e] = (L::TM + row) * L::LD + EPV * part;
     }
     float4 va[L::NA], vb[L::NB];
@@ -481,10 +552,9 @@ __global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, in
     typedef LdsTile<T, WM, WN> L;
     __shared__ __align__(16) T smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
-    if (n0 >= cnt) return;
+    if (col_slot(ncl, n0) < 0) return;
     typename Acc<T>::type acc[WM][WN];
-    lds_tile<T, WM, WN>(A, lda, B, ldb, kdim, m0, n0, ncl, cnt, smem, acc);
+    lds_tile<T, WM, WN>(A, lda, B, ldb, kdim, m0, n0, ncl, smem, acc);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -493,7 +563,8 @@ __global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, in
             for (int v = 0; v < 4; ++v) {
                 int m, n;
                 lds_pos<T, WM, WN>(i, j, v, m, n);
-                if (n0 + n < cnt) U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = acc[i][j][v];
+                const int sl = col_slot(ncl, n0 + n);
+                if (sl >= 0) U[(int64_t)sl * ldu + m0 + m] = acc[i][j][v];
             }
 }
 
@@ -502,7 +573,7 @@ __global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, in
 // up (xor 16, 32), the two wave rows meet in LDS.  e[i][j][t]: term t of
 // block (i, j)'s 4 rows of this lane.
 template <int WM, int WN>
-__device__ __forceinline__ void lds_store_estimate(double (&e)[WN][5], const NodeCols &ncl, int64_t n0, int cnt,
+__device__ __forceinline__ void lds_store_estimate(double (&e)[WN][5], const NodeCols &ncl, int64_t n0,
                                                    double *__restrict__ gpart, double *red) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
@@ -524,8 +595,9 @@ __device__ __forceinline__ void lds_store_estimate(double (&e)[WN][5], const Nod
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
             const int n = wn * 16 * WN + 16 * j + lane;
-            if (n0 + n >= cnt) continue;
-            double *d = gpart + (col_slot(ncl, n0 + n, cnt) * (int64_t)gridDim.x + blockIdx.x) * 5;
+            const int sl = col_slot(ncl, n0 + n);
+            if (sl < 0) continue;
+            double *d = gpart + ((int64_t)sl * gridDim.x + blockIdx.x) * 5;
 #pragma unroll
             for (int t = 0; t < 5; ++t) d[t] = e[j][t] + red[((wn * WN + j) * 16 + lane) * 5 + t];
         }
@@ -543,10 +615,9 @@ __global__ __launch_bounds__(256) void k_admm_xtu_lds(const T *__restrict__ A, i
     typedef LdsTile<T, WM, WN> L;
     __shared__ __align__(16) T smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
-    if (n0 >= cnt) return;
+    if (col_slot(ncl, n0) < 0) return;
     typename Acc<T>::type acc[WM][WN];
-    lds_tile<T, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, smem, acc);
+    lds_tile<T, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
     const bool est = gpart != nullptr;
     double e[WN][5] = {};
 #pragma unroll
@@ -557,9 +628,8 @@ __global__ __launch_bounds__(256) void k_admm_xtu_lds(const T *__restrict__ A, i
             for (int v = 0; v < 4; ++v) {
                 int m, n;
                 lds_pos<T, WM, WN>(i, j, v, m, n);
-                const bool live = n0 + n < cnt;
-                const int64_t node = col_slot(ncl, n0 + n, cnt), jj = m0 + m;
-                if (live && active[node]) {
+                const int64_t node = col_slot(ncl, n0 + n), jj = m0 + m;
+                if (node >= 0 && active[node]) {
                     double ev[5] = {0, 0, 0, 0, 0};
                     admm_update<T>(acc[i][j][v], node * ldp + jj, jj, W, beta, V, Bst, codes, c, q, store_b, est,
                                    ga, ev);
@@ -567,7 +637,7 @@ __global__ __launch_bounds__(256) void k_admm_xtu_lds(const T *__restrict__ A, i
                     for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
                 }
             }
-    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, cnt, gpart, reinterpret_cast<double *>(smem));
+    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, gpart, reinterpret_cast<double *>(smem));
 }
 
 // Contraction over n of an anchored sweep, LDS-staged tile.
@@ -581,10 +651,9 @@ __global__ __launch_bounds__(256) void k_admm_xtu_anch_lds(
     typedef LdsTile<float, WM, WN> L;
     __shared__ __align__(16) float smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
-    if (n0 >= cnt) return;
+    if (col_slot(ncl, n0) < 0) return;
     f32x4 acc[WM][WN];
-    lds_tile<float, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, cnt, smem, acc);
+    lds_tile<float, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
     const bool est = gpart != nullptr;
     double e[WN][5] = {};
 #pragma unroll
@@ -595,9 +664,8 @@ __global__ __launch_bounds__(256) void k_admm_xtu_anch_lds(
             for (int v = 0; v < 4; ++v) {
                 int m, n;
                 lds_pos<float, WM, WN>(i, j, v, m, n);
-                const bool live = n0 + n < cnt;
-                const int64_t node = col_slot(ncl, n0 + n, cnt), jj = m0 + m;
-                if (live && active[node]) {
+                const int64_t node = col_slot(ncl, n0 + n), jj = m0 + m;
+                if (node >= 0 && active[node]) {
                     const int64_t o = node * ldp + jj;
                     double ev[5] = {0, 0, 0, 0, 0};
                     admm_update<double>(Za[o] + (double)acc[i][j][v], o, jj, W, beta, V, Bst, codes, c, q, store_b,
@@ -607,7 +675,7 @@ __global__ __launch_bounds__(256) void k_admm_xtu_anch_lds(
                     for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
                 }
             }
-    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, cnt, gpart, reinterpret_cast<double *>(smem));
+    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, gpart, reinterpret_cast<double *>(smem));
 }
 
 // ---------------------------------------------------------------------------
@@ -641,10 +709,10 @@ __device__ __forceinline__ void load8f(const float *p, float out[8]) {
 template <int WAVES>
 __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
                                              int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
-                                             int64_t m0, int64_t n0, const NodeCols &ncl, int cnt, float *red) {
+                                             int64_t m0, int64_t n0, const int (&sb)[2], float *red) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
-    const int64_t brow[2] = {col_slot(ncl, n0 + r, cnt), col_slot(ncl, n0 + 16 + r, cnt)};
+    const int64_t brow[2] = {col_row(sb[0], n0 + r), col_row(sb[1], n0 + 16 + r)};
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
@@ -713,7 +781,7 @@ struct LdsTileBf {
 template <int WM, int WN>
 __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
                                               int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
-                                              int64_t m0, int64_t n0, const NodeCols &ncl, int cnt,
+                                              int64_t m0, int64_t n0, const NodeCols &ncl,
                                               unsigned char *smem, f32x4 (&acc)[WM][WN]) {
     typedef LdsTileBf<WM, WN> L;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -738,7 +806,8 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
 #pragma unroll
     for (int e = 0; e < L::NB; ++e) {
         const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
-        gb[e] = reinterpret_cast<const unsigned char *>(B + col_slot(ncl, n0 + row, cnt) * ldb) + 16 * part;
+        gb[e] = reinterpret_cast<const unsigned char *>(B + col_row(col_slot(ncl, n0 + row), n0 + row) * ldb) +
+                16 * part;
         lb[e] = (L::TM + row) * L::ROWB + 16 * part;
     }
     float4 va[L::NA], vb[L::NB];
@@ -799,10 +868,9 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restri
     typedef LdsTileBf<WM, WN> L;
     __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
-    if (n0 >= cnt) return;
+    if (col_slot(ncl, n0) < 0) return;
     f32x4 acc[WM][WN];
-    lds_tile_bf16<WM, WN>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, ncl, cnt, smem, acc);
+    lds_tile_bf16<WM, WN>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, ncl, smem, acc);
 #pragma unroll
     for (int i = 0; i < WM; ++i)
 #pragma unroll
@@ -811,7 +879,8 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restri
             for (int v = 0; v < 4; ++v) {
                 int m, n;
                 lds_pos<float, WM, WN>(i, j, v, m, n);
-                if (n0 + n < cnt) U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = acc[i][j][v];
+                const int sl = col_slot(ncl, n0 + n);
+                if (sl >= 0) U[(int64_t)sl * ldu + m0 + m] = acc[i][j][v];
             }
 }
 
@@ -830,10 +899,9 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
     typedef LdsTileBf<WM, WN> L;
     __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * L::TN));
-    if (n0 >= cnt) return;
+    if (col_slot(ncl, n0) < 0) return;
     f32x4 acc[WM][WN];
-    lds_tile_bf16<WM, WN>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, cnt, smem, acc);
+    lds_tile_bf16<WM, WN>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
     const bool est = gpart != nullptr;
     double e[WN][5] = {};
 #pragma unroll
@@ -844,9 +912,8 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
             for (int v = 0; v < 4; ++v) {
                 int m, n;
                 lds_pos<float, WM, WN>(i, j, v, m, n);
-                const bool live = n0 + n < cnt;
-                const int64_t node = col_slot(ncl, n0 + n, cnt), jj = m0 + m;
-                if (live && active[node]) {
+                const int64_t node = col_slot(ncl, n0 + n), jj = m0 + m;
+                if (node >= 0 && active[node]) {
                     const int64_t o = node * ldp + jj;
                     double ev[5] = {0, 0, 0, 0, 0};
                     if (ANCH) {
@@ -861,7 +928,7 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
                     for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
                 }
             }
-    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, cnt, gpart, reinterpret_cast<double *>(smem));
+    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, gpart, reinterpret_cast<double *>(smem));
 }
 
 constexpr int kWavesBf16 = 8;
@@ -874,13 +941,14 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *
                                                                   NodeCols ncl) {
     __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
-    if (n0 >= cnt) return;
-    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, ncl, cnt, red);
-    for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
-        int n = idx >> 5, m = idx & 31;
-        if (n0 + n >= cnt) continue;
-        U[col_slot(ncl, n0 + n, cnt) * ldu + m0 + m] = sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
+    constexpr int E = 1024 / (64 * kWavesBf16);
+    int sb[2], se[E];
+    if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, sb, red);
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16, n = idx >> 5, m = idx & 31;
+        if (se[t] >= 0) U[(int64_t)se[t] * ldu + m0 + m] = sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
     }
 }
 
@@ -893,19 +961,25 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
     GateArgs ga, NodeCols ncl) {
     __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
-    if (n0 >= cnt) return;
-    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
+    constexpr int E = 1024 / (64 * kWavesBf16);
+    int sb[2], se[E];
+    if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
+    EpiIn<float> ei[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16;
+        epi_load<float>(ei[t], se[t], n0 + (idx >> 5), m0 + (idx & 31), ldp, W, V, codes, c, active);
+    }
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, sb, red);
     const bool est = gpart != nullptr;
-    for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
-        const int n = idx >> 5, m = idx & 31;
-        const bool live = n0 + n < cnt;
-        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16, n = idx >> 5, m = idx & 31;
         double e[5] = {0, 0, 0, 0, 0};
-        if (live && active[node])
-            admm_update<float>(sum_waves<float, 32, 32, kWavesBf16>(red, n, m), node * ldp + j, j, W, beta, V, Bst,
-                               codes, c, q, store_b, est, ga, e);
-        if (est) store_estimate<32>(e, m, live ? node : -1, gpart);
+        if (ei[t].on)
+            admm_update<float>(sum_waves<float, 32, 32, kWavesBf16>(red, n, m), ei[t], (int64_t)se[t] * ldp + m0 + m,
+                               W, beta, V, Bst, q, store_b, est, ga, e);
+        if (est) store_estimate<32>(e, m, se[t], gpart);
     }
 }
 
@@ -919,22 +993,32 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_anch_bf16(
     DevParams<double> q, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
     __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
-    if (n0 >= cnt) return;
-    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, cnt, red);
+    constexpr int E = 1024 / (64 * kWavesBf16);
+    int sb[2], se[E];
+    if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
+    EpiIn<double> ei[E];
+    double za[E], wa[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16;
+        const int64_t col = n0 + (idx >> 5), j = m0 + (idx & 31), o = col_row(se[t], col) * ldp + j;
+        epi_load<double>(ei[t], se[t], col, j, ldp, W, V, codes, c, active);
+        za[t] = Za[o];
+        wa[t] = Wa[o];
+    }
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, sb, red);
     const bool est = gpart != nullptr;
-    for (int idx = threadIdx.x; idx < 1024; idx += 64 * kWavesBf16) {
-        const int n = idx >> 5, m = idx & 31;
-        const bool live = n0 + n < cnt;
-        const int64_t node = col_slot(ncl, n0 + n, cnt), j = m0 + m;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16, n = idx >> 5, m = idx & 31;
         double e[5] = {0, 0, 0, 0, 0};
-        if (live && active[node]) {
-            const int64_t o = node * ldp + j;
-            const double Qv = Za[o] + (double)sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
-            admm_update<double>(Qv, o, j, W, beta, V, Bst, codes, c, q, store_b, est, ga, e);
-            d[o] = (float)(W[o] - Wa[o]);
+        if (ei[t].on) {
+            const int64_t o = (int64_t)se[t] * ldp + m0 + m;
+            const double Qv = za[t] + (double)sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
+            const double wn = admm_update<double>(Qv, ei[t], o, W, beta, V, Bst, q, store_b, est, ga, e);
+            d[o] = (float)(wn - wa[t]);
         }
-        if (est) store_estimate<32>(e, m, live ? node : -1, gpart);
+        if (est) store_estimate<32>(e, m, se[t], gpart);
     }
 }
 
@@ -962,14 +1046,16 @@ __global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR,
     __shared__ double red[WAVES * Red<32, 32>::WS];
     const bool with_b = blockIdx.z == 0;
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
-    if (n0 >= cnt) return;
-    nt_tile<double, T, double, 2, 2, WAVES>(XR, ldx, with_b ? B : beta, ldb, kdim, m0, n0, ncl, cnt, red);
+    constexpr int E = 1024 / (64 * WAVES);
+    int sb[2], se[E];
+    if (!tile_slots<32, 2, E, WAVES>(ncl, n0, sb, se)) return;
+    nt_tile<double, T, double, 2, 2, WAVES>(XR, ldx, with_b ? B : beta, ldb, kdim, m0, n0, sb, red);
     const int64_t ntr = gridDim.x;
-    for (int idx = threadIdx.x; idx < 1024; idx += 64 * WAVES) {
-        const int n = idx >> 5, m = idx & 31;
-        const bool live = n0 + n < cnt;
-        const int64_t node = col_slot(ncl, n0 + n, cnt), i = m0 + m;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * WAVES, n = idx >> 5, m = idx & 31;
+        const bool live = se[t] >= 0;
+        const int64_t node = se[t], i = m0 + m;
         const double yi = y[i];
         const double rv = yi - sum_waves<double, 32, 32, WAVES>(red, n, m);
         double e0, e1 = 0.0, e2 = 0.0;
@@ -1019,14 +1105,16 @@ __global__ __launch_bounds__(64 * kWavesDual) void k_dual_xtr(
     __shared__ double red[kWavesDual * Red<32, 32>::WS];
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
-    const int cnt = live_cols(ncl, (int)(gridDim.y * 32));
-    if (n0 >= cnt) return;
-    nt_tile<double, double, double, 2, 2, kWavesDual>(A, lda, R, ldr, kdim, m0, n0, ncl, cnt, red);
+    constexpr int E = 1024 / (64 * kWavesDual);
+    int sb[2], se[E];
     // 16 threads per node: thread t takes node t / 16, coordinates 2 (t % 16) and
     // 2 (t % 16) + 1 of the tile
     const int n = tid >> 4, jl = (tid & 15) * 2;
-    const bool live = n0 + n < cnt;
-    const int64_t node = col_slot(ncl, n0 + n, cnt);
+    const int slot = col_slot(ncl, n0 + n);
+    if (!tile_slots<32, 2, E, kWavesDual>(ncl, n0, sb, se)) return;
+    nt_tile<double, double, double, 2, 2, kWavesDual>(A, lda, R, ldr, kdim, m0, n0, sb, red);
+    const bool live = slot >= 0;
+    const int64_t node = col_row(slot, n0 + n);   // rows read for an idle column are valid and unused
     // ||r||^2 of the node from the row-tile sums of the first check kernel
     double rr = 0.0;
     for (int64_t t = tid & 15; t < ntr; t += 16) rr += rpart[(node * ntr + t) * 4];
@@ -1138,12 +1226,15 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpa
     }
 }
 
-// The next active list becomes the current one (one workgroup).
+// The next active list becomes the current one, with -1 past its nodes, and
+// the check list is emptied (all -1) for the next gap estimate (one workgroup).
 __global__ __launch_bounds__(256) void k_list_commit(const int *__restrict__ nlist, const int *__restrict__ ncount,
-                                                     int *__restrict__ list, int *__restrict__ count) {
+                                                     int *__restrict__ list, int *__restrict__ clist, int64_t Kp) {
     const int n = *ncount;
-    for (int i = threadIdx.x; i < n; i += 256) list[i] = nlist[i];
-    if (threadIdx.x == 0) *count = n;
+    for (int64_t i = threadIdx.x; i < Kp; i += 256) {
+        list[i] = i < n ? nlist[i] : -1;
+        clist[i] = -1;
+    }
 }
 
 struct GateFin {
@@ -1263,7 +1354,7 @@ bool shape_fits(int v, int64_t Kp) { return Kp % kTileTN[v] == 0; }
 
 template <class TA, class TB, class TC>
 void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int64_t ldb, TC *U, int64_t ldu,
-               int64_t rows, int64_t Kp, int64_t kdim, NodeCols ncl = NodeCols{nullptr, nullptr}) {
+               int64_t rows, int64_t Kp, int64_t kdim, NodeCols ncl = NodeCols{nullptr}) {
     if (sizeof(TC) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(rows / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
@@ -1300,7 +1391,7 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
 template <class T>
 void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes,
                 const int *active, const DevParams<T> &q, int store_b, double *gpart = nullptr,
-                const GateArgs &ga = GateArgs{}, NodeCols ncl = NodeCols{nullptr, nullptr}) {
+                const GateArgs &ga = GateArgs{}, NodeCols ncl = NodeCols{nullptr}) {
     const int64_t ldp = sw.ldp;
     if (sizeof(T) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
@@ -1447,7 +1538,7 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
 // Host drivers
 // ---------------------------------------------------------------------------
 // The active list of the current batch.
-NodeCols active_cols(l0l2_ctx *ctx) { return NodeCols{ctx->ws.list.as<int>(), ctx->ws.count.as<int>()}; }
+NodeCols active_cols(l0l2_ctx *ctx) { return NodeCols{ctx->ws.list.as<int>()}; }
 
 GateArgs gate_args(const Instance &in) {
     GateArgs g;
@@ -1571,8 +1662,8 @@ TileChoice &tile_choice_bf16(l0l2_ctx *ctx, int64_t Kp) {
         auto time_shape = [&](int v, int which, int reps) {
             HIPCHK(hipEventRecord(e0, s));
             for (int t = 0; t < reps; ++t) {
-                if (which == 0) launch_xw_bf16(v, ctx, s32.W, s32.U, Kp, NodeCols{nullptr, nullptr});
-                else launch_xtu_bf16(v, ctx, false, Kp, inactive.as<int>(), 0, nullptr, NodeCols{nullptr, nullptr});
+                if (which == 0) launch_xw_bf16(v, ctx, s32.W, s32.U, Kp, NodeCols{nullptr});
+                else launch_xtu_bf16(v, ctx, false, Kp, inactive.as<int>(), 0, nullptr, NodeCols{nullptr});
             }
             HIPCHK(hipEventRecord(e1, s));
             HIPCHK(hipEventSynchronize(e1));
@@ -1688,8 +1779,8 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     hipStream_t s = ctx->stream;
     const int64_t np = in.np, pp = in.pp;
     const int64_t ntr = np / 32;
-    NodeCols ncl{nullptr, nullptr};
-    if (mode == 0) ncl = gated ? NodeCols{ws.clist.as<int>(), ws.gate.as<int>()} : active_cols(ctx);
+    NodeCols ncl{nullptr};
+    if (mode == 0) ncl = gated ? NodeCols{ws.clist.as<int>()} : active_cols(ctx);
     dim3 g1((unsigned)ntr, (unsigned)(Kp / 32), mode == 0 ? 2u : 1u);
     dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / 32));
     prof_begin(ctx, PROF_CHECK);
@@ -1717,7 +1808,7 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
                        ws.gest.as<double>());
     if (mode == 0)
         hipLaunchKernelGGL(k_list_commit, dim3(1), dim3(256), 0, s, ws.nlist.as<int>(), ws.ncount.as<int>(),
-                           ws.list.as<int>(), ws.count.as<int>());
+                           ws.list.as<int>(), ws.clist.as<int>(), Kp);
     prof_end(ctx, PROF_CHECK);
     HIPCHK(hipGetLastError());
 }
@@ -1728,7 +1819,7 @@ void init_batch(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t K, int64_t Kp) {
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
-                       ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(), ws.count.as<int>(), K, Kp,
+                       ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(), ws.clist.as<int>(), K, Kp,
                        ws.sweep_no.as<int>());
     hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.ldp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta,
                        sw.V, sw.W, sw.c, (T)in.mp.rho, in.ldp, Kp * in.ldp);
@@ -1949,7 +2040,6 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.clist.ensure(4 * Kp);
     ws.list.ensure(4 * Kp);
     ws.nlist.ensure(4 * Kp);
-    ws.count.ensure(sizeof(int));
     ws.ncount.ensure(sizeof(int));
     ws.active.ensure(4 * Kp);
     ws.iters.ensure(4 * Kp);
@@ -2049,7 +2139,7 @@ void run_dual_bound(l0l2_ctx *ctx, int K, const void *) {
     Workspace &ws = ctx->ws;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, ctx->stream,
                        ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(),
-                       ws.count.as<int>(), (int64_t)K, Kp, ws.sweep_no.as<int>());
+                       ws.clist.as<int>(), (int64_t)K, Kp, ws.sweep_no.as<int>());
     if (ctx->inst.prec == L0L2_FP64)
         check_once<double>(ctx, ws.B.as<double>(), ws.B.as<double>(), Kp, 0.0, 0.0, 1);
     else

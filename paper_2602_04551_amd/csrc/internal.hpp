@@ -119,8 +119,8 @@ struct Workspace {
     DevBuf gate;                   // int32: length of the check list
     DevBuf needs;                  // Kp int32: the gap estimate leaves the node to the exact check
     DevBuf gest;                   // Kp FP64: the gap estimate (a lower bound of the exact relative gap)
-    DevBuf clist;                  // Kp int32: node slots the exact check evaluates
-    DevBuf list, count;            // active node slots of the batch and their number
+    DevBuf clist;                  // Kp int32: node slots the exact check evaluates, then -1
+    DevBuf list;                   // Kp int32: active node slots of the batch, then -1
     DevBuf nlist, ncount;          // the active list being rebuilt by the check
     DevBuf active, iters, status;  // Kp int32
     DevBuf lb, primal;             // Kp doubles
