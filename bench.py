@@ -34,8 +34,8 @@ METRIC = "node relaxations/s + time-to-certified-optimum, mixed vs FP64 GPU path
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--K", type=int, default=256)
     ap.add_argument("--no-ttco", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")

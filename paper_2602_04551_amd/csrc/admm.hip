@@ -544,6 +544,64 @@ __device__ __forceinline__ void lds_pos(int i, int j, int v, int &m, int &n) {
     n = (w & 1) * 16 * WN + 16 * j + (lane & 15);
 }
 
+// Epilogue of an LDS-staged tile.  A lane's accumulators cover 16 node columns
+// and rows 4 apart, so writing node state straight from them scatters every
+// access over 16 rows.  Instead the TM x TN tile goes to LDS node-major (row
+// stride TM + 1: both the writes and the reads are free of bank conflicts) in
+// NP passes of PN = TN / NP node columns (as many as the staging buffers hold),
+// and each wave then takes whole node columns: lane l handles coordinates
+// l + 64 h (h < TM / 64) of node column c0 + w + 4 t, so the node-state accesses
+// of a wave are contiguous.
+template <class TA, int WM, int WN>
+struct LdsEpi {
+    static constexpr int TM = 32 * WM, TN = 32 * WN, LD = TM + 1, H = TM / 64;
+    // passes for a staging buffer of `bytes` bytes (0: not even a quarter fits)
+    static constexpr int passes(size_t bytes) {
+        return (size_t)TN * LD * sizeof(TA) <= bytes         ? 1
+               : (size_t)(TN / 2) * LD * sizeof(TA) <= bytes ? 2
+               : (size_t)(TN / 4) * LD * sizeof(TA) <= bytes ? 4
+                                                               : 0;
+    }
+};
+
+// Writes this lane's accumulators of node columns [c0, c0 + pn) to buf.
+template <class TA, int WM, int WN>
+__device__ __forceinline__ void acc_stage(const typename Acc<TA>::type (&acc)[WM][WN], TA *buf, int c0, int pn) {
+    constexpr int LD = LdsEpi<TA, WM, WN>::LD;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            int m, n;
+            lds_pos<TA, WM, WN>(i, j, 0, m, n);
+            if (n < c0 || n >= c0 + pn) continue;   // whole 16-column block in or out
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                lds_pos<TA, WM, WN>(i, j, v, m, n);
+                buf[(n - c0) * LD + m] = acc[i][j][v];
+            }
+        }
+}
+
+// Sum of each of the five estimate terms over the wave (every lane receives them).
+__device__ __forceinline__ void wave_sum5(double e[5]) {
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int t = 0; t < 5; ++t) e[t] += __shfl_xor(e[t], off);
+}
+
+// Node-state operands of the coordinates m0 + lane + 64 h of one node column
+// (col: its column index, slot: its list entry), all loaded before any update.
+template <class T, int H>
+__device__ __forceinline__ void epi_load_row(EpiIn<T> (&ei)[H], int slot, int64_t col, int64_t m0, int64_t ldp,
+                                             const T *__restrict__ W, const T *__restrict__ V,
+                                             const uint8_t *__restrict__ codes, const T *__restrict__ c,
+                                             const int *__restrict__ active) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int h = 0; h < H; ++h) epi_load<T>(ei[h], slot, col, m0 + lane + 64 * h, ldp, W, V, codes, c, active);
+}
+
 // Contraction over p (U = Xh W^T) with an LDS-staged tile.
 template <class T, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
@@ -555,52 +613,24 @@ __global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, in
     if (col_slot(ncl, n0) < 0) return;
     typename Acc<T>::type acc[WM][WN];
     lds_tile<T, WM, WN>(A, lda, B, ldb, kdim, m0, n0, ncl, smem, acc);
+    typedef LdsEpi<T, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int pass = 0; pass < NP; ++pass) {
+        const int c0 = pass * PN;
+        __syncthreads();
+        acc_stage<T, WM, WN>(acc, smem, c0, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            if (slot < 0) continue;
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int m, n;
-                lds_pos<T, WM, WN>(i, j, v, m, n);
-                const int sl = col_slot(ncl, n0 + n);
-                if (sl >= 0) U[(int64_t)sl * ldu + m0 + m] = acc[i][j][v];
-            }
-}
-
-// Per-(node, tile) sums of the gap estimate over the TM rows of an LDS tile:
-// each lane adds its 4 rows of every block row, the 4 lanes of a column add
-// up (xor 16, 32), the two wave rows meet in LDS.  e[i][j][t]: term t of
-// block (i, j)'s 4 rows of this lane.
-template <int WM, int WN>
-__device__ __forceinline__ void lds_store_estimate(double (&e)[WN][5], const NodeCols &ncl, int64_t n0,
-                                                   double *__restrict__ gpart, double *red) {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int wm = w >> 1, wn = w & 1;
-#pragma unroll
-    for (int j = 0; j < WN; ++j)
-#pragma unroll
-        for (int t = 0; t < 5; ++t) {
-            e[j][t] += __shfl_xor(e[j][t], 16);
-            e[j][t] += __shfl_xor(e[j][t], 32);
+            for (int h = 0; h < E::H; ++h)
+                U[(int64_t)slot * ldu + m0 + lane + 64 * h] = smem[(nl - c0) * E::LD + lane + 64 * h];
         }
-    __syncthreads();
-    if (wm == 1 && lane < 16)
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-            for (int t = 0; t < 5; ++t) red[((wn * WN + j) * 16 + lane) * 5 + t] = e[j][t];
-    __syncthreads();
-    if (wm == 0 && lane < 16)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            const int n = wn * 16 * WN + 16 * j + lane;
-            const int sl = col_slot(ncl, n0 + n);
-            if (sl < 0) continue;
-            double *d = gpart + ((int64_t)sl * gridDim.x + blockIdx.x) * 5;
-#pragma unroll
-            for (int t = 0; t < 5; ++t) d[t] = e[j][t] + red[((wn * WN + j) * 16 + lane) * 5 + t];
-        }
+    }
 }
 
 // Contraction over n with the ADMM epilogue, LDS-staged tile.
@@ -619,25 +649,38 @@ __global__ __launch_bounds__(256) void k_admm_xtu_lds(const T *__restrict__ A, i
     typename Acc<T>::type acc[WM][WN];
     lds_tile<T, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
     const bool est = gpart != nullptr;
-    double e[WN][5] = {};
+    typedef LdsEpi<T, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int pass = 0; pass < NP; ++pass) {
+        const int c0 = pass * PN;
+        __syncthreads();
+        acc_stage<T, WM, WN>(acc, smem, c0, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            EpiIn<T> ei[E::H];
+            epi_load_row<T, E::H>(ei, slot, n0 + nl, m0, ldp, W, V, codes, c, active);
+            double e[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+            for (int h = 0; h < E::H; ++h) {
+                if (!ei[h].on) continue;
+                const int m = lane + 64 * h;
+                double ev[5] = {0, 0, 0, 0, 0};
+                admm_update<T>(smem[(nl - c0) * E::LD + m], ei[h], (int64_t)slot * ldp + m0 + m, W, beta, V, Bst, q,
+                               store_b, est, ga, ev);
 #pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int m, n;
-                lds_pos<T, WM, WN>(i, j, v, m, n);
-                const int64_t node = col_slot(ncl, n0 + n), jj = m0 + m;
-                if (node >= 0 && active[node]) {
-                    double ev[5] = {0, 0, 0, 0, 0};
-                    admm_update<T>(acc[i][j][v], node * ldp + jj, jj, W, beta, V, Bst, codes, c, q, store_b, est,
-                                   ga, ev);
-#pragma unroll
-                    for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
-                }
+                for (int u = 0; u < 5; ++u) e[u] += ev[u];
             }
-    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, gpart, reinterpret_cast<double *>(smem));
+            if (est) {
+                wave_sum5(e);
+                if (lane == 0 && slot >= 0)
+                    for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
+            }
+        }
+    }
 }
 
 // Contraction over n of an anchored sweep, LDS-staged tile.
@@ -655,27 +698,47 @@ __global__ __launch_bounds__(256) void k_admm_xtu_anch_lds(
     f32x4 acc[WM][WN];
     lds_tile<float, WM, WN>(A, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
     const bool est = gpart != nullptr;
-    double e[WN][5] = {};
+    typedef LdsEpi<float, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int pass = 0; pass < NP; ++pass) {
+        const int c0 = pass * PN;
+        __syncthreads();
+        acc_stage<float, WM, WN>(acc, smem, c0, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            EpiIn<double> ei[E::H];
+            double za[E::H], wa[E::H];
+            epi_load_row<double, E::H>(ei, slot, n0 + nl, m0, ldp, W, V, codes, c, active);
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int m, n;
-                lds_pos<float, WM, WN>(i, j, v, m, n);
-                const int64_t node = col_slot(ncl, n0 + n), jj = m0 + m;
-                if (node >= 0 && active[node]) {
-                    const int64_t o = node * ldp + jj;
-                    double ev[5] = {0, 0, 0, 0, 0};
-                    admm_update<double>(Za[o] + (double)acc[i][j][v], o, jj, W, beta, V, Bst, codes, c, q, store_b,
-                                        est, ga, ev);
-                    d[o] = (float)(W[o] - Wa[o]);
-#pragma unroll
-                    for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
-                }
+            for (int h = 0; h < E::H; ++h) {
+                const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
+                za[h] = Za[o];
+                wa[h] = Wa[o];
             }
-    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, gpart, reinterpret_cast<double *>(smem));
+            double e[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int h = 0; h < E::H; ++h) {
+                if (!ei[h].on) continue;
+                const int m = lane + 64 * h;
+                const int64_t o = (int64_t)slot * ldp + m0 + m;
+                double ev[5] = {0, 0, 0, 0, 0};
+                const double wn = admm_update<double>(za[h] + (double)smem[(nl - c0) * E::LD + m], ei[h], o, W, beta,
+                                                      V, Bst, q, store_b, est, ga, ev);
+                d[o] = (float)(wn - wa[h]);
+#pragma unroll
+                for (int u = 0; u < 5; ++u) e[u] += ev[u];
+            }
+            if (est) {
+                wave_sum5(e);
+                if (lane == 0 && slot >= 0)
+                    for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -871,17 +934,25 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restri
     if (col_slot(ncl, n0) < 0) return;
     f32x4 acc[WM][WN];
     lds_tile_bf16<WM, WN>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, ncl, smem, acc);
+    typedef LdsEpi<float, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    float *buf = reinterpret_cast<float *>(smem);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int pass = 0; pass < NP; ++pass) {
+        const int c0 = pass * PN;
+        __syncthreads();
+        acc_stage<float, WM, WN>(acc, buf, c0, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            if (slot < 0) continue;
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int m, n;
-                lds_pos<float, WM, WN>(i, j, v, m, n);
-                const int sl = col_slot(ncl, n0 + n);
-                if (sl >= 0) U[(int64_t)sl * ldu + m0 + m] = acc[i][j][v];
-            }
+            for (int h = 0; h < E::H; ++h)
+                U[(int64_t)slot * ldu + m0 + lane + 64 * h] = buf[(nl - c0) * E::LD + lane + 64 * h];
+        }
+    }
 }
 
 // BF16 split form, contraction over n with the FP32 ADMM epilogue (anch == 0)
@@ -903,32 +974,63 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
     f32x4 acc[WM][WN];
     lds_tile_bf16<WM, WN>(Ahi, Alo, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
     const bool est = gpart != nullptr;
-    double e[WN][5] = {};
+    typedef LdsEpi<float, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    float *buf = reinterpret_cast<float *>(smem);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int pass = 0; pass < NP; ++pass) {
+        const int c0 = pass * PN;
+        __syncthreads();
+        acc_stage<float, WM, WN>(acc, buf, c0, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            double e[5] = {0, 0, 0, 0, 0};
+            if (ANCH) {
+                EpiIn<double> ei[E::H];
+                double za[E::H], wa[E::H];
+                epi_load_row<double, E::H>(ei, slot, n0 + nl, m0, ldp, W64, V64, codes, c64, active);
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+                for (int h = 0; h < E::H; ++h) {
+                    const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
+                    za[h] = Za[o];
+                    wa[h] = Wa[o];
+                }
 #pragma unroll
-        for (int j = 0; j < WN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int m, n;
-                lds_pos<float, WM, WN>(i, j, v, m, n);
-                const int64_t node = col_slot(ncl, n0 + n), jj = m0 + m;
-                if (node >= 0 && active[node]) {
-                    const int64_t o = node * ldp + jj;
+                for (int h = 0; h < E::H; ++h) {
+                    if (!ei[h].on) continue;
+                    const int m = lane + 64 * h;
+                    const int64_t o = (int64_t)slot * ldp + m0 + m;
                     double ev[5] = {0, 0, 0, 0, 0};
-                    if (ANCH) {
-                        admm_update<double>(Za[o] + (double)acc[i][j][v], o, jj, W64, beta64, V64, B64, codes, c64,
-                                            q64, store_b, est, ga, ev);
-                        W32[o] = (float)(W64[o] - Wa[o]);
-                    } else {
-                        admm_update<float>(acc[i][j][v], o, jj, W32, beta32, V32, B32, codes, c32, q32, store_b, est,
-                                           ga, ev);
-                    }
+                    const double wn = admm_update<double>(za[h] + (double)buf[(nl - c0) * E::LD + m], ei[h], o, W64,
+                                                          beta64, V64, B64, q64, store_b, est, ga, ev);
+                    W32[o] = (float)(wn - wa[h]);
 #pragma unroll
-                    for (int t = 0; t < 5; ++t) e[j][t] += ev[t];
+                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
+                }
+            } else {
+                EpiIn<float> ei[E::H];
+                epi_load_row<float, E::H>(ei, slot, n0 + nl, m0, ldp, W32, V32, codes, c32, active);
+#pragma unroll
+                for (int h = 0; h < E::H; ++h) {
+                    if (!ei[h].on) continue;
+                    const int m = lane + 64 * h;
+                    double ev[5] = {0, 0, 0, 0, 0};
+                    admm_update<float>(buf[(nl - c0) * E::LD + m], ei[h], (int64_t)slot * ldp + m0 + m, W32, beta32,
+                                       V32, B32, q32, store_b, est, ga, ev);
+#pragma unroll
+                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
                 }
             }
-    if (est) lds_store_estimate<WM, WN>(e, ncl, n0, gpart, reinterpret_cast<double *>(smem));
+            if (est) {
+                wave_sum5(e);
+                if (lane == 0 && slot >= 0)
+                    for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
+            }
+        }
+    }
 }
 
 constexpr int kWavesBf16 = 8;
