@@ -48,9 +48,14 @@ enum {
  * FP32 iterates until each node meets its tolerance (the FP32 iterates alone
  * stall near a relative gap of 1e-6 .. 1e-5); node state returned in FP32.  BF16: the transformed design matrix is
  * stored in BF16, the node operand is split into two BF16 halves, accumulation
- * and node state are FP32.  In every mode the dual bound and the incumbent
- * objective are computed in FP64 with the original X. */
-enum { L0L2_FP64 = 0, L0L2_FP32 = 1, L0L2_BF16 = 2 };
+ * and node state are FP32.  FP8: the transformed design matrix is stored as
+ * FP8 e4m3 codes with one FP32 scale per column (s_j = max_i |Xh_ij| / 448,
+ * one byte per element), the codes are widened to BF16 in the products and
+ * every sweep is anchored (an FP64 product every block, the reduced products
+ * act on the movement since the anchor only), so the iterates converge to the
+ * FP64 fixed point; node state returned in FP32.  In every mode the dual bound
+ * and the incumbent objective are computed in FP64 with the original X. */
+enum { L0L2_FP64 = 0, L0L2_FP32 = 1, L0L2_BF16 = 2, L0L2_FP8 = 3 };
 
 enum { L0L2_FREE = 0, L0L2_FIX0 = 1, L0L2_FIX1 = 2 };
 
@@ -72,8 +77,8 @@ int l0l2_state_bytes(const l0l2_ctx *ctx);
  * pointers when ptrs_on_device == 0, device pointers otherwise; the library
  * copies them and the caller keeps ownership.  Requires n, p >= 1, finite
  * X and y, lambda0 >= 0, lambda2 > 0, M > 0 (INFINITY allowed), rho > 0.
- * x_precision is one of L0L2_FP64, L0L2_FP32, L0L2_BF16.  Replaces any
- * previous instance on ctx. */
+ * x_precision is one of L0L2_FP64, L0L2_FP32, L0L2_BF16, L0L2_FP8.  Replaces
+ * any previous instance on ctx. */
 int l0l2_set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p,
                   double lambda0, double lambda2, double M, double rho,
                   int x_precision, int ptrs_on_device);
@@ -88,7 +93,8 @@ typedef struct {
  * checks.  codes: device, K x p uint8.  beta, v: device, K x p state elements
  * (double for FP64, float otherwise), read as the start and overwritten with
  * the result; b_out: device, K x p state elements, receives the last b.  The
- * F0 fixings are imposed on beta before the first sweep (Sec. 3.1.3). */
+ * F0 fixings are imposed on beta before the first sweep (Sec. 3.1.3).  FP8 mode
+ * gives L0L2_E_UNSUPPORTED (its sweeps only run anchored inside a solve). */
 int l0l2_admm_sweeps(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta, void *v,
                      void *b_out, int sweeps);
 
@@ -240,7 +246,9 @@ int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
  * "admm_xtu.f64" (contraction over n with the prox/V epilogue), "gap_check"
  * (the FP64 gap evaluation, all of its kernels), "round_branch", "fista",
  * "anchor.f64" (the two FP64 products that start each block of anchored
- * sweeps in FP32 mode; those sweeps themselves count as the FP32 families).
+ * sweeps; in FP32 mode those sweeps count as the FP32 families, in BF16 mode as
+ * the BF16 ones), "gemm_xw.fp8" / "admm_xtu.fp8" (the two products of an
+ * anchored sweep in FP8 mode).
  * units (may be NULL) receives the work the timed launches did: for the sweep
  * families the number of node-iterations of nodes that were still active
  * (columns of converged nodes are not counted).  Unknown names give

@@ -16,10 +16,10 @@ LIB_PATH = os.path.join(_HERE, "libl0l2.so")
 
 L0L2_OK, L0L2_E_INVALID, L0L2_E_NODATA, L0L2_E_OOM = 0, -1, -2, -3
 L0L2_E_DEVICE, L0L2_E_NUMERIC, L0L2_E_TIMEOUT, L0L2_E_UNSUPPORTED = -4, -5, -6, -8
-L0L2_FP64, L0L2_FP32, L0L2_BF16 = 0, 1, 2
+L0L2_FP64, L0L2_FP32, L0L2_BF16, L0L2_FP8 = 0, 1, 2, 3
 L0L2_FREE, L0L2_FIX0, L0L2_FIX1 = 0, 1, 2
 L0L2_BEST_FIRST, L0L2_DFS = 0, 1
-PRECISIONS = {"fp64": L0L2_FP64, "fp32": L0L2_FP32, "bf16": L0L2_BF16}
+PRECISIONS = {"fp64": L0L2_FP64, "fp32": L0L2_FP32, "bf16": L0L2_BF16, "fp8": L0L2_FP8}
 
 
 class l0l2_admm_opts(C.Structure):
@@ -244,7 +244,7 @@ class Context:
         self._check(lib.l0l2_profile_enable(self._h, 1 if enable else 0))
 
     KERNELS = ("gemm_xw.f32", "admm_xtu.f32", "gemm_xw.f64", "admm_xtu.f64", "gemm_xw.bf16", "admm_xtu.bf16",
-               "gap_check", "round_branch", "fista", "anchor.f64")
+               "gap_check", "round_branch", "fista", "anchor.f64", "gemm_xw.fp8", "admm_xtu.fp8")
 
     def profile_query(self, kernel):
         """(launches, total milliseconds, work units) of one timed kernel family."""

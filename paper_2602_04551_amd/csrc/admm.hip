@@ -1125,6 +1125,164 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_anch_bf16(
 }
 
 // ---------------------------------------------------------------------------
+// FP8 storage (anchored sweeps only).  The folded operand is stored as FP8 e4m3
+// codes with one FP32 scale per column, Xh[i][j] ~ q[i][j] s[j] with
+// s[j] = max_i |Xh[i][j]| / 448, one byte per element in both layouts.  The
+// products widen the codes to BF16 on load (exact: every e4m3 value is a BF16
+// value) and multiply the node operand split into BF16 hi + lo:
+//   U = Xh d   = q (s o d)      contraction over p: the operand is scaled on load
+//   Q = Xh^T U = s o (q^T U)    contraction over n: the output is scaled
+// so a product takes two BF16 MFMAs per block and a quarter of the FP32
+// operand bytes.  The rounding of the codes (about 2^-4 relative) enters only
+// through d = W - w_a: the anchor z_a = Xh^T Xh w_a is FP64, so the error of a
+// sweep's product scales with the movement since the anchor and the iterates
+// converge to the FP64 fixed point.
+// ---------------------------------------------------------------------------
+
+// 8 FP8 codes (one 8-byte word, code t in byte t) -> 8 BF16 values: each pair
+// is widened to FP32 and the upper halves of the two patterns are packed (the
+// truncation is exact for e4m3 values).
+__device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 v) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 r;
+#define L0L2_PAIR(w, hi)                                                                                  \
+    __builtin_amdgcn_perm(__float_as_uint(__builtin_amdgcn_cvt_pk_f32_fp8((int)(w), hi)[1]),              \
+                          __float_as_uint(__builtin_amdgcn_cvt_pk_f32_fp8((int)(w), hi)[0]), 0x07060302u)
+    r[0] = L0L2_PAIR(v.x, false);
+    r[1] = L0L2_PAIR(v.x, true);
+    r[2] = L0L2_PAIR(v.y, false);
+    r[3] = L0L2_PAIR(v.y, true);
+#undef L0L2_PAIR
+    return __builtin_bit_cast(bf16x8, r);
+}
+
+// 32 x 32 tile of C[m][n] = sum_k q[m][k] (sc[k] B[n][k]) (SCALE_B) or
+// sum_k q[m][k] B[n][k] with q rows of FP8 codes (lda bytes) and B rows in FP32
+// (split into BF16 hi, lo on load); chunks of 32 k split in pairs over WAVES
+// waves with the branch-free two-stage loop of nt_tile.  Lane l reads the 8
+// codes of row l%16 at k offset 8 (l/16) with one 8-byte load.  kdim must be a
+// multiple of 64.
+template <int WAVES, bool SCALE_B>
+__device__ __forceinline__ void nt_tile_fp8(const uint8_t *__restrict__ qA, int64_t lda, const float *__restrict__ sc,
+                                            const float *__restrict__ B, int64_t ldb, int64_t kdim, int64_t m0,
+                                            int64_t n0, const int (&sb)[2], float *red) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int q = lane >> 4, r = lane & 15;
+    const int64_t brow[2] = {col_row(sb[0], n0 + r), col_row(sb[1], n0 + 16 + r)};
+    f32x4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
+    const int64_t npr = kdim / 64;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
+    const int64_t c0 = 2 * (npr * wu / WAVES), c1 = 2 * (npr * (wu + 1) / WAVES);
+    uint2 av[2][2];
+    float bv[2][2][8], sv[2][8];
+    auto load = [&](int st, int64_t c) {
+        for (int a = 0; a < 2; ++a)
+            av[st][a] = *reinterpret_cast<const uint2 *>(qA + (m0 + 16 * a + r) * lda + 32 * c + 8 * q);
+        for (int b = 0; b < 2; ++b) load8f(B + brow[b] * ldb + 32 * c + 8 * q, bv[st][b]);
+        if (SCALE_B) load8f(sc + 32 * c + 8 * q, sv[st]);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto compute = [&](int st) {
+        const bf16x8 ah[2] = {fp8x8_to_bf16(av[st][0]), fp8x8_to_bf16(av[st][1])};
+        for (int b = 0; b < 2; ++b) {
+            float x[8];
+            for (int t = 0; t < 8; ++t) x[t] = SCALE_B ? bv[st][b][t] * sv[st][t] : bv[st][b][t];
+            bf16x8 bh, bl;
+            split8(x, bh, bl);
+            for (int a = 0; a < 2; ++a) {
+                acc[a][b] = mfma16_bf16(ah[a], bh, acc[a][b]);
+                acc[a][b] = mfma16_bf16(ah[a], bl, acc[a][b]);
+            }
+        }
+    };
+    if (c0 < c1) {
+        load(0, c0);
+        int64_t c = c0;
+        for (; c + 2 < c1; c += 2) {
+            load(1, c + 1);
+            compute(0);
+            __builtin_amdgcn_sched_barrier(0);
+            load(0, c + 2);
+            compute(1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        load(1, c + 1);
+        compute(0);
+        compute(1);
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int v = 0; v < 4; ++v) {
+                int m = a * 16 + acc_row<float>(lane, v);
+                int n = b * 16 + r;
+                red[w * Red<32, 32>::WS + n * Red<32, 32>::LD + m] = acc[a][b][v];
+            }
+    __syncthreads();
+}
+
+// Contraction over p in FP8 storage: U[k][i] = sum_j q[i][j] s[j] d[k][j].
+__global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_fp8(const uint8_t *__restrict__ qA, int64_t lda,
+                                                                 const float *__restrict__ sc,
+                                                                 const float *__restrict__ B, int64_t ldb,
+                                                                 float *__restrict__ U, int64_t ldu, int64_t kdim,
+                                                                 NodeCols ncl) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    constexpr int E = 1024 / (64 * kWavesBf16);
+    int sb[2], se[E];
+    if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
+    nt_tile_fp8<kWavesBf16, true>(qA, lda, sc, B, ldb, kdim, m0, n0, sb, red);
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16, n = idx >> 5, m = idx & 31;
+        if (se[t] >= 0) U[(int64_t)se[t] * ldu + m0 + m] = sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
+    }
+}
+
+// Contraction over n of an anchored sweep in FP8 storage: Q = z_a + s o (q^T U),
+// FP64 update, d = fl32(W_new - w_a).
+__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_fp8(
+    const uint8_t *__restrict__ qA, int64_t lda, const float *__restrict__ sc, const float *__restrict__ U,
+    int64_t ldu, int64_t kdim, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W,
+    double *__restrict__ beta, double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d,
+    const uint8_t *__restrict__ codes, const double *__restrict__ c, const int *__restrict__ active,
+    DevParams<double> q, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    constexpr int E = 1024 / (64 * kWavesBf16);
+    int sb[2], se[E];
+    if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
+    EpiIn<double> ei[E];
+    double za[E], wa[E];
+    float sj[E];
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16;
+        const int64_t col = n0 + (idx >> 5), j = m0 + (idx & 31), o = col_row(se[t], col) * ldp + j;
+        epi_load<double>(ei[t], se[t], col, j, ldp, W, V, codes, c, active);
+        za[t] = Za[o];
+        wa[t] = Wa[o];
+        sj[t] = sc[j];
+    }
+    nt_tile_fp8<kWavesBf16, false>(qA, lda, nullptr, U, ldu, kdim, m0, n0, sb, red);
+    const bool est = gpart != nullptr;
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+        const int idx = threadIdx.x + t * 64 * kWavesBf16, n = idx >> 5, m = idx & 31;
+        double e[5] = {0, 0, 0, 0, 0};
+        if (ei[t].on) {
+            const int64_t o = (int64_t)se[t] * ldp + m0 + m;
+            const double Qv = za[t] + (double)sj[t] * (double)sum_waves<float, 32, 32, kWavesBf16>(red, n, m);
+            const double wn = admm_update<double>(Qv, ei[t], o, W, beta, V, Bst, q, store_b, est, ga, e);
+            d[o] = (float)(wn - wa[t]);
+        }
+        if (est) store_estimate<32>(e, m, se[t], gpart);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Gap check (FP64)
 // ---------------------------------------------------------------------------
 // Sum over the 64 lanes of a wave (xor butterfly: every lane gets the same value).
@@ -1857,6 +2015,29 @@ void sweep_once_anch(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
     HIPCHK(hipGetLastError());
 }
 
+// One anchored sweep in FP8 storage (register tiles 32 x 32, 8 waves): U = Xh d
+// with the codes, then the FP64 update from z_a + Xh^T U.
+void sweep_once_fp8(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    const NodeCols ncl = active_cols(ctx);
+    prof_begin(ctx, PROF_GEMM_XW_FP8);
+    hipLaunchKernelGGL(k_gemm_xw_fp8, dim3((unsigned)(in.np / 32), (unsigned)(Kp / 32)), dim3(64 * kWavesBf16), 0, s,
+                       in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), s32.W, in.ldp, s32.U, in.ldu, in.pp, ncl);
+    prof_end(ctx, PROF_GEMM_XW_FP8, active);
+    prof_begin(ctx, PROF_ADMM_XTU_FP8);
+    hipLaunchKernelGGL(k_admm_xtu_fp8, dim3((unsigned)(in.pp / 32), (unsigned)(Kp / 32)), dim3(64 * kWavesBf16), 0, s,
+                       in.qC.as<uint8_t>(), in.ldqc, in.qs.as<float>(), s32.U, in.ldu, in.np, ws.Za.as<double>(),
+                       ws.Wa.as<double>(), s64.W, s64.beta, s64.V, s64.B, s32.W, ws.codes.as<uint8_t>(), s64.c,
+                       ws.active.as<int>(), dev_params<double>(in.mp), in.ldp, store_b ? 1 : 0,
+                       gate ? ws.gpart.as<double>() : nullptr, gate_args(in), ncl);
+    prof_end(ctx, PROF_ADMM_XTU_FP8, active);
+    HIPCHK(hipGetLastError());
+}
+
 DualArgs dual_args(const Instance &in) {
     DualArgs d;
     d.l0 = in.mp.l0; d.l2 = in.mp.l2; d.M = in.mp.M; d.s = in.mp.s;
@@ -1968,6 +2149,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), cols, last, active, gate);
         else if (kind == SK_BF16) sweep_once_bf16(ctx, cols, last, active, gate, false);
         else if (kind == SK_ANCH && in.prec == L0L2_BF16) sweep_once_bf16(ctx, cols, last, active, gate, true);
+        else if (kind == SK_ANCH && in.prec == L0L2_FP8) sweep_once_fp8(ctx, cols, last, active, gate);
         else if (kind == SK_ANCH) sweep_once_anch(ctx, cols, last, active, gate);
         else sweep_once<float>(ctx, sweep32(ctx), cols, last, active, gate);
     }
@@ -1976,6 +2158,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), cols).xtu];
         else if (kind == SK_BF16 || (kind == SK_ANCH && in.prec == L0L2_BF16))
             rows = kBfTM[tile_choice_bf16(ctx, cols).xtu];
+        else if (kind == SK_ANCH && in.prec == L0L2_FP8) rows = 32;
         else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), cols).xtu];
         GateFin gf{in.yy, tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
@@ -2010,9 +2193,10 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
             // settle the tile shapes (the autotuner synchronises) before capturing
-            const bool bf = ctx->inst.prec == L0L2_BF16;
+            const bool bf = ctx->inst.prec == L0L2_BF16, f8 = ctx->inst.prec == L0L2_FP8;
             if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), cols);
-            if (kind == SK_F32 || (kind == SK_ANCH && !bf)) (void)tile_choice<float>(ctx, sweep32(ctx), cols);
+            if (kind == SK_F32 || (kind == SK_ANCH && !bf && !f8))
+                (void)tile_choice<float>(ctx, sweep32(ctx), cols);
             if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);
             hipGraph_t g = nullptr;
             hipGraphExec_t ex = nullptr;
@@ -2066,13 +2250,15 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
 }
 
 // Mixed precision (FP32 state): reduced-precision sweeps (FP32, or the BF16
-// form) while the batch converges, then the remaining active nodes continue in
-// FP64 from their FP32 iterates.  The reduced sweeps stop for the batch once
-// every active node's gap is below switch_tol (50 tol_node for FP32, 200
-// tol_node for BF16: the measured floors are about 1e-6..5e-6 and 1e-4), or the
-// number of nodes above it has not dropped for 5 checks, or half the sweep
-// budget is spent.  Bounds are FP64 in both phases; the final iterates are
-// returned in FP32.
+// form) while the batch converges, then anchored sweeps (FP64 state, the
+// reduced products act on the movement since each block's FP64 anchor) from the
+// FP32 iterates.  The plain reduced sweeps stop for the batch once every active
+// node's gap is below switch_tol (50 tol_node for FP32, 200 tol_node for BF16:
+// the measured floors are about 1e-6..5e-6 and 1e-4), or the number of nodes
+// above it has not dropped for 5 checks, or half the sweep budget is spent.
+// FP8 storage has no plain phase (its floor is far above any useful gap): its
+// sweeps are anchored from the start.  Bounds are FP64 throughout; the final
+// iterates are returned in FP32.
 void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     Instance &in = ctx->inst;
     const int64_t Kp = round_up(K, kPadNodes);
@@ -2083,6 +2269,13 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     const bool bf16 = in.prec == L0L2_BF16;
     const double switch_tol = (bf16 ? 200.0 : 50.0) * o.tol_node;
     bool fp64 = false;
+    if (in.prec == L0L2_FP8) {
+        // FP8 storage: anchored sweeps from the start, on the FP64 state
+        hipLaunchKernelGGL(k_promote, dim3(grid1d(Kp * in.ldp)), dim3(256), 0, ctx->stream, s32.beta, s32.V, s64.beta,
+                           s64.V, s64.W, s64.c, in.mp.rho, in.ldp, Kp * in.ldp);
+        HIPCHK(hipGetLastError());
+        fp64 = true;
+    }
     int cnt[2], best_above = 1 << 30, flat = 0;
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
@@ -2218,6 +2411,7 @@ void store_batch(l0l2_ctx *ctx, int K, void *beta, void *v, void *b) {
 }
 
 void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool) {
+    if (ctx->inst.prec == L0L2_FP8) fail(L0L2_E_UNSUPPORTED, "FP8 storage runs anchored solves only");
     if (ctx->inst.prec == L0L2_FP64) {
         sweeps_t<double>(ctx, sweep64(ctx), K, sweeps);
     } else if (ctx->inst.prec == L0L2_FP32) {

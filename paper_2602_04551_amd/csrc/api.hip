@@ -158,7 +158,8 @@ int l0l2_set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, in
         if (!(std::isfinite(lambda2) && lambda2 > 0)) l0l2::fail(L0L2_E_INVALID, "lambda2 must be finite and > 0");
         if (!(M > 0) || std::isnan(M)) l0l2::fail(L0L2_E_INVALID, "M must be > 0 (INFINITY allowed)");
         if (!(std::isfinite(rho) && rho > 0)) l0l2::fail(L0L2_E_INVALID, "rho must be finite and > 0");
-        if (x_precision != L0L2_FP64 && x_precision != L0L2_FP32 && x_precision != L0L2_BF16)
+        if (x_precision != L0L2_FP64 && x_precision != L0L2_FP32 && x_precision != L0L2_BF16 &&
+            x_precision != L0L2_FP8)
             l0l2::fail(L0L2_E_INVALID, "unknown x_precision");
         if (!ptrs_on_device) {
             for (int64_t e = 0; e < n * p; ++e)
@@ -175,6 +176,8 @@ int l0l2_admm_sweeps(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta, voi
         need_data(ctx);
         check_K(K);
         if (sweeps < 1) l0l2::fail(L0L2_E_INVALID, "sweeps must be >= 1");
+        if (ctx->inst.prec == L0L2_FP8)
+            l0l2::fail(L0L2_E_UNSUPPORTED, "FP8 storage runs anchored solves only (l0l2_solve_node_batch)");
         if (K == 0) return;
         if (!codes || !beta || !v) l0l2::fail(L0L2_E_INVALID, "null buffer");
         l0l2::load_batch(ctx, K, codes, beta, v, false);

@@ -99,6 +99,9 @@ struct Instance {
     DevBuf XhRw;      // FP64 / FP32 mode: row-major copy of Xh in the working precision (ld ldxr / ldwr)
     DevBuf Xh64R;     // FP32 / BF16 mode: row-major copy of Xh64 (ld ldxr)
     DevBuf X64R;      // row-major copy of X64 (contraction over p of the gap check), ld ldxr
+    DevBuf qR, qC;    // FP8 mode: e4m3 codes of Xh / s (row-major, ld ldqr bytes; column-major, ld ldqc bytes)
+    DevBuf qs;        // FP8 mode: FP32 column scales s_j (ldp entries, zero past p)
+    int64_t ldqr = 0, ldqc = 0;
     DevBuf codes_pad; // scratch
     std::map<std::pair<int, int64_t>, TileChoice> tiles;   // autotuned per (type, padded K)
 };
@@ -132,7 +135,8 @@ struct Workspace {
 };
 
 enum { PROF_GEMM_XW_F32 = 0, PROF_ADMM_XTU_F32, PROF_GEMM_XW_F64, PROF_ADMM_XTU_F64, PROF_GEMM_XW_BF16,
-       PROF_ADMM_XTU_BF16, PROF_CHECK, PROF_ROUND, PROF_FISTA, PROF_ANCHOR, kProfCount };
+       PROF_ADMM_XTU_BF16, PROF_CHECK, PROF_ROUND, PROF_FISTA, PROF_ANCHOR, PROF_GEMM_XW_FP8, PROF_ADMM_XTU_FP8,
+       kProfCount };
 extern const char *const kProfNames[kProfCount];
 
 struct Profiler {

@@ -243,6 +243,38 @@ __global__ void k_to_bf16x2(const double *__restrict__ src, int64_t lds, __bf16 
     }
 }
 
+// FP8 e4m3 (OCP): largest finite magnitude.
+constexpr double kFp8Max = 448.0;
+
+// One wave per column: s_j = max_i |Xh_ij| / 448 (1 for an all-zero column).
+__global__ __launch_bounds__(256) void k_fp8_scales(const double *__restrict__ X, int64_t ldx, int64_t np,
+                                                    int64_t pp, float *__restrict__ s) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= pp) return;
+    double mx = 0.0;
+    for (int64_t i = lane; i < np; i += 64) mx = fmax(mx, fabs(X[i + j * ldx]));
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if (lane == 0) s[j] = mx > 0.0 ? (float)(mx / kFp8Max) : 1.0f;
+}
+
+// q_ij = e4m3(Xh_ij / s_j) (round to nearest even; the quotient is clamped to
+// the finite range, the conversion gives NaN beyond it), stored column-major
+// (stride ldc bytes) and row-major (stride ldr bytes).
+__global__ void k_to_fp8(const double *__restrict__ X, int64_t ldx, const float *__restrict__ s,
+                         uint8_t *__restrict__ col, int64_t ldc, uint8_t *__restrict__ row, int64_t ldr, int64_t np,
+                         int64_t pp) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < np * pp; idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % np, j = idx / np;
+        const double t = X[i + j * ldx] / (double)s[j];
+        const float v = (float)fmin(kFp8Max, fmax(-kFp8Max, t));
+        const uint8_t q = (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(v, v, 0, false) & 0xFF);
+        col[i + j * ldc] = q;
+        row[i * ldr + j] = q;
+    }
+}
+
 void dgemm(hipStream_t st, int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t sai,
            int64_t sak, const double *B, int64_t sbk, int64_t sbj, double beta, double *C, int64_t ldc) {
     if (M <= 0 || N <= 0) return;
@@ -412,6 +444,21 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
         HIPCHK(hipMemsetAsync(in.XhRLo.ptr, 0, nbr, st));
         hipLaunchKernelGGL(k_to_bf16x2, dim3(4096), dim3(256), 0, st, Xh, ldx, in.Xh.as<__bf16>(),
                            in.XhLo.as<__bf16>(), ldw, in.XhR.as<__bf16>(), in.XhRLo.as<__bf16>(), ldwr, np, pp);
+        in.cst.ensure(sizeof(float) * (size_t)ldp);
+        hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), ldp);
+    } else if (prec == L0L2_FP8) {
+        in.ldqr = ld_pad(pp, 1);
+        in.ldqc = ld_pad(np, 1);
+        in.qs.ensure(sizeof(float) * (size_t)ldp);
+        in.qR.ensure((size_t)(np * in.ldqr));
+        in.qC.ensure((size_t)(in.ldqc * pp));
+        HIPCHK(hipMemsetAsync(in.qs.ptr, 0, sizeof(float) * (size_t)ldp, st));
+        HIPCHK(hipMemsetAsync(in.qR.ptr, 0, (size_t)(np * in.ldqr), st));
+        HIPCHK(hipMemsetAsync(in.qC.ptr, 0, (size_t)(in.ldqc * pp), st));
+        hipLaunchKernelGGL(k_fp8_scales, dim3((unsigned)((pp + 3) / 4)), dim3(256), 0, st, Xh, ldx, np, pp,
+                           in.qs.as<float>());
+        hipLaunchKernelGGL(k_to_fp8, dim3(4096), dim3(256), 0, st, Xh, ldx, in.qs.as<float>(), in.qC.as<uint8_t>(),
+                           in.ldqc, in.qR.as<uint8_t>(), in.ldqr, np, pp);
         in.cst.ensure(sizeof(float) * (size_t)ldp);
         hipLaunchKernelGGL(k_to_f32, dim3(64), dim3(256), 0, st, in.c64.as<double>(), in.cst.as<float>(), ldp);
     } else {

@@ -9,7 +9,7 @@ namespace l0l2 {
 const char *const kProfNames[kProfCount] = {"gemm_xw.f32",  "admm_xtu.f32", "gemm_xw.f64",
                                              "admm_xtu.f64", "gemm_xw.bf16", "admm_xtu.bf16",
                                              "gap_check",    "round_branch", "fista",
-                                             "anchor.f64"};
+                                             "anchor.f64",   "gemm_xw.fp8",  "admm_xtu.fp8"};
 
 static hipEvent_t pool_event(Profiler &p) {
     if (p.next < p.pool.size()) return p.pool[p.next++];

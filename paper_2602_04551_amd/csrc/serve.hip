@@ -29,9 +29,12 @@ size_t footprint_bytes(int64_t n, int64_t p, int prec, int K) {
     const double Kp = (double)round_up(std::max(K, 1), kPadNodes);
     const double sb = prec == L0L2_FP64 ? 8.0 : 4.0;
     double inst = 8.0 * np * pp + 32.0 * (np + pp);
-    if (prec == L0L2_FP64) inst += 8.0 * np * pp;
-    else if (prec == L0L2_FP32) inst += 12.0 * np * pp;
-    else inst += 16.0 * np * pp;
+    // the copies of Xh and X beside X64 (FP64 X64R everywhere; FP64 Xh and its
+    // row-major copy for the anchors; the working-precision layouts)
+    if (prec == L0L2_FP64) inst += 24.0 * np * pp;
+    else if (prec == L0L2_FP32) inst += 32.0 * np * pp;
+    else if (prec == L0L2_BF16) inst += 32.0 * np * pp;
+    else inst += 26.0 * np * pp;
     double transient = 8.0 * np * np + 8.0 * (double)n * (double)p;
     double ws = 4.0 * sb * Kp * pp + sb * Kp * np + 24.0 * Kp * np + Kp * pp + 1.0 * Kp * pp / 4.0 + 128.0 * Kp;
     if (prec != L0L2_FP64) ws += 32.0 * Kp * pp + 8.0 * Kp * np;
@@ -158,7 +161,8 @@ int l0l2_server_create(int device, size_t hbm_budget_bytes, int max_concurrent, 
 int l0l2_server_submit(l0l2_server *s, const double *X, const double *y, int64_t n, int64_t p, double lambda0,
                        double lambda2, double M, double rho, int precision, int64_t *req_id) {
     if (!s || !X || !y || !req_id || n < 1 || p < 1) return L0L2_E_INVALID;
-    if (precision != L0L2_FP64 && precision != L0L2_FP32 && precision != L0L2_BF16) return L0L2_E_INVALID;
+    if (precision != L0L2_FP64 && precision != L0L2_FP32 && precision != L0L2_BF16 && precision != L0L2_FP8)
+        return L0L2_E_INVALID;
     auto r = std::make_shared<l0l2_server::Request>();
     try {
         r->X.assign(X, X + n * p);

@@ -188,18 +188,18 @@ def test_node_solve_fp64_matches_oracle(torch_cuda, cases, name):
 
 
 @pytest.mark.parametrize("name,precision", [("C1", "fp32"), ("wide", "fp32"), ("C1", "bf16"),
-                                            ("wide", "bf16")])
+                                            ("wide", "bf16"), ("C1", "fp8"), ("wide", "fp8")])
 def test_node_solve_mixed_bounds_within_1e5(torch_cuda, cases, name, precision):
-    """Mixed paths: FP32 (or BF16 split) sweeps, then FP64 sweeps from the FP32
-    iterates; every node reaches the 1e-6 gap and its FP64 bound is within 1e-5
-    of the oracle's."""
+    """Mixed paths: FP32 (or BF16 split) sweeps, then anchored sweeps on the FP64
+    state; FP8 storage anchored from the start.  Every node reaches the 1e-6 gap
+    and its FP64 bound is within 1e-5 of the oracle's."""
     inst, o, root = cases[name]
     K = 40
     codes, beta0, v0 = random_nodes(inst.p, K, 5, root["beta"], root["v"])
     ctx = ctx_for(inst, precision)
     ctx.profile_enable(True)
     res = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-6, max_iter=4000, check_every=10)
-    n32 = ctx.profile_query("admm_xtu." + ("f32" if precision == "fp32" else "bf16"))[0]
+    n32 = ctx.profile_query("admm_xtu." + {"fp32": "f32", "bf16": "bf16", "fp8": "fp8"}[precision])[0]
     assert n32 > 0
     lb, stt = res["lb"].cpu().numpy(), res["status"].cpu().numpy()
     for k in range(K):
@@ -209,13 +209,14 @@ def test_node_solve_mixed_bounds_within_1e5(torch_cuda, cases, name, precision):
         assert lb[k] <= ref["primal"] + 1e-12
 
 
-@pytest.mark.parametrize("name,precision", [("C1", "fp32"), ("wide", "fp32"), ("C1", "bf16"), ("wide", "bf16")])
+@pytest.mark.parametrize("name,precision", [("C1", "fp32"), ("wide", "fp32"), ("C1", "bf16"), ("wide", "bf16"),
+                                            ("C1", "fp8"), ("wide", "fp8")])
 def test_reduced_modes_reach_fp64_tolerances(torch_cuda, cases, name, precision):
-    """FP32 and BF16 modes below their own rounding floors: the anchored FP64
-    sweeps that follow the reduced phase multiply only the movement since the
-    block's FP64 anchor (in FP32, or in the BF16 split form), so a 1e-9 gap is
-    reached and the FP64 bound agrees with the oracle's to 1e-8 of the primal
-    value."""
+    """FP32, BF16 and FP8 modes below their own rounding floors: the anchored
+    sweeps on the FP64 state multiply only the movement since the block's FP64
+    anchor (in FP32, in the BF16 split form, or with the FP8 codes), so a 1e-9
+    gap is reached and the FP64 bound agrees with the oracle's to 1e-8 of the
+    primal value."""
     inst, o, root = cases[name]
     K = 24
     codes, beta0, v0 = random_nodes(inst.p, K, 8, root["beta"], root["v"])
@@ -291,7 +292,7 @@ def test_bnb_dfs_fp64_trace_identical_to_oracle(torch_cuda, orc):
     assert list(got["support"]) == list(ref["support"])
 
 
-@pytest.mark.parametrize("precision,K", [("fp64", 64), ("fp32", 64), ("fp32", 256), ("bf16", 128)])
+@pytest.mark.parametrize("precision,K", [("fp64", 64), ("fp32", 64), ("fp32", 256), ("bf16", 128), ("fp8", 128)])
 def test_bnb_best_first_certifies_the_oracle_optimum(torch_cuda, orc, precision, K):
     inst = datagen.config_instance("C1", seed=0)
     o = orc.Oracle.from_instance(inst)
@@ -325,9 +326,14 @@ def test_edge_cases(torch_cuda, cases):
         ctx.solve_node_batch(np.zeros((2, inst.p), np.uint8), max_iter=0)
     with pytest.raises(L0L2Error):
         ctx.set_data(inst.X, inst.y, inst.lambda0, -1.0, inst.M)
+    # FP8 storage runs anchored solves only: fixed sweeps are refused
+    c8 = ctx_for(inst, "fp8")
+    with pytest.raises(L0L2Error):
+        c8.admm_sweeps(np.zeros((2, inst.p), np.uint8), np.zeros((2, inst.p), np.float32),
+                       np.zeros((2, inst.p), np.float32), 3)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp8"])
 def test_graph_replay_and_eager_issue_agree_bitwise(torch_cuda, cases, precision):
     """Blocks of sweeps replayed from captured HIP graphs and the same blocks
     issued launch by launch (the profiler forces that) give identical bits; a
