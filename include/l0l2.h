@@ -234,7 +234,10 @@ int l0l2_server_destroy(l0l2_server *srv);
  * and the fastest kept per instance; fixed shapes serve tests and tuning
  * studies (a fixed shape whose node tile does not divide the padded batch makes
  * the solve calls fail with L0L2_E_INVALID).  Results do not depend on the
- * shape beyond rounding of the summation order. */
+ * shape beyond rounding of the summation order.  BF16 mode maps the shape to
+ * its own three (0 = 32x32 register tile, 1 = 64x64 and 2 = 128x128 LDS-staged,
+ * larger values taken as 2); FP8 mode does the same for the contraction over n
+ * and has one shape (32x32) for the contraction over p. */
 int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
 
 /* Opt-in timing of the library's kernels with HIP events recorded on the

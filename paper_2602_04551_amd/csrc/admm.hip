@@ -1282,6 +1282,163 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_fp8(
     }
 }
 
+// LDS-staged tile of the FP8 form (4 waves, 2 x 2; TM = 32 WM, TN = 32 WN) for
+// the contraction over n.  A k chunk of 32 stages, per row, the 32 code bytes of
+// A (rows 32 bytes apart: the 8-byte fragment reads of 16 rows x 4 k offsets
+// cover 512 contiguous bytes) and the FP32 values of B (rows padded to 144
+// bytes as in the BF16 tile); lane l reads the 8 codes of row l%16 at k offset
+// 8 (l/16) and widens them, and the B fragment is split into BF16 hi / lo.
+template <int WM, int WN>
+struct LdsTileF8 {
+    static constexpr int TM = 32 * WM, TN = 32 * WN;
+    static constexpr int ROWA = 32, ROWB = 144;                // bytes per staged row
+    static constexpr int PA = TM * 2, NA = (PA + 255) / 256;   // 16-byte parts of the A slab
+    static constexpr int NB = TN * 8 / 256;
+    static constexpr int STAGE = TM * ROWA + TN * ROWB;        // bytes per buffer
+};
+
+template <int WM, int WN>
+__device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int64_t lda,
+                                             const float *__restrict__ B, int64_t ldb, int64_t kdim, int64_t m0,
+                                             int64_t n0, const NodeCols &ncl, unsigned char *smem,
+                                             f32x4 (&acc)[WM][WN]) {
+    typedef LdsTileF8<WM, WN> L;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int q = lane >> 4, r = lane & 15;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    // staged 16-byte part e of this thread: A row idx / 2, part idx % 2 (only
+    // idx < PA); B row idx / 8, part idx % 8
+    const unsigned char *ga[L::NA];
+    const unsigned char *gb[L::NB];
+    int la[L::NA], lb[L::NB];
+    bool ha[L::NA];
+#pragma unroll
+    for (int e = 0; e < L::NA; ++e) {
+        const int idx = tid + 256 * e, row = (idx < L::PA ? idx : 0) >> 1, part = idx & 1;
+        ha[e] = idx < L::PA;
+        ga[e] = qA + (m0 + row) * lda + 16 * part;
+        la[e] = row * L::ROWA + 16 * part;
+    }
+#pragma unroll
+    for (int e = 0; e < L::NB; ++e) {
+        const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
+        gb[e] = reinterpret_cast<const unsigned char *>(B + col_row(col_slot(ncl, n0 + row), n0 + row) * ldb) +
+                16 * part;
+        lb[e] = L::TM * L::ROWA + row * L::ROWB + 16 * part;
+    }
+    float4 va[L::NA], vb[L::NB];
+    // chunk c covers 32 k: 32 code bytes, 128 bytes of FP32
+#define L0L2_GLOADF(c)                                                                                       \
+    _Pragma("unroll") for (int e = 0; e < L::NA; ++e) va[e] = *reinterpret_cast<const float4 *>(ga[e] + 32 * (c)); \
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) vb[e] = *reinterpret_cast<const float4 *>(gb[e] + 128 * (c));
+#define L0L2_SSTOREF(st)                                                                                     \
+    _Pragma("unroll") for (int e = 0; e < L::NA; ++e) if (ha[e])                                              \
+        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + la[e]) = va[e];                                  \
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e)                                                        \
+        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + lb[e]) = vb[e];
+    const int64_t nch = kdim / 32;
+    L0L2_GLOADF(0)
+    L0L2_SSTOREF(0)
+    __syncthreads();
+    for (int64_t c = 0; c < nch; ++c) {
+        const int st = (int)(c & 1);
+        const int64_t cn = c + 1 < nch ? c + 1 : c;
+        L0L2_GLOADF(cn)
+        const unsigned char *sa = smem + st * L::STAGE;
+        bf16x8 ah[WM], bh[WN], bl[WN];
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+            ah[i] = fp8x8_to_bf16(*reinterpret_cast<const uint2 *>(sa + (wm * 16 * WM + 16 * i + r) * L::ROWA + 8 * q));
+#pragma unroll
+        for (int j = 0; j < WN; ++j) {
+            const float *row =
+                reinterpret_cast<const float *>(sa + L::TM * L::ROWA + (wn * 16 * WN + 16 * j + r) * L::ROWB);
+            float bv[8];
+            load8f(row + 8 * q, bv);
+            split8(bv, bh[j], bl[j]);
+        }
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int j = 0; j < WN; ++j) {
+                acc[i][j] = mfma16_bf16(ah[i], bh[j], acc[i][j]);
+                acc[i][j] = mfma16_bf16(ah[i], bl[j], acc[i][j]);
+            }
+        L0L2_SSTOREF(st ^ 1)
+        __syncthreads();
+    }
+#undef L0L2_GLOADF
+#undef L0L2_SSTOREF
+}
+
+// Contraction over n of an anchored sweep in FP8 storage, LDS-staged tile:
+// Q = z_a + s o (q^T U), FP64 update, d = fl32(W_new - w_a), with the
+// node-major LDS epilogue of the other LDS tiles.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_admm_xtu_fp8_lds(
+    const uint8_t *__restrict__ qA, int64_t lda, const float *__restrict__ sc, const float *__restrict__ U,
+    int64_t ldu, int64_t kdim, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W,
+    double *__restrict__ beta, double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d,
+    const uint8_t *__restrict__ codes, const double *__restrict__ c, const int *__restrict__ active,
+    DevParams<double> q, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    typedef LdsTileF8<WM, WN> L;
+    __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    if (col_slot(ncl, n0) < 0) return;
+    f32x4 acc[WM][WN];
+    lds_tile_fp8<WM, WN>(qA, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
+    const bool est = gpart != nullptr;
+    typedef LdsEpi<float, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    float *buf = reinterpret_cast<float *>(smem);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    float sj[E::H];
+#pragma unroll
+    for (int h = 0; h < E::H; ++h) sj[h] = sc[m0 + lane + 64 * h];
+    for (int pass = 0; pass < NP; ++pass) {
+        const int c0 = pass * PN;
+        __syncthreads();
+        acc_stage<float, WM, WN>(acc, buf, c0, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            EpiIn<double> ei[E::H];
+            double za[E::H], wa[E::H];
+            epi_load_row<double, E::H>(ei, slot, n0 + nl, m0, ldp, W, V, codes, c, active);
+#pragma unroll
+            for (int h = 0; h < E::H; ++h) {
+                const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
+                za[h] = Za[o];
+                wa[h] = Wa[o];
+            }
+            double e[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+            for (int h = 0; h < E::H; ++h) {
+                if (!ei[h].on) continue;
+                const int m = lane + 64 * h;
+                const int64_t o = (int64_t)slot * ldp + m0 + m;
+                double ev[5] = {0, 0, 0, 0, 0};
+                const double Qv = za[h] + (double)sj[h] * (double)buf[(nl - c0) * E::LD + m];
+                const double wn = admm_update<double>(Qv, ei[h], o, W, beta, V, Bst, q, store_b, est, ga, ev);
+                d[o] = (float)(wn - wa[h]);
+#pragma unroll
+                for (int u = 0; u < 5; ++u) e[u] += ev[u];
+            }
+            if (est) {
+                wave_sum5(e);
+                if (lane == 0 && slot >= 0)
+                    for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Gap check (FP64)
 // ---------------------------------------------------------------------------
@@ -2015,25 +2172,91 @@ void sweep_once_anch(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
     HIPCHK(hipGetLastError());
 }
 
-// One anchored sweep in FP8 storage (register tiles 32 x 32, 8 waves): U = Xh d
-// with the codes, then the FP64 update from z_a + Xh^T U.
+// Contraction over n of the FP8 form: shape 0 = register tile 32 x 32 (8
+// waves), 1 = LDS-staged 64 x 64, 2 = LDS-staged 128 x 128.
+constexpr int kShapesFp8 = 3;
+constexpr int kF8TM[kShapesFp8] = {32, 64, 128};
+constexpr int kF8TN[kShapesFp8] = {32, 64, 128};
+
+void launch_xtu_fp8(int v, l0l2_ctx *ctx, int64_t Kp, const int *active, int store_b, double *gpart, NodeCols ncl) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    if (v < 0 || v >= kShapesFp8 || Kp % kF8TN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    dim3 g((unsigned)(in.pp / kF8TM[v]), (unsigned)(Kp / kF8TN[v]));
+#define L0L2_XTUF8(KER, NT)                                                                                     \
+    hipLaunchKernelGGL(KER, g, dim3(NT), 0, ctx->stream, in.qC.as<uint8_t>(), in.ldqc, in.qs.as<float>(), s32.U,   \
+                       in.ldu, in.np, ws.Za.as<double>(), ws.Wa.as<double>(), s64.W, s64.beta, s64.V, s64.B, s32.W, \
+                       ws.codes.as<uint8_t>(), s64.c, active, dev_params<double>(in.mp), in.ldp, store_b, gpart,    \
+                       gate_args(in), ncl)
+    if (v == 0) L0L2_XTUF8(k_admm_xtu_fp8, 64 * kWavesBf16);
+    else if (v == 1) L0L2_XTUF8((k_admm_xtu_fp8_lds<2, 2>), 256);
+    else L0L2_XTUF8((k_admm_xtu_fp8_lds<4, 4>), 256);
+#undef L0L2_XTUF8
+}
+
+// FP8 shape of the contraction over n, per live bucket, timed like tile_choice
+// (kind 3; the contraction over p has one shape).
+int tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
+    Instance &in = ctx->inst;
+    if (ctx->force_xw >= 0) return std::min(ctx->force_xtu, kShapesFp8 - 1);
+    auto key = std::make_pair(3, Kp);
+    auto it = in.tiles.find(key);
+    if (it != in.tiles.end()) return it->second.xtu;
+    TileChoice tc;
+    tc.xw = tc.xtu = 0;
+    if (ctx->tune) {
+        hipStream_t s = ctx->stream;
+        DevBuf inactive;
+        inactive.ensure(sizeof(int) * Kp);
+        HIPCHK(hipMemsetAsync(inactive.ptr, 0, sizeof(int) * Kp, s));
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto time_shape = [&](int v, int reps) {
+            HIPCHK(hipEventRecord(e0, s));
+            for (int t = 0; t < reps; ++t) launch_xtu_fp8(v, ctx, Kp, inactive.as<int>(), 0, nullptr, NodeCols{nullptr});
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return ms / (float)reps;
+        };
+        float t0 = 0.f;
+        for (int v = 0; v < kShapesFp8; ++v)
+            if (Kp % kF8TN[v] == 0) t0 = std::max(t0, time_shape(v, 1));
+        const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
+        const int rounds = t0 > 1.0f ? 2 : 4;
+        float best[kShapesFp8];
+        for (int v = 0; v < kShapesFp8; ++v) best[v] = 1e30f;
+        for (int r = 0; r < rounds; ++r)
+            for (int v = 0; v < kShapesFp8; ++v)
+                if (Kp % kF8TN[v] == 0) best[v] = std::min(best[v], time_shape(v, reps));
+        for (int v = 1; v < kShapesFp8; ++v)
+            if (best[v] < best[tc.xtu]) tc.xtu = v;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(hipGetLastError());
+    }
+    return (in.tiles[key] = tc).xtu;
+}
+
+// One anchored sweep in FP8 storage: U = Xh d with the codes (register tile
+// 32 x 32, 8 waves), then the FP64 update from z_a + Xh^T U.
 void sweep_once_fp8(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
     Sweep<float> s32 = sweep32(ctx);
-    Sweep<double> s64 = sweep64(ctx);
     const NodeCols ncl = active_cols(ctx);
+    const int v = tile_choice_fp8(ctx, Kp);
     prof_begin(ctx, PROF_GEMM_XW_FP8);
     hipLaunchKernelGGL(k_gemm_xw_fp8, dim3((unsigned)(in.np / 32), (unsigned)(Kp / 32)), dim3(64 * kWavesBf16), 0, s,
                        in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), s32.W, in.ldp, s32.U, in.ldu, in.pp, ncl);
     prof_end(ctx, PROF_GEMM_XW_FP8, active);
     prof_begin(ctx, PROF_ADMM_XTU_FP8);
-    hipLaunchKernelGGL(k_admm_xtu_fp8, dim3((unsigned)(in.pp / 32), (unsigned)(Kp / 32)), dim3(64 * kWavesBf16), 0, s,
-                       in.qC.as<uint8_t>(), in.ldqc, in.qs.as<float>(), s32.U, in.ldu, in.np, ws.Za.as<double>(),
-                       ws.Wa.as<double>(), s64.W, s64.beta, s64.V, s64.B, s32.W, ws.codes.as<uint8_t>(), s64.c,
-                       ws.active.as<int>(), dev_params<double>(in.mp), in.ldp, store_b ? 1 : 0,
-                       gate ? ws.gpart.as<double>() : nullptr, gate_args(in), ncl);
+    launch_xtu_fp8(v, ctx, Kp, ws.active.as<int>(), store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, ncl);
     prof_end(ctx, PROF_ADMM_XTU_FP8, active);
     HIPCHK(hipGetLastError());
 }
@@ -2158,7 +2381,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), cols).xtu];
         else if (kind == SK_BF16 || (kind == SK_ANCH && in.prec == L0L2_BF16))
             rows = kBfTM[tile_choice_bf16(ctx, cols).xtu];
-        else if (kind == SK_ANCH && in.prec == L0L2_FP8) rows = 32;
+        else if (kind == SK_ANCH && in.prec == L0L2_FP8) rows = kF8TM[tile_choice_fp8(ctx, cols)];
         else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), cols).xtu];
         GateFin gf{in.yy, tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
@@ -2198,6 +2421,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
             if (kind == SK_F32 || (kind == SK_ANCH && !bf && !f8))
                 (void)tile_choice<float>(ctx, sweep32(ctx), cols);
             if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);
+            if (kind == SK_ANCH && f8) (void)tile_choice_fp8(ctx, cols);
             hipGraph_t g = nullptr;
             hipGraphExec_t ex = nullptr;
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
