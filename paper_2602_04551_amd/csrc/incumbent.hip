@@ -150,10 +150,42 @@ struct FistaShared {
     int it;
 };
 
+// Wave-wide reductions of doubles without the LDS crossbar: DPP row
+// butterflies (xor 1 and xor 2 within quads, then the half-row and row mirrors)
+// leave every lane of a 16-lane row with the row's value, and the four row
+// values are read from lanes 0, 16, 32 and 48 and combined in the same order on
+// every lane, so all lanes return identical bits.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
 // Sum over the 64 lanes of a wave; every lane receives the same value.
 __device__ __forceinline__ double wsum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
+// Maximum over the 64 lanes of a wave; every lane receives the same value.
+__device__ __forceinline__ double wmax(double v) {
+    v = fmax(v, dpp_f64<kDppXor1>(v));
+    v = fmax(v, dpp_f64<kDppXor2>(v));
+    v = fmax(v, dpp_f64<kDppHalfMirror>(v));
+    v = fmax(v, dpp_f64<kDppMirror>(v));
+    return fmax(fmax(lane_f64(v, 0), lane_f64(v, 16)), fmax(lane_f64(v, 32), lane_f64(v, 48)));
 }
 
 // Lane a < k: (G v)_a for v held one coordinate per lane (wave-local LDS
@@ -325,36 +357,36 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
             double alpha = 4.0 / (wsum(cn * cn) + 2.0 * fa.l2);
             // lane share of U(v) - yy/2 given (G v)_lane
             auto upart = [&](double v, double Gv) { return on ? 0.5 * v * Gv - g * v + fa.l2 * v * v : 0.0; };
-            double Ucur = 0.5 * yy + wsum(upart(cur, gram_mv(sm, cur, k, lane)));
+            // G cur and G prev are kept, so G ext = G cur + mom (G cur - G prev)
+            // needs no product (linearity); each trial forms G nxt
+            double Gcur = gram_mv(sm, cur, k, lane), Gprev = Gcur;
+            double Ucur = 0.5 * yy + wsum(upart(cur, Gcur));
             int it = 0;
             while (it < fa.max_iter) {
                 const double mom = (double)it / ((double)it + 3.0);
                 const double ext = cur + mom * (cur - prev);
-                const double Gve = gram_mv(sm, ext, k, lane);
+                const double Gve = Gcur + mom * (Gcur - Gprev);
                 const double grad = on ? Gve - g + 2.0 * fa.l2 * ext : 0.0;
-                const double ue = upart(ext, Gve);
-                double Uext = 0.0, Unxt = 0.0, nxt = 0.0, dm = 0.0;
+                const double Uext = 0.5 * yy + wsum(upart(ext, Gve));
+                double Unxt = 0.0, nxt = 0.0, Gn = 0.0, dm = 0.0;
                 for (int bt = 0; bt <= 60; ++bt) {
                     double v = ext - alpha * grad;
                     nxt = on ? (v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v)) : 0.0;
                     const double d = nxt - ext;
-                    // one fused pass of independent butterflies: U(ext) (first trial
-                    // only), <grad, d>, |d|^2, U(nxt) and max |nxt - cur|
-                    double r[5] = {ue, grad * d, d * d, upart(nxt, gram_mv(sm, nxt, k, lane)), fabs(nxt - cur)};
-                    for (int off = 32; off > 0; off >>= 1) {
-                        for (int i = 0; i < 4; ++i) r[i] += __shfl_xor(r[i], off);
-                        r[4] = fmax(r[4], __shfl_xor(r[4], off));
-                    }
-                    if (bt == 0) Uext = 0.5 * yy + r[0];
-                    Unxt = 0.5 * yy + r[3];
-                    dm = r[4];
-                    if (Unxt <= Uext + r[1] + r[2] / (2.0 * alpha) || bt == 60) break;
+                    Gn = gram_mv(sm, nxt, k, lane);
+                    // independent wave reductions: <grad, d>, |d|^2, U(nxt), max |nxt - cur|
+                    const double gd = wsum(grad * d), dd = wsum(d * d);
+                    Unxt = 0.5 * yy + wsum(upart(nxt, Gn));
+                    dm = wmax(fabs(nxt - cur));
+                    if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
                     alpha *= 0.5;
                 }
                 ++it;
                 const double dU = fabs(Unxt - Ucur);
                 prev = cur;
                 cur = nxt;
+                Gprev = Gcur;
+                Gcur = Gn;
                 Ucur = Unxt;
                 if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
             }
