@@ -156,16 +156,42 @@ def batch_detail(path):
             "fista_iters_mean": round(float(fi.mean()), 2), "fista_iters_max": int(fi.max())}
 
 
-def roofline(prof, n, p):
+def measured_traffic(kname):
+    """HBM bytes per launch of a contraction family from the committed counter
+    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE passes), or None when the kernel
+    sources have changed since those counters were taken."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for fn in sorted(glob.glob(os.path.join(ROOT, "paper_2602_04551_amd", "csrc", "*"))):
+        if fn.endswith((".hip", ".hpp")):
+            with open(fn, "rb") as f:
+                h.update(f.read())
+    if h.hexdigest() != rec.get("source_digest"):
+        return None
+    return rec["per_launch_bytes"].get(kname)
+
+
+def roofline(prof, n, p, traffic_from_counters=False):
     """Dominant sweep contraction by measured time; achieved = algorithmic flops
-    (2 n p per active node-iteration) over its summed launch durations."""
+    (2 n p per active node-iteration) over its summed launch durations.  The
+    counter summary covers the mixed FP32 path of the n = p = 1000 node batch
+    only (traffic_from_counters); elsewhere traffic is None."""
     sweep = [k for k in prof if k.startswith(("gemm_xw", "admm_xtu")) and prof[k][0] > 0]
     kname = max(sweep, key=lambda k: prof[k][1])
     launches, ms, units = prof[kname]
     prec = kname.split(".")[1]
     achieved = 2.0 * n * p * units / (ms * 1e-3) / 1e12
+    traffic = measured_traffic(kname) if traffic_from_counters and prec == "f32" else None
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK[prec], 4), "traffic": None, "kernel": kname,
+            "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 counters, profiles/c2_hbm_traffic.json)",
+            "kernel": kname,
             "launches": launches, "avg_us": round(1e3 * ms / max(launches, 1), 3),
             "flops_per_launch": round(2.0 * n * p * units / max(launches, 1)),
             "node_iterations": units}
@@ -331,7 +357,7 @@ def main():
     ms_per_step = 1e3 * dt / args.steps
     value = K * args.steps / dt
 
-    roof, kernels = roofline(prof, n, p)
+    roof, kernels = roofline(prof, n, p, traffic_from_counters=True)
     others = {}
     if not args.only_mixed:
         for prec in ("fp64", "bf16", "fp8"):

@@ -1,0 +1,49 @@
+"""Host-side checks of bench.py's contract helpers (no GPU)."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_roofline_counts_algorithmic_flops_of_the_dominant_family():
+    import bench
+    n, p = 1000, 1000
+    # family: (launches, ms, active node-iterations)
+    prof = {"gemm_xw.f32": (10, 0.10, 2560), "admm_xtu.f32": (10, 0.12, 2560), "gap_check": (2, 0.05, 0)}
+    roof, kernels = bench.roofline(prof, n, p)
+    assert roof["kernel"] == "admm_xtu.f32"
+    achieved = 2.0 * n * p * 2560 / (0.12e-3) / 1e12
+    assert roof["achieved"] == pytest.approx(achieved, rel=1e-3)
+    assert roof["peak"] == 157.3 and roof["frac"] == pytest.approx(achieved / 157.3, rel=1e-3)
+    assert roof["traffic"] is None          # not asked for
+    assert set(kernels) == set(prof)
+
+
+def test_counter_traffic_is_dropped_when_the_kernel_sources_change(tmp_path, monkeypatch):
+    import bench
+    prof_dir = tmp_path / "profiles"
+    prof_dir.mkdir()
+    (prof_dir / "c2_hbm_traffic.json").write_text(json.dumps(
+        {"source_digest": "not-the-current-sources", "per_launch_bytes": {"admm_xtu.f32": 123}}))
+    csrc = tmp_path / "paper_2602_04551_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    (csrc / "a.hip").write_text("// kernel source\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("admm_xtu.f32") is None
+    import hashlib
+    digest = hashlib.sha256(b"// kernel source\n").hexdigest()
+    (prof_dir / "c2_hbm_traffic.json").write_text(json.dumps(
+        {"source_digest": digest, "per_launch_bytes": {"admm_xtu.f32": 123}}))
+    assert bench.measured_traffic("admm_xtu.f32") == 123
