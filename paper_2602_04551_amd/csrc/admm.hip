@@ -186,7 +186,8 @@ __device__ __forceinline__ void mma_chunk(typename Acc<TC>::type (&acc)[BM][BN],
 
 template <class TA, class TB, class TC, int BM, int BN, int WAVES>
 __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B, int64_t ldb,
-                                        int64_t kdim, int64_t m0, int64_t n0, const int (&sb)[BN], TC *red) {
+                                        int64_t kdim, int64_t m0, int64_t n0, const int (&sb)[BN], TC *red,
+                                        int64_t pr0 = 0, int64_t pr1 = -1) {
     constexpr int TM = 16 * BM, TN = 16 * BN;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
@@ -194,9 +195,11 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
     AccT acc[BM][BN];
     for (int i = 0; i < BM; ++i)
         for (int j = 0; j < BN; ++j) acc[i][j] = AccT{0, 0, 0, 0};
-    const int64_t npr = kdim / 32;
+    // pairs [pr0, pr1) of the workgroup (all of kdim by default), split over the waves
+    if (pr1 < 0) pr1 = kdim / 32;
+    const int64_t npr = pr1 - pr0;
     const int wu = __builtin_amdgcn_readfirstlane(w);
-    const int64_t c0 = 2 * (npr * wu / WAVES), c1 = 2 * (npr * (wu + 1) / WAVES);
+    const int64_t c0 = 2 * (pr0 + npr * wu / WAVES), c1 = 2 * (pr0 + npr * (wu + 1) / WAVES);
     const TA *Ap[BM];
     const TB *Bp[BN];
     for (int i = 0; i < BM; ++i) Ap[i] = A + (m0 + 16 * i + r) * lda + 4 * q;
@@ -234,18 +237,23 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
 }
 
 // Contraction over p: U[k][i] = sum_j Xh[i][j] W[k][j] (A = row-major Xh), for
-// the node slots k of the live columns.
+// the node slots k of the live columns.  With gridDim.z = S > 1 slice z takes
+// pairs [npr z / S, npr (z + 1) / S) of the 32-wide pairs of k and writes its
+// partial product to U + z pstride (added in slice order by k_splitk_sum): a
+// grid of S times as many workgroups for few live nodes and a long range p.
 template <class TA, class TB, class TC, int BM, int BN, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A, int64_t lda,
                                                         const TB *__restrict__ B, int64_t ldb, TC *__restrict__ U,
-                                                        int64_t ldu, int64_t kdim, NodeCols ncl) {
+                                                        int64_t ldu, int64_t kdim, NodeCols ncl, int64_t pstride) {
     constexpr int TM = 16 * BM, TN = 16 * BN, E = TM * TN / (64 * WAVES);
     static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
     __shared__ TC red[WAVES * Red<TM, TN>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
     int sb[BN], se[E];
     if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
-    nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, sb, red);
+    const int64_t npr = kdim / 32, z = blockIdx.z, S = gridDim.z;
+    U += pstride * z;
+    nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, sb, red, npr * z / S, npr * (z + 1) / S);
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int idx = threadIdx.x + t * 64 * WAVES, n = idx / TM, m = idx % TM;
@@ -602,17 +610,23 @@ __device__ __forceinline__ void epi_load_row(EpiIn<T> (&ei)[H], int slot, int64_
     for (int h = 0; h < H; ++h) epi_load<T>(ei[h], slot, col, m0 + lane + 64 * h, ldp, W, V, codes, c, active);
 }
 
-// Contraction over p (U = Xh W^T) with an LDS-staged tile.
+// Contraction over p (U = Xh W^T) with an LDS-staged tile.  With gridDim.z = S
+// > 1 the contraction range is cut into S equal slices (kdim / S a multiple of
+// 16) and slice z writes its partial product to U + z pstride; k_splitk_sum adds
+// the slices in order.  That gives a grid of S times as many workgroups when the
+// output (n x nodes) is small and the range p long.
 template <class T, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
                                                      int64_t ldb, T *__restrict__ U, int64_t ldu, int64_t kdim,
-                                                     NodeCols ncl) {
+                                                     NodeCols ncl, int64_t pstride) {
     typedef LdsTile<T, WM, WN> L;
     __shared__ __align__(16) T smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
     if (col_slot(ncl, n0) < 0) return;
+    const int64_t ks = kdim / gridDim.z, k0 = ks * blockIdx.z;
+    U += pstride * blockIdx.z;
     typename Acc<T>::type acc[WM][WN];
-    lds_tile<T, WM, WN>(A, lda, B, ldb, kdim, m0, n0, ncl, smem, acc);
+    lds_tile<T, WM, WN>(A + k0, lda, B + k0, ldb, ks, m0, n0, ncl, smem, acc);
     typedef LdsEpi<T, WM, WN> E;
     constexpr int NP = E::passes(sizeof(smem));
     static_assert(NP > 0, "epilogue staging does not fit");
@@ -631,6 +645,21 @@ __global__ __launch_bounds__(256) void k_gemm_xw_lds(const T *__restrict__ A, in
                 U[(int64_t)slot * ldu + m0 + lane + 64 * h] = smem[(nl - c0) * E::LD + lane + 64 * h];
         }
     }
+}
+
+// U[slot][m] = sum over the S slices of the partial products, in slice order,
+// for the live columns.
+template <class T>
+__global__ __launch_bounds__(256) void k_splitk_sum(const T *__restrict__ P, int64_t pstride, int S,
+                                                    T *__restrict__ U, int64_t ldu, int64_t rows, NodeCols ncl) {
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x, c = blockIdx.y;
+    if (m >= rows) return;
+    const int slot = col_slot(ncl, c);
+    if (slot < 0) return;
+    const int64_t o = (int64_t)slot * ldu + m;
+    T v = P[o];
+    for (int z = 1; z < S; ++z) v += P[z * pstride + o];
+    U[o] = v;
 }
 
 // Contraction over n with the ADMM epilogue, LDS-staged tile.
@@ -772,16 +801,19 @@ __device__ __forceinline__ void load8f(const float *p, float out[8]) {
 template <int WAVES>
 __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
                                              int64_t lda, const float *__restrict__ B, int64_t ldb, int64_t kdim,
-                                             int64_t m0, int64_t n0, const int (&sb)[2], float *red) {
+                                             int64_t m0, int64_t n0, const int (&sb)[2], float *red,
+                                             int64_t pr0 = 0, int64_t pr1 = -1) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
     const int64_t brow[2] = {col_row(sb[0], n0 + r), col_row(sb[1], n0 + 16 + r)};
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
-    const int64_t npr = kdim / 64;
+    // pairs [pr0, pr1) of 64 k (all of kdim by default), split over the waves
+    if (pr1 < 0) pr1 = kdim / 64;
+    const int64_t npr = pr1 - pr0;
     const int wu = __builtin_amdgcn_readfirstlane(w);
-    const int64_t c0 = 2 * (npr * wu / WAVES), c1 = 2 * (npr * (wu + 1) / WAVES);
+    const int64_t c0 = 2 * (pr0 + npr * wu / WAVES), c1 = 2 * (pr0 + npr * (wu + 1) / WAVES);
     bf16x8 ah[2][2], al[2][2];
     float bv[2][2][8];
     auto load = [&](int st, int64_t c) {
@@ -1035,18 +1067,22 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
 
 constexpr int kWavesBf16 = 8;
 
-// U[k][i] = sum_j Xh[i][j] W[k][j] with Xh row-major (row i at A + i*lda).
+// U[k][i] = sum_j Xh[i][j] W[k][j] with Xh row-major (row i at A + i*lda); with
+// gridDim.z = S > 1, slices of the range write partial products to U + z pstride
+// as in k_gemm_xw.
 __global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *__restrict__ Ahi,
                                                                   const __bf16 *__restrict__ Alo, int64_t lda,
                                                                   const float *__restrict__ B, int64_t ldb,
                                                                   float *__restrict__ U, int64_t ldu, int64_t kdim,
-                                                                  NodeCols ncl) {
+                                                                  NodeCols ncl, int64_t pstride) {
     __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
     constexpr int E = 1024 / (64 * kWavesBf16);
     int sb[2], se[E];
     if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
-    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, sb, red);
+    const int64_t npr = kdim / 64, z = blockIdx.z, S = gridDim.z;
+    U += pstride * z;
+    nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, sb, red, npr * z / S, npr * (z + 1) / S);
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int idx = threadIdx.x + t * 64 * kWavesBf16, n = idx >> 5, m = idx & 31;
@@ -1165,16 +1201,19 @@ __device__ __forceinline__ bf16x8 fp8x8_to_bf16(uint2 v) {
 template <int WAVES, bool SCALE_B>
 __device__ __forceinline__ void nt_tile_fp8(const uint8_t *__restrict__ qA, int64_t lda, const float *__restrict__ sc,
                                             const float *__restrict__ B, int64_t ldb, int64_t kdim, int64_t m0,
-                                            int64_t n0, const int (&sb)[2], float *red) {
+                                            int64_t n0, const int (&sb)[2], float *red, int64_t pr0 = 0,
+                                            int64_t pr1 = -1) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int q = lane >> 4, r = lane & 15;
     const int64_t brow[2] = {col_row(sb[0], n0 + r), col_row(sb[1], n0 + 16 + r)};
     f32x4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0, 0, 0, 0};
-    const int64_t npr = kdim / 64;
+    // pairs [pr0, pr1) of 64 k (all of kdim by default), split over the waves
+    if (pr1 < 0) pr1 = kdim / 64;
+    const int64_t npr = pr1 - pr0;
     const int wu = __builtin_amdgcn_readfirstlane(w);
-    const int64_t c0 = 2 * (npr * wu / WAVES), c1 = 2 * (npr * (wu + 1) / WAVES);
+    const int64_t c0 = 2 * (pr0 + npr * wu / WAVES), c1 = 2 * (pr0 + npr * (wu + 1) / WAVES);
     uint2 av[2][2];
     float bv[2][2][8], sv[2][8];
     auto load = [&](int st, int64_t c) {
@@ -1222,18 +1261,22 @@ __device__ __forceinline__ void nt_tile_fp8(const uint8_t *__restrict__ qA, int6
     __syncthreads();
 }
 
-// Contraction over p in FP8 storage: U[k][i] = sum_j q[i][j] s[j] d[k][j].
+// Contraction over p in FP8 storage: U[k][i] = sum_j q[i][j] s[j] d[k][j]; with
+// gridDim.z = S > 1, slices of the range write partial products to U + z pstride
+// as in k_gemm_xw.
 __global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_fp8(const uint8_t *__restrict__ qA, int64_t lda,
                                                                  const float *__restrict__ sc,
                                                                  const float *__restrict__ B, int64_t ldb,
                                                                  float *__restrict__ U, int64_t ldu, int64_t kdim,
-                                                                 NodeCols ncl) {
+                                                                 NodeCols ncl, int64_t pstride) {
     __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
     const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
     constexpr int E = 1024 / (64 * kWavesBf16);
     int sb[2], se[E];
     if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
-    nt_tile_fp8<kWavesBf16, true>(qA, lda, sc, B, ldb, kdim, m0, n0, sb, red);
+    const int64_t npr = kdim / 64, z = blockIdx.z, S = gridDim.z;
+    U += pstride * z;
+    nt_tile_fp8<kWavesBf16, true>(qA, lda, sc, B, ldb, kdim, m0, n0, sb, red, npr * z / S, npr * (z + 1) / S);
 #pragma unroll
     for (int t = 0; t < E; ++t) {
         const int idx = threadIdx.x + t * 64 * kWavesBf16, n = idx >> 5, m = idx & 31;
@@ -1760,10 +1803,23 @@ template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
 // waves per workgroup.  Shapes 0-8 are register tiles whose waves split the
 // contraction range (FP64 keeps at most 8 waves on the 32 x 32 tile: LDS for
 // the cross-wave reduction); shapes 9-11 are LDS-staged tiles (4 waves, 2 x 2).
-constexpr int kShapes = 12;
-constexpr int kTileTM[kShapes] = {32, 32, 32, 16, 32, 16, 64, 32, 64, 64, 128, 128};
-constexpr int kTileTN[kShapes] = {32, 32, 32, 32, 16, 16, 32, 64, 32, 64, 64, 128};
-constexpr int kTileW[kShapes] = {4, 8, 16, 8, 8, 4, 8, 8, 4, 4, 4, 4};
+// Shapes 12-16 serve the contraction over p only and cut its range into
+// slices: 12, 13 = the 128 x 128 LDS-staged tile in 2 or 4 slices; 14, 15 = the
+// 16 x 16 register tile (4 waves) in 4 or 8 slices; 16 = the 32 x 32 register
+// tile (4 waves) in 4 slices.
+constexpr int kShapes = 12, kShapesXw = 17;
+constexpr int kTileTM[kShapesXw] = {32, 32, 32, 16, 32, 16, 64, 32, 64, 64, 128, 128, 128, 128, 16, 16, 32};
+constexpr int kTileTN[kShapesXw] = {32, 32, 32, 32, 16, 16, 32, 64, 32, 64, 64, 128, 128, 128, 16, 16, 32};
+constexpr int kTileW[kShapesXw] = {4, 8, 16, 8, 8, 4, 8, 8, 4, 4, 4, 4, 4, 4, 4, 4, 4};
+constexpr int kSplit[kShapesXw] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 4, 8, 4};
+constexpr int kMaxSplit = 8;
+int split_of(int v) { return kSplit[v]; }
+
+// Partial-product buffer of the sliced shapes.
+struct SplitBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
 
 // A shape fits a padded batch when its node tile divides it (rows are padded to
 // multiples of 128).
@@ -1771,15 +1827,38 @@ bool shape_fits(int v, int64_t Kp) { return Kp % kTileTN[v] == 0; }
 
 template <class TA, class TB, class TC>
 void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int64_t ldb, TC *U, int64_t ldu,
-               int64_t rows, int64_t Kp, int64_t kdim, NodeCols ncl = NodeCols{nullptr}) {
+               int64_t rows, int64_t Kp, int64_t kdim, NodeCols ncl = NodeCols{nullptr}, SplitBuf sk = SplitBuf{}) {
     if (sizeof(TC) == 8 && v == 2) v = 1;
-    if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    if (v < 0 || v >= kShapesXw || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(rows / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XW(PBM, PBN, PW) \
-    hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, PBM, PBN, PW>), g, b, 0, s, A, lda, B, ldb, U, ldu, kdim, ncl)
+    hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, PBM, PBN, PW>), g, b, 0, s, A, lda, B, ldb, U, ldu, kdim, ncl, (int64_t)0)
 #define L0L2_XWL(WM, WN) \
-    hipLaunchKernelGGL((k_gemm_xw_lds<TC, WM, WN>), g, b, 0, s, (const TC *)A, lda, (const TC *)B, ldb, U, ldu, kdim, ncl)
+    hipLaunchKernelGGL((k_gemm_xw_lds<TC, WM, WN>), g, b, 0, s, (const TC *)A, lda, (const TC *)B, ldb, U, ldu, kdim, \
+                       ncl, (int64_t)0)
+    if (v >= kShapes) {
+        const int S = split_of(v);
+        const int64_t pstride = Kp * ldu;
+        if ((size_t)S * pstride * sizeof(TC) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+        TC *P = static_cast<TC *>(sk.ptr);
+        const dim3 gs(g.x, g.y, (unsigned)S);
+        if (v <= 13) {
+            if (!std::is_same<TA, TC>::value || !std::is_same<TB, TC>::value)
+                fail(L0L2_E_INVALID, "LDS-staged tiles take one operand type");
+            hipLaunchKernelGGL((k_gemm_xw_lds<TC, 4, 4>), gs, b, 0, s, (const TC *)A, lda, (const TC *)B, ldb, P, ldu,
+                               kdim, ncl, pstride);
+        } else if (v <= 15) {
+            hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 1, 1, 4>), gs, b, 0, s, A, lda, B, ldb, P, ldu, kdim, ncl,
+                               pstride);
+        } else {
+            hipLaunchKernelGGL((k_gemm_xw<TA, TB, TC, 2, 2, 4>), gs, b, 0, s, A, lda, B, ldb, P, ldu, kdim, ncl,
+                               pstride);
+        }
+        hipLaunchKernelGGL(k_splitk_sum<TC>, dim3((unsigned)((rows + 255) / 256), (unsigned)Kp), dim3(256), 0, s,
+                           (const TC *)P, pstride, S, U, ldu, rows, ncl);
+        return;
+    }
     if (v >= 9) {
         if (!std::is_same<TA, TC>::value || !std::is_same<TB, TC>::value)
             fail(L0L2_E_INVALID, "LDS-staged tiles take one operand type");
@@ -1880,6 +1959,21 @@ void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<
 #undef L0L2_XTUAL
 }
 
+// The partial-product buffer of the sliced shapes, sized for kMaxSplit slices of
+// a Kp-node product with rows of ld elements of elem bytes.  It grows only
+// before a capture (the tile choice runs first); a move drops the captured
+// graphs, which hold its address.
+void ensure_split(l0l2_ctx *ctx, int64_t Kp, int64_t ld, size_t elem) {
+    Workspace &ws = ctx->ws;
+    const size_t need = (size_t)kMaxSplit * Kp * ld * elem;
+    if (need <= ws.Upart.bytes) return;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ws.Upart.ensure(need);
+    drop_graphs(ctx);
+    ++ws.gen;
+}
+SplitBuf split_buf(l0l2_ctx *ctx) { return SplitBuf{ctx->ws.Upart.ptr, ctx->ws.Upart.bytes}; }
+
 // Tile shapes chosen for (arithmetic type, padded batch): each shape that fits
 // is timed on the live batch (every node masked inactive, so the epilogue
 // writes nothing), the best of several interleaved samples per shape, and the
@@ -1888,6 +1982,7 @@ template <class T>
 TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
+    ensure_split(ctx, Kp, sw.ldu, sizeof(T));
     if (ctx->force_xw >= 0) {
         static thread_local TileChoice forced;
         forced.xw = ctx->force_xw;
@@ -1914,7 +2009,9 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         auto time_shape = [&](int v, int which, int reps) {
             HIPCHK(hipEventRecord(e0, s));
             for (int t = 0; t < reps; ++t) {
-                if (which == 0) launch_xw<T, T, T>(v, s, sw.XhR, sw.ldr, sw.W, sw.ldp, sw.U, sw.ldu, np, Kp, pp);
+                if (which == 0)
+                    launch_xw<T, T, T>(v, s, sw.XhR, sw.ldr, sw.W, sw.ldp, sw.U, sw.ldu, np, Kp, pp, NodeCols{nullptr},
+                                       split_buf(ctx));
                 else launch_xtu<T>(v, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), inactive.as<int>(), q, 0);
             }
             HIPCHK(hipEventRecord(e1, s));
@@ -1925,24 +2022,30 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         };
         // warm-up round, which also sizes the measurement: about 0.2 ms of work
         // per sample, and fewer rounds for launches longer than 1 ms
+        // which = 1 (the contraction over n) has no sliced shapes; a sliced shape
+        // is a candidate only where its tile unsliced would leave CUs idle
+        // (fewer workgroups than the 256 compute units)
+        auto valid = [&](int v, int which) {
+            if (!shape_fits(v, Kp)) return false;
+            if (v < kShapes) return true;
+            return which == 0 && (np / kTileTM[v]) * (Kp / kTileTN[v]) < 256;
+        };
         float t0 = 0.f;
-        for (int v = 0; v < kShapes; ++v)
-            if (shape_fits(v, Kp)) t0 = std::max(t0, std::max(time_shape(v, 0, 1), time_shape(v, 1, 1)));
+        for (int v = 0; v < kShapesXw; ++v)
+            for (int which = 0; which < 2; ++which)
+                if (valid(v, which)) t0 = std::max(t0, time_shape(v, which, 1));
         const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
         const int rounds = t0 > 1.0f ? 2 : 4;
-        float best[kShapes][2];
-        for (int v = 0; v < kShapes; ++v) best[v][0] = best[v][1] = 1e30f;
+        float best[kShapesXw][2];
+        for (int v = 0; v < kShapesXw; ++v) best[v][0] = best[v][1] = 1e30f;
         for (int r = 0; r < rounds; ++r)
-            for (int v = 0; v < kShapes; ++v) {
-                if (!shape_fits(v, Kp)) continue;
+            for (int v = 0; v < kShapesXw; ++v)
                 for (int which = 0; which < 2; ++which)
-                    best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
-            }
+                    if (valid(v, which)) best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
         float best_xw = 1e30f, best_xtu = 1e30f;
-        for (int v = 0; v < kShapes; ++v) {
-            if (!shape_fits(v, Kp)) continue;
-            if (best[v][0] < best_xw) { best_xw = best[v][0]; tc.xw = v; }
-            if (best[v][1] < best_xtu) { best_xtu = best[v][1]; tc.xtu = v; }
+        for (int v = 0; v < kShapesXw; ++v) {
+            if (valid(v, 0) && best[v][0] < best_xw) { best_xw = best[v][0]; tc.xw = v; }
+            if (valid(v, 1) && best[v][1] < best_xtu) { best_xtu = best[v][1]; tc.xtu = v; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -1976,7 +2079,8 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
     DevParams<T> q = dev_params<T>(in.mp);
     const TileChoice &tc = tile_choice<T>(ctx, sw, Kp);
     prof_begin(ctx, prof_xw<T>());
-    launch_xw<T, T, T>(tc.xw, s, sw.XhR, sw.ldr, sw.W, sw.ldp, sw.U, sw.ldu, np, Kp, pp, active_cols(ctx));
+    launch_xw<T, T, T>(tc.xw, s, sw.XhR, sw.ldr, sw.W, sw.ldp, sw.U, sw.ldu, np, Kp, pp, active_cols(ctx),
+                       split_buf(ctx));
     prof_end(ctx, prof_xw<T>(), active);
     prof_begin(ctx, prof_xtu<T>());
     launch_xtu<T>(tc.xtu, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), ws.active.as<int>(), q, store_b ? 1 : 0,
@@ -1987,20 +2091,35 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
 
 // Tile shapes of the BF16 split form: 0 = register tile 32 x 32 (8 waves split
 // the contraction), 1 = LDS-staged 64 x 64, 2 = LDS-staged 128 x 128.
-constexpr int kShapesBf16 = 3;
-constexpr int kBfTM[kShapesBf16] = {32, 64, 128};
-constexpr int kBfTN[kShapesBf16] = {32, 64, 128};
+// 3, 4 (contraction over p only): the register tile with the range cut into 4
+// or 8 slices.
+constexpr int kShapesBf16 = 3, kShapesBf16Xw = 5;
+constexpr int kBfTM[kShapesBf16Xw] = {32, 64, 128, 32, 32};
+constexpr int kBfTN[kShapesBf16Xw] = {32, 64, 128, 32, 32};
+constexpr int kBfSplit[kShapesBf16Xw] = {1, 1, 1, 4, 8};
 
 void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, NodeCols ncl) {
     Instance &in = ctx->inst;
     const int64_t np = in.np, pp = in.pp;
-    if (v < 0 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    if (v < 0 || v >= kShapesBf16Xw || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(np / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
     const __bf16 *hi = in.XhR.as<__bf16>(), *lo = in.XhRLo.as<__bf16>();
     const int64_t lda = in.ldwr, ldb = in.ldp, ldu = in.ldu;
+    if (v >= kShapesBf16) {
+        const int S = kBfSplit[v];
+        const int64_t pstride = Kp * ldu;
+        SplitBuf sk = split_buf(ctx);
+        if ((size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+        float *P = static_cast<float *>(sk.ptr);
+        hipLaunchKernelGGL(k_gemm_xw_bf16, dim3(g.x, g.y, (unsigned)S), dim3(64 * kWavesBf16), 0, ctx->stream, hi, lo,
+                           lda, B, ldb, P, ldu, pp, ncl, pstride);
+        hipLaunchKernelGGL(k_splitk_sum<float>, dim3((unsigned)((np + 255) / 256), (unsigned)Kp), dim3(256), 0,
+                           ctx->stream, (const float *)P, pstride, S, U, ldu, np, ncl);
+        return;
+    }
     if (v == 0)
         hipLaunchKernelGGL(k_gemm_xw_bf16, g, dim3(64 * kWavesBf16), 0, ctx->stream, hi, lo, lda, B, ldb, U, ldu, pp,
-                           ncl);
+                           ncl, (int64_t)0);
     else if (v == 1)
         hipLaunchKernelGGL((k_gemm_xw_bf16_lds<2, 2>), g, dim3(256), 0, ctx->stream, hi, lo, lda, B, ldb, U, ldu, pp,
                            ncl);
@@ -2056,9 +2175,12 @@ void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *act
 TileChoice &tile_choice_bf16(l0l2_ctx *ctx, int64_t Kp) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
+    ensure_split(ctx, Kp, in.ldu, sizeof(float));
     if (ctx->force_xw >= 0) {
+        // fixed shapes: 0-11 map to the three unsliced shapes, the sliced ones
+        // (12-16) to 4 slices, 15 to 8 slices
         static thread_local TileChoice forced;
-        forced.xw = std::min(ctx->force_xw, kShapesBf16 - 1);
+        forced.xw = ctx->force_xw < kShapes ? std::min(ctx->force_xw, kShapesBf16 - 1) : (ctx->force_xw == 15 ? 4 : 3);
         forced.xtu = std::min(ctx->force_xtu, kShapesBf16 - 1);
         return forced;
     }
@@ -2088,24 +2210,29 @@ TileChoice &tile_choice_bf16(l0l2_ctx *ctx, int64_t Kp) {
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             return ms / (float)reps;
         };
+        // sliced shapes: the contraction over p only, where the unsliced grid
+        // would leave compute units idle
+        auto valid = [&](int v, int which) {
+            if (Kp % kBfTN[v] != 0) return false;
+            if (v < kShapesBf16) return true;
+            return which == 0 && (in.np / kBfTM[v]) * (Kp / kBfTN[v]) < 256;
+        };
         float t0 = 0.f;
-        for (int v = 0; v < kShapesBf16; ++v)
-            if (Kp % kBfTN[v] == 0) t0 = std::max(t0, std::max(time_shape(v, 0, 1), time_shape(v, 1, 1)));
+        for (int v = 0; v < kShapesBf16Xw; ++v)
+            for (int which = 0; which < 2; ++which)
+                if (valid(v, which)) t0 = std::max(t0, time_shape(v, which, 1));
         const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
         const int rounds = t0 > 1.0f ? 2 : 4;
-        float best[kShapesBf16][2];
-        for (int v = 0; v < kShapesBf16; ++v) best[v][0] = best[v][1] = 1e30f;
+        float best[kShapesBf16Xw][2];
+        for (int v = 0; v < kShapesBf16Xw; ++v) best[v][0] = best[v][1] = 1e30f;
         for (int r = 0; r < rounds; ++r)
-            for (int v = 0; v < kShapesBf16; ++v) {
-                if (Kp % kBfTN[v] != 0) continue;
+            for (int v = 0; v < kShapesBf16Xw; ++v)
                 for (int which = 0; which < 2; ++which)
-                    best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
-            }
+                    if (valid(v, which)) best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
         float bx = 1e30f, bt = 1e30f;
-        for (int v = 0; v < kShapesBf16; ++v) {
-            if (Kp % kBfTN[v] != 0) continue;
-            if (best[v][0] < bx) { bx = best[v][0]; tc.xw = v; }
-            if (best[v][1] < bt) { bt = best[v][1]; tc.xtu = v; }
+        for (int v = 0; v < kShapesBf16Xw; ++v) {
+            if (valid(v, 0) && best[v][0] < bx) { bx = best[v][0]; tc.xw = v; }
+            if (valid(v, 1) && best[v][1] < bt) { bt = best[v][1]; tc.xtu = v; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -2144,8 +2271,10 @@ void anchor_start(l0l2_ctx *ctx, int64_t Kp, int64_t cols) {
     hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
                        Kp * ldp);
     launch_xw<double, double, double>(tc.xw, s, s64.XhR, s64.ldr, ws.Wa.as<double>(), ldp, s64.U, s64.ldu, np, cols,
-                                      pp, active_cols(ctx));
-    launch_xw<double, double, double>(tc.xw, s, s64.Xh, s64.ldc, s64.U, s64.ldu, ws.Za.as<double>(), ldp, pp, cols,
+                                      pp, active_cols(ctx), split_buf(ctx));
+    // the second product runs over n (short) into a p x nodes output: never sliced
+    const int v2 = split_of(tc.xw) > 1 ? tc.xtu : tc.xw;
+    launch_xw<double, double, double>(v2, s, s64.Xh, s64.ldc, s64.U, s64.ldu, ws.Za.as<double>(), ldp, pp, cols,
                                       np, active_cols(ctx));
     prof_end(ctx, PROF_ANCHOR);
     HIPCHK(hipGetLastError());
@@ -2162,7 +2291,7 @@ void sweep_once_anch(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
     const TileChoice &tc = tile_choice<float>(ctx, s32, Kp);
     prof_begin(ctx, PROF_GEMM_XW_F32);
     launch_xw<float, float, float>(tc.xw, s, s32.XhR, s32.ldr, s32.W, s32.ldp, s32.U, s32.ldu, np, Kp, pp,
-                                   active_cols(ctx));
+                                   active_cols(ctx), split_buf(ctx));
     prof_end(ctx, PROF_GEMM_XW_F32, active);
     prof_begin(ctx, PROF_ADMM_XTU_F32);
     launch_xtu_anch(tc.xtu, s, s32, s64, ws.Za.as<double>(), ws.Wa.as<double>(), np, pp, Kp,
@@ -2196,14 +2325,43 @@ void launch_xtu_fp8(int v, l0l2_ctx *ctx, int64_t Kp, const int *active, int sto
 #undef L0L2_XTUF8
 }
 
-// FP8 shape of the contraction over n, per live bucket, timed like tile_choice
-// (kind 3; the contraction over p has one shape).
-int tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
+// The contraction over p of the FP8 form: the 32 x 32 register tile, its range
+// in 1, 4 or 8 slices (xw shape 0, 1, 2).
+constexpr int kFp8XwSplit[3] = {1, 4, 8};
+
+void launch_xw_fp8(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, NodeCols ncl) {
     Instance &in = ctx->inst;
-    if (ctx->force_xw >= 0) return std::min(ctx->force_xtu, kShapesFp8 - 1);
+    if (v < 0 || v > 2 || Kp % 32 != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    const int S = kFp8XwSplit[v];
+    const dim3 g((unsigned)(in.np / 32), (unsigned)(Kp / 32), (unsigned)S), b(64 * kWavesBf16);
+    if (S == 1) {
+        hipLaunchKernelGGL(k_gemm_xw_fp8, g, b, 0, ctx->stream, in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), B,
+                           in.ldp, U, in.ldu, in.pp, ncl, (int64_t)0);
+        return;
+    }
+    const int64_t pstride = Kp * in.ldu;
+    SplitBuf sk = split_buf(ctx);
+    if ((size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+    float *P = static_cast<float *>(sk.ptr);
+    hipLaunchKernelGGL(k_gemm_xw_fp8, g, b, 0, ctx->stream, in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), B,
+                       in.ldp, P, in.ldu, in.pp, ncl, pstride);
+    hipLaunchKernelGGL(k_splitk_sum<float>, dim3((unsigned)((in.np + 255) / 256), (unsigned)Kp), dim3(256), 0,
+                       ctx->stream, (const float *)P, pstride, S, U, in.ldu, in.np, ncl);
+}
+
+// FP8 shapes per live bucket, timed like tile_choice (kind 3).
+TileChoice tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
+    Instance &in = ctx->inst;
+    ensure_split(ctx, Kp, in.ldu, sizeof(float));
+    if (ctx->force_xw >= 0) {
+        TileChoice f;
+        f.xw = ctx->force_xw < kShapes ? 0 : (ctx->force_xw == 15 ? 2 : 1);
+        f.xtu = std::min(ctx->force_xtu, kShapesFp8 - 1);
+        return f;
+    }
     auto key = std::make_pair(3, Kp);
     auto it = in.tiles.find(key);
-    if (it != in.tiles.end()) return it->second.xtu;
+    if (it != in.tiles.end()) return it->second;
     TileChoice tc;
     tc.xw = tc.xtu = 0;
     if (ctx->tune) {
@@ -2214,32 +2372,47 @@ int tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        auto time_shape = [&](int v, int reps) {
+        Sweep<float> s32 = sweep32(ctx);
+        auto time_shape = [&](int v, int which, int reps) {
             HIPCHK(hipEventRecord(e0, s));
-            for (int t = 0; t < reps; ++t) launch_xtu_fp8(v, ctx, Kp, inactive.as<int>(), 0, nullptr, NodeCols{nullptr});
+            for (int t = 0; t < reps; ++t) {
+                if (which == 0) launch_xw_fp8(v, ctx, s32.W, s32.U, Kp, NodeCols{nullptr});
+                else launch_xtu_fp8(v, ctx, Kp, inactive.as<int>(), 0, nullptr, NodeCols{nullptr});
+            }
             HIPCHK(hipEventRecord(e1, s));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             return ms / (float)reps;
         };
+        // xw shapes 0-2 all fit (node tile 32), the sliced ones are candidates
+        // where the unsliced grid would leave compute units idle; xtu shapes
+        // need their node tile
+        auto valid = [&](int v, int which) {
+            if (which == 1) return Kp % kF8TN[v] == 0;
+            return v == 0 || (in.np / 32) * (Kp / 32) < 256;
+        };
         float t0 = 0.f;
         for (int v = 0; v < kShapesFp8; ++v)
-            if (Kp % kF8TN[v] == 0) t0 = std::max(t0, time_shape(v, 1));
+            for (int which = 0; which < 2; ++which)
+                if (valid(v, which)) t0 = std::max(t0, time_shape(v, which, 1));
         const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
         const int rounds = t0 > 1.0f ? 2 : 4;
-        float best[kShapesFp8];
-        for (int v = 0; v < kShapesFp8; ++v) best[v] = 1e30f;
+        float best[kShapesFp8][2];
+        for (int v = 0; v < kShapesFp8; ++v) best[v][0] = best[v][1] = 1e30f;
         for (int r = 0; r < rounds; ++r)
             for (int v = 0; v < kShapesFp8; ++v)
-                if (Kp % kF8TN[v] == 0) best[v] = std::min(best[v], time_shape(v, reps));
-        for (int v = 1; v < kShapesFp8; ++v)
-            if (best[v] < best[tc.xtu]) tc.xtu = v;
+                for (int which = 0; which < 2; ++which)
+                    if (valid(v, which)) best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
+        for (int v = 1; v < kShapesFp8; ++v) {
+            if (best[v][0] < best[tc.xw][0]) tc.xw = v;
+            if (best[v][1] < best[tc.xtu][1]) tc.xtu = v;
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         HIPCHK(hipGetLastError());
     }
-    return (in.tiles[key] = tc).xtu;
+    return in.tiles[key] = tc;
 }
 
 // One anchored sweep in FP8 storage: U = Xh d with the codes (register tile
@@ -2250,13 +2423,12 @@ void sweep_once_fp8(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, boo
     hipStream_t s = ctx->stream;
     Sweep<float> s32 = sweep32(ctx);
     const NodeCols ncl = active_cols(ctx);
-    const int v = tile_choice_fp8(ctx, Kp);
+    const TileChoice tc = tile_choice_fp8(ctx, Kp);
     prof_begin(ctx, PROF_GEMM_XW_FP8);
-    hipLaunchKernelGGL(k_gemm_xw_fp8, dim3((unsigned)(in.np / 32), (unsigned)(Kp / 32)), dim3(64 * kWavesBf16), 0, s,
-                       in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), s32.W, in.ldp, s32.U, in.ldu, in.pp, ncl);
+    launch_xw_fp8(tc.xw, ctx, s32.W, s32.U, Kp, ncl);
     prof_end(ctx, PROF_GEMM_XW_FP8, active);
     prof_begin(ctx, PROF_ADMM_XTU_FP8);
-    launch_xtu_fp8(v, ctx, Kp, ws.active.as<int>(), store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, ncl);
+    launch_xtu_fp8(tc.xtu, ctx, Kp, ws.active.as<int>(), store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr, ncl);
     prof_end(ctx, PROF_ADMM_XTU_FP8, active);
     HIPCHK(hipGetLastError());
 }
@@ -2381,7 +2553,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
         if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), cols).xtu];
         else if (kind == SK_BF16 || (kind == SK_ANCH && in.prec == L0L2_BF16))
             rows = kBfTM[tile_choice_bf16(ctx, cols).xtu];
-        else if (kind == SK_ANCH && in.prec == L0L2_FP8) rows = kF8TM[tile_choice_fp8(ctx, cols)];
+        else if (kind == SK_ANCH && in.prec == L0L2_FP8) rows = kF8TM[tile_choice_fp8(ctx, cols).xtu];
         else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), cols).xtu];
         GateFin gf{in.yy, tol, Kp, in.pp / rows};
         prof_begin(ctx, PROF_CHECK);
@@ -2412,16 +2584,16 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
         issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
     } else {
         const int64_t cols = live_bucket(ctx, active, Kp);
+        // settle the tile shapes first (the autotuner synchronises, and may grow
+        // the split buffer, which drops the captured graphs)
+        const bool bf = ctx->inst.prec == L0L2_BF16, f8 = ctx->inst.prec == L0L2_FP8;
+        if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), cols);
+        if (kind == SK_F32 || (kind == SK_ANCH && !bf && !f8)) (void)tile_choice<float>(ctx, sweep32(ctx), cols);
+        if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);
+        if (kind == SK_ANCH && f8) (void)tile_choice_fp8(ctx, cols);
         GraphKey key{kind, Kp, cols, n, force ? 1 : 0, tol, switch_tol, ws.gen};
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
-            // settle the tile shapes (the autotuner synchronises) before capturing
-            const bool bf = ctx->inst.prec == L0L2_BF16, f8 = ctx->inst.prec == L0L2_FP8;
-            if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), cols);
-            if (kind == SK_F32 || (kind == SK_ANCH && !bf && !f8))
-                (void)tile_choice<float>(ctx, sweep32(ctx), cols);
-            if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);
-            if (kind == SK_ANCH && f8) (void)tile_choice_fp8(ctx, cols);
             hipGraph_t g = nullptr;
             hipGraphExec_t ex = nullptr;
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {

@@ -111,6 +111,7 @@ struct Workspace {
     int64_t cap = 0;
     DevBuf W, beta, V, B;          // Kp rows of ldp, state precision
     DevBuf U;                      // Kp rows of ldu, state precision (ADMM product)
+    DevBuf Upart;                  // partial products of the contraction over p cut into slices
     DevBuf W64, beta64, V64, B64;  // FP32 / BF16 mode: FP64 state of the anchored sweeps (Kp rows of ldp)
     DevBuf U64;                    // FP32 / BF16 mode: Kp rows of ldu64
     DevBuf Wa, Za;                 // FP32 / BF16 mode: anchor w_a and Xh^T Xh w_a (Kp rows of ldp, FP64)

@@ -39,6 +39,7 @@ size_t footprint_bytes(int64_t n, int64_t p, int prec, int K) {
     double ws = 4.0 * sb * Kp * pp + sb * Kp * np + 24.0 * Kp * np + Kp * pp + 1.0 * Kp * pp / 4.0 + 128.0 * Kp;
     if (prec != L0L2_FP64) ws += 32.0 * Kp * pp + 8.0 * Kp * np;
     ws += 8.0 * Kp * np;                                   // refinement residuals
+    ws += 8.0 * 8.0 * Kp * np;                             // partial products of the sliced contraction over p
     double bnb = 9.0 * Kp * (double)p + 2.0 * sb * pp * 16.0 * Kp;   // supports, starts, pool reserve
     return (size_t)(inst + std::max(transient, ws + bnb));
 }

@@ -83,13 +83,15 @@ def test_sweeps_fp64_match_oracle(torch_cuda, cases, name):
             assert rel(gbb[k], bb) < 1e-11, (S, k)
 
 
-@pytest.mark.parametrize("shape", list(range(12)))
+@pytest.mark.parametrize("shape", list(range(17)))
 def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
+    """Every shape of the contraction over p (12-16: LDS or register tiles with
+    the range cut into slices) and of the contraction over n."""
     inst, o, root = cases["ragged"]
     K = 100
     codes, beta0, v0 = random_nodes(inst.p, K, 11, root["beta"], root["v"])
     ctx = ctx_for(inst, "fp64")
-    ctx.set_tiles(shape, 11 - shape)
+    ctx.set_tiles(shape, 11 - shape if shape < 12 else 0)
     gb, gv, gbb = ctx.admm_sweeps(codes, beta0, v0, 7)
     gb, gbb = gb.cpu().numpy(), gbb.cpu().numpy()
     for k in range(K):
@@ -101,7 +103,7 @@ def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
         assert rel(gb[k], b) < 1e-11 and rel(gbb[k], bb) < 1e-11
 
 
-@pytest.mark.parametrize("shape", [9, 10, 11])
+@pytest.mark.parametrize("shape", [9, 10, 11, 12, 13])
 def test_lds_tiles_fp32_and_anchored_match(torch_cuda, cases, shape):
     """The LDS-staged tiles in FP32 mode (plain and anchored sweeps, with the gap
     estimate's epilogue) give the same node solves as the register tiles, to
@@ -113,7 +115,7 @@ def test_lds_tiles_fp32_and_anchored_match(torch_cuda, cases, shape):
     ref.set_tiles(1, 1)
     r0 = ref.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
     ctx = ctx_for(inst, "fp32")
-    ctx.set_tiles(shape, shape)
+    ctx.set_tiles(shape, min(shape, 11))
     r1 = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
     lb0, lb1 = r0["lb"].cpu().numpy(), r1["lb"].cpu().numpy()
     pr = r0["primal"].cpu().numpy()
@@ -142,6 +144,27 @@ def test_fp8_lds_tiles_match_the_register_tile(torch_cuda, cases, shape):
     for k in range(0, K, 16):
         ref_k = o.node_admm(codes[k], beta0[k], v0[k], tol=1e-8, max_iter=3000, check_every=10)
         assert abs(lb1[k] - ref_k["lb"]) <= 1e-7 * abs(ref_k["primal"])
+
+
+@pytest.mark.parametrize("precision,xw", [("bf16", 13), ("bf16", 15), ("fp8", 13), ("fp8", 15)])
+def test_sliced_contraction_over_p_matches_unsliced(torch_cuda, cases, precision, xw):
+    """BF16 and FP8 forms: the contraction over p cut into 4 or 8 slices (partial
+    products added in slice order) gives the same node solves as the unsliced
+    register tile, to FP32 rounding of the summation order.  (The FP64 anchors
+    take the fixed shape too; 13 tiles 128 nodes, so the batch is 128.)"""
+    inst, o, root = cases["wide"]
+    K = 128
+    codes, beta0, v0 = random_nodes(inst.p, K, 17, root["beta"], root["v"])
+    ref = ctx_for(inst, precision)
+    ref.set_tiles(0, 0)
+    r0 = ref.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
+    ctx = ctx_for(inst, precision)
+    ctx.set_tiles(xw, 0)
+    r1 = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
+    lb0, lb1 = r0["lb"].cpu().numpy(), r1["lb"].cpu().numpy()
+    pr = r0["primal"].cpu().numpy()
+    assert (r1["status"].cpu().numpy() == 0).all()
+    assert np.max(np.abs(lb0 - lb1) / np.abs(pr)) < 1e-7
 
 
 def test_fixed_shape_that_does_not_fit_the_batch_is_rejected(torch_cuda, cases):
