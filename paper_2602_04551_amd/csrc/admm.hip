@@ -16,6 +16,7 @@
 // of Sec. 4.1): r = y - X b, g = X^T r, LB = rigorous D(r); P(beta) from X beta.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <type_traits>
 
 #include "device_math.hpp"
@@ -30,7 +31,11 @@ DevParams<T> dev_params(const MethodParams &m) {
     DevParams<T> q;
     q.M = (T)m.M;
     q.rho = (T)m.rho;
-    q.inv_rho_dummy = T(0);
+    int e = 0;
+    // a normal power of two whose reciprocal is normal too
+    q.rho_pow2 = std::frexp((double)q.rho, &e) == 0.5 && std::fabs((double)q.rho) >= 4.0 * (double)std::numeric_limits<T>::min() &&
+                 std::fabs((double)q.rho) <= 0.25 / (double)std::numeric_limits<T>::min();
+    q.inv_rho = q.rho_pow2 ? (T)(1.0 / (double)q.rho) : T(0);
     q.a_plus_s = (T)m.a_plus_s;
     q.ridge = (T)m.ridge;
     q.thr_free = (T)m.thr_free;
@@ -308,17 +313,21 @@ __device__ __forceinline__ T admm_update(T Qv, const EpiIn<T> &ei, int64_t o, T 
                                          double e[5]) {
     const uint8_t code = ei.code;
     const T wv = ei.w;
-    const T bb = (wv - Qv) / q.rho;
+    const T bb = div_rho(wv - Qv, q);
     const T v = ei.v;
-    const T bt = bb + v / q.rho;
+    const T bt = bb + div_rho(v, q);
     const T be = prox_beta(bt, code, q);
     const T vn = v + q.rho * (bb - be);
     const T cj = ei.c;
     const T wn = cj + q.rho * be - vn;
-    beta[o] = be;
     V[o] = vn;
     W[o] = wn;
-    if (store_b) Bst[o] = bb;
+    // beta is read only after a block's last sweep (gap check, promotion,
+    // read-back), which is the sweep that stores it, with b
+    if (store_b) {
+        beta[o] = be;
+        Bst[o] = bb;
+    }
     if (est) {
         const double b = (double)bb, w = (double)wv, cd = (double)cj, rho = (double)q.rho, bn = (double)be;
         const double g = cd - w + rho * b;

@@ -9,13 +9,22 @@ namespace l0l2 {
 
 enum : uint8_t { CODE_FREE = 0, CODE_FIX0 = 1, CODE_FIX1 = 2 };
 
-// The scalars of MethodParams in the arithmetic type T of the sweep.
+// The scalars of MethodParams in the arithmetic type T of the sweep.  When rho
+// is a power of two, x / rho and x * (1 / rho) are the same correctly rounded
+// number (both scale x by an exact power of two), so the update multiplies by
+// inv_rho instead of dividing (rho_pow2 set).
 template <class T>
 struct DevParams {
-    T M, rho, inv_rho_dummy;
+    T M, rho, inv_rho;
     T a_plus_s, ridge, thr_free, thr_free_M;
-    int free_quad;
+    int free_quad, rho_pow2;
 };
+
+// x / rho, by the exact reciprocal when rho is a power of two.
+template <class T>
+__device__ __forceinline__ T div_rho(T x, const DevParams<T> &q) {
+    return q.rho_pow2 ? x * q.inv_rho : x / q.rho;
+}
 
 template <class T>
 __device__ __forceinline__ T clip_box(T x, T m) {

@@ -83,6 +83,34 @@ def test_sweeps_fp64_match_oracle(torch_cuda, cases, name):
             assert rel(gbb[k], bb) < 1e-11, (S, k)
 
 
+@pytest.mark.parametrize("rho", [0.7, 2.0, 0.3])
+def test_sweeps_and_node_solve_other_rho(torch_cuda, orc, rho):
+    """rho other than 1: a power of two (the update multiplies by 1/rho, which is
+    exact) and two that are not (it divides); sweeps and FP64 node solves match
+    the oracle run with the same rho, sweep counts included."""
+    inst = INSTANCES["wide"]()
+    o = orc.Oracle.from_instance(inst, rho=rho)
+    root = o.node_admm(None, tol=1e-7, max_iter=20000)
+    K = 24
+    codes, beta0, v0 = random_nodes(inst.p, K, 21, root["beta"], root["v"])
+    ctx = ctx_for(inst, "fp64", rho=rho)
+    gb, gv, gbb = ctx.admm_sweeps(codes, beta0, v0, 9)
+    gb, gv, gbb = gb.cpu().numpy(), gv.cpu().numpy(), gbb.cpu().numpy()
+    for k in range(K):
+        b = beta0[k].copy()
+        b[codes[k] == FIX0] = 0.0
+        v = v0[k].copy()
+        for _ in range(9):
+            b, v, bb = o.sweep(codes[k], b, v)
+        assert rel(gb[k], b) < 1e-11 and rel(gv[k], v) < 1e-11 and rel(gbb[k], bb) < 1e-11, k
+    res = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-7, max_iter=3000, check_every=10)
+    it, lb = res["iters"].cpu().numpy(), res["lb"].cpu().numpy()
+    for k in range(K):
+        ref = o.node_admm(codes[k], beta0[k], v0[k], tol=1e-7, max_iter=3000, check_every=10)
+        assert it[k] == ref["iters"], k
+        assert abs(lb[k] - ref["lb"]) <= 1e-10 * abs(ref["primal"]), k
+
+
 @pytest.mark.parametrize("shape", list(range(17)))
 def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
     """Every shape of the contraction over p (12-16: LDS or register tiles with
