@@ -231,19 +231,22 @@ int l0l2_server_destroy(l0l2_server *srv);
  * 6 = 64x32/8, 7 = 32x64/8, 8 = 64x32/4; LDS-staged tiles (4 waves), 9 = 64x64,
  * 10 = 128x64, 11 = 128x128; for the contraction over p only (xw_shape), the
  * range cut into slices whose partial products are then added in slice order
- * (more workgroups when n x nodes is small and p long): 12, 13 = 128x128
- * LDS-staged in 2 / 4 slices, 14, 15 = 16x16/4 in 4 / 8 slices, 16 = 32x32/4 in
- * 4 slices.  By default (both -1) each new padded batch size
+ * (more workgroups when n x nodes is small and p long): 12, 13, 17 = 128x128
+ * LDS-staged in 2 / 4 / 8 slices, 14, 15 = 16x16/4 in 4 / 8 slices, 16 = 32x32/4
+ * in 4 slices.  By default (both -1) each new padded batch size
  * is timed once with every shape whose node tile divides it, on the live batch,
  * and the fastest kept per instance; fixed shapes serve tests and tuning
  * studies (a fixed shape whose node tile does not divide the padded batch makes
  * the solve calls fail with L0L2_E_INVALID).  Results do not depend on the
  * shape beyond rounding of the summation order.  BF16 mode maps shapes 0-11 to
  * its own three (0 = 32x32 register tile, 1 = 64x64 and 2 = 128x128 LDS-staged,
- * larger values taken as 2) and the sliced shapes 12-16 of the contraction
- * over p to its 32x32 register tile in 4 slices (15: 8 slices); FP8 mode maps
- * the contraction over n the same way and its contraction over p to the 32x32
- * register tile, unsliced for 0-11, in 4 slices for 12-16 (15: 8 slices). */
+ * larger values taken as 2) and the sliced shapes of the contraction over p
+ * to its 32x32 register tile in 4 slices (14, 16) or 8 (15) and to its 128x128
+ * LDS-staged tile in 4 slices (12, 13) or 8 (17); FP8 mode maps the contraction
+ * over n the same way and its contraction over p to the 32x32 register tile,
+ * unsliced for 0-11, in 4 slices for 14 and 16, 8 for 15, and to its 128x128
+ * LDS-staged tile in 4 slices for 12 and 13, 8 for 17.  A sliced shape never
+ * uses more slices than the range has 32-wide chunks. */
 int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
 
 /* Opt-in timing of the library's kernels with HIP events recorded on the

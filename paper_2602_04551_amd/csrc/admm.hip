@@ -962,19 +962,25 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
 #undef L0L2_SSTOREB
 }
 
-// BF16 split form, contraction over p, LDS-staged tile.
+// BF16 split form, contraction over p, LDS-staged tile.  With gridDim.z = S > 1,
+// slice z takes the chunks [nch z / S, nch (z + 1) / S) of 32 k (the launcher
+// keeps S <= nch) and writes its partial product to U + z pstride.
 template <int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restrict__ Ahi,
                                                           const __bf16 *__restrict__ Alo, int64_t lda,
                                                           const float *__restrict__ B, int64_t ldb,
                                                           float *__restrict__ U, int64_t ldu, int64_t kdim,
-                                                          NodeCols ncl) {
+                                                          NodeCols ncl, int64_t pstride) {
     typedef LdsTileBf<WM, WN> L;
     __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
     if (col_slot(ncl, n0) < 0) return;
+    const int64_t nch = kdim / 32, z = blockIdx.z, S = gridDim.z;
+    const int64_t c0 = nch * z / S, c1 = nch * (z + 1) / S;
+    U += pstride * z;
     f32x4 acc[WM][WN];
-    lds_tile_bf16<WM, WN>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, ncl, smem, acc);
+    lds_tile_bf16<WM, WN>(Ahi + 32 * c0, Alo + 32 * c0, lda, B + 32 * c0, ldb, 32 * (c1 - c0), m0, n0, ncl, smem,
+                          acc);
     typedef LdsEpi<float, WM, WN> E;
     constexpr int NP = E::passes(sizeof(smem));
     static_assert(NP > 0, "epilogue staging does not fit");
@@ -1334,12 +1340,14 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_fp8(
     }
 }
 
-// LDS-staged tile of the FP8 form (4 waves, 2 x 2; TM = 32 WM, TN = 32 WN) for
-// the contraction over n.  A k chunk of 32 stages, per row, the 32 code bytes of
-// A (rows 32 bytes apart: the 8-byte fragment reads of 16 rows x 4 k offsets
-// cover 512 contiguous bytes) and the FP32 values of B (rows padded to 144
-// bytes as in the BF16 tile); lane l reads the 8 codes of row l%16 at k offset
-// 8 (l/16) and widens them, and the B fragment is split into BF16 hi / lo.
+// LDS-staged tile of the FP8 form (4 waves, 2 x 2; TM = 32 WM, TN = 32 WN).  A k
+// chunk of 32 stages, per row, the 32 code bytes of A (rows 32 bytes apart: the
+// 8-byte fragment reads of 16 rows x 4 k offsets cover 512 contiguous bytes)
+// and the FP32 values of B (rows padded to 144 bytes as in the BF16 tile); lane
+// l reads the 8 codes of row l%16 at k offset 8 (l/16) and widens them, and the
+// B fragment is split into BF16 hi / lo.  SCALE_B (the contraction over p)
+// multiplies B by the column scales s_k as it is loaded, as the register tile
+// does; the contraction over n scales its output rows instead.
 template <int WM, int WN>
 struct LdsTileF8 {
     static constexpr int TM = 32 * WM, TN = 32 * WN;
@@ -1349,8 +1357,8 @@ struct LdsTileF8 {
     static constexpr int STAGE = TM * ROWA + TN * ROWB;        // bytes per buffer
 };
 
-template <int WM, int WN>
-__device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int64_t lda,
+template <int WM, int WN, bool SCALE_B>
+__device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int64_t lda, const float *__restrict__ sc,
                                              const float *__restrict__ B, int64_t ldb, int64_t kdim, int64_t m0,
                                              int64_t n0, const NodeCols &ncl, unsigned char *smem,
                                              f32x4 (&acc)[WM][WN]) {
@@ -1366,7 +1374,7 @@ __device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int
     // idx < PA); B row idx / 8, part idx % 8
     const unsigned char *ga[L::NA];
     const unsigned char *gb[L::NB];
-    int la[L::NA], lb[L::NB];
+    int la[L::NA], lb[L::NB], pb[L::NB];
     bool ha[L::NA];
 #pragma unroll
     for (int e = 0; e < L::NA; ++e) {
@@ -1381,12 +1389,23 @@ __device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int
         gb[e] = reinterpret_cast<const unsigned char *>(B + col_row(col_slot(ncl, n0 + row), n0 + row) * ldb) +
                 16 * part;
         lb[e] = L::TM * L::ROWA + row * L::ROWB + 16 * part;
+        pb[e] = 4 * part;
     }
     float4 va[L::NA], vb[L::NB];
-    // chunk c covers 32 k: 32 code bytes, 128 bytes of FP32
+    // chunk c covers 32 k: 32 code bytes, 128 bytes of FP32 (times the 4 scales
+    // of its k when SCALE_B)
 #define L0L2_GLOADF(c)                                                                                       \
     _Pragma("unroll") for (int e = 0; e < L::NA; ++e) va[e] = *reinterpret_cast<const float4 *>(ga[e] + 32 * (c)); \
-    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) vb[e] = *reinterpret_cast<const float4 *>(gb[e] + 128 * (c));
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) {                                                      \
+        vb[e] = *reinterpret_cast<const float4 *>(gb[e] + 128 * (c));                                         \
+        if (SCALE_B) {                                                                                        \
+            const float4 s4 = *reinterpret_cast<const float4 *>(sc + 32 * (c) + pb[e]);                       \
+            vb[e].x *= s4.x;                                                                                  \
+            vb[e].y *= s4.y;                                                                                  \
+            vb[e].z *= s4.z;                                                                                  \
+            vb[e].w *= s4.w;                                                                                  \
+        }                                                                                                     \
+    }
 #define L0L2_SSTOREF(st)                                                                                     \
     _Pragma("unroll") for (int e = 0; e < L::NA; ++e) if (ha[e])                                              \
         *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + la[e]) = va[e];                                  \
@@ -1427,6 +1446,46 @@ __device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int
 #undef L0L2_SSTOREF
 }
 
+// Contraction over p in FP8 storage, LDS-staged tile: U[k][i] = sum_j q[i][j]
+// s[j] d[k][j].  With gridDim.z = S > 1, slice z takes the chunks
+// [nch z / S, nch (z + 1) / S) of 32 k (the launcher keeps S <= nch, so none is
+// empty) and writes its partial product to U + z pstride.
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm_xw_fp8_lds(const uint8_t *__restrict__ qA, int64_t lda,
+                                                         const float *__restrict__ sc, const float *__restrict__ B,
+                                                         int64_t ldb, float *__restrict__ U, int64_t ldu,
+                                                         int64_t kdim, NodeCols ncl, int64_t pstride) {
+    typedef LdsTileF8<WM, WN> L;
+    __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    if (col_slot(ncl, n0) < 0) return;
+    const int64_t nch = kdim / 32, z = blockIdx.z, S = gridDim.z;
+    const int64_t c0 = nch * z / S, c1 = nch * (z + 1) / S;
+    U += pstride * z;
+    f32x4 acc[WM][WN];
+    lds_tile_fp8<WM, WN, true>(qA + 32 * c0, lda, sc + 32 * c0, B + 32 * c0, ldb, 32 * (c1 - c0), m0, n0, ncl, smem,
+                               acc);
+    typedef LdsEpi<float, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    float *buf = reinterpret_cast<float *>(smem);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int pass = 0; pass < NP; ++pass) {
+        const int cc = pass * PN;
+        __syncthreads();
+        acc_stage<float, WM, WN>(acc, buf, cc, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = cc + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            if (slot < 0) continue;
+#pragma unroll
+            for (int h = 0; h < E::H; ++h)
+                U[(int64_t)slot * ldu + m0 + lane + 64 * h] = buf[(nl - cc) * E::LD + lane + 64 * h];
+        }
+    }
+}
+
 // Contraction over n of an anchored sweep in FP8 storage, LDS-staged tile:
 // Q = z_a + s o (q^T U), FP64 update, d = fl32(W_new - w_a), with the
 // node-major LDS epilogue of the other LDS tiles.
@@ -1442,7 +1501,7 @@ __global__ __launch_bounds__(256) void k_admm_xtu_fp8_lds(
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
     if (col_slot(ncl, n0) < 0) return;
     f32x4 acc[WM][WN];
-    lds_tile_fp8<WM, WN>(qA, lda, U, ldu, kdim, m0, n0, ncl, smem, acc);
+    lds_tile_fp8<WM, WN, false>(qA, lda, nullptr, U, ldu, kdim, m0, n0, ncl, smem, acc);
     const bool est = gpart != nullptr;
     typedef LdsEpi<float, WM, WN> E;
     constexpr int NP = E::passes(sizeof(smem));
@@ -1812,15 +1871,15 @@ template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
 // waves per workgroup.  Shapes 0-8 are register tiles whose waves split the
 // contraction range (FP64 keeps at most 8 waves on the 32 x 32 tile: LDS for
 // the cross-wave reduction); shapes 9-11 are LDS-staged tiles (4 waves, 2 x 2).
-// Shapes 12-16 serve the contraction over p only and cut its range into
-// slices: 12, 13 = the 128 x 128 LDS-staged tile in 2 or 4 slices; 14, 15 = the
-// 16 x 16 register tile (4 waves) in 4 or 8 slices; 16 = the 32 x 32 register
-// tile (4 waves) in 4 slices.
-constexpr int kShapes = 12, kShapesXw = 17;
-constexpr int kTileTM[kShapesXw] = {32, 32, 32, 16, 32, 16, 64, 32, 64, 64, 128, 128, 128, 128, 16, 16, 32};
-constexpr int kTileTN[kShapesXw] = {32, 32, 32, 32, 16, 16, 32, 64, 32, 64, 64, 128, 128, 128, 16, 16, 32};
-constexpr int kTileW[kShapesXw] = {4, 8, 16, 8, 8, 4, 8, 8, 4, 4, 4, 4, 4, 4, 4, 4, 4};
-constexpr int kSplit[kShapesXw] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 4, 8, 4};
+// Shapes 12-17 serve the contraction over p only and cut its range into
+// slices: 12, 13, 17 = the 128 x 128 LDS-staged tile in 2, 4 or 8 slices; 14, 15
+// = the 16 x 16 register tile (4 waves) in 4 or 8 slices; 16 = the 32 x 32
+// register tile (4 waves) in 4 slices.
+constexpr int kShapes = 12, kShapesXw = 18;
+constexpr int kTileTM[kShapesXw] = {32, 32, 32, 16, 32, 16, 64, 32, 64, 64, 128, 128, 128, 128, 16, 16, 32, 128};
+constexpr int kTileTN[kShapesXw] = {32, 32, 32, 32, 16, 16, 32, 64, 32, 64, 64, 128, 128, 128, 16, 16, 32, 128};
+constexpr int kTileW[kShapesXw] = {4, 8, 16, 8, 8, 4, 8, 8, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4};
+constexpr int kSplit[kShapesXw] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 4, 8, 4, 8};
 constexpr int kMaxSplit = 8;
 int split_of(int v) { return kSplit[v]; }
 
@@ -1852,7 +1911,7 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
         if ((size_t)S * pstride * sizeof(TC) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
         TC *P = static_cast<TC *>(sk.ptr);
         const dim3 gs(g.x, g.y, (unsigned)S);
-        if (v <= 13) {
+        if (v <= 13 || v == 17) {
             if (!std::is_same<TA, TC>::value || !std::is_same<TB, TC>::value)
                 fail(L0L2_E_INVALID, "LDS-staged tiles take one operand type");
             hipLaunchKernelGGL((k_gemm_xw_lds<TC, 4, 4>), gs, b, 0, s, (const TC *)A, lda, (const TC *)B, ldb, P, ldu,
@@ -2102,10 +2161,10 @@ void sweep_once(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp, bool store_b, int
 // the contraction), 1 = LDS-staged 64 x 64, 2 = LDS-staged 128 x 128.
 // 3, 4 (contraction over p only): the register tile with the range cut into 4
 // or 8 slices.
-constexpr int kShapesBf16 = 3, kShapesBf16Xw = 5;
-constexpr int kBfTM[kShapesBf16Xw] = {32, 64, 128, 32, 32};
-constexpr int kBfTN[kShapesBf16Xw] = {32, 64, 128, 32, 32};
-constexpr int kBfSplit[kShapesBf16Xw] = {1, 1, 1, 4, 8};
+constexpr int kShapesBf16 = 3, kShapesBf16Xw = 7;
+constexpr int kBfTM[kShapesBf16Xw] = {32, 64, 128, 32, 32, 128, 128};
+constexpr int kBfTN[kShapesBf16Xw] = {32, 64, 128, 32, 32, 128, 128};
+constexpr int kBfSplit[kShapesBf16Xw] = {1, 1, 1, 4, 8, 4, 8};
 
 void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, NodeCols ncl) {
     Instance &in = ctx->inst;
@@ -2115,13 +2174,18 @@ void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, 
     const __bf16 *hi = in.XhR.as<__bf16>(), *lo = in.XhRLo.as<__bf16>();
     const int64_t lda = in.ldwr, ldb = in.ldp, ldu = in.ldu;
     if (v >= kShapesBf16) {
-        const int S = kBfSplit[v];
+        // no slice may be empty: at most one per 32-wide chunk (LDS) or 64-wide pair (register)
+        const int S = (int)std::min<int64_t>(kBfSplit[v], v >= 5 ? pp / 32 : pp / 64);
         const int64_t pstride = Kp * ldu;
         SplitBuf sk = split_buf(ctx);
         if ((size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
         float *P = static_cast<float *>(sk.ptr);
-        hipLaunchKernelGGL(k_gemm_xw_bf16, dim3(g.x, g.y, (unsigned)S), dim3(64 * kWavesBf16), 0, ctx->stream, hi, lo,
-                           lda, B, ldb, P, ldu, pp, ncl, pstride);
+        if (v >= 5)
+            hipLaunchKernelGGL((k_gemm_xw_bf16_lds<4, 4>), dim3(g.x, g.y, (unsigned)S), dim3(256), 0, ctx->stream, hi,
+                               lo, lda, B, ldb, P, ldu, pp, ncl, pstride);
+        else
+            hipLaunchKernelGGL(k_gemm_xw_bf16, dim3(g.x, g.y, (unsigned)S), dim3(64 * kWavesBf16), 0, ctx->stream, hi,
+                               lo, lda, B, ldb, P, ldu, pp, ncl, pstride);
         hipLaunchKernelGGL(k_splitk_sum<float>, dim3((unsigned)((np + 255) / 256), (unsigned)Kp), dim3(256), 0,
                            ctx->stream, (const float *)P, pstride, S, U, ldu, np, ncl);
         return;
@@ -2131,10 +2195,10 @@ void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, 
                            ncl, (int64_t)0);
     else if (v == 1)
         hipLaunchKernelGGL((k_gemm_xw_bf16_lds<2, 2>), g, dim3(256), 0, ctx->stream, hi, lo, lda, B, ldb, U, ldu, pp,
-                           ncl);
+                           ncl, (int64_t)0);
     else
         hipLaunchKernelGGL((k_gemm_xw_bf16_lds<4, 4>), g, dim3(256), 0, ctx->stream, hi, lo, lda, B, ldb, U, ldu, pp,
-                           ncl);
+                           ncl, (int64_t)0);
 }
 
 // Contraction over n in the BF16 split form: FP32 update (anch = false, on the
@@ -2186,10 +2250,12 @@ TileChoice &tile_choice_bf16(l0l2_ctx *ctx, int64_t Kp) {
     Workspace &ws = ctx->ws;
     ensure_split(ctx, Kp, in.ldu, sizeof(float));
     if (ctx->force_xw >= 0) {
-        // fixed shapes: 0-11 map to the three unsliced shapes, the sliced ones
-        // (12-16) to 4 slices, 15 to 8 slices
+        // fixed shapes: 0-11 map to the three unsliced shapes; the sliced ones to
+        // the register tile in 4 slices (14, 16) or 8 (15), the 128 x 128
+        // LDS-staged tile in 4 slices (12, 13) or 8 (17)
         static thread_local TileChoice forced;
-        forced.xw = ctx->force_xw < kShapes ? std::min(ctx->force_xw, kShapesBf16 - 1) : (ctx->force_xw == 15 ? 4 : 3);
+        const int f = ctx->force_xw;
+        forced.xw = f < kShapes ? std::min(f, kShapesBf16 - 1) : f == 15 ? 4 : (f == 12 || f == 13) ? 5 : f == 17 ? 6 : 3;
         forced.xtu = std::min(ctx->force_xtu, kShapesBf16 - 1);
         return forced;
     }
@@ -2334,14 +2400,31 @@ void launch_xtu_fp8(int v, l0l2_ctx *ctx, int64_t Kp, const int *active, int sto
 #undef L0L2_XTUF8
 }
 
-// The contraction over p of the FP8 form: the 32 x 32 register tile, its range
-// in 1, 4 or 8 slices (xw shape 0, 1, 2).
-constexpr int kFp8XwSplit[3] = {1, 4, 8};
+// Contraction over p in FP8 storage: 0-2 = the 32 x 32 register tile (8 waves)
+// unsliced or in 4 / 8 slices; 3, 4 = the 128 x 128 LDS-staged tile in 4 / 8
+// slices.
+constexpr int kShapesFp8Xw = 5;
+constexpr int kFp8XwSplit[kShapesFp8Xw] = {1, 4, 8, 4, 8};
+constexpr int kF8XwT[kShapesFp8Xw] = {32, 32, 32, 128, 128};
 
 void launch_xw_fp8(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, NodeCols ncl) {
     Instance &in = ctx->inst;
-    if (v < 0 || v > 2 || Kp % 32 != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
-    const int S = kFp8XwSplit[v];
+    if (v < 0 || v >= kShapesFp8Xw || Kp % kF8XwT[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    if (v >= 3) {
+        // no slice may be empty: at most one per 32-wide chunk
+        const int S = (int)std::min<int64_t>(kFp8XwSplit[v], in.pp / 32);
+        const int64_t pstride = Kp * in.ldu;
+        SplitBuf sk = split_buf(ctx);
+        if ((size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+        float *P = static_cast<float *>(sk.ptr);
+        hipLaunchKernelGGL((k_gemm_xw_fp8_lds<4, 4>), dim3((unsigned)(in.np / 128), (unsigned)(Kp / 128), (unsigned)S),
+                           dim3(256), 0, ctx->stream, in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), B, in.ldp, P,
+                           in.ldu, in.pp, ncl, pstride);
+        hipLaunchKernelGGL(k_splitk_sum<float>, dim3((unsigned)((in.np + 255) / 256), (unsigned)Kp), dim3(256), 0,
+                           ctx->stream, (const float *)P, pstride, S, U, in.ldu, in.np, ncl);
+        return;
+    }
+    const int S = (int)std::min<int64_t>(kFp8XwSplit[v], in.pp / 64);
     const dim3 g((unsigned)(in.np / 32), (unsigned)(Kp / 32), (unsigned)S), b(64 * kWavesBf16);
     if (S == 1) {
         hipLaunchKernelGGL(k_gemm_xw_fp8, g, b, 0, ctx->stream, in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), B,
@@ -2363,8 +2446,12 @@ TileChoice tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
     Instance &in = ctx->inst;
     ensure_split(ctx, Kp, in.ldu, sizeof(float));
     if (ctx->force_xw >= 0) {
+        // fixed shapes: 0-11 -> the unsliced register tile; the sliced ones to the
+        // register tile in 4 slices (14, 16) or 8 (15), the 128 x 128 LDS-staged
+        // tile in 4 slices (12, 13) or 8 (17)
         TileChoice f;
-        f.xw = ctx->force_xw < kShapes ? 0 : (ctx->force_xw == 15 ? 2 : 1);
+        const int x = ctx->force_xw;
+        f.xw = x < kShapes ? 0 : x == 15 ? 2 : (x == 12 || x == 13) ? 3 : x == 17 ? 4 : 1;
         f.xtu = std::min(ctx->force_xtu, kShapesFp8 - 1);
         return f;
     }
@@ -2394,28 +2481,30 @@ TileChoice tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             return ms / (float)reps;
         };
-        // xw shapes 0-2 all fit (node tile 32), the sliced ones are candidates
-        // where the unsliced grid would leave compute units idle; xtu shapes
-        // need their node tile
+        // xw shape 0 always fits (node tile 32); a sliced one is a candidate
+        // where its tile unsliced would leave compute units idle (fewer
+        // workgroups than the 256 CUs); xtu shapes need their node tile
         auto valid = [&](int v, int which) {
-            if (which == 1) return Kp % kF8TN[v] == 0;
-            return v == 0 || (in.np / 32) * (Kp / 32) < 256;
+            if (which == 1) return v < kShapesFp8 && Kp % kF8TN[v] == 0;
+            if (v == 0) return true;
+            return Kp % kF8XwT[v] == 0 && (in.np / kF8XwT[v]) * (Kp / kF8XwT[v]) < 256;
         };
+        constexpr int NV = kShapesFp8Xw > kShapesFp8 ? kShapesFp8Xw : kShapesFp8;
         float t0 = 0.f;
-        for (int v = 0; v < kShapesFp8; ++v)
+        for (int v = 0; v < NV; ++v)
             for (int which = 0; which < 2; ++which)
                 if (valid(v, which)) t0 = std::max(t0, time_shape(v, which, 1));
         const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
         const int rounds = t0 > 1.0f ? 2 : 4;
-        float best[kShapesFp8][2];
-        for (int v = 0; v < kShapesFp8; ++v) best[v][0] = best[v][1] = 1e30f;
+        float best[NV][2];
+        for (int v = 0; v < NV; ++v) best[v][0] = best[v][1] = 1e30f;
         for (int r = 0; r < rounds; ++r)
-            for (int v = 0; v < kShapesFp8; ++v)
+            for (int v = 0; v < NV; ++v)
                 for (int which = 0; which < 2; ++which)
                     if (valid(v, which)) best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
-        for (int v = 1; v < kShapesFp8; ++v) {
-            if (best[v][0] < best[tc.xw][0]) tc.xw = v;
-            if (best[v][1] < best[tc.xtu][1]) tc.xtu = v;
+        for (int v = 1; v < NV; ++v) {
+            if (valid(v, 0) && best[v][0] < best[tc.xw][0]) tc.xw = v;
+            if (valid(v, 1) && best[v][1] < best[tc.xtu][1]) tc.xtu = v;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);

@@ -283,8 +283,8 @@ int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *ou
 int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape) {
     return guarded(ctx, [&] {
         bool auto_ = xw_shape < 0 && xtu_shape < 0;
-        if (!auto_ && (xw_shape < 0 || xw_shape > 16 || xtu_shape < 0 || xtu_shape > 11))
-            l0l2::fail(L0L2_E_INVALID, "tile shapes are 0..16 for xw, 0..11 for xtu (or both -1)");
+        if (!auto_ && (xw_shape < 0 || xw_shape > 17 || xtu_shape < 0 || xtu_shape > 11))
+            l0l2::fail(L0L2_E_INVALID, "tile shapes are 0..17 for xw, 0..11 for xtu (or both -1)");
         // captured blocks hold the shapes they were captured with
         if (ctx->force_xw != (auto_ ? -1 : xw_shape) || ctx->force_xtu != (auto_ ? -1 : xtu_shape)) {
             HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -111,9 +111,9 @@ def test_sweeps_and_node_solve_other_rho(torch_cuda, orc, rho):
         assert abs(lb[k] - ref["lb"]) <= 1e-10 * abs(ref["primal"]), k
 
 
-@pytest.mark.parametrize("shape", list(range(17)))
+@pytest.mark.parametrize("shape", list(range(18)))
 def test_every_tile_shape_matches_oracle(torch_cuda, cases, shape):
-    """Every shape of the contraction over p (12-16: LDS or register tiles with
+    """Every shape of the contraction over p (12-17: LDS or register tiles with
     the range cut into slices) and of the contraction over n."""
     inst, o, root = cases["ragged"]
     K = 100
@@ -174,13 +174,24 @@ def test_fp8_lds_tiles_match_the_register_tile(torch_cuda, cases, shape):
         assert abs(lb1[k] - ref_k["lb"]) <= 1e-7 * abs(ref_k["primal"])
 
 
-@pytest.mark.parametrize("precision,xw", [("bf16", 13), ("bf16", 15), ("fp8", 13), ("fp8", 15)])
-def test_sliced_contraction_over_p_matches_unsliced(torch_cuda, cases, precision, xw):
-    """BF16 and FP8 forms: the contraction over p cut into 4 or 8 slices (partial
-    products added in slice order) gives the same node solves as the unsliced
-    register tile, to FP32 rounding of the summation order.  (The FP64 anchors
-    take the fixed shape too; 13 tiles 128 nodes, so the batch is 128.)"""
-    inst, o, root = cases["wide"]
+SLICED = [("bf16", 13), ("bf16", 15), ("bf16", 17), ("fp8", 13), ("fp8", 15), ("fp8", 17), ("fp32", 13),
+          ("fp32", 17)]
+
+
+@pytest.mark.parametrize("shape_name", ["wide", "long"])
+@pytest.mark.parametrize("precision,xw", SLICED)
+def test_sliced_contraction_over_p_matches_unsliced(torch_cuda, cases, orc, precision, xw, shape_name):
+    """The contraction over p cut into 4 or 8 slices (partial products added in
+    slice order; register or 128 x 128 LDS-staged tiles) gives the same node
+    solves as the unsliced register tile, to FP32 rounding of the summation
+    order.  (The FP64 anchors take the fixed shape too; the LDS tiles take 128
+    nodes, so the batch is 128.)  "long" has p = 300: its padded range of 384 is
+    12 chunks of 32, so 8 slices are uneven (1 or 2 chunks each)."""
+    if shape_name == "wide":
+        inst, o, root = cases["wide"]
+    else:
+        inst = datagen.make_instance(60, 300, rho=0.3, k=4, seed=9, lambda0=0.01, lambda2=0.01)
+        root = orc.Oracle.from_instance(inst).node_admm(None, tol=1e-7, max_iter=20000)
     K = 128
     codes, beta0, v0 = random_nodes(inst.p, K, 17, root["beta"], root["v"])
     ref = ctx_for(inst, precision)
