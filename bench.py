@@ -224,6 +224,28 @@ def run_path(path, steps, warmup):
     return dt, its, prof
 
 
+# bytes per element of the stored folded operand: FP8 codes, BF16 hi + lo, FP32, FP64
+X_BYTES = {"fp8": 1, "bf16": 4, "fp32": 4, "fp64": 8}
+
+
+def sweep_bytes_roofline(prof, n, p, prec):
+    """HBM view of the sweeps: algorithmic bytes of a sweep = the stored operand
+    streamed once per contraction (2 n p b_X) plus the node state read and
+    written once per active node (beta and V in FP32, 16 p) and its codes
+    (p / 4 at two bits), over the summed durations of both contractions."""
+    fam = {"fp8": "fp8", "bf16": "bf16", "fp32": "f32", "fp64": "f64"}[prec]
+    xw, xtu = prof.get("gemm_xw." + fam, (0, 0.0, 0)), prof.get("admm_xtu." + fam, (0, 0.0, 0))
+    sweeps, units = xw[0], xw[2]
+    ms = xw[1] + xtu[1]
+    if sweeps == 0 or ms <= 0:
+        return None
+    nbytes = sweeps * 2.0 * n * p * X_BYTES[prec] + units * (16.0 * p + p / 4.0)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "sweeps": sweeps,
+            "node_iterations": units, "kernels": ["gemm_xw." + fam, "admm_xtu." + fam]}
+
+
 def node_batch_runs(inst, Ks, precs, workload, label):
     """Node-batch throughput on one instance: each node keeps f ~ U{50..p} free coordinates,
     |F1| ~ U{0..20}, the rest fixed to zero, warm-started from the root; one batch per K and
@@ -264,11 +286,13 @@ def node_batch_runs(inst, Ks, precs, workload, label):
             prof = {k: ctx.profile_query(k) for k in ctx.KERNELS}
             ctx.profile_enable(False)
             roof, kernels = roofline(prof, n, p)
+            roof_hbm = sweep_bytes_roofline(prof, n, p, prec)
             it = r["iters"].cpu().numpy()
             out["runs"][f"{prec}_K{K}"] = {"value": round(K / dt, 2), "seconds": round(dt, 4),
                                            "iters_mean": float(it.mean()), "iters_max": int(it.max()),
                                            "converged": int((r["status"] == 0).sum().item()),
-                                           "roofline": roof, "kernels": kernels, "set_data_s": round(sd, 3)}
+                                           "roofline": roof, "roofline_hbm": roof_hbm, "kernels": kernels,
+                                           "set_data_s": round(sd, 3)}
             print(json.dumps({f"{prec}_K{K}": out["runs"][f"{prec}_K{K}"]["value"]}), file=sys.stderr, flush=True)
         ctx.close()
     print(json.dumps(out), flush=True)

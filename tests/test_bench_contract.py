@@ -47,3 +47,18 @@ def test_counter_traffic_is_dropped_when_the_kernel_sources_change(tmp_path, mon
     (prof_dir / "c2_hbm_traffic.json").write_text(json.dumps(
         {"source_digest": digest, "per_launch_bytes": {"admm_xtu.f32": 123}}))
     assert bench.measured_traffic("admm_xtu.f32") == 123
+
+
+def test_sweep_bytes_roofline_counts_operand_and_state_bytes():
+    """HBM view of the node-batch sweeps: per sweep the stored operand twice
+    (2 n p b_X, b_X = 1 for FP8 codes) plus 16 p + p / 4 bytes per active node,
+    over the summed time of both contractions."""
+    import bench
+    n, p = 1000, 50000
+    prof = {"gemm_xw.fp8": (100, 40.0, 25600), "admm_xtu.fp8": (100, 60.0, 25600)}
+    r = bench.sweep_bytes_roofline(prof, n, p, "fp8")
+    nbytes = 100 * 2.0 * n * p * 1 + 25600 * (16.0 * p + p / 4.0)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["achieved"] == pytest.approx(nbytes / 0.1 / 1e9, rel=1e-3)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
+    assert bench.sweep_bytes_roofline({}, n, p, "fp32") is None
