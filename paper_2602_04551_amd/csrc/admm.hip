@@ -1883,10 +1883,14 @@ constexpr int kSplit[kShapesXw] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 4, 
 constexpr int kMaxSplit = 8;
 int split_of(int v) { return kSplit[v]; }
 
-// Partial-product buffer of the sliced shapes.
+// Partial-product buffer of the sliced shapes.  A slice writes node slot k's
+// partial row at k ldu, and the slots of a live bucket's columns range over the
+// whole padded batch (not only the bucket's width), so each slice spans `rows`
+// node rows: the workspace's node capacity.
 struct SplitBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    int64_t rows = 0;
 };
 
 // A shape fits a padded batch when its node tile divides it (rows are padded to
@@ -1907,8 +1911,8 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
                        ncl, (int64_t)0)
     if (v >= kShapes) {
         const int S = split_of(v);
-        const int64_t pstride = Kp * ldu;
-        if ((size_t)S * pstride * sizeof(TC) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+        const int64_t pstride = sk.rows * ldu;
+        if (sk.rows < Kp || (size_t)S * pstride * sizeof(TC) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
         TC *P = static_cast<TC *>(sk.ptr);
         const dim3 gs(g.x, g.y, (unsigned)S);
         if (v <= 13 || v == 17) {
@@ -2028,19 +2032,20 @@ void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<
 }
 
 // The partial-product buffer of the sliced shapes, sized for kMaxSplit slices of
-// a Kp-node product with rows of ld elements of elem bytes.  It grows only
-// before a capture (the tile choice runs first); a move drops the captured
-// graphs, which hold its address.
+// the workspace's node capacity (every slot a live column may name; at least Kp)
+// with rows of ld elements of elem bytes.  It grows only before a capture (the
+// tile choice runs first); a move drops the captured graphs, which hold its
+// address.
 void ensure_split(l0l2_ctx *ctx, int64_t Kp, int64_t ld, size_t elem) {
     Workspace &ws = ctx->ws;
-    const size_t need = (size_t)kMaxSplit * Kp * ld * elem;
+    const size_t need = (size_t)kMaxSplit * std::max(Kp, ws.cap) * ld * elem;
     if (need <= ws.Upart.bytes) return;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     ws.Upart.ensure(need);
     drop_graphs(ctx);
     ++ws.gen;
 }
-SplitBuf split_buf(l0l2_ctx *ctx) { return SplitBuf{ctx->ws.Upart.ptr, ctx->ws.Upart.bytes}; }
+SplitBuf split_buf(l0l2_ctx *ctx) { return SplitBuf{ctx->ws.Upart.ptr, ctx->ws.Upart.bytes, ctx->ws.cap}; }
 
 // Tile shapes chosen for (arithmetic type, padded batch): each shape that fits
 // is timed on the live batch (every node masked inactive, so the epilogue
@@ -2176,9 +2181,10 @@ void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, 
     if (v >= kShapesBf16) {
         // no slice may be empty: at most one per 32-wide chunk (LDS) or 64-wide pair (register)
         const int S = (int)std::min<int64_t>(kBfSplit[v], v >= 5 ? pp / 32 : pp / 64);
-        const int64_t pstride = Kp * ldu;
         SplitBuf sk = split_buf(ctx);
-        if ((size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+        const int64_t pstride = sk.rows * ldu;
+        if (sk.rows < Kp || (size_t)S * pstride * sizeof(float) > sk.bytes)
+            fail(L0L2_E_INVALID, "split buffer too small");
         float *P = static_cast<float *>(sk.ptr);
         if (v >= 5)
             hipLaunchKernelGGL((k_gemm_xw_bf16_lds<4, 4>), dim3(g.x, g.y, (unsigned)S), dim3(256), 0, ctx->stream, hi,
@@ -2413,9 +2419,10 @@ void launch_xw_fp8(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, N
     if (v >= 3) {
         // no slice may be empty: at most one per 32-wide chunk
         const int S = (int)std::min<int64_t>(kFp8XwSplit[v], in.pp / 32);
-        const int64_t pstride = Kp * in.ldu;
         SplitBuf sk = split_buf(ctx);
-        if ((size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+        const int64_t pstride = sk.rows * in.ldu;
+        if (sk.rows < Kp || (size_t)S * pstride * sizeof(float) > sk.bytes)
+            fail(L0L2_E_INVALID, "split buffer too small");
         float *P = static_cast<float *>(sk.ptr);
         hipLaunchKernelGGL((k_gemm_xw_fp8_lds<4, 4>), dim3((unsigned)(in.np / 128), (unsigned)(Kp / 128), (unsigned)S),
                            dim3(256), 0, ctx->stream, in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), B, in.ldp, P,
@@ -2431,9 +2438,9 @@ void launch_xw_fp8(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, N
                            in.ldp, U, in.ldu, in.pp, ncl, (int64_t)0);
         return;
     }
-    const int64_t pstride = Kp * in.ldu;
     SplitBuf sk = split_buf(ctx);
-    if ((size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
+    const int64_t pstride = sk.rows * in.ldu;
+    if (sk.rows < Kp || (size_t)S * pstride * sizeof(float) > sk.bytes) fail(L0L2_E_INVALID, "split buffer too small");
     float *P = static_cast<float *>(sk.ptr);
     hipLaunchKernelGGL(k_gemm_xw_fp8, g, b, 0, ctx->stream, in.qR.as<uint8_t>(), in.ldqr, in.qs.as<float>(), B,
                        in.ldp, P, in.ldu, in.pp, ncl, pstride);

@@ -206,6 +206,39 @@ def test_sliced_contraction_over_p_matches_unsliced(torch_cuda, cases, orc, prec
     assert np.max(np.abs(lb0 - lb1) / np.abs(pr)) < 1e-7
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp8"])
+def test_live_bucket_narrower_than_the_batch_with_sliced_tiles(torch_cuda, precision):
+    """Few rows and a long p: the tuner takes sliced contractions over p.  Once
+    fewer than half of a 64-node batch is live, the launches cover a 32-column
+    bucket whose columns name slots up to 63; each slice's partial products are
+    kept per slot, so the node results equal those of a fixed unsliced shape
+    (which always covers the whole batch)."""
+    inst = datagen.make_instance(200, 4000, rho=0.3, k=5, seed=5, lambda0=0.01, lambda2=0.01)
+    K = 64
+    zero = np.zeros(inst.p)
+    codes, beta0, v0 = random_nodes(inst.p, K, 31, zero, zero, nfix=(1, 40))
+    ref = ctx_for(inst, precision)
+    ref.set_tiles(0, 0)
+    r0 = ref.solve_node_batch(codes, beta0, v0, tol_node=1e-6, max_iter=3000, check_every=10)
+    ctx = ctx_for(inst, precision)
+    r1 = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-6, max_iter=3000, check_every=10)
+    it0, it1 = r0["iters"].cpu().numpy(), r1["iters"].cpu().numpy()
+    st0, st1 = r0["status"].cpu().numpy(), r1["status"].cpu().numpy()
+    lb0, lb1 = r0["lb"].cpu().numpy(), r1["lb"].cpu().numpy()
+    pr = r0["primal"].cpu().numpy()
+    conv = st0 == 0
+    assert conv.sum() >= 48
+    # the batch thins out: the last half of the nodes run on after the first half converged
+    assert np.sort(it0)[31] < it0.max()
+    if precision == "fp64":
+        assert (st0 == st1).all() and (it0 == it1).all()
+        assert np.max(np.abs(lb0 - lb1) / np.abs(pr)) < 1e-10
+    else:
+        both = conv & (st1 == 0)
+        assert both.sum() >= conv.sum() - 2
+        assert np.max(np.abs(lb0 - lb1)[both] / np.abs(pr[both])) < 1e-6
+
+
 def test_fixed_shape_that_does_not_fit_the_batch_is_rejected(torch_cuda, cases):
     """Shape 7 tiles 64 nodes; a batch padded to 32 nodes cannot use it."""
     from paper_2602_04551_amd.binding import L0L2Error
