@@ -795,6 +795,16 @@ __device__ __forceinline__ void split8(const float w[8], bf16x8 &hi, bf16x8 &lo)
     }
 }
 
+// The same split of four values (a staged 16-byte vector).
+__device__ __forceinline__ void split4(const float4 &w, bf16x4 &hi, bf16x4 &lo) {
+    const float x[4] = {w.x, w.y, w.z, w.w};
+    for (int t = 0; t < 4; ++t) {
+        __bf16 h = (__bf16)x[t];
+        hi[t] = h;
+        lo[t] = (__bf16)(x[t] - (float)h);
+    }
+}
+
 __device__ __forceinline__ void load8f(const float *p, float out[8]) {
     float4 a = *reinterpret_cast<const float4 *>(p);
     float4 b = *reinterpret_cast<const float4 *>(p + 4);
@@ -870,10 +880,9 @@ __device__ __forceinline__ void nt_tile_bf16(const __bf16 *__restrict__ Ahi, con
 }
 
 // LDS-staged tile of the BF16 split form (4 waves, 2 x 2; TM = 32 WM, TN = 32 WN).
-// A k chunk of 32 stages, per row, the BF16 hi and lo terms of A (2 x 64 B) or the
-// FP32 values of B (128 B), each row padded to 144 B; lane l reads 8
-// consecutive k of row l%16 (one 16-byte read per BF16 term, two for FP32) and
-// the B fragment is split into BF16 hi / lo in registers.
+// A k chunk of 32 stages, per row, the BF16 hi and lo terms (2 x 64 B) of A and
+// of B (whose FP32 values are split as they are staged), each row padded to
+// 144 B; lane l reads 8 consecutive k of row l%16, one 16-byte read per term.
 template <int WM, int WN>
 struct LdsTileBf {
     static constexpr int TM = 32 * WM, TN = 32 * WN;
@@ -896,7 +905,10 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
 #pragma unroll
         for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
     // staged vector e of this thread: row idx / 8, part idx % 8 (A: parts 0-3 hi,
-    // 4-7 lo; B: parts 0-7 of the FP32 row)
+    // 4-7 lo; B: parts 0-7 of the FP32 row, each 4 values split into BF16 hi and
+    // lo as they are staged, so a B row in LDS has the layout of an A row: 32 hi
+    // terms, then 32 lo terms, and every element is split once per workgroup
+    // rather than once per wave that reads it)
     const unsigned char *ga[L::NA];
     const unsigned char *gb[L::NB];
     int la[L::NA], lb[L::NB];
@@ -912,7 +924,7 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
         const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
         gb[e] = reinterpret_cast<const unsigned char *>(B + col_row(col_slot(ncl, n0 + row), n0 + row) * ldb) +
                 16 * part;
-        lb[e] = (L::TM + row) * L::ROWB + 16 * part;
+        lb[e] = (L::TM + row) * L::ROWB + 8 * part;
     }
     float4 va[L::NA], vb[L::NB];
     // chunk c covers 32 k: 64 bytes of each BF16 term, 128 bytes of FP32
@@ -922,8 +934,12 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
 #define L0L2_SSTOREB(st)                                                                                    \
     _Pragma("unroll") for (int e = 0; e < L::NA; ++e)                                                       \
         *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + la[e]) = va[e];                                 \
-    _Pragma("unroll") for (int e = 0; e < L::NB; ++e)                                                       \
-        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + lb[e]) = vb[e];
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) {                                                     \
+        bf16x4 h4, l4;                                                                                      \
+        split4(vb[e], h4, l4);                                                                              \
+        *reinterpret_cast<bf16x4 *>(smem + (st) * L::STAGE + lb[e]) = h4;                                    \
+        *reinterpret_cast<bf16x4 *>(smem + (st) * L::STAGE + lb[e] + 64) = l4;                               \
+    }
     const int64_t nch = kdim / 32;
     L0L2_GLOADB(0)
     L0L2_SSTOREB(0)
@@ -942,10 +958,9 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
         }
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
-            const float *row = reinterpret_cast<const float *>(sa + (L::TM + wn * 16 * WN + 16 * j + r) * L::ROWB);
-            float bv[8];
-            load8f(row + 8 * q, bv);
-            split8(bv, bh[j], bl[j]);
+            const unsigned char *row = sa + (L::TM + wn * 16 * WN + 16 * j + r) * L::ROWB;
+            bh[j] = *reinterpret_cast<const bf16x8 *>(row + 16 * q);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);
         }
 #pragma unroll
         for (int i = 0; i < WM; ++i)

@@ -152,6 +152,30 @@ def test_lds_tiles_fp32_and_anchored_match(torch_cuda, cases, shape):
 
 
 @pytest.mark.parametrize("shape", [1, 2])
+def test_bf16_lds_tiles_match_the_register_tile(torch_cuda, cases, shape):
+    """BF16 split form: the LDS-staged tiles (64 x 64, 128 x 128; the FP32 node
+    operand split into hi / lo as it is staged) for both contractions give the
+    same node solves as the register tiles, to FP32 rounding of the summation
+    order, and agree with the oracle's bounds."""
+    inst, o, root = cases["wide"]
+    K = 128
+    codes, beta0, v0 = random_nodes(inst.p, K, 14, root["beta"], root["v"])
+    ref = ctx_for(inst, "bf16")
+    ref.set_tiles(0, 0)
+    r0 = ref.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
+    ctx = ctx_for(inst, "bf16")
+    ctx.set_tiles(shape, shape)
+    r1 = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=3000, check_every=10)
+    lb0, lb1 = r0["lb"].cpu().numpy(), r1["lb"].cpu().numpy()
+    pr = r0["primal"].cpu().numpy()
+    assert (r1["status"].cpu().numpy() == 0).all()
+    assert np.max(np.abs(lb0 - lb1) / np.abs(pr)) < 1e-7
+    for k in range(0, K, 16):
+        ref_k = o.node_admm(codes[k], beta0[k], v0[k], tol=1e-8, max_iter=3000, check_every=10)
+        assert abs(lb1[k] - ref_k["lb"]) <= 1e-7 * abs(ref_k["primal"])
+
+
+@pytest.mark.parametrize("shape", [1, 2])
 def test_fp8_lds_tiles_match_the_register_tile(torch_cuda, cases, shape):
     """FP8 storage: the LDS-staged contraction over n (64 x 64, 128 x 128) gives
     the same anchored node solves as the register tile, to FP32 rounding of the
