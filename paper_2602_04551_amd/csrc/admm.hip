@@ -1358,10 +1358,11 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_fp8(
 // LDS-staged tile of the FP8 form (4 waves, 2 x 2; TM = 32 WM, TN = 32 WN).  A k
 // chunk of 32 stages, per row, the 32 code bytes of A (rows 32 bytes apart: the
 // 8-byte fragment reads of 16 rows x 4 k offsets cover 512 contiguous bytes)
-// and the FP32 values of B (rows padded to 144 bytes as in the BF16 tile); lane
-// l reads the 8 codes of row l%16 at k offset 8 (l/16) and widens them, and the
-// B fragment is split into BF16 hi / lo.  SCALE_B (the contraction over p)
-// multiplies B by the column scales s_k as it is loaded, as the register tile
+// and the BF16 hi and lo terms of B (its FP32 values split as they are staged;
+// rows of 2 x 64 bytes padded to 144 as in the BF16 tile); lane l reads the 8
+// codes of row l%16 at k offset 8 (l/16) and widens them, and the matching hi
+// and lo terms of B.  SCALE_B (the contraction over p) multiplies B by the
+// column scales s_k as it is loaded, before the split, as the register tile
 // does; the contraction over n scales its output rows instead.
 template <int WM, int WN>
 struct LdsTileF8 {
@@ -1403,7 +1404,7 @@ __device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int
         const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
         gb[e] = reinterpret_cast<const unsigned char *>(B + col_row(col_slot(ncl, n0 + row), n0 + row) * ldb) +
                 16 * part;
-        lb[e] = L::TM * L::ROWA + row * L::ROWB + 16 * part;
+        lb[e] = L::TM * L::ROWA + row * L::ROWB + 8 * part;
         pb[e] = 4 * part;
     }
     float4 va[L::NA], vb[L::NB];
@@ -1424,8 +1425,12 @@ __device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int
 #define L0L2_SSTOREF(st)                                                                                     \
     _Pragma("unroll") for (int e = 0; e < L::NA; ++e) if (ha[e])                                              \
         *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + la[e]) = va[e];                                  \
-    _Pragma("unroll") for (int e = 0; e < L::NB; ++e)                                                        \
-        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + lb[e]) = vb[e];
+    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) {                                                      \
+        bf16x4 h4, l4;                                                                                       \
+        split4(vb[e], h4, l4);                                                                               \
+        *reinterpret_cast<bf16x4 *>(smem + (st) * L::STAGE + lb[e]) = h4;                                     \
+        *reinterpret_cast<bf16x4 *>(smem + (st) * L::STAGE + lb[e] + 64) = l4;                                \
+    }
     const int64_t nch = kdim / 32;
     L0L2_GLOADF(0)
     L0L2_SSTOREF(0)
@@ -1441,11 +1446,9 @@ __device__ __forceinline__ void lds_tile_fp8(const uint8_t *__restrict__ qA, int
             ah[i] = fp8x8_to_bf16(*reinterpret_cast<const uint2 *>(sa + (wm * 16 * WM + 16 * i + r) * L::ROWA + 8 * q));
 #pragma unroll
         for (int j = 0; j < WN; ++j) {
-            const float *row =
-                reinterpret_cast<const float *>(sa + L::TM * L::ROWA + (wn * 16 * WN + 16 * j + r) * L::ROWB);
-            float bv[8];
-            load8f(row + 8 * q, bv);
-            split8(bv, bh[j], bl[j]);
+            const unsigned char *row = sa + L::TM * L::ROWA + (wn * 16 * WN + 16 * j + r) * L::ROWB;
+            bh[j] = *reinterpret_cast<const bf16x8 *>(row + 16 * q);
+            bl[j] = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);
         }
 #pragma unroll
         for (int i = 0; i < WM; ++i)
