@@ -2096,14 +2096,21 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         // time `reps` back-to-back launches of shape v (which = 0: contraction
-        // over p, 1: contraction over n with its masked epilogue)
+        // over p, 1: contraction over n with its masked epilogue, 2: the plain
+        // product over n that completes an anchor, into the anchor buffer z_a,
+        // which every anchored block recomputes before it reads it)
+        const bool anchors = sizeof(T) == 8 && in.prec != L0L2_FP64;
         auto time_shape = [&](int v, int which, int reps) {
             HIPCHK(hipEventRecord(e0, s));
             for (int t = 0; t < reps; ++t) {
                 if (which == 0)
                     launch_xw<T, T, T>(v, s, sw.XhR, sw.ldr, sw.W, sw.ldp, sw.U, sw.ldu, np, Kp, pp, NodeCols{nullptr},
                                        split_buf(ctx));
-                else launch_xtu<T>(v, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), inactive.as<int>(), q, 0);
+                else if (which == 1)
+                    launch_xtu<T>(v, s, sw, np, pp, Kp, ws.codes.as<uint8_t>(), inactive.as<int>(), q, 0);
+                else
+                    launch_xw<T, T, T>(v, s, sw.Xh, sw.ldc, sw.U, sw.ldu, reinterpret_cast<T *>(ws.Za.ptr), sw.ldp, pp,
+                                       Kp, np, NodeCols{nullptr});
             }
             HIPCHK(hipEventRecord(e1, s));
             HIPCHK(hipEventSynchronize(e1));
@@ -2118,25 +2125,27 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         // (fewer workgroups than the 256 compute units)
         auto valid = [&](int v, int which) {
             if (!shape_fits(v, Kp)) return false;
+            if (which == 2) return anchors && v < kShapes;
             if (v < kShapes) return true;
             return which == 0 && (np / kTileTM[v]) * (Kp / kTileTN[v]) < 256;
         };
         float t0 = 0.f;
         for (int v = 0; v < kShapesXw; ++v)
-            for (int which = 0; which < 2; ++which)
+            for (int which = 0; which < 3; ++which)
                 if (valid(v, which)) t0 = std::max(t0, time_shape(v, which, 1));
         const int reps = std::max(1, std::min(8, (int)(0.2f / std::max(t0, 1e-4f))));
         const int rounds = t0 > 1.0f ? 2 : 4;
-        float best[kShapesXw][2];
-        for (int v = 0; v < kShapesXw; ++v) best[v][0] = best[v][1] = 1e30f;
+        float best[kShapesXw][3];
+        for (int v = 0; v < kShapesXw; ++v) best[v][0] = best[v][1] = best[v][2] = 1e30f;
         for (int r = 0; r < rounds; ++r)
             for (int v = 0; v < kShapesXw; ++v)
-                for (int which = 0; which < 2; ++which)
+                for (int which = 0; which < 3; ++which)
                     if (valid(v, which)) best[v][which] = std::min(best[v][which], time_shape(v, which, reps));
-        float best_xw = 1e30f, best_xtu = 1e30f;
+        float best_xw = 1e30f, best_xtu = 1e30f, best_z2 = 1e30f;
         for (int v = 0; v < kShapesXw; ++v) {
             if (valid(v, 0) && best[v][0] < best_xw) { best_xw = best[v][0]; tc.xw = v; }
             if (valid(v, 1) && best[v][1] < best_xtu) { best_xtu = best[v][1]; tc.xtu = v; }
+            if (valid(v, 2) && best[v][2] < best_z2) { best_z2 = best[v][2]; tc.z2 = v; }
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -2371,8 +2380,10 @@ void anchor_start(l0l2_ctx *ctx, int64_t Kp, int64_t cols) {
                        Kp * ldp);
     launch_xw<double, double, double>(tc.xw, s, s64.XhR, s64.ldr, ws.Wa.as<double>(), ldp, s64.U, s64.ldu, np, cols,
                                       pp, active_cols(ctx), split_buf(ctx));
-    // the second product runs over n (short) into a p x nodes output: never sliced
-    const int v2 = split_of(tc.xw) > 1 ? tc.xtu : tc.xw;
+    // the second product runs over n (short) into a p x nodes output: its own
+    // timed shape, else (fixed shapes) the contraction over p's unless that is
+    // sliced, then the contraction over n's
+    const int v2 = tc.z2 >= 0 ? tc.z2 : (split_of(tc.xw) > 1 ? tc.xtu : tc.xw);
     launch_xw<double, double, double>(v2, s, s64.Xh, s64.ldc, s64.U, s64.ldu, ws.Za.as<double>(), ldp, pp, cols,
                                       np, active_cols(ctx));
     prof_end(ctx, PROF_ANCHOR);

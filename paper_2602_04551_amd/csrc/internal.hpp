@@ -71,6 +71,7 @@ struct MethodParams {
 // Tile shapes (index into the sweep kernels' shape table) of the two contractions.
 struct TileChoice {
     int xw = 0, xtu = 0;
+    int z2 = -1;   // FP64 tiles of reduced modes: the anchor's product over n (-1: not timed)
 };
 
 struct Instance {
