@@ -1,0 +1,114 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark
+times (autotuned tiles, live buckets, graph-replayed blocks).
+
+n = p = 1000, 256 frontier nodes: the oracle solves a spread sample of the
+batch's nodes one by one from the same codes and warm start (its own FP64 root),
+and every node is checked for the properties a rigorous bound has at any size.
+n = p = 5000 and n = 1000, p = 50 000 are beyond what the single-threaded oracle
+finishes in seconds (its precompute alone is O(n^2 p)); there the reduced-precision
+paths are checked against the FP64 GPU path, itself held to the oracle at the
+smaller sizes, and every node against the bound's own properties."""
+import numpy as np
+import pytest
+
+from paper_2602_04551_amd import datagen
+
+pytestmark = pytest.mark.gpu
+C2_K = 256
+C2_SAMPLE = list(range(0, C2_K, 16)) + [C2_K - 1]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def c2(orc):
+    """The benchmark's node batch rebuilt from the oracle's own root: 256 nodes
+    with 1-16 fixings among the 64 largest root coordinates, warm-started from the
+    root, and the oracle's solves of the sampled nodes."""
+    inst = datagen.config_instance("C2", seed=0)
+    o = orc.Oracle.from_instance(inst)
+    root = o.node_admm(None, tol=1e-6, max_iter=10000)
+    p = inst.p
+    cand = np.lexsort((np.arange(p), -np.abs(root["beta"])))[:64]
+    codes = datagen.frontier_codes(p, C2_K, cand, seed=0)
+    refs = {k: o.node_admm(codes[k], root["beta"], root["v"], tol=1e-6, max_iter=2000, check_every=10)
+            for k in C2_SAMPLE}
+    return inst, o, root, codes, refs
+
+
+def solve(inst, precision, codes, beta0, v0, **kw):
+    from paper_2602_04551_amd.binding import Context
+    ctx = Context(0)
+    ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, rho=1.0, precision=precision)
+    r = ctx.solve_node_batch(codes, beta0, v0, **kw)
+    return ctx, {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in r.items()}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp8"])
+def test_c2_batch_matches_the_oracle_on_sampled_nodes(torch_cuda, c2, precision):
+    inst, o, root, codes, refs = c2
+    K = C2_K
+    beta0 = np.tile(root["beta"], (K, 1))
+    v0 = np.tile(root["v"], (K, 1))
+    ctx, r = solve(inst, precision, codes, beta0, v0, tol_node=1e-6, max_iter=2000, check_every=10)
+    lb, pr, it, st = r["lb"], r["primal"], r["iters"], r["status"]
+    # every node: converged, its rigorous bound below the primal value at its iterate, gap within tol
+    assert (st == 0).all()
+    assert np.all(lb <= pr)
+    assert np.all((pr - lb) / np.abs(pr) <= 1e-6)
+    for k, ref in refs.items():
+        if precision == "fp64":
+            assert it[k] == ref["iters"], k
+            assert abs(lb[k] - ref["lb"]) <= 1e-10 * abs(ref["primal"]), k
+            assert abs(pr[k] - ref["primal"]) <= 1e-10 * abs(ref["primal"]), k
+        else:
+            assert abs(lb[k] - ref["lb"]) <= 1e-5 * abs(ref["primal"]), k
+    if precision == "fp64":
+        # rounding, branching and refinement on the sampled nodes, from the GPU iterates
+        rb = ctx.round_branch(codes, r["beta"])
+        sup, bj = rb["support"].cpu().numpy(), rb["branch_j"].cpu().numpy()
+        for k, ref in refs.items():
+            mask, _ = o.support(codes[k], ref["beta"])
+            assert (sup[k] == mask).all(), k
+            assert bj[k] == o.branch(codes[k], ref["beta"]), k
+        obj, _, _ = ctx.refine_incumbent(sup, r["beta"])
+        obj = obj.cpu().numpy()
+        for k, ref in refs.items():
+            f, _, _ = o.fista(sup[k], ref["beta"])
+            assert abs(obj[k] - f) <= 1e-9 * abs(f), k
+
+
+def node_batch(cfg, K):
+    inst = datagen.config_instance(cfg, seed=0)
+    codes = datagen.node_batch_codes(inst.p, K, seed=K)
+    zero = np.zeros((K, inst.p))
+    return inst, codes, zero
+
+
+@pytest.mark.parametrize("cfg,K,precisions", [("C3", 512, ("fp32", "bf16")),
+                                              ("C5", 256, ("fp32", "bf16", "fp8"))])
+def test_full_size_batches_agree_with_the_fp64_path(torch_cuda, cfg, K, precisions):
+    """The batching (n = p = 5000) and high-dimensional (n = 1000, p = 50 000)
+    workloads at the benchmark's batch sizes: every bound stays below its
+    node's primal value, converged nodes meet the tolerance, and the bounds of
+    nodes converged in both paths agree with the FP64 path within 1e-5."""
+    inst, codes, zero = node_batch(cfg, K)
+    _, ref = solve(inst, "fp64", codes, zero, zero, tol_node=1e-6, max_iter=2000, check_every=10)
+    conv64 = ref["status"] == 0
+    assert np.all(ref["lb"] <= ref["primal"])
+    assert conv64.sum() >= 0.5 * K
+    for precision in precisions:
+        _, r = solve(inst, precision, codes, zero, zero, tol_node=1e-6, max_iter=2000, check_every=10)
+        lb, pr, st = r["lb"], r["primal"], r["status"]
+        conv = st == 0
+        assert np.all(lb <= pr), precision
+        assert np.all((pr - lb)[conv] / np.abs(pr[conv]) <= 1e-6), precision
+        assert conv.sum() >= conv64.sum() - 0.05 * K, precision
+        both = conv & conv64
+        assert np.max(np.abs(lb - ref["lb"])[both] / np.abs(ref["primal"][both])) <= 1e-5, precision
