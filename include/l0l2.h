@@ -44,11 +44,14 @@ enum {
 };
 
 /* Precision of the X products inside the ADMM sweep.  FP64: everything in FP64.
- * FP32 (mixed): sweeps in FP32 while a batch converges, then FP64 sweeps from the
- * FP32 iterates until each node meets its tolerance (the FP32 iterates alone
- * stall near a relative gap of 1e-6 .. 1e-5); node state returned in FP32.  BF16: the transformed design matrix is
- * stored in BF16, the node operand is split into two BF16 halves, accumulation
- * and node state are FP32.  FP8: the transformed design matrix is stored as
+ * FP32 (mixed): sweeps in FP32 while a batch converges, then anchored sweeps
+ * until each node meets its tolerance: the node state and update are FP64, an
+ * FP64 product anchors every block and the FP32 products act on the movement
+ * since that anchor only (FP32 sweeps alone stall near a relative gap of
+ * 1e-6 .. 1e-5); node state returned in FP32.  BF16: the transformed design
+ * matrix is stored as two BF16 terms (hi + lo), the node operand is split into
+ * two BF16 halves, accumulation is FP32; the BF16 phase ends in anchored sweeps
+ * as in FP32 mode.  FP8: the transformed design matrix is stored as
  * FP8 e4m3 codes with one FP32 scale per column (s_j = max_i |Xh_ij| / 448,
  * one byte per element), the codes are widened to BF16 in the products and
  * every sweep is anchored (an FP64 product every block, the reduced products
@@ -233,9 +236,10 @@ int l0l2_server_destroy(l0l2_server *srv);
  * range cut into slices whose partial products are then added in slice order
  * (more workgroups when n x nodes is small and p long): 12, 13, 17 = 128x128
  * LDS-staged in 2 / 4 / 8 slices, 14, 15 = 16x16/4 in 4 / 8 slices, 16 = 32x32/4
- * in 4 slices.  By default (both -1) each new padded batch size
- * is timed once with every shape whose node tile divides it, on the live batch,
- * and the fastest kept per instance; fixed shapes serve tests and tuning
+ * in 4 slices.  By default (both -1) each live bucket (the live node count
+ * rounded up to a power of two, at most the padded batch) is timed once with
+ * every shape whose node tile divides it, on the live batch, and the fastest
+ * kept per instance (in the reduced modes also for the anchor's FP64 product); fixed shapes serve tests and tuning
  * studies (a fixed shape whose node tile does not divide the padded batch makes
  * the solve calls fail with L0L2_E_INVALID).  Results do not depend on the
  * shape beyond rounding of the summation order.  BF16 mode maps shapes 0-11 to
