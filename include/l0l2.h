@@ -239,9 +239,10 @@ int l0l2_server_destroy(l0l2_server *srv);
  * in 4 slices.  By default (both -1) each live bucket (the live node count
  * rounded up to a power of two, at most the padded batch) is timed once with
  * every shape whose node tile divides it, on the live batch, and the fastest
- * kept per instance (in the reduced modes also for the anchor's FP64 product); fixed shapes serve tests and tuning
- * studies (a fixed shape whose node tile does not divide the padded batch makes
- * the solve calls fail with L0L2_E_INVALID).  Results do not depend on the
+ * kept per instance (in the reduced modes also for the anchor's FP64
+ * product); fixed shapes serve tests and tuning studies (they cover the whole
+ * padded batch, and one whose node tile does not divide it makes the solve
+ * calls fail with L0L2_E_INVALID).  Results do not depend on the
  * shape beyond rounding of the summation order.  BF16 mode maps shapes 0-11 to
  * its own three (0 = 32x32 register tile, 1 = 64x64 and 2 = 128x128 LDS-staged,
  * larger values taken as 2) and the sliced shapes of the contraction over p
