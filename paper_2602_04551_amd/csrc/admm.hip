@@ -2280,7 +2280,6 @@ void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *act
 // BF16 shapes chosen per padded batch, timed like tile_choice (kind 2).
 TileChoice &tile_choice_bf16(l0l2_ctx *ctx, int64_t Kp) {
     Instance &in = ctx->inst;
-    Workspace &ws = ctx->ws;
     ensure_split(ctx, Kp, in.ldu, sizeof(float));
     if (ctx->force_xw >= 0) {
         // fixed shapes: 0-11 map to the three unsliced shapes; the sliced ones to
@@ -2549,12 +2548,10 @@ TileChoice tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
     return in.tiles[key] = tc;
 }
 
-// One anchored sweep in FP8 storage: U = Xh d with the codes (register tile
-// 32 x 32, 8 waves), then the FP64 update from z_a + Xh^T U.
+// One anchored sweep in FP8 storage: U = Xh d with the codes (register or
+// LDS-staged tiles, as timed), then the FP64 update from z_a + Xh^T U.
 void sweep_once_fp8(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate) {
-    Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
-    hipStream_t s = ctx->stream;
     Sweep<float> s32 = sweep32(ctx);
     const NodeCols ncl = active_cols(ctx);
     const TileChoice tc = tile_choice_fp8(ctx, Kp);
@@ -2636,14 +2633,6 @@ void init_batch(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t K, int64_t Kp) {
     hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.ldp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta,
                        sw.V, sw.W, sw.c, (T)in.mp.rho, in.ldp, Kp * in.ldp);
     HIPCHK(hipGetLastError());
-}
-
-void read_counters(l0l2_ctx *ctx, int out[2]) {
-    Workspace &ws = ctx->ws;
-    HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
-    out[0] = ws.host_counter[0];
-    out[1] = ws.host_counter[1];
 }
 
 enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2, SK_ANCH = 3 };

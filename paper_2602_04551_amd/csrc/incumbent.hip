@@ -137,8 +137,6 @@ __device__ double U_S(const double *__restrict__ X, int64_t ldx, const double *_
 // the returned objective F(S, beta) is evaluated from the residual y - X_S beta
 // in FP64.
 constexpr int kGramMax = 64;
-constexpr int kGramBlocks = kGramMax / 16;
-constexpr int kGramTri = kGramBlocks * (kGramBlocks + 1) / 2;
 
 struct FistaShared {
     int idx[kSMax];
