@@ -299,12 +299,22 @@ def node_batch_runs(inst, Ks, precs, workload, label):
 
 
 def batching_main(args):
-    """n = p = 5000 batches, K in {512, 1024, 2048, 4096}: BF16 split sweeps against FP32."""
+    """n = p = 5000 batches, K in {512, 1024, 2048, 4096}: BF16 split sweeps against FP32; then
+    the autotuner's batch axis (node-sweeps per second for K = 32 .. 4096) in both precisions."""
     from paper_2602_04551_amd import datagen
+    from paper_2602_04551_amd.binding import Context
     inst = datagen.config_instance("C3", seed=0)
     node_batch_runs(inst, (512, 1024, 2048, 4096), ("bf16", "fp32"),
                     "n=p=5000 Toeplitz rho=0.3 k=20 SNR=3 lambda0=0.005 lambda2=0.01, node batches with free sets "
                     "U{50..p}, |F1| U{0..20}", "batching")
+    tuning = {}
+    for prec in ("bf16", "fp32"):
+        ctx = Context(0)
+        ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
+        k_t, rates = ctx.tune_batch_size(k_max=4096, frac=0.9)
+        tuning[prec] = {"chosen_K": k_t, "node_sweeps_per_s": {str(k): round(v) for k, v in rates.items()}}
+        ctx.close()
+    print(json.dumps({"batch_tuning": tuning}), flush=True)
 
 
 def highdim_main(args):
@@ -427,6 +437,10 @@ def main():
                         "batches": r["batches"], "certified": r["certified"], "status": r["status"],
                         "support": [int(s) for s in r["support"]]}
         out["ttco"] = tt
+    if not args.no_ttco:
+        # the autotuner's batch axis on this instance (after the timed work; the workload keeps K = 256)
+        k_t, rates = mixed.ctx.tune_batch_size(k_max=1024, frac=0.9)
+        out["batch_tuning"] = {"chosen_K": k_t, "node_sweeps_per_s": {str(k): round(v) for k, v in rates.items()}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mixed, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -157,7 +157,8 @@ typedef struct {
 } l0l2_trace_rec;
 
 typedef struct {
-    int K;                 /* nodes per batch (Alg. 1) */
+    int K;                 /* nodes per batch (Alg. 1); 0: chosen by l0l2_tune_batch_size
+                              (k_max 1024, frac 0.9) once per instance */
     int policy;            /* L0L2_BEST_FIRST or L0L2_DFS */
     double eps_prune;      /* prune when LB >= UB (1 - eps_prune) */
     double gap_tol;        /* stop when (UB - LB) / UB <= gap_tol; 0 runs to exhaustion */
@@ -188,6 +189,20 @@ typedef struct {
  * LIFO), the incumbent and the pruning decisions.  Fills *out. */
 int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *out);
 void l0l2_result_free(l0l2_bnb_result *res);
+
+/* Node-batch size by measurement (the batch axis of the autotuner; the batch
+ * size K of Alg. 1 is the paper's parameter for how many nodes are solved at
+ * once).  Each candidate K = 32, 64, ..., up to k_max (powers of two) solves a
+ * batch of K nodes of the instance with every coordinate free from a cold start
+ * for 20 sweeps (two gap checks, zero tolerance so that no node retires) in the
+ * context's precision, once to settle tiles and graphs and once timed; the
+ * chosen K is the smallest whose node-sweeps per second reach frac (0 < frac
+ * <= 1) of the best candidate's.  *k_out receives it; rates (host, may be NULL,
+ * room for 12 entries) receives each candidate's node-sweeps per second and
+ * *n_rates (may be NULL) their count.  The choice is kept with the instance for
+ * l0l2_bnb_solve with K = 0.  Requires 32 <= k_max <= 65536; uses the context's
+ * batch workspace (grown to k_max nodes). */
+int l0l2_tune_batch_size(l0l2_ctx *ctx, int k_max, double frac, int *k_out, double *rates, int *n_rates);
 
 /* ---- Serving: branch and bound for many instances on one device ---------- */
 

@@ -80,6 +80,7 @@ SIGNATURES = {
     "l0l2_server_last_error": (C.c_char_p, [_vp]),
     "l0l2_server_destroy": (_i, [_vp]),
     "l0l2_set_tiles": (_i, [_vp, _i, _i]),
+    "l0l2_tune_batch_size": (_i, [_vp, _i, _d, C.POINTER(_i), _vp, C.POINTER(_i)]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
     "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
 }
@@ -88,6 +89,10 @@ SIGNATURES = {
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"libl0l2 is not built ({path} missing): run __graft_entry__.build()")
+    # torch first: its HIP runtime is then the one the library binds to, the same
+    # runtime instance that owns the tensors and streams handed to the library
+    # (loaded the other way round, the process can end up with no usable device)
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)
@@ -236,6 +241,15 @@ class Context:
         obj = C.c_double()
         self._check(lib.l0l2_exact_objective(self._h, mask.ctypes.data, beta.ctypes.data, C.byref(obj)))
         return obj.value, beta
+
+    def tune_batch_size(self, k_max=1024, frac=0.9):
+        """(chosen K, {candidate K: node-sweeps per second})."""
+        k = C.c_int()
+        n = C.c_int()
+        rates = np.zeros(12)
+        self._check(lib.l0l2_tune_batch_size(self._h, int(k_max), float(frac), C.byref(k), rates.ctypes.data,
+                                             C.byref(n)))
+        return k.value, {32 << i: float(rates[i]) for i in range(n.value)}
 
     def set_tiles(self, xw_shape=-1, xtu_shape=-1):
         self._check(lib.l0l2_set_tiles(self._h, int(xw_shape), int(xtu_shape)))

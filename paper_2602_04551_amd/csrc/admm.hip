@@ -15,6 +15,7 @@
 // evaluated in FP64 with the original X (Sec. 3.1.2 and the node stopping rule
 // of Sec. 4.1): r = y - X b, g = X^T r, LB = rigorous D(r); P(beta) from X beta.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <limits>
 #include <type_traits>
@@ -2946,6 +2947,56 @@ void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool) {
 void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     if (ctx->inst.prec == L0L2_FP64) solve_plain<double>(ctx, sweep64(ctx), K, o);
     else solve_mixed(ctx, K, o);
+}
+
+// The batch axis of the autotuner.  Each candidate K (32, 64, ... up to k_max)
+// solves a batch of K nodes with every coordinate free from a cold start, for
+// two blocks of the default check interval with a zero tolerance (no node
+// retires, so every node does every sweep): the precision path, gap checks,
+// live buckets and graph replay of a real solve.  The first solve settles the
+// tile shapes and graphs of that K, the second is timed on the host clock.  The
+// chosen K is the smallest whose node-sweeps per second reach frac of the best
+// candidate's: past it a larger batch adds little throughput, while in a
+// best-first tree it solves nodes that a better incumbent found meanwhile would
+// have pruned.
+int tune_batch_size(l0l2_ctx *ctx, int k_max, double frac, std::vector<double> &rates) {
+    Instance &in = ctx->inst;
+    const size_t sb = state_bytes(in.prec);
+    rates.clear();
+    l0l2_admm_opts o{};
+    o.tol_node = 0.0;
+    o.check_every = 10;
+    o.max_iter = 2 * o.check_every;
+    DevBuf codes, beta, v;
+    int best_k = kPadNodes;
+    double best = 0.0;
+    for (int K = kPadNodes; K <= k_max; K *= 2) {
+        codes.ensure((size_t)K * in.p);
+        beta.ensure(sb * K * in.p);
+        v.ensure(sb * K * in.p);
+        double secs = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIPCHK(hipMemsetAsync(codes.ptr, 0, (size_t)K * in.p, ctx->stream));   // every coordinate free
+            HIPCHK(hipMemsetAsync(beta.ptr, 0, sb * K * in.p, ctx->stream));
+            HIPCHK(hipMemsetAsync(v.ptr, 0, sb * K * in.p, ctx->stream));
+            load_batch(ctx, K, codes.as<uint8_t>(), beta.ptr, v.ptr, false);
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            const auto t0 = std::chrono::steady_clock::now();
+            run_solve(ctx, K, o);
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        const double r = (double)K * o.max_iter / std::max(secs, 1e-9);
+        rates.push_back(r);
+        best = std::max(best, r);
+    }
+    for (size_t i = 0; i < rates.size(); ++i)
+        if (rates[i] >= frac * best) {
+            best_k = kPadNodes << i;
+            break;
+        }
+    in.tuned_K = best_k;
+    return best_k;
 }
 
 // Bound at b already loaded in ws.B (codes in ws.codes): fills ws.lb.

@@ -272,11 +272,31 @@ int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *ou
     return guarded(ctx, [&] {
         need_data(ctx);
         if (!opts || !out) l0l2::fail(L0L2_E_INVALID, "null argument");
-        if (opts->K < 1 || opts->admm.max_iter < 1 || opts->admm.check_every < 1 || opts->max_iter_root < 1 ||
+        if (opts->K < 0 || opts->admm.max_iter < 1 || opts->admm.check_every < 1 || opts->max_iter_root < 1 ||
             opts->fista.max_iter < 1 || !(opts->eps_prune >= 0) || !(opts->gap_tol >= 0) || opts->max_nodes < 1 ||
             (opts->policy != L0L2_BEST_FIRST && opts->policy != L0L2_DFS))
             l0l2::fail(L0L2_E_INVALID, "bad branch-and-bound options");
-        l0l2::bnb_solve(ctx, *opts, out);
+        l0l2_bnb_opts o = *opts;
+        if (o.K == 0) {
+            // batch size by measurement, once per instance
+            std::vector<double> rates;
+            o.K = ctx->inst.tuned_K > 0 ? ctx->inst.tuned_K : l0l2::tune_batch_size(ctx, 1024, 0.9, rates);
+        }
+        l0l2::bnb_solve(ctx, o, out);
+    });
+}
+
+int l0l2_tune_batch_size(l0l2_ctx *ctx, int k_max, double frac, int *k_out, double *rates, int *n_rates) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        if (!k_out) l0l2::fail(L0L2_E_INVALID, "null argument");
+        if (k_max < 32 || k_max > 65536 || !(frac > 0.0 && frac <= 1.0))
+            l0l2::fail(L0L2_E_INVALID, "need 32 <= k_max <= 65536 and 0 < frac <= 1");
+        std::vector<double> r;
+        *k_out = l0l2::tune_batch_size(ctx, k_max, frac, r);
+        if (n_rates) *n_rates = (int)r.size();
+        if (rates)
+            for (size_t i = 0; i < r.size(); ++i) rates[i] = r[i];
     });
 }
 

@@ -105,6 +105,7 @@ struct Instance {
     int64_t ldqr = 0, ldqc = 0;
     DevBuf codes_pad; // scratch
     std::map<std::pair<int, int64_t>, TileChoice> tiles;   // autotuned per (type, padded K)
+    int tuned_K = 0;                                      // node-batch size chosen by measurement (0: none yet)
 };
 
 // Per-batch workspace, grown on demand (capacity in padded nodes).
@@ -206,6 +207,9 @@ void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool store_b_last);
 void run_dual_bound(l0l2_ctx *ctx, int K, const void *b_internal_or_null);
 // Solve the K nodes loaded in the workspace; results stay in ws.lb/primal/iters/status.
 void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o);
+// Node-batch size by measurement: candidates 32, 64, ... up to k_max; returns
+// the chosen K and fills rates[i] (node-sweeps per second of candidate 32 * 2^i).
+int tune_batch_size(l0l2_ctx *ctx, int k_max, double frac, std::vector<double> &rates);
 
 // incumbent.hip
 void run_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, int64_t ld_codes, const void *beta, int64_t ld_beta,

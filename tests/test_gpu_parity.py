@@ -263,6 +263,28 @@ def test_live_bucket_narrower_than_the_batch_with_sliced_tiles(torch_cuda, preci
         assert np.max(np.abs(lb0 - lb1)[both] / np.abs(pr[both])) < 1e-6
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_size_tuner_and_bnb_with_tuned_K(torch_cuda, orc, precision):
+    """The batch axis of the autotuner: one positive rate per candidate K, the
+    chosen K the smallest within the fraction of the best rate, and a best-first
+    BnB with K = 0 (tuned) certifying the oracle's optimum."""
+    from paper_2602_04551_amd.binding import L0L2Error
+    inst = datagen.config_instance("C1", seed=0)
+    ctx = ctx_for(inst, precision)
+    K, rates = ctx.tune_batch_size(k_max=256, frac=0.9)
+    assert list(rates) == [32, 64, 128, 256] and all(r > 0 for r in rates.values())
+    best = max(rates.values())
+    assert rates[K] >= 0.9 * best and all(rates[k] < 0.9 * best for k in rates if k < K)
+    r = ctx.bnb_solve(K=0, policy="best", tol_node=1e-6, max_iter=2000)
+    o = orc.Oracle.from_instance(inst)
+    ref = o.bnb(tol_node=1e-6, max_iter=2000)
+    assert r["status"] == 0
+    assert abs(r["certified"] - ref["certified"]) <= 1e-8 * abs(ref["certified"])
+    assert sorted(r["support"].tolist()) == sorted(np.flatnonzero(ref["mask"]).tolist())
+    with pytest.raises(L0L2Error):
+        ctx.tune_batch_size(k_max=16)
+
+
 def test_fixed_shape_that_does_not_fit_the_batch_is_rejected(torch_cuda, cases):
     """Shape 7 tiles 64 nodes; a batch padded to 32 nodes cannot use it."""
     from paper_2602_04551_amd.binding import L0L2Error
