@@ -269,6 +269,18 @@ int l0l2_server_destroy(l0l2_server *srv);
  * uses more slices than the range has 32-wide chunks. */
 int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
 
+/* Form of the b-update of the ADMM sweep (Sec. 3.1.1: b = D w with
+ * D = (X^T X + rho I)^{-1}).  1: through the folded operand Xh = L^{-1} X
+ * (S = X X^T + rho I = L L^T), b = (w - Xh^T (Xh w)) / rho, two contractions of
+ * 2 n p flops per node per sweep.  2: through the p x p Gram matrix G = Xh^T Xh,
+ * b = (w - G w) / rho, one contraction of 2 p^2 flops (the paper's p x p D,
+ * here in the form I - rho D).  0 (default): the Gram form in FP32 mode when
+ * p <= 1.5 n and the padded p is at most 8192, else the folded operand.  The
+ * Gram form exists in FP32 mode only (other precisions always use the folded
+ * operand; l0l2_admm_sweeps always does).  G is built in FP64 (the anchors) and
+ * FP32 on the first solve that uses it. */
+int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form);
+
 /* Opt-in timing of the library's kernels with HIP events recorded on the
  * context stream around each launch (adds one event pair per launch).
  * l0l2_profile_enable clears the counters and switches timing on (1) or off (0).

@@ -81,6 +81,7 @@ SIGNATURES = {
     "l0l2_server_destroy": (_i, [_vp]),
     "l0l2_set_tiles": (_i, [_vp, _i, _i]),
     "l0l2_tune_batch_size": (_i, [_vp, _i, _d, C.POINTER(_i), _vp, C.POINTER(_i)]),
+    "l0l2_set_bupdate_form": (_i, [_vp, _i]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
     "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
 }
@@ -250,6 +251,9 @@ class Context:
         self._check(lib.l0l2_tune_batch_size(self._h, int(k_max), float(frac), C.byref(k), rates.ctypes.data,
                                              C.byref(n)))
         return k.value, {32 << i: float(rates[i]) for i in range(n.value)}
+
+    def set_bupdate_form(self, form="auto"):
+        self._check(lib.l0l2_set_bupdate_form(self._h, {"auto": 0, "folded": 1, "gram": 2}[form]))
 
     def set_tiles(self, xw_shape=-1, xtu_shape=-1):
         self._check(lib.l0l2_set_tiles(self._h, int(xw_shape), int(xtu_shape)))

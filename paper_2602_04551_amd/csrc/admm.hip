@@ -284,7 +284,7 @@ struct EpiIn {
 
 template <class T>
 __device__ __forceinline__ void epi_load(EpiIn<T> &ei, int slot, int64_t col, int64_t j, int64_t ldp,
-                                         const T *__restrict__ W, const T *__restrict__ V,
+                                         const T *W, const T *__restrict__ V,
                                          const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                          const int *__restrict__ active) {
     const int64_t row = col_row(slot, col), o = row * ldp + j;
@@ -370,11 +370,13 @@ __device__ __forceinline__ void store_estimate(double e[5], int m, int64_t node,
 }
 
 // Contraction over n with the ADMM epilogue: Q[k][j] = sum_i Xh[i][j] U[k][i],
-// then admm_update for node k and coordinate j.  gpart != nullptr adds the
-// per-tile sums of the gap estimate.
+// then admm_update for node k and coordinate j, reading W and writing the new W
+// to Wout (the same array, or in the Gram form, whose operand U is W itself,
+// the other buffer of a pair).  gpart != nullptr adds the per-tile sums of the
+// gap estimate.
 template <class TA, class T, int BM, int BN, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
-                                                  int64_t ldu, int64_t kdim, T *__restrict__ W,
+                                                  int64_t ldu, int64_t kdim, const T *W, T *Wout,
                                                   T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
                                                   const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                                   const int *__restrict__ active, DevParams<T> q, int64_t ldp,
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ 
         const int idx = threadIdx.x + t * 64 * WAVES, n = idx / TM, m = idx % TM;
         double e[5] = {0, 0, 0, 0, 0};
         if (ei[t].on)
-            admm_update<T>(sum_waves<T, TM, TN, WAVES>(red, n, m), ei[t], (int64_t)se[t] * ldp + m0 + m, W, beta, V,
+            admm_update<T>(sum_waves<T, TM, TN, WAVES>(red, n, m), ei[t], (int64_t)se[t] * ldp + m0 + m, Wout, beta, V,
                            Bst, q, store_b, est, ga, e);
         if (est) store_estimate<TM>(e, m, se[t], gpart);
     }
@@ -612,7 +614,7 @@ __device__ __forceinline__ void wave_sum5(double e[5]) {
 // (col: its column index, slot: its list entry), all loaded before any update.
 template <class T, int H>
 __device__ __forceinline__ void epi_load_row(EpiIn<T> (&ei)[H], int slot, int64_t col, int64_t m0, int64_t ldp,
-                                             const T *__restrict__ W, const T *__restrict__ V,
+                                             const T *W, const T *__restrict__ V,
                                              const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                              const int *__restrict__ active) {
     const int lane = threadIdx.x & 63;
@@ -675,7 +677,7 @@ __global__ __launch_bounds__(256) void k_splitk_sum(const T *__restrict__ P, int
 // Contraction over n with the ADMM epilogue, LDS-staged tile.
 template <class T, int WM, int WN>
 __global__ __launch_bounds__(256) void k_admm_xtu_lds(const T *__restrict__ A, int64_t lda, const T *__restrict__ U,
-                                                      int64_t ldu, int64_t kdim, T *__restrict__ W,
+                                                      int64_t ldu, int64_t kdim, const T *W, T *Wout,
                                                       T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
                                                       const uint8_t *__restrict__ codes, const T *__restrict__ c,
                                                       const int *__restrict__ active, DevParams<T> q, int64_t ldp,
@@ -708,8 +710,8 @@ __global__ __launch_bounds__(256) void k_admm_xtu_lds(const T *__restrict__ A, i
                 if (!ei[h].on) continue;
                 const int m = lane + 64 * h;
                 double ev[5] = {0, 0, 0, 0, 0};
-                admm_update<T>(smem[(nl - c0) * E::LD + m], ei[h], (int64_t)slot * ldp + m0 + m, W, beta, V, Bst, q,
-                               store_b, est, ga, ev);
+                admm_update<T>(smem[(nl - c0) * E::LD + m], ei[h], (int64_t)slot * ldp + m0 + m, Wout, beta, V, Bst,
+                               q, store_b, est, ga, ev);
 #pragma unroll
                 for (int u = 0; u < 5; ++u) e[u] += ev[u];
             }
@@ -1978,18 +1980,19 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
 template <class T>
 void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp, int64_t Kp, const uint8_t *codes,
                 const int *active, const DevParams<T> &q, int store_b, double *gpart = nullptr,
-                const GateArgs &ga = GateArgs{}, NodeCols ncl = NodeCols{nullptr}) {
+                const GateArgs &ga = GateArgs{}, NodeCols ncl = NodeCols{nullptr}, T *Wout = nullptr) {
     const int64_t ldp = sw.ldp;
+    if (!Wout) Wout = sw.W;
     if (sizeof(T) == 8 && v == 2) v = 1;
     if (v < 0 || v >= kShapes || !shape_fits(v, Kp)) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / kTileTM[v]), (unsigned)(Kp / kTileTN[v]));
     dim3 b((unsigned)(64 * kTileW[v]));
 #define L0L2_XTU(PBM, PBN, PW)                                                                                  \
-    hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, sw.ldc, sw.U, sw.ldu, np, sw.W,      \
-                       sw.beta, sw.V, sw.B, codes, sw.c, active, q, ldp, store_b, gpart, ga, ncl)
+    hipLaunchKernelGGL((k_admm_xtu<T, T, PBM, PBN, PW>), g, b, 0, s, sw.Xh, sw.ldc, sw.U, sw.ldu, np,            \
+                       (const T *)sw.W, Wout, sw.beta, sw.V, sw.B, codes, sw.c, active, q, ldp, store_b, gpart, ga, ncl)
 #define L0L2_XTUL(WM, WN)                                                                                       \
-    hipLaunchKernelGGL((k_admm_xtu_lds<T, WM, WN>), g, b, 0, s, sw.Xh, sw.ldc, sw.U, sw.ldu, np, sw.W, sw.beta,  \
-                       sw.V, sw.B, codes, sw.c, active, q, ldp, store_b, gpart, ga, ncl)
+    hipLaunchKernelGGL((k_admm_xtu_lds<T, WM, WN>), g, b, 0, s, sw.Xh, sw.ldc, sw.U, sw.ldu, np, (const T *)sw.W, \
+                       Wout, sw.beta, sw.V, sw.B, codes, sw.c, active, q, ldp, store_b, gpart, ga, ncl)
     if (v >= 9) {
         switch (v) {
             case 9: L0L2_XTUL(2, 2); break;
@@ -2411,6 +2414,113 @@ void sweep_once_anch(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
     HIPCHK(hipGetLastError());
 }
 
+// ---------------------------------------------------------------------------
+// Gram form of the b-update (FP32 mode).  With G = Xh^T Xh (p x p, symmetric;
+// Xh = L^{-1} X), b = D w = (w - G w) / rho: one contraction over p per sweep
+// instead of two (over p, then over n), the paper's p x p form of D written
+// through the folded operand.  Its work per node-sweep is 2 p^2 against 4 n p,
+// and it halves the launches per sweep, so it is taken when p <= 1.5 n (and G
+// stays small).  The contraction's node operand is W itself, which the same
+// launch updates, so W alternates between two buffers (the anchored sweeps: d).
+// ---------------------------------------------------------------------------
+__global__ void k_f64_to_f32(const double *__restrict__ src, int64_t lds, float *__restrict__ dst, int64_t ldd,
+                             int64_t rows, int64_t cols) {
+    const int64_t r = blockIdx.y, j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < rows && j < cols) dst[r * ldd + j] = (float)src[r * lds + j];
+}
+
+bool gram_form(const l0l2_ctx *ctx) {
+    const Instance &in = ctx->inst;
+    if (in.prec != L0L2_FP32 || ctx->bform == 1) return false;
+    if (ctx->bform == 2) return true;
+    return 2 * in.pp <= 3 * in.np && in.pp <= 8192;
+}
+
+// G in FP64 (the anchors) and FP32 (the sweeps), once per instance.
+void ensure_gram(l0l2_ctx *ctx) {
+    Instance &in = ctx->inst;
+    if (in.gram_built) return;
+    hipStream_t s = ctx->stream;
+    const int64_t pp = in.pp, np = in.np;
+    in.ldg64 = ld_pad(pp, 8);
+    in.ldg32 = ld_pad(pp, 4);
+    in.G64.ensure(sizeof(double) * pp * in.ldg64);
+    in.G32.ensure(sizeof(float) * pp * in.ldg32);
+    // G[j][i] = sum_r Xh[r][i] Xh[r][j]: rows of the column-major Xh64 are columns of Xh
+    launch_xw<double, double, double>(0, s, in.Xh64.as<double>(), in.ldx, in.Xh64.as<double>(), in.ldx,
+                                      in.G64.as<double>(), in.ldg64, pp, pp, np);
+    hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((pp + 255) / 256), (unsigned)pp), dim3(256), 0, s,
+                       in.G64.as<double>(), in.ldg64, in.G32.as<float>(), in.ldg32, pp, pp);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    in.gram_built = true;
+}
+
+// Sweep t (1-based) of a block reads the W (or d) buffer it names and writes the
+// other: odd sweeps ws.W -> ws.W2, even ones back.
+float *gram_in(l0l2_ctx *ctx, int t) { return (t & 1) ? ctx->ws.W.as<float>() : ctx->ws.W2.as<float>(); }
+float *gram_out(l0l2_ctx *ctx, int t) { return (t & 1) ? ctx->ws.W2.as<float>() : ctx->ws.W.as<float>(); }
+
+// One Gram-form sweep on the FP32 state.
+void sweep_once_gram(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate, int t) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    Sweep<float> s32 = sweep32(ctx);
+    const TileChoice &tc = tile_choice<float>(ctx, s32, Kp);
+    Sweep<float> g = s32;
+    g.Xh = in.G32.as<float>();
+    g.ldc = in.ldg32;
+    g.W = gram_in(ctx, t);
+    g.U = g.W;
+    g.ldu = in.ldp;
+    prof_begin(ctx, PROF_ADMM_XTU_F32);
+    launch_xtu<float>(tc.xtu, ctx->stream, g, in.pp, in.pp, Kp, ws.codes.as<uint8_t>(), ws.active.as<int>(),
+                      dev_params<float>(in.mp), store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr,
+                      gate_args(in), active_cols(ctx), gram_out(ctx, t));
+    prof_end(ctx, PROF_ADMM_XTU_F32, active);
+    HIPCHK(hipGetLastError());
+}
+
+// Start of an anchored Gram-form block: w_a = W (FP64), d = 0 in ws.W, z_a = G w_a.
+void anchor_start_gram(l0l2_ctx *ctx, int64_t Kp, int64_t cols) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    Sweep<double> s64 = sweep64(ctx);
+    Sweep<float> s32 = sweep32(ctx);
+    const TileChoice &tc = tile_choice<double>(ctx, s64, cols);
+    prof_begin(ctx, PROF_ANCHOR);
+    const int64_t ldp = in.ldp;
+    hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
+                       Kp * ldp);
+    const int v = tc.z2 >= 0 ? tc.z2 : (split_of(tc.xw) > 1 ? tc.xtu : tc.xw);
+    launch_xw<double, double, double>(v, s, in.G64.as<double>(), in.ldg64, ws.Wa.as<double>(), ldp,
+                                      ws.Za.as<double>(), ldp, in.pp, cols, in.pp, active_cols(ctx));
+    prof_end(ctx, PROF_ANCHOR);
+    HIPCHK(hipGetLastError());
+}
+
+// One anchored Gram-form sweep: Q = z_a + G32 d_in, FP64 update, d_out = fl32(W - w_a).
+void sweep_once_anch_gram(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate, int t) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    const TileChoice &tc = tile_choice<float>(ctx, s32, Kp);
+    Sweep<float> g = s32;
+    g.Xh = in.G32.as<float>();
+    g.ldc = in.ldg32;
+    g.U = gram_in(ctx, t);
+    g.ldu = in.ldp;
+    g.W = gram_out(ctx, t);   // the d the update writes
+    prof_begin(ctx, PROF_ADMM_XTU_F32);
+    launch_xtu_anch(tc.xtu, ctx->stream, g, s64, ws.Za.as<double>(), ws.Wa.as<double>(), in.pp, in.pp, Kp,
+                    ws.codes.as<uint8_t>(), ws.active.as<int>(), dev_params<double>(in.mp), store_b ? 1 : 0,
+                    gate ? ws.gpart.as<double>() : nullptr, gate_args(in), active_cols(ctx));
+    prof_end(ctx, PROF_ADMM_XTU_F32, active);
+    HIPCHK(hipGetLastError());
+}
+
 // Contraction over n of the FP8 form: shape 0 = register tile 32 x 32 (8
 // waves), 1 = LDS-staged 64 x 64, 2 = LDS-staged 128 x 128.
 constexpr int kShapesFp8 = 3;
@@ -2662,16 +2772,27 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     const int64_t cols = live_bucket(ctx, active, Kp);
     hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>(),
                        ws.ncount.as<int>(), ws.counter.as<int>());
-    if (kind == SK_ANCH) anchor_start(ctx, Kp, cols);
+    const bool gram = (kind == SK_F32 || kind == SK_ANCH) && gram_form(ctx);
+    if (gram) ensure_gram(ctx);
+    if (kind == SK_ANCH) {
+        if (gram) anchor_start_gram(ctx, Kp, cols);
+        else anchor_start(ctx, Kp, cols);
+    }
     for (int t = 1; t <= n; ++t) {
         const bool last = t == n, gate = last && !force;
-        if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), cols, last, active, gate);
+        if (gram && kind == SK_F32) sweep_once_gram(ctx, cols, last, active, gate, t);
+        else if (gram) sweep_once_anch_gram(ctx, cols, last, active, gate, t);
+        else if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), cols, last, active, gate);
         else if (kind == SK_BF16) sweep_once_bf16(ctx, cols, last, active, gate, false);
         else if (kind == SK_ANCH && in.prec == L0L2_BF16) sweep_once_bf16(ctx, cols, last, active, gate, true);
         else if (kind == SK_ANCH && in.prec == L0L2_FP8) sweep_once_fp8(ctx, cols, last, active, gate);
         else if (kind == SK_ANCH) sweep_once_anch(ctx, cols, last, active, gate);
         else sweep_once<float>(ctx, sweep32(ctx), cols, last, active, gate);
     }
+    // an odd Gram-form block leaves the latest W in the second buffer (a node that
+    // retires keeps a stale W in it, which nothing reads again)
+    if (gram && kind == SK_F32 && (n & 1))
+        HIPCHK(hipMemcpyAsync(ws.W.ptr, ws.W2.ptr, sizeof(float) * Kp * in.ldp, hipMemcpyDeviceToDevice, s));
     if (!force) {
         int rows = 32;
         if (kind == SK_F64) rows = kTileTM[tile_choice<double>(ctx, sweep64(ctx), cols).xtu];
@@ -2711,6 +2832,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
         // settle the tile shapes first (the autotuner synchronises, and may grow
         // the split buffer, which drops the captured graphs)
         const bool bf = ctx->inst.prec == L0L2_BF16, f8 = ctx->inst.prec == L0L2_FP8;
+        if ((kind == SK_F32 || kind == SK_ANCH) && gram_form(ctx)) ensure_gram(ctx);   // not under capture
         if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), cols);
         if (kind == SK_F32 || (kind == SK_ANCH && !bf && !f8)) (void)tile_choice<float>(ctx, sweep32(ctx), cols);
         if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);
@@ -2867,6 +2989,8 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ++ws.gen;
     if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 2 * sizeof(int), hipHostMallocDefault));
     if (in.prec != L0L2_FP64) {
+        ws.W2.ensure(4 * Kp * ldp);
+        HIPCHK(hipMemsetAsync(ws.W2.ptr, 0, 4 * Kp * ldp, ctx->stream));
         ws.Wa.ensure(8 * Kp * ldp);
         ws.Za.ensure(8 * Kp * ldp);
         ws.W64.ensure(8 * Kp * ldp);

@@ -315,6 +315,18 @@ int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape) {
     });
 }
 
+int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form) {
+    return guarded(ctx, [&] {
+        if (form < 0 || form > 2) l0l2::fail(L0L2_E_INVALID, "form is 0 (auto), 1 (folded operand) or 2 (Gram)");
+        if (ctx->bform != form) {
+            // captured blocks hold the form they were captured with
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            l0l2::drop_graphs(ctx);
+        }
+        ctx->bform = form;
+    });
+}
+
 int l0l2_profile_enable(l0l2_ctx *ctx, int enable) {
     return guarded(ctx, [&] {
         l0l2::prof_collect(ctx);

@@ -106,12 +106,18 @@ struct Instance {
     DevBuf codes_pad; // scratch
     std::map<std::pair<int, int64_t>, TileChoice> tiles;   // autotuned per (type, padded K)
     int tuned_K = 0;                                      // node-batch size chosen by measurement (0: none yet)
+    // Gram form of the b-update (FP32 mode): G = Xh^T Xh (pp x pp, symmetric),
+    // b = (w - G w) / rho in one contraction; built on first use
+    DevBuf G64, G32;
+    int64_t ldg64 = 0, ldg32 = 0;
+    bool gram_built = false;
 };
 
 // Per-batch workspace, grown on demand (capacity in padded nodes).
 struct Workspace {
     int64_t cap = 0;
     DevBuf W, beta, V, B;          // Kp rows of ldp, state precision
+    DevBuf W2;                     // FP32 mode: second W (or d) buffer of the Gram-form sweeps
     DevBuf U;                      // Kp rows of ldu, state precision (ADMM product)
     DevBuf Upart;                  // partial products of the contraction over p cut into slices
     DevBuf W64, beta64, V64, B64;  // FP32 / BF16 mode: FP64 state of the anchored sweeps (Kp rows of ldp)
@@ -184,6 +190,7 @@ struct l0l2_ctx {
     bool has_data = false;
     bool tune = true;          // time the tile shapes of each new batch size
     int force_xw = -1, force_xtu = -1;   // fixed tile shapes (-1: autotune)
+    int bform = 0;                       // b-update form: 0 auto, 1 folded operand (two contractions), 2 Gram
     bool use_graphs = true;              // replay captured blocks of sweeps
     std::map<l0l2::GraphKey, hipGraphExec_t> graphs;
     l0l2::Instance inst;

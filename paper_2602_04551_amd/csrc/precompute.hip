@@ -312,6 +312,8 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     ctx->ws.cap = 0;
     drop_graphs(ctx);
     in.tiles.clear();
+    in.tuned_K = 0;
+    in.gram_built = false;
     in.n = n;
     in.p = p;
     in.np = round_up(n, kPadRows);
