@@ -414,6 +414,8 @@ def main():
            "config": {"workload": "n=1000 p=1000 Toeplitz rho=0.5 k=10 SNR=5 lambda0=0.005 lambda2=0.01, "
                                   "node batches of 256, FP32 ADMM + FP64 bounds",
                       "n": n, "p": p, "K": K, "node_tol": 1e-6, "check_every": 10, "rho": 1.0,
+                      "b_update": "Gram form b = (w - G w) / rho, G = Xh^T Xh (FP32 mode, p <= 1.5 n): one "
+                                  "contraction of 2 p^2 = 2 n p flops per node-sweep here",
                       "batch": "frontier nodes: 1-16 fixings among the 64 largest root coordinates, "
                                "warm-started from the root"},
            "roofline": roof,
