@@ -274,11 +274,12 @@ int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
  * (S = X X^T + rho I = L L^T), b = (w - Xh^T (Xh w)) / rho, two contractions of
  * 2 n p flops per node per sweep.  2: through the p x p Gram matrix G = Xh^T Xh,
  * b = (w - G w) / rho, one contraction of 2 p^2 flops (the paper's p x p D,
- * here in the form I - rho D).  0 (default): the Gram form in FP32 mode when
- * p <= 1.5 n and the padded p is at most 8192, else the folded operand.  The
- * Gram form exists in FP32 mode only (other precisions always use the folded
- * operand; l0l2_admm_sweeps always does).  G is built in FP64 (the anchors) and
- * FP32 on the first solve that uses it. */
+ * here in the form I - rho D).  0 (default): the Gram form in FP32 and BF16
+ * modes when p <= 1.5 n and the padded p is at most 8192, else the folded
+ * operand.  The Gram form exists in FP32 and BF16 modes only (FP64 and FP8
+ * always use the folded operand; l0l2_admm_sweeps always does).  G is built in
+ * FP64 (the anchors), then FP32 (FP32 mode) or a BF16 hi/lo pair of its FP32
+ * value (BF16 mode), on the first solve that uses it. */
 int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form);
 
 /* Opt-in timing of the library's kernels with HIP events recorded on the

@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restri
 template <int WM, int WN, int ANCH>
 __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
     const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
-    int64_t ldu, int64_t kdim, float *__restrict__ W32, float *__restrict__ beta32, float *__restrict__ V32,
+    int64_t ldu, int64_t kdim, const float *W32, float *W32out, float *__restrict__ beta32, float *__restrict__ V32,
     float *__restrict__ B32, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W64,
     double *__restrict__ beta64, double *__restrict__ V64, double *__restrict__ B64, const uint8_t *__restrict__ codes,
     const float *__restrict__ c32, const double *__restrict__ c64, const int *__restrict__ active,
@@ -1071,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
                     double ev[5] = {0, 0, 0, 0, 0};
                     const double wn = admm_update<double>(za[h] + (double)buf[(nl - c0) * E::LD + m], ei[h], o, W64,
                                                           beta64, V64, B64, q64, store_b, est, ga, ev);
-                    W32[o] = (float)(wn - wa[h]);
+                    W32out[o] = (float)(wn - wa[h]);
 #pragma unroll
                     for (int u = 0; u < 5; ++u) e[u] += ev[u];
                 }
@@ -1083,8 +1083,8 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
                     if (!ei[h].on) continue;
                     const int m = lane + 64 * h;
                     double ev[5] = {0, 0, 0, 0, 0};
-                    admm_update<float>(buf[(nl - c0) * E::LD + m], ei[h], (int64_t)slot * ldp + m0 + m, W32, beta32,
-                                       V32, B32, q32, store_b, est, ga, ev);
+                    admm_update<float>(buf[(nl - c0) * E::LD + m], ei[h], (int64_t)slot * ldp + m0 + m, W32out,
+                                       beta32, V32, B32, q32, store_b, est, ga, ev);
 #pragma unroll
                     for (int u = 0; u < 5; ++u) e[u] += ev[u];
                 }
@@ -1126,7 +1126,7 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *
 // Q[k][j] = sum_i Xh[i][j] U[k][i] (Xh column-major) with the ADMM epilogue.
 __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
     const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
-    int64_t ldu, int64_t kdim, float *__restrict__ W, float *__restrict__ beta, float *__restrict__ V,
+    int64_t ldu, int64_t kdim, const float *W, float *Wout, float *__restrict__ beta, float *__restrict__ V,
     float *__restrict__ Bst, const uint8_t *__restrict__ codes, const float *__restrict__ c,
     const int *__restrict__ active, DevParams<float> q, int64_t ldp, int store_b, double *__restrict__ gpart,
     GateArgs ga, NodeCols ncl) {
@@ -1149,7 +1149,7 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
         double e[5] = {0, 0, 0, 0, 0};
         if (ei[t].on)
             admm_update<float>(sum_waves<float, 32, 32, kWavesBf16>(red, n, m), ei[t], (int64_t)se[t] * ldp + m0 + m,
-                               W, beta, V, Bst, q, store_b, est, ga, e);
+                               Wout, beta, V, Bst, q, store_b, est, ga, e);
         if (est) store_estimate<32>(e, m, se[t], gpart);
     }
 }
@@ -2240,16 +2240,29 @@ void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, 
 
 // Contraction over n in the BF16 split form: FP32 update (anch = false, on the
 // FP32 state) or the anchored FP64 update (anch = true).
+// Operands of a Gram-form sweep in the BF16 split form: G's BF16 pair over the
+// range p, the node operand (W, or d when anchored) read from win, the new W
+// (or d) written to wout.
+struct GramBf {
+    const __bf16 *hi, *lo;
+    int64_t lda;
+    float *win, *wout;
+};
+
 void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *active, int store_b, double *gpart,
-                     NodeCols ncl) {
+                     NodeCols ncl, const GramBf *gr = nullptr) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
-    const int64_t np = in.np, pp = in.pp;
+    const int64_t pp = in.pp;
     if (v < 0 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
     dim3 g((unsigned)(pp / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
-    const __bf16 *hi = in.Xh.as<__bf16>(), *lo = in.XhLo.as<__bf16>();
-    const int64_t lda = in.ldw, ldu = in.ldu, ldp = in.ldp;
     Sweep<float> s32 = sweep32(ctx);
+    const __bf16 *hi = gr ? gr->hi : in.Xh.as<__bf16>(), *lo = gr ? gr->lo : in.XhLo.as<__bf16>();
+    const int64_t lda = gr ? gr->lda : in.ldw, ldu = gr ? in.ldp : in.ldu, ldp = in.ldp;
+    const int64_t np = gr ? pp : in.np;   // the contraction's range
+    const float *U = gr ? gr->win : s32.U;
+    const float *wr = gr ? gr->win : s32.W;
+    float *ww = gr ? gr->wout : s32.W;
     Sweep<double> s64 = sweep64(ctx);
     const DevParams<float> q32 = dev_params<float>(in.mp);
     const DevParams<double> q64 = dev_params<double>(in.mp);
@@ -2259,16 +2272,16 @@ void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *act
     hipStream_t s = ctx->stream;
     if (v == 0) {
         if (anch)
-            hipLaunchKernelGGL(k_admm_xtu_anch_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, lda, s32.U, ldu, np, Za,
-                               Wa, s64.W, s64.beta, s64.V, s64.B, s32.W, codes, s64.c, active, q64, ldp, store_b,
+            hipLaunchKernelGGL(k_admm_xtu_anch_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, lda, U, ldu, np, Za,
+                               Wa, s64.W, s64.beta, s64.V, s64.B, ww, codes, s64.c, active, q64, ldp, store_b,
                                gpart, ga, ncl);
         else
-            hipLaunchKernelGGL(k_admm_xtu_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, lda, s32.U, ldu, np, s32.W,
+            hipLaunchKernelGGL(k_admm_xtu_bf16, g, dim3(64 * kWavesBf16), 0, s, hi, lo, lda, U, ldu, np, wr, ww,
                                s32.beta, s32.V, s32.B, codes, s32.c, active, q32, ldp, store_b, gpart, ga, ncl);
         return;
     }
 #define L0L2_XTUB(WM, WN, A)                                                                                    \
-    hipLaunchKernelGGL((k_admm_xtu_bf16_lds<WM, WN, A>), g, dim3(256), 0, s, hi, lo, lda, s32.U, ldu, np, s32.W,   \
+    hipLaunchKernelGGL((k_admm_xtu_bf16_lds<WM, WN, A>), g, dim3(256), 0, s, hi, lo, lda, U, ldu, np, wr, ww,     \
                        s32.beta, s32.V, s32.B, Za, Wa, s64.W, s64.beta, s64.V, s64.B, codes, s32.c, s64.c, active, \
                        q32, q64, ldp, store_b, gpart, ga, ncl)
     if (v == 1) {
@@ -2429,9 +2442,20 @@ __global__ void k_f64_to_f32(const double *__restrict__ src, int64_t lds, float 
     if (r < rows && j < cols) dst[r * ldd + j] = (float)src[r * lds + j];
 }
 
+__global__ void k_f64_to_bf16x2(const double *__restrict__ src, int64_t lds, __bf16 *__restrict__ hi,
+                                __bf16 *__restrict__ lo, int64_t ldd, int64_t rows, int64_t cols) {
+    const int64_t r = blockIdx.y, j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < rows && j < cols) {
+        const float x = (float)src[r * lds + j];
+        const __bf16 h = (__bf16)x;
+        hi[r * ldd + j] = h;
+        lo[r * ldd + j] = (__bf16)(x - (float)h);
+    }
+}
+
 bool gram_form(const l0l2_ctx *ctx) {
     const Instance &in = ctx->inst;
-    if (in.prec != L0L2_FP32 || ctx->bform == 1) return false;
+    if ((in.prec != L0L2_FP32 && in.prec != L0L2_BF16) || ctx->bform == 1) return false;
     if (ctx->bform == 2) return true;
     return 2 * in.pp <= 3 * in.np && in.pp <= 8192;
 }
@@ -2451,6 +2475,13 @@ void ensure_gram(l0l2_ctx *ctx) {
                                       in.G64.as<double>(), in.ldg64, pp, pp, np);
     hipLaunchKernelGGL(k_f64_to_f32, dim3((unsigned)((pp + 255) / 256), (unsigned)pp), dim3(256), 0, s,
                        in.G64.as<double>(), in.ldg64, in.G32.as<float>(), in.ldg32, pp, pp);
+    if (in.prec == L0L2_BF16) {
+        in.ldgb = ld_pad(pp, 2);
+        in.Ghi.ensure(sizeof(__bf16) * pp * in.ldgb);
+        in.Glo.ensure(sizeof(__bf16) * pp * in.ldgb);
+        hipLaunchKernelGGL(k_f64_to_bf16x2, dim3((unsigned)((pp + 255) / 256), (unsigned)pp), dim3(256), 0, s,
+                           in.G64.as<double>(), in.ldg64, in.Ghi.as<__bf16>(), in.Glo.as<__bf16>(), in.ldgb, pp, pp);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
     in.gram_built = true;
@@ -2518,6 +2549,20 @@ void sweep_once_anch_gram(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t activ
                     ws.codes.as<uint8_t>(), ws.active.as<int>(), dev_params<double>(in.mp), store_b ? 1 : 0,
                     gate ? ws.gpart.as<double>() : nullptr, gate_args(in), active_cols(ctx));
     prof_end(ctx, PROF_ADMM_XTU_F32, active);
+    HIPCHK(hipGetLastError());
+}
+
+// One Gram-form sweep in the BF16 split form (anch: the anchored FP64 update,
+// the node operand d).
+void sweep_once_bf16_gram(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate, bool anch, int t) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    const TileChoice &tc = tile_choice_bf16(ctx, Kp);
+    const GramBf gr{in.Ghi.as<__bf16>(), in.Glo.as<__bf16>(), in.ldgb, gram_in(ctx, t), gram_out(ctx, t)};
+    prof_begin(ctx, PROF_ADMM_XTU_BF16);
+    launch_xtu_bf16(tc.xtu, ctx, anch, Kp, ws.active.as<int>(), store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr,
+                    active_cols(ctx), &gr);
+    prof_end(ctx, PROF_ADMM_XTU_BF16, active);
     HIPCHK(hipGetLastError());
 }
 
@@ -2772,7 +2817,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     const int64_t cols = live_bucket(ctx, active, Kp);
     hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>(),
                        ws.ncount.as<int>(), ws.counter.as<int>());
-    const bool gram = (kind == SK_F32 || kind == SK_ANCH) && gram_form(ctx);
+    const bool gram = (kind == SK_F32 || kind == SK_BF16 || kind == SK_ANCH) && gram_form(ctx);
     if (gram) ensure_gram(ctx);
     if (kind == SK_ANCH) {
         if (gram) anchor_start_gram(ctx, Kp, cols);
@@ -2781,6 +2826,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     for (int t = 1; t <= n; ++t) {
         const bool last = t == n, gate = last && !force;
         if (gram && kind == SK_F32) sweep_once_gram(ctx, cols, last, active, gate, t);
+        else if (gram && in.prec == L0L2_BF16) sweep_once_bf16_gram(ctx, cols, last, active, gate, kind == SK_ANCH, t);
         else if (gram) sweep_once_anch_gram(ctx, cols, last, active, gate, t);
         else if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), cols, last, active, gate);
         else if (kind == SK_BF16) sweep_once_bf16(ctx, cols, last, active, gate, false);
@@ -2791,7 +2837,7 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     }
     // an odd Gram-form block leaves the latest W in the second buffer (a node that
     // retires keeps a stale W in it, which nothing reads again)
-    if (gram && kind == SK_F32 && (n & 1))
+    if (gram && (kind == SK_F32 || kind == SK_BF16) && (n & 1))
         HIPCHK(hipMemcpyAsync(ws.W.ptr, ws.W2.ptr, sizeof(float) * Kp * in.ldp, hipMemcpyDeviceToDevice, s));
     if (!force) {
         int rows = 32;
@@ -2832,7 +2878,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
         // settle the tile shapes first (the autotuner synchronises, and may grow
         // the split buffer, which drops the captured graphs)
         const bool bf = ctx->inst.prec == L0L2_BF16, f8 = ctx->inst.prec == L0L2_FP8;
-        if ((kind == SK_F32 || kind == SK_ANCH) && gram_form(ctx)) ensure_gram(ctx);   // not under capture
+        if ((kind == SK_F32 || kind == SK_BF16 || kind == SK_ANCH) && gram_form(ctx)) ensure_gram(ctx);   // not under capture
         if (kind == SK_F64 || kind == SK_ANCH) (void)tile_choice<double>(ctx, sweep64(ctx), cols);
         if (kind == SK_F32 || (kind == SK_ANCH && !bf && !f8)) (void)tile_choice<float>(ctx, sweep32(ctx), cols);
         if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);

@@ -108,8 +108,8 @@ struct Instance {
     int tuned_K = 0;                                      // node-batch size chosen by measurement (0: none yet)
     // Gram form of the b-update (FP32 mode): G = Xh^T Xh (pp x pp, symmetric),
     // b = (w - G w) / rho in one contraction; built on first use
-    DevBuf G64, G32;
-    int64_t ldg64 = 0, ldg32 = 0;
+    DevBuf G64, G32, Ghi, Glo;   // Ghi / Glo: BF16 mode, G as two BF16 terms (ld ldgb)
+    int64_t ldg64 = 0, ldg32 = 0, ldgb = 0;
     bool gram_built = false;
 };
 
