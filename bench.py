@@ -156,23 +156,32 @@ def batch_detail(path):
             "fista_iters_mean": round(float(fi.mean()), 2), "fista_iters_max": int(fi.max())}
 
 
+def kernel_source_digest():
+    """SHA-256 over the sources that define the kernels and their launches: every
+    header, and every HIP file that defines a kernel (host-only files, such as
+    the ABI wrappers and the server, do not count)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for fn in sorted(glob.glob(os.path.join(ROOT, "paper_2602_04551_amd", "csrc", "*"))):
+        if fn.endswith((".hip", ".hpp")):
+            with open(fn, "rb") as f:
+                text = f.read()
+            if fn.endswith(".hpp") or b"__global__" in text:
+                h.update(text)
+    return h.hexdigest()
+
+
 def measured_traffic(kname):
     """HBM bytes per launch of a contraction family from the committed counter
     summary (rocprofv3 FETCH_SIZE + WRITE_SIZE passes), or None when the kernel
     sources have changed since those counters were taken."""
-    import glob
-    import hashlib
     path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for fn in sorted(glob.glob(os.path.join(ROOT, "paper_2602_04551_amd", "csrc", "*"))):
-        if fn.endswith((".hip", ".hpp")):
-            with open(fn, "rb") as f:
-                h.update(f.read())
-    if h.hexdigest() != rec.get("source_digest"):
+    if kernel_source_digest() != rec.get("source_digest"):
         return None
     return rec["per_launch_bytes"].get(kname)
 

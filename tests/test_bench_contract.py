@@ -39,14 +39,21 @@ def test_counter_traffic_is_dropped_when_the_kernel_sources_change(tmp_path, mon
         {"source_digest": "not-the-current-sources", "per_launch_bytes": {"admm_xtu.f32": 123}}))
     csrc = tmp_path / "paper_2602_04551_amd" / "csrc"
     csrc.mkdir(parents=True)
-    (csrc / "a.hip").write_text("// kernel source\n")
+    (csrc / "a.hip").write_text("__global__ void k() {}\n")
+    (csrc / "b.hpp").write_text("// header\n")
+    (csrc / "host.hip").write_text("// host code only\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.measured_traffic("admm_xtu.f32") is None
     import hashlib
-    digest = hashlib.sha256(b"// kernel source\n").hexdigest()
+    digest = hashlib.sha256(b"__global__ void k() {}\n// header\n").hexdigest()
     (prof_dir / "c2_hbm_traffic.json").write_text(json.dumps(
         {"source_digest": digest, "per_launch_bytes": {"admm_xtu.f32": 123}}))
     assert bench.measured_traffic("admm_xtu.f32") == 123
+    # a host-only file may change; a kernel file or a header may not
+    (csrc / "host.hip").write_text("// host code, edited\n")
+    assert bench.measured_traffic("admm_xtu.f32") == 123
+    (csrc / "b.hpp").write_text("// header, edited\n")
+    assert bench.measured_traffic("admm_xtu.f32") is None
 
 
 def test_sweep_bytes_roofline_counts_operand_and_state_bytes():
