@@ -310,6 +310,41 @@ def test_gram_form_matches_folded_form_and_oracle(torch_cuda, cases, precision, 
         assert abs(lb1[k] - ref["lb"]) <= tol * abs(ref["primal"]), k
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("shape", ["wide", "tall"])
+def test_gram_form_with_unequal_padded_extents(torch_cuda, cases, orc, precision, shape):
+    """The Gram form where the padded p differs from the padded n: forced on a
+    wide design (n = 70, p = 150: 128 against 256 padded, where the default is
+    the folded operand) and by default on a tall one (n = 300, p = 100: 384
+    against 128).  The tile shapes are timed on the folded operands, whose
+    contraction over n has another length than the Gram form's over p."""
+    if shape == "wide":
+        inst, o, root = cases["wide"]
+    else:
+        inst = datagen.make_instance(300, 100, rho=0.3, k=5, seed=6, lambda0=0.01, lambda2=0.01)
+        o = orc.Oracle.from_instance(inst)
+        root = o.node_admm(None, tol=1e-7, max_iter=20000)
+    tol = 1e-7 if precision == "fp32" else 1e-6
+    K = 45
+    codes, beta0, v0 = random_nodes(inst.p, K, 41, root["beta"], root["v"])
+    res = {}
+    for form in ("folded", "gram"):
+        ctx = ctx_for(inst, precision)
+        ctx.set_bupdate_form(form)
+        r = ctx.solve_node_batch(codes, beta0, v0, tol_node=1e-8, max_iter=4000, check_every=7)
+        res[form] = {k: v.cpu().numpy() for k, v in r.items()}
+    f, g = res["folded"], res["gram"]
+    assert np.all(g["lb"] <= g["primal"])
+    conv = (f["status"] == 0) & (g["status"] == 0)
+    assert conv.sum() >= K - 2
+    assert np.max(np.abs(f["lb"] - g["lb"])[conv] / np.abs(f["primal"][conv])) < tol
+    for k in range(0, K, 9):
+        if not conv[k]:
+            continue
+        ref = o.node_admm(codes[k], beta0[k], v0[k], tol=1e-8, max_iter=4000, check_every=7)
+        assert abs(g["lb"][k] - ref["lb"]) <= tol * abs(ref["primal"]), k
+
+
 def test_fixed_shape_that_does_not_fit_the_batch_is_rejected(torch_cuda, cases):
     """Shape 7 tiles 64 nodes; a batch padded to 32 nodes cannot use it."""
     from paper_2602_04551_amd.binding import L0L2Error
