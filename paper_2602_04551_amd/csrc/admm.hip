@@ -2238,8 +2238,6 @@ void launch_xw_bf16(int v, l0l2_ctx *ctx, const float *B, float *U, int64_t Kp, 
                            ncl, (int64_t)0);
 }
 
-// Contraction over n in the BF16 split form: FP32 update (anch = false, on the
-// FP32 state) or the anchored FP64 update (anch = true).
 // Operands of a Gram-form sweep in the BF16 split form: G's BF16 pair over the
 // range p, the node operand (W, or d when anchored) read from win, the new W
 // (or d) written to wout.
@@ -2249,6 +2247,9 @@ struct GramBf {
     float *win, *wout;
 };
 
+// Contraction over n in the BF16 split form (over p with G when gr is given):
+// FP32 update (anch = false, on the FP32 state) or the anchored FP64 update
+// (anch = true).
 void launch_xtu_bf16(int v, l0l2_ctx *ctx, bool anch, int64_t Kp, const int *active, int store_b, double *gpart,
                      NodeCols ncl, const GramBf *gr = nullptr) {
     Instance &in = ctx->inst;
