@@ -253,7 +253,11 @@ class Context:
         return k.value, {32 << i: float(rates[i]) for i in range(n.value)}
 
     def set_bupdate_form(self, form="auto"):
-        self._check(lib.l0l2_set_bupdate_form(self._h, {"auto": 0, "folded": 1, "gram": 2}[form]))
+        """"auto" (Gram form where it applies), "folded" or "gram"."""
+        forms = {"auto": 0, "folded": 1, "gram": 2}
+        if form not in forms:
+            raise ValueError(f"b-update form must be one of {sorted(forms)}, not {form!r}")
+        self._check(lib.l0l2_set_bupdate_form(self._h, forms[form]))
 
     def set_tiles(self, xw_shape=-1, xtu_shape=-1):
         self._check(lib.l0l2_set_tiles(self._h, int(xw_shape), int(xtu_shape)))
