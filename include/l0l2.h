@@ -209,7 +209,8 @@ int l0l2_tune_batch_size(l0l2_ctx *ctx, int k_max, double frac, int *k_out, doub
 /* Estimated device bytes one instance of n x p needs at batch size K in the
  * given precision (instance copies, precompute peak, batch workspace, a
  * warm-start reserve of 16 K slots, and where the default b-update form is the
- * Gram form, G's copies and the second W buffer).  Used for admission; the pool of parent
+ * Gram form, G's copies and the second W buffer), plus a tenth and 16 MiB for
+ * the small buffers and captured graphs.  Used for admission; the pool of parent
  * states can outgrow its reserve on large trees. */
 size_t l0l2_footprint_bytes(int64_t n, int64_t p, int precision, int K);
 

@@ -48,7 +48,9 @@ size_t footprint_bytes(int64_t n, int64_t p, int prec, int K) {
         inst += (prec == L0L2_BF16 ? 16.0 : 12.0) * pp * pp;
         ws += 4.0 * Kp * pp;
     }
-    return (size_t)(inst + std::max(transient, ws + bnb));
+    // the terms above are the large buffers; a tenth more and 16 MiB cover the
+    // small ones (gap-check partials, lists, refinement staging, captured graphs)
+    return (size_t)(1.1 * (inst + std::max(transient, ws + bnb)) + 16.0 * 1048576.0);
 }
 
 }  // namespace l0l2

@@ -90,3 +90,31 @@ def test_oversized_request_is_rejected(instances):
     with pytest.raises(L0L2Error):
         srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M)
     srv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp8"])
+def test_footprint_estimate_covers_a_solve(instances, precision):
+    """The admission estimate bounds what a whole solve holds on the device: the
+    free device memory drops by at most l0l2_footprint_bytes between before the
+    context exists and the end of a BnB solve on n = p = 1000 with K = 256
+    (instance copies, batch workspace, the Gram form's G where it applies,
+    captured graphs, the warm-start pool)."""
+    import torch
+    from paper_2602_04551_amd.binding import Context, lib
+    inst = datagen.config_instance("C2", seed=0)
+    code = {"fp64": 0, "fp32": 1, "bf16": 2, "fp8": 3}[precision]
+    est = lib.l0l2_footprint_bytes(inst.n, inst.p, code, 256)
+    torch.zeros(1, device="cuda")   # the runtime's own first-use memory is not the solve's
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free0 = torch.cuda.mem_get_info()[0]
+    c = Context(0)
+    c.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=precision)
+    r = c.bnb_solve(K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    c.close()
+    assert r["status"] == 0
+    print(f"{precision}: used {used / 2**20:.1f} MiB, estimate {est / 2**20:.1f} MiB")
+    assert used <= est
