@@ -1,17 +1,21 @@
 """Benchmark of the batched node-relaxation hot path on one MI355X.
 
-Workload: n = p = 1000, Toeplitz rho = 0.5, k = 10 unit spikes, SNR = 5,
-lambda0 = 0.005, lambda2 = 0.01, node batches of 256, FP32 ADMM with FP64 bounds
-and FP64 incumbent objective (the "mixed" path); the FP64 GPU path is measured
-beside it.  One step = one pass of the whole hot path over one batch:
-warm-start assembly, ADMM to the node tolerance with the FP64 gap checks and
-rigorous bounds, rounding and branching, FP64 incumbent refinement, and the
-host's prune / branch decisions.  Inputs are synthetic and resident on the
-GPU before timing starts.
+Headline workload (the batching configuration, the largest that the benchmark
+runs on one GPU at full size): n = p = 5000, Toeplitz rho = 0.3, k = 20 unit
+spikes, SNR = 3, lambda0 = 0.005, lambda2 = 0.01, node batches of 4096 whose
+nodes keep f ~ U{50..p} free coordinates (|F1| ~ U{0..20}, the rest fixed to
+zero), warm-started from the root relaxation.  The mixed path multiplies with
+X in BF16 (FP32 accumulation, FP32 state, FP64 bounds and incumbent
+objective); the FP32 and FP64 GPU paths run the same batches.  One step = one
+pass of the whole hot path over one batch: warm-start assembly, ADMM to the
+node tolerance with the FP64 gap checks and rigorous bounds, rounding and
+branching, FP64 incumbent refinement, and the host's prune / branch decisions.
+Inputs are synthetic and resident on the GPU before timing starts.
 
-Prints one JSON line (rank 0).  `value` = node relaxations per second of the
-mixed path.  Time-to-certified-optimum of the full branch and bound on the
-same instance is reported for both paths.
+Also in the same JSON line: time-to-certified-optimum of the full branch and
+bound on the n = p = 1000 instance in every precision, node batches of the
+n = 1000, p = 50000 (FP8 storage) workload, and the CPU oracle timed on a
+32-node sample of the headline batch.
 """
 from __future__ import annotations
 
@@ -35,54 +39,70 @@ METRIC = "node relaxations/s + time-to-certified-optimum, mixed vs FP64 GPU path
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--K", type=int, default=256)
-    ap.add_argument("--no-ttco", action="store_true")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--K", type=int, default=4096, help="nodes per batch of the headline workload")
+    ap.add_argument("--no-ttco", action="store_true", help="skip the n = p = 1000 branch-and-bound runs")
+    ap.add_argument("--no-highdim", action="store_true", help="skip the n = 1000, p = 50000 node batches")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--only-mixed", action="store_true", help="skip the FP64 path (short profiled runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-sample", type=int, default=32, help="nodes of the headline batch the oracle solves")
+    ap.add_argument("--only-mixed", action="store_true", help="headline precision only (short profiled runs)")
     ap.add_argument("--batching", action="store_true",
-                    help="n = p = 5000 node batches of 512..4096 (free sets U[50, p]), BF16 split vs FP32")
+                    help="n = p = 5000 node batches of 512..4096 (free sets U[50, p]), BF16 vs FP32")
     ap.add_argument("--serve", action="store_true",
                     help="Poisson stream of independent instances through the server: p50/p99 TTCO")
     ap.add_argument("--serve-requests", type=int, default=16)
     ap.add_argument("--serve-concurrent", type=int, default=8, help="instances in flight at once")
     ap.add_argument("--highdim", action="store_true",
-                    help="n = 1000, p = 50000 node batches of 256 and 1024: FP32 and BF16 split vs FP64")
+                    help="n = 1000, p = 50000 node batches of 256 and 1024: FP8, BF16, FP32 vs FP64")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="first dispatch one device copy of 256 MiB, the reference for HBM counter scaling")
     return ap.parse_args()
 
 
-class Path:
-    """One precision of the hot path on the workload's instance and node batch."""
+HEADLINE = ("C3", "n=p=5000 Toeplitz rho=0.3 k=20 SNR=3 lambda0=0.005 lambda2=0.01, node batches of {K} "
+                  "(free sets U{{50..p}}, |F1| U{{0..20}}, warm-started from the root), X products in BF16 "
+                  "with FP32 accumulation and FP32 state, FP64 bounds and incumbent objective")
 
-    def __init__(self, inst, precision, K, seed=0):
+
+def fp64_root(inst, tol=1e-9, max_iter=20000):
+    """Root relaxation solved once in FP64 on the GPU (the warm start every precision
+    shares), its rounded incumbent refined in FP64: (beta, v, UB, sweeps)."""
+    from paper_2602_04551_amd.binding import Context
+    ctx = Context(0)
+    ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp64")
+    p = inst.p
+    z = np.zeros((1, p), np.uint8)
+    r = ctx.solve_node_batch(z, tol_node=tol, max_iter=max_iter)
+    obj, _, _ = ctx.refine_incumbent(ctx.round_branch(z, r["beta"])["support"], r["beta"])
+    out = (r["beta"][0].cpu().numpy(), r["v"][0].cpu().numpy(), float(obj[0].item()), int(r["iters"][0].item()))
+    ctx.close()
+    return out
+
+
+class Path:
+    """One precision of the hot path on one instance's node batch (same codes and
+    the same FP64 root warm start for every precision)."""
+
+    def __init__(self, inst, precision, codes, root):
         import torch
-        from paper_2602_04551_amd import datagen
         from paper_2602_04551_amd.binding import Context
         self.torch = torch
-        self.inst, self.precision, self.K = inst, precision, K
+        self.inst, self.precision = inst, precision
+        self.K = codes.shape[0]
         self.ctx = Context(0)
         t0 = time.perf_counter()
         self.ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, rho=1.0, precision=precision)
         torch.cuda.synchronize()
         self.set_data_s = time.perf_counter() - t0
-        p = inst.p
-        # root relaxation: warm start of every node of the batch
-        root = self.ctx.solve_node_batch(np.zeros((1, p), np.uint8), tol_node=1e-6, max_iter=10000)
-        rb = self.ctx.root_beta = root["beta"]
-        obj, _, _ = self.ctx.refine_incumbent(self.ctx.round_branch(np.zeros((1, p), np.uint8), rb)["support"], rb)
-        self.ub = float(obj[0].item())
-        bh = rb[0].double().cpu().numpy()
-        cand = np.lexsort((np.arange(p), -np.abs(bh)))[:64]
-        codes = datagen.frontier_codes(p, K, cand, seed=seed)
-        dev = self.ctx.torch_device
-        self.codes = torch.from_numpy(codes).to(dev)
-        self.beta0 = root["beta"].expand(K, p).contiguous()
-        self.v0 = root["v"].expand(K, p).contiguous()
-        self.codes_np, self.beta0_np, self.v0_np = codes, self.beta0.double().cpu().numpy(), self.v0.double().cpu().numpy()
+        rb, rv, self.ub, _ = root
+        dev, dt = self.ctx.torch_device, self.ctx.state_dtype
+        self.codes = torch.from_numpy(np.ascontiguousarray(codes)).to(dev)
+        self.beta0 = torch.from_numpy(rb).to(dev, dt).expand(self.K, inst.p).contiguous()
+        self.v0 = torch.from_numpy(rv).to(dev, dt).expand(self.K, inst.p).contiguous()
+        torch.cuda.synchronize()
+        self.step()   # settles the tile shapes and captured graphs outside any timed region
         torch.cuda.synchronize()
 
     def step(self):
@@ -91,7 +111,7 @@ class Path:
         res = c.solve_node_batch(self.codes, self.beta0, self.v0, tol_node=1e-6, max_iter=2000, check_every=10)
         rb = c.round_branch(self.codes, res["beta"])
         obj, _, fit = c.refine_incumbent(rb["support"], res["beta"])
-        self.detail = (res["iters"], rb["support_size"], fit)
+        self.detail = (res["iters"], rb["support_size"], fit, res["status"])
         lb = res["lb"].cpu().numpy()
         ub = obj.cpu().numpy()
         bj = rb["branch_j"].cpu().numpy()
@@ -102,56 +122,106 @@ class Path:
         branched = int(np.sum((lb < thr) & (bj >= 0)))
         return iters, pruned, branched
 
+    def close(self):
+        self.ctx.close()
 
-def _oracle_nodes(args):
-    """Worker of the CPU baseline: the oracle as it stands on a contiguous run of
-    the batch's nodes (node solve, rounding, branching, FISTA) until `seconds`."""
-    X, y, l0, l2, M, codes, beta0, v0, seconds = args
-    import oracle
-    o = oracle.Oracle(X, y, l0, l2, M, 1.0)
+
+# --- CPU baseline: the oracle on a sample of the headline batch --------------
+
+_CPU = None   # (oracle instance, codes, root beta, root v), inherited by the forked workers
+
+
+def _cpu_nodes(args):
+    """One worker: the oracle as it stands on its share of the sample (node solve,
+    rounding, branching, refinement), until `seconds` of work have passed."""
+    idx, seconds = args
+    o, codes, rb, rv = _CPU
     t0 = time.perf_counter()
-    done = 0
-    for k in range(codes.shape[0]):
-        r = o.node_admm(codes[k], beta0[k], v0[k], tol=1e-6, max_iter=2000, check_every=10)
+    done = sweeps = 0
+    for k in idx:
+        r = o.node_admm(codes[k], rb, rv, tol=1e-6, max_iter=2000, check_every=10)
         mask, _ = o.support(codes[k], r["beta"])
         o.branch(codes[k], r["beta"])
         o.fista(mask, r["beta"])
         done += 1
+        sweeps += r["iters"]
         if time.perf_counter() - t0 >= seconds:
             break
-    return done, time.perf_counter() - t0
+    return done, sweeps, time.perf_counter() - t0
 
 
-def cpu_baseline(path, seconds):
-    """The CPU oracle as it stands on the nodes of the same batch (same codes,
-    same warm starts), node-parallel: the batch is split into contiguous runs,
-    one per worker process (each a single-threaded oracle), every worker stops
-    after `seconds` of work."""
+def _cpu_baseline_proc(cfg, K, sample, rb, rv, seconds, workers, conn):
+    """Runs in a spawned process that never touches the GPU: builds the oracle's
+    instance once (its once-per-tree factor from numpy's LAPACK, which the timing
+    leaves out), then forks `workers` single-threaded oracle processes that
+    share it and solve the sampled nodes."""
+    global _CPU
     import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-    workers = max(1, min(16, os.cpu_count() or 1, path.K))
-    bounds = np.linspace(0, path.K, workers + 1).astype(int)
-    jobs = [(path.inst.X, path.inst.y, path.inst.lambda0, path.inst.lambda2, path.inst.M,
-             path.codes_np[a:b], path.beta0_np[a:b], path.v0_np[a:b], seconds)
-            for a, b in zip(bounds[:-1], bounds[1:])]
+    import oracle
+    from paper_2602_04551_amd import datagen
+    inst = datagen.config_instance(cfg, seed=0)
+    codes = datagen.node_batch_codes(inst.p, K, seed=K)
     t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        res = list(ex.map(_oracle_nodes, jobs))
-    wall = time.perf_counter() - t0
-    done = sum(d for d, _ in res)
-    busy = max(t for _, t in res)
-    per_core = sum(d for d, _ in res) / sum(t for _, t in res)
-    return dict(value=done / busy, unit="node relaxations/s", cores=workers, kind="oracle",
-                per_core_value=round(per_core, 3),
-                sample=f"{done} of the {path.K} nodes of the timed batch (same codes and warm starts), "
-                       f"split over {workers} single-threaded FP64 oracle processes, {busy:.1f} s of work "
-                       f"each at most ({wall:.1f} s wall with process start-up)")
+    o = oracle.Oracle.from_instance(inst, factor="numpy")
+    t_factor = time.perf_counter() - t0
+    slots = np.linspace(0, K - 1, sample).round().astype(int)
+    _CPU = (o, codes, rb, rv)
+    shares = [list(slots[i::workers]) for i in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_cpu_nodes, [(s, seconds) for s in shares if s])
+    conn.send({"res": res, "wall": time.perf_counter() - t0, "factor_s": t_factor})
+    conn.close()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, K, root, seconds, sample):
+    """The CPU oracle on `sample` nodes spread over the headline batch (same codes,
+    same warm start), node-parallel over the host's cores."""
+    import multiprocessing as mp
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    # at most 16 worker processes: the share of host CPUs that comes with one GPU here
+    workers = max(1, min(avail, 16, sample))
+    ctx = mp.get_context("spawn")
+    a, b = ctx.Pipe(duplex=False)
+    pr = ctx.Process(target=_cpu_baseline_proc, args=(cfg, K, sample, root[0], root[1], seconds, workers, b))
+    pr.start()
+    msg = a.recv()
+    pr.join()
+    res = msg["res"]
+    done = sum(d for d, _, _ in res)
+    sweeps = sum(s for _, s, _ in res)
+    busy = max(t for _, _, t in res)
+    per_core = done / sum(t for _, _, t in res)
+    return dict(value=round(done / busy, 3), unit="node relaxations/s", cores=len(res), kind="oracle",
+                per_core_value=round(per_core, 4), cpu_model=cpu_model(), nproc=nproc, affinity=avail,
+                sample=f"{done} of {sample} nodes spread over the {K}-node batch (same codes, same FP64 root "
+                       f"warm start), {sweeps} ADMM sweeps in all, each node solved to the 1e-6 gap, rounded, "
+                       f"branched and refined by the single-threaded FP64 oracle; {len(res)} worker processes "
+                       f"(at most 16: the host CPU share of one GPU) ran for {busy:.1f} s at most; the oracle's "
+                       f"once-per-tree factor (X^T X + rho I)^-1 came from numpy in {msg['factor_s']:.1f} s, "
+                       f"not timed")
 
 
 def batch_detail(path):
-    """Per-node work of the last step: ADMM sweeps, support sizes and FISTA iterations."""
-    sw, ss, fi = (t.cpu().numpy().astype(np.float64) for t in path.detail)
+    """Per-node work of the last step: ADMM sweeps, support sizes, refinement iterations."""
+    sw, ss, fi, st = (t.cpu().numpy().astype(np.float64) for t in path.detail)
     return {"admm_sweeps_mean": round(float(sw.mean()), 2), "admm_sweeps_max": int(sw.max()),
+            "converged": int((st == 0).sum()), "nodes": int(len(st)),
             "support_mean": round(float(ss.mean()), 2), "support_max": int(ss.max()),
             "fista_iters_mean": round(float(fi.mean()), 2), "fista_iters_max": int(fi.max())}
 
@@ -172,34 +242,37 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kname):
-    """HBM bytes per launch of a contraction family from the committed counter
-    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE passes), or None when the kernel
-    sources have changed since those counters were taken."""
-    path = os.path.join(ROOT, "profiles", "c2_hbm_traffic.json")
+TRAFFIC_FILE = "hbm_traffic.json"
+
+
+def measured_traffic(kname, workload):
+    """HBM bytes per launch of a contraction family on a workload from the
+    committed counter summary (rocprofv3 FETCH_SIZE + WRITE_SIZE passes), or None
+    when there is none or the kernel sources have changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        rec = json.load(f)
-    if kernel_source_digest() != rec.get("source_digest"):
+        rec = json.load(f).get(workload)
+    if not rec or kernel_source_digest() != rec.get("source_digest"):
         return None
     return rec["per_launch_bytes"].get(kname)
 
 
-def roofline(prof, n, p, traffic_from_counters=False):
+def roofline(prof, n, p, workload=None):
     """Dominant sweep contraction by measured time; achieved = algorithmic flops
-    (2 n p per active node-iteration) over its summed launch durations.  The
-    counter summary covers the mixed FP32 path of the n = p = 1000 node batch
-    only (traffic_from_counters); elsewhere traffic is None."""
+    (2 n p per active node-iteration; the Gram form's 2 p^2 equals it at n = p)
+    over its summed launch durations.  traffic: the counter figure for that
+    kernel on `workload` when one is committed for the current sources."""
     sweep = [k for k in prof if k.startswith(("gemm_xw", "admm_xtu")) and prof[k][0] > 0]
     kname = max(sweep, key=lambda k: prof[k][1])
     launches, ms, units = prof[kname]
     prec = kname.split(".")[1]
     achieved = 2.0 * n * p * units / (ms * 1e-3) / 1e12
-    traffic = measured_traffic(kname) if traffic_from_counters and prec == "f32" else None
+    traffic = measured_traffic(kname, workload) if workload else None
     roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK[prec], "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[prec], 4), "traffic": traffic,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 counters, profiles/c2_hbm_traffic.json)",
+            "traffic_unit": f"HBM bytes per launch (rocprofv3 counters, profiles/{TRAFFIC_FILE})",
             "kernel": kname,
             "launches": launches, "avg_us": round(1e3 * ms / max(launches, 1), 3),
             "flops_per_launch": round(2.0 * n * p * units / max(launches, 1)),
@@ -255,55 +328,54 @@ def sweep_bytes_roofline(prof, n, p, prec):
             "node_iterations": units, "kernels": ["gemm_xw." + fam, "admm_xtu." + fam]}
 
 
-def node_batch_runs(inst, Ks, precs, workload, label):
-    """Node-batch throughput on one instance: each node keeps f ~ U{50..p} free coordinates,
-    |F1| ~ U{0..20}, the rest fixed to zero, warm-started from the root; one batch per K and
-    precision, timed after a warm-up solve of the same batch (tiles and graphs settled)."""
+def node_batch_run(inst, prec, K, root, profile=True):
+    """One node batch of the workload (free sets U{50..p}, |F1| U{0..20}, seed K),
+    warm-started from the shared FP64 root: one untimed solve (tiles, graphs),
+    one timed, one with per-launch HIP-event timing."""
     import torch
     from paper_2602_04551_amd import datagen
     from paper_2602_04551_amd.binding import Context
     n, p = inst.n, inst.p
+    ctx = Context(0)
+    t0 = time.perf_counter()
+    ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
+    torch.cuda.synchronize()
+    sd = time.perf_counter() - t0
+    codes = torch.from_numpy(datagen.node_batch_codes(p, K, seed=K)).to(ctx.torch_device)
+    b0 = torch.from_numpy(root[0]).to(ctx.torch_device, ctx.state_dtype).expand(K, p).contiguous()
+    v0 = torch.from_numpy(root[1]).to(ctx.torch_device, ctx.state_dtype).expand(K, p).contiguous()
+    ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)     # warm-up, tiles, graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = r["iters"].cpu().numpy()
+    run = {"value": round(K / dt, 2), "seconds": round(dt, 4), "iters_mean": round(float(it.mean()), 2),
+           "iters_max": int(it.max()), "converged": int((r["status"] == 0).sum().item()),
+           "set_data_s": round(sd, 3)}
+    if profile:
+        ctx.profile_enable(True)
+        ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
+        prof = {k: ctx.profile_query(k) for k in ctx.KERNELS}
+        ctx.profile_enable(False)
+        run["roofline"], run["kernels"] = roofline(prof, n, p)
+        run["roofline_hbm"] = sweep_bytes_roofline(prof, n, p, prec)
+    ctx.close()
+    print(json.dumps({f"{prec}_K{K}": run["value"]}), file=sys.stderr, flush=True)
+    return run
+
+
+def node_batch_runs(inst, Ks, precs, workload, label):
+    """Node-batch throughput on one instance, one batch per K and precision."""
     out = {"metric": f"node relaxations/s ({label} workload)", "unit": "node relaxations/s",
            "config": {"workload": workload, "node_tol": 1e-6,
                       "warm_start": "root relaxation solved once in FP64 to a 1e-9 gap, shared by all precisions"},
            "runs": {}}
-    # one warm start for every precision: the root, solved tightly in FP64
-    rc = Context(0)
-    rc.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp64")
-    root = rc.solve_node_batch(np.zeros((1, p), np.uint8), tol_node=1e-9, max_iter=20000)
-    root = {k: root[k].cpu() for k in ("beta", "v")}
-    rc.close()
+    root = fp64_root(inst)
     for prec in precs:
-        ctx = Context(0)
-        t0 = time.perf_counter()
-        ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
-        torch.cuda.synchronize()
-        sd = time.perf_counter() - t0
-        print(json.dumps({"set_data": prec, "seconds": round(sd, 3)}), file=sys.stderr, flush=True)
         for K in Ks:
-            codes = torch.from_numpy(datagen.node_batch_codes(p, K, seed=K)).to(ctx.torch_device)
-            b0 = root["beta"].to(ctx.torch_device, ctx.state_dtype).expand(K, p).contiguous()
-            v0 = root["v"].to(ctx.torch_device, ctx.state_dtype).expand(K, p).contiguous()
-            ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)     # warm-up, tiles, graphs
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            r = ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
-            ctx.profile_enable(True)
-            ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
-            prof = {k: ctx.profile_query(k) for k in ctx.KERNELS}
-            ctx.profile_enable(False)
-            roof, kernels = roofline(prof, n, p)
-            roof_hbm = sweep_bytes_roofline(prof, n, p, prec)
-            it = r["iters"].cpu().numpy()
-            out["runs"][f"{prec}_K{K}"] = {"value": round(K / dt, 2), "seconds": round(dt, 4),
-                                           "iters_mean": float(it.mean()), "iters_max": int(it.max()),
-                                           "converged": int((r["status"] == 0).sum().item()),
-                                           "roofline": roof, "roofline_hbm": roof_hbm, "kernels": kernels,
-                                           "set_data_s": round(sd, 3)}
-            print(json.dumps({f"{prec}_K{K}": out["runs"][f"{prec}_K{K}"]["value"]}), file=sys.stderr, flush=True)
-        ctx.close()
+            out["runs"][f"{prec}_K{K}"] = node_batch_run(inst, prec, K, root)
     print(json.dumps(out), flush=True)
 
 
@@ -378,17 +450,16 @@ def serve_main(args):
 
 def main():
     args = parse()
-    if args.batching or args.serve or args.highdim:
-        if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-            print("bench.py: this build runs on exactly one GPU", file=sys.stderr)
-            sys.exit(2)
-        if args.batching:
-            return batching_main(args)
-        return highdim_main(args) if args.highdim else serve_main(args)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.batching:
+        return batching_main(args)
+    if args.highdim:
+        return highdim_main(args)
+    if args.serve:
+        return serve_main(args)
     import torch
     from paper_2602_04551_amd import datagen
 
@@ -400,60 +471,82 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    inst = datagen.config_instance("C2", seed=0)
+    cfg, wl = HEADLINE
+    inst = datagen.config_instance(cfg, seed=0)
     n, p, K = inst.n, inst.p, args.K
-    mixed = Path(inst, "fp32", K)
+    codes = datagen.node_batch_codes(p, K, seed=K)
+    root = fp64_root(inst)
+    print(json.dumps({"root_sweeps": root[3], "root_ub": root[2]}), file=sys.stderr, flush=True)
+    mixed = Path(inst, "bf16", codes, root)
     dt, its, prof = run_path(mixed, args.steps, args.warmup)
     ms_per_step = 1e3 * dt / args.steps
     value = K * args.steps / dt
-
-    roof, kernels = roofline(prof, n, p, traffic_from_counters=True)
-    others = {}
-    if not args.only_mixed:
-        for prec in ("fp64", "bf16", "fp8"):
-            path = Path(inst, prec, K)
-            steps_o = max(2, args.steps // 2)
-            dt_o, _, prof_o = run_path(path, steps_o, 1)
-            roof_o, kernels_o = roofline(prof_o, n, p)
-            others[prec] = (path, dt_o, steps_o, roof_o, kernels_o)
+    roof, kernels = roofline(prof, n, p, workload=cfg.lower())
     out = {"metric": METRIC, "value": round(value, 2), "unit": "node relaxations/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
            "data": "synthetic",
-           "config": {"workload": "n=1000 p=1000 Toeplitz rho=0.5 k=10 SNR=5 lambda0=0.005 lambda2=0.01, "
-                                  "node batches of 256, FP32 ADMM + FP64 bounds",
-                      "n": n, "p": p, "K": K, "node_tol": 1e-6, "check_every": 10, "rho": 1.0,
-                      "b_update": "Gram form b = (w - G w) / rho, G = Xh^T Xh (FP32 mode, p <= 1.5 n): one "
-                                  "contraction of 2 p^2 = 2 n p flops per node-sweep here",
-                      "batch": "frontier nodes: 1-16 fixings among the 64 largest root coordinates, "
-                               "warm-started from the root"},
+           "config": {"workload": wl.format(K=K), "n": n, "p": p, "K": K, "node_tol": 1e-6, "check_every": 10,
+                      "rho": 1.0, "root_warm_start": f"FP64 root relaxation to a 1e-9 gap ({root[3]} sweeps), "
+                                                     "shared by every precision",
+                      "b_update": "Gram form b = (w - G w) / rho, G = Xh^T Xh (p <= 1.5 n): one contraction of "
+                                  "2 p^2 = 2 n p flops per node-sweep here"},
            "roofline": roof,
+           "roofline_hbm": sweep_bytes_roofline(prof, n, p, "bf16"),
            "kernels": kernels,
            "batch_detail": batch_detail(mixed),
-           "set_data_s": {"fp32": round(mixed.set_data_s, 4)}}
-    for prec, (path, dt_o, steps_o, roof_o, kernels_o) in others.items():
-        out[prec + "_path"] = {"value": round(K * steps_o / dt_o, 2), "unit": "node relaxations/s",
-                               "ms_per_step": round(1e3 * dt_o / steps_o, 3), "roofline": roof_o,
-                               "kernels": kernels_o}
-        out["set_data_s"][prec] = round(path.set_data_s, 4)
+           "set_data_s": {"bf16": round(mixed.set_data_s, 4)}}
+    mixed.close()
+    print(json.dumps({"bf16": out["value"]}), file=sys.stderr, flush=True)
+    if not args.only_mixed:
+        for prec, steps_o in (("fp32", max(2, args.steps // 2)), ("fp64", max(2, args.steps // 4))):
+            path = Path(inst, prec, codes, root)
+            dt_o, _, prof_o = run_path(path, steps_o, 1)
+            roof_o, kernels_o = roofline(prof_o, n, p)
+            out[prec + "_path"] = {"value": round(K * steps_o / dt_o, 2), "unit": "node relaxations/s",
+                                   "steps": steps_o, "ms_per_step": round(1e3 * dt_o / steps_o, 3),
+                                   "roofline": roof_o, "kernels": kernels_o, "batch_detail": batch_detail(path)}
+            out["set_data_s"][prec] = round(path.set_data_s, 4)
+            path.close()
+            print(json.dumps({prec: out[prec + "_path"]["value"]}), file=sys.stderr, flush=True)
+        out["mixed_vs_fp64"] = round(out["value"] / out["fp64_path"]["value"], 3)
 
     if not args.no_ttco:
+        # time to certified optimum of the whole branch and bound, n = p = 1000, every precision
+        from paper_2602_04551_amd.binding import Context
+        inst2 = datagen.config_instance("C2", seed=0)
         tt = {}
-        for name, path in [("mixed_fp32", mixed)] + [(k, v[0]) for k, v in others.items()]:
+        for prec in ("bf16", "fp32", "fp64", "fp8"):
+            ctx = Context(0)
+            t0 = time.perf_counter()
+            ctx.set_data(inst2.X, inst2.y, inst2.lambda0, inst2.lambda2, inst2.M, precision=prec)
+            torch.cuda.synchronize()
+            sd = time.perf_counter() - t0
+            ctx.bnb_solve(K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000)   # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = path.ctx.bnb_solve(K=K, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000)
+            r = ctx.bnb_solve(K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000)
             torch.cuda.synchronize()
-            tt[name] = {"seconds": round(time.perf_counter() - t0, 4), "nodes": r["nodes_solved"],
-                        "batches": r["batches"], "certified": r["certified"], "status": r["status"],
-                        "support": [int(s) for s in r["support"]]}
-        out["ttco"] = tt
-    if not args.no_ttco:
-        # the autotuner's batch axis on this instance (after the timed work; the workload keeps K = 256)
-        k_t, rates = mixed.ctx.tune_batch_size(k_max=1024, frac=0.9)
-        out["batch_tuning"] = {"chosen_K": k_t, "node_sweeps_per_s": {str(k): round(v) for k, v in rates.items()}}
+            tt[prec] = {"seconds": round(time.perf_counter() - t0, 4), "set_data_s": round(sd, 4),
+                        "nodes": r["nodes_solved"], "batches": r["batches"], "certified": r["certified"],
+                        "lb": r["lb"], "status": r["status"], "support": [int(s) for s in r["support"]]}
+            ctx.close()
+        out["ttco_n1000"] = {"workload": "n=p=1000 Toeplitz rho=0.5 k=10 SNR=5 lambda0=0.005 lambda2=0.01, "
+                                         "best-first branch and bound with batches of 256 to certification "
+                                         "(gap 0, eps_prune 2e-6), after one untimed solve",
+                             "runs": tt,
+                             "mixed_vs_fp64": round(tt["fp64"]["seconds"] / tt["bf16"]["seconds"], 3)}
+        print(json.dumps({"ttco": {k: v["seconds"] for k, v in tt.items()}}), file=sys.stderr, flush=True)
+    if not args.no_highdim:
+        inst5 = datagen.config_instance("C5", seed=0)
+        root5 = fp64_root(inst5)
+        runs = {prec: node_batch_run(inst5, prec, 1024, root5) for prec in ("fp8", "bf16", "fp32", "fp64")}
+        out["highdim_n1000_p50000"] = {
+            "workload": "n=1000 p=50000 constant correlation 0.2 k=25 SNR=3 lambda0=0.002 lambda2=0.005, node "
+                        "batches of 1024 (free sets U{50..p}, |F1| U{0..20}) from the FP64 root",
+            "runs": runs, "fp8_vs_fp64": round(runs["fp8"]["value"] / runs["fp64"]["value"], 3)}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(mixed, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfg, K, root, args.cpu_seconds, args.cpu_sample)
     print(json.dumps(out), flush=True)
 
 

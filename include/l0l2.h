@@ -174,7 +174,9 @@ typedef struct {
 typedef struct {
     double ub;             /* incumbent objective from the node refinements */
     double certified;      /* F of the incumbent support solved exactly */
-    double lb;             /* global lower bound at exit (= ub when exhausted) */
+    double lb;             /* global lower bound at exit: the smallest bound over the closed
+                              (pruned or leaf) and the open nodes, at most ub; when the tree
+                              is exhausted it is at least ub (1 - eps_prune) */
     int64_t nodes_solved, nodes_pruned, trace_len, batches;
     double seconds;
     int status;            /* 0 exhausted (certified), 1 node budget, 2 gap_tol, 3 time limit */

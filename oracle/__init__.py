@@ -21,8 +21,10 @@ FREE, FIX0, FIX1 = 0, 1, 2
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (plain -O2, no fast-math, no FMA contraction)."""
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
-                               SRC, "-o", LIB_PATH, "-lm"])
+                               SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB_PATH)   # a process that has the old library loaded keeps it
     return LIB_PATH
 
 
@@ -63,6 +65,7 @@ def lib():
             ("orc_prox", d, [d, i, d, d, d, d]), ("orc_h", d, [d, d, d, d]),
             ("orc_nu", d, [d, i, d, d, d]), ("orc_z", d, [d, i, d, d, d]),
             ("orc_create", vp, [_D, _D, i64, i64, d, d, d, d]), ("orc_free", None, [vp]),
+            ("orc_create_factored", vp, [_D, _D, i64, i64, d, d, d, d, _D]),
             ("orc_c", _D, [vp]),
             ("orc_b_update", None, [vp, _D, _D]),
             ("orc_admm_sweep", None, [vp, _U8, _D, _D, _D]),
@@ -117,20 +120,35 @@ def z(beta, code, l0, l2, M):
 class Oracle:
     """One problem instance held by the oracle (X, y, lambda0, lambda2, M, rho)."""
 
-    def __init__(self, X, y, lambda0, lambda2, M, rho=1.0):
+    def __init__(self, X, y, lambda0, lambda2, M, rho=1.0, factor=None):
+        """factor=None: the oracle forms the once-per-tree factor itself (plain C
+        loops, O(n p min(n, p)) single-threaded).  factor="numpy": the factor is
+        taken from numpy's LAPACK routines instead (for the large instances;
+        only that precompute differs)."""
         X = np.asfortranarray(X, dtype=np.float64)
         y = np.ascontiguousarray(y, dtype=np.float64)
         self.n, self.p = X.shape
         self.lambda0, self.lambda2, self.M, self.rho = float(lambda0), float(lambda2), float(M), float(rho)
         self.X, self.y = X, y
-        self._h = lib().orc_create(_dp(X), _dp(y), self.n, self.p, self.lambda0, self.lambda2,
-                                   self.M, self.rho)
+        if factor is None:
+            self._h = lib().orc_create(_dp(X), _dp(y), self.n, self.p, self.lambda0, self.lambda2,
+                                       self.M, self.rho)
+        elif factor == "numpy":
+            if self.n >= self.p:
+                A = X.T @ X + self.rho * np.eye(self.p)
+                F = np.asfortranarray(np.linalg.inv(A))
+            else:
+                F = np.asfortranarray(np.linalg.cholesky(X @ X.T + self.rho * np.eye(self.n)))
+            self._h = lib().orc_create_factored(_dp(X), _dp(y), self.n, self.p, self.lambda0, self.lambda2,
+                                                self.M, self.rho, _dp(F))
+        else:
+            raise ValueError("factor is None or 'numpy'")
         if not self._h:
             raise ValueError("oracle rejected the instance")
 
     @classmethod
-    def from_instance(cls, inst, rho=1.0):
-        return cls(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, rho)
+    def from_instance(cls, inst, rho=1.0, factor=None):
+        return cls(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, rho, factor=factor)
 
     def __del__(self):
         h_ = getattr(self, "_h", None)

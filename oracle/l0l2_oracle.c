@@ -136,8 +136,9 @@ static void chol_solve(const double *L, int64_t m, double *x) {
     }
 }
 
-orc_inst *orc_create(const double *X, const double *y, int64_t n, int64_t p,
-                     double lambda0, double lambda2, double M, double rho) {
+/* Instance data every constructor fills: copies of X and y, c = X^T y, ||X_j||. */
+static orc_inst *inst_common(const double *X, const double *y, int64_t n, int64_t p,
+                             double lambda0, double lambda2, double M, double rho) {
     if (n < 1 || p < 1 || !(lambda0 >= 0) || !(lambda2 > 0) || !(M > 0) || !(rho > 0)) return NULL;
     orc_inst *in = (orc_inst *)calloc(1, sizeof(orc_inst));
     in->n = n; in->p = p; in->l0 = lambda0; in->l2 = lambda2; in->M = M; in->rho = rho;
@@ -153,10 +154,17 @@ orc_inst *orc_create(const double *X, const double *y, int64_t n, int64_t p,
         in->c[j] = s;
         in->colnrm[j] = sqrt(q);
     }
+    in->dform = (n >= p);
+    return in;
+}
+
+orc_inst *orc_create(const double *X, const double *y, int64_t n, int64_t p,
+                     double lambda0, double lambda2, double M, double rho) {
+    orc_inst *in = inst_common(X, y, n, p, lambda0, lambda2, M, rho);
+    if (!in) return NULL;
     /* Precompute D once for the whole tree (Sec. 3.1.1, update for b).  Reading:
      * the printed Woodbury form carries 1/rho^2 where (1/rho)(I - X^T (X X^T +
      * rho I)^{-1} X) is the identity; the latter is used. */
-    in->dform = (n >= p);
     if (in->dform) {
         double *A = (double *)malloc(sizeof(double) * (size_t)p * (size_t)p);
         for (int64_t j = 0; j < p; ++j)
@@ -185,6 +193,24 @@ orc_inst *orc_create(const double *X, const double *y, int64_t n, int64_t p,
             }
         if (cholesky(in->L, n) != 0) { orc_free(in); return NULL; }
     }
+    return in;
+}
+
+/* The same instance with the once-per-tree factor supplied by the caller (for
+ * large instances, where it comes from a library factorisation): D =
+ * (X^T X + rho I)^{-1} (p x p) when n >= p, else the lower Cholesky factor L of
+ * X X^T + rho I (n x n), column-major either way.  Everything else is computed
+ * here exactly as in orc_create. */
+orc_inst *orc_create_factored(const double *X, const double *y, int64_t n, int64_t p,
+                              double lambda0, double lambda2, double M, double rho, const double *factor) {
+    if (!factor) return NULL;
+    orc_inst *in = inst_common(X, y, n, p, lambda0, lambda2, M, rho);
+    if (!in) return NULL;
+    int64_t m = in->dform ? p : n;
+    double *F = (double *)malloc(sizeof(double) * (size_t)m * (size_t)m);
+    memcpy(F, factor, sizeof(double) * (size_t)m * (size_t)m);
+    if (in->dform) in->D = F;
+    else in->L = F;
     return in;
 }
 

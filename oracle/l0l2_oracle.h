@@ -10,6 +10,7 @@
  *   orc_T, orc_psi, orc_prox   pinned: brute-force 1-D minimisation
  *   orc_h, orc_nu              pinned: brute-force convex conjugate
  *   orc_b_update               pinned: (X^T X + rho I) b = w to 1e-12
+ *   orc_create_factored        pinned: same b-update and node solves as orc_create
  *   orc_dual_value/bound       pinned: weak duality for random r, strong duality
  *   orc_node_admm              pinned: gap -> 0, fully-fixed special cases
  *   orc_fista / exact          pinned: Cholesky ridge and scipy bounded LSQ
@@ -42,6 +43,12 @@ double orc_z(double beta, int code, double l0, double l2, double M);         /* 
 typedef struct orc_inst orc_inst;
 orc_inst *orc_create(const double *X, const double *y, int64_t n, int64_t p,
                      double lambda0, double lambda2, double M, double rho);
+/* The same with the once-per-tree factor supplied: D = (X^T X + rho I)^{-1}
+   (p x p) when n >= p, else the lower Cholesky factor of X X^T + rho I (n x n),
+   column-major; copied. */
+orc_inst *orc_create_factored(const double *X, const double *y, int64_t n, int64_t p,
+                              double lambda0, double lambda2, double M, double rho,
+                              const double *factor);
 void orc_free(orc_inst *);
 const double *orc_c(const orc_inst *);                /* X^T y */
 

@@ -248,7 +248,9 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     HIPCHK(hipStreamSynchronize(st));
     const double UB = core.ub();
     out->ub = UB;
-    out->lb = status == 0 ? UB : std::min(UB, core.frontier_lb());
+    // every support lies in a closed node (pruned: its bound reached UB (1 - eps);
+    // a leaf) or an open one, so the smallest of their bounds bounds the optimum
+    out->lb = std::min(UB, std::min(core.closed_lb(), status == 0 ? INFINITY : core.frontier_lb()));
     out->nodes_solved = core.solved();
     out->nodes_pruned = core.pruned();
     out->trace_len = core.trace_len();

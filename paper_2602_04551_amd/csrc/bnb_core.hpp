@@ -51,6 +51,9 @@ class BnbCore {
     int64_t trace_len() const { return tl_; }
     int64_t slots_in_use() const { return used_; }
     int64_t slot_high_water() const { return (int64_t)refs_.size(); }
+    // Smallest bound among the closed nodes (pruned or leaves): with the open
+    // nodes' bounds it bounds the optimum from below (+inf when none closed).
+    double closed_lb() const { return closed_lb_; }
 
     // Smallest inherited bound over the open nodes (+inf when none).
     double frontier_lb() const {
@@ -82,6 +85,7 @@ class BnbCore {
                 r.decision = 3;
                 r.lb = u.lb;
                 r.ub_global = ub_;
+                closed_lb_ = std::min(closed_lb_, u.lb);
                 put(r);
                 release(u.slot);
                 continue;
@@ -123,6 +127,7 @@ class BnbCore {
                 ++pruned_;
                 r.decision = 1;
                 r.ub_global = ub_;
+                closed_lb_ = std::min(closed_lb_, lb_eff);
                 put(r);
                 continue;
             }
@@ -136,6 +141,7 @@ class BnbCore {
             r.ub_global = ub_;
             if (x.branch_j < 0) {
                 r.decision = 2;
+                closed_lb_ = std::min(closed_lb_, lb_eff);
                 put(r);
                 continue;
             }
@@ -210,6 +216,7 @@ class BnbCore {
     std::priority_queue<OpenNode, std::vector<OpenNode>, HeapCmp> heap_;
     std::vector<OpenNode> stack_;
     double ub_ = INFINITY;
+    double closed_lb_ = INFINITY;
     bool have_inc_ = false;
     int64_t solved_ = 0, pruned_ = 0, tl_ = 0, used_ = 0;
     std::vector<int32_t> refs_;

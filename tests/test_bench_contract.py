@@ -35,25 +35,26 @@ def test_counter_traffic_is_dropped_when_the_kernel_sources_change(tmp_path, mon
     import bench
     prof_dir = tmp_path / "profiles"
     prof_dir.mkdir()
-    (prof_dir / "c2_hbm_traffic.json").write_text(json.dumps(
-        {"source_digest": "not-the-current-sources", "per_launch_bytes": {"admm_xtu.f32": 123}}))
+    (prof_dir / bench.TRAFFIC_FILE).write_text(json.dumps(
+        {"c3": {"source_digest": "not-the-current-sources", "per_launch_bytes": {"admm_xtu.bf16": 123}}}))
     csrc = tmp_path / "paper_2602_04551_amd" / "csrc"
     csrc.mkdir(parents=True)
     (csrc / "a.hip").write_text("__global__ void k() {}\n")
     (csrc / "b.hpp").write_text("// header\n")
     (csrc / "host.hip").write_text("// host code only\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("admm_xtu.f32") is None
+    assert bench.measured_traffic("admm_xtu.bf16", "c3") is None
     import hashlib
     digest = hashlib.sha256(b"__global__ void k() {}\n// header\n").hexdigest()
-    (prof_dir / "c2_hbm_traffic.json").write_text(json.dumps(
-        {"source_digest": digest, "per_launch_bytes": {"admm_xtu.f32": 123}}))
-    assert bench.measured_traffic("admm_xtu.f32") == 123
+    (prof_dir / bench.TRAFFIC_FILE).write_text(json.dumps(
+        {"c3": {"source_digest": digest, "per_launch_bytes": {"admm_xtu.bf16": 123}}}))
+    assert bench.measured_traffic("admm_xtu.bf16", "c3") == 123
+    assert bench.measured_traffic("admm_xtu.bf16", "c5") is None     # no counters for that workload
     # a host-only file may change; a kernel file or a header may not
     (csrc / "host.hip").write_text("// host code, edited\n")
-    assert bench.measured_traffic("admm_xtu.f32") == 123
+    assert bench.measured_traffic("admm_xtu.bf16", "c3") == 123
     (csrc / "b.hpp").write_text("// header, edited\n")
-    assert bench.measured_traffic("admm_xtu.f32") is None
+    assert bench.measured_traffic("admm_xtu.bf16", "c3") is None
 
 
 def test_sweep_bytes_roofline_counts_operand_and_state_bytes():

@@ -1,0 +1,116 @@
+"""Decision-level parity of the GPU branch and bound (Alg. 1) with the oracle.
+
+* FP64, depth-first, one node per batch on the n = 100, p = 50 instance: the
+  GPU trace equals the oracle's own depth-first trace record by record.
+* Best-first batches in every precision, on the n = 100, p = 50 and the
+  n = p = 1000 instances: the oracle replays the GPU tree (the same fixings,
+  warm-started from its own solution of the parent, against the same incumbent
+  sequence; tests/replay.py) and every prune, rounding and branching decision
+  whose oracle-side margin clears the tolerance band must agree; decisions
+  inside the band are counted and printed.  The certified optimum and its
+  support must equal the oracle's (n = p = 1000: the committed oracle result).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import replay
+from paper_2602_04551_amd import datagen
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+KW = dict(tol_node=1e-6, max_iter=2000, max_iter_root=10000, check_every=10)
+EPS = 2e-6
+# Bands of the replay (readings of the comparison of batched / reduced-precision
+# trees with the oracle's): the FP64 path reproduces the oracle's iterates to
+# rounding, so its branching band is one step of the 2^-20 score grid; the
+# reduced paths stop at the node tolerance at other sweeps than the oracle, so
+# scores and z values are compared only where they clear 1e-3.
+BANDS = {"fp64": dict(score_band=2.0 ** -20, z_band=1e-9, prune_band=1e-5),
+         "fp32": dict(score_band=1e-3, z_band=1e-3, prune_band=1e-5),
+         "bf16": dict(score_band=1e-3, z_band=1e-3, prune_band=1e-5),
+         "fp8": dict(score_band=1e-3, z_band=1e-3, prune_band=1e-5)}
+_CACHE = {}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _ctx(inst, precision):
+    from paper_2602_04551_amd.binding import Context
+    c = Context(0)
+    c.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=precision)
+    return c
+
+
+def test_c1_dfs_fp64_trace_identical_to_oracle(torch_cuda, orc):
+    inst = datagen.config_instance("C1", seed=0)
+    o = orc.Oracle.from_instance(inst)
+    ref = o.bnb(**KW, eps_prune=EPS, trace_cap=200000)
+    got = _ctx(inst, "fp64").bnb_solve(K=1, policy="dfs", **KW, eps_prune=EPS, trace_cap=200000)
+    assert got["status"] == 0 and ref["status"] == 0
+    assert len(got["trace"]) == len(ref["trace"])
+    for a, b in zip(got["trace"], ref["trace"]):
+        for f in ("id", "parent", "depth", "branch_j", "decision", "iters", "support_size", "admm_status"):
+            assert a[f] == b[f], (f, a, b)
+        assert abs(a["lb"] - b["lb"]) <= 1e-10 * max(1.0, abs(b["lb"]))
+    assert abs(got["certified"] - ref["certified"]) <= 1e-10 * ref["certified"]
+    assert list(got["support"]) == list(ref["support"])
+
+
+def _check_replay(o, got, precision, cache):
+    out = replay.replay(o, got["trace"], eps_prune=EPS, cache=cache, **KW, **BANDS[precision])
+    summary = {k: v for k, v in out.items() if k != "mismatch"}
+    summary["mismatches"] = len(out["mismatch"])
+    print("[replay] " + precision + " " + json.dumps(summary), flush=True)
+    assert out["mismatch"] == [], out["mismatch"][:5]
+    assert out["solved"] == got["nodes_solved"]
+    assert out["prune_cmp"] >= 0.9 * (out["prune_cmp"] + out["prune_band"])
+    assert out["branch_cmp"] >= 0.9 * (out["branch_cmp"] + out["branch_band"]) - 1
+    if precision == "fp64":
+        assert out["prune_band"] + out["branch_band"] + out["support_band"] <= max(2, out["solved"] // 50)
+    return out
+
+
+@pytest.mark.parametrize("precision,K", [("fp64", 64), ("fp32", 64), ("bf16", 64), ("fp8", 64), ("fp64", 8)])
+def test_c1_best_first_decisions_replayed_by_oracle(torch_cuda, orc, precision, K):
+    inst = datagen.config_instance("C1", seed=0)
+    o = orc.Oracle.from_instance(inst)
+    ref = o.bnb(**KW, eps_prune=EPS)
+    got = _ctx(inst, precision).bnb_solve(K=K, policy="best", **KW, eps_prune=EPS, trace_cap=200000)
+    assert got["status"] == 0
+    assert len(got["trace"]) == got["trace_len"] if "trace_len" in got else True
+    _check_replay(o, got, precision, _CACHE.setdefault("C1", {}))
+    assert abs(got["certified"] - ref["certified"]) <= 1e-8 * ref["certified"]
+    assert list(got["support"]) == list(ref["support"])
+
+
+@pytest.fixture(scope="module")
+def c2():
+    inst = datagen.config_instance("C2", seed=0)
+    with open(os.path.join(GOLD, "fullsize_c2_bnb.json")) as f:
+        gold = json.load(f)
+    return inst, gold
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16", "fp8"])
+def test_c2_best_first_decisions_replayed_by_oracle(torch_cuda, orc, c2, precision):
+    """n = p = 1000, best-first batches of 256: the certified optimum equals the
+    committed oracle result, and the oracle replays the tree."""
+    inst, gold = c2
+    got = _ctx(inst, precision).bnb_solve(K=256, policy="best", **KW, eps_prune=EPS, trace_cap=200000)
+    assert got["status"] == 0
+    assert abs(got["certified"] - gold["certified"]) <= 1e-8 * gold["certified"]
+    assert [int(j) for j in got["support"]] == gold["support"]
+    o = _CACHE.get("C2_oracle")
+    if o is None:
+        o = _CACHE["C2_oracle"] = orc.Oracle.from_instance(inst)
+    _check_replay(o, got, precision, _CACHE.setdefault("C2", {}))

@@ -4,14 +4,24 @@ times (autotuned tiles, live buckets, graph-replayed blocks).
 n = p = 1000, 256 frontier nodes: the oracle solves a spread sample of the
 batch's nodes one by one from the same codes and warm start (its own FP64 root),
 and every node is checked for the properties a rigorous bound has at any size.
-n = p = 5000 and n = 1000, p = 50 000 are beyond what the single-threaded oracle
-finishes in seconds (its precompute alone is O(n^2 p)); there the reduced-precision
-paths are checked against the FP64 GPU path, itself held to the oracle at the
-smaller sizes, and every node against the bound's own properties."""
+n = p = 5000 (4096 nodes) and n = 1000, p = 50 000 (1024 nodes) are beyond what
+the single-threaded oracle finishes in seconds (its precompute alone is
+O(n^2 p)): there eight sampled nodes of each batch were solved once by the
+oracle from its own root (tests/golden/make_fullsize_goldens.py, which calls only
+the oracle and the input generator) and every precision's bounds on those nodes
+are held to those values; every node of the batch is also checked against the
+bound's own properties and against the FP64 GPU path.  All full-size batches
+start from the root relaxation solved in FP64 to a 1e-9 gap, as the benchmark's
+do."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 from paper_2602_04551_amd import datagen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 pytestmark = pytest.mark.gpu
 C2_K = 256
@@ -87,28 +97,66 @@ def test_c2_batch_matches_the_oracle_on_sampled_nodes(torch_cuda, c2, precision)
 def node_batch(cfg, K):
     inst = datagen.config_instance(cfg, seed=0)
     codes = datagen.node_batch_codes(inst.p, K, seed=K)
-    zero = np.zeros((K, inst.p))
-    return inst, codes, zero
+    return inst, codes
 
 
-@pytest.mark.parametrize("cfg,K,precisions", [("C3", 512, ("fp32", "bf16")),
-                                              ("C5", 256, ("fp32", "bf16", "fp8"))])
-def test_full_size_batches_agree_with_the_fp64_path(torch_cuda, cfg, K, precisions):
-    """The batching (n = p = 5000) and high-dimensional (n = 1000, p = 50 000)
-    workloads at the benchmark's batch sizes: every bound stays below its
-    node's primal value, converged nodes meet the tolerance, and the bounds of
-    nodes converged in both paths agree with the FP64 path within 1e-5."""
-    inst, codes, zero = node_batch(cfg, K)
-    _, ref = solve(inst, "fp64", codes, zero, zero, tol_node=1e-6, max_iter=2000, check_every=10)
-    conv64 = ref["status"] == 0
-    assert np.all(ref["lb"] <= ref["primal"])
-    assert conv64.sum() >= 0.5 * K
+_ROOTS = {}
+
+
+def gpu_root(cfg, inst):
+    """The root relaxation in FP64 on the GPU to a 1e-9 gap (the benchmark's warm start)."""
+    if cfg not in _ROOTS:
+        from paper_2602_04551_amd.binding import Context
+        rc = Context(0)
+        rc.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp64")
+        r = rc.solve_node_batch(np.zeros((1, inst.p), np.uint8), tol_node=1e-9, max_iter=20000)
+        _ROOTS[cfg] = (r["beta"].cpu().numpy()[0], r["v"].cpu().numpy()[0], int(r["iters"][0].item()))
+        rc.close()
+    return _ROOTS[cfg]
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("cfg,K,precisions", [("C3", 4096, ("fp64", "fp32", "bf16", "fp8")),
+                                              ("C5", 1024, ("fp64", "fp32", "bf16", "fp8"))])
+def test_full_size_batches_match_the_oracle_on_sampled_nodes(torch_cuda, cfg, K, precisions):
+    """The batching (n = p = 5000, 4096 nodes) and high-dimensional (n = 1000,
+    p = 50 000, 1024 nodes) batches of the benchmark, from the FP64 root: on the
+    eight nodes the oracle solved (committed values), converged bounds agree
+    within 1e-10 (FP64, at equal sweep counts) or 1e-5 (reduced precisions) of
+    the primal value; a node the oracle left at the sweep budget only has to
+    bound from below the oracle's primal value there.  Every node of the batch:
+    its bound is below its primal value and a converged node meets the tolerance;
+    the bounds of nodes converged in both agree with the FP64 path within 1e-5."""
+    with open(os.path.join(GOLD, f"fullsize_{cfg.lower()}_nodes.json")) as f:
+        gold = json.load(f)
+    assert gold["K"] == K
+    inst, codes = node_batch(cfg, K)
+    rb, rv, root_iters = gpu_root(cfg, inst)
+    print(f"[root] {cfg} GPU sweeps {root_iters}, oracle sweeps {gold['root']['iters']}", flush=True)
+    beta0 = np.tile(rb, (K, 1))
+    v0 = np.tile(rv, (K, 1))
+    ref64 = None
     for precision in precisions:
-        _, r = solve(inst, precision, codes, zero, zero, tol_node=1e-6, max_iter=2000, check_every=10)
-        lb, pr, st = r["lb"], r["primal"], r["status"]
+        _, r = solve(inst, precision, codes, beta0, v0, tol_node=1e-6, max_iter=2000, check_every=10)
+        lb, pr, st, it = r["lb"], r["primal"], r["status"], r["iters"]
         conv = st == 0
         assert np.all(lb <= pr), precision
         assert np.all((pr - lb)[conv] / np.abs(pr[conv]) <= 1e-6), precision
-        assert conv.sum() >= conv64.sum() - 0.05 * K, precision
-        both = conv & conv64
-        assert np.max(np.abs(lb - ref["lb"])[both] / np.abs(ref["primal"][both])) <= 1e-5, precision
+        for g in gold["nodes"]:
+            k = g["slot"]
+            line = (f"[node] {cfg} {precision} slot {k}: gpu lb {lb[k]:.15g} sweeps {it[k]} status {st[k]}; "
+                    f"oracle lb {g['lb']:.15g} sweeps {g['iters']} status {g['status']}")
+            print(line, flush=True)
+            assert lb[k] <= g["primal"] + 1e-12 * abs(g["primal"]), line
+            if g["status"] != 0 or st[k] != 0:
+                continue
+            if precision == "fp64" and it[k] == g["iters"]:
+                assert abs(lb[k] - g["lb"]) <= 1e-10 * abs(g["primal"]), line
+            else:
+                assert abs(lb[k] - g["lb"]) <= 1e-5 * abs(g["primal"]), line
+        if precision == "fp64":
+            ref64 = r
+        else:
+            both = conv & (ref64["status"] == 0)
+            assert both.sum() >= 0.9 * K, precision
+            assert np.max(np.abs(lb - ref64["lb"])[both] / np.abs(ref64["primal"][both])) <= 1e-5, precision

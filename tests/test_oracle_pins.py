@@ -384,3 +384,142 @@ def test_bnb_matches_enumeration(orc, seed, M):
     for rec in res["trace"]:
         if rec["decision"] in (0, 2):
             assert rec["ub_node"] >= opt * (1 - 1e-12)
+
+
+# ----------------------------------------------------------------------------
+# FISTA trajectory on a separable quadratic (closed form)
+# ----------------------------------------------------------------------------
+
+def _separable_case():
+    """Two support columns that are orthogonal, with squared norms 1 and 1/4, a
+    third column off the support; y has X_S^T y = (1, 0.5) exactly.  Then
+    U(beta) = 1/2 ||y||^2 - c^T beta + 1/2 sum_a L_a beta_a^2 with L_a = A_a +
+    2 lambda2 (A = (1, 1/4)): the gradient is L_a beta_a - c_a coordinatewise,
+    and the Armijo inequality of eq. fpg_armijo at step alpha reduces to
+    sum_a (alpha L_a - 1) d_a^2 <= 0 for the step d = -alpha grad (no clipping)."""
+    X = np.array([[1.0, 0.0, 0.3],
+                  [0.0, 0.5, 0.2],
+                  [0.0, 0.0, 0.9]], order="F")
+    y = np.array([1.0, 1.0, 0.7])           # X_0^T y = 1, X_1^T y = 0.5
+    l0, l2, M = 0.05, 0.01, 100.0
+    return X, y, l0, l2, M
+
+
+def _fista_closed_form(T, mom):
+    """Iterate after T steps from beta = 0: step alpha_0 = 4 / (||X_S||_F^2 + 2 lambda2)
+    halved while the reduced Armijo test fails, then carried; per coordinate
+    e_{t+1} = (1 - alpha L_a) (e_t + m_t (e_t - e_{t-1})) for the error
+    e = beta - c / L, with the momentum m_t of the extrapolation."""
+    A = np.array([1.0, 0.25])
+    c = np.array([1.0, 0.5])
+    l2 = 0.01
+    L = A + 2 * l2
+    alpha = 4.0 / (A.sum() + 2 * l2)
+    g = -c                                  # gradient at the start (beta = 0)
+    while np.sum((alpha * L - 1.0) * (alpha * g) ** 2) > 0.0:
+        alpha *= 0.5
+    q = 1.0 - alpha * L
+    star = c / L
+    e_prev = e = -star
+    for t in range(T):
+        e_new = q * (e + mom(t) * (e - e_prev))
+        e_prev, e = e, e_new
+    return star + e, alpha
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 5, 8, 13, 21])
+def test_fista_trajectory_matches_closed_form(orc, T):
+    """Pins the extrapolation coefficient t/(t+3) of eq. fpg_extrapolate, the
+    gradient of eq. fpg_grad, the projected step and the backtracking of
+    eq. fpg_armijo with a carried step, iterate by iterate: a coefficient of
+    t/(t+2), a missing 2 lambda2 or a missing 1/(2 alpha) term moves the
+    iterates far beyond the tolerance."""
+    X, y, l0, l2, M = _separable_case()
+    o = orc.Oracle(X, y, l0, l2, M)
+    mask = np.array([1, 1, 0], np.uint8)
+    f, beta, it = o.fista(mask, np.zeros(3), tol=0.0, max_iter=T)
+    want, alpha = _fista_closed_form(T, lambda t: t / (t + 3.0))
+    assert alpha == pytest.approx(4.0 / 1.27 / 4.0, rel=1e-15)      # two halvings
+    assert it == T
+    assert np.max(np.abs(beta[:2] - want)) <= 1e-13
+    assert beta[2] == 0.0
+    if T >= 2:
+        other, _ = _fista_closed_form(T, lambda t: t / (t + 2.0))
+        assert np.max(np.abs(other - want)) > 1e-4
+
+
+def test_fista_first_step_is_the_accepted_step_times_c(orc):
+    """The same case with the Armijo test as written: the first iterate is
+    alpha c (from zero, one projected gradient step), with alpha the accepted step."""
+    X, y, l0, l2, M = _separable_case()
+    o = orc.Oracle(X, y, l0, l2, M)
+    _, beta, _ = o.fista(np.array([1, 1, 0], np.uint8), np.zeros(3), tol=0.0, max_iter=1)
+    alpha = 4.0 / 1.27 / 4.0
+    assert beta[:2] == pytest.approx(alpha * np.array([1.0, 0.5]), rel=1e-14)
+
+
+# ----------------------------------------------------------------------------
+# bounds along the path to the optimum
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed,M", [(0, None), (2, 10.0), (4, 0.4)])
+def test_bounds_on_the_path_to_the_optimum_stay_below_opt(orc, seed, M):
+    """Every node whose fixings are consistent with the optimal support S*
+    (F1 within S*, F0 outside it) contains S*, so its rigorous bound, the one
+    it inherits and the one it was pruned on must all be <= OPT (from
+    enumeration), and they never decrease from parent to child on that path."""
+    import replay
+    inst = datagen.make_instance(35, 11, rho=0.5, k=3, snr=2.0, seed=seed, lambda0=0.02,
+                                 lambda2=0.01, M=M)
+    o = orc.Oracle.from_instance(inst)
+    res = o.bnb(tol_node=1e-7, max_iter=5000, max_iter_root=20000)
+    opt, S_opt = enumerate_opt(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M)[0]
+    codes, _, parent = replay.node_codes(res["trace"], inst.p)
+    inS = np.zeros(inst.p, bool)
+    inS[list(S_opt)] = True
+    lb_of = {}
+    on_path = 0
+    for rec in res["trace"]:
+        c = codes[rec["id"]]
+        lb_of[rec["id"]] = rec["lb"]
+        if np.any((c == FIX1) & ~inS) or np.any((c == FIX0) & inS):
+            continue
+        on_path += 1
+        assert rec["lb"] <= opt * (1 + 1e-12), rec
+        if rec["id"] > 0:
+            assert rec["lb"] >= lb_of[parent[rec["id"]]]
+    assert on_path >= 1
+
+
+def test_replay_of_the_oracle_own_trace_has_no_mismatch(orc):
+    """The trace replayer (used against GPU traces) replaying a depth-first
+    oracle trace reproduces every decision of it."""
+    import replay
+    inst = datagen.make_instance(35, 11, rho=0.5, k=3, snr=2.0, seed=1, lambda0=0.02, lambda2=0.01)
+    o = orc.Oracle.from_instance(inst)
+    kw = dict(tol_node=1e-7, max_iter=5000, max_iter_root=20000, check_every=10)
+    res = o.bnb(**kw, eps_prune=2e-7)
+    out = replay.replay(o, res["trace"], eps_prune=2e-7, **kw)
+    assert out["mismatch"] == []
+    assert out["solved"] == res["nodes_solved"]
+    assert out["prune_cmp"] + out["prune_band"] == out["solved"]
+    assert out["branch_cmp"] > 0
+
+
+@pytest.mark.parametrize("n,p", [(40, 25), (25, 40)])
+def test_factored_constructor_matches_the_plain_one(orc, n, p):
+    """The oracle with its once-per-tree factor taken from numpy (used for the
+    large instances) gives the same b-update and node solves as the oracle that
+    forms the factor itself, in both forms (D for n >= p, the Cholesky factor of
+    X X^T + rho I for n < p)."""
+    inst = datagen.make_instance(n, p, rho=0.4, k=3, seed=7)
+    a = orc.Oracle.from_instance(inst, rho=0.7)
+    b = orc.Oracle.from_instance(inst, rho=0.7, factor="numpy")
+    w = np.random.default_rng(1).normal(size=p)
+    assert np.max(np.abs(a.b_update(w) - b.b_update(w))) <= 1e-12 * np.max(np.abs(w))
+    codes = np.zeros(p, np.uint8)
+    codes[:3] = [FIX0, FIX1, FIX0]
+    ra = a.node_admm(codes, tol=1e-8, max_iter=20000)
+    rb = b.node_admm(codes, tol=1e-8, max_iter=20000)
+    assert ra["status"] == rb["status"] == 0
+    assert abs(ra["lb"] - rb["lb"]) <= 1e-9 * abs(ra["primal"])
