@@ -15,6 +15,10 @@ Decisions are compared where the oracle's margins clear a tolerance band:
   min(z, 1 - z) is >= score_band (when every free score is 0: the gap between
   the two largest |beta_j| relative to the largest is >= score_band).
 Decisions inside a band are counted and returned, never silently accepted.
+For an in-band branching decision the GPU's index must still be a free
+coordinate, and the oracle-side score deficit of that index (the oracle's best
+floored score minus its score at the GPU's index; with every free score 0, the
+relative |beta| deficit) is returned as its maximum over the tree.
 """
 from __future__ import annotations
 
@@ -72,6 +76,7 @@ def replay(o, trace, *, tol_node, max_iter, max_iter_root, check_every, eps_prun
     out = {k: 0 for k in ("prune_cmp", "prune_band", "branch_cmp", "branch_band", "support_cmp", "support_band",
                           "ub_cmp", "solved", "select_cmp", "select_band")}
     out["mismatch"] = []
+    out["band_deficit_max"] = 0.0
     ub_before = math.inf
     for rec in trace:
         i, d = rec["id"], rec["decision"]
@@ -149,5 +154,16 @@ def replay(o, trace, *, tol_node, max_iter, max_iter_root, check_every, eps_prun
                     out["mismatch"].append(("branch", i, gpu_j, j_o, margin))
             else:
                 out["branch_band"] += 1
+                if d == 0:
+                    pos = np.flatnonzero(free == gpu_j)
+                    if len(pos) == 0:
+                        out["mismatch"].append(("branch_not_free", i, gpu_j))
+                    elif sc.max() > 0:
+                        deficit = (sc.max() - sc[pos[0]]) / GRID
+                        out["band_deficit_max"] = max(out["band_deficit_max"], float(deficit))
+                    else:
+                        ab = np.abs(r["beta"][free])
+                        deficit = (ab.max() - ab[pos[0]]) / max(ab.max(), 1e-300)
+                        out["band_deficit_max"] = max(out["band_deficit_max"], float(deficit))
         ub_before = rec["ub_global"]
     return out

@@ -25,13 +25,19 @@ KW = dict(tol_node=1e-6, max_iter=2000, max_iter_root=10000, check_every=10)
 EPS = 2e-6
 # Bands of the replay (readings of the comparison of batched / reduced-precision
 # trees with the oracle's): the FP64 path reproduces the oracle's iterates to
-# rounding, so its branching band is one step of the 2^-20 score grid; the
-# reduced paths stop at the node tolerance at other sweeps than the oracle, so
-# scores and z values are compared only where they clear 1e-3.
-BANDS = {"fp64": dict(score_band=2.0 ** -20, z_band=1e-9, prune_band=1e-5),
+# rounding (node bounds within 1e-10 relative, equal sweep counts), so its
+# branching band is one step of the 2^-20 score grid and its prune band ten
+# times that bound tolerance; the reduced paths stop at the node tolerance at
+# other sweeps than the oracle, so their bounds agree to 1e-5 (the node-bound
+# tolerance of the reduced forms) and scores and z values are compared only
+# where they clear 1e-3.
+BANDS = {"fp64": dict(score_band=2.0 ** -20, z_band=1e-9, prune_band=1e-9),
          "fp32": dict(score_band=1e-3, z_band=1e-3, prune_band=1e-5),
          "bf16": dict(score_band=1e-3, z_band=1e-3, prune_band=1e-5),
          "fp8": dict(score_band=1e-3, z_band=1e-3, prune_band=1e-5)}
+# Largest oracle-side score deficit of an in-band branching choice of a reduced
+# path (scores min(z, 1 - z) lie in [0, 1/2]).
+DEFICIT_MAX = 0.05
 _CACHE = {}
 
 
@@ -73,9 +79,15 @@ def _check_replay(o, got, precision, cache):
     assert out["mismatch"] == [], out["mismatch"][:5]
     assert out["solved"] == got["nodes_solved"]
     assert out["prune_cmp"] >= 0.9 * (out["prune_cmp"] + out["prune_band"])
-    assert out["branch_cmp"] >= 0.9 * (out["branch_cmp"] + out["branch_band"]) - 1
     if precision == "fp64":
+        # the FP64 path reproduces the oracle's iterates: nearly every decision is compared
+        assert out["branch_cmp"] >= 0.9 * (out["branch_cmp"] + out["branch_band"]) - 1
         assert out["prune_band"] + out["branch_band"] + out["support_band"] <= max(2, out["solved"] // 50)
+    else:
+        # a reduced path stops at other sweeps than the oracle, so where two free
+        # scores lie within the band its choice may differ; it must still pick a
+        # coordinate that the oracle's own iterate scores close to its best
+        assert out["band_deficit_max"] <= DEFICIT_MAX, out["band_deficit_max"]
     return out
 
 
