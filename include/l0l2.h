@@ -141,6 +141,26 @@ typedef struct {
 int l0l2_refine_incumbent(l0l2_ctx *ctx, int K, const uint8_t *support, const void *beta_start,
                           double *beta_out, const l0l2_fista_opts *opts, double *obj, int32_t *iters);
 
+/* Allocation-free form of l0l2_refine_incumbent, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, layouts and results as
+ * l0l2_refine_incumbent (the same kernels, bit-identical outputs), except:
+ *  - the FP64 residual rows of supports wider than 64 coordinates live in a
+ *    fixed device scratch of 32 MiB (each device the library runs on holds
+ *    its own copy until the process ends); K x (n rounded up to a multiple of
+ *    128) x 8 bytes must fit in it, else L0L2_E_INVALID (n = 1000: K <= 4096;
+ *    n = 5000: K <= 819);
+ *  - no device memory is allocated or freed and no library routine that
+ *    allocates is called; the call is not timed by l0l2_profile_*;
+ *  - it returns without waiting: the outputs are ready in stream order on the
+ *    context's stream (and on the caller's stream given to l0l2_create).
+ * Every call on one device shares that device's scratch: calls that overlap
+ * on one device (contexts on different streams, or threads) race and must be
+ * serialised by the caller.  Nothing in the scratch needs to start at zero
+ * (each residual row is written before it is read). */
+int l0l2_refine_incumbent_noalloc(l0l2_ctx *ctx, int K, const uint8_t *support, const void *beta_start,
+                                  double *beta_out, const l0l2_fista_opts *opts, double *obj, int32_t *iters);
+
 /* Objective of one support solved to full FP64 accuracy (box-constrained ridge
  * on S; used for the certified value of the final incumbent).  support and
  * beta_out (p doubles) are host pointers. */

@@ -70,6 +70,7 @@ SIGNATURES = {
     "l0l2_solve_node_batch": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_admm_opts), _vp, _vp, _vp, _vp]),
     "l0l2_round_branch": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
     "l0l2_refine_incumbent": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_fista_opts), _vp, _vp]),
+    "l0l2_refine_incumbent_noalloc": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_fista_opts), _vp, _vp]),
     "l0l2_exact_objective": (_i, [_vp, _vp, _vp, _vp]),
     "l0l2_bnb_solve": (_i, [_vp, C.POINTER(l0l2_bnb_opts), C.POINTER(l0l2_bnb_result)]),
     "l0l2_result_free": (None, [C.POINTER(l0l2_bnb_result)]),
@@ -235,6 +236,18 @@ class Context:
         self._check(lib.l0l2_refine_incumbent(self._h, K, _ptr(support), _ptr(start), _ptr(beta), C.byref(o),
                                               _ptr(obj), _ptr(iters)))
         return obj, beta, iters
+
+    def refine_incumbent_noalloc(self, support, beta_start, beta_out, obj, iters=None, tol=1e-12, max_iter=1000):
+        """Allocation-free refinement into caller-provided device tensors
+        (beta_out: K x p float64, obj: K float64, iters: K int32 or None)."""
+        torch = _torch()
+        support = self._dev(support, torch.uint8)
+        K = support.shape[0]
+        start = self._dev(beta_start, self.state_dtype)
+        o = l0l2_fista_opts(float(tol), int(max_iter))
+        self._check(lib.l0l2_refine_incumbent_noalloc(self._h, K, _ptr(support), _ptr(start), _ptr(beta_out),
+                                                      C.byref(o), _ptr(obj), _ptr(iters)))
+        return obj, beta_out, iters
 
     def exact_objective(self, mask):
         mask = np.ascontiguousarray(mask, dtype=np.uint8)

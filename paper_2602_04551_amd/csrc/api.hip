@@ -124,6 +124,13 @@ int l0l2_create(int device, void *hip_stream, l0l2_ctx **out) {
         delete c;
         return L0L2_E_DEVICE;
     }
+    // address of the allocation-free entry point's scratch on this device, looked
+    // up here (once per device) so that the entry point itself allocates nothing
+    try {
+        (void)l0l2::noalloc_scratch(device);
+    } catch (const l0l2::Error &e) {
+        c->noalloc_err = e.msg;
+    }
     *out = c;
     return L0L2_OK;
 }
@@ -256,6 +263,28 @@ int l0l2_refine_incumbent(l0l2_ctx *ctx, int K, const uint8_t *support, const vo
         l0l2::state_to_f64(ctx, K, beta_start, p, beta_out, p);
         l0l2::run_fista(ctx, K, support, p, beta_out, p, *opts, obj, iters);
         HIPCHK(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int l0l2_refine_incumbent_noalloc(l0l2_ctx *ctx, int K, const uint8_t *support, const void *beta_start,
+                                  double *beta_out, const l0l2_fista_opts *opts, double *obj, int32_t *iters) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        check_K(K);
+        if (!opts || opts->max_iter < 1 || !(opts->tol >= 0)) l0l2::fail(L0L2_E_INVALID, "bad FISTA options");
+        if (K == 0) return;
+        if (!support || !beta_start || !beta_out || !obj) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        const size_t need = sizeof(double) * (size_t)K * (size_t)ctx->inst.np;
+        if (need > l0l2::kNoAllocScratchBytes)
+            l0l2::fail(L0L2_E_INVALID, "K x padded n x 8 = " + std::to_string(need) + " bytes exceeds the " +
+                                           std::to_string(l0l2::kNoAllocScratchBytes) +
+                                           "-byte device scratch of the allocation-free refinement");
+        if (!ctx->noalloc_err.empty()) l0l2::fail(L0L2_E_DEVICE, ctx->noalloc_err);
+        // looked up at l0l2_create; this only reads the stored address
+        double *scr = static_cast<double *>(l0l2::noalloc_scratch(ctx->device));
+        const int64_t p = ctx->inst.p;
+        l0l2::state_to_f64(ctx, K, beta_start, p, beta_out, p);
+        l0l2::run_fista(ctx, K, support, p, beta_out, p, *opts, obj, iters, scr);
     });
 }
 

@@ -2,12 +2,45 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "device_math.hpp"
 #include "internal.hpp"
 
+// Residual scratch of the allocation-free refinement (one row of the padded n
+// doubles per node), a file-scope device array: every device the library runs
+// on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address); it uses the per-device address that hipGetSymbolAddress returns.
+static __device__ __align__(256) double scratch[l0l2::kNoAllocScratchBytes / sizeof(double)];
+
 namespace l0l2 {
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+}  // namespace
+
+void *noalloc_scratch(int device) {
+    if (device < 0 || device >= kNoAllocMaxDevices)
+        fail(L0L2_E_UNSUPPORTED, "the allocation-free entry points support device indices below " +
+                                     std::to_string(kNoAllocMaxDevices));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        // the caller has made `device` current
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            fail(L0L2_E_DEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = ptr;
+    }
+    return g_scratch_ptr[device];
+}
 
 namespace {
 
@@ -592,16 +625,22 @@ void run_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, int64_t ld_cod
 }
 
 void run_fista(l0l2_ctx *ctx, int K, const uint8_t *support, int64_t ld_support, double *beta, int64_t ld_beta,
-               const l0l2_fista_opts &o, double *obj, int32_t *iters) {
+               const l0l2_fista_opts &o, double *obj, int32_t *iters, double *resbuf) {
     Instance &in = ctx->inst;
     if (K <= 0) return;
-    ctx->ws.fista.ensure(sizeof(double) * (size_t)K * in.np);
+    // resbuf: K rows of np doubles supplied by the caller (the allocation-free
+    // entry point), else the workspace's, grown here
+    const bool own = resbuf == nullptr;
+    if (own) {
+        ctx->ws.fista.ensure(sizeof(double) * (size_t)K * in.np);
+        resbuf = ctx->ws.fista.as<double>();
+    }
     FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, o.tol, o.max_iter, in.n, in.np, in.p, in.ldx};
-    prof_begin(ctx, PROF_FISTA);
+    if (own) prof_begin(ctx, PROF_FISTA);
     hipLaunchKernelGGL(k_fista, dim3((unsigned)K), dim3(256), 0, ctx->stream, in.X64.as<double>(), in.y64.as<double>(),
                        in.colnrm.as<double>(), in.c64.as<double>(), in.yy, support, ld_support, beta, ld_beta,
-                       ctx->ws.fista.as<double>(), obj, iters, fa);
-    prof_end(ctx, PROF_FISTA);
+                       resbuf, obj, iters, fa);
+    if (own) prof_end(ctx, PROF_FISTA);
     HIPCHK(hipGetLastError());
 }
 

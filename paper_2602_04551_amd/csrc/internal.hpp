@@ -16,6 +16,11 @@ namespace l0l2 {
 constexpr int kPadRows = 128;   // n and p are padded to multiples of this
 constexpr int kPadNodes = 32;   // K is padded to multiples of this (one GEMM tile)
 
+// Device scratch of the allocation-free entry point (l0l2_refine_incumbent_noalloc):
+// its size, and the device indices it serves.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 // Leading dimension of a matrix whose rows (or columns) hold `extent` elements
@@ -192,6 +197,7 @@ struct l0l2_ctx {
     int force_xw = -1, force_xtu = -1;   // fixed tile shapes (-1: autotune)
     int bform = 0;                       // b-update form: 0 auto, 1 folded operand (two contractions), 2 Gram
     bool use_graphs = true;              // replay captured blocks of sweeps
+    std::string noalloc_err;             // why the allocation-free scratch is unavailable (empty: it is)
     std::map<l0l2::GraphKey, hipGraphExec_t> graphs;
     l0l2::Instance inst;
     l0l2::Workspace ws;
@@ -223,7 +229,10 @@ void run_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, int64_t ld_cod
                       uint8_t *support, int32_t *support_size, int32_t *branch_j, int32_t *z_up,
                       int32_t *nfree);
 void run_fista(l0l2_ctx *ctx, int K, const uint8_t *support, int64_t ld_support, double *beta,
-               int64_t ld_beta, const l0l2_fista_opts &o, double *obj, int32_t *iters);
+               int64_t ld_beta, const l0l2_fista_opts &o, double *obj, int32_t *iters, double *resbuf = nullptr);
+// Device address of the allocation-free entry point's scratch on `device`
+// (which must be current), looked up once per device.
+void *noalloc_scratch(int device);
 double run_exact_objective(l0l2_ctx *ctx, const uint8_t *support_host, double *beta_host);
 // state (f32 or f64, ld_src) -> f64 (ld_dst) copy of K rows of length p
 void state_to_f64(l0l2_ctx *ctx, int K, const void *src, int64_t ld_src, double *dst, int64_t ld_dst);
