@@ -56,8 +56,7 @@ _U8 = C.POINTER(C.c_uint8)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
+        build()   # compiles when the library is missing or older than its source
         L = C.CDLL(LIB_PATH)
         d, i, i64, vp = C.c_double, C.c_int, C.c_int64, C.c_void_p
         for name, res, args in [
@@ -77,6 +76,8 @@ def lib():
             ("orc_exact_objective", d, [vp, _U8, _D]), ("orc_objective", d, [vp, _U8, _D]),
             ("orc_bnb", i, [vp, C.POINTER(BnbOpts), C.POINTER(BnbResult), _U8, _D,
                             C.POINTER(TraceRec), i64]),
+            ("orc_mp_deltas", None, [vp, _U8, _D, _D, _D, _D]),
+            ("orc_matching_pursuit", i, [vp, i, _U8, _D, C.POINTER(C.c_int32)]),
         ]:
             f = getattr(L, name)
             f.restype = res
@@ -225,6 +226,27 @@ class Oracle:
     def objective(self, mask, beta):
         return lib().orc_objective(self._h, _up(np.ascontiguousarray(mask, np.uint8)),
                                    _dp(np.ascontiguousarray(beta, np.float64)))
+
+    def mp_deltas(self, mask, beta, r):
+        """Objective change of every single-coordinate move (App. A.2) and the
+        coefficient each move sets."""
+        delta = np.empty(self.p)
+        bnew = np.empty(self.p)
+        lib().orc_mp_deltas(self._h, _up(np.ascontiguousarray(mask, np.uint8)),
+                            _dp(np.ascontiguousarray(beta, np.float64)), _dp(np.ascontiguousarray(r, np.float64)),
+                            _dp(delta), _dp(bnew))
+        return delta, bnew
+
+    def matching_pursuit(self, max_moves=None):
+        """Forward / backward matching pursuit from the empty support: (mask, beta, moves)."""
+        if max_moves is None:
+            max_moves = 4 * self.p
+        mask = np.zeros(self.p, np.uint8)
+        beta = np.zeros(self.p)
+        moves = np.zeros(max(max_moves, 1), np.int32)
+        nm = lib().orc_matching_pursuit(self._h, int(max_moves), _up(mask), _dp(beta),
+                                        moves.ctypes.data_as(C.POINTER(C.c_int32)))
+        return mask, beta, [int(m) for m in moves[:nm]]
 
     def bnb(self, tol_node=1e-6, max_iter=2000, max_iter_root=10000, check_every=10,
             eps_prune=None, gap_tol=0.0, max_nodes=10**7, fista_tol=1e-12, fista_max_iter=1000,

@@ -591,6 +591,88 @@ double orc_exact_objective(const orc_inst *in, const uint8_t *mask, double *beta
 }
 
 /* ------------------------------------------------------------------------- */
+/* Matching-pursuit root heuristic (Sec. 3.5, App. A.2)                       */
+/* ------------------------------------------------------------------------- */
+
+/* Objective change of each single-coordinate move at (mask, beta) with the
+ * residual r = y - X beta given, the other coordinates frozen (App. A.2):
+ *   j outside the support: adding j with b = clip(c_j / D_j, -M, M),
+ *     c_j = X_j^T r, D_j = ||X_j||^2 + 2 lambda2,
+ *     Delta_j = -b c_j + D_j b^2 / 2 + lambda0            (bnew[j] = b);
+ *   j in the support: removing it (beta_j -> 0),
+ *     Delta_j = beta_j c_j + (||X_j||^2 / 2 - lambda2) beta_j^2 - lambda0
+ *                                                         (bnew[j] = 0). */
+void orc_mp_deltas(const orc_inst *in, const uint8_t *mask, const double *beta, const double *r,
+                   double *delta, double *bnew) {
+    const int64_t n = in->n, p = in->p;
+    for (int64_t j = 0; j < p; ++j) {
+        double c = 0.0, q = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            c += XC(in, i, j) * r[i];
+            q += XC(in, i, j) * XC(in, i, j);
+        }
+        if (mask[j]) {
+            const double b = beta[j];
+            delta[j] = b * c + (0.5 * q - in->l2) * b * b - in->l0;
+            bnew[j] = 0.0;
+        } else {
+            const double D = q + 2.0 * in->l2;
+            const double b = clip(c / D, in->M);
+            delta[j] = -b * c + 0.5 * D * b * b + in->l0;
+            bnew[j] = b;
+        }
+    }
+}
+
+/* From S = {} and beta = 0 (r = y), alternate a forward step (the addition of
+ * smallest Delta_j among j outside S, taken when Delta_j < 0) and a backward
+ * step (the removal of smallest Delta_j among j in S, taken when Delta_j < 0),
+ * each recomputing c = X^T r at the current residual, which is updated
+ * exactly (r -= X_j b on an addition, r += X_j beta_j on a removal); stop when
+ * a forward and the following backward step both take no move, or after
+ * max_moves moves.  Ties go to the smallest index.  Fills mask and beta (p
+ * entries) and moves (room for max_moves: j + 1 for an addition of j, -(j + 1)
+ * for a removal), returns the number of moves. */
+int orc_matching_pursuit(const orc_inst *in, int max_moves, uint8_t *mask, double *beta, int32_t *moves) {
+    const int64_t n = in->n, p = in->p;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n);
+    double *delta = (double *)malloc(sizeof(double) * (size_t)p);
+    double *bnew = (double *)malloc(sizeof(double) * (size_t)p);
+    memcpy(r, in->y, sizeof(double) * (size_t)n);
+    memset(mask, 0, (size_t)p);
+    for (int64_t j = 0; j < p; ++j) beta[j] = 0.0;
+    int nm = 0;
+    while (nm < max_moves) {
+        int moved = 0;
+        for (int phase = 0; phase < 2 && nm < max_moves; ++phase) {
+            const int want = phase == 0 ? 0 : 1;    /* forward: j outside S; backward: j in S */
+            orc_mp_deltas(in, mask, beta, r, delta, bnew);
+            int64_t best = -1;
+            for (int64_t j = 0; j < p; ++j)
+                if ((mask[j] != 0) == want && delta[j] < 0.0 && (best < 0 || delta[j] < delta[best])) best = j;
+            if (best < 0) continue;
+            if (phase == 0) {
+                const double b = bnew[best];
+                for (int64_t i = 0; i < n; ++i) r[i] = r[i] - XC(in, i, best) * b;
+                beta[best] = b;
+                mask[best] = 1;
+                moves[nm++] = (int32_t)(best + 1);
+            } else {
+                const double b = beta[best];
+                for (int64_t i = 0; i < n; ++i) r[i] = r[i] + XC(in, i, best) * b;
+                beta[best] = 0.0;
+                mask[best] = 0;
+                moves[nm++] = (int32_t)(-(best + 1));
+            }
+            moved = 1;
+        }
+        if (!moved) break;
+    }
+    free(r); free(delta); free(bnew);
+    return nm;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Depth-first branch and bound                                               */
 /* ------------------------------------------------------------------------- */
 

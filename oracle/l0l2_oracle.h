@@ -15,6 +15,11 @@
  *   orc_node_admm              pinned: gap -> 0, fully-fixed special cases
  *   orc_fista / exact          pinned: Cholesky ridge and scipy bounded LSQ
  *   orc_bnb                    pinned: enumeration of all supports, p <= 14
+ *   orc_mp_deltas              pinned: brute-force 1-D minimisation / direct
+ *                              objective differences
+ *   orc_matching_pursuit       pinned: each move lowers F by its Delta; no
+ *                              improving single move at exit; global optimum
+ *                              on orthonormal designs (enumeration)
  *   trajectory details (iteration counts, node counts) are parity unpinned
  *   beyond this oracle: the paper prints no worked example.
  *
@@ -84,6 +89,17 @@ double orc_fista(const orc_inst *, const uint8_t *mask, double *beta,
 double orc_exact_objective(const orc_inst *, const uint8_t *mask, double *beta);
 /* F(S, beta) evaluated as written (eq. upperboundbeta plus lambda0 |S|) */
 double orc_objective(const orc_inst *, const uint8_t *mask, const double *beta);
+
+/* --- matching-pursuit root heuristic (Sec. 3.5, App. A.2) ----------------- */
+/* Objective change of each single-coordinate move at (mask, beta), residual r =
+   y - X beta given, other coordinates frozen: an addition for j outside the
+   support (bnew[j] = its coefficient), a removal for j in it (bnew[j] = 0). */
+void orc_mp_deltas(const orc_inst *, const uint8_t *mask, const double *beta, const double *r,
+                   double *delta, double *bnew);
+/* Alternating forward / backward steps from the empty support until neither
+   moves or max_moves moves; moves[t] = j + 1 (addition) or -(j + 1) (removal).
+   Returns the number of moves; mask and beta (p) receive the result. */
+int orc_matching_pursuit(const orc_inst *, int max_moves, uint8_t *mask, double *beta, int32_t *moves);
 
 /* --- depth-first branch and bound (Alg. 1 with K = 1 and a LIFO frontier) --- */
 typedef struct {

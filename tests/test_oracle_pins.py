@@ -523,3 +523,112 @@ def test_factored_constructor_matches_the_plain_one(orc, n, p):
     rb = b.node_admm(codes, tol=1e-8, max_iter=20000)
     assert ra["status"] == rb["status"] == 0
     assert abs(ra["lb"] - rb["lb"]) <= 1e-9 * abs(ra["primal"])
+
+
+# ----------------------------------------------------------------------------
+# matching-pursuit root heuristic (Sec. 3.5, App. A.2)
+# ----------------------------------------------------------------------------
+
+def _F(X, y, l0, l2, beta, mask):
+    """F(S, beta) = 1/2 ||y - X beta||^2 + l2 ||beta||^2 + l0 |S|, written out."""
+    r = y - X @ beta
+    return 0.5 * float(r @ r) + l2 * float(beta @ beta) + l0 * int(mask.sum())
+
+
+def _mp_state(rng, n, p, M):
+    X = rng.standard_normal((n, p))
+    X /= np.linalg.norm(X, axis=0)
+    y = rng.standard_normal(n)
+    y /= np.linalg.norm(y)
+    mask = (rng.random(p) < 0.4).astype(np.uint8)
+    beta = np.where(mask == 1, rng.uniform(-M, M, p), 0.0)
+    return X, y, mask, beta
+
+
+@pytest.mark.parametrize("seed,M", [(0, 10.0), (1, 0.3), (2, 0.05)])
+def test_mp_deltas_match_one_coordinate_brute_force(orc, seed, M):
+    """Forward Delta_j = min over |b| <= M of F(S + j, beta + b e_j) - F(S, beta)
+    (grid, then a bounded scalar search); backward Delta_j = F(S - j, beta with
+    beta_j = 0) - F(S, beta), evaluated directly."""
+    rng = np.random.default_rng(seed)
+    n, p, l0, l2 = 30, 9, 0.01, 0.02
+    X, y, mask, beta = _mp_state(rng, n, p, M)
+    o = orc.Oracle(X, y, l0, l2, M)
+    r = y - X @ beta
+    delta, bnew = o.mp_deltas(mask, beta, r)
+    F0 = _F(X, y, l0, l2, beta, mask)
+    for j in range(p):
+        if mask[j]:
+            b2, m2 = beta.copy(), mask.copy()
+            b2[j], m2[j] = 0.0, 0
+            assert abs(delta[j] - (_F(X, y, l0, l2, b2, m2) - F0)) <= 1e-12
+            assert bnew[j] == 0.0
+            continue
+        m2 = mask.copy()
+        m2[j] = 1
+
+        def g(b):
+            b2 = beta.copy()
+            b2[j] = b
+            return _F(X, y, l0, l2, b2, m2) - F0
+
+        grid = np.linspace(-M, M, 4001)
+        vals = np.array([g(b) for b in grid])
+        k = int(np.argmin(vals))
+        lo, hi = grid[max(k - 1, 0)], grid[min(k + 1, len(grid) - 1)]
+        res = minimize_scalar(g, bounds=(lo, hi), method="bounded", options=dict(xatol=1e-12))
+        best = min(res.fun, vals[k])
+        assert abs(delta[j] - best) <= 1e-10
+        assert delta[j] <= best + 1e-13
+        assert abs(bnew[j] - (res.x if res.fun <= vals[k] else grid[k])) <= 1e-5
+
+
+@pytest.mark.parametrize("seed,M", [(0, 10.0), (3, 0.2), (5, 1.0)])
+def test_mp_moves_lower_F_by_their_delta_and_end_locally_optimal(orc, seed, M):
+    """Replaying the moves: each lowers F by exactly the Delta of its state (and
+    is the smallest of its kind, ties to the smallest index); at exit no single
+    addition or removal lowers F."""
+    rng = np.random.default_rng(seed)
+    n, p, l0, l2 = 40, 14, 0.005, 0.01
+    X, y, _, _ = _mp_state(rng, n, p, M)
+    y = X[:, [1, 6, 11]] @ np.array([0.8, -0.5, 0.6]) + 0.3 * y
+    o = orc.Oracle(X, y, l0, l2, M)
+    mask_f, beta_f, moves = o.matching_pursuit()
+    assert moves and moves[0] > 0
+    mask = np.zeros(p, np.uint8)
+    beta = np.zeros(p)
+    F = _F(X, y, l0, l2, beta, mask)
+    for mv in moves:
+        j = abs(mv) - 1
+        delta, bnew = o.mp_deltas(mask, beta, y - X @ beta)
+        cand = np.flatnonzero(mask == (0 if mv > 0 else 1))
+        assert delta[j] < 0 and j == cand[np.argmin(delta[cand])]
+        if mv > 0:
+            beta[j], mask[j] = bnew[j], 1
+        else:
+            beta[j], mask[j] = 0.0, 0
+        F_new = _F(X, y, l0, l2, beta, mask)
+        assert abs((F_new - F) - delta[j]) <= 1e-12
+        F = F_new
+    assert np.array_equal(mask, mask_f) and np.allclose(beta, beta_f, rtol=0, atol=1e-14)
+    delta, _ = o.mp_deltas(mask, beta, y - X @ beta)
+    assert np.all(delta >= 0.0)
+
+
+@pytest.mark.parametrize("seed,M", [(0, 10.0), (1, 0.25)])
+def test_mp_reaches_the_global_optimum_on_orthonormal_designs(orc, seed, M):
+    """With orthonormal columns F separates over coordinates, so the frozen
+    one-coordinate moves are exact and the heuristic must end at the optimum
+    found by enumerating every support."""
+    rng = np.random.default_rng(seed)
+    n, p, l0, l2 = 30, 10, 0.01, 0.02
+    Q, _ = np.linalg.qr(rng.standard_normal((n, p)))
+    y = Q @ rng.uniform(-0.6, 0.6, p) + 0.05 * rng.standard_normal(n)
+    o = orc.Oracle(np.asfortranarray(Q), y, l0, l2, M)
+    mask, beta, moves = o.matching_pursuit()
+    assert all(m > 0 for m in moves)
+    vals = enumerate_opt(Q, y, l0, l2, M)
+    f_opt, S_opt = vals[0]
+    assert vals[1][0] - f_opt > 1e-9
+    assert tuple(np.flatnonzero(mask)) == S_opt
+    assert abs(_F(Q, y, l0, l2, beta, mask) - f_opt) <= 1e-12
