@@ -166,6 +166,23 @@ int l0l2_refine_incumbent_noalloc(l0l2_ctx *ctx, int K, const uint8_t *support, 
  * beta_out (p doubles) are host pointers. */
 int l0l2_exact_objective(l0l2_ctx *ctx, const uint8_t *support, double *beta_out, double *obj);
 
+/* Matching-pursuit root heuristic (Sec. 3.5; forward and backward scores of
+ * App. A.2), FP64 with the original X.  From the empty support, a forward
+ * step adds the j outside S of smallest Delta_j = -b c_j + D_j b^2 / 2 + lambda0
+ * (c_j = X_j^T r, D_j = ||X_j||^2 + 2 lambda2, b = clip(c_j / D_j, -M, M), r the
+ * residual y - X beta; the other coefficients frozen), a backward step removes
+ * the j in S of smallest Delta_j = beta_j c_j + (||X_j||^2 / 2 - lambda2) beta_j^2
+ * - lambda0; a step is taken only when its Delta_j < 0, ties go to the smallest
+ * index, steps alternate forward / backward, and the run ends when a forward
+ * step and the backward step after it both take nothing, or after max_moves
+ * moves (>= 1).  Host outputs: support (p bytes, 0/1), beta (p doubles, the
+ * heuristic's coefficients, zero off S), *obj = F(S, beta) including
+ * lambda0 |S|, moves (room for max_moves int32, may be NULL: j + 1 for an
+ * addition of j, -(j + 1) for a removal, in order), *n_moves.  Waits for the
+ * device. */
+int l0l2_matching_pursuit(l0l2_ctx *ctx, int max_moves, uint8_t *support, double *beta, double *obj,
+                          int32_t *moves, int32_t *n_moves);
+
 enum { L0L2_BEST_FIRST = 0, L0L2_DFS = 1 };
 
 typedef struct {
@@ -189,6 +206,9 @@ typedef struct {
     l0l2_fista_opts fista;
     l0l2_trace_rec *trace; /* optional host buffer of trace_cap records (NULL: none) */
     int64_t trace_cap;
+    int root_heuristic;    /* 1: before the root, the support of l0l2_matching_pursuit
+                              (max_moves 4 min(n, p)) solved exactly seeds the incumbent
+                              (Sec. 3.5); 0: none */
 } l0l2_bnb_opts;
 
 typedef struct {

@@ -42,7 +42,7 @@ class l0l2_bnb_opts(C.Structure):
     _fields_ = [("K", C.c_int), ("policy", C.c_int), ("eps_prune", C.c_double),
                 ("gap_tol", C.c_double), ("time_limit_s", C.c_double), ("max_nodes", C.c_int64),
                 ("max_iter_root", C.c_int), ("admm", l0l2_admm_opts), ("fista", l0l2_fista_opts),
-                ("trace", C.POINTER(l0l2_trace_rec)), ("trace_cap", C.c_int64)]
+                ("trace", C.POINTER(l0l2_trace_rec)), ("trace_cap", C.c_int64), ("root_heuristic", C.c_int)]
 
 
 class l0l2_bnb_result(C.Structure):
@@ -72,6 +72,7 @@ SIGNATURES = {
     "l0l2_refine_incumbent": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_fista_opts), _vp, _vp]),
     "l0l2_refine_incumbent_noalloc": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_fista_opts), _vp, _vp]),
     "l0l2_exact_objective": (_i, [_vp, _vp, _vp, _vp]),
+    "l0l2_matching_pursuit": (_i, [_vp, _i, _vp, _vp, C.POINTER(_d), _vp, C.POINTER(C.c_int32)]),
     "l0l2_bnb_solve": (_i, [_vp, C.POINTER(l0l2_bnb_opts), C.POINTER(l0l2_bnb_result)]),
     "l0l2_result_free": (None, [C.POINTER(l0l2_bnb_result)]),
     "l0l2_footprint_bytes": (C.c_size_t, [_i64, _i64, _i, _i]),
@@ -256,6 +257,20 @@ class Context:
         self._check(lib.l0l2_exact_objective(self._h, mask.ctypes.data, beta.ctypes.data, C.byref(obj)))
         return obj.value, beta
 
+    def matching_pursuit(self, max_moves=None):
+        """Forward / backward matching pursuit from the empty support:
+        (mask, beta, F(S, beta), moves), moves as j + 1 (addition) / -(j + 1) (removal)."""
+        if max_moves is None:
+            max_moves = 4 * min(self.n, self.p)
+        mask = np.zeros(self.p, np.uint8)
+        beta = np.zeros(self.p)
+        moves = np.zeros(max(int(max_moves), 1), np.int32)
+        obj = C.c_double()
+        nm = C.c_int32()
+        self._check(lib.l0l2_matching_pursuit(self._h, int(max_moves), mask.ctypes.data, beta.ctypes.data,
+                                              C.byref(obj), moves.ctypes.data, C.byref(nm)))
+        return mask, beta, obj.value, [int(m) for m in moves[:nm.value]]
+
     def tune_batch_size(self, k_max=1024, frac=0.9):
         """(chosen K, {candidate K: node-sweeps per second})."""
         k = C.c_int()
@@ -289,7 +304,7 @@ class Context:
 
     def bnb_solve(self, K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000,
                   check_every=10, eps_prune=None, gap_tol=0.0, time_limit_s=0.0, max_nodes=10**9,
-                  fista_tol=1e-12, fista_max_iter=1000, trace_cap=0):
+                  fista_tol=1e-12, fista_max_iter=1000, trace_cap=0, root_heuristic=False):
         if eps_prune is None:
             eps_prune = 2.0 * tol_node
         tr = (l0l2_trace_rec * max(trace_cap, 1))()
@@ -297,7 +312,7 @@ class Context:
                           float(gap_tol), float(time_limit_s), int(max_nodes), int(max_iter_root),
                           l0l2_admm_opts(float(tol_node), int(max_iter), int(check_every)),
                           l0l2_fista_opts(float(fista_tol), int(fista_max_iter)),
-                          tr if trace_cap > 0 else None, int(trace_cap))
+                          tr if trace_cap > 0 else None, int(trace_cap), 1 if root_heuristic else 0)
         r = l0l2_bnb_result()
         self._check(lib.l0l2_bnb_solve(self._h, C.byref(o), C.byref(r)))
         try:
@@ -314,13 +329,14 @@ class Context:
 
 def bnb_options(K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000, check_every=10,
                 eps_prune=None, gap_tol=0.0, time_limit_s=0.0, max_nodes=10**9, fista_tol=1e-12,
-                fista_max_iter=1000):
+                fista_max_iter=1000, root_heuristic=False):
     if eps_prune is None:
         eps_prune = 2.0 * tol_node
     return l0l2_bnb_opts(int(K), L0L2_DFS if policy == "dfs" else L0L2_BEST_FIRST, float(eps_prune),
                          float(gap_tol), float(time_limit_s), int(max_nodes), int(max_iter_root),
                          l0l2_admm_opts(float(tol_node), int(max_iter), int(check_every)),
-                         l0l2_fista_opts(float(fista_tol), int(fista_max_iter)), None, 0)
+                         l0l2_fista_opts(float(fista_tol), int(fista_max_iter)), None, 0,
+                         1 if root_heuristic else 0)
 
 
 def _result_dict(r, p):

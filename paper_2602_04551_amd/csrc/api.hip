@@ -296,6 +296,16 @@ int l0l2_exact_objective(l0l2_ctx *ctx, const uint8_t *support, double *beta_out
     });
 }
 
+int l0l2_matching_pursuit(l0l2_ctx *ctx, int max_moves, uint8_t *support, double *beta, double *obj,
+                          int32_t *moves, int32_t *n_moves) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        if (max_moves < 1) l0l2::fail(L0L2_E_INVALID, "max_moves must be >= 1");
+        if (!support || !beta || !obj || !n_moves) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        l0l2::run_matching_pursuit(ctx, max_moves, support, beta, moves, n_moves, obj);
+    });
+}
+
 int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *out) {
     if (out) std::memset(out, 0, sizeof(*out));
     return guarded(ctx, [&] {
@@ -303,7 +313,8 @@ int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *ou
         if (!opts || !out) l0l2::fail(L0L2_E_INVALID, "null argument");
         if (opts->K < 0 || opts->admm.max_iter < 1 || opts->admm.check_every < 1 || opts->max_iter_root < 1 ||
             opts->fista.max_iter < 1 || !(opts->eps_prune >= 0) || !(opts->gap_tol >= 0) || opts->max_nodes < 1 ||
-            (opts->policy != L0L2_BEST_FIRST && opts->policy != L0L2_DFS))
+            (opts->policy != L0L2_BEST_FIRST && opts->policy != L0L2_DFS) || opts->root_heuristic < 0 ||
+            opts->root_heuristic > 1)
             l0l2::fail(L0L2_E_INVALID, "bad branch-and-bound options");
         l0l2_bnb_opts o = *opts;
         if (o.K == 0) {

@@ -158,6 +158,18 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
 
     BnbCore core(o);
     std::vector<uint8_t> inc_mask((size_t)p, 0);
+    if (o.root_heuristic == 1) {
+        // Sec. 3.5: the matching-pursuit support, solved exactly, is the first incumbent
+        std::vector<uint8_t> mp_mask((size_t)p, 0);
+        std::vector<double> mp_beta((size_t)p, 0.0);
+        int32_t nm = 0;
+        double mp_obj = 0.0;
+        const int64_t mm = 4 * std::min(in.n, in.p);
+        run_matching_pursuit(ctx, (int)std::min<int64_t>(mm, 1 << 30), mp_mask.data(), mp_beta.data(), nullptr, &nm,
+                             &mp_obj);
+        const double f = run_exact_objective(ctx, mp_mask.data(), mp_beta.data());
+        if (std::isfinite(f) && core.seed_incumbent(f)) inc_mask = mp_mask;
+    }
     int64_t batches = 0;
     int status = 0;
     std::vector<OpenNode> batch;

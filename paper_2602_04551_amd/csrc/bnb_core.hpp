@@ -55,6 +55,15 @@ class BnbCore {
     // nodes' bounds it bounds the optimum from below (+inf when none closed).
     double closed_lb() const { return closed_lb_; }
 
+    // An incumbent found before the tree (the root heuristic): its objective
+    // becomes UB when it is smaller.  Returns whether it did.
+    bool seed_incumbent(double ub) {
+        if (!(ub < ub_)) return false;
+        ub_ = ub;
+        have_inc_ = true;
+        return true;
+    }
+
     // Smallest inherited bound over the open nodes (+inf when none).
     double frontier_lb() const {
         if (dfs_) {

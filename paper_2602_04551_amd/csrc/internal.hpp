@@ -237,7 +237,12 @@ double run_exact_objective(l0l2_ctx *ctx, const uint8_t *support_host, double *b
 // state (f32 or f64, ld_src) -> f64 (ld_dst) copy of K rows of length p
 void state_to_f64(l0l2_ctx *ctx, int K, const void *src, int64_t ld_src, double *dst, int64_t ld_dst);
 
-// bnb.cpp
+// heuristic.hip: forward / backward matching pursuit from the empty support;
+// host outputs mask and beta (p entries), moves (room for max_moves, may be null)
+void run_matching_pursuit(l0l2_ctx *ctx, int max_moves, uint8_t *mask_host, double *beta_host, int32_t *moves_host,
+                          int32_t *n_moves, double *obj);
+
+// bnb.hip
 void bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out);
 
 void drop_graphs(l0l2_ctx *ctx);
