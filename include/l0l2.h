@@ -326,6 +326,19 @@ int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
  * value (BF16 mode), on the first solve that uses it. */
 int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form);
 
+/* Products of the BF16 Gram-form sweeps.  3: every sweep multiplies with the
+ * split form (G as a BF16 hi/lo pair times the node operand split into two
+ * BF16 halves: three MFMA products, FP32 accumulation).  1 (default): blocks
+ * of single-term sweeps wherever the LDS-staged tiles are chosen: each block is
+ * anchored (FP32 phase: its first sweep is a split-form sweep whose product
+ * z = G w_a and operand w_a become the anchor; FP64 phase: the FP64 anchor
+ * product), and its other sweeps multiply only d = W - w_a, rounded to one BF16
+ * term, by G rounded to one BF16 term (one MFMA product), taking
+ * G W = z + G d; the product's error then scales with the movement since the
+ * anchor.  FP32, FP64 and FP8 modes ignore the setting.  Returns
+ * L0L2_E_INVALID for other values. */
+int l0l2_set_bf16_terms(l0l2_ctx *ctx, int terms);
+
 /* Opt-in timing of the library's kernels with HIP events recorded on the
  * context stream around each launch (adds one event pair per launch).
  * l0l2_profile_enable clears the counters and switches timing on (1) or off (0).

@@ -84,6 +84,7 @@ SIGNATURES = {
     "l0l2_set_tiles": (_i, [_vp, _i, _i]),
     "l0l2_tune_batch_size": (_i, [_vp, _i, _d, C.POINTER(_i), _vp, C.POINTER(_i)]),
     "l0l2_set_bupdate_form": (_i, [_vp, _i]),
+    "l0l2_set_bf16_terms": (_i, [_vp, _i]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
     "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
 }
@@ -286,6 +287,10 @@ class Context:
         if form not in forms:
             raise ValueError(f"b-update form must be one of {sorted(forms)}, not {form!r}")
         self._check(lib.l0l2_set_bupdate_form(self._h, forms[form]))
+
+    def set_bf16_terms(self, terms=1):
+        """BF16 Gram-form sweeps: 1 single-term anchored blocks (default), 3 split form in every sweep."""
+        self._check(lib.l0l2_set_bf16_terms(self._h, int(terms)))
 
     def set_tiles(self, xw_shape=-1, xtu_shape=-1):
         self._check(lib.l0l2_set_tiles(self._h, int(xw_shape), int(xtu_shape)))

@@ -15,6 +15,7 @@
 // evaluated in FP64 with the original X (Sec. 3.1.2 and the node stopping rule
 // of Sec. 4.1): r = y - X b, g = X^T r, LB = rigorous D(r); P(beta) from X beta.
 #include <algorithm>
+#include <utility>
 #include <chrono>
 #include <cmath>
 #include <limits>
@@ -26,6 +27,16 @@
 namespace l0l2 {
 
 namespace {
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, unrolled at compile time.
+template <class F, int... I>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void sfor(F &&f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <class T>
 DevParams<T> dev_params(const MethodParams &m) {
@@ -808,6 +819,14 @@ __device__ __forceinline__ void split4(const float4 &w, bf16x4 &hi, bf16x4 &lo) 
     }
 }
 
+__device__ __forceinline__ void split4(const f32x4 &w, bf16x4 &hi, bf16x4 &lo) {
+    for (int t = 0; t < 4; ++t) {
+        __bf16 h = (__bf16)w[t];
+        hi[t] = h;
+        lo[t] = (__bf16)(w[t] - (float)h);
+    }
+}
+
 __device__ __forceinline__ void load8f(const float *p, float out[8]) {
     float4 a = *reinterpret_cast<const float4 *>(p);
     float4 b = *reinterpret_cast<const float4 *>(p + 4);
@@ -929,62 +948,75 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
                 16 * part;
         lb[e] = (L::TM + row) * L::ROWB + 8 * part;
     }
-    float4 va[L::NA], vb[L::NB];
+    // two register sets: chunk c + 2's loads are issued while chunk c is
+    // multiplied, chunk c + 1's (issued a chunk earlier) are staged after it;
+    // the arrays are indexed with compile-time constants (sfor) only
+    f32x4 va0[L::NA], vb0[L::NB], va1[L::NA], vb1[L::NB];
     // chunk c covers 32 k: 64 bytes of each BF16 term, 128 bytes of FP32
-#define L0L2_GLOADB(c)                                                                                      \
-    _Pragma("unroll") for (int e = 0; e < L::NA; ++e) va[e] = *reinterpret_cast<const float4 *>(ga[e] + 64 * (c)); \
-    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) vb[e] = *reinterpret_cast<const float4 *>(gb[e] + 128 * (c));
-#define L0L2_SSTOREB(st)                                                                                    \
-    _Pragma("unroll") for (int e = 0; e < L::NA; ++e)                                                       \
-        *reinterpret_cast<float4 *>(smem + (st) * L::STAGE + la[e]) = va[e];                                 \
-    _Pragma("unroll") for (int e = 0; e < L::NB; ++e) {                                                     \
+#define L0L2_GLOADB(VA, VB, c)                                                                              \
+    {                                                                                                       \
+        const int64_t c_ = (c);                                                                             \
+        sfor<L::NA>([&](auto e) { VA[e] = *reinterpret_cast<const f32x4 *>(ga[e] + 64 * c_); });           \
+        sfor<L::NB>([&](auto e) { VB[e] = *reinterpret_cast<const f32x4 *>(gb[e] + 128 * c_); });          \
+    }                                                                                                       \
+    __builtin_amdgcn_sched_barrier(0);
+#define L0L2_SSTOREB(st, VA, VB)                                                                            \
+    sfor<L::NA>([&](auto e) { *reinterpret_cast<f32x4 *>(smem + (st) * L::STAGE + la[e]) = VA[e]; });      \
+    sfor<L::NB>([&](auto e) {                                                                               \
         bf16x4 h4, l4;                                                                                      \
-        split4(vb[e], h4, l4);                                                                              \
+        split4(VB[e], h4, l4);                                                                              \
         *reinterpret_cast<bf16x4 *>(smem + (st) * L::STAGE + lb[e]) = h4;                                    \
         *reinterpret_cast<bf16x4 *>(smem + (st) * L::STAGE + lb[e] + 64) = l4;                               \
+    });
+#define L0L2_COMPUTEB(st)                                                                                   \
+    {                                                                                                       \
+        const unsigned char *sa = smem + (st) * L::STAGE;                                                   \
+        bf16x8 bh[WN], bl[WN];                                                                              \
+        _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                                    \
+            const unsigned char *row = sa + (L::TM + wn * 16 * WN + 16 * j + r) * L::ROWB;                  \
+            bh[j] = *reinterpret_cast<const bf16x8 *>(row + 16 * q);                                        \
+            bl[j] = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);                                   \
+        }                                                                                                   \
+        _Pragma("unroll") for (int i = 0; i < WM; ++i) {                                                    \
+            const unsigned char *row = sa + (wm * 16 * WM + 16 * i + r) * L::ROWB;                          \
+            const bf16x8 ah = *reinterpret_cast<const bf16x8 *>(row + 16 * q);                              \
+            const bf16x8 al = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);                         \
+            _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                                \
+                acc[i][j] = mfma16_bf16(ah, bh[j], acc[i][j]);                                              \
+                acc[i][j] = mfma16_bf16(ah, bl[j], acc[i][j]);                                              \
+                acc[i][j] = mfma16_bf16(al, bh[j], acc[i][j]);                                              \
+            }                                                                                               \
+        }                                                                                                   \
     }
-    const int64_t nch = kdim / 32;
-    L0L2_GLOADB(0)
-    L0L2_SSTOREB(0)
+    // chunks past the last re-load the last one (in bounds, never staged)
+    const int64_t nch = kdim / 32, last = nch - 1;
+    L0L2_GLOADB(va0, vb0, 0)
+    L0L2_GLOADB(va1, vb1, last < 1 ? last : 1)
+    L0L2_SSTOREB(0, va0, vb0)
     __syncthreads();
-    for (int64_t c = 0; c < nch; ++c) {
-        const int st = (int)(c & 1);
-        const int64_t cn = c + 1 < nch ? c + 1 : c;
-        L0L2_GLOADB(cn)
-        const unsigned char *sa = smem + st * L::STAGE;
-        bf16x8 ah[WM], al[WM], bh[WN], bl[WN];
-#pragma unroll
-        for (int i = 0; i < WM; ++i) {
-            const unsigned char *row = sa + (wm * 16 * WM + 16 * i + r) * L::ROWB;
-            ah[i] = *reinterpret_cast<const bf16x8 *>(row + 16 * q);
-            al[i] = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);
-        }
-#pragma unroll
-        for (int j = 0; j < WN; ++j) {
-            const unsigned char *row = sa + (L::TM + wn * 16 * WN + 16 * j + r) * L::ROWB;
-            bh[j] = *reinterpret_cast<const bf16x8 *>(row + 16 * q);
-            bl[j] = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);
-        }
-#pragma unroll
-        for (int i = 0; i < WM; ++i)
-#pragma unroll
-            for (int j = 0; j < WN; ++j) {
-                acc[i][j] = mfma16_bf16(ah[i], bh[j], acc[i][j]);
-                acc[i][j] = mfma16_bf16(ah[i], bl[j], acc[i][j]);
-                acc[i][j] = mfma16_bf16(al[i], bh[j], acc[i][j]);
-            }
-        L0L2_SSTOREB(st ^ 1)
+    for (int64_t c = 0; c < nch; c += 2) {
+        L0L2_GLOADB(va0, vb0, c + 2 < last ? c + 2 : last)
+        L0L2_COMPUTEB(0)
+        __builtin_amdgcn_sched_barrier(0);
+        L0L2_SSTOREB(1, va1, vb1)
+        __syncthreads();
+        if (c + 1 >= nch) break;
+        L0L2_GLOADB(va1, vb1, c + 3 < last ? c + 3 : last)
+        L0L2_COMPUTEB(1)
+        __builtin_amdgcn_sched_barrier(0);
+        L0L2_SSTOREB(0, va0, vb0)
         __syncthreads();
     }
 #undef L0L2_GLOADB
 #undef L0L2_SSTOREB
+#undef L0L2_COMPUTEB
 }
 
 // BF16 split form, contraction over p, LDS-staged tile.  With gridDim.z = S > 1,
 // slice z takes the chunks [nch z / S, nch (z + 1) / S) of 32 k (the launcher
 // keeps S <= nch) and writes its partial product to U + z pstride.
 template <int WM, int WN>
-__global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restrict__ Ahi,
+__global__ __launch_bounds__(256, 2) void k_gemm_xw_bf16_lds(const __bf16 *__restrict__ Ahi,
                                                           const __bf16 *__restrict__ Alo, int64_t lda,
                                                           const float *__restrict__ B, int64_t ldb,
                                                           float *__restrict__ U, int64_t ldu, int64_t kdim,
@@ -1022,16 +1054,20 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16_lds(const __bf16 *__restri
 
 // BF16 split form, contraction over n with the FP32 ADMM epilogue (anch == 0)
 // or the anchored FP64 epilogue (anch == 1: Q = z_a + Q_bf16, FP64 state,
-// d = fl32(W - w_a) into dst32), LDS-staged tile.
+// d = fl32(W - w_a) into dst32), LDS-staged tile.  anch == 2: the first sweep
+// of a block of single-term sweeps (Gram form, FP32 state): the FP32 update as
+// for anch == 0, and this sweep's product and operand become the block's FP32
+// anchor (Za32 = G w, Wa32 = w) with the next operand d = bf16(W_new - w) in Dout.
 template <int WM, int WN, int ANCH>
-__global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
+__global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16_lds(
     const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
     int64_t ldu, int64_t kdim, const float *W32, float *W32out, float *__restrict__ beta32, float *__restrict__ V32,
     float *__restrict__ B32, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W64,
     double *__restrict__ beta64, double *__restrict__ V64, double *__restrict__ B64, const uint8_t *__restrict__ codes,
     const float *__restrict__ c32, const double *__restrict__ c64, const int *__restrict__ active,
     DevParams<float> q32, DevParams<double> q64, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga,
-    NodeCols ncl) {
+    NodeCols ncl, float *__restrict__ Za32 = nullptr, float *__restrict__ Wa32 = nullptr,
+    __bf16 *__restrict__ Dout = nullptr) {
     typedef LdsTileBf<WM, WN> L;
     __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
     const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
@@ -1053,7 +1089,7 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
         for (int t = 0; t < PN / 4; ++t) {
             const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
             double e[5] = {0, 0, 0, 0, 0};
-            if (ANCH) {
+            if (ANCH == 1) {
                 EpiIn<double> ei[E::H];
                 double za[E::H], wa[E::H];
                 epi_load_row<double, E::H>(ei, slot, n0 + nl, m0, ldp, W64, V64, codes, c64, active);
@@ -1082,9 +1118,16 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
                 for (int h = 0; h < E::H; ++h) {
                     if (!ei[h].on) continue;
                     const int m = lane + 64 * h;
+                    const int64_t o = (int64_t)slot * ldp + m0 + m;
                     double ev[5] = {0, 0, 0, 0, 0};
-                    admm_update<float>(buf[(nl - c0) * E::LD + m], ei[h], (int64_t)slot * ldp + m0 + m, W32out,
-                                       beta32, V32, B32, q32, store_b, est, ga, ev);
+                    const float qv = buf[(nl - c0) * E::LD + m];
+                    const float wn = admm_update<float>(qv, ei[h], o, W32out, beta32, V32, B32, q32, store_b, est,
+                                                        ga, ev);
+                    if (ANCH == 2) {
+                        Za32[o] = qv;
+                        Wa32[o] = ei[h].w;
+                        Dout[o] = (__bf16)(wn - ei[h].w);
+                    }
 #pragma unroll
                     for (int u = 0; u < 5; ++u) e[u] += ev[u];
                 }
@@ -1095,6 +1138,206 @@ __global__ __launch_bounds__(256) void k_admm_xtu_bf16_lds(
                     for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
             }
         }
+    }
+}
+
+// LDS-staged tile of the single-term BF16 form: A and B are BF16 arrays (one
+// term each); a k chunk of 64 stages the 128 bytes of each row (padded to 144 B,
+// the split form's geometry), and each 16x16x32 MFMA pair covers the chunk's two
+// 32-wide halves (lane l reads 8 consecutive k of row l % 16 in each half).  One
+// MFMA per 32 k of the product, a third of the split form's three.
+template <int WM, int WN>
+__device__ __forceinline__ void lds_tile_bf16s(const __bf16 *__restrict__ A, int64_t lda,
+                                               const __bf16 *__restrict__ B, int64_t ldb, int64_t kdim, int64_t m0,
+                                               int64_t n0, const NodeCols &ncl, unsigned char *smem,
+                                               f32x4 (&acc)[WM][WN]) {
+    typedef LdsTileBf<WM, WN> L;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int q = lane >> 4, r = lane & 15;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
+    // staged vector e of this thread: row idx / 8, bytes 16 (idx % 8) .. + 15 of the row's chunk
+    const unsigned char *ga[L::NA];
+    const unsigned char *gb[L::NB];
+    int la[L::NA], lb[L::NB];
+#pragma unroll
+    for (int e = 0; e < L::NA; ++e) {
+        const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
+        ga[e] = reinterpret_cast<const unsigned char *>(A + (m0 + row) * lda) + 16 * part;
+        la[e] = row * L::ROWB + 16 * part;
+    }
+#pragma unroll
+    for (int e = 0; e < L::NB; ++e) {
+        const int idx = tid + 256 * e, row = idx >> 3, part = idx & 7;
+        gb[e] = reinterpret_cast<const unsigned char *>(B + col_row(col_slot(ncl, n0 + row), n0 + row) * ldb) +
+                16 * part;
+        lb[e] = (L::TM + row) * L::ROWB + 16 * part;
+    }
+    // two register sets of staged vectors: the loads of chunk c + 2 are issued
+    // while chunk c is multiplied, and those of chunk c + 1 (a whole chunk
+    // earlier) are stored to the other LDS stage after it, so each chunk's loads
+    // have two chunks of MFMA work to arrive
+    f32x4 va0[L::NA], vb0[L::NB], va1[L::NA], vb1[L::NB];
+    // the staging loops index their arrays with compile-time constants (sfor),
+    // so the register sets never become stack arrays
+#define L0L2_GLOADS(VA, VB, c)                                                                              \
+    {                                                                                                       \
+        const int64_t off_ = 128 * (c);                                                                     \
+        sfor<L::NA>([&](auto e) { VA[e] = *reinterpret_cast<const f32x4 *>(ga[e] + off_); });             \
+        sfor<L::NB>([&](auto e) { VB[e] = *reinterpret_cast<const f32x4 *>(gb[e] + off_); });             \
+    }                                                                                                       \
+    __builtin_amdgcn_sched_barrier(0);
+#define L0L2_SSTORES(st, VA, VB)                                                                            \
+    sfor<L::NA>([&](auto e) { *reinterpret_cast<f32x4 *>(smem + (st) * L::STAGE + la[e]) = VA[e]; });     \
+    sfor<L::NB>([&](auto e) { *reinterpret_cast<f32x4 *>(smem + (st) * L::STAGE + lb[e]) = VB[e]; });
+#define L0L2_COMPUTES(st)                                                                                   \
+    {                                                                                                       \
+        const unsigned char *sa = smem + (st) * L::STAGE;                                                   \
+        bf16x8 b0[WN], b1[WN];                                                                              \
+        _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                                    \
+            const unsigned char *row = sa + (L::TM + wn * 16 * WN + 16 * j + r) * L::ROWB;                  \
+            b0[j] = *reinterpret_cast<const bf16x8 *>(row + 16 * q);                                        \
+            b1[j] = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);                                   \
+        }                                                                                                   \
+        _Pragma("unroll") for (int i = 0; i < WM; ++i) {                                                    \
+            const unsigned char *row = sa + (wm * 16 * WM + 16 * i + r) * L::ROWB;                          \
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(row + 16 * q);                              \
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(row + 64 + 16 * q);                         \
+            _Pragma("unroll") for (int j = 0; j < WN; ++j) {                                                \
+                acc[i][j] = mfma16_bf16(a0, b0[j], acc[i][j]);                                              \
+                acc[i][j] = mfma16_bf16(a1, b1[j], acc[i][j]);                                              \
+            }                                                                                               \
+        }                                                                                                   \
+    }
+    // chunks past the last re-load the last one (in bounds, never stored)
+    const int64_t nch = kdim / 64, last = nch - 1;
+    L0L2_GLOADS(va0, vb0, 0)
+    L0L2_GLOADS(va1, vb1, last < 1 ? last : 1)
+    L0L2_SSTORES(0, va0, vb0)
+    __syncthreads();
+    for (int64_t c = 0; c < nch; c += 2) {
+        // chunk c in LDS stage 0, chunk c + 1 in register set 1
+        L0L2_GLOADS(va0, vb0, c + 2 < last ? c + 2 : last)
+        L0L2_COMPUTES(0)
+        __builtin_amdgcn_sched_barrier(0);
+        L0L2_SSTORES(1, va1, vb1)
+        __syncthreads();
+        if (c + 1 >= nch) break;
+        // chunk c + 1 in LDS stage 1, chunk c + 2 in register set 0
+        L0L2_GLOADS(va1, vb1, c + 3 < last ? c + 3 : last)
+        L0L2_COMPUTES(1)
+        __builtin_amdgcn_sched_barrier(0);
+        L0L2_SSTORES(0, va0, vb0)
+        __syncthreads();
+    }
+#undef L0L2_GLOADS
+#undef L0L2_SSTORES
+#undef L0L2_COMPUTES
+}
+
+// Anchored single-term sweep of the Gram form: Q = z + G_bf16 d_bf16, where d is
+// the movement since the block's anchor (w = w_a + d) and z = G w_a.  MODE 1: FP32
+// state with the FP32 anchor (Za32, Wa32) of the block's first sweep; MODE 2:
+// FP64 state with the FP64 anchor (Za, Wa).  Both write the next operand
+// d = bf16(W_new - w_a) to Dout.  The product's rounding error scales with |d|,
+// which vanishes as the iterates settle, so the single BF16 term costs the
+// fixed point nothing that the anchor does not already fix.
+template <int WM, int WN, int MODE>
+__global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16s_lds(
+    const __bf16 *__restrict__ A, int64_t lda, const __bf16 *__restrict__ Din, __bf16 *__restrict__ Dout,
+    int64_t kdim, const float *W32, float *W32out, float *__restrict__ beta32, float *__restrict__ V32,
+    float *__restrict__ B32, const float *__restrict__ Za32, const float *__restrict__ Wa32,
+    const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W64,
+    double *__restrict__ beta64, double *__restrict__ V64, double *__restrict__ B64, const uint8_t *__restrict__ codes,
+    const float *__restrict__ c32, const double *__restrict__ c64, const int *__restrict__ active,
+    DevParams<float> q32, DevParams<double> q64, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga,
+    NodeCols ncl) {
+    typedef LdsTileBf<WM, WN> L;
+    __shared__ __align__(16) unsigned char smem[2 * L::STAGE];
+    const int64_t m0 = (int64_t)blockIdx.x * L::TM, n0 = (int64_t)blockIdx.y * L::TN;
+    if (col_slot(ncl, n0) < 0) return;
+    f32x4 acc[WM][WN];
+    lds_tile_bf16s<WM, WN>(A, lda, Din, ldp, kdim, m0, n0, ncl, smem, acc);
+    const bool est = gpart != nullptr;
+    typedef LdsEpi<float, WM, WN> E;
+    constexpr int NP = E::passes(sizeof(smem));
+    static_assert(NP > 0, "epilogue staging does not fit");
+    constexpr int PN = L::TN / NP;
+    float *buf = reinterpret_cast<float *>(smem);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int pass = 0; pass < NP; ++pass) {
+        const int c0 = pass * PN;
+        __syncthreads();
+        acc_stage<float, WM, WN>(acc, buf, c0, PN);
+        __syncthreads();
+        for (int t = 0; t < PN / 4; ++t) {
+            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+            double e[5] = {0, 0, 0, 0, 0};
+            if (MODE == 2) {
+                EpiIn<double> ei[E::H];
+                double za[E::H], wa[E::H];
+                epi_load_row<double, E::H>(ei, slot, n0 + nl, m0, ldp, W64, V64, codes, c64, active);
+#pragma unroll
+                for (int h = 0; h < E::H; ++h) {
+                    const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
+                    za[h] = Za[o];
+                    wa[h] = Wa[o];
+                }
+#pragma unroll
+                for (int h = 0; h < E::H; ++h) {
+                    if (!ei[h].on) continue;
+                    const int m = lane + 64 * h;
+                    const int64_t o = (int64_t)slot * ldp + m0 + m;
+                    double ev[5] = {0, 0, 0, 0, 0};
+                    const double wn = admm_update<double>(za[h] + (double)buf[(nl - c0) * E::LD + m], ei[h], o, W64,
+                                                          beta64, V64, B64, q64, store_b, est, ga, ev);
+                    Dout[o] = (__bf16)(float)(wn - wa[h]);
+#pragma unroll
+                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
+                }
+            } else {
+                EpiIn<float> ei[E::H];
+                float za[E::H], wa[E::H];
+                epi_load_row<float, E::H>(ei, slot, n0 + nl, m0, ldp, W32, V32, codes, c32, active);
+#pragma unroll
+                for (int h = 0; h < E::H; ++h) {
+                    const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
+                    za[h] = Za32[o];
+                    wa[h] = Wa32[o];
+                }
+#pragma unroll
+                for (int h = 0; h < E::H; ++h) {
+                    if (!ei[h].on) continue;
+                    const int m = lane + 64 * h;
+                    const int64_t o = (int64_t)slot * ldp + m0 + m;
+                    double ev[5] = {0, 0, 0, 0, 0};
+                    const float wn = admm_update<float>(za[h] + buf[(nl - c0) * E::LD + m], ei[h], o, W32out, beta32,
+                                                        V32, B32, q32, store_b, est, ga, ev);
+                    Dout[o] = (__bf16)(wn - wa[h]);
+#pragma unroll
+                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
+                }
+            }
+            if (est) {
+                wave_sum5(e);
+                if (lane == 0 && slot >= 0)
+                    for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
+            }
+        }
+    }
+}
+
+// Start of an anchored single-term block (FP64 state): w_a = W (FP64) and the
+// operand of the block's first sweep d = 0.
+__global__ void k_anchor_init_bf(const double *__restrict__ W, double *__restrict__ Wa, __bf16 *__restrict__ d,
+                                 int64_t total) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; idx < total; idx += (int64_t)gridDim.x * blockDim.x) {
+        Wa[idx] = W[idx];
+        d[idx] = (__bf16)0.0f;
     }
 }
 
@@ -2513,7 +2756,11 @@ void sweep_once_gram(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bo
     HIPCHK(hipGetLastError());
 }
 
-// Start of an anchored Gram-form block: w_a = W (FP64), d = 0 in ws.W, z_a = G w_a.
+bool bf16_single(l0l2_ctx *ctx, int64_t cols);
+__bf16 *dbf_in(l0l2_ctx *ctx, int t);
+
+// Start of an anchored Gram-form block: w_a = W (FP64), d = 0 (in ws.W, or in
+// the BF16 operand of single-term sweeps), z_a = G w_a.
 void anchor_start_gram(l0l2_ctx *ctx, int64_t Kp, int64_t cols) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
@@ -2523,8 +2770,12 @@ void anchor_start_gram(l0l2_ctx *ctx, int64_t Kp, int64_t cols) {
     const TileChoice &tc = tile_choice<double>(ctx, s64, cols);
     prof_begin(ctx, PROF_ANCHOR);
     const int64_t ldp = in.ldp;
-    hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
-                       Kp * ldp);
+    if (bf16_single(ctx, cols))
+        hipLaunchKernelGGL(k_anchor_init_bf, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(),
+                           dbf_in(ctx, 1), Kp * ldp);
+    else
+        hipLaunchKernelGGL(k_anchor_init, dim3(grid1d(Kp * ldp)), dim3(256), 0, s, s64.W, ws.Wa.as<double>(), s32.W,
+                           Kp * ldp);
     const int v = tc.z2 >= 0 ? tc.z2 : (split_of(tc.xw) > 1 ? tc.xtu : tc.xw);
     launch_xw<double, double, double>(v, s, in.G64.as<double>(), in.ldg64, ws.Wa.as<double>(), ldp,
                                       ws.Za.as<double>(), ldp, in.pp, cols, in.pp, active_cols(ctx));
@@ -2553,16 +2804,92 @@ void sweep_once_anch_gram(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t activ
     HIPCHK(hipGetLastError());
 }
 
-// One Gram-form sweep in the BF16 split form (anch: the anchored FP64 update,
-// the node operand d).
+// Single-term BF16 blocks of the Gram form (the default where the LDS-staged
+// tiles are chosen): each block is anchored and its sweeps multiply only the
+// movement d since the anchor, with one BF16 term of G and of d (one MFMA per
+// product instead of the split form's three).  FP32 phase: the block's first
+// sweep is a split-form sweep whose product and operand become the FP32 anchor;
+// FP64 phase: the FP64 anchor of anchor_start_gram.  Operand d alternates
+// between two BF16 buffers: sweep t reads Dbf[t & 1] and writes Dbf[(t + 1) & 1].
+bool bf16_single(l0l2_ctx *ctx, int64_t cols) {
+    const Instance &in = ctx->inst;
+    return in.prec == L0L2_BF16 && ctx->bf16_terms == 1 && gram_form(ctx) && tile_choice_bf16(ctx, cols).xtu >= 1;
+}
+
+__bf16 *dbf_in(l0l2_ctx *ctx, int t) { return ctx->ws.Dbf[t & 1].as<__bf16>(); }
+__bf16 *dbf_out(l0l2_ctx *ctx, int t) { return ctx->ws.Dbf[(t + 1) & 1].as<__bf16>(); }
+
+// mode 1: FP32 state and anchor; mode 2: FP64 state and anchor.
+void launch_xtu_bf16s(int v, l0l2_ctx *ctx, int mode, int64_t Kp, int store_b, double *gpart, NodeCols ncl, int t) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    if (v < 1 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    dim3 g((unsigned)(in.pp / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    const DevParams<float> q32 = dev_params<float>(in.mp);
+    const DevParams<double> q64 = dev_params<double>(in.mp);
+    const GateArgs ga = gate_args(in);
+    const __bf16 *A = in.Ghi.as<__bf16>();
+    const float *wr = gram_in(ctx, t);
+    float *ww = gram_out(ctx, t);
+#define L0L2_XTUS(WM, WN, MODE)                                                                                    \
+    hipLaunchKernelGGL((k_admm_xtu_bf16s_lds<WM, WN, MODE>), g, dim3(256), 0, ctx->stream, A, in.ldgb,             \
+                       (const __bf16 *)dbf_in(ctx, t), dbf_out(ctx, t), in.pp, wr, ww, s32.beta, s32.V, s32.B,     \
+                       ws.Za32.as<float>(), ws.Wa32.as<float>(), ws.Za.as<double>(), ws.Wa.as<double>(), s64.W,   \
+                       s64.beta, s64.V, s64.B, ws.codes.as<uint8_t>(), s32.c, s64.c, ws.active.as<int>(), q32,   \
+                       q64, in.ldp, store_b, gpart, ga, ncl)
+    if (v == 1) {
+        if (mode == 2) L0L2_XTUS(2, 2, 2);
+        else L0L2_XTUS(2, 2, 1);
+    } else {
+        if (mode == 2) L0L2_XTUS(4, 4, 2);
+        else L0L2_XTUS(4, 4, 1);
+    }
+#undef L0L2_XTUS
+}
+
+// The first sweep of an FP32-phase single-term block: a split-form sweep that
+// also writes the block's FP32 anchor (z = G w in Za32, w in Wa32) and d.
+void launch_xtu_bf16_start(int v, l0l2_ctx *ctx, int64_t Kp, int store_b, double *gpart, NodeCols ncl, int t) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    if (v < 1 || v >= kShapesBf16 || Kp % kBfTN[v] != 0) fail(L0L2_E_INVALID, "tile shape does not fit the batch");
+    dim3 g((unsigned)(in.pp / kBfTM[v]), (unsigned)(Kp / kBfTN[v]));
+    Sweep<float> s32 = sweep32(ctx);
+    Sweep<double> s64 = sweep64(ctx);
+    const DevParams<float> q32 = dev_params<float>(in.mp);
+    const DevParams<double> q64 = dev_params<double>(in.mp);
+    const GateArgs ga = gate_args(in);
+    const float *wr = gram_in(ctx, t);
+    float *ww = gram_out(ctx, t);
+#define L0L2_XTUA(WM, WN)                                                                                          \
+    hipLaunchKernelGGL((k_admm_xtu_bf16_lds<WM, WN, 2>), g, dim3(256), 0, ctx->stream, in.Ghi.as<__bf16>(),        \
+                       in.Glo.as<__bf16>(), in.ldgb, wr, in.ldp, in.pp, wr, ww, s32.beta, s32.V, s32.B,           \
+                       ws.Za.as<double>(), ws.Wa.as<double>(), s64.W, s64.beta, s64.V, s64.B,                     \
+                       ws.codes.as<uint8_t>(), s32.c, s64.c, ws.active.as<int>(), q32, q64, in.ldp, store_b,      \
+                       gpart, ga, ncl, ws.Za32.as<float>(), ws.Wa32.as<float>(), dbf_out(ctx, t))
+    if (v == 1) L0L2_XTUA(2, 2);
+    else L0L2_XTUA(4, 4);
+#undef L0L2_XTUA
+}
+
+// One Gram-form sweep in BF16 mode (anch: the anchored FP64 update).  Split form
+// in every sweep, or single-term blocks (bf16_single).
 void sweep_once_bf16_gram(l0l2_ctx *ctx, int64_t Kp, bool store_b, int64_t active, bool gate, bool anch, int t) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     const TileChoice &tc = tile_choice_bf16(ctx, Kp);
-    const GramBf gr{in.Ghi.as<__bf16>(), in.Glo.as<__bf16>(), in.ldgb, gram_in(ctx, t), gram_out(ctx, t)};
+    double *gp = gate ? ws.gpart.as<double>() : nullptr;
     prof_begin(ctx, PROF_ADMM_XTU_BF16);
-    launch_xtu_bf16(tc.xtu, ctx, anch, Kp, ws.active.as<int>(), store_b ? 1 : 0, gate ? ws.gpart.as<double>() : nullptr,
-                    active_cols(ctx), &gr);
+    if (bf16_single(ctx, Kp)) {
+        if (anch) launch_xtu_bf16s(tc.xtu, ctx, 2, Kp, store_b ? 1 : 0, gp, active_cols(ctx), t);
+        else if (t == 1) launch_xtu_bf16_start(tc.xtu, ctx, Kp, store_b ? 1 : 0, gp, active_cols(ctx), t);
+        else launch_xtu_bf16s(tc.xtu, ctx, 1, Kp, store_b ? 1 : 0, gp, active_cols(ctx), t);
+    } else {
+        const GramBf gr{in.Ghi.as<__bf16>(), in.Glo.as<__bf16>(), in.ldgb, gram_in(ctx, t), gram_out(ctx, t)};
+        launch_xtu_bf16(tc.xtu, ctx, anch, Kp, ws.active.as<int>(), store_b ? 1 : 0, gp, active_cols(ctx), &gr);
+    }
     prof_end(ctx, PROF_ADMM_XTU_BF16, active);
     HIPCHK(hipGetLastError());
 }
@@ -3046,6 +3373,14 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
         ws.B64.ensure(8 * Kp * ldp);
         ws.U64.ensure(8 * Kp * in.ldu64);
         HIPCHK(hipMemsetAsync(ws.B64.ptr, 0, 8 * Kp * ldp, ctx->stream));
+    }
+    if (in.prec == L0L2_BF16) {
+        ws.Wa32.ensure(4 * Kp * ldp);
+        ws.Za32.ensure(4 * Kp * ldp);
+        for (int i = 0; i < 2; ++i) {
+            ws.Dbf[i].ensure(2 * Kp * ldp);
+            HIPCHK(hipMemsetAsync(ws.Dbf[i].ptr, 0, 2 * Kp * ldp, ctx->stream));
+        }
     }
     // inactive padded rows must read as zeros on first use
     HIPCHK(hipMemsetAsync(ws.W.ptr, 0, sb * Kp * ldp, ctx->stream));

@@ -367,6 +367,18 @@ int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form) {
     });
 }
 
+int l0l2_set_bf16_terms(l0l2_ctx *ctx, int terms) {
+    return guarded(ctx, [&] {
+        if (terms != 1 && terms != 3) l0l2::fail(L0L2_E_INVALID, "terms is 1 (single-term blocks) or 3 (split)");
+        if (ctx->bf16_terms != terms) {
+            // captured blocks hold the sweeps they were captured with
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            l0l2::drop_graphs(ctx);
+        }
+        ctx->bf16_terms = terms;
+    });
+}
+
 int l0l2_profile_enable(l0l2_ctx *ctx, int enable) {
     return guarded(ctx, [&] {
         l0l2::prof_collect(ctx);

@@ -128,6 +128,8 @@ struct Workspace {
     DevBuf W64, beta64, V64, B64;  // FP32 / BF16 mode: FP64 state of the anchored sweeps (Kp rows of ldp)
     DevBuf U64;                    // FP32 / BF16 mode: Kp rows of ldu64
     DevBuf Wa, Za;                 // FP32 / BF16 mode: anchor w_a and Xh^T Xh w_a (Kp rows of ldp, FP64)
+    DevBuf Wa32, Za32;             // BF16 mode: FP32 anchor of a block of single-term Gram sweeps (Kp rows of ldp)
+    DevBuf Dbf[2];                 // BF16 mode: BF16 operand d = W - w_a of the single-term sweeps, alternating
     DevBuf R;                      // Kp rows of ldu64: FP64 residuals of the gap check
     DevBuf codes;                  // Kp rows of ldp, uint8
     DevBuf rpart;                  // Kp x (np/32) x 4 doubles: row-tile sums of the gap check
@@ -196,6 +198,7 @@ struct l0l2_ctx {
     bool tune = true;          // time the tile shapes of each new batch size
     int force_xw = -1, force_xtu = -1;   // fixed tile shapes (-1: autotune)
     int bform = 0;                       // b-update form: 0 auto, 1 folded operand (two contractions), 2 Gram
+    int bf16_terms = 1;                  // BF16 Gram sweeps: 1 single-term anchored blocks, 3 split every sweep
     bool use_graphs = true;              // replay captured blocks of sweeps
     std::string noalloc_err;             // why the allocation-free scratch is unavailable (empty: it is)
     std::map<l0l2::GraphKey, hipGraphExec_t> graphs;
