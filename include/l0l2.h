@@ -20,7 +20,15 @@
  *    coordinate in F0) or L0L2_FIX1 (z = 1, coordinate in F1).
  *  - "Device" buffers are caller-owned GPU memory on the context's device; the
  *    library reads and writes them on the context's stream and never frees them.
- *  - A context is used by one host thread at a time.
+ *  - A context is used by one host thread at a time (l0l2_cancel excepted).
+ *  - Synchronisation: work runs on the context's stream, ordered after what the
+ *    caller's stream (given to l0l2_create) holds at the call and before what it
+ *    receives afterwards.  l0l2_admm_sweeps, l0l2_dual_bound, l0l2_round_branch
+ *    and the refinement entry points return without waiting for the device.
+ *    l0l2_solve_node_batch waits at the end of every block of check_every sweeps
+ *    (the host reads two counters there to switch precision and to stop) but not
+ *    for its final copies; l0l2_set_data, l0l2_bnb_solve, l0l2_matching_pursuit,
+ *    l0l2_exact_objective and the server calls return host results and wait.
  */
 #ifndef L0L2_H
 #define L0L2_H
@@ -40,6 +48,7 @@ enum {
     L0L2_E_DEVICE = -4,      /* a HIP runtime call failed */
     L0L2_E_NUMERIC = -5,     /* factorisation failed (matrix not positive definite) */
     L0L2_E_TIMEOUT = -6,     /* time limit reached before certification */
+    L0L2_E_CANCELLED = -7,   /* stopped by l0l2_cancel / l0l2_server_cancel */
     L0L2_E_UNSUPPORTED = -8  /* option not available in this build */
 };
 
@@ -261,6 +270,7 @@ typedef struct l0l2_server l0l2_server;
 typedef struct {
     double submit_s, admit_s, done_s;   /* seconds since the server was created */
     size_t footprint_bytes;             /* reserved from the HBM budget while running */
+    size_t peak_bytes;                  /* device bytes its context held at most (l0l2_memory_stats) */
 } l0l2_request_stats;
 
 /* Create a server on `device`.  hbm_budget_bytes bounds the summed footprints
@@ -284,7 +294,17 @@ int l0l2_server_submit(l0l2_server *srv, const double *X, const double *y, int64
 int l0l2_server_wait(l0l2_server *srv, int64_t req_id, double timeout_s, l0l2_bnb_result *out,
                      l0l2_request_stats *stats);
 const char *l0l2_server_last_error(const l0l2_server *srv);
-/* Stop admitting, drop queued requests, wait for running ones, free all. */
+/* Cancel request req_id: a queued request ends at once with L0L2_E_CANCELLED
+ * (its wait returns that code); a running one stops at its next batch and ends
+ * the same way; a finished one is left as it is.  L0L2_E_INVALID for an unknown
+ * or already collected id. */
+int l0l2_server_cancel(l0l2_server *srv, int64_t req_id);
+/* Stop admitting, end queued requests as cancelled, ask running ones to stop
+ * (they end cancelled at their next batch), wait for the workers and for the
+ * threads already inside l0l2_server_wait, free all.  No call on srv may start
+ * once destroy has begun.  Server contexts choose tile shapes by a size rule
+ * (no timing under contention), so an instance runs the same kernels alone and
+ * beside others. */
 int l0l2_server_destroy(l0l2_server *srv);
 
 /* Tile shapes of the two sweep contractions (output rows x nodes / waves):
@@ -325,6 +345,23 @@ int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
  * FP64 (the anchors), then FP32 (FP32 mode) or a BF16 hi/lo pair of its FP32
  * value (BF16 mode), on the first solve that uses it. */
 int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form);
+
+/* Device memory the library holds (device allocations of its calls; caller-owned
+ * buffers are not counted): for ctx, the buffers that calls on ctx allocated
+ * (instance copies, factors, workspace, and the transient buffers of each
+ * call while they live); for ctx == NULL, the whole process.  *in_use: bytes
+ * held now; *peak: the largest in_use since the counter was created or last
+ * reset; reset_peak != 0 then sets peak to in_use.  Either pointer may be
+ * NULL.  Safe to call from any thread. */
+int l0l2_memory_stats(l0l2_ctx *ctx, size_t *in_use, size_t *peak, int reset_peak);
+
+/* Ask the call running on ctx (or, if none is running, the next one) to stop:
+ * l0l2_solve_node_batch, l0l2_bnb_solve and l0l2_matching_pursuit test the
+ * request at each block of sweeps, batch or group of steps and then return
+ * L0L2_E_CANCELLED (outputs unspecified, the context stays usable); the
+ * request is consumed by that return.  The one entry point that may be called
+ * from another thread than the one using ctx. */
+int l0l2_cancel(l0l2_ctx *ctx);
 
 /* Products of the BF16 Gram-form sweeps.  3: every sweep multiplies with the
  * split form (G as a BF16 hi/lo pair times the node operand split into two

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libl0l2.so")
 
 L0L2_OK, L0L2_E_INVALID, L0L2_E_NODATA, L0L2_E_OOM = 0, -1, -2, -3
-L0L2_E_DEVICE, L0L2_E_NUMERIC, L0L2_E_TIMEOUT, L0L2_E_UNSUPPORTED = -4, -5, -6, -8
+L0L2_E_DEVICE, L0L2_E_NUMERIC, L0L2_E_TIMEOUT, L0L2_E_CANCELLED, L0L2_E_UNSUPPORTED = -4, -5, -6, -7, -8
 L0L2_FP64, L0L2_FP32, L0L2_BF16, L0L2_FP8 = 0, 1, 2, 3
 L0L2_FREE, L0L2_FIX0, L0L2_FIX1 = 0, 1, 2
 L0L2_BEST_FIRST, L0L2_DFS = 0, 1
@@ -55,7 +55,7 @@ class l0l2_bnb_result(C.Structure):
 
 class l0l2_request_stats(C.Structure):
     _fields_ = [("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
-                ("footprint_bytes", C.c_size_t)]
+                ("footprint_bytes", C.c_size_t), ("peak_bytes", C.c_size_t)]
 
 
 _vp, _i, _i64, _d = C.c_void_p, C.c_int, C.c_int64, C.c_double
@@ -81,10 +81,13 @@ SIGNATURES = {
     "l0l2_server_wait": (_i, [_vp, _i64, _d, C.POINTER(l0l2_bnb_result), C.POINTER(l0l2_request_stats)]),
     "l0l2_server_last_error": (C.c_char_p, [_vp]),
     "l0l2_server_destroy": (_i, [_vp]),
+    "l0l2_server_cancel": (_i, [_vp, _i64]),
+    "l0l2_memory_stats": (_i, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), _i]),
     "l0l2_set_tiles": (_i, [_vp, _i, _i]),
     "l0l2_tune_batch_size": (_i, [_vp, _i, _d, C.POINTER(_i), _vp, C.POINTER(_i)]),
     "l0l2_set_bupdate_form": (_i, [_vp, _i]),
     "l0l2_set_bf16_terms": (_i, [_vp, _i]),
+    "l0l2_cancel": (_i, [_vp]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
     "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
 }
@@ -288,6 +291,14 @@ class Context:
             raise ValueError(f"b-update form must be one of {sorted(forms)}, not {form!r}")
         self._check(lib.l0l2_set_bupdate_form(self._h, forms[form]))
 
+    def memory_stats(self, reset_peak=False):
+        """(bytes held now, peak bytes) of the device buffers this context's calls allocated."""
+        return memory_stats(self, reset_peak)
+
+    def cancel(self):
+        """Ask the running (or next) long call on this context to stop with L0L2_E_CANCELLED."""
+        self._check(lib.l0l2_cancel(self._h))
+
     def set_bf16_terms(self, terms=1):
         """BF16 Gram-form sweeps: 1 single-term anchored blocks (default), 3 split form in every sweep."""
         self._check(lib.l0l2_set_bf16_terms(self._h, int(terms)))
@@ -330,6 +341,14 @@ class Context:
         return dict(ub=r.ub, certified=r.certified, lb=r.lb, nodes_solved=r.nodes_solved,
                     nodes_pruned=r.nodes_pruned, batches=r.batches, seconds=r.seconds, status=r.status,
                     support=support, beta=beta, trace=trace)
+
+
+def memory_stats(ctx=None, reset_peak=False):
+    """(bytes held now, peak bytes) of the library's device buffers: of one
+    Context, or of the whole process (ctx None)."""
+    a, b = C.c_size_t(), C.c_size_t()
+    lib.l0l2_memory_stats(ctx._h if ctx is not None else None, C.byref(a), C.byref(b), 1 if reset_peak else 0)
+    return a.value, b.value
 
 
 def bnb_options(K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000, check_every=10,
@@ -381,6 +400,9 @@ class Server:
         r = l0l2_bnb_result()
         st = l0l2_request_stats()
         rc = lib.l0l2_server_wait(self._h, int(rid), float(timeout_s), C.byref(r), C.byref(st))
+        if rc == L0L2_E_CANCELLED:
+            # the server may be being destroyed by another thread: do not call into it again
+            raise L0L2Error(rc, "request cancelled")
         if rc != L0L2_OK:
             raise L0L2Error(rc, lib.l0l2_server_last_error(self._h).decode())
         try:
@@ -388,8 +410,13 @@ class Server:
         finally:
             lib.l0l2_result_free(C.byref(r))
         out.update(submit_s=st.submit_s, admit_s=st.admit_s, done_s=st.done_s,
-                   footprint_bytes=st.footprint_bytes)
+                   footprint_bytes=st.footprint_bytes, peak_bytes=st.peak_bytes)
         return out
+
+    def cancel(self, rid):
+        rc = lib.l0l2_server_cancel(self._h, int(rid))
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, "unknown or collected request")
 
     def close(self):
         if getattr(self, "_h", None):

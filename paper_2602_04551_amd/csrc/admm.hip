@@ -2316,6 +2316,14 @@ SplitBuf split_buf(l0l2_ctx *ctx) { return SplitBuf{ctx->ws.Upart.ptr, ctx->ws.U
 // is timed on the live batch (every node masked inactive, so the epilogue
 // writes nothing), the best of several interleaved samples per shape, and the
 // fastest kept for this instance.
+// Shapes without timing (contexts whose timings would vary, such as the
+// server's under contention): the LDS-staged 128 x 128 tiles when both
+// contractions' grids of them hold at least one workgroup per compute unit,
+// else the 32 x 32 register tile (shape 0), whatever the load.
+bool big_batch_rule(const Instance &in, int64_t Kp) {
+    return Kp % 128 == 0 && (in.np / 128) * (Kp / 128) >= 256 && (in.pp / 128) * (Kp / 128) >= 256;
+}
+
 template <class T>
 TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
     Instance &in = ctx->inst;
@@ -2398,6 +2406,7 @@ TileChoice &tile_choice(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t Kp) {
         (void)hipEventDestroy(e1);
         HIPCHK(hipGetLastError());
     }
+    if (!ctx->tune && big_batch_rule(in, Kp)) tc.xw = tc.xtu = 11;   // LDS-staged 128 x 128
     return in.tiles[key] = tc;
 }
 
@@ -2606,6 +2615,7 @@ TileChoice &tile_choice_bf16(l0l2_ctx *ctx, int64_t Kp) {
         (void)hipEventDestroy(e1);
         HIPCHK(hipGetLastError());
     }
+    if (!ctx->tune && big_batch_rule(in, Kp)) tc.xw = tc.xtu = 2;    // LDS-staged 128 x 128
     return in.tiles[key] = tc;
 }
 
@@ -3029,6 +3039,7 @@ TileChoice tile_choice_fp8(l0l2_ctx *ctx, int64_t Kp) {
         (void)hipEventDestroy(e1);
         HIPCHK(hipGetLastError());
     }
+    if (!ctx->tune && big_batch_rule(in, Kp)) tc.xtu = 2;            // LDS-staged 128 x 128
     return in.tiles[key] = tc;
 }
 
@@ -3256,6 +3267,7 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
     int cnt[2];
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
+        check_cancel(ctx);
         const int n = std::min(m, o.max_iter - t);
         run_block(ctx, sizeof(T) == 8 ? SK_F64 : SK_F32, Kp, n, o.tol_node, o.tol_node, active,
                   t + n >= o.max_iter, cnt);
@@ -3295,6 +3307,7 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     int cnt[2], best_above = 1 << 30, flat = 0;
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
+        check_cancel(ctx);
         const int n = std::min(m, o.max_iter - t);
         const int kind = fp64 ? SK_ANCH : (bf16 ? SK_BF16 : SK_F32);
         run_block(ctx, kind, Kp, n, o.tol_node, switch_tol, active, t + n >= o.max_iter, cnt);

@@ -24,10 +24,25 @@ void drop_graphs(l0l2_ctx *ctx) {
     ctx->graphs.clear();
 }
 
+MemCount &global_mem() {
+    static MemCount m;
+    return m;
+}
+
+MemCount *&thread_mem() {
+    static thread_local MemCount *m = nullptr;
+    return m;
+}
+
 void DevBuf::release() {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) {
+        (void)hipFree(ptr);
+        global_mem().sub(bytes);
+        if (charged) charged->sub(bytes);
+    }
     ptr = nullptr;
     bytes = 0;
+    charged = nullptr;
 }
 
 void DevBuf::ensure(size_t b) {
@@ -41,6 +56,9 @@ void DevBuf::ensure(size_t b) {
         fail(L0L2_E_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
     }
     bytes = b;
+    global_mem().add(b);
+    charged = thread_mem();
+    if (charged) charged->add(b);
 }
 
 }  // namespace l0l2
@@ -60,6 +78,12 @@ int guarded(l0l2_ctx *ctx, F &&f) {
         if (hipEventRecord(ctx->ev_out, ctx->stream) == hipSuccess)
             (void)hipStreamWaitEvent(ctx->user_stream, ctx->ev_out, 0);
     };
+    // allocations made by this call are charged to ctx
+    struct Charge {
+        l0l2::MemCount *prev;
+        explicit Charge(l0l2::MemCount *m) : prev(l0l2::thread_mem()) { l0l2::thread_mem() = m; }
+        ~Charge() { l0l2::thread_mem() = prev; }
+    } charge(&ctx->mem);
     try {
         if (hipSetDevice(ctx->device) != hipSuccess) l0l2::fail(L0L2_E_DEVICE, "hipSetDevice failed");
         HIPCHK(hipEventRecord(ctx->ev_in, ctx->user_stream));
@@ -190,7 +214,6 @@ int l0l2_admm_sweeps(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta, voi
         l0l2::load_batch(ctx, K, codes, beta, v, false);
         l0l2::run_sweeps(ctx, K, sweeps, true);
         l0l2::store_batch(ctx, K, beta, v, b_out);
-        HIPCHK(hipStreamSynchronize(ctx->stream));
     });
 }
 
@@ -208,7 +231,6 @@ int l0l2_dual_bound(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *b, d
         HIPCHK(hipMemcpyAsync(ws.B.ptr, ws.beta.ptr, sb * Kp * ctx->inst.ldp, hipMemcpyDeviceToDevice, ctx->stream));
         l0l2::run_dual_bound(ctx, K, nullptr);
         HIPCHK(hipMemcpyAsync(lb, ws.lb.ptr, sizeof(double) * K, hipMemcpyDeviceToDevice, ctx->stream));
-        HIPCHK(hipStreamSynchronize(ctx->stream));
     });
 }
 
@@ -231,7 +253,6 @@ int l0l2_solve_node_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta
         HIPCHK(hipMemcpyAsync(primal, ws.primal.ptr, sizeof(double) * K, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(iters, ws.iters.ptr, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(status, ws.status.ptr, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
     });
 }
 
@@ -243,11 +264,13 @@ int l0l2_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *be
         if (K == 0) return;
         if (!codes || !beta || !support || !support_size || !branch_j || !z_up)
             l0l2::fail(L0L2_E_INVALID, "null buffer");
-        l0l2::DevBuf nfree;
-        nfree.ensure(sizeof(int32_t) * K);
+        // free-coordinate counts go to a context buffer (grown, never freed in the call)
+        if (ctx->ws.nfree.bytes < sizeof(int32_t) * (size_t)K) {
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            ctx->ws.nfree.ensure(sizeof(int32_t) * (size_t)K);
+        }
         l0l2::run_round_branch(ctx, K, codes, ctx->inst.p, beta, ctx->inst.p, support, support_size, branch_j, z_up,
-                               nfree.as<int32_t>());
-        HIPCHK(hipStreamSynchronize(ctx->stream));
+                               ctx->ws.nfree.as<int32_t>());
     });
 }
 
@@ -262,7 +285,6 @@ int l0l2_refine_incumbent(l0l2_ctx *ctx, int K, const uint8_t *support, const vo
         const int64_t p = ctx->inst.p;
         l0l2::state_to_f64(ctx, K, beta_start, p, beta_out, p);
         l0l2::run_fista(ctx, K, support, p, beta_out, p, *opts, obj, iters);
-        HIPCHK(hipStreamSynchronize(ctx->stream));
     });
 }
 
@@ -365,6 +387,20 @@ int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form) {
         }
         ctx->bform = form;
     });
+}
+
+int l0l2_memory_stats(l0l2_ctx *ctx, size_t *in_use, size_t *peak, int reset_peak) {
+    l0l2::MemCount &m = ctx ? ctx->mem : l0l2::global_mem();
+    if (in_use) *in_use = m.in_use.load();
+    if (peak) *peak = m.peak.load();
+    if (reset_peak) m.peak.store(m.in_use.load());
+    return L0L2_OK;
+}
+
+int l0l2_cancel(l0l2_ctx *ctx) {
+    if (!ctx) return L0L2_E_INVALID;
+    ctx->cancel.store(1);
+    return L0L2_OK;
 }
 
 int l0l2_set_bf16_terms(l0l2_ctx *ctx, int terms) {

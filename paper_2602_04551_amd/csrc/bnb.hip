@@ -120,6 +120,7 @@ struct DevicePool {
         HIPCHK(hipStreamSynchronize(st));
         std::swap(buf.ptr, nb.ptr);
         std::swap(buf.bytes, nb.bytes);
+        std::swap(buf.charged, nb.charged);
         cap = ncap;
     }
 };
@@ -178,6 +179,7 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
     std::vector<std::pair<int, int64_t>> saves;
 
     while (!core.frontier_empty()) {
+        check_cancel(ctx);
         if ((status = core.gap_reached()) != 0) break;
         if (o.time_limit_s > 0 && std::chrono::duration<double>(clock::now() - t0).count() > o.time_limit_s) {
             status = 3;

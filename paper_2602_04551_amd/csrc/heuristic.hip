@@ -205,6 +205,7 @@ void run_matching_pursuit(l0l2_ctx *ctx, int max_moves, uint8_t *mask_host, doub
     // 2 (max_moves + 1) steps are needed
     const int64_t max_steps = 2 * ((int64_t)max_moves + 1);
     for (int64_t done_steps = 0; done_steps < max_steps; done_steps += kMpGroup) {
+        check_cancel(ctx);
         for (int g = 0; g < kMpGroup; ++g) {
             hipLaunchKernelGGL(k_mp_scores, dim3((unsigned)nparts), dim3(64 * kMpWaves), 0, s, in.X64.as<double>(),
                                (const double *)r.ptr, (const double *)beta.ptr, (const uint8_t *)mask.ptr,

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <string>
@@ -41,10 +42,27 @@ struct Error {
 void hip_check(hipError_t e, const char *what);
 #define HIPCHK(x) ::l0l2::hip_check((x), #x)
 
+// Device bytes the library holds: process-wide, and per context (charged to the
+// context whose call allocated the buffer: the calling thread's current context).
+struct MemCount {
+    std::atomic<size_t> in_use{0}, peak{0};
+    void add(size_t b) {
+        const size_t now = in_use.fetch_add(b) + b;
+        size_t pk = peak.load();
+        while (now > pk && !peak.compare_exchange_weak(pk, now)) {
+        }
+    }
+    void sub(size_t b) { in_use.fetch_sub(b); }
+};
+MemCount &global_mem();
+// The context whose entry point runs on this thread (null outside calls).
+MemCount *&thread_mem();
+
 // Device buffer owned by the library.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    MemCount *charged = nullptr;   // the context counter the allocation was charged to
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -147,6 +165,7 @@ struct Workspace {
     DevBuf sweep_no;               // int32 sweep counter of the batch
     int64_t gen = 0;               // bumped whenever the buffers above move
     DevBuf fista;                  // FP64 residual scratch for the incumbent kernels
+    DevBuf nfree;                  // int32 per node: free-coordinate counts of l0l2_round_branch
     int *host_counter = nullptr;   // pinned
 };
 
@@ -201,13 +220,22 @@ struct l0l2_ctx {
     int bf16_terms = 1;                  // BF16 Gram sweeps: 1 single-term anchored blocks, 3 split every sweep
     bool use_graphs = true;              // replay captured blocks of sweeps
     std::string noalloc_err;             // why the allocation-free scratch is unavailable (empty: it is)
+    std::atomic<int> cancel{0};          // set by l0l2_cancel (any thread), taken by the next block boundary
+    l0l2::MemCount mem;                  // device bytes held by buffers this context's calls allocated
     std::map<l0l2::GraphKey, hipGraphExec_t> graphs;
+    // declared after mem: destroyed before it, so their releases can uncharge it
     l0l2::Instance inst;
     l0l2::Workspace ws;
     l0l2::Profiler prof;
 };
 
 namespace l0l2 {
+
+// Throws L0L2_E_CANCELLED (and clears the request) when l0l2_cancel was called
+// on ctx; called at block and batch boundaries of the long-running calls.
+inline void check_cancel(l0l2_ctx *ctx) {
+    if (ctx->cancel.exchange(0) != 0) fail(L0L2_E_CANCELLED, "cancelled by l0l2_cancel");
+}
 
 // precompute.hip
 void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p, double l0,

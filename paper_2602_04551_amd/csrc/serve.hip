@@ -5,8 +5,11 @@
 // its estimated device footprint fits in what the HBM budget has left; it then
 // runs on its own context and HIP stream (default priority), so the kernels of
 // all admitted instances overlap on the device, and its footprint returns to
-// the budget when it finishes.  Each instance's computation is the same
-// deterministic sequence of kernels whether it runs alone or beside others.
+// the budget when it finishes.  Server contexts take their tile shapes from a
+// size rule instead of timing them (timings taken while other instances load
+// the device would vary, and with them the summation order), so each
+// instance's computation is the same sequence of kernels whether it runs alone
+// or beside others.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -64,7 +67,9 @@ struct l0l2_server {
         int prec;
         size_t bytes;
         double t_submit = 0, t_admit = 0, t_done = 0;
-        bool done = false, taken = false;
+        bool done = false, taken = false, cancel = false;
+        l0l2_ctx *ctx = nullptr;   // while running (guarded by mu)
+        size_t peak = 0;           // device bytes its context held at most
         int rc = L0L2_OK;
         std::string err;
         l0l2_bnb_result res{};
@@ -82,6 +87,8 @@ struct l0l2_server {
     std::vector<std::thread> workers;
     int64_t next_id = 1;
     bool stopping = false;
+    int waiters = 0;                  // threads inside l0l2_server_wait
+    std::condition_variable cv_waiters;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 
     double now() const {
@@ -131,12 +138,25 @@ struct l0l2_server {
     void run(Request &r, hipStream_t stream) {
         l0l2_ctx *ctx = nullptr;
         int rc = l0l2_create(device, stream, &ctx);
+        if (rc == L0L2_OK) {
+            ctx->tune = false;   // rule-based tile shapes: the same kernels alone and in the mix
+            std::lock_guard<std::mutex> lk(mu);
+            r.ctx = ctx;
+            if (r.cancel) l0l2_cancel(ctx);
+        }
         if (rc == L0L2_OK)
             rc = l0l2_set_data(ctx, r.X.data(), r.y.data(), r.n, r.p, r.l0, r.l2, r.M, r.rho, r.prec, 0);
         if (rc == L0L2_OK) rc = l0l2_bnb_solve(ctx, &opts, &r.res);
         r.rc = rc;
         if (rc != L0L2_OK) r.err = ctx ? l0l2_last_error(ctx) : l0l2_last_error(nullptr);
-        if (ctx) l0l2_destroy(ctx);
+        if (ctx) {
+            (void)l0l2_memory_stats(ctx, nullptr, &r.peak, 0);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                r.ctx = nullptr;
+            }
+            l0l2_destroy(ctx);
+        }
     }
 };
 
@@ -207,8 +227,18 @@ int l0l2_server_wait(l0l2_server *s, int64_t req_id, double timeout_s, l0l2_bnb_
     if (it == s->all.end() || it->second->taken) return L0L2_E_INVALID;
     auto r = it->second;
     auto pred = [&] { return r->done; };
+    // l0l2_server_destroy waits for the threads counted here before it frees s
+    ++s->waiters;
+    struct Leave {
+        l0l2_server *s;
+        ~Leave() {
+            if (--s->waiters == 0) s->cv_waiters.notify_all();
+        }
+    } leave{s};
     if (timeout_s < 0) s->cv_done.wait(lk, pred);
     else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), pred)) return L0L2_E_TIMEOUT;
+    it = s->all.find(req_id);
+    if (it == s->all.end() || it->second->taken) return L0L2_E_INVALID;
     *out = r->res;
     r->res.support = nullptr;
     r->res.beta = nullptr;
@@ -218,6 +248,7 @@ int l0l2_server_wait(l0l2_server *s, int64_t req_id, double timeout_s, l0l2_bnb_
         stats->admit_s = r->t_admit;
         stats->done_s = r->t_done;
         stats->footprint_bytes = r->bytes;
+        stats->peak_bytes = r->peak;
     }
     int rc = r->rc;
     if (rc != L0L2_OK) s->err = r->err;
@@ -227,15 +258,56 @@ int l0l2_server_wait(l0l2_server *s, int64_t req_id, double timeout_s, l0l2_bnb_
 
 const char *l0l2_server_last_error(const l0l2_server *s) { return s ? s->err.c_str() : ""; }
 
+int l0l2_server_cancel(l0l2_server *s, int64_t req_id) {
+    if (!s) return L0L2_E_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->all.find(req_id);
+        if (it == s->all.end() || it->second->taken) return L0L2_E_INVALID;
+        auto r = it->second;
+        if (r->done) return L0L2_OK;
+        r->cancel = true;
+        auto q = std::find(s->pending.begin(), s->pending.end(), r);
+        if (q != s->pending.end()) {
+            // not admitted yet: finished here
+            s->pending.erase(q);
+            r->done = true;
+            r->rc = L0L2_E_CANCELLED;
+            r->err = "cancelled before admission";
+            r->t_done = s->now();
+        } else if (r->ctx) {
+            l0l2_cancel(r->ctx);
+        }
+    }
+    s->cv_done.notify_all();
+    return L0L2_OK;
+}
+
 int l0l2_server_destroy(l0l2_server *s) {
     if (!s) return L0L2_E_INVALID;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stopping = true;
+        // queued requests end as cancelled (their waiters return), running ones
+        // are asked to stop at their next batch
+        for (auto &r : s->pending) {
+            r->done = true;
+            r->rc = L0L2_E_CANCELLED;
+            r->err = "server destroyed before admission";
+        }
         s->pending.clear();
+        for (auto &kv : s->all)
+            if (kv.second->ctx) l0l2_cancel(kv.second->ctx);
     }
     s->cv_work.notify_all();
+    s->cv_done.notify_all();
     for (auto &t : s->workers) t.join();
+    {
+        // threads still inside l0l2_server_wait leave before s is freed
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.notify_all();
+        s->cv_waiters.wait(lk, [&] { return s->waiters == 0; });
+    }
     for (auto &kv : s->all) l0l2_result_free(&kv.second->res);
     delete s;
     return L0L2_OK;

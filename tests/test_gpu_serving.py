@@ -1,8 +1,10 @@
 """Serving: whole branch-and-bound solves of several instances of different
 sizes admitted under an HBM budget and run concurrently.  Each result is the
-same alone and in the mix (the per-instance kernel sequence is deterministic),
-admitted instances overlap in time, and the budget caps the concurrent
-footprint."""
+same alone and in the mix, bit for bit (server contexts take their tile shapes
+from a size rule, so an instance runs the same kernels whatever else runs),
+admitted instances overlap in time, the budget caps the concurrent footprint,
+each request's device high-water mark stays within its admission estimate, and
+queued or running requests can be cancelled."""
 import time
 
 import numpy as np
@@ -27,13 +29,14 @@ def instances():
 
 @pytest.fixture(scope="module")
 def alone(instances):
-    from paper_2602_04551_amd.binding import Context
+    """Each instance through a server that runs one request at a time."""
+    from paper_2602_04551_amd.binding import Server
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=1, **KW)
     out = []
     for inst in instances:
-        c = Context(0)
-        c.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp32")
-        out.append(c.bnb_solve(**KW))
-        c.close()
+        rid = srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp32")
+        out.append(srv.wait(rid, timeout_s=600))
+    srv.close()
     return out
 
 
@@ -54,9 +57,11 @@ def test_results_identical_alone_and_in_the_mix(instances, alone, orc):
     srv.close()
     for a, b in zip(res, alone):
         assert a["status"] == 0
-        assert a["certified"] == b["certified"]
+        for key in ("certified", "ub", "lb", "nodes_solved", "nodes_pruned", "batches"):
+            assert a[key] == b[key], key
         assert list(a["support"]) == list(b["support"])
-        assert a["nodes_solved"] == b["nodes_solved"]
+        assert np.array_equal(a["beta"], b["beta"])
+        assert 0 < a["peak_bytes"] <= a["footprint_bytes"]
     assert overlaps(res)
     ref = orc.Oracle.from_instance(instances[1]).bnb(tol_node=1e-6, max_iter=3000, max_iter_root=10000)
     assert abs(res[1]["certified"] - ref["certified"]) <= 1e-8 * ref["certified"]
@@ -114,7 +119,66 @@ def test_footprint_estimate_covers_a_solve(instances, precision):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     used = free0 - torch.cuda.mem_get_info()[0]
+    held, peak = c.memory_stats()
     c.close()
     assert r["status"] == 0
-    print(f"{precision}: used {used / 2**20:.1f} MiB, estimate {est / 2**20:.1f} MiB")
+    print(f"{precision}: held after {used / 2**20:.1f} MiB, library peak {peak / 2**20:.1f} MiB, "
+          f"estimate {est / 2**20:.1f} MiB")
+    # the high-water mark of the library's own buffers (transients of set_data and
+    # of the solve included), and what stays on the device, within the estimate
+    assert held <= peak <= est
     assert used <= est
+
+
+def test_cancel_queued_and_running_requests(instances):
+    """A queued request cancelled ends at once with L0L2_E_CANCELLED; a running
+    one ends cancelled or (if it finished first) certified; the others are
+    unaffected."""
+    from paper_2602_04551_amd.binding import L0L2_E_CANCELLED, L0L2Error, Server
+    big = datagen.config_instance("C2", seed=0)
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=1, **KW)
+    r0 = srv.submit(big.X, big.y, big.lambda0, big.lambda2, big.M, precision="fp64")
+    r1 = srv.submit(instances[0].X, instances[0].y, instances[0].lambda0, instances[0].lambda2, instances[0].M)
+    r2 = srv.submit(instances[1].X, instances[1].y, instances[1].lambda0, instances[1].lambda2, instances[1].M)
+    srv.cancel(r1)
+    time.sleep(0.05)
+    srv.cancel(r0)
+    with pytest.raises(L0L2Error) as e:
+        srv.wait(r1, timeout_s=60)
+    assert e.value.code == L0L2_E_CANCELLED
+    try:
+        a = srv.wait(r0, timeout_s=600)
+        assert a["status"] == 0
+    except L0L2Error as e0:
+        assert e0.code == L0L2_E_CANCELLED
+    b = srv.wait(r2, timeout_s=600)
+    assert b["status"] == 0
+    with pytest.raises(L0L2Error):
+        srv.cancel(r2)    # already collected
+    srv.close()
+
+
+def test_destroy_releases_a_waiting_thread(instances):
+    """Destroying the server while another thread waits (without a time limit)
+    on a queued request: the waiter returns L0L2_E_CANCELLED, nothing hangs."""
+    import threading
+    from paper_2602_04551_amd.binding import L0L2_E_CANCELLED, L0L2Error, Server
+    big = datagen.config_instance("C2", seed=0)
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=1, **KW)
+    srv.submit(big.X, big.y, big.lambda0, big.lambda2, big.M, precision="fp64")
+    rq = srv.submit(instances[2].X, instances[2].y, instances[2].lambda0, instances[2].lambda2, instances[2].M)
+    got = {}
+
+    def waiter():
+        try:
+            got["res"] = srv.wait(rq)
+        except L0L2Error as e:
+            got["code"] = e.code
+
+    t = threading.Thread(target=waiter)
+    t.start()
+    time.sleep(0.1)
+    srv.close()
+    t.join(timeout=120)
+    assert not t.is_alive()
+    assert got.get("code") == L0L2_E_CANCELLED or got.get("res", {}).get("status") == 0
