@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "serve_core.hpp"
 
 namespace l0l2 {
 
@@ -76,13 +77,12 @@ struct l0l2_server {
     };
 
     int device = 0;
-    size_t budget = 0, reserved = 0;
-    int max_concurrent = 1, running = 0;
+    std::unique_ptr<l0l2::Admission<Request>> adm;   // guarded by mu
+    int max_concurrent = 1;
     l0l2_bnb_opts opts{};
     std::string err;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<std::shared_ptr<Request>> pending;
     std::map<int64_t, std::shared_ptr<Request>> all;
     std::vector<std::thread> workers;
     int64_t next_id = 1;
@@ -95,16 +95,10 @@ struct l0l2_server {
         return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     }
 
-    // Next admissible request, in arrival order (the head blocks later ones so
-    // that large instances are not starved).
+    // Next admissible request (serve_core.hpp: arrival order, HBM budget).
     std::shared_ptr<Request> admit_locked() {
-        if (pending.empty() || running >= max_concurrent) return nullptr;
-        auto r = pending.front();
-        if (reserved + r->bytes > budget && running > 0) return nullptr;
-        pending.pop_front();
-        reserved += r->bytes;
-        ++running;
-        r->t_admit = now();
+        auto r = adm->admit();
+        if (r) r->t_admit = now();
         return r;
     }
 
@@ -122,8 +116,7 @@ struct l0l2_server {
             run(*r, stream);
             {
                 std::lock_guard<std::mutex> lk(mu);
-                reserved -= r->bytes;
-                --running;
+                adm->finish(*r);
                 r->t_done = now();
                 r->done = true;
                 r->X.clear();
@@ -178,7 +171,12 @@ int l0l2_server_create(int device, size_t hbm_budget_bytes, int max_concurrent, 
     l0l2_server *s = new (std::nothrow) l0l2_server();
     if (!s) return L0L2_E_OOM;
     s->device = device;
-    s->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)freeb);
+    s->adm.reset(new (std::nothrow) l0l2::Admission<l0l2_server::Request>(
+        hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)freeb), max_concurrent));
+    if (!s->adm) {
+        delete s;
+        return L0L2_E_OOM;
+    }
     s->max_concurrent = max_concurrent;
     s->opts = *opts;
     s->opts.trace = nullptr;
@@ -205,13 +203,13 @@ int l0l2_server_submit(l0l2_server *s, const double *X, const double *y, int64_t
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stopping) return L0L2_E_INVALID;
-        if (r->bytes > s->budget) {
+        if (!s->adm->fits_at_all(*r)) {
             s->err = "request footprint exceeds the server's HBM budget";
             return L0L2_E_OOM;
         }
         r->id = s->next_id++;
         r->t_submit = s->now();
-        s->pending.push_back(r);
+        s->adm->push(r);
         s->all[r->id] = r;
         *req_id = r->id;
     }
@@ -267,10 +265,8 @@ int l0l2_server_cancel(l0l2_server *s, int64_t req_id) {
         auto r = it->second;
         if (r->done) return L0L2_OK;
         r->cancel = true;
-        auto q = std::find(s->pending.begin(), s->pending.end(), r);
-        if (q != s->pending.end()) {
+        if (s->adm->remove(r)) {
             // not admitted yet: finished here
-            s->pending.erase(q);
             r->done = true;
             r->rc = L0L2_E_CANCELLED;
             r->err = "cancelled before admission";
@@ -290,12 +286,11 @@ int l0l2_server_destroy(l0l2_server *s) {
         s->stopping = true;
         // queued requests end as cancelled (their waiters return), running ones
         // are asked to stop at their next batch
-        for (auto &r : s->pending) {
-            r->done = true;
-            r->rc = L0L2_E_CANCELLED;
-            r->err = "server destroyed before admission";
-        }
-        s->pending.clear();
+        s->adm->drain([](l0l2_server::Request &r) {
+            r.done = true;
+            r.rc = L0L2_E_CANCELLED;
+            r.err = "server destroyed before admission";
+        });
         for (auto &kv : s->all)
             if (kv.second->ctx) l0l2_cancel(kv.second->ctx);
     }
