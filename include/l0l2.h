@@ -218,6 +218,13 @@ typedef struct {
     int root_heuristic;    /* 1: before the root, the support of l0l2_matching_pursuit
                               (max_moves 4 min(n, p)) solved exactly seeds the incumbent
                               (Sec. 3.5); 0: none */
+    const uint8_t *init_support; /* optional host array of p bytes (0/1): a support whose
+                              exact objective at the current penalties seeds the incumbent
+                              (the better of it and the heuristic's); NULL: none */
+    int warm_root;         /* 1: the root relaxation starts from the root iterates of the
+                              previous l0l2_bnb_solve on this context (same instance and
+                              precision, any penalties; Sec. 3.1.3's warm start across
+                              solves), else from zero */
 } l0l2_bnb_opts;
 
 typedef struct {
@@ -240,6 +247,30 @@ typedef struct {
  * LIFO), the incumbent and the pruning decisions.  Fills *out. */
 int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *out);
 void l0l2_result_free(l0l2_bnb_result *res);
+
+/* New penalties (lambda0 >= 0, lambda2 > 0, M > 0 or INFINITY) for the instance
+ * of ctx, keeping everything l0l2_set_data precomputed (c, the factor, the
+ * transformed operands and the Gram matrix depend on X, y and rho only), so a
+ * sequence of solves over a lambda0 grid (Sec. 4.1, selection of lambda0)
+ * pays the precompute once. */
+int l0l2_set_penalties(l0l2_ctx *ctx, double lambda0, double lambda2, double M);
+
+/* The smallest lambda0 at which the empty support is not improved by adding any
+ * single coordinate (the forward scores of App. A.2 at S = {} with lambda0 = 0:
+ * max_j (b_j c_j - D_j b_j^2 / 2), b_j = clip(c_j / D_j, -M, M),
+ * D_j = ||X_j||^2 + 2 lambda2, c = X^T y): the top of a decreasing lambda0 grid. */
+int l0l2_lambda0_max(l0l2_ctx *ctx, double *out);
+
+/* Branch and bound along a decreasing lambda0 grid (Sec. 4.1's regularization
+ * path): for i = 0 .. m-1, the penalties become (lambda0s[i], lambda2, M) of the
+ * current instance and l0l2_bnb_solve(opts) runs with the previous grid point's
+ * certified support as init_support and, for i > 0, warm_root = 1 (the previous
+ * root iterates).  results[i] receives each solve's result (release each with
+ * l0l2_result_free).  On return the instance keeps the last grid point's
+ * penalties.  A failed solve stops the path with its error code; the results
+ * filled before it are valid. */
+int l0l2_bnb_path(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, int m, const double *lambda0s,
+                  l0l2_bnb_result *results);
 
 /* Node-batch size by measurement (the batch axis of the autotuner; the batch
  * size K of Alg. 1 is the paper's parameter for how many nodes are solved at

@@ -42,7 +42,8 @@ class l0l2_bnb_opts(C.Structure):
     _fields_ = [("K", C.c_int), ("policy", C.c_int), ("eps_prune", C.c_double),
                 ("gap_tol", C.c_double), ("time_limit_s", C.c_double), ("max_nodes", C.c_int64),
                 ("max_iter_root", C.c_int), ("admm", l0l2_admm_opts), ("fista", l0l2_fista_opts),
-                ("trace", C.POINTER(l0l2_trace_rec)), ("trace_cap", C.c_int64), ("root_heuristic", C.c_int)]
+                ("trace", C.POINTER(l0l2_trace_rec)), ("trace_cap", C.c_int64), ("root_heuristic", C.c_int),
+                ("init_support", C.c_void_p), ("warm_root", C.c_int)]
 
 
 class l0l2_bnb_result(C.Structure):
@@ -85,6 +86,9 @@ SIGNATURES = {
     "l0l2_memory_stats": (_i, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), _i]),
     "l0l2_set_tiles": (_i, [_vp, _i, _i]),
     "l0l2_tune_batch_size": (_i, [_vp, _i, _d, C.POINTER(_i), _vp, C.POINTER(_i)]),
+    "l0l2_set_penalties": (_i, [_vp, _d, _d, _d]),
+    "l0l2_lambda0_max": (_i, [_vp, C.POINTER(_d)]),
+    "l0l2_bnb_path": (_i, [_vp, C.POINTER(l0l2_bnb_opts), _i, _vp, C.POINTER(l0l2_bnb_result)]),
     "l0l2_set_bupdate_form": (_i, [_vp, _i]),
     "l0l2_set_bf16_terms": (_i, [_vp, _i]),
     "l0l2_cancel": (_i, [_vp]),
@@ -275,6 +279,39 @@ class Context:
                                               C.byref(obj), moves.ctypes.data, C.byref(nm)))
         return mask, beta, obj.value, [int(m) for m in moves[:nm.value]]
 
+    def set_penalties(self, lambda0, lambda2=None, M=None):
+        """New (lambda0, lambda2, M) for the loaded instance; the precompute is kept."""
+        lambda2 = self.lambda2 if lambda2 is None else lambda2
+        M = self.M if M is None else M
+        self._check(lib.l0l2_set_penalties(self._h, float(lambda0), float(lambda2), float(M)))
+        self.lambda0, self.lambda2, self.M = lambda0, lambda2, M
+
+    def lambda0_max(self):
+        out = C.c_double()
+        self._check(lib.l0l2_lambda0_max(self._h, C.byref(out)))
+        return out.value
+
+    def bnb_path(self, lambda0s, K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000,
+                 check_every=10, eps_prune=None, gap_tol=0.0, time_limit_s=0.0, max_nodes=10**9,
+                 fista_tol=1e-12, fista_max_iter=1000, root_heuristic=False):
+        """Branch and bound along the decreasing lambda0 grid, each point warm-started
+        from the previous one (its certified support as the first incumbent, its
+        root iterates as the root's start): one result dict per grid point."""
+        lam = np.ascontiguousarray(lambda0s, dtype=np.float64)
+        m = len(lam)
+        o = bnb_options(K, policy, tol_node, max_iter, max_iter_root, check_every, eps_prune, gap_tol,
+                        time_limit_s, max_nodes, fista_tol, fista_max_iter, root_heuristic)
+        res = (l0l2_bnb_result * m)()
+        rc = lib.l0l2_bnb_path(self._h, C.byref(o), m, lam.ctypes.data, res)
+        try:
+            out = [_result_dict(res[i], self.p) for i in range(m) if res[i].support or res[i].beta]
+        finally:
+            for i in range(m):
+                lib.l0l2_result_free(C.byref(res[i]))
+        self._check(rc)
+        self.lambda0 = float(lam[-1])
+        return out
+
     def tune_batch_size(self, k_max=1024, frac=0.9):
         """(chosen K, {candidate K: node-sweeps per second})."""
         k = C.c_int()
@@ -320,7 +357,8 @@ class Context:
 
     def bnb_solve(self, K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000,
                   check_every=10, eps_prune=None, gap_tol=0.0, time_limit_s=0.0, max_nodes=10**9,
-                  fista_tol=1e-12, fista_max_iter=1000, trace_cap=0, root_heuristic=False):
+                  fista_tol=1e-12, fista_max_iter=1000, trace_cap=0, root_heuristic=False, init_support=None,
+                  warm_root=False):
         if eps_prune is None:
             eps_prune = 2.0 * tol_node
         tr = (l0l2_trace_rec * max(trace_cap, 1))()
@@ -329,6 +367,12 @@ class Context:
                           l0l2_admm_opts(float(tol_node), int(max_iter), int(check_every)),
                           l0l2_fista_opts(float(fista_tol), int(fista_max_iter)),
                           tr if trace_cap > 0 else None, int(trace_cap), 1 if root_heuristic else 0)
+        init = None
+        if init_support is not None:
+            init = np.zeros(self.p, np.uint8)
+            init[np.asarray(init_support, dtype=np.int64)] = 1
+            o.init_support = init.ctypes.data
+        o.warm_root = 1 if warm_root else 0
         r = l0l2_bnb_result()
         self._check(lib.l0l2_bnb_solve(self._h, C.byref(o), C.byref(r)))
         try:

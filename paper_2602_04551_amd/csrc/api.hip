@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -336,7 +337,7 @@ int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *ou
         if (opts->K < 0 || opts->admm.max_iter < 1 || opts->admm.check_every < 1 || opts->max_iter_root < 1 ||
             opts->fista.max_iter < 1 || !(opts->eps_prune >= 0) || !(opts->gap_tol >= 0) || opts->max_nodes < 1 ||
             (opts->policy != L0L2_BEST_FIRST && opts->policy != L0L2_DFS) || opts->root_heuristic < 0 ||
-            opts->root_heuristic > 1)
+            opts->root_heuristic > 1 || opts->warm_root < 0 || opts->warm_root > 1)
             l0l2::fail(L0L2_E_INVALID, "bad branch-and-bound options");
         l0l2_bnb_opts o = *opts;
         if (o.K == 0) {
@@ -346,6 +347,54 @@ int l0l2_bnb_solve(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, l0l2_bnb_result *ou
         }
         l0l2::bnb_solve(ctx, o, out);
     });
+}
+
+void check_penalties(double lambda0, double lambda2, double M) {
+    if (!(std::isfinite(lambda0) && lambda0 >= 0)) l0l2::fail(L0L2_E_INVALID, "lambda0 must be finite and >= 0");
+    if (!(std::isfinite(lambda2) && lambda2 > 0)) l0l2::fail(L0L2_E_INVALID, "lambda2 must be finite and > 0");
+    if (!(M > 0) || std::isnan(M)) l0l2::fail(L0L2_E_INVALID, "M must be > 0 (INFINITY allowed)");
+}
+
+int l0l2_set_penalties(l0l2_ctx *ctx, double lambda0, double lambda2, double M) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        check_penalties(lambda0, lambda2, M);
+        l0l2::set_penalties(ctx, lambda0, lambda2, M);
+    });
+}
+
+int l0l2_lambda0_max(l0l2_ctx *ctx, double *out) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        if (!out) l0l2::fail(L0L2_E_INVALID, "null argument");
+        *out = l0l2::lambda0_max(ctx);
+    });
+}
+
+int l0l2_bnb_path(l0l2_ctx *ctx, const l0l2_bnb_opts *opts, int m, const double *lambda0s,
+                  l0l2_bnb_result *results) {
+    if (results && m > 0) std::memset(results, 0, sizeof(*results) * (size_t)m);
+    if (!ctx) return L0L2_E_INVALID;
+    if (!opts || !lambda0s || !results || m < 1) {
+        ctx->err = "need opts, m >= 1 lambda0 values and m results";
+        return L0L2_E_INVALID;
+    }
+    const double l2 = ctx->inst.mp.l2, M = ctx->inst.mp.M;
+    std::vector<uint8_t> prev;
+    for (int i = 0; i < m; ++i) {
+        int rc = l0l2_set_penalties(ctx, lambda0s[i], l2, M);
+        if (rc != L0L2_OK) return rc;
+        l0l2_bnb_opts o = *opts;
+        if (i > 0) {
+            o.warm_root = 1;
+            if (!prev.empty()) o.init_support = prev.data();
+        }
+        rc = l0l2_bnb_solve(ctx, &o, &results[i]);
+        if (rc != L0L2_OK) return rc;
+        prev.assign((size_t)ctx->inst.p, 0);
+        for (int64_t e = 0; e < results[i].support_len; ++e) prev[(size_t)results[i].support[e]] = 1;
+    }
+    return L0L2_OK;
 }
 
 int l0l2_tune_batch_size(l0l2_ctx *ctx, int k_max, double frac, int *k_out, double *rates, int *n_rates) {

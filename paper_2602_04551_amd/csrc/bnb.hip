@@ -171,6 +171,16 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
         const double f = run_exact_objective(ctx, mp_mask.data(), mp_beta.data());
         if (std::isfinite(f) && core.seed_incumbent(f)) inc_mask = mp_mask;
     }
+    if (o.init_support) {
+        // a support given by the caller (e.g. the previous point of a lambda0
+        // path), solved exactly at the current penalties
+        std::vector<uint8_t> m0((size_t)p, 0);
+        for (int64_t j = 0; j < p; ++j) m0[(size_t)j] = o.init_support[j] ? 1 : 0;
+        std::vector<double> b0((size_t)p, 0.0);
+        const double f = run_exact_objective(ctx, m0.data(), b0.data());
+        if (std::isfinite(f) && core.seed_incumbent(f)) inc_mask = m0;
+    }
+    const size_t row_bytes = state_bytes(in.prec) * (size_t)pp;
     int64_t batches = 0;
     int status = 0;
     std::vector<OpenNode> batch;
@@ -217,8 +227,21 @@ void bnb_t(l0l2_ctx *ctx, const l0l2_bnb_opts &o, l0l2_bnb_result *out) {
         HIPCHK(hipGetLastError());
         core.gathered(batch);
         l0l2_admm_opts ao = o.admm;
-        if (batch[0].id == 0) ao.max_iter = o.max_iter_root;
+        const bool root = batch[0].id == 0;
+        if (root) ao.max_iter = o.max_iter_root;
+        if (root && o.warm_root && ws.have_root && ws.root_beta.bytes >= row_bytes) {
+            // Sec. 3.1.3 across solves: the root starts from the previous tree's root iterates
+            HIPCHK(hipMemcpyAsync(ws.beta.ptr, ws.root_beta.ptr, row_bytes, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(ws.V.ptr, ws.root_v.ptr, row_bytes, hipMemcpyDeviceToDevice, st));
+        }
         run_solve(ctx, B, ao);
+        if (root) {
+            ws.root_beta.ensure(row_bytes);
+            ws.root_v.ensure(row_bytes);
+            HIPCHK(hipMemcpyAsync(ws.root_beta.ptr, ws.beta.ptr, row_bytes, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(ws.root_v.ptr, ws.V.ptr, row_bytes, hipMemcpyDeviceToDevice, st));
+            ws.have_root = true;
+        }
         run_round_branch(ctx, B, ws.codes.as<uint8_t>(), pp, ws.beta.ptr, pp, d_sup.as<uint8_t>(),
                          d_ssize.as<int32_t>(), d_bj.as<int32_t>(), d_zup.as<int32_t>(), d_nfree.as<int32_t>());
         state_to_f64(ctx, B, ws.beta.ptr, pp, d_fbeta.as<double>(), p);

@@ -166,6 +166,8 @@ struct Workspace {
     int64_t gen = 0;               // bumped whenever the buffers above move
     DevBuf fista;                  // FP64 residual scratch for the incumbent kernels
     DevBuf nfree;                  // int32 per node: free-coordinate counts of l0l2_round_branch
+    DevBuf root_beta, root_v;      // the last branch and bound's root iterates (ldp state elements each)
+    bool have_root = false;
     int *host_counter = nullptr;   // pinned
 };
 
@@ -241,6 +243,10 @@ inline void check_cancel(l0l2_ctx *ctx) {
 void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p, double l0,
               double l2, double M, double rho, int prec, int on_device);
 MethodParams make_params(double l0, double l2, double M, double rho);
+// New penalties for the loaded instance; the precompute is kept.
+void set_penalties(l0l2_ctx *ctx, double l0, double l2, double M);
+// max_j of the gain of adding j to the empty support at lambda0 = 0 (App. A.2).
+double lambda0_max(l0l2_ctx *ctx);
 
 // admm.hip
 void ensure_workspace(l0l2_ctx *ctx, int64_t K);

@@ -2,7 +2,9 @@
 // norms, S = X X^T + rho I, its Cholesky factor L, and the folded operand
 // Xh = L^{-1} X so that D w = (w - Xh^T (Xh w)) / rho for D = (X^T X + rho I)^{-1}
 // (the Woodbury identity with the 1/rho factor; Xh^T Xh = X^T S^{-1} X).
+#include <algorithm>
 #include <cmath>
+#include <vector>
 #include <cstring>
 
 #include "device_math.hpp"
@@ -303,6 +305,31 @@ MethodParams make_params(double l0, double l2, double M, double rho) {
     return q;
 }
 
+void set_penalties(l0l2_ctx *ctx, double l0, double l2, double M) {
+    Instance &in = ctx->inst;
+    // the captured blocks of sweeps hold the old scalars as kernel arguments
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    drop_graphs(ctx);
+    in.mp = make_params(l0, l2, M, in.mp.rho);
+}
+
+double lambda0_max(l0l2_ctx *ctx) {
+    Instance &in = ctx->inst;
+    const int64_t p = in.p;
+    std::vector<double> c((size_t)p), nrm((size_t)p);
+    HIPCHK(hipMemcpyAsync(c.data(), in.c64.ptr, sizeof(double) * p, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(nrm.data(), in.colnrm.ptr, sizeof(double) * p, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    double best = 0.0;
+    for (int64_t j = 0; j < p; ++j) {
+        const double D = nrm[(size_t)j] * nrm[(size_t)j] + 2.0 * in.mp.l2;
+        double b = c[(size_t)j] / D;
+        b = b > in.mp.M ? in.mp.M : (b < -in.mp.M ? -in.mp.M : b);
+        best = std::max(best, b * c[(size_t)j] - 0.5 * D * b * b);
+    }
+    return best;
+}
+
 void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_t p, double l0, double l2,
               double M, double rho, int prec, int on_device) {
     Instance &in = ctx->inst;
@@ -310,6 +337,7 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     ctx->has_data = false;
     // the per-batch workspace is sized for the previous instance: drop it
     ctx->ws.cap = 0;
+    ctx->ws.have_root = false;
     drop_graphs(ctx);
     in.tiles.clear();
     in.tuned_K = 0;
