@@ -56,6 +56,13 @@ def parse():
     ap.add_argument("--serve-concurrent", type=int, default=8, help="instances in flight at once")
     ap.add_argument("--highdim", action="store_true",
                     help="n = 1000, p = 50000 node batches of 256 and 1024: FP8, BF16, FP32 vs FP64")
+    ap.add_argument("--node-parallel", action="store_true",
+                    help="the node-parallel study: n = 3000, p in {1e4, 3e4, 1e5}, K in {1, 10, 50, 100}, "
+                         "branch and bound under a time limit: nodes/s, gap and peak device memory vs K")
+    ap.add_argument("--np-seconds", type=float, default=10.0, help="time limit of each node-parallel run")
+    ap.add_argument("--np-p", type=str, default="10000,30000,100000")
+    ap.add_argument("--np-precision", type=str, default="fp64")
+    ap.add_argument("--np-tol", type=float, default=1e-4, help="node gap tolerance of the study (the paper's 1e-4)")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="first dispatch one device copy of 256 MiB, the reference for HBM counter scaling")
     return ap.parse_args()
@@ -217,6 +224,14 @@ def cpu_baseline(cfg, K, root, seconds, sample):
                        f"not timed")
 
 
+def b_update_info(ctx):
+    """The b-update form the library measured and kept for the instance (Sec. 3.1.1)."""
+    form, ms_f, ms_g = ctx.bupdate_form()
+    return {"form": form, "measured_ms_per_sweep": {"folded": round(ms_f, 4), "gram": round(ms_g, 4)},
+            "note": "Gram form b = (w - G w) / rho with G = Xh^T Xh (2 p^2 flops per node-sweep) against the "
+                    "folded operand Xh = L^-1 X (two contractions, 4 n p); timed once per instance on the batch"}
+
+
 def batch_detail(path):
     """Per-node work of the last step: ADMM sweeps, support sizes, refinement iterations."""
     sw, ss, fi, st = (t.cpu().numpy().astype(np.float64) for t in path.detail)
@@ -353,7 +368,7 @@ def node_batch_run(inst, prec, K, root, profile=True):
     it = r["iters"].cpu().numpy()
     run = {"value": round(K / dt, 2), "seconds": round(dt, 4), "iters_mean": round(float(it.mean()), 2),
            "iters_max": int(it.max()), "converged": int((r["status"] == 0).sum().item()),
-           "set_data_s": round(sd, 3)}
+           "set_data_s": round(sd, 3), "b_update": b_update_info(ctx)["form"]}
     if profile:
         ctx.profile_enable(True)
         ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
@@ -408,6 +423,67 @@ def highdim_main(args):
                     "with free sets U{50..p}, |F1| U{0..20}", "high-dimensional")
 
 
+def mp_lambda0(ctx, k0, ratio=0.8, steps=60):
+    """lambda0 for a study instance (a reading of Sec. 4.1's tuning, which runs
+    the branch and bound along a path and keeps the lambda0 whose support best
+    matches the truth): the largest lambda0 on the grid lambda0_max ratio^i at
+    which the matching-pursuit support (Sec. 3.5) holds at least k0 coordinates."""
+    lmax = ctx.lambda0_max()
+    lam = lmax
+    for _ in range(steps):
+        lam *= ratio
+        ctx.set_penalties(lam)
+        mask = ctx.matching_pursuit()[0]
+        if int(mask.sum()) >= k0:
+            return lam, int(mask.sum()), lmax
+    return lam, int(mask.sum()), lmax
+
+
+def node_parallel_main(args):
+    """Sec. 4.4's node-parallel study rerun on synthetic data: branch and bound
+    with batches of K in {1, 10, 50, 100} under a time limit on n = 3000
+    instances with p in {1e4, 3e4, 1e5}: nodes per second, the gap reached, and
+    the peak device memory of the library's buffers relative to K = 1."""
+    import torch
+    from paper_2602_04551_amd import datagen
+    from paper_2602_04551_amd.binding import Context
+    out = {"metric": "node-parallel study (nodes/s and peak device memory vs batch size K)",
+           "config": {"workload": "n=3000 constant correlation 0.2 k=10 SNR=10/3, lambda2 = lambda2* (ridge on the "
+                                  "true support), M = 1.5 x ridge max, lambda0 by the matching-pursuit rule; "
+                                  f"best-first branch and bound, {args.np_seconds:g} s per run, "
+                                  f"{args.np_precision} path, node tolerance {args.np_tol:g}",
+                      "time_limit_s": args.np_seconds, "precision": args.np_precision, "node_tol": args.np_tol},
+           "runs": {}}
+    for p in [int(v) for v in args.np_p.split(",")]:
+        inst = datagen.node_parallel_instance(p)
+        ctx = Context(0)
+        t0 = time.perf_counter()
+        ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=args.np_precision)
+        torch.cuda.synchronize()
+        sd = time.perf_counter() - t0
+        lam, k_mp, lmax = mp_lambda0(ctx, 10)
+        rows = {}
+        for K in (1, 10, 50, 100):
+            ctx.memory_stats(reset_peak=True)
+            r = ctx.bnb_solve(K=K, policy="best", tol_node=args.np_tol, max_iter=2000, max_iter_root=10000,
+                              time_limit_s=args.np_seconds)
+            held, peak = ctx.memory_stats()
+            gap = (r["ub"] - r["lb"]) / abs(r["ub"]) if np.isfinite(r["ub"]) and r["ub"] != 0 else None
+            rows[str(K)] = {"nodes": r["nodes_solved"], "seconds": round(r["seconds"], 3),
+                            "nodes_per_s": round(r["nodes_solved"] / max(r["seconds"], 1e-9), 2),
+                            "gap": gap, "status": r["status"], "peak_gb": round(peak / 1e9, 3),
+                            "support_size": len(r["support"])}
+            print(json.dumps({"p": p, "K": K, **rows[str(K)]}), file=sys.stderr, flush=True)
+        base = rows["1"]
+        for K, v in rows.items():
+            v["nodes_per_s_vs_K1"] = round(v["nodes_per_s"] / max(base["nodes_per_s"], 1e-9), 2)
+            v["peak_vs_K1"] = round(v["peak_gb"] / base["peak_gb"], 3)
+        out["runs"][str(p)] = {"n": inst.n, "lambda0": lam, "lambda0_max": lmax, "mp_support": k_mp,
+                               "lambda2": inst.lambda2, "M": inst.M, "set_data_s": round(sd, 3), "by_K": rows}
+        ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def serve_main(args):
     """A Poisson stream of independent instances (n ~ U{500..2000}, p ~ U{1000..4000}, Toeplitz
     rho ~ U[0, 0.7], k ~ U{5..12}, SNR ~ U[2, 10], lambda0 = 0.005, lambda2 = 0.01) through the
@@ -460,6 +536,8 @@ def main():
         return highdim_main(args)
     if args.serve:
         return serve_main(args)
+    if args.node_parallel:
+        return node_parallel_main(args)
     import torch
     from paper_2602_04551_amd import datagen
 
@@ -489,8 +567,7 @@ def main():
            "config": {"workload": wl.format(K=K), "n": n, "p": p, "K": K, "node_tol": 1e-6, "check_every": 10,
                       "rho": 1.0, "root_warm_start": f"FP64 root relaxation to a 1e-9 gap ({root[3]} sweeps), "
                                                      "shared by every precision",
-                      "b_update": "Gram form b = (w - G w) / rho, G = Xh^T Xh (p <= 1.5 n): one contraction of "
-                                  "2 p^2 = 2 n p flops per node-sweep here"},
+                      "b_update": b_update_info(mixed.ctx)},
            "roofline": roof,
            "roofline_hbm": sweep_bytes_roofline(prof, n, p, "bf16"),
            "kernels": kernels,
@@ -505,7 +582,8 @@ def main():
             roof_o, kernels_o = roofline(prof_o, n, p)
             out[prec + "_path"] = {"value": round(K * steps_o / dt_o, 2), "unit": "node relaxations/s",
                                    "steps": steps_o, "ms_per_step": round(1e3 * dt_o / steps_o, 3),
-                                   "roofline": roof_o, "kernels": kernels_o, "batch_detail": batch_detail(path)}
+                                   "roofline": roof_o, "kernels": kernels_o, "batch_detail": batch_detail(path),
+                                   "b_update": b_update_info(path.ctx)}
             out["set_data_s"][prec] = round(path.set_data_s, 4)
             path.close()
             print(json.dumps({prec: out[prec + "_path"]["value"]}), file=sys.stderr, flush=True)

@@ -370,12 +370,20 @@ int l0l2_set_tiles(l0l2_ctx *ctx, int xw_shape, int xtu_shape);
  * 2 n p flops per node per sweep.  2: through the p x p Gram matrix G = Xh^T Xh,
  * b = (w - G w) / rho, one contraction of 2 p^2 flops (the paper's p x p D,
  * here in the form I - rho D).  0 (default): the Gram form in FP32 and BF16
- * modes when p <= 1.5 n and the padded p is at most 8192, else the folded
+ * modes where it can win (p < 2 n, its 2 p^2 flops against the folded form's
+ * 4 n p, and padded p at most 8192), chosen by measurement: on the instance's
+ * first solve one sweep of each form is timed on the batch (every node masked,
+ * best of three) and the faster is kept for the instance; elsewhere the folded
  * operand.  The Gram form exists in FP32 and BF16 modes only (FP64 and FP8
  * always use the folded operand; l0l2_admm_sweeps always does).  G is built in
  * FP64 (the anchors), then FP32 (FP32 mode) or a BF16 hi/lo pair of its FP32
- * value (BF16 mode), on the first solve that uses it. */
+ * value (BF16 mode), on the first solve that uses it (and freed if the folded
+ * form wins the measurement). */
 int l0l2_set_bupdate_form(l0l2_ctx *ctx, int form);
+/* The b-update form in use: *form = 1 folded, 2 Gram; *ms_folded / *ms_gram
+ * (may be NULL) the measured time of one sweep of each (0 when the choice was
+ * not measured: forced, not a candidate, or before the first solve). */
+int l0l2_bupdate_form(l0l2_ctx *ctx, int *form, double *ms_folded, double *ms_gram);
 
 /* Device memory the library holds (device allocations of its calls; caller-owned
  * buffers are not counted): for ctx, the buffers that calls on ctx allocated

@@ -91,6 +91,7 @@ SIGNATURES = {
     "l0l2_bnb_path": (_i, [_vp, C.POINTER(l0l2_bnb_opts), _i, _vp, C.POINTER(l0l2_bnb_result)]),
     "l0l2_set_bupdate_form": (_i, [_vp, _i]),
     "l0l2_set_bf16_terms": (_i, [_vp, _i]),
+    "l0l2_bupdate_form": (_i, [_vp, C.POINTER(_i), C.POINTER(_d), C.POINTER(_d)]),
     "l0l2_cancel": (_i, [_vp]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
     "l0l2_profile_query": (_i, [_vp, C.c_char_p, C.POINTER(_i64), C.POINTER(_d), C.POINTER(_i64)]),
@@ -335,6 +336,12 @@ class Context:
     def cancel(self):
         """Ask the running (or next) long call on this context to stop with L0L2_E_CANCELLED."""
         self._check(lib.l0l2_cancel(self._h))
+
+    def bupdate_form(self):
+        """("folded" | "gram", measured ms per sweep of the folded form, of the Gram form)."""
+        f, a, b = C.c_int(), C.c_double(), C.c_double()
+        self._check(lib.l0l2_bupdate_form(self._h, C.byref(f), C.byref(a), C.byref(b)))
+        return ("gram" if f.value == 2 else "folded"), a.value, b.value
 
     def set_bf16_terms(self, terms=1):
         """BF16 Gram-form sweeps: 1 single-term anchored blocks (default), 3 split form in every sweep."""

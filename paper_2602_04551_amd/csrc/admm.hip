@@ -2707,11 +2707,23 @@ __global__ void k_f64_to_bf16x2(const double *__restrict__ src, int64_t lds, __b
     }
 }
 
+// The Gram form is a candidate in FP32 and BF16 modes when its contraction
+// (2 p^2 flops per node-sweep) can beat the folded form's two (4 n p), i.e.
+// p < 2 n, and G (padded p squared in FP64 plus its working copies) stays
+// within padded p <= 8192.  Among candidates the form is measured on the first
+// solve (decide_form); before that, and where it is not measured, the Gram form
+// is assumed when p <= 1.5 n.
+bool gram_candidate(const Instance &in) {
+    return (in.prec == L0L2_FP32 || in.prec == L0L2_BF16) && in.pp <= 2 * in.np && in.pp <= 8192;
+}
+
 bool gram_form(const l0l2_ctx *ctx) {
     const Instance &in = ctx->inst;
     if ((in.prec != L0L2_FP32 && in.prec != L0L2_BF16) || ctx->bform == 1) return false;
     if (ctx->bform == 2) return true;
-    return 2 * in.pp <= 3 * in.np && in.pp <= 8192;
+    if (!gram_candidate(in)) return false;
+    if (in.form_pick) return in.form_pick == 2;
+    return 2 * in.pp <= 3 * in.np;
 }
 
 // G in FP64 (the anchors) and FP32 (the sweeps), once per instance.
@@ -3277,6 +3289,87 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
     }
 }
 
+// The b-update form by measurement (Sec. 3.1.1 offers both the p x p matrix
+// D and the Woodbury form): on the instance's first solve with the Gram form a
+// candidate, one sweep of each form is timed on the padded batch with every
+// node masked (the products run, the epilogues write nothing), best of three
+// rounds after a warm-up; the faster form is kept for the instance, and G is
+// freed when the folded form wins.  BF16 mode times its Gram sweeps as they
+// run: a block of ten is one split-form sweep and nine single-term sweeps
+// where the LDS-staged tiles are chosen.
+void decide_form(l0l2_ctx *ctx, int64_t Kp) {
+    Instance &in = ctx->inst;
+    if (in.form_pick || ctx->bform != 0 || !gram_candidate(in) || !ctx->tune) return;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    ensure_gram(ctx);
+    const bool bf = in.prec == L0L2_BF16;
+    Sweep<float> s32 = sweep32(ctx);
+    const DevParams<float> q32 = dev_params<float>(in.mp);
+    // settle the tile shapes (their autotuner synchronises) before timing
+    const TileChoice tcf = bf ? tile_choice_bf16(ctx, Kp) : tile_choice<float>(ctx, s32, Kp);
+    HIPCHK(hipMemsetAsync(ws.active.ptr, 0, sizeof(int) * Kp, s));
+    const int *inactive = ws.active.as<int>();
+    const NodeCols all{nullptr};
+    auto folded = [&] {
+        if (bf) {
+            launch_xw_bf16(tcf.xw, ctx, s32.W, s32.U, Kp, all);
+            launch_xtu_bf16(tcf.xtu, ctx, false, Kp, inactive, 0, nullptr, all);
+        } else {
+            launch_xw<float, float, float>(tcf.xw, s, s32.XhR, s32.ldr, s32.W, s32.ldp, s32.U, s32.ldu, in.np, Kp,
+                                           in.pp, all, split_buf(ctx));
+            launch_xtu<float>(tcf.xtu, s, s32, in.np, in.pp, Kp, ws.codes.as<uint8_t>(), inactive, q32, 0);
+        }
+    };
+    const bool single = bf && ctx->bf16_terms == 1 && tcf.xtu >= 1;
+    auto gram_split = [&] {
+        if (bf) {
+            const GramBf gr{in.Ghi.as<__bf16>(), in.Glo.as<__bf16>(), in.ldgb, ws.W.as<float>(), ws.W2.as<float>()};
+            launch_xtu_bf16(tcf.xtu, ctx, false, Kp, inactive, 0, nullptr, all, &gr);
+        } else {
+            Sweep<float> g = s32;
+            g.Xh = in.G32.as<float>();
+            g.ldc = in.ldg32;
+            g.U = g.W;
+            g.ldu = in.ldp;
+            launch_xtu<float>(tcf.xtu, s, g, in.pp, in.pp, Kp, ws.codes.as<uint8_t>(), inactive, q32, 0, nullptr,
+                              GateArgs{}, all, ws.W2.as<float>());
+        }
+    };
+    auto gram_single = [&] { launch_xtu_bf16s(tcf.xtu, ctx, 1, Kp, 0, nullptr, all, 2); };
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_ms = [&](auto &&f) {
+        f();   // warm-up
+        float best = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            HIPCHK(hipEventRecord(e0, s));
+            f();
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return (double)best;
+    };
+    in.form_ms[0] = time_ms(folded);
+    in.form_ms[1] = single ? 0.1 * time_ms(gram_split) + 0.9 * time_ms(gram_single) : time_ms(gram_split);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    in.form_pick = in.form_ms[1] < in.form_ms[0] ? 2 : 1;
+    if (in.form_pick == 1) {
+        in.G64.release();
+        in.G32.release();
+        in.Ghi.release();
+        in.Glo.release();
+        in.gram_built = false;
+    }
+    drop_graphs(ctx);   // any block captured before the decision took the assumed form
+}
+
 // Mixed precision (FP32 state): reduced-precision sweeps (FP32, or the BF16
 // form) while the batch converges, then anchored sweeps (FP64 state, the
 // reduced products act on the movement since each block's FP64 anchor) from the
@@ -3290,6 +3383,7 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
 void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     Instance &in = ctx->inst;
     const int64_t Kp = round_up(K, kPadNodes);
+    decide_form(ctx, Kp);
     Sweep<float> s32 = sweep32(ctx);
     Sweep<double> s64 = sweep64(ctx);
     init_batch<float>(ctx, s32, K, Kp);
@@ -3529,6 +3623,12 @@ void run_dual_bound(l0l2_ctx *ctx, int K, const void *) {
         check_once<double>(ctx, ws.B.as<double>(), ws.B.as<double>(), Kp, 0.0, 0.0, 1);
     else
         check_once<float>(ctx, ws.B.as<float>(), ws.B.as<float>(), Kp, 0.0, 0.0, 1);
+}
+
+int bupdate_form(l0l2_ctx *ctx, double ms[2]) {
+    ms[0] = ctx->inst.form_ms[0];
+    ms[1] = ctx->inst.form_ms[1];
+    return gram_form(ctx) ? 2 : 1;
 }
 
 }  // namespace l0l2

@@ -464,6 +464,17 @@ int l0l2_set_bf16_terms(l0l2_ctx *ctx, int terms) {
     });
 }
 
+int l0l2_bupdate_form(l0l2_ctx *ctx, int *form, double *ms_folded, double *ms_gram) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        if (!form) l0l2::fail(L0L2_E_INVALID, "null argument");
+        double ms[2];
+        *form = l0l2::bupdate_form(ctx, ms);
+        if (ms_folded) *ms_folded = ms[0];
+        if (ms_gram) *ms_gram = ms[1];
+    });
+}
+
 int l0l2_profile_enable(l0l2_ctx *ctx, int enable) {
     return guarded(ctx, [&] {
         l0l2::prof_collect(ctx);

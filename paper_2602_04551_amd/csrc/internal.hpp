@@ -134,6 +134,8 @@ struct Instance {
     DevBuf G64, G32, Ghi, Glo;   // Ghi / Glo: BF16 mode, G as two BF16 terms (ld ldgb)
     int64_t ldg64 = 0, ldg32 = 0, ldgb = 0;
     bool gram_built = false;
+    int form_pick = 0;           // b-update form measured on the first solve: 0 not yet, 1 folded, 2 Gram
+    double form_ms[2] = {0, 0};  // the per-sweep times that decided it (folded, Gram)
 };
 
 // Per-batch workspace, grown on demand (capacity in padded nodes).
@@ -273,6 +275,10 @@ void *noalloc_scratch(int device);
 double run_exact_objective(l0l2_ctx *ctx, const uint8_t *support_host, double *beta_host);
 // state (f32 or f64, ld_src) -> f64 (ld_dst) copy of K rows of length p
 void state_to_f64(l0l2_ctx *ctx, int K, const void *src, int64_t ld_src, double *dst, int64_t ld_dst);
+
+// b-update form (l0l2_bupdate_form): 1 folded, 2 Gram; times of one sweep of
+// each as measured (0 when not measured).
+int bupdate_form(l0l2_ctx *ctx, double ms[2]);
 
 // heuristic.hip: forward / backward matching pursuit from the empty support;
 // host outputs mask and beta (p entries), moves (room for max_moves, may be null)

@@ -342,6 +342,8 @@ void set_data(l0l2_ctx *ctx, const double *X, const double *y, int64_t n, int64_
     in.tiles.clear();
     in.tuned_K = 0;
     in.gram_built = false;
+    in.form_pick = 0;
+    in.form_ms[0] = in.form_ms[1] = 0.0;
     in.n = n;
     in.p = p;
     in.np = round_up(n, kPadRows);

@@ -45,10 +45,11 @@ size_t footprint_bytes(int64_t n, int64_t p, int prec, int K) {
     ws += 8.0 * Kp * np;                                   // refinement residuals
     ws += 8.0 * 8.0 * Kp * np;                             // partial products of the sliced contraction over p
     double bnb = 9.0 * Kp * (double)p + 2.0 * sb * pp * 16.0 * Kp;   // supports, starts, pool reserve
-    // Gram form of the b-update (FP32 and BF16 modes, p <= 1.5 n, padded p at
-    // most 8192): G in FP64 and FP32 (and a BF16 pair), and a second W buffer
+    // Gram form of the b-update where it is a candidate (FP32 and BF16 modes,
+    // padded p at most twice padded n and at most 8192): G in FP64 and FP32 (and
+    // a BF16 pair), and a second W buffer
     const int64_t np0 = round_up(n, kPadRows), pp0 = round_up(p, kPadRows);
-    if ((prec == L0L2_FP32 || prec == L0L2_BF16) && 2 * pp0 <= 3 * np0 && pp0 <= 8192) {
+    if ((prec == L0L2_FP32 || prec == L0L2_BF16) && pp0 <= 2 * np0 && pp0 <= 8192) {
         inst += (prec == L0L2_BF16 ? 16.0 : 12.0) * pp * pp;
         ws += 4.0 * Kp * pp;
     }

@@ -28,7 +28,7 @@ import dataclasses
 import numpy as np
 
 __all__ = ["Instance", "make_instance", "CONFIGS", "config_instance", "node_batch_codes", "frontier_codes",
-           "FREE", "FIX0", "FIX1"]
+           "select_lambda2", "node_parallel_instance", "serving_instance", "FREE", "FIX0", "FIX1"]
 
 FREE, FIX0, FIX1 = 0, 1, 2
 
@@ -43,6 +43,7 @@ class Instance:
     beta_true: np.ndarray  # (p,) float64
     name: str = ""
     seed: int = 0
+    y_scale: float = 1.0   # the norm y was divided by: the truth in the units of y is beta_true / y_scale
 
     @property
     def n(self) -> int:
@@ -102,7 +103,7 @@ def make_instance(n: int, p: int, *, corr: str = "toeplitz", rho: float = 0.5, k
     if M is None:
         M = 1.5 * float(np.max(np.abs(_ridge_on_support(X, y, support, lambda2)))) if k else 1.0
     return Instance(X=X, y=y, lambda0=float(lambda0), lambda2=float(lambda2), M=float(M),
-                    beta_true=beta, name=name, seed=seed)
+                    beta_true=beta, name=name, seed=seed, y_scale=float(ny) if ny > 0 else 1.0)
 
 
 # The workloads: (small oracle case, plain GPU case, batching, serving draw, high-dim).
@@ -118,6 +119,35 @@ def config_instance(name: str, seed: int = 0, **override) -> Instance:
     kw = dict(CONFIGS[name])
     kw.update(override)
     return make_instance(seed=seed, name=name, **kw)
+
+
+def select_lambda2(inst: Instance, grid=None) -> float:
+    """lambda2* of Sec. 4.1: the lambda2 on a grid (100 log-spaced points over
+    [1e-4, 1e4]) whose ridge fit restricted to the true support is closest in
+    l2 to beta_dagger, taken in the units of the scaled response (beta_dagger /
+    y_scale: y was divided by its norm)."""
+    grid = np.logspace(-4, 4, 100) if grid is None else np.asarray(grid, dtype=np.float64)
+    support = np.flatnonzero(inst.beta_true)
+    if len(support) == 0:
+        return float(grid[0])
+    truth = inst.beta_true[support] / inst.y_scale
+    errs = [np.linalg.norm(_ridge_on_support(inst.X, inst.y, support, l2) - truth) for l2 in grid]
+    return float(grid[int(np.argmin(errs))])
+
+
+def node_parallel_instance(p: int, seed: int = 0) -> Instance:
+    """The node-parallel study's design (Sec. 4.4, with the data of Sec. 4.1):
+    n = 3000, constant correlation 0.2, k = 10 unit spikes, SNR = 10/3; lambda2 =
+    lambda2* (select_lambda2), M = 1.5 x the ridge fit on the true support at
+    that lambda2.  lambda0 is left to the caller (the paper tunes it along a
+    path); the placeholder is 0.005."""
+    inst = make_instance(3000, p, corr="constant", rho=0.2, k=10, snr=10.0 / 3.0, lambda0=0.005,
+                         lambda2=0.01, seed=seed, name=f"np{p}")
+    l2 = select_lambda2(inst)
+    support = np.flatnonzero(inst.beta_true)
+    inst.lambda2 = l2
+    inst.M = 1.5 * float(np.max(np.abs(_ridge_on_support(inst.X, inst.y, support, l2))))
+    return inst
 
 
 def serving_instance(rng: np.random.Generator, seed: int) -> Instance:

@@ -56,13 +56,14 @@ def test_footprint_estimate_grows_with_size_and_batch():
     assert f(1000, 1000, 1, 256) > f(1000, 1000, 1, 32) > 0
     assert f(2000, 1000, 1, 256) > f(1000, 1000, 1, 256)
     assert f(1000, 2000, 1, 256) > f(1000, 1000, 1, 256)
-    assert f(1000, 2000, 0, 256) > f(1000, 2000, 1, 256)  # FP64 state is twice as wide
-    # the Gram form's p x p buffers count where that form applies (p <= 1.5 n):
-    # just inside the limit the estimate exceeds that of a wider design just outside
+    assert f(1000, 2100, 0, 256) > f(1000, 2100, 1, 256)  # FP64 state is twice as wide (no Gram form at p > 2 n)
+    # the Gram form's p x p buffers count where that form is a candidate (padded
+    # p <= 2 padded n): just inside the limit the estimate exceeds that of a
+    # wider design just outside
     for prec in (1, 2):
-        assert f(1000, 1500, prec, 256) > f(1000, 1600, prec, 256)
+        assert f(1000, 2000, prec, 256) > f(1000, 2100, prec, 256)
         assert f(1000, 1500, prec, 256) - f(1000, 1400, prec, 256) > 12 * 1536 ** 2 - 12 * 1408 ** 2
     assert f(1000, 1500, 2, 256) - f(1000, 1500, 1, 256) >= 4 * 1536 ** 2   # BF16 also keeps G as a BF16 pair
-    assert f(1000, 1500, 3, 256) < f(1000, 1600, 3, 256)       # no Gram form in FP8 mode
+    assert f(1000, 2000, 3, 256) < f(1000, 2100, 3, 256)       # no Gram form in FP8 mode
     # dominated by the instance copies for a wide design
     assert f(1000, 50000, 2, 256) > 8 * 1000 * 50000
