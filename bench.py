@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--no-highdim", action="store_true", help="skip the n = 1000, p = 50000 node batches")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--cpu-sample", type=int, default=32, help="nodes of the headline batch the oracle solves")
+    ap.add_argument("--cpu-sample", type=int, default=128, help="nodes of the headline batch the oracle solves")
     ap.add_argument("--only-mixed", action="store_true", help="headline precision only (short profiled runs)")
     ap.add_argument("--batching", action="store_true",
                     help="n = p = 5000 node batches of 512..4096 (free sets U[50, p]), BF16 vs FP32")
@@ -63,6 +63,10 @@ def parse():
     ap.add_argument("--np-p", type=str, default="10000,30000,100000")
     ap.add_argument("--np-precision", type=str, default="fp64")
     ap.add_argument("--np-tol", type=float, default=1e-4, help="node gap tolerance of the study (the paper's 1e-4)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/hbm_traffic.json from two rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE) "
+                         "of a --copy-calibrate run of the headline, then exit")
+    ap.add_argument("--traffic-workload", default="c3")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="first dispatch one device copy of 256 MiB, the reference for HBM counter scaling")
     return ap.parse_args()
@@ -182,14 +186,31 @@ def _cpu_baseline_proc(cfg, K, sample, rb, rv, seconds, workers, conn):
 
 
 def cpu_model():
+    """The host CPU as lscpu names it (model name, sockets, cores), else /proc/cpuinfo's model name."""
+    import subprocess
+    info = {}
     try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return "unknown"
+    name = info.get("Model name")
+    if not name:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        name = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    parts = [name or "unknown"]
+    for k in ("Socket(s)", "Core(s) per socket", "Thread(s) per core", "CPU(s)"):
+        if k in info:
+            parts.append(f"{k} {info[k]}")
+    return ", ".join(parts)
 
 
 def cpu_baseline(cfg, K, root, seconds, sample):
@@ -272,6 +293,56 @@ def measured_traffic(kname, workload):
     if not rec or kernel_source_digest() != rec.get("source_digest"):
         return None
     return rec["per_launch_bytes"].get(kname)
+
+
+# library kernel families and the kernel names that belong to them
+FAMILIES = {"admm_xtu.bf16": ("k_admm_xtu_bf16", "k_admm_xtu_anch_bf16"),
+            "admm_xtu.f32": ("k_admm_xtu<float", "k_admm_xtu_lds<float", "k_admm_xtu_anch"),
+            "admm_xtu.f64": ("k_admm_xtu<double", "k_admm_xtu_lds<double")}
+
+
+def traffic_summary(fetch_csv, write_csv, workload, last=50):
+    """HBM bytes per launch of each sweep family from two rocprofv3 counter
+    passes of the same command: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    scaled by what each reads for the 256 MiB device copy dispatched first
+    (--copy-calibrate), averaged over the family's last `last` dispatches (the
+    benchmark's last step; the tile tuner's masked launches come earlier)."""
+    import csv
+    import re
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return rows
+
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = load(path, counter)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        ref = max(copies) * 1024.0 if copies else None
+        scale = (256.0 * 2 ** 20) / ref if ref else 1.0
+        for fam, pats in FAMILIES.items():
+            vals = [float(r["Counter_Value"]) * 1024.0 * scale for r in rows
+                    if any(re.search(re.escape(pt), r["Kernel_Name"]) for pt in pats)]
+            if vals:
+                v = vals[-last:]
+                out.setdefault(fam, {})[counter] = (sum(v) / len(v), len(v), scale)
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
+    allw = json.load(open(path)) if os.path.exists(path) else {}
+    allw[workload] = {
+        "what": "HBM bytes per launch of each sweep family: FETCH_SIZE + WRITE_SIZE, each scaled so that the "
+                "256 MiB device copy dispatched first reads 256 MiB, averaged over the family's last dispatches "
+                "(the benchmark's last step); valid for the kernel sources of the digest",
+        "source_digest": kernel_source_digest(),
+        "per_launch_bytes": {f: round(v["FETCH_SIZE"][0] + v["WRITE_SIZE"][0]) for f, v in out.items()
+                             if "FETCH_SIZE" in v and "WRITE_SIZE" in v},
+        "fetch_bytes": {f: round(v["FETCH_SIZE"][0]) for f, v in out.items() if "FETCH_SIZE" in v},
+        "write_bytes": {f: round(v["WRITE_SIZE"][0]) for f, v in out.items() if "WRITE_SIZE" in v},
+        "dispatches": {f: v["FETCH_SIZE"][1] for f, v in out.items() if "FETCH_SIZE" in v},
+        "scale": {c: next(iter(out.values()))[c][2] for c in ("FETCH_SIZE", "WRITE_SIZE") if out}}
+    with open(path, "w") as f:
+        json.dump(allw, f, indent=1)
+    print(json.dumps(allw[workload]))
 
 
 def roofline(prof, n, p, workload=None):
@@ -526,6 +597,8 @@ def serve_main(args):
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        return traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.traffic_workload)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)

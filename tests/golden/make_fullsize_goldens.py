@@ -17,7 +17,11 @@ tests/golden/ so that they can be regenerated independently:
   k = 25, SNR 3, lambda0 = 0.002, lambda2 = 0.005): the same with eight nodes of
   the 1024-node batch (seed 1024).
 
-Usage: python tests/golden/make_fullsize_goldens.py {c2|c3|c5} [workers]
+* fullsize_c3_root.npz / fullsize_c5_root.npz -- the oracle's root iterates
+  (beta, v) of the two node parts, the warm start the sampled nodes were solved
+  from (written with the node part, or alone by the c3root / c5root modes).
+
+Usage: python tests/golden/make_fullsize_goldens.py {c2|c3|c5|c3root|c5root} [workers]
 The node parts build one oracle instance, solve the root, then solve the
 sampled nodes in `workers` forked processes; c3 and c5 take tens of minutes of
 CPU time.
@@ -74,7 +78,12 @@ def _node(args):
             "cpu_seconds": round(time.perf_counter() - t0, 1)}
 
 
-def nodes(name, workers):
+def save_root(name, root):
+    np.savez_compressed(os.path.join(HERE, f"fullsize_{name.lower()}_root.npz"), beta=root["beta"], v=root["v"],
+                        iters=np.int64(root["iters"]), lb=np.float64(root["lb"]), primal=np.float64(root["primal"]))
+
+
+def nodes(name, workers, root_only=False):
     global _O
     import multiprocessing as mp
     inst = datagen.config_instance(name, seed=0)
@@ -86,6 +95,9 @@ def nodes(name, workers):
     t_root = time.perf_counter() - t0 - t_create
     print(json.dumps({"root_iters": root["iters"], "root_status": root["status"], "create_s": round(t_create, 1),
                       "root_s": round(t_root, 1)}), flush=True)
+    save_root(name, root)
+    if root_only:
+        return
     codes = datagen.node_batch_codes(inst.p, K, seed=K)
     jobs = [(k, codes[k], root["beta"], root["v"]) for k in slots]
     # fork: the workers share the precomputed instance (this process never uses a GPU)
@@ -109,5 +121,7 @@ if __name__ == "__main__":
     w = int(sys.argv[2]) if len(sys.argv) > 2 else 4
     if which == "c2":
         c2()
+    elif which.endswith("root"):
+        nodes(which[:2].upper(), w, root_only=True)
     else:
         nodes(which.upper(), w)
