@@ -125,6 +125,30 @@ int l0l2_solve_node_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta
                           const l0l2_admm_opts *opts, double *lb, double *primal,
                           int32_t *iters, int32_t *status);
 
+/* Continuous batching of node relaxations (the batching pattern's slot refill,
+ * Sec. 3.2's batch of K nodes kept full): N queued nodes run through K slots;
+ * at every block boundary (check_every sweeps) the slots whose nodes retired
+ * (gap <= tol_node, or max_iter sweeps of their own done) hand over their
+ * results and take the next queued nodes, in queue order, until the queue is
+ * empty.  Each node counts its own sweeps.  FP64 mode runs the plain FP64
+ * sweeps; FP32, BF16 and FP8 modes run anchored from the first sweep (FP64
+ * state, an FP64 anchor product per block, the reduced products on the
+ * movement since it), so a node joining a running batch needs no phase of its
+ * own.  codes: device N x p uint8; beta, v: device N x p state elements (FP64,
+ * or FP32 in the reduced modes), the warm starts, overwritten with each node's
+ * final iterates; outputs (device, N each) as in l0l2_solve_node_batch.
+ * Waits at every block boundary. */
+int l0l2_solve_node_queue(l0l2_ctx *ctx, int N, const uint8_t *codes, void *beta, void *v, int K,
+                          const l0l2_admm_opts *opts, double *lb, double *primal, int32_t *iters,
+                          int32_t *status);
+
+/* Block statistics of the last l0l2_solve_node_batch or l0l2_solve_node_queue
+ * on ctx: *blocks = blocks of sweeps issued, *sparse_blocks = those with fewer
+ * than 1/8 of the padded batch still live, *node_blocks = the live nodes summed
+ * over the blocks (node_blocks / (blocks x padded K) is the batch's occupancy).
+ * Any pointer may be NULL. */
+int l0l2_batch_stats(l0l2_ctx *ctx, int64_t *blocks, int64_t *sparse_blocks, int64_t *node_blocks);
+
 /* Rounding and branching for K nodes (Sec. 3.3; branching rule: most fractional
  * z_j, score floored to a 2^-20 grid, ties to the smallest index; when all free
  * scores are 0, the free index of largest |beta_j|).  z_j follows App. A.1.

@@ -70,6 +70,8 @@ SIGNATURES = {
     "l0l2_dual_bound": (_i, [_vp, _i, _vp, _vp, _vp]),
     "l0l2_solve_node_batch": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_admm_opts), _vp, _vp, _vp, _vp]),
     "l0l2_round_branch": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "l0l2_solve_node_queue": (_i, [_vp, _i, _vp, _vp, _vp, _i, C.POINTER(l0l2_admm_opts), _vp, _vp, _vp, _vp]),
+    "l0l2_batch_stats": (_i, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "l0l2_refine_incumbent": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_fista_opts), _vp, _vp]),
     "l0l2_refine_incumbent_noalloc": (_i, [_vp, _i, _vp, _vp, _vp, C.POINTER(l0l2_fista_opts), _vp, _vp]),
     "l0l2_exact_objective": (_i, [_vp, _vp, _vp, _vp]),
@@ -221,6 +223,29 @@ class Context:
         self._check(lib.l0l2_solve_node_batch(self._h, K, _ptr(codes), _ptr(beta), _ptr(v), C.byref(o),
                                               _ptr(lb), _ptr(primal), _ptr(iters), _ptr(status)))
         return dict(lb=lb, primal=primal, iters=iters, status=status, beta=beta, v=v)
+
+    def solve_node_queue(self, codes, beta=None, v=None, K=256, tol_node=1e-6, max_iter=2000, check_every=10):
+        """N queued nodes through K slots, refilled as nodes retire (l0l2_solve_node_queue)."""
+        torch = _torch()
+        codes = self._dev(codes, torch.uint8)
+        N = codes.shape[0]
+        dt = self.state_dtype
+        beta = torch.zeros((N, self.p), dtype=dt, device=self.torch_device) if beta is None else self._dev(beta, dt).clone()
+        v = torch.zeros((N, self.p), dtype=dt, device=self.torch_device) if v is None else self._dev(v, dt).clone()
+        lb = torch.empty(N, dtype=torch.float64, device=self.torch_device)
+        primal = torch.empty_like(lb)
+        iters = torch.empty(N, dtype=torch.int32, device=self.torch_device)
+        status = torch.empty_like(iters)
+        o = l0l2_admm_opts(float(tol_node), int(max_iter), int(check_every))
+        self._check(lib.l0l2_solve_node_queue(self._h, N, _ptr(codes), _ptr(beta), _ptr(v), int(K), C.byref(o),
+                                              _ptr(lb), _ptr(primal), _ptr(iters), _ptr(status)))
+        return dict(lb=lb, primal=primal, iters=iters, status=status, beta=beta, v=v)
+
+    def batch_stats(self):
+        """(blocks, blocks with < 1/8 of the batch live, live nodes summed over blocks) of the last solve."""
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._check(lib.l0l2_batch_stats(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
 
     def round_branch(self, codes, beta):
         torch = _torch()

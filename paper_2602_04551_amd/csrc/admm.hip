@@ -89,7 +89,7 @@ __global__ void k_store_state(const T *__restrict__ src, int64_t K, int64_t p, i
 
 // Batch start: nodes 0..K-1 active (the active list is 0..K-1), padding inactive.
 __global__ void k_set_active(int *active, int *status, int *iters, int *list, int *clist, int64_t K, int64_t Kp,
-                             int *sweep_no) {
+                             int *sweep_no, int *start) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < Kp) {
         active[k] = k < K;
@@ -97,6 +97,7 @@ __global__ void k_set_active(int *active, int *status, int *iters, int *list, in
         iters[k] = 0;
         list[k] = k < K ? (int)k : -1;
         clist[k] = -1;
+        start[k] = 0;
     }
     if (k == 0) *sweep_no = 0;
 }
@@ -110,6 +111,7 @@ __global__ void k_sweep_add(int *sweep_no, int n, int *gate, int *ncount, int *c
     *ncount = 0;
     counter[0] = 0;
     counter[1] = 0;
+    counter[2] = 0;
 }
 
 // Warm start of Sec. 3.1.3: impose F0 on beta, then W = c + rho beta - V.
@@ -1945,7 +1947,8 @@ __global__ __launch_bounds__(64 * kWavesDual) void k_dual_xtr(
 struct FinArgs {
     double gamma_n2, gamma_p, tol, switch_tol;
     int64_t K, ntile, ntr;
-    int mode;  // mode 0: solve (gap test), 1: bound only
+    int mode;    // mode 0: solve (gap test), 1: bound only
+    int budget;  // > 0: a node that has done this many sweeps since it started retires (status 1)
 };
 
 // One wave per node slot: LB = (q - sum nu+) - margin (Prop. 1 plus the
@@ -1963,10 +1966,17 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpa
                                                   double *__restrict__ primal, int *__restrict__ counter,
                                                   int *__restrict__ nlist, int *__restrict__ ncount,
                                                   const int *__restrict__ sweep_no, FinArgs fa,
-                                                  const int *__restrict__ needs, const double *__restrict__ gest) {
+                                                  const int *__restrict__ needs, const double *__restrict__ gest,
+                                                  const int *__restrict__ start, int *__restrict__ dlist) {
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= fa.K || !active[k]) return;
+    // a retired node (converged, or at its sweep budget) is listed for the host
+    auto retire = [&](int st) {
+        status[k] = st;
+        active[k] = 0;
+        dlist[atomicAdd(&counter[2], 1)] = (int)k;
+    };
     auto keep = [&](bool above) {
         nlist[atomicAdd(ncount, 1)] = (int)k;
         atomicAdd(&counter[0], 1);
@@ -2007,11 +2017,13 @@ __global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ rpa
     if (fa.mode == 1) return;
     const double P = 0.5 * rbrb + spsi;
     primal[k] = P;
-    iters[k] = *sweep_no;
+    const int done = *sweep_no - start[k];
+    iters[k] = done;
     const double den = fabs(P) > 1e-300 ? fabs(P) : 1e-300;
     if ((P - LB) / den <= fa.tol) {
-        status[k] = 0;
-        active[k] = 0;
+        retire(0);
+    } else if (fa.budget > 0 && done >= fa.budget) {
+        retire(1);
     } else {
         status[k] = 1;
         keep((P - LB) / den > fa.switch_tol);
@@ -2032,6 +2044,7 @@ __global__ __launch_bounds__(256) void k_list_commit(const int *__restrict__ nli
 struct GateFin {
     double yy, tol;
     int64_t K, ntile;
+    int budget;   // > 0: nodes at their sweep budget go to the exact check whatever the estimate
 };
 
 // Gap estimate per node (one wave each) from the per-tile sums of the last
@@ -2043,7 +2056,8 @@ struct GateFin {
 // the check list (clist, gate[0]) with integer atomics.
 __global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, const int *__restrict__ active,
                                               int *__restrict__ needs, double *__restrict__ gest,
-                                              int *__restrict__ clist, int *__restrict__ gate, GateFin gf) {
+                                              int *__restrict__ clist, int *__restrict__ gate, GateFin gf,
+                                              const int *__restrict__ sweep_no, const int *__restrict__ start) {
     const int lane = threadIdx.x & 63;
     const int64_t k = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= gf.K || !active[k]) return;
@@ -2056,7 +2070,8 @@ __global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, 
         const double rr = gf.yy - 2.0 * e[0] + e[1];
         const double D = -0.5 * rr + (gf.yy - e[0]) - e[2];
         const double Pl = 0.5 * rr - e[3] + e[4];
-        const bool far = Pl > 0.0 && (Pl - D) > 2.0 * gf.tol * Pl;
+        const bool spent = gf.budget > 0 && *sweep_no - start[k] >= gf.budget;
+        const bool far = !spent && Pl > 0.0 && (Pl - D) > 2.0 * gf.tol * Pl;
         needs[k] = far ? 0 : 1;
         gest[k] = Pl > 0.0 ? (Pl - D) / Pl : INFINITY;
         if (!far) clist[atomicAdd(&gate[0], 1)] = (int)k;
@@ -3089,7 +3104,7 @@ DualArgs dual_args(const Instance &in) {
 // node (mode 0) or every node of the padded batch (mode 1, bound only).
 template <class T>
 void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol, double switch_tol, int mode,
-                bool gated = false) {
+                bool gated = false, int budget = 0) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
@@ -3117,11 +3132,12 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     fa.ntile = pp / 32;
     fa.ntr = ntr;
     fa.mode = mode;
+    fa.budget = budget;
     hipLaunchKernelGGL(k_finalize, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.rpart.as<double>(),
                        ws.part.as<double>(), ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(),
                        ws.lb.as<double>(), ws.primal.as<double>(), ws.counter.as<int>(), ws.nlist.as<int>(),
                        ws.ncount.as<int>(), ws.sweep_no.as<int>(), fa, gated ? ws.needs.as<int>() : nullptr,
-                       ws.gest.as<double>());
+                       ws.gest.as<double>(), ws.start.as<int>(), ws.dlist.as<int>());
     if (mode == 0)
         hipLaunchKernelGGL(k_list_commit, dim3(1), dim3(256), 0, s, ws.nlist.as<int>(), ws.ncount.as<int>(),
                            ws.list.as<int>(), ws.clist.as<int>(), Kp);
@@ -3136,10 +3152,76 @@ void init_batch(l0l2_ctx *ctx, const Sweep<T> &sw, int64_t K, int64_t Kp) {
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
                        ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(), ws.clist.as<int>(), K, Kp,
-                       ws.sweep_no.as<int>());
+                       ws.sweep_no.as<int>(), ws.start.as<int>());
     hipLaunchKernelGGL((k_init<T>), dim3(grid1d(Kp * in.ldp)), dim3(256), 0, s, ws.codes.as<uint8_t>(), sw.beta,
                        sw.V, sw.W, sw.c, (T)in.mp.rho, in.ldp, Kp * in.ldp);
     HIPCHK(hipGetLastError());
+}
+
+// Continuous batching (node queue): slot pairs[2e] takes queue node pairs[2e+1]:
+// its codes (FIX0 past p), its warm start (beta with F0 imposed, V) in the state
+// type T, W = c + rho beta - V, and (promote) the FP64 state of the anchored
+// sweeps; the slot becomes active with its sweep count starting now.
+template <class T>
+__global__ void k_queue_load(const uint8_t *__restrict__ qcodes, const T *__restrict__ qbeta,
+                             const T *__restrict__ qv, int64_t p, const int *__restrict__ pairs, uint8_t *codes,
+                             T *beta, T *V, T *W, const T *__restrict__ c, T rho, double *beta64, double *V64,
+                             double *W64, const double *__restrict__ c64, double rho64, int promote, int64_t ldp,
+                             int *active, int *status, int *iters, int *start, const int *__restrict__ sweep_no) {
+    const int e = blockIdx.y;
+    const int slot = pairs[2 * e], q = pairs[2 * e + 1];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < ldp) {
+        const int64_t o = (int64_t)slot * ldp + j;
+        const uint8_t code = j < p ? qcodes[(int64_t)q * p + j] : (uint8_t)CODE_FIX0;
+        const T b = (j < p && code != CODE_FIX0) ? qbeta[(int64_t)q * p + j] : T(0);
+        const T v = j < p ? qv[(int64_t)q * p + j] : T(0);
+        codes[o] = code;
+        beta[o] = b;
+        V[o] = v;
+        W[o] = c[j] + rho * b - v;
+        if (promote) {
+            beta64[o] = (double)b;
+            V64[o] = (double)v;
+            W64[o] = c64[j] + rho64 * (double)b - (double)v;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        active[slot] = 1;
+        status[slot] = 1;
+        iters[slot] = 0;
+        start[slot] = *sweep_no;
+    }
+}
+
+// The results of retired slots to their queue positions: lb, primal, sweeps,
+// status, and the final (beta, V) in the output type TO from the state of the
+// slot (the FP64 state of anchored sweeps, or the state itself).
+template <class TS, class TO>
+__global__ void k_queue_store(const int *__restrict__ pairs, const TS *__restrict__ beta, const TS *__restrict__ V,
+                              int64_t ldp, int64_t p, const double *__restrict__ lb, const double *__restrict__ primal,
+                              const int *__restrict__ iters, const int *__restrict__ status, TO *__restrict__ qbeta,
+                              TO *__restrict__ qv, double *__restrict__ qlb, double *__restrict__ qprimal,
+                              int *__restrict__ qiters, int *__restrict__ qstatus) {
+    const int e = blockIdx.y;
+    const int slot = pairs[2 * e], q = pairs[2 * e + 1];
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < p) {
+        qbeta[(int64_t)q * p + j] = (TO)beta[(int64_t)slot * ldp + j];
+        qv[(int64_t)q * p + j] = (TO)V[(int64_t)slot * ldp + j];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        qlb[q] = lb[slot];
+        qprimal[q] = primal[slot];
+        qiters[q] = iters[slot];
+        qstatus[q] = status[slot];
+    }
+}
+
+// Appends m slots to the active list after its first `base` entries.
+__global__ void k_list_append(int *list, int64_t base, const int *__restrict__ pairs, int m) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) list[base + e] = pairs[2 * e];
 }
 
 enum SweepKind { SK_F32 = 0, SK_F64 = 1, SK_BF16 = 2, SK_ANCH = 3 };
@@ -3161,7 +3243,7 @@ int64_t live_bucket(const l0l2_ctx *ctx, int64_t active, int64_t Kp) {
 }
 
 void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
-                 bool force) {
+                 bool force, int budget) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
@@ -3197,33 +3279,36 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
             rows = kBfTM[tile_choice_bf16(ctx, cols).xtu];
         else if (kind == SK_ANCH && in.prec == L0L2_FP8) rows = kF8TM[tile_choice_fp8(ctx, cols).xtu];
         else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), cols).xtu];
-        GateFin gf{in.yy, tol, Kp, in.pp / rows};
+        GateFin gf{in.yy, tol, Kp, in.pp / rows, budget};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
                            ws.active.as<int>(), ws.needs.as<int>(), ws.gest.as<double>(), ws.clist.as<int>(),
-                           ws.gate.as<int>(), gf);
+                           ws.gate.as<int>(), gf, (const int *)ws.sweep_no.ptr, (const int *)ws.start.ptr);
         prof_end(ctx, PROF_CHECK);
         HIPCHK(hipGetLastError());
     }
     if (kind == SK_F64 || kind == SK_ANCH) {
         Sweep<double> sw = sweep64(ctx);
-        check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, !force);
+        check_once<double>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, !force, budget);
     } else {
         Sweep<float> sw = sweep32(ctx);
-        check_once<float>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, !force);
+        check_once<float>(ctx, sw.B, sw.beta, Kp, tol, switch_tol, 0, !force, budget);
     }
-    HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
 }
 
 // Run one block and return the counters.  Blocks are captured once into a HIP
 // graph per (kind, padded batch, block length, tolerances) and replayed; with
 // the profiler on they are issued eagerly so each launch can be timed.
 void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
-               bool force, int out[2]) {
+               bool force, int out[3], int budget = 0) {
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
+    ++ws.stat_blocks;
+    ws.stat_node_blocks += active;
+    if (8 * active < Kp) ++ws.stat_sparse;
     if (!ctx->use_graphs || ctx->prof.on) {
-        issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
+        issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force, budget);
     } else {
         const int64_t cols = live_bucket(ctx, active, Kp);
         // settle the tile shapes first (the autotuner synchronises, and may grow
@@ -3234,7 +3319,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
         if (kind == SK_F32 || (kind == SK_ANCH && !bf && !f8)) (void)tile_choice<float>(ctx, sweep32(ctx), cols);
         if (kind == SK_BF16 || (kind == SK_ANCH && bf)) (void)tile_choice_bf16(ctx, cols);
         if (kind == SK_ANCH && f8) (void)tile_choice_fp8(ctx, cols);
-        GraphKey key{kind, Kp, cols, n, force ? 1 : 0, tol, switch_tol, ws.gen};
+        GraphKey key{kind, Kp, cols, n, force ? 1 : 0, tol, switch_tol, ws.gen, budget};
         auto it = ctx->graphs.find(key);
         if (it == ctx->graphs.end()) {
             hipGraph_t g = nullptr;
@@ -3242,7 +3327,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
             if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                 bool ok = true;
                 try {
-                    issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
+                    issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force, budget);
                 } catch (...) {
                     ok = false;
                 }
@@ -3255,10 +3340,11 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
             if (!ex) {
                 // capture is not available here: issue blocks launch by launch from now on
                 ctx->use_graphs = false;
-                issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force);
+                issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force, budget);
                 HIPCHK(hipStreamSynchronize(s));
                 out[0] = ws.host_counter[0];
                 out[1] = ws.host_counter[1];
+                out[2] = ws.host_counter[2];
                 return;
             }
             it = ctx->graphs.emplace(key, ex).first;
@@ -3268,6 +3354,7 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
     HIPCHK(hipStreamSynchronize(s));
     out[0] = ws.host_counter[0];
     out[1] = ws.host_counter[1];
+    out[2] = ws.host_counter[2];
 }
 
 // Single-precision-type solve (FP64 mode).
@@ -3276,7 +3363,7 @@ void solve_plain(l0l2_ctx *ctx, const Sweep<T> &sw, int K, const l0l2_admm_opts 
     const int64_t Kp = round_up(K, kPadNodes);
     init_batch<T>(ctx, sw, K, Kp);
     const int m = std::max(1, o.check_every);
-    int cnt[2];
+    int cnt[3];
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
         check_cancel(ctx);
@@ -3398,7 +3485,7 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
         HIPCHK(hipGetLastError());
         fp64 = true;
     }
-    int cnt[2], best_above = 1 << 30, flat = 0;
+    int cnt[3], best_above = 1 << 30, flat = 0;
     int64_t active = K;
     for (int t = 0; t < o.max_iter;) {
         check_cancel(ctx);
@@ -3426,6 +3513,101 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     }
 }
 
+// Continuous batching of node relaxations (the batching pattern's slot
+// refill): N queued nodes run through the K slots of the workspace; at each
+// block boundary the slots whose nodes retired (converged, or at their own
+// sweep budget) hand their results to the nodes' queue positions and take the
+// next queued nodes, so the sweeps keep covering a full batch until the queue
+// runs dry.  Each node has its own sweep count and budget.  FP64 mode runs its
+// plain sweeps; the reduced modes run anchored from the first sweep (FP64
+// state, an FP64 anchor per block, the reduced products act on the movement
+// since it), so a node that joins a running batch needs no phase of its own.
+template <class T>
+void solve_queue_t(l0l2_ctx *ctx, int N, const uint8_t *qcodes, void *qbeta, void *qv, int K,
+                   const l0l2_admm_opts &o, double *qlb, double *qprimal, int32_t *qiters, int32_t *qstatus) {
+    Instance &in = ctx->inst;
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    const int64_t Kp = round_up(K, kPadNodes), ldp = in.ldp;
+    const bool fp64 = in.prec == L0L2_FP64;
+    if (!fp64) decide_form(ctx, Kp);
+    Sweep<double> s64 = sweep64(ctx);
+    Sweep<float> s32 = sweep32(ctx);
+    const T *c = fp64 ? (const T *)s64.c : (const T *)s32.c;
+    T *beta = fp64 ? (T *)s64.beta : (T *)s32.beta;
+    T *V = fp64 ? (T *)s64.V : (T *)s32.V;
+    T *W = fp64 ? (T *)s64.W : (T *)s32.W;
+    hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, s, ws.active.as<int>(),
+                       ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(), ws.clist.as<int>(), (int64_t)0,
+                       Kp, ws.sweep_no.as<int>(), ws.start.as<int>());
+    HIPCHK(hipGetLastError());
+    std::vector<int> slot_q((size_t)Kp, -1), freed, pairs, dl;
+    DevBuf dpairs;
+    dpairs.ensure(sizeof(int) * 2 * (size_t)Kp);
+    int next = 0;
+    int64_t active = 0;
+    // slots `freed` take the next queued nodes (as many as remain)
+    auto refill = [&](std::vector<int> &slots) {
+        const int m = (int)std::min<int64_t>((int64_t)slots.size(), (int64_t)N - next);
+        if (m <= 0) return;
+        pairs.assign((size_t)2 * m, 0);
+        for (int e = 0; e < m; ++e) {
+            pairs[(size_t)2 * e] = slots[(size_t)e];
+            pairs[(size_t)2 * e + 1] = next;
+            slot_q[(size_t)slots[(size_t)e]] = next++;
+        }
+        HIPCHK(hipMemcpyAsync(dpairs.ptr, pairs.data(), sizeof(int) * 2 * m, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL((k_queue_load<T>), dim3((unsigned)((ldp + 255) / 256), (unsigned)m), dim3(256), 0, s,
+                           qcodes, (const T *)qbeta, (const T *)qv, in.p, dpairs.as<int>(), ws.codes.as<uint8_t>(),
+                           beta, V, W, c, (T)in.mp.rho, s64.beta, s64.V, s64.W, (const double *)s64.c, in.mp.rho,
+                           fp64 ? 0 : 1, ldp, ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(),
+                           ws.start.as<int>(), (const int *)ws.sweep_no.ptr);
+        hipLaunchKernelGGL(k_list_append, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, ws.list.as<int>(),
+                           active, (const int *)dpairs.ptr, m);
+        HIPCHK(hipGetLastError());
+        // the pairs buffer is reused by the next refill only after a block has synchronised
+        active += m;
+    };
+    freed.clear();
+    for (int k = 0; k < (int)std::min<int64_t>(K, N); ++k) freed.push_back(k);
+    refill(freed);
+    const int m = std::max(1, o.check_every);
+    const int kind = fp64 ? SK_F64 : SK_ANCH;
+    int cnt[3];
+    while (active > 0) {
+        check_cancel(ctx);
+        run_block(ctx, kind, Kp, m, o.tol_node, o.tol_node, active, false, cnt, o.max_iter);
+        active = cnt[0];
+        const int nd = cnt[2];
+        if (nd <= 0) continue;
+        dl.assign((size_t)nd, 0);
+        HIPCHK(hipMemcpyAsync(dl.data(), ws.dlist.ptr, sizeof(int) * nd, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        pairs.assign((size_t)2 * nd, 0);
+        for (int e = 0; e < nd; ++e) {
+            pairs[(size_t)2 * e] = dl[(size_t)e];
+            pairs[(size_t)2 * e + 1] = slot_q[(size_t)dl[(size_t)e]];
+            slot_q[(size_t)dl[(size_t)e]] = -1;
+        }
+        HIPCHK(hipMemcpyAsync(dpairs.ptr, pairs.data(), sizeof(int) * 2 * nd, hipMemcpyHostToDevice, s));
+        const dim3 gs((unsigned)((in.p + 255) / 256), (unsigned)nd);
+        if (fp64)
+            hipLaunchKernelGGL((k_queue_store<double, double>), gs, dim3(256), 0, s, (const int *)dpairs.ptr,
+                               (const double *)s64.beta, (const double *)s64.V, ldp, in.p, (const double *)ws.lb.ptr,
+                               (const double *)ws.primal.ptr, (const int *)ws.iters.ptr, (const int *)ws.status.ptr,
+                               (double *)qbeta, (double *)qv, qlb, qprimal, qiters, qstatus);
+        else
+            hipLaunchKernelGGL((k_queue_store<double, float>), gs, dim3(256), 0, s, (const int *)dpairs.ptr,
+                               (const double *)s64.beta, (const double *)s64.V, ldp, in.p, (const double *)ws.lb.ptr,
+                               (const double *)ws.primal.ptr, (const int *)ws.iters.ptr, (const int *)ws.status.ptr,
+                               (float *)qbeta, (float *)qv, qlb, qprimal, qiters, qstatus);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s));   // the pairs buffer is rewritten by the refill below
+        freed.assign(dl.begin(), dl.end());
+        refill(freed);
+    }
+}
+
 template <class T>
 void sweeps_t(l0l2_ctx *ctx, const Sweep<T> &sw, int K, int sweeps) {
     const int64_t Kp = round_up(K, kPadNodes);
@@ -3434,6 +3616,14 @@ void sweeps_t(l0l2_ctx *ctx, const Sweep<T> &sw, int K, int sweeps) {
 }
 
 }  // namespace
+
+void run_queue(l0l2_ctx *ctx, int N, const uint8_t *codes, void *beta, void *v, int K, const l0l2_admm_opts &o,
+               double *lb, double *primal, int32_t *iters, int32_t *status) {
+    Workspace &ws = ctx->ws;
+    ws.stat_blocks = ws.stat_sparse = ws.stat_node_blocks = 0;
+    if (ctx->inst.prec == L0L2_FP64) solve_queue_t<double>(ctx, N, codes, beta, v, K, o, lb, primal, iters, status);
+    else solve_queue_t<float>(ctx, N, codes, beta, v, K, o, lb, primal, iters, status);
+}
 
 void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     Instance &in = ctx->inst;
@@ -3464,11 +3654,13 @@ void ensure_workspace(l0l2_ctx *ctx, int64_t K) {
     ws.status.ensure(4 * Kp);
     ws.lb.ensure(8 * Kp);
     ws.primal.ensure(8 * Kp);
-    ws.counter.ensure(2 * sizeof(int));
+    ws.counter.ensure(3 * sizeof(int));
+    ws.start.ensure(4 * Kp);
+    ws.dlist.ensure(4 * Kp);
     ws.sweep_no.ensure(sizeof(int));
     drop_graphs(ctx);
     ++ws.gen;
-    if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 2 * sizeof(int), hipHostMallocDefault));
+    if (!ws.host_counter) HIPCHK(hipHostMalloc((void **)&ws.host_counter, 3 * sizeof(int), hipHostMallocDefault));
     if (in.prec != L0L2_FP64) {
         ws.W2.ensure(4 * Kp * ldp);
         HIPCHK(hipMemsetAsync(ws.W2.ptr, 0, 4 * Kp * ldp, ctx->stream));
@@ -3558,6 +3750,7 @@ void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool) {
 }
 
 void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
+    ctx->ws.stat_blocks = ctx->ws.stat_sparse = ctx->ws.stat_node_blocks = 0;
     if (ctx->inst.prec == L0L2_FP64) solve_plain<double>(ctx, sweep64(ctx), K, o);
     else solve_mixed(ctx, K, o);
 }
@@ -3618,7 +3811,7 @@ void run_dual_bound(l0l2_ctx *ctx, int K, const void *) {
     Workspace &ws = ctx->ws;
     hipLaunchKernelGGL(k_set_active, dim3((unsigned)((Kp + 255) / 256)), dim3(256), 0, ctx->stream,
                        ws.active.as<int>(), ws.status.as<int>(), ws.iters.as<int>(), ws.list.as<int>(),
-                       ws.clist.as<int>(), (int64_t)K, Kp, ws.sweep_no.as<int>());
+                       ws.clist.as<int>(), (int64_t)K, Kp, ws.sweep_no.as<int>(), ws.start.as<int>());
     if (ctx->inst.prec == L0L2_FP64)
         check_once<double>(ctx, ws.B.as<double>(), ws.B.as<double>(), Kp, 0.0, 0.0, 1);
     else

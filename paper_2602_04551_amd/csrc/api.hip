@@ -1,5 +1,6 @@
 // extern "C" entry points of libl0l2 (include/l0l2.h): argument validation,
 // error capture and dispatch.  No exception crosses this boundary.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -255,6 +256,30 @@ int l0l2_solve_node_batch(l0l2_ctx *ctx, int K, const uint8_t *codes, void *beta
         HIPCHK(hipMemcpyAsync(iters, ws.iters.ptr, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
         HIPCHK(hipMemcpyAsync(status, ws.status.ptr, sizeof(int32_t) * K, hipMemcpyDeviceToDevice, s));
     });
+}
+
+int l0l2_solve_node_queue(l0l2_ctx *ctx, int N, const uint8_t *codes, void *beta, void *v, int K,
+                          const l0l2_admm_opts *opts, double *lb, double *primal, int32_t *iters, int32_t *status) {
+    return guarded(ctx, [&] {
+        need_data(ctx);
+        if (N < 0 || K < 1) l0l2::fail(L0L2_E_INVALID, "need N >= 0 and K >= 1");
+        if (!opts) l0l2::fail(L0L2_E_INVALID, "null options");
+        if (opts->max_iter < 1 || opts->check_every < 1 || !(opts->tol_node >= 0))
+            l0l2::fail(L0L2_E_INVALID, "need max_iter >= 1, check_every >= 1, tol_node >= 0");
+        if (N == 0) return;
+        if (!codes || !beta || !v || !lb || !primal || !iters || !status) l0l2::fail(L0L2_E_INVALID, "null buffer");
+        const int Ks = (int)std::min<int64_t>(K, N);
+        l0l2::ensure_workspace(ctx, Ks);
+        l0l2::run_queue(ctx, N, codes, beta, v, Ks, *opts, lb, primal, iters, status);
+    });
+}
+
+int l0l2_batch_stats(l0l2_ctx *ctx, int64_t *blocks, int64_t *sparse_blocks, int64_t *node_blocks) {
+    if (!ctx) return L0L2_E_INVALID;
+    if (blocks) *blocks = ctx->ws.stat_blocks;
+    if (sparse_blocks) *sparse_blocks = ctx->ws.stat_sparse;
+    if (node_blocks) *node_blocks = ctx->ws.stat_node_blocks;
+    return L0L2_OK;
 }
 
 int l0l2_round_branch(l0l2_ctx *ctx, int K, const uint8_t *codes, const void *beta, uint8_t *support,

@@ -163,7 +163,10 @@ struct Workspace {
     DevBuf nlist, ncount;          // the active list being rebuilt by the check
     DevBuf active, iters, status;  // Kp int32
     DevBuf lb, primal;             // Kp doubles
-    DevBuf counter;                // int32 x 2: active nodes, active nodes above the switch tolerance
+    DevBuf counter;                // int32 x 3: active nodes, active nodes above the switch tolerance, retired
+    DevBuf start;                  // Kp int32: sweep number at which the slot's node started
+    DevBuf dlist;                  // Kp int32: slots retired in the last block (counter[2] of them)
+    int64_t stat_blocks = 0, stat_sparse = 0, stat_node_blocks = 0;   // blocks of the last solve; with < 1/8 live
     DevBuf sweep_no;               // int32 sweep counter of the batch
     int64_t gen = 0;               // bumped whenever the buffers above move
     DevBuf fista;                  // FP64 residual scratch for the incumbent kernels
@@ -197,6 +200,7 @@ struct GraphKey {
     int force;
     double tol, switch_tol;
     int64_t gen;
+    int budget;
     bool operator<(const GraphKey &o) const {
         if (kind != o.kind) return kind < o.kind;
         if (Kp != o.Kp) return Kp < o.Kp;
@@ -205,7 +209,8 @@ struct GraphKey {
         if (force != o.force) return force < o.force;
         if (tol != o.tol) return tol < o.tol;
         if (switch_tol != o.switch_tol) return switch_tol < o.switch_tol;
-        return gen < o.gen;
+        if (gen != o.gen) return gen < o.gen;
+        return budget < o.budget;
     }
 };
 
@@ -259,6 +264,11 @@ void run_sweeps(l0l2_ctx *ctx, int K, int sweeps, bool store_b_last);
 void run_dual_bound(l0l2_ctx *ctx, int K, const void *b_internal_or_null);
 // Solve the K nodes loaded in the workspace; results stay in ws.lb/primal/iters/status.
 void run_solve(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o);
+// N queued nodes (device codes N x p, warm starts / results N x p in the state
+// type: FP64, or FP32 in the reduced modes) through K slots with refill; results
+// to the device arrays lb, primal, iters, status (N each).
+void run_queue(l0l2_ctx *ctx, int N, const uint8_t *codes, void *beta, void *v, int K, const l0l2_admm_opts &o,
+               double *lb, double *primal, int32_t *iters, int32_t *status);
 // Node-batch size by measurement: candidates 32, 64, ... up to k_max; returns
 // the chosen K and fills rates[i] (node-sweeps per second of candidate 32 * 2^i).
 int tune_batch_size(l0l2_ctx *ctx, int k_max, double frac, std::vector<double> &rates);
