@@ -440,6 +440,9 @@ def node_batch_run(inst, prec, K, root, profile=True):
     run = {"value": round(K / dt, 2), "seconds": round(dt, 4), "iters_mean": round(float(it.mean()), 2),
            "iters_max": int(it.max()), "converged": int((r["status"] == 0).sum().item()),
            "set_data_s": round(sd, 3), "b_update": b_update_info(ctx)["form"]}
+    blocks, sparse, node_blocks = ctx.batch_stats()
+    run["blocks"] = {"total": blocks, "under_1_8_live": sparse,
+                     "occupancy": round(node_blocks / max(1, blocks * ((K + 31) // 32 * 32)), 4)}
     if profile:
         ctx.profile_enable(True)
         ctx.solve_node_batch(codes, b0, v0, tol_node=1e-6, max_iter=2000)
@@ -450,6 +453,37 @@ def node_batch_run(inst, prec, K, root, profile=True):
     ctx.close()
     print(json.dumps({f"{prec}_K{K}": run["value"]}), file=sys.stderr, flush=True)
     return run
+
+
+def node_queue_run(inst, prec, N, K, root):
+    """N nodes of the workload (free sets U{50..p}, |F1| U{0..20}, seed N) through K
+    slots refilled as nodes retire (l0l2_solve_node_queue), from the shared FP64
+    root: one untimed run (tiles, graphs, form), one timed."""
+    import torch
+    from paper_2602_04551_amd import datagen
+    from paper_2602_04551_amd.binding import Context
+    n, p = inst.n, inst.p
+    ctx = Context(0)
+    ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
+    codes = torch.from_numpy(datagen.node_batch_codes(p, N, seed=N)).to(ctx.torch_device)
+    b0 = torch.from_numpy(root[0]).to(ctx.torch_device, ctx.state_dtype).expand(N, p).contiguous()
+    v0 = torch.from_numpy(root[1]).to(ctx.torch_device, ctx.state_dtype).expand(N, p).contiguous()
+    ctx.solve_node_queue(codes[:K], b0[:K], v0[:K], K=K, tol_node=1e-6, max_iter=2000)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.solve_node_queue(codes, b0, v0, K=K, tol_node=1e-6, max_iter=2000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    blocks, sparse, node_blocks = ctx.batch_stats()
+    it = r["iters"].cpu().numpy()
+    ctx.close()
+    out = {"value": round(N / dt, 2), "seconds": round(dt, 4), "queue": N, "slots": K,
+           "iters_mean": round(float(it.mean()), 2), "iters_max": int(it.max()),
+           "converged": int((r["status"] == 0).sum().item()),
+           "blocks": {"total": blocks, "under_1_8_live": sparse,
+                      "occupancy": round(node_blocks / max(1, blocks * ((K + 31) // 32 * 32)), 4)}}
+    print(json.dumps({f"{prec}_queue{N}_K{K}": out["value"]}), file=sys.stderr, flush=True)
+    return out
 
 
 def node_batch_runs(inst, Ks, precs, workload, label):
@@ -692,10 +726,15 @@ def main():
         inst5 = datagen.config_instance("C5", seed=0)
         root5 = fp64_root(inst5)
         runs = {prec: node_batch_run(inst5, prec, 1024, root5) for prec in ("fp8", "bf16", "fp32", "fp64")}
+        queue = {prec: node_queue_run(inst5, prec, 4096, 1024, root5) for prec in ("fp8", "fp64")}
         out["highdim_n1000_p50000"] = {
             "workload": "n=1000 p=50000 constant correlation 0.2 k=25 SNR=3 lambda0=0.002 lambda2=0.005, node "
                         "batches of 1024 (free sets U{50..p}, |F1| U{0..20}) from the FP64 root",
-            "runs": runs, "fp8_vs_fp64": round(runs["fp8"]["value"] / runs["fp64"]["value"], 3)}
+            "runs": runs, "fp8_vs_fp64": round(runs["fp8"]["value"] / runs["fp64"]["value"], 3),
+            "queue": {"what": "4096 queued nodes of the same workload through 1024 slots refilled as nodes "
+                              "retire (continuous batching), against the fixed batch of 1024 above",
+                      "runs": queue,
+                      "fp8_queue_vs_batch": round(queue["fp8"]["value"] / runs["fp8"]["value"], 3)}}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, K, root, args.cpu_seconds, args.cpu_sample)
     print(json.dumps(out), flush=True)
