@@ -170,7 +170,11 @@ typedef struct {
  * the support are read).  beta_out: device K x p doubles, receives the refined
  * coefficients, zero off the support (may alias beta_start in FP64 mode).
  * obj: device K doubles, F(S, beta) = 1/2||y - X_S beta_S||^2 + lambda2
- * ||beta_S||^2 + lambda0 |S|.  iters: device K int32 (may be NULL). */
+ * ||beta_S||^2 + lambda0 |S|.  iters: device K int32 (may be NULL).
+ * Supports of up to 1024 coordinates are refined with their per-coordinate
+ * state in LDS; wider ones (p > 1024 only) by a second kernel whose state
+ * lives in a workspace of at most 64 slots of 44 p bytes (at most 256 MiB),
+ * the widest supports taking turns in the slots. */
 int l0l2_refine_incumbent(l0l2_ctx *ctx, int K, const uint8_t *support, const void *beta_start,
                           double *beta_out, const l0l2_fista_opts *opts, double *obj, int32_t *iters);
 
@@ -183,6 +187,8 @@ int l0l2_refine_incumbent(l0l2_ctx *ctx, int K, const uint8_t *support, const vo
  *    its own copy until the process ends); K x (n rounded up to a multiple of
  *    128) x 8 bytes must fit in it, else L0L2_E_INVALID (n = 1000: K <= 4096;
  *    n = 5000: K <= 819);
+ *  - supports wider than 1024 coordinates are not refined: their obj is NaN
+ *    and their iters -1 (their beta_out row keeps the converted start);
  *  - no device memory is allocated or freed and no library routine that
  *    allocates is called; the call is not timed by l0l2_profile_*;
  *  - it returns without waiting: the outputs are ready in stream order on the

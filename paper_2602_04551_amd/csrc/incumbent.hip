@@ -329,11 +329,83 @@ __device__ void gram_build(FistaShared &sm, const double *__restrict__ X, int64_
     }
 }
 
+// The streaming refinement of one support of k coordinates (k > kGramMax):
+// X_S is streamed once per evaluation with all four waves; per-coordinate
+// arrays (cur, prev, ext, nxt, grad: k entries each, the support's indices in
+// idx) live in LDS for k <= kSMax and in global scratch beyond.  Starts at
+// the node iterate brow on S clipped to the box; returns the iterations done,
+// the result in cur.
+__device__ int fista_stream(const double *__restrict__ X, const double *__restrict__ y,
+                            const double *__restrict__ colnrm, const double *__restrict__ brow, const int *idx,
+                            int k, double *cur, double *prev, double *ext, double *nxt, double *grad,
+                            double *__restrict__ res, double *sh, const FistaArgs &fa) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double fro = 0.0;
+    for (int a = tid; a < k; a += 256) {
+        double b0 = brow[idx[a]];
+        b0 = b0 > fa.M ? fa.M : (b0 < -fa.M ? -fa.M : b0);
+        cur[a] = b0;
+        prev[a] = b0;
+        double cn = colnrm[idx[a]];
+        fro += cn * cn;
+    }
+    fro = bsum(fro, sh);
+    double alpha = 4.0 / (fro + 2.0 * fa.l2);
+    double Ucur = U_S(X, fa.ldx, y, idx, k, cur, res, false, sh, fa);
+    int it = 0;
+    while (it < fa.max_iter) {
+        double mom = (double)it / ((double)it + 3.0);
+        for (int a = tid; a < k; a += 256) ext[a] = cur[a] + mom * (cur[a] - prev[a]);
+        __syncthreads();
+        double Uext = U_S(X, fa.ldx, y, idx, k, ext, res, true, sh, fa);
+        __syncthreads();
+        for (int a = w; a < k; a += 4) {
+            const double *col = X + (int64_t)idx[a] * fa.ldx;
+            double s = 0.0;
+            for (int64_t i = lane; i < fa.n; i += 64) s += col[i] * res[i];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if (lane == 0) grad[a] = s + 2.0 * fa.l2 * ext[a];
+        }
+        __syncthreads();
+        double Unxt = 0.0;
+        for (int bt = 0; bt <= 60; ++bt) {
+            double gd = 0.0, dd = 0.0;
+            for (int a = tid; a < k; a += 256) {
+                double v = ext[a] - alpha * grad[a];
+                v = v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v);
+                nxt[a] = v;
+                double d = v - ext[a];
+                gd += grad[a] * d;
+                dd += d * d;
+            }
+            gd = bsum(gd, sh);
+            dd = bsum(dd, sh);
+            Unxt = U_S(X, fa.ldx, y, idx, k, nxt, res, false, sh, fa);
+            if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
+            alpha *= 0.5;
+        }
+        ++it;
+        double dm = 0.0;
+        for (int a = tid; a < k; a += 256) dm = fmax(dm, fabs(nxt[a] - cur[a]));
+        dm = bmax(dm, sh);
+        double dU = fabs(Unxt - Ucur);
+        for (int a = tid; a < k; a += 256) {
+            prev[a] = cur[a];
+            cur[a] = nxt[a];
+        }
+        __syncthreads();
+        Ucur = Unxt;
+        if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
+    }
+    return it;
+}
+
 __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, const double *__restrict__ y,
                                                const double *__restrict__ colnrm, const double *__restrict__ c,
                                                double yy, const uint8_t *__restrict__ sup, int64_t lds,
                                                double *__restrict__ beta, int64_t ldb, double *__restrict__ resbuf,
-                                               double *__restrict__ obj, int32_t *__restrict__ iters, FistaArgs fa) {
+                                               double *__restrict__ obj, int32_t *__restrict__ iters,
+                                               int *__restrict__ wlist, int *__restrict__ wcount, FistaArgs fa) {
     __shared__ FistaShared sm;
     const int64_t node = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -356,9 +428,11 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
     __syncthreads();
     const int *idx = sm.idx;
     if (k > kSMax) {
+        // left to k_fista_wide when a wide list is given, else marked unrefined
         if (tid == 0) {
             obj[node] = NAN;
             if (iters) iters[node] = -1;
+            if (wlist) wlist[atomicAdd(wcount, 1)] = (int)node;
         }
         return;
     }
@@ -426,63 +500,8 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         }
         __syncthreads();
     } else {
-        double fro = 0.0;
-        for (int a = tid; a < k; a += 256) {
-            double b0 = beta[node * ldb + idx[a]];
-            b0 = b0 > fa.M ? fa.M : (b0 < -fa.M ? -fa.M : b0);
-            sm.cur[a] = b0;
-            sm.prev[a] = b0;
-            double cn = colnrm[idx[a]];
-            fro += cn * cn;
-        }
-        fro = bsum(fro, sm.sh);
-        double alpha = 4.0 / (fro + 2.0 * fa.l2);
-        double Ucur = U_S(X, fa.ldx, y, idx, k, sm.cur, res, false, sm.sh, fa);
-        int it = 0;
-        while (it < fa.max_iter) {
-            double mom = (double)it / ((double)it + 3.0);
-            for (int a = tid; a < k; a += 256) sm.ext[a] = sm.cur[a] + mom * (sm.cur[a] - sm.prev[a]);
-            __syncthreads();
-            double Uext = U_S(X, fa.ldx, y, idx, k, sm.ext, res, true, sm.sh, fa);
-            __syncthreads();
-            for (int a = w; a < k; a += 4) {
-                const double *col = X + (int64_t)idx[a] * fa.ldx;
-                double s = 0.0;
-                for (int64_t i = lane; i < fa.n; i += 64) s += col[i] * res[i];
-                for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-                if (lane == 0) sm.grad[a] = s + 2.0 * fa.l2 * sm.ext[a];
-            }
-            __syncthreads();
-            double Unxt = 0.0;
-            for (int bt = 0; bt <= 60; ++bt) {
-                double gd = 0.0, dd = 0.0;
-                for (int a = tid; a < k; a += 256) {
-                    double v = sm.ext[a] - alpha * sm.grad[a];
-                    v = v > fa.M ? fa.M : (v < -fa.M ? -fa.M : v);
-                    sm.nxt[a] = v;
-                    double d = v - sm.ext[a];
-                    gd += sm.grad[a] * d;
-                    dd += d * d;
-                }
-                gd = bsum(gd, sm.sh);
-                dd = bsum(dd, sm.sh);
-                Unxt = U_S(X, fa.ldx, y, idx, k, sm.nxt, res, false, sm.sh, fa);
-                if (Unxt <= Uext + gd + dd / (2.0 * alpha) || bt == 60) break;
-                alpha *= 0.5;
-            }
-            ++it;
-            double dm = 0.0;
-            for (int a = tid; a < k; a += 256) dm = fmax(dm, fabs(sm.nxt[a] - sm.cur[a]));
-            dm = bmax(dm, sm.sh);
-            double dU = fabs(Unxt - Ucur);
-            for (int a = tid; a < k; a += 256) {
-                sm.prev[a] = sm.cur[a];
-                sm.cur[a] = sm.nxt[a];
-            }
-            __syncthreads();
-            Ucur = Unxt;
-            if (dU <= fa.tol * (Ucur > 1.0 ? Ucur : 1.0) || dm <= 1e-10) break;
-        }
+        const int it = fista_stream(X, y, colnrm, beta + node * ldb, idx, k, sm.cur, sm.prev, sm.ext, sm.nxt, sm.grad,
+                                    res, sm.sh, fa);
         if (tid == 0) sm.it = it;
         __syncthreads();
     }
@@ -495,6 +514,58 @@ __global__ __launch_bounds__(256) void k_fista(const double *__restrict__ X, con
         if (iters) iters[node] = sm.it;
     }
 }
+
+// Supports wider than kSMax: the nodes k_fista listed, one workgroup per node
+// in grid-stride order over the list, the support's indices and the five
+// per-coordinate arrays in a global slot of stride doubles per workgroup
+// (indices first, as ints).  Same iteration as k_fista's streaming form.
+__global__ __launch_bounds__(256) void k_fista_wide(const double *__restrict__ X, const double *__restrict__ y,
+                                                    const double *__restrict__ colnrm, const uint8_t *__restrict__ sup,
+                                                    int64_t lds, double *__restrict__ beta, int64_t ldb,
+                                                    double *__restrict__ resbuf, double *__restrict__ obj,
+                                                    int32_t *__restrict__ iters, const int *__restrict__ wlist,
+                                                    const int *__restrict__ wcount, double *__restrict__ wscr,
+                                                    int64_t stride, FistaArgs fa) {
+    __shared__ double sh[4];
+    __shared__ int shw[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double *slot = wscr + (int64_t)blockIdx.x * stride;
+    int *idx = reinterpret_cast<int *>(slot);
+    const int64_t pi = (fa.p + 1) / 2;   // doubles taken by the indices
+    double *cur = slot + pi, *prev = cur + fa.p, *ext = prev + fa.p, *nxt = ext + fa.p, *grad = nxt + fa.p;
+    const int count = *wcount;
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        const int64_t node = wlist[e];
+        double *res = resbuf + node * fa.np;
+        int k = 0;
+        for (int64_t base = 0; base < fa.p; base += 256) {
+            const int64_t j = base + tid;
+            const int f = (j < fa.p) ? sup[node * lds + j] != 0 : 0;
+            const unsigned long long bal = __ballot(f);
+            const int before = __popcll(bal & ((1ull << lane) - 1ull));
+            __syncthreads();
+            if (lane == 0) shw[w] = __popcll(bal);
+            __syncthreads();
+            int off = k;
+            for (int ww = 0; ww < w; ++ww) off += shw[ww];
+            if (f) idx[off + before] = (int)j;
+            k += shw[0] + shw[1] + shw[2] + shw[3];
+        }
+        __syncthreads();
+        const int it = fista_stream(X, y, colnrm, beta + node * ldb, idx, k, cur, prev, ext, nxt, grad, res, sh, fa);
+        const double f = U_S(X, fa.ldx, y, idx, k, cur, res, false, sh, fa) + fa.l0 * (double)k;
+        for (int64_t j = tid; j < fa.p; j += 256) beta[node * ldb + j] = 0.0;
+        __syncthreads();
+        for (int a = tid; a < k; a += 256) beta[node * ldb + idx[a]] = cur[a];
+        if (tid == 0) {
+            obj[node] = f;
+            if (iters) iters[node] = it;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_int(int *v) { *v = 0; }
 
 template <class T>
 __global__ void k_state_f64(const T *__restrict__ src, int64_t lds, double *__restrict__ dst, int64_t ldd, int64_t K,
@@ -636,10 +707,29 @@ void run_fista(l0l2_ctx *ctx, int K, const uint8_t *support, int64_t ld_support,
         resbuf = ctx->ws.fista.as<double>();
     }
     FistaArgs fa{in.mp.l0, in.mp.l2, in.mp.M, o.tol, o.max_iter, in.n, in.np, in.p, in.ldx};
+    // supports wider than kSMax (possible only when p > kSMax) go to the wide
+    // kernel, whose slots (at most 64, at most 256 MiB) the workspace holds;
+    // the allocation-free form leaves them unrefined
+    const bool wide = own && in.p > kSMax;
+    int *wlist = nullptr, *wcount = nullptr;
+    int slots = 0;
+    const int64_t stride = 5 * in.p + (in.p + 1) / 2;
+    if (wide) {
+        slots = (int)std::min<int64_t>({(int64_t)K, 64, std::max<int64_t>(1, (256ll << 20) / (8 * stride))});
+        ctx->ws.fista_wide.ensure(sizeof(double) * (size_t)slots * stride);
+        ctx->ws.fista_list.ensure(sizeof(int) * ((size_t)K + 1));
+        wcount = ctx->ws.fista_list.as<int>();
+        wlist = wcount + 1;
+    }
     if (own) prof_begin(ctx, PROF_FISTA);
+    if (wide) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, ctx->stream, wcount);
     hipLaunchKernelGGL(k_fista, dim3((unsigned)K), dim3(256), 0, ctx->stream, in.X64.as<double>(), in.y64.as<double>(),
                        in.colnrm.as<double>(), in.c64.as<double>(), in.yy, support, ld_support, beta, ld_beta,
-                       resbuf, obj, iters, fa);
+                       resbuf, obj, iters, wlist, wcount, fa);
+    if (wide)
+        hipLaunchKernelGGL(k_fista_wide, dim3((unsigned)slots), dim3(256), 0, ctx->stream, in.X64.as<double>(),
+                           in.y64.as<double>(), in.colnrm.as<double>(), support, ld_support, beta, ld_beta, resbuf, obj,
+                           iters, (const int *)wlist, (const int *)wcount, ctx->ws.fista_wide.as<double>(), stride, fa);
     if (own) prof_end(ctx, PROF_FISTA);
     HIPCHK(hipGetLastError());
 }

@@ -170,6 +170,7 @@ struct Workspace {
     DevBuf sweep_no;               // int32 sweep counter of the batch
     int64_t gen = 0;               // bumped whenever the buffers above move
     DevBuf fista;                  // FP64 residual scratch for the incumbent kernels
+    DevBuf fista_wide, fista_list; // slots and node list of supports wider than one workgroup's LDS
     DevBuf nfree;                  // int32 per node: free-coordinate counts of l0l2_round_branch
     DevBuf root_beta, root_v;      // the last branch and bound's root iterates (ldp state elements each)
     bool have_root = false;

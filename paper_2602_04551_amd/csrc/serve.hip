@@ -53,6 +53,11 @@ size_t footprint_bytes(int64_t n, int64_t p, int prec, int K) {
         inst += (prec == L0L2_BF16 ? 16.0 : 12.0) * pp * pp;
         ws += 4.0 * Kp * pp;
     }
+    // slots of the refinement of supports wider than 1024 coordinates
+    if (p > 1024) {
+        const double stride = 8.0 * (5.0 * (double)p + (double)((p + 1) / 2));
+        ws += std::min({Kp, 64.0, std::max(1.0, std::floor(268435456.0 / stride))}) * stride + 4.0 * Kp;
+    }
     // the terms above are the large buffers; a tenth more and 16 MiB cover the
     // small ones (gap-check partials, lists, refinement staging, captured graphs)
     return (size_t)(1.1 * (inst + std::max(transient, ws + bnb)) + 16.0 * 1048576.0);
