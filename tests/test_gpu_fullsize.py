@@ -122,8 +122,9 @@ def test_full_size_batches_match_the_oracle_on_sampled_nodes(torch_cuda, cfg, K,
     """The batching (n = p = 5000, 4096 nodes) and high-dimensional (n = 1000,
     p = 50 000, 1024 nodes) batches of the benchmark, from the FP64 root: on the
     eight nodes the oracle solved (committed values), converged bounds agree
-    within 1e-10 (FP64, at equal sweep counts) or 1e-5 (reduced precisions) of
-    the primal value; a node the oracle left at the sweep budget only has to
+    within 1e-10, or the rounding drift t (n + p) u after t sweeps where that is
+    larger (FP64, at equal sweep counts), or 1e-5 (reduced precisions) of the
+    primal value; a node the oracle left at the sweep budget only has to
     bound from below the oracle's primal value there.  Every node of the batch:
     its bound is below its primal value and a converged node meets the tolerance;
     the bounds of nodes converged in both agree with the FP64 path within 1e-5."""
@@ -158,7 +159,12 @@ def test_full_size_batches_match_the_oracle_on_sampled_nodes(torch_cuda, cfg, K,
             if g["status"] != 0 or st[k] != 0:
                 continue
             if precision == "fp64" and it[k] == g["iters"]:
-                assert abs(lb[k] - g["lb"]) <= 1e-10 * abs(g["primal"]), line
+                # ADMM's fixed-point map is non-expansive, so two FP64 runs from
+                # one start drift apart by at most the sum of their per-sweep
+                # rounding errors: t sweeps of contractions of lengths n and p,
+                # each at worst (n + p) u relative
+                drift = it[k] * (inst.n + inst.p) * 2.0 ** -53
+                assert abs(lb[k] - g["lb"]) <= max(1e-10, drift) * abs(g["primal"]), line
             else:
                 assert abs(lb[k] - g["lb"]) <= 1e-5 * abs(g["primal"]), line
         if precision == "fp64":
