@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--K", type=int, default=4096, help="nodes per batch of the headline workload")
     ap.add_argument("--no-ttco", action="store_true", help="skip the n = p = 1000 branch-and-bound runs")
+    ap.add_argument("--heuristic-study", action="store_true",
+                    help="branch and bound with and without the matching-pursuit root incumbent")
+    ap.add_argument("--heur-seconds", type=float, default=20.0,
+                    help="time limit of the n = 1000, p = 50 000 runs of --heuristic-study")
     ap.add_argument("--no-highdim", action="store_true", help="skip the n = 1000, p = 50000 node batches")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -589,6 +593,40 @@ def node_parallel_main(args):
     print(json.dumps(out), flush=True)
 
 
+def heuristic_main(args):
+    """Branch and bound with and without the matching-pursuit incumbent (Sec. 3.5,
+    App. A.2) seeded before the root: n = p = 1000 to certification, and
+    n = 1000, p = 50 000 under a time limit (gap reached, incumbent value,
+    nodes), in the mixed BF16 and the FP64 paths."""
+    import torch
+    from paper_2602_04551_amd import datagen
+    from paper_2602_04551_amd.binding import Context
+    out = {"metric": "branch and bound with / without the matching-pursuit root incumbent", "runs": {}}
+    for cfg, K, limit in (("C2", 256, 0.0), ("C5", 256, args.heur_seconds)):
+        inst = datagen.config_instance(cfg, seed=0)
+        for prec in ("bf16", "fp64"):
+            ctx = Context(0)
+            ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
+            if cfg == "C2":    # settle tiles and graphs
+                ctx.bnb_solve(K=K, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000)
+            row = {}
+            for heur in (False, True):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = ctx.bnb_solve(K=K, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000,
+                                  time_limit_s=limit, root_heuristic=heur)
+                torch.cuda.synchronize()
+                gap = (r["ub"] - r["lb"]) / abs(r["ub"]) if np.isfinite(r["ub"]) and r["ub"] != 0 else None
+                row["heuristic" if heur else "plain"] = {
+                    "seconds": round(time.perf_counter() - t0, 3), "status": r["status"], "ub": r["ub"],
+                    "lb": r["lb"], "gap": gap, "nodes": r["nodes_solved"], "support_size": len(r["support"])}
+                print(json.dumps({"cfg": cfg, "prec": prec, "heuristic": heur,
+                                  **row["heuristic" if heur else "plain"]}), file=sys.stderr, flush=True)
+            ctx.close()
+            out["runs"][f"{cfg}_{prec}"] = {"n": inst.n, "p": inst.p, "K": K, "time_limit_s": limit, **row}
+    print(json.dumps(out), flush=True)
+
+
 def serve_main(args):
     """A Poisson stream of independent instances (n ~ U{500..2000}, p ~ U{1000..4000}, Toeplitz
     rho ~ U[0, 0.7], k ~ U{5..12}, SNR ~ U[2, 10], lambda0 = 0.005, lambda2 = 0.01) through the
@@ -645,6 +683,8 @@ def main():
         return serve_main(args)
     if args.node_parallel:
         return node_parallel_main(args)
+    if args.heuristic_study:
+        return heuristic_main(args)
     import torch
     from paper_2602_04551_amd import datagen
 
@@ -715,6 +755,17 @@ def main():
             tt[prec] = {"seconds": round(time.perf_counter() - t0, 4), "set_data_s": round(sd, 4),
                         "nodes": r["nodes_solved"], "batches": r["batches"], "certified": r["certified"],
                         "lb": r["lb"], "status": r["status"], "support": [int(s) for s in r["support"]]}
+            if prec in ("bf16", "fp64"):
+                # the same solve with the matching-pursuit incumbent seeded before the root
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rh = ctx.bnb_solve(K=256, policy="best", tol_node=1e-6, max_iter=2000, max_iter_root=10000,
+                                   root_heuristic=True)
+                torch.cuda.synchronize()
+                tt[prec]["with_heuristic"] = {"seconds": round(time.perf_counter() - t0, 4),
+                                              "nodes": rh["nodes_solved"], "certified": rh["certified"],
+                                              "status": rh["status"],
+                                              "same_support": [int(s) for s in rh["support"]] == tt[prec]["support"]}
             ctx.close()
         out["ttco_n1000"] = {"workload": "n=p=1000 Toeplitz rho=0.5 k=10 SNR=5 lambda0=0.005 lambda2=0.01, "
                                          "best-first branch and bound with batches of 256 to certification "

@@ -368,6 +368,26 @@ int l0l2_server_cancel(l0l2_server *srv, int64_t req_id);
  * beside others. */
 int l0l2_server_destroy(l0l2_server *srv);
 
+/* Batching across instances (the batched node solves of Sec. 3.2 pooled over
+ * the admitted instances).  on = 1 (the default): instances admitted
+ * after the call hand every block of ADMM sweeps to the server's executor,
+ * which runs all blocks waiting when it becomes free together on one stream:
+ * the sweep contractions of FP32-mode and FP64-mode instances whose batches
+ * use the 32 x 32 register tile (node batches below 128, or grids too small
+ * for the 128 x 128 tile) go out as one grouped launch per contraction kind
+ * covering up to 8 instances, the other sweeps launch by launch.  on = 0:
+ * each instance replays its own captured blocks on its own stream.  Results
+ * are identical either way (a grouped tile computes what the instance's own
+ * launch would).  Errors: L0L2_E_INVALID for a null server or on outside {0, 1}. */
+int l0l2_server_set_batching(l0l2_server *srv, int on);
+
+/* Executor counters since the server was created (any pointer may be NULL):
+ * rounds run, blocks run in them, grouped contraction launches, and the
+ * instance contractions those launches carried (members / launches = mean
+ * instances per shared launch). */
+int l0l2_server_batching_stats(l0l2_server *srv, int64_t *rounds, int64_t *blocks, int64_t *launches,
+                               int64_t *members);
+
 /* Tile shapes of the two sweep contractions (output rows x nodes / waves):
  * register tiles whose waves split the contraction range, 0 = 32x32/4,
  * 1 = 32x32/8, 2 = 32x32/16 (8 in FP64), 3 = 16x32/8, 4 = 32x16/8, 5 = 16x16/4,

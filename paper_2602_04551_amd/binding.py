@@ -85,6 +85,8 @@ SIGNATURES = {
     "l0l2_server_last_error": (C.c_char_p, [_vp]),
     "l0l2_server_destroy": (_i, [_vp]),
     "l0l2_server_cancel": (_i, [_vp, _i64]),
+    "l0l2_server_set_batching": (_i, [_vp, _i]),
+    "l0l2_server_batching_stats": (_i, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "l0l2_memory_stats": (_i, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), _i]),
     "l0l2_set_tiles": (_i, [_vp, _i, _i]),
     "l0l2_tune_batch_size": (_i, [_vp, _i, _d, C.POINTER(_i), _vp, C.POINTER(_i)]),
@@ -450,7 +452,7 @@ def _result_dict(r, p):
 class Server:
     """l0l2_server: continuous batching of whole branch-and-bound solves."""
 
-    def __init__(self, device=0, hbm_budget_bytes=0, max_concurrent=4, **bnb_kw):
+    def __init__(self, device=0, hbm_budget_bytes=0, max_concurrent=4, batching=True, **bnb_kw):
         h = C.c_void_p()
         self.opts = bnb_options(**bnb_kw)
         rc = lib.l0l2_server_create(device, int(hbm_budget_bytes), int(max_concurrent), C.byref(self.opts),
@@ -459,6 +461,21 @@ class Server:
             raise L0L2Error(rc, "server creation failed")
         self._h = h
         self._p = {}
+        self.set_batching(batching)
+
+    def set_batching(self, on):
+        rc = lib.l0l2_server_set_batching(self._h, 1 if on else 0)
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, "set_batching failed")
+
+    def batching_stats(self):
+        """Executor counters: rounds, blocks, grouped launches, instance
+        contractions carried by them."""
+        v = [C.c_int64() for _ in range(4)]
+        rc = lib.l0l2_server_batching_stats(self._h, *[C.byref(x) for x in v])
+        if rc != L0L2_OK:
+            raise L0L2Error(rc, "batching_stats failed")
+        return dict(rounds=v[0].value, blocks=v[1].value, launches=v[2].value, members=v[3].value)
 
     def submit(self, X, y, lambda0, lambda2, M, rho=1.0, precision="fp32"):
         X = np.asfortranarray(X, dtype=np.float64)

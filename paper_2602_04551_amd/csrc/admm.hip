@@ -15,11 +15,18 @@
 // evaluated in FP64 with the original X (Sec. 3.1.2 and the node stopping rule
 // of Sec. 4.1): r = y - X b, g = X^T r, LB = rigorous D(r); P(beta) from X beta.
 #include <algorithm>
-#include <utility>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
 #include <limits>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "device_math.hpp"
 #include "internal.hpp"
@@ -260,17 +267,18 @@ __device__ __forceinline__ void nt_tile(const TA *__restrict__ A, int64_t lda, c
 // pairs [npr z / S, npr (z + 1) / S) of the 32-wide pairs of k and writes its
 // partial product to U + z pstride (added in slice order by k_splitk_sum): a
 // grid of S times as many workgroups for few live nodes and a long range p.
+// The workgroup's tile (bx, by) of slice z of S (the grid's coordinates, or a
+// grouped launch's tile of one member).
 template <class TA, class TB, class TC, int BM, int BN, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A, int64_t lda,
-                                                        const TB *__restrict__ B, int64_t ldb, TC *__restrict__ U,
-                                                        int64_t ldu, int64_t kdim, NodeCols ncl, int64_t pstride) {
+__device__ __forceinline__ void xw_tile(const TA *__restrict__ A, int64_t lda, const TB *__restrict__ B, int64_t ldb,
+                                        TC *__restrict__ U, int64_t ldu, int64_t kdim, NodeCols ncl, int64_t pstride,
+                                        int64_t bx, int64_t by, int64_t z, int64_t S, TC *red) {
     constexpr int TM = 16 * BM, TN = 16 * BN, E = TM * TN / (64 * WAVES);
     static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
-    __shared__ TC red[WAVES * Red<TM, TN>::WS];
-    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    const int64_t m0 = bx * TM, n0 = by * TN;
     int sb[BN], se[E];
     if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
-    const int64_t npr = kdim / 32, z = blockIdx.z, S = gridDim.z;
+    const int64_t npr = kdim / 32;
     U += pstride * z;
     nt_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, kdim, m0, n0, sb, red, npr * z / S, npr * (z + 1) / S);
 #pragma unroll
@@ -278,6 +286,15 @@ __global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A
         const int idx = threadIdx.x + t * 64 * WAVES, n = idx / TM, m = idx % TM;
         if (se[t] >= 0) U[(int64_t)se[t] * ldu + m0 + m] = sum_waves<TC, TM, TN, WAVES>(red, n, m);
     }
+}
+
+template <class TA, class TB, class TC, int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_gemm_xw(const TA *__restrict__ A, int64_t lda,
+                                                        const TB *__restrict__ B, int64_t ldb, TC *__restrict__ U,
+                                                        int64_t ldu, int64_t kdim, NodeCols ncl, int64_t pstride) {
+    __shared__ TC red[WAVES * Red<16 * BM, 16 * BN>::WS];
+    xw_tile<TA, TB, TC, BM, BN, WAVES>(A, lda, B, ldb, U, ldu, kdim, ncl, pstride, blockIdx.x, blockIdx.y, blockIdx.z,
+                                       gridDim.z, red);
 }
 
 // Scalars of the gap estimate (FP64).
@@ -373,13 +390,20 @@ __device__ __forceinline__ T admm_update(T Qv, int64_t o, int64_t j, T *__restri
 // Sums the five estimate terms over the TM consecutive threads that hold one
 // node's coordinates of the tile and stores them at gpart[(node * ntile + tile) * 5].
 template <int TM>
-__device__ __forceinline__ void store_estimate(double e[5], int m, int64_t node, double *__restrict__ gpart) {
+__device__ __forceinline__ void store_estimate(double e[5], int m, int64_t node, double *__restrict__ gpart,
+                                               int64_t ntile, int64_t tile) {
     for (int t = 0; t < 5; ++t)
         for (int off = 1; off < TM; off <<= 1) e[t] += __shfl_xor(e[t], off);
     if (m == 0 && node >= 0) {
-        double *d = gpart + (node * (int64_t)gridDim.x + blockIdx.x) * 5;
+        double *d = gpart + (node * ntile + tile) * 5;
         for (int t = 0; t < 5; ++t) d[t] = e[t];
     }
+}
+
+// The row tiles of the grid's x axis.
+template <int TM>
+__device__ __forceinline__ void store_estimate(double e[5], int m, int64_t node, double *__restrict__ gpart) {
+    store_estimate<TM>(e, m, node, gpart, (int64_t)gridDim.x, (int64_t)blockIdx.x);
 }
 
 // Contraction over n with the ADMM epilogue: Q[k][j] = sum_i Xh[i][j] U[k][i],
@@ -388,16 +412,15 @@ __device__ __forceinline__ void store_estimate(double e[5], int m, int64_t node,
 // the other buffer of a pair).  gpart != nullptr adds the per-tile sums of the
 // gap estimate.
 template <class TA, class T, int BM, int BN, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
-                                                  int64_t ldu, int64_t kdim, const T *W, T *Wout,
-                                                  T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
-                                                  const uint8_t *__restrict__ codes, const T *__restrict__ c,
-                                                  const int *__restrict__ active, DevParams<T> q, int64_t ldp,
-                                                  int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+__device__ __forceinline__ void xtu_tile(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U, int64_t ldu,
+                                         int64_t kdim, const T *W, T *Wout, T *__restrict__ beta, T *__restrict__ V,
+                                         T *__restrict__ Bst, const uint8_t *__restrict__ codes,
+                                         const T *__restrict__ c, const int *__restrict__ active,
+                                         const DevParams<T> &q, int64_t ldp, int store_b, double *__restrict__ gpart,
+                                         const GateArgs &ga, NodeCols ncl, int64_t bx, int64_t by, int64_t gx, T *red) {
     constexpr int TM = 16 * BM, TN = 16 * BN, E = TM * TN / (64 * WAVES);
     static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
-    __shared__ T red[WAVES * Red<TM, TN>::WS];
-    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    const int64_t m0 = bx * TM, n0 = by * TN;
     int sb[BN], se[E];
     if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
     EpiIn<T> ei[E];
@@ -415,8 +438,20 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ 
         if (ei[t].on)
             admm_update<T>(sum_waves<T, TM, TN, WAVES>(red, n, m), ei[t], (int64_t)se[t] * ldp + m0 + m, Wout, beta, V,
                            Bst, q, store_b, est, ga, e);
-        if (est) store_estimate<TM>(e, m, se[t], gpart);
+        if (est) store_estimate<TM>(e, m, se[t], gpart, gx, bx);
     }
+}
+
+template <class TA, class T, int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_admm_xtu(const TA *__restrict__ A, int64_t lda, const T *__restrict__ U,
+                                                  int64_t ldu, int64_t kdim, const T *W, T *Wout,
+                                                  T *__restrict__ beta, T *__restrict__ V, T *__restrict__ Bst,
+                                                  const uint8_t *__restrict__ codes, const T *__restrict__ c,
+                                                  const int *__restrict__ active, DevParams<T> q, int64_t ldp,
+                                                  int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    __shared__ T red[WAVES * Red<16 * BM, 16 * BN>::WS];
+    xtu_tile<TA, T, BM, BN, WAVES>(A, lda, U, ldu, kdim, W, Wout, beta, V, Bst, codes, c, active, q, ldp, store_b,
+                                   gpart, ga, ncl, blockIdx.x, blockIdx.y, gridDim.x, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -439,16 +474,16 @@ __global__ void k_anchor_init(const double *__restrict__ W, double *__restrict__
 // Contraction over n of an anchored sweep: Q32 = Xh^T U32 (FP32 MFMA), then
 // admm_update<double> with Q = z_a + Q32 and d = fl32(W_new - w_a).
 template <int BM, int BN, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_admm_xtu_anch(
+__device__ __forceinline__ void xtu_anch_tile(
     const float *__restrict__ A, int64_t lda, const float *__restrict__ U, int64_t ldu, int64_t kdim,
     const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W, double *__restrict__ beta,
     double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d, const uint8_t *__restrict__ codes,
-    const double *__restrict__ c, const int *__restrict__ active, DevParams<double> q, int64_t ldp, int store_b,
-    double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    const double *__restrict__ c, const int *__restrict__ active, const DevParams<double> &q, int64_t ldp,
+    int store_b, double *__restrict__ gpart, const GateArgs &ga, NodeCols ncl, int64_t bx, int64_t by, int64_t gx,
+    float *red) {
     constexpr int TM = 16 * BM, TN = 16 * BN, E = TM * TN / (64 * WAVES);
     static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
-    __shared__ float red[WAVES * Red<TM, TN>::WS];
-    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    const int64_t m0 = bx * TM, n0 = by * TN;
     int sb[BN], se[E];
     if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
     EpiIn<double> ei[E];
@@ -473,9 +508,114 @@ __global__ __launch_bounds__(64 * WAVES) void k_admm_xtu_anch(
             const double wn = admm_update<double>(Qv, ei[t], o, W, beta, V, Bst, q, store_b, est, ga, e);
             d[o] = (float)(wn - wa[t]);
         }
-        if (est) store_estimate<TM>(e, m, se[t], gpart);
+        if (est) store_estimate<TM>(e, m, se[t], gpart, gx, bx);
     }
 }
+
+template <int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_admm_xtu_anch(
+    const float *__restrict__ A, int64_t lda, const float *__restrict__ U, int64_t ldu, int64_t kdim,
+    const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W, double *__restrict__ beta,
+    double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d, const uint8_t *__restrict__ codes,
+    const double *__restrict__ c, const int *__restrict__ active, DevParams<double> q, int64_t ldp, int store_b,
+    double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    __shared__ float red[WAVES * Red<16 * BM, 16 * BN>::WS];
+    xtu_anch_tile<BM, BN, WAVES>(A, lda, U, ldu, kdim, Za, Wa, W, beta, V, Bst, d, codes, c, active, q, ldp, store_b,
+                                 gpart, ga, ncl, blockIdx.x, blockIdx.y, gridDim.x, red);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped launches (batching across instances).  One launch runs the same
+// register-tile contraction (32 x 32 tile, 4 waves) for up to kGroupMax
+// members, each with its own instance's operands, node batch and gx x gy tile
+// grid: the launch's workgroups are the members' tiles one member after another
+// (member g owns workgroups [tile0_g, tile0_g + gx_g gy_g), x fastest as in its
+// own grid), so each tile computes exactly what the member's own launch would.
+// ---------------------------------------------------------------------------
+constexpr int kGroupMax = 8;
+
+template <class T>
+struct XwMember {
+    const T *A, *B;
+    T *U;
+    const int *cols;
+    int64_t lda, ldb, ldu, kdim;
+    int gx, tile0;
+};
+
+template <class T>
+struct XtuMember {
+    const T *A, *U, *W, *c;
+    T *Wout, *beta, *V, *Bst;
+    const uint8_t *codes;
+    const int *active, *cols;
+    double *gpart;
+    int64_t lda, ldu, kdim, ldp;
+    int store_b, gx, tile0;
+    DevParams<T> q;
+    GateArgs ga;
+};
+
+struct AnchMember {
+    const float *A, *U;
+    const double *Za, *Wa, *c;
+    double *W, *beta, *V, *Bst;
+    float *d;
+    const uint8_t *codes;
+    const int *active, *cols;
+    double *gpart;
+    int64_t lda, ldu, kdim, ldp;
+    int store_b, gx, tile0;
+    DevParams<double> q;
+    GateArgs ga;
+};
+
+template <class M>
+struct Group {
+    M m[kGroupMax];
+    int count;
+};
+
+// Member owning workgroup b (members in tile order; uniform over the workgroup).
+template <class M>
+__device__ __forceinline__ int group_member(const Group<M> &g, int b) {
+    int k = 0;
+    for (int i = 1; i < g.count; ++i) k += b >= g.m[i].tile0;
+    return k;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm_xw_grp(Group<XwMember<T>> g) {
+    __shared__ T red[4 * Red<32, 32>::WS];
+    const int b = blockIdx.x;
+    const XwMember<T> &d = g.m[group_member(g, b)];
+    const int loc = b - d.tile0;
+    xw_tile<T, T, T, 2, 2, 4>(d.A, d.lda, d.B, d.ldb, d.U, d.ldu, d.kdim, NodeCols{d.cols}, 0, loc % d.gx,
+                              loc / d.gx, 0, 1, red);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_admm_xtu_grp(Group<XtuMember<T>> g) {
+    __shared__ T red[4 * Red<32, 32>::WS];
+    const int b = blockIdx.x;
+    const XtuMember<T> &d = g.m[group_member(g, b)];
+    const int loc = b - d.tile0;
+    xtu_tile<T, T, 2, 2, 4>(d.A, d.lda, d.U, d.ldu, d.kdim, d.W, d.Wout, d.beta, d.V, d.Bst, d.codes, d.c, d.active,
+                            d.q, d.ldp, d.store_b, d.gpart, d.ga, NodeCols{d.cols}, loc % d.gx, loc / d.gx, d.gx, red);
+}
+
+__global__ __launch_bounds__(256) void k_admm_xtu_anch_grp(Group<AnchMember> g) {
+    __shared__ float red[4 * Red<32, 32>::WS];
+    const int b = blockIdx.x;
+    const AnchMember &d = g.m[group_member(g, b)];
+    const int loc = b - d.tile0;
+    xtu_anch_tile<2, 2, 4>(d.A, d.lda, d.U, d.ldu, d.kdim, d.Za, d.Wa, d.W, d.beta, d.V, d.Bst, d.d, d.codes, d.c,
+                           d.active, d.q, d.ldp, d.store_b, d.gpart, d.ga, NodeCols{d.cols}, loc % d.gx, loc / d.gx,
+                           d.gx, red);
+}
+
+static_assert(sizeof(Group<XtuMember<double>>) <= 4096 && sizeof(Group<AnchMember>) <= 4096,
+              "a group travels in the kernel arguments");
 
 // ---------------------------------------------------------------------------
 // LDS-staged tiles for large grids.  A workgroup of 4 waves (2 x 2) owns a
@@ -3242,35 +3382,53 @@ int64_t live_bucket(const l0l2_ctx *ctx, int64_t active, int64_t Kp) {
     return std::min(b, Kp);
 }
 
-void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
-                 bool force, int budget) {
+// A block of sweeps in three parts (its start, sweep t, its end), so that the
+// cross-instance executor can interleave the blocks of several instances.
+struct BlockPlan {
+    int64_t cols = 0;   // node columns of the launches: the live count rounded up (live_bucket)
+    bool gram = false;  // Gram form of the b-update
+};
+
+BlockPlan block_begin(l0l2_ctx *ctx, int kind, int64_t Kp, int n, int64_t active) {
+    Workspace &ws = ctx->ws;
+    hipStream_t s = ctx->stream;
+    BlockPlan bp;
+    bp.cols = live_bucket(ctx, active, Kp);
+    hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>(),
+                       ws.ncount.as<int>(), ws.counter.as<int>());
+    bp.gram = (kind == SK_F32 || kind == SK_BF16 || kind == SK_ANCH) && gram_form(ctx);
+    if (bp.gram) ensure_gram(ctx);
+    if (kind == SK_ANCH) {
+        if (bp.gram) anchor_start_gram(ctx, Kp, bp.cols);
+        else anchor_start(ctx, Kp, bp.cols);
+    }
+    return bp;
+}
+
+void block_sweep(l0l2_ctx *ctx, int kind, const BlockPlan &bp, int t, int n, bool force, int64_t active) {
+    Instance &in = ctx->inst;
+    const int64_t cols = bp.cols;
+    const bool last = t == n, gate = last && !force, gram = bp.gram;
+    if (gram && kind == SK_F32) sweep_once_gram(ctx, cols, last, active, gate, t);
+    else if (gram && in.prec == L0L2_BF16) sweep_once_bf16_gram(ctx, cols, last, active, gate, kind == SK_ANCH, t);
+    else if (gram) sweep_once_anch_gram(ctx, cols, last, active, gate, t);
+    else if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), cols, last, active, gate);
+    else if (kind == SK_BF16) sweep_once_bf16(ctx, cols, last, active, gate, false);
+    else if (kind == SK_ANCH && in.prec == L0L2_BF16) sweep_once_bf16(ctx, cols, last, active, gate, true);
+    else if (kind == SK_ANCH && in.prec == L0L2_FP8) sweep_once_fp8(ctx, cols, last, active, gate);
+    else if (kind == SK_ANCH) sweep_once_anch(ctx, cols, last, active, gate);
+    else sweep_once<float>(ctx, sweep32(ctx), cols, last, active, gate);
+}
+
+void block_end(l0l2_ctx *ctx, int kind, const BlockPlan &bp, int64_t Kp, int n, double tol, double switch_tol,
+               bool force, int budget) {
     Instance &in = ctx->inst;
     Workspace &ws = ctx->ws;
     hipStream_t s = ctx->stream;
-    const int64_t cols = live_bucket(ctx, active, Kp);
-    hipLaunchKernelGGL(k_sweep_add, dim3(1), dim3(1), 0, s, ws.sweep_no.as<int>(), n, ws.gate.as<int>(),
-                       ws.ncount.as<int>(), ws.counter.as<int>());
-    const bool gram = (kind == SK_F32 || kind == SK_BF16 || kind == SK_ANCH) && gram_form(ctx);
-    if (gram) ensure_gram(ctx);
-    if (kind == SK_ANCH) {
-        if (gram) anchor_start_gram(ctx, Kp, cols);
-        else anchor_start(ctx, Kp, cols);
-    }
-    for (int t = 1; t <= n; ++t) {
-        const bool last = t == n, gate = last && !force;
-        if (gram && kind == SK_F32) sweep_once_gram(ctx, cols, last, active, gate, t);
-        else if (gram && in.prec == L0L2_BF16) sweep_once_bf16_gram(ctx, cols, last, active, gate, kind == SK_ANCH, t);
-        else if (gram) sweep_once_anch_gram(ctx, cols, last, active, gate, t);
-        else if (kind == SK_F64) sweep_once<double>(ctx, sweep64(ctx), cols, last, active, gate);
-        else if (kind == SK_BF16) sweep_once_bf16(ctx, cols, last, active, gate, false);
-        else if (kind == SK_ANCH && in.prec == L0L2_BF16) sweep_once_bf16(ctx, cols, last, active, gate, true);
-        else if (kind == SK_ANCH && in.prec == L0L2_FP8) sweep_once_fp8(ctx, cols, last, active, gate);
-        else if (kind == SK_ANCH) sweep_once_anch(ctx, cols, last, active, gate);
-        else sweep_once<float>(ctx, sweep32(ctx), cols, last, active, gate);
-    }
+    const int64_t cols = bp.cols;
     // an odd Gram-form block leaves the latest W in the second buffer (a node that
     // retires keeps a stale W in it, which nothing reads again)
-    if (gram && (kind == SK_F32 || kind == SK_BF16) && (n & 1))
+    if (bp.gram && (kind == SK_F32 || kind == SK_BF16) && (n & 1))
         HIPCHK(hipMemcpyAsync(ws.W.ptr, ws.W2.ptr, sizeof(float) * Kp * in.ldp, hipMemcpyDeviceToDevice, s));
     if (!force) {
         int rows = 32;
@@ -3297,6 +3455,364 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
     HIPCHK(hipMemcpyAsync(ws.host_counter, ws.counter.ptr, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
 }
 
+void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
+                 bool force, int budget) {
+    const BlockPlan bp = block_begin(ctx, kind, Kp, n, active);
+    for (int t = 1; t <= n; ++t) block_sweep(ctx, kind, bp, t, n, force, active);
+    block_end(ctx, kind, bp, Kp, n, tol, switch_tol, force, budget);
+}
+
+// ---------------------------------------------------------------------------
+// Batching across instances.  Contexts attached to an executor (the server's)
+// hand each block of sweeps to it instead of replaying their own graph.  The
+// executor takes every block waiting when it becomes free, issues their starts,
+// then sweep t of all of them together, then their ends, on its own stream, and
+// hands each context its counters.  The sweeps whose contractions use the
+// 32 x 32 register tile (FP32 mode in both b-update forms and both phases, FP64
+// mode) go out as grouped launches, one per contraction kind, whose
+// workgroups are the tiles of every member; the other sweeps are issued for
+// their context alone, between them.  Instances join and leave between blocks
+// (continuous batching).  A member's tiles compute what its own launch would,
+// so results do not depend on what else runs.
+// ---------------------------------------------------------------------------
+enum GroupClass { GC_NONE, GC_F32, GC_F32_GRAM, GC_F64, GC_ANCH, GC_ANCH_GRAM };
+
+GroupClass group_class(l0l2_ctx *ctx, int kind, const BlockPlan &bp) {
+    const Instance &in = ctx->inst;
+    if (kind == SK_F64) {
+        const TileChoice &tc = tile_choice<double>(ctx, sweep64(ctx), bp.cols);
+        return tc.xw == 0 && tc.xtu == 0 ? GC_F64 : GC_NONE;
+    }
+    if (in.prec != L0L2_FP32 || (kind != SK_F32 && kind != SK_ANCH)) return GC_NONE;
+    const TileChoice &tc = tile_choice<float>(ctx, sweep32(ctx), bp.cols);
+    if (tc.xtu != 0 || (!bp.gram && tc.xw != 0)) return GC_NONE;
+    if (kind == SK_F32) return bp.gram ? GC_F32_GRAM : GC_F32;
+    return bp.gram ? GC_ANCH_GRAM : GC_ANCH;
+}
+
+// The members of one grouped launch kind, flushed when full.
+template <class M>
+struct GroupBatch {
+    Group<M> g{};
+    int tiles = 0;
+    int64_t *launches, *members;
+    void (*go)(const Group<M> &, int, hipStream_t);
+    void add(const M &m, int ntiles, hipStream_t s) {
+        if (g.count == kGroupMax) flush(s);
+        g.m[g.count] = m;
+        g.m[g.count].tile0 = tiles;
+        ++g.count;
+        tiles += ntiles;
+    }
+    void flush(hipStream_t s) {
+        if (!g.count) return;
+        go(g, tiles, s);
+        ++*launches;
+        *members += g.count;
+        g.count = 0;
+        tiles = 0;
+    }
+};
+
+template <class T>
+void go_xw(const Group<XwMember<T>> &g, int tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_gemm_xw_grp<T>, dim3((unsigned)tiles), dim3(256), 0, s, g);
+}
+template <class T>
+void go_xtu(const Group<XtuMember<T>> &g, int tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_admm_xtu_grp<T>, dim3((unsigned)tiles), dim3(256), 0, s, g);
+}
+void go_anch(const Group<AnchMember> &g, int tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_admm_xtu_anch_grp, dim3((unsigned)tiles), dim3(256), 0, s, g);
+}
+
+template <class T>
+XwMember<T> xw_member(const Sweep<T> &sw, const Instance &in, const int *cols, int64_t ncols, int &ntiles) {
+    XwMember<T> m{};
+    m.A = sw.XhR; m.lda = sw.ldr; m.B = sw.W; m.ldb = sw.ldp; m.U = sw.U; m.ldu = sw.ldu; m.kdim = in.pp;
+    m.cols = cols;
+    m.gx = (int)(in.np / 32);
+    ntiles = m.gx * (int)(ncols / 32);
+    return m;
+}
+
+struct GroupReq {
+    l0l2_ctx *ctx;
+    int kind;
+    int64_t Kp;
+    int n;
+    double tol, switch_tol;
+    int64_t active;
+    bool force;
+    int budget;
+    int out[3] = {0, 0, 0};
+    bool done = false;
+    int rc = L0L2_OK;
+    std::string err;
+};
+
+}  // namespace
+
+struct GroupExec {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::condition_variable cv, cv_done;
+    std::deque<GroupReq *> pending;
+    bool stop = false;
+    std::thread th;
+    GroupStats st;
+};
+
+namespace {
+
+// The ctx's work goes to the executor's stream (and its allocations are
+// charged to the ctx) while the executor issues for it.
+struct OnExec {
+    l0l2_ctx *ctx;
+    hipStream_t saved;
+    MemCount *mem_saved;
+    OnExec(l0l2_ctx *c, hipStream_t s) : ctx(c), saved(c->stream), mem_saved(thread_mem()) {
+        c->stream = s;
+        thread_mem() = &c->mem;
+    }
+    ~OnExec() {
+        ctx->stream = saved;
+        thread_mem() = mem_saved;
+    }
+};
+
+GroupStats run_group(GroupExec &ex, std::vector<GroupReq *> &batch) {
+    hipStream_t S = ex.stream;
+    GroupStats st;
+    const size_t m = batch.size();
+    std::vector<BlockPlan> plan(m);
+    std::vector<GroupClass> cls(m, GC_NONE);
+    std::vector<char> ok(m, 1);
+    auto guard = [&](size_t i, auto &&f) {
+        if (!ok[i]) return;
+        OnExec on(batch[i]->ctx, S);
+        try {
+            f();
+        } catch (const Error &e) {
+            ok[i] = 0;
+            batch[i]->rc = e.code;
+            batch[i]->err = e.msg;
+        } catch (const std::exception &e) {
+            ok[i] = 0;
+            batch[i]->rc = L0L2_E_DEVICE;
+            batch[i]->err = e.what();
+        }
+    };
+    int nmax = 0;
+    for (size_t i = 0; i < m; ++i) {
+        GroupReq &r = *batch[i];
+        guard(i, [&] {
+            HIPCHK(hipStreamWaitEvent(S, r.ctx->ev_group, 0));
+            plan[i] = block_begin(r.ctx, r.kind, r.Kp, r.n, r.active);
+            cls[i] = group_class(r.ctx, r.kind, plan[i]);
+        });
+        if (ok[i]) nmax = std::max(nmax, r.n);
+    }
+    GroupBatch<XwMember<float>> xw32{{}, 0, &st.launches, &st.members, go_xw<float>};
+    GroupBatch<XwMember<double>> xw64{{}, 0, &st.launches, &st.members, go_xw<double>};
+    GroupBatch<XtuMember<float>> xtu32{{}, 0, &st.launches, &st.members, go_xtu<float>};
+    GroupBatch<XtuMember<double>> xtu64{{}, 0, &st.launches, &st.members, go_xtu<double>};
+    GroupBatch<AnchMember> anch{{}, 0, &st.launches, &st.members, go_anch};
+    for (int t = 1; t <= nmax; ++t) {
+        bool xtu_pending = false;
+        for (size_t i = 0; i < m; ++i) {
+            GroupReq &r = *batch[i];
+            if (!ok[i] || t > r.n) continue;
+            l0l2_ctx *ctx = r.ctx;
+            if (cls[i] == GC_NONE) {
+                guard(i, [&] { block_sweep(ctx, r.kind, plan[i], t, r.n, r.force, r.active); });
+                continue;
+            }
+            guard(i, [&] {
+                Instance &in = ctx->inst;
+                Workspace &ws = ctx->ws;
+                const bool last = t == r.n, gate = last && !r.force;
+                const int64_t ncols = plan[i].cols;
+                const int *cols = ws.list.as<int>();
+                const int gy = (int)(ncols / 32), gxp = (int)(in.pp / 32);
+                int nt = 0;
+                // a member's contraction over n waits for its contraction over p:
+                // flush the pending contractions over p before an XTU group fills
+                auto before_xtu = [&] {
+                    if (xtu32.g.count == kGroupMax || xtu64.g.count == kGroupMax || anch.g.count == kGroupMax) {
+                        xw32.flush(S);
+                        xw64.flush(S);
+                    }
+                };
+                if (cls[i] == GC_F64) {
+                    const Sweep<double> sw = sweep64(ctx);
+                    xw64.add(xw_member<double>(sw, in, cols, ncols, nt), nt, S);
+                    XtuMember<double> x{};
+                    x.A = sw.Xh; x.lda = sw.ldc; x.U = sw.U; x.ldu = sw.ldu; x.kdim = in.np;
+                    x.W = sw.W; x.Wout = sw.W; x.beta = sw.beta; x.V = sw.V; x.Bst = sw.B; x.c = sw.c;
+                    x.codes = ws.codes.as<uint8_t>(); x.active = ws.active.as<int>(); x.cols = cols;
+                    x.gpart = gate ? ws.gpart.as<double>() : nullptr; x.ldp = sw.ldp; x.store_b = last ? 1 : 0;
+                    x.gx = gxp; x.q = dev_params<double>(in.mp); x.ga = gate_args(in);
+                    before_xtu();
+                    xtu64.add(x, gxp * gy, S);
+                } else if (cls[i] == GC_F32 || cls[i] == GC_F32_GRAM) {
+                    Sweep<float> sw = sweep32(ctx);
+                    float *wout = sw.W;
+                    if (cls[i] == GC_F32_GRAM) {
+                        sw.Xh = in.G32.as<float>();
+                        sw.ldc = in.ldg32;
+                        sw.W = gram_in(ctx, t);
+                        sw.U = sw.W;
+                        sw.ldu = in.ldp;
+                        wout = gram_out(ctx, t);
+                    } else {
+                        xw32.add(xw_member<float>(sw, in, cols, ncols, nt), nt, S);
+                    }
+                    XtuMember<float> x{};
+                    x.A = sw.Xh; x.lda = sw.ldc; x.U = sw.U; x.ldu = sw.ldu;
+                    x.kdim = cls[i] == GC_F32_GRAM ? in.pp : in.np;
+                    x.W = sw.W; x.Wout = wout; x.beta = sw.beta; x.V = sw.V; x.Bst = sw.B; x.c = sw.c;
+                    x.codes = ws.codes.as<uint8_t>(); x.active = ws.active.as<int>(); x.cols = cols;
+                    x.gpart = gate ? ws.gpart.as<double>() : nullptr; x.ldp = sw.ldp; x.store_b = last ? 1 : 0;
+                    x.gx = gxp; x.q = dev_params<float>(in.mp); x.ga = gate_args(in);
+                    before_xtu();
+                    xtu32.add(x, gxp * gy, S);
+                } else {
+                    Sweep<float> s32 = sweep32(ctx);
+                    const Sweep<double> s64 = sweep64(ctx);
+                    AnchMember a{};
+                    if (cls[i] == GC_ANCH_GRAM) {
+                        a.A = in.G32.as<float>(); a.lda = in.ldg32; a.U = gram_in(ctx, t); a.ldu = in.ldp;
+                        a.kdim = in.pp; a.d = gram_out(ctx, t);
+                    } else {
+                        xw32.add(xw_member<float>(s32, in, cols, ncols, nt), nt, S);
+                        a.A = s32.Xh; a.lda = s32.ldc; a.U = s32.U; a.ldu = s32.ldu; a.kdim = in.np; a.d = s32.W;
+                    }
+                    a.Za = ws.Za.as<double>(); a.Wa = ws.Wa.as<double>();
+                    a.W = s64.W; a.beta = s64.beta; a.V = s64.V; a.Bst = s64.B; a.c = s64.c;
+                    a.codes = ws.codes.as<uint8_t>(); a.active = ws.active.as<int>(); a.cols = cols;
+                    a.gpart = gate ? ws.gpart.as<double>() : nullptr; a.ldp = s32.ldp; a.store_b = last ? 1 : 0;
+                    a.gx = gxp; a.q = dev_params<double>(in.mp); a.ga = gate_args(in);
+                    before_xtu();
+                    anch.add(a, gxp * gy, S);
+                }
+                xtu_pending = true;
+            });
+        }
+        xw32.flush(S);
+        xw64.flush(S);
+        if (xtu_pending) {
+            xtu32.flush(S);
+            xtu64.flush(S);
+            anch.flush(S);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            for (size_t i = 0; i < m; ++i)
+                if (ok[i]) {
+                    ok[i] = 0;
+                    batch[i]->rc = L0L2_E_DEVICE;
+                    batch[i]->err = std::string("grouped sweep launch: ") + hipGetErrorString(e);
+                }
+    }
+    for (size_t i = 0; i < m; ++i) {
+        GroupReq &r = *batch[i];
+        guard(i, [&] { block_end(r.ctx, r.kind, plan[i], r.Kp, r.n, r.tol, r.switch_tol, r.force, r.budget); });
+    }
+    const hipError_t e = hipStreamSynchronize(S);
+    st.rounds = 1;
+    st.blocks = (int64_t)m;
+    for (size_t i = 0; i < m; ++i) {
+        GroupReq &r = *batch[i];
+        if (e != hipSuccess && ok[i]) {
+            ok[i] = 0;
+            r.rc = L0L2_E_DEVICE;
+            r.err = std::string("executor stream: ") + hipGetErrorString(e);
+        }
+        if (ok[i])
+            for (int k = 0; k < 3; ++k) r.out[k] = r.ctx->ws.host_counter[k];
+    }
+    return st;
+}
+
+void group_loop(GroupExec *ex) {
+    (void)hipSetDevice(ex->device);
+    for (;;) {
+        std::vector<GroupReq *> batch;
+        {
+            std::unique_lock<std::mutex> lk(ex->mu);
+            ex->cv.wait(lk, [&] { return ex->stop || !ex->pending.empty(); });
+            if (ex->pending.empty()) break;
+            batch.assign(ex->pending.begin(), ex->pending.end());
+            ex->pending.clear();
+        }
+        const GroupStats d = run_group(*ex, batch);
+        {
+            std::lock_guard<std::mutex> lk(ex->mu);
+            for (GroupReq *r : batch) r->done = true;
+            ex->st.rounds += d.rounds;
+            ex->st.blocks += d.blocks;
+            ex->st.launches += d.launches;
+            ex->st.members += d.members;
+        }
+        ex->cv_done.notify_all();
+    }
+}
+
+// The block through the context's executor: waits for the round that runs it.
+void group_run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double switch_tol, int64_t active,
+                     bool force, int out[3], int budget) {
+    GroupExec *ex = ctx->group;
+    if (!ctx->ev_group) HIPCHK(hipEventCreateWithFlags(&ctx->ev_group, hipEventDisableTiming));
+    // the executor's stream waits for what the context queued before the block
+    HIPCHK(hipEventRecord(ctx->ev_group, ctx->stream));
+    GroupReq r{ctx, kind, Kp, n, tol, switch_tol, active, force, budget};
+    {
+        std::lock_guard<std::mutex> lk(ex->mu);
+        ex->pending.push_back(&r);
+    }
+    ex->cv.notify_one();
+    {
+        std::unique_lock<std::mutex> lk(ex->mu);
+        ex->cv_done.wait(lk, [&] { return r.done; });
+    }
+    if (r.rc != L0L2_OK) fail(r.rc, r.err);
+    out[0] = r.out[0];
+    out[1] = r.out[1];
+    out[2] = r.out[2];
+}
+
+}  // namespace
+
+GroupExec *group_exec_create(int device) {
+    auto ex = std::make_unique<GroupExec>();
+    ex->device = device;
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamCreateWithFlags(&ex->stream, hipStreamNonBlocking));
+    ex->th = std::thread(group_loop, ex.get());
+    return ex.release();
+}
+
+void group_exec_destroy(GroupExec *ex) {
+    if (!ex) return;
+    {
+        std::lock_guard<std::mutex> lk(ex->mu);
+        ex->stop = true;
+    }
+    ex->cv.notify_all();
+    if (ex->th.joinable()) ex->th.join();
+    if (ex->stream) (void)hipStreamDestroy(ex->stream);
+    delete ex;
+}
+
+GroupStats group_exec_stats(GroupExec *ex) {
+    std::lock_guard<std::mutex> lk(ex->mu);
+    return ex->st;
+}
+
+namespace {
+
 // Run one block and return the counters.  Blocks are captured once into a HIP
 // graph per (kind, padded batch, block length, tolerances) and replayed; with
 // the profiler on they are issued eagerly so each launch can be timed.
@@ -3307,6 +3823,10 @@ void run_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double sw
     ++ws.stat_blocks;
     ws.stat_node_blocks += active;
     if (8 * active < Kp) ++ws.stat_sparse;
+    if (ctx->group && !ctx->prof.on) {
+        group_run_block(ctx, kind, Kp, n, tol, switch_tol, active, force, out, budget);
+        return;
+    }
     if (!ctx->use_graphs || ctx->prof.on) {
         issue_block(ctx, kind, Kp, n, tol, switch_tol, active, force, budget);
     } else {

@@ -172,6 +172,7 @@ void l0l2_destroy(l0l2_ctx *ctx) {
     (void)hipStreamDestroy(ctx->stream);
     (void)hipEventDestroy(ctx->ev_in);
     (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->ev_group) (void)hipEventDestroy(ctx->ev_group);
     delete ctx;
 }
 

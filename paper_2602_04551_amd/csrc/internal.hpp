@@ -217,6 +217,20 @@ struct GraphKey {
 
 }  // namespace l0l2
 
+namespace l0l2 {
+// Executor of blocks of several contexts in shared launches (admm.hip).
+struct GroupExec;
+struct GroupStats {
+    int64_t rounds = 0;     // executor rounds (each runs every block waiting at its start)
+    int64_t blocks = 0;     // blocks run
+    int64_t launches = 0;   // grouped contraction launches
+    int64_t members = 0;    // member contractions in them
+};
+GroupExec *group_exec_create(int device);
+void group_exec_destroy(GroupExec *ex);
+GroupStats group_exec_stats(GroupExec *ex);
+}  // namespace l0l2
+
 struct l0l2_ctx {
     int device = 0;
     hipStream_t stream = nullptr;       // the context's own stream (non-blocking, default priority)
@@ -231,6 +245,8 @@ struct l0l2_ctx {
     bool use_graphs = true;              // replay captured blocks of sweeps
     std::string noalloc_err;             // why the allocation-free scratch is unavailable (empty: it is)
     std::atomic<int> cancel{0};          // set by l0l2_cancel (any thread), taken by the next block boundary
+    l0l2::GroupExec *group = nullptr;    // the executor its blocks go through (server contexts), or none
+    hipEvent_t ev_group = nullptr;       // orders the executor's stream after this context's stream
     l0l2::MemCount mem;                  // device bytes held by buffers this context's calls allocated
     std::map<l0l2::GraphKey, hipGraphExec_t> graphs;
     // declared after mem: destroyed before it, so their releases can uncharge it

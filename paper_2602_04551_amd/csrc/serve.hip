@@ -3,14 +3,20 @@
 // Requests (X, y, lambda0, lambda2, M, rho, precision) arrive at any time.  A
 // request is admitted, in arrival order, as soon as a worker slot is free and
 // its estimated device footprint fits in what the HBM budget has left; it then
-// runs on its own context and HIP stream (default priority), so the kernels of
-// all admitted instances overlap on the device, and its footprint returns to
-// the budget when it finishes.  Server contexts take their tile shapes from a
+// runs its branch and bound on its own context and HIP stream (default
+// priority), and its footprint returns to the budget when it finishes.  The
+// blocks of ADMM sweeps of all admitted instances go through one executor
+// (admm.hip), which runs every block waiting when it becomes free in shared
+// launches: the node solves of several instances are batched into one grid
+// per contraction (continuous batching across instances; instances join and
+// leave between blocks).  With batching off, each instance replays its own
+// blocks on its stream and the device overlaps the streams.  Server contexts take their tile shapes from a
 // size rule instead of timing them (timings taken while other instances load
 // the device would vary, and with them the summation order), so each
 // instance's computation is the same sequence of kernels whether it runs alone
 // or beside others.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -83,6 +89,8 @@ struct l0l2_server {
     };
 
     int device = 0;
+    l0l2::GroupExec *exec = nullptr;  // shared executor of the admitted instances' blocks
+    std::atomic<int> batching{1};     // attach newly admitted instances to exec
     std::unique_ptr<l0l2::Admission<Request>> adm;   // guarded by mu
     int max_concurrent = 1;
     l0l2_bnb_opts opts{};
@@ -139,6 +147,7 @@ struct l0l2_server {
         int rc = l0l2_create(device, stream, &ctx);
         if (rc == L0L2_OK) {
             ctx->tune = false;   // rule-based tile shapes: the same kernels alone and in the mix
+            if (batching.load()) ctx->group = exec;
             std::lock_guard<std::mutex> lk(mu);
             r.ctx = ctx;
             if (r.cancel) l0l2_cancel(ctx);
@@ -182,6 +191,12 @@ int l0l2_server_create(int device, size_t hbm_budget_bytes, int max_concurrent, 
     if (!s->adm) {
         delete s;
         return L0L2_E_OOM;
+    }
+    try {
+        s->exec = l0l2::group_exec_create(device);
+    } catch (...) {
+        delete s;
+        return L0L2_E_DEVICE;
     }
     s->max_concurrent = max_concurrent;
     s->opts = *opts;
@@ -310,7 +325,25 @@ int l0l2_server_destroy(l0l2_server *s) {
         s->cv_waiters.wait(lk, [&] { return s->waiters == 0; });
     }
     for (auto &kv : s->all) l0l2_result_free(&kv.second->res);
+    l0l2::group_exec_destroy(s->exec);
     delete s;
+    return L0L2_OK;
+}
+
+int l0l2_server_set_batching(l0l2_server *s, int on) {
+    if (!s || (on != 0 && on != 1)) return L0L2_E_INVALID;
+    s->batching.store(on);
+    return L0L2_OK;
+}
+
+int l0l2_server_batching_stats(l0l2_server *s, int64_t *rounds, int64_t *blocks, int64_t *launches,
+                               int64_t *members) {
+    if (!s) return L0L2_E_INVALID;
+    const l0l2::GroupStats st = l0l2::group_exec_stats(s->exec);
+    if (rounds) *rounds = st.rounds;
+    if (blocks) *blocks = st.blocks;
+    if (launches) *launches = st.launches;
+    if (members) *members = st.members;
     return L0L2_OK;
 }
 

@@ -1,10 +1,14 @@
 """Serving: whole branch-and-bound solves of several instances of different
-sizes admitted under an HBM budget and run concurrently.  Each result is the
-same alone and in the mix, bit for bit (server contexts take their tile shapes
-from a size rule, so an instance runs the same kernels whatever else runs),
-admitted instances overlap in time, the budget caps the concurrent footprint,
-each request's device high-water mark stays within its admission estimate, and
-queued or running requests can be cancelled."""
+sizes admitted under an HBM budget and run concurrently, their blocks of ADMM
+sweeps batched across instances into shared launches by the server's executor.
+Each result is the same alone and in the mix, bit for bit, and the same with
+batching across instances on and off (server contexts take their tile shapes
+from a size rule, and a grouped tile computes what the instance's own launch
+would), admitted instances overlap in time, the budget caps the concurrent
+footprint, each request's device high-water mark stays within its admission
+estimate, and queued or running requests can be cancelled."""
+import json
+import os
 import time
 
 import numpy as np
@@ -29,9 +33,10 @@ def instances():
 
 @pytest.fixture(scope="module")
 def alone(instances):
-    """Each instance through a server that runs one request at a time."""
+    """Each instance through a server that runs one request at a time, with
+    batching across instances off (its own captured blocks on its own stream)."""
     from paper_2602_04551_amd.binding import Server
-    srv = Server(0, hbm_budget_bytes=0, max_concurrent=1, **KW)
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=1, batching=False, **KW)
     out = []
     for inst in instances:
         rid = srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp32")
@@ -66,6 +71,59 @@ def test_results_identical_alone_and_in_the_mix(instances, alone, orc):
     ref = orc.Oracle.from_instance(instances[1]).bnb(tol_node=1e-6, max_iter=3000, max_iter_root=10000)
     assert abs(res[1]["certified"] - ref["certified"]) <= 1e-8 * ref["certified"]
     assert list(res[1]["support"]) == list(ref["support"])
+
+
+def _same(a, b):
+    assert a["status"] == b["status"] == 0
+    for key in ("certified", "ub", "lb", "nodes_solved", "nodes_pruned", "batches"):
+        assert a[key] == b[key], key
+    assert list(a["support"]) == list(b["support"])
+    assert np.array_equal(a["beta"], b["beta"])
+
+
+def _serve(insts, precs, batching, max_concurrent, **kw):
+    from paper_2602_04551_amd.binding import Server
+    srv = Server(0, hbm_budget_bytes=0, max_concurrent=max_concurrent, batching=batching, **kw)
+    ids = [srv.submit(i.X, i.y, i.lambda0, i.lambda2, i.M, precision=pr) for i, pr in zip(insts, precs)]
+    res = [srv.wait(r, timeout_s=600) for r in ids]
+    st = srv.batching_stats()
+    srv.close()
+    return res, st
+
+
+@pytest.mark.parametrize("precisions", [("fp32", "fp64")])
+def test_batching_across_instances_at_n_p_1000(instances, precisions):
+    """Three n = p = 1000 instances (the benchmark's configuration with three
+    seeds) in FP32 and FP64 mode, six requests at once: their blocks share
+    launches (more than one instance per grouped launch on average) and every
+    result equals, bit for bit, the instance solved alone with batching off
+    (its own captured blocks on its own stream); the seed-0 instance's certified
+    value and support equal the oracle's (tests/golden/fullsize_c2_bnb.json)."""
+    big = [datagen.config_instance("C2", seed=s) for s in (0, 1, 2)]
+    insts = [i for i in big for _ in precisions]
+    precs = [pr for _ in big for pr in precisions]
+    alone_res, _ = _serve(insts, precs, False, 1, **KW)
+    mix_res, st = _serve(insts, precs, True, len(insts), **KW)
+    print(f"batching stats {st}: {st['members'] / max(st['launches'], 1):.2f} instances per shared launch")
+    assert st["launches"] > 0 and st["members"] > st["launches"]
+    for a, b in zip(mix_res, alone_res):
+        _same(a, b)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fullsize_c2_bnb.json")) as f:
+        ref = json.load(f)
+    for r in mix_res[:len(precisions)]:
+        assert abs(r["certified"] - ref["certified"]) <= 1e-8 * ref["certified"]
+        assert list(r["support"]) == ref["support"]
+
+
+def test_batching_more_instances_than_a_group_holds(instances, alone):
+    """Twelve requests at once (two copies of each small instance): groups hold
+    at most eight members, so rounds split into several launches per kind;
+    every result equals the alone run."""
+    insts = instances + instances
+    res, st = _serve(insts, ["fp32"] * len(insts), True, len(insts), **KW)
+    assert st["launches"] > 0
+    for a, b in zip(res, alone + alone):
+        _same(a, b)
 
 
 def test_budget_caps_concurrent_footprint(instances, alone):
