@@ -56,8 +56,15 @@ def parse():
                     help="n = p = 5000 node batches of 512..4096 (free sets U[50, p]), BF16 vs FP32")
     ap.add_argument("--serve", action="store_true",
                     help="Poisson stream of independent instances through the server: p50/p99 TTCO")
-    ap.add_argument("--serve-requests", type=int, default=16)
+    ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-concurrent", type=int, default=8, help="instances in flight at once")
+    ap.add_argument("--serve-config", choices=["c4", "reduced"], default="c4")
+    ap.add_argument("--serve-precision", default="fp32")
+    ap.add_argument("--serve-K", type=int, default=64, help="node batch of each instance's branch and bound")
+    ap.add_argument("--serve-limit", type=float, default=60.0, help="per-request time limit (censored beyond)")
+    ap.add_argument("--serve-solo", type=int, default=4, help="draws timed alone to set the arrival rate")
+    ap.add_argument("--serve-interarrival", type=float, default=0.0, help="mean inter-arrival time (0: measured)")
+    ap.add_argument("--serve-batching", choices=["on", "off", "both"], default="on")
     ap.add_argument("--highdim", action="store_true",
                     help="n = 1000, p = 50000 node batches of 256 and 1024: FP8, BF16, FP32 vs FP64")
     ap.add_argument("--node-parallel", action="store_true",
@@ -628,42 +635,94 @@ def heuristic_main(args):
 
 
 def serve_main(args):
-    """A Poisson stream of independent instances (n ~ U{500..2000}, p ~ U{1000..4000}, Toeplitz
-    rho ~ U[0, 0.7], k ~ U{5..12}, SNR ~ U[2, 10], lambda0 = 0.005, lambda2 = 0.01) through the
-    server (continuous admission under an HBM budget); per-request time to certified optimum
-    (submit to done) and admission wait, p50 / p99, beside the throughput."""
+    """The serving stream: independent instances arriving as a Poisson process
+    through the server (admission under an HBM budget of 80 % of the free device
+    memory, node solves of the admitted instances batched into shared launches).
+    c4: 64 draws of n ~ U{500..5000}, p ~ U{1000..20000}, Toeplitz rho ~ U[0, 0.7],
+    k ~ U{5..30}, SNR ~ U[2, 10], lambda0 = 0.005, lambda2 = 0.01 (datagen.
+    serving_instance, seed 0); reduced: n ~ U{500..2000}, p ~ U{1000..4000},
+    k ~ U{5..12}.  The mean inter-arrival time is half the mean solo time to
+    certified optimum of the first --serve-solo draws (measured first, one at a
+    time, batching on) unless --serve-interarrival gives it.  Per request: time
+    to certified optimum (submit to done) with a per-request limit; requests that
+    hit it are censored (their time counts at the limit) and reported as such.
+    --serve-batching both runs the stream with batching across instances on and
+    then off."""
+    import torch
     from paper_2602_04551_amd import datagen
     from paper_2602_04551_amd.binding import Server
     rng = np.random.default_rng(0)
     reqs = []
+    t_gen = time.perf_counter()
     for i in range(args.serve_requests):
-        n = int(rng.integers(500, 2001))
-        p = int(rng.integers(1000, 4001))
-        reqs.append(datagen.make_instance(n, p, corr="toeplitz", rho=float(rng.uniform(0, 0.7)),
-                                          k=int(rng.integers(5, 13)), snr=float(rng.uniform(2, 10)),
-                                          lambda0=0.005, lambda2=0.01, seed=1000 + i))
-    gaps = rng.exponential(0.05, size=len(reqs))
-    srv = Server(0, hbm_budget_bytes=0, max_concurrent=args.serve_concurrent, K=64, tol_node=1e-6, max_iter=2000,
-                 max_iter_root=10000, time_limit_s=30.0)
-    t0 = time.perf_counter()
-    ids = []
-    for inst, g in zip(reqs, gaps):
-        time.sleep(float(g))
-        ids.append(srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="fp32"))
-    res = [srv.wait(r) for r in ids]
-    wall = time.perf_counter() - t0
-    srv.close()
-    tt = np.array([r["done_s"] - r["submit_s"] for r in res])
-    wait = np.array([r["admit_s"] - r["submit_s"] for r in res])
-    nodes = sum(r["nodes_solved"] for r in res)
+        if args.serve_config == "c4":
+            inst = datagen.serving_instance(rng, seed=1000 + i)
+        else:
+            n = int(rng.integers(500, 2001))
+            p = int(rng.integers(1000, 4001))
+            inst = datagen.make_instance(n, p, corr="toeplitz", rho=float(rng.uniform(0, 0.7)),
+                                         k=int(rng.integers(5, 13)), snr=float(rng.uniform(2, 10)),
+                                         lambda0=0.005, lambda2=0.01, seed=1000 + i)
+        reqs.append(inst)
+        if (i + 1) % 8 == 0:
+            print(json.dumps({"generated": i + 1, "s": round(time.perf_counter() - t_gen, 1)}), file=sys.stderr,
+                  flush=True)
+    kw = dict(K=args.serve_K, tol_node=1e-6, max_iter=2000, max_iter_root=10000, time_limit_s=args.serve_limit)
+    prec = args.serve_precision
     out = {"metric": "time-to-certified-optimum under serving", "unit": "s",
-           "requests": len(res), "certified": int(sum(r["status"] == 0 for r in res)),
-           "ttco_p50": round(float(np.percentile(tt, 50)), 4), "ttco_p99": round(float(np.percentile(tt, 99)), 4),
-           "admit_wait_p50": round(float(np.percentile(wait, 50)), 4),
-           "throughput_requests_per_s": round(len(res) / wall, 3), "node_relaxations_per_s": round(nodes / wall, 1),
-           "wall_s": round(wall, 3), "mean_interarrival_s": 0.05, "max_concurrent": args.serve_concurrent,
-           "per_request": [{"n": i.n, "p": i.p, "ttco": round(float(t), 4), "nodes": r["nodes_solved"],
-                            "status": r["status"]} for i, t, r in zip(reqs, tt, res)]}
+           "config": {"workload": args.serve_config, "requests": len(reqs), "precision": prec, "K": args.serve_K,
+                      "per_request_limit_s": args.serve_limit, "max_concurrent": args.serve_concurrent,
+                      "hbm_budget": "80 % of free device memory"}}
+    # solo times of the first draws: the arrival rate
+    solo = []
+    if args.serve_interarrival > 0:
+        gap_mean = args.serve_interarrival
+    else:
+        srv = Server(0, hbm_budget_bytes=0, max_concurrent=1, **kw)
+        for inst in reqs[:args.serve_solo]:
+            rid = srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec)
+            r = srv.wait(rid)
+            solo.append({"n": inst.n, "p": inst.p, "ttco": round(r["done_s"] - r["admit_s"], 3),
+                         "status": r["status"], "nodes": r["nodes_solved"]})
+            print(json.dumps({"solo": solo[-1]}), file=sys.stderr, flush=True)
+        srv.close()
+        gap_mean = 0.5 * float(np.mean([x["ttco"] for x in solo]))
+    out["config"]["mean_interarrival_s"] = round(gap_mean, 4)
+    out["solo"] = solo
+    gaps = np.random.default_rng(1).exponential(gap_mean, size=len(reqs))
+    modes = {"on": [True], "off": [False], "both": [True, False]}[args.serve_batching]
+    out["runs"] = {}
+    for batching in modes:
+        srv = Server(0, hbm_budget_bytes=0, max_concurrent=args.serve_concurrent, batching=batching, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ids = []
+        for inst, g in zip(reqs, gaps):
+            time.sleep(float(g))
+            ids.append(srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec))
+        res = []
+        for k, rid in enumerate(ids):
+            res.append(srv.wait(rid))
+            print(json.dumps({"batching": batching, "done": k + 1, "status": res[-1]["status"],
+                              "ttco": round(res[-1]["done_s"] - res[-1]["submit_s"], 3)}), file=sys.stderr,
+                  flush=True)
+        wall = time.perf_counter() - t0
+        st = srv.batching_stats()
+        srv.close()
+        tt = np.array([r["done_s"] - r["submit_s"] for r in res])
+        wait = np.array([r["admit_s"] - r["submit_s"] for r in res])
+        censored = [i for i, r in enumerate(res) if r["status"] != 0]
+        nodes = sum(r["nodes_solved"] for r in res)
+        out["runs"]["batching_on" if batching else "batching_off"] = {
+            "requests": len(res), "certified": len(res) - len(censored), "censored": len(censored),
+            "ttco_p50": round(float(np.percentile(tt, 50)), 4), "ttco_p99": round(float(np.percentile(tt, 99)), 4),
+            "ttco_mean": round(float(tt.mean()), 4), "admit_wait_p50": round(float(np.percentile(wait, 50)), 4),
+            "throughput_requests_per_s": round(len(res) / wall, 4), "node_relaxations_per_s": round(nodes / wall, 1),
+            "wall_s": round(wall, 3), "executor": st,
+            "instances_per_shared_launch": round(st["members"] / st["launches"], 3) if st["launches"] else None,
+            "per_request": [{"n": i.n, "p": i.p, "ttco": round(float(t), 4), "nodes": r["nodes_solved"],
+                             "status": r["status"], "peak_gb": round(r["peak_bytes"] / 1e9, 3)}
+                            for i, t, r in zip(reqs, tt, res)]}
     print(json.dumps(out), flush=True)
 
 

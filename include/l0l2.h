@@ -375,8 +375,9 @@ int l0l2_server_destroy(l0l2_server *srv);
  * the sweep contractions of FP32-mode and FP64-mode instances whose batches
  * use the 32 x 32 register tile (node batches below 128, or grids too small
  * for the 128 x 128 tile) go out as one grouped launch per contraction kind
- * covering up to 8 instances, the other sweeps launch by launch.  on = 0:
- * each instance replays its own captured blocks on its own stream.  Results
+ * covering up to 8 instances, the other sweeps launch by launch; BF16- and
+ * FP8-mode instances keep their own streams.  on = 0: each instance replays
+ * its own captured blocks on its own stream.  Results
  * are identical either way (a grouped tile computes what the instance's own
  * launch would).  Errors: L0L2_E_INVALID for a null server or on outside {0, 1}. */
 int l0l2_server_set_batching(l0l2_server *srv, int on);

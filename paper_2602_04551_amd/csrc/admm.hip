@@ -3559,6 +3559,7 @@ struct GroupExec {
     std::mutex mu;
     std::condition_variable cv, cv_done;
     std::deque<GroupReq *> pending;
+    int attached = 0;   // contexts attached (each has at most one block pending)
     bool stop = false;
     std::thread th;
     GroupStats st;
@@ -3736,6 +3737,13 @@ GroupStats run_group(GroupExec &ex, std::vector<GroupReq *> &batch) {
     return st;
 }
 
+// A round starts once every attached context has a block waiting, or
+// kGroupWindowUs after the first one arrived: contexts released by the same
+// round come back within microseconds (they only read their counters), while
+// one busy with the end of its node batch (rounding, refinement, the next
+// batch's assembly) is not waited for.
+constexpr int kGroupWindowUs = 200;
+
 void group_loop(GroupExec *ex) {
     (void)hipSetDevice(ex->device);
     for (;;) {
@@ -3744,6 +3752,8 @@ void group_loop(GroupExec *ex) {
             std::unique_lock<std::mutex> lk(ex->mu);
             ex->cv.wait(lk, [&] { return ex->stop || !ex->pending.empty(); });
             if (ex->pending.empty()) break;
+            const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(kGroupWindowUs);
+            ex->cv.wait_until(lk, until, [&] { return ex->stop || (int)ex->pending.size() >= ex->attached; });
             batch.assign(ex->pending.begin(), ex->pending.end());
             ex->pending.clear();
         }
@@ -3804,6 +3814,14 @@ void group_exec_destroy(GroupExec *ex) {
     if (ex->th.joinable()) ex->th.join();
     if (ex->stream) (void)hipStreamDestroy(ex->stream);
     delete ex;
+}
+
+void group_exec_attach(GroupExec *ex, int delta) {
+    {
+        std::lock_guard<std::mutex> lk(ex->mu);
+        ex->attached += delta;
+    }
+    ex->cv.notify_all();
 }
 
 GroupStats group_exec_stats(GroupExec *ex) {

@@ -228,6 +228,8 @@ struct GroupStats {
 };
 GroupExec *group_exec_create(int device);
 void group_exec_destroy(GroupExec *ex);
+// Contexts whose blocks the executor may wait for (+1 when one is attached, -1 when it leaves).
+void group_exec_attach(GroupExec *ex, int delta);
 GroupStats group_exec_stats(GroupExec *ex);
 }  // namespace l0l2
 

@@ -147,17 +147,24 @@ struct l0l2_server {
         int rc = l0l2_create(device, stream, &ctx);
         if (rc == L0L2_OK) {
             ctx->tune = false;   // rule-based tile shapes: the same kernels alone and in the mix
-            if (batching.load()) ctx->group = exec;
             std::lock_guard<std::mutex> lk(mu);
             r.ctx = ctx;
             if (r.cancel) l0l2_cancel(ctx);
         }
         if (rc == L0L2_OK)
             rc = l0l2_set_data(ctx, r.X.data(), r.y.data(), r.n, r.p, r.l0, r.l2, r.M, r.rho, r.prec, 0);
+        // attached once its precompute is done (the executor waits briefly for
+        // every attached context); BF16 and FP8 sweeps have no grouped kernels:
+        // those instances keep their own streams rather than queue behind it
+        if (rc == L0L2_OK && batching.load() && (r.prec == L0L2_FP32 || r.prec == L0L2_FP64)) {
+            ctx->group = exec;
+            l0l2::group_exec_attach(exec, 1);
+        }
         if (rc == L0L2_OK) rc = l0l2_bnb_solve(ctx, &opts, &r.res);
         r.rc = rc;
         if (rc != L0L2_OK) r.err = ctx ? l0l2_last_error(ctx) : l0l2_last_error(nullptr);
         if (ctx) {
+            if (ctx->group) l0l2::group_exec_attach(ctx->group, -1);
             (void)l0l2_memory_stats(ctx, nullptr, &r.peak, 0);
             {
                 std::lock_guard<std::mutex> lk(mu);
