@@ -78,6 +78,8 @@ def parse():
                     help="write profiles/hbm_traffic.json from two rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE) "
                          "of a --copy-calibrate run of the headline, then exit")
     ap.add_argument("--traffic-workload", default="c3")
+    ap.add_argument("--traffic-families", default="",
+                    help="comma-separated sweep families to summarise (default: every family found)")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="first dispatch one device copy of 256 MiB, the reference for HBM counter scaling")
     return ap.parse_args()
@@ -312,7 +314,7 @@ FAMILIES = {"admm_xtu.bf16": ("k_admm_xtu_bf16", "k_admm_xtu_anch_bf16"),
             "admm_xtu.f64": ("k_admm_xtu<double", "k_admm_xtu_lds<double")}
 
 
-def traffic_summary(fetch_csv, write_csv, workload, last=50):
+def traffic_summary(fetch_csv, write_csv, workload, last=50, families=None):
     """HBM bytes per launch of each sweep family from two rocprofv3 counter
     passes of the same command: FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
     scaled by what each reads for the 256 MiB device copy dispatched first
@@ -333,6 +335,8 @@ def traffic_summary(fetch_csv, write_csv, workload, last=50):
         ref = max(copies) * 1024.0 if copies else None
         scale = (256.0 * 2 ** 20) / ref if ref else 1.0
         for fam, pats in FAMILIES.items():
+            if families and fam not in families:
+                continue
             vals = [float(r["Counter_Value"]) * 1024.0 * scale for r in rows
                     if any(re.search(re.escape(pt), r["Kernel_Name"]) for pt in pats)]
             if vals:
@@ -729,7 +733,8 @@ def serve_main(args):
 def main():
     args = parse()
     if args.traffic_summary:
-        return traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.traffic_workload)
+        return traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.traffic_workload,
+                               families=args.traffic_families.split(",") if args.traffic_families else None)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build runs on exactly one GPU (no multi-GPU path); use --gpus 1", file=sys.stderr)
