@@ -701,9 +701,11 @@ def serve_main(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ids = []
-        for inst, g in zip(reqs, gaps):
+        for k, (inst, g) in enumerate(zip(reqs, gaps)):
             time.sleep(float(g))
             ids.append(srv.submit(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision=prec))
+            print(json.dumps({"batching": batching, "submitted": k + 1, "n": inst.n, "p": inst.p,
+                              "t": round(time.perf_counter() - t0, 2)}), file=sys.stderr, flush=True)
         res = []
         for k, rid in enumerate(ids):
             res.append(srv.wait(rid))

@@ -372,11 +372,11 @@ int l0l2_server_destroy(l0l2_server *srv);
  * the admitted instances).  on = 1 (the default): instances admitted
  * after the call hand every block of ADMM sweeps to the server's executor,
  * which runs all blocks waiting when it becomes free together on one stream:
- * the sweep contractions of FP32-mode and FP64-mode instances whose batches
+ * the sweep contractions of FP32-, FP64- and BF16-mode instances whose batches
  * use the 32 x 32 register tile (node batches below 128, or grids too small
- * for the 128 x 128 tile) go out as one grouped launch per contraction kind
- * covering up to 8 instances, the other sweeps launch by launch; BF16- and
- * FP8-mode instances keep their own streams.  on = 0: each instance replays
+ * for the 128 x 128 tile; BF16 then takes the split form) go out as one
+ * grouped launch per contraction kind covering up to 8 instances, the other
+ * sweeps launch by launch; FP8-mode instances keep their own streams.  on = 0: each instance replays
  * its own captured blocks on its own stream.  Results
  * are identical either way (a grouped tile computes what the instance's own
  * launch would).  Errors: L0L2_E_INVALID for a null server or on outside {0, 1}. */

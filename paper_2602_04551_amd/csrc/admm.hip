@@ -1488,17 +1488,16 @@ constexpr int kWavesBf16 = 8;
 // U[k][i] = sum_j Xh[i][j] W[k][j] with Xh row-major (row i at A + i*lda); with
 // gridDim.z = S > 1, slices of the range write partial products to U + z pstride
 // as in k_gemm_xw.
-__global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *__restrict__ Ahi,
-                                                                  const __bf16 *__restrict__ Alo, int64_t lda,
-                                                                  const float *__restrict__ B, int64_t ldb,
-                                                                  float *__restrict__ U, int64_t ldu, int64_t kdim,
-                                                                  NodeCols ncl, int64_t pstride) {
-    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+__device__ __forceinline__ void xw_bf16_tile(const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo,
+                                             int64_t lda, const float *__restrict__ B, int64_t ldb,
+                                             float *__restrict__ U, int64_t ldu, int64_t kdim, NodeCols ncl,
+                                             int64_t pstride, int64_t bx, int64_t by, int64_t z, int64_t S,
+                                             float *red) {
+    const int64_t m0 = bx * 32, n0 = by * 32;
     constexpr int E = 1024 / (64 * kWavesBf16);
     int sb[2], se[E];
     if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
-    const int64_t npr = kdim / 64, z = blockIdx.z, S = gridDim.z;
+    const int64_t npr = kdim / 64;
     U += pstride * z;
     nt_tile_bf16<kWavesBf16>(Ahi, Alo, lda, B, ldb, kdim, m0, n0, sb, red, npr * z / S, npr * (z + 1) / S);
 #pragma unroll
@@ -1508,15 +1507,24 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *
     }
 }
 
+__global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16(const __bf16 *__restrict__ Ahi,
+                                                                  const __bf16 *__restrict__ Alo, int64_t lda,
+                                                                  const float *__restrict__ B, int64_t ldb,
+                                                                  float *__restrict__ U, int64_t ldu, int64_t kdim,
+                                                                  NodeCols ncl, int64_t pstride) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    xw_bf16_tile(Ahi, Alo, lda, B, ldb, U, ldu, kdim, ncl, pstride, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z,
+                 red);
+}
+
 // Q[k][j] = sum_i Xh[i][j] U[k][i] (Xh column-major) with the ADMM epilogue.
-__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
+__device__ __forceinline__ void xtu_bf16_tile(
     const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
     int64_t ldu, int64_t kdim, const float *W, float *Wout, float *__restrict__ beta, float *__restrict__ V,
     float *__restrict__ Bst, const uint8_t *__restrict__ codes, const float *__restrict__ c,
-    const int *__restrict__ active, DevParams<float> q, int64_t ldp, int store_b, double *__restrict__ gpart,
-    GateArgs ga, NodeCols ncl) {
-    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    const int *__restrict__ active, const DevParams<float> &q, int64_t ldp, int store_b, double *__restrict__ gpart,
+    const GateArgs &ga, NodeCols ncl, int64_t bx, int64_t by, int64_t gx, float *red) {
+    const int64_t m0 = bx * 32, n0 = by * 32;
     constexpr int E = 1024 / (64 * kWavesBf16);
     int sb[2], se[E];
     if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
@@ -1535,20 +1543,31 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
         if (ei[t].on)
             admm_update<float>(sum_waves<float, 32, 32, kWavesBf16>(red, n, m), ei[t], (int64_t)se[t] * ldp + m0 + m,
                                Wout, beta, V, Bst, q, store_b, est, ga, e);
-        if (est) store_estimate<32>(e, m, se[t], gpart);
+        if (est) store_estimate<32>(e, m, se[t], gpart, gx, bx);
     }
+}
+
+__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16(
+    const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
+    int64_t ldu, int64_t kdim, const float *W, float *Wout, float *__restrict__ beta, float *__restrict__ V,
+    float *__restrict__ Bst, const uint8_t *__restrict__ codes, const float *__restrict__ c,
+    const int *__restrict__ active, DevParams<float> q, int64_t ldp, int store_b, double *__restrict__ gpart,
+    GateArgs ga, NodeCols ncl) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    xtu_bf16_tile(Ahi, Alo, lda, U, ldu, kdim, W, Wout, beta, V, Bst, codes, c, active, q, ldp, store_b, gpart, ga,
+                  ncl, blockIdx.x, blockIdx.y, gridDim.x, red);
 }
 
 // Contraction over n of an anchored sweep in the BF16 split form (register
 // tile): Q = z_a + Xh^T U with the BF16 pair, FP64 update, d = fl32(W - w_a).
-__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_anch_bf16(
+__device__ __forceinline__ void xtu_anch_bf16_tile(
     const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
     int64_t ldu, int64_t kdim, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W,
     double *__restrict__ beta, double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d,
     const uint8_t *__restrict__ codes, const double *__restrict__ c, const int *__restrict__ active,
-    DevParams<double> q, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
-    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+    const DevParams<double> &q, int64_t ldp, int store_b, double *__restrict__ gpart, const GateArgs &ga,
+    NodeCols ncl, int64_t bx, int64_t by, int64_t gx, float *red) {
+    const int64_t m0 = bx * 32, n0 = by * 32;
     constexpr int E = 1024 / (64 * kWavesBf16);
     int sb[2], se[E];
     if (!tile_slots<32, 2, E, kWavesBf16>(ncl, n0, sb, se)) return;
@@ -1574,9 +1593,90 @@ __global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_anch_bf16(
             const double wn = admm_update<double>(Qv, ei[t], o, W, beta, V, Bst, q, store_b, est, ga, e);
             d[o] = (float)(wn - wa[t]);
         }
-        if (est) store_estimate<32>(e, m, se[t], gpart);
+        if (est) store_estimate<32>(e, m, se[t], gpart, gx, bx);
     }
 }
+
+__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_anch_bf16(
+    const __bf16 *__restrict__ Ahi, const __bf16 *__restrict__ Alo, int64_t lda, const float *__restrict__ U,
+    int64_t ldu, int64_t kdim, const double *__restrict__ Za, const double *__restrict__ Wa, double *__restrict__ W,
+    double *__restrict__ beta, double *__restrict__ V, double *__restrict__ Bst, float *__restrict__ d,
+    const uint8_t *__restrict__ codes, const double *__restrict__ c, const int *__restrict__ active,
+    DevParams<double> q, int64_t ldp, int store_b, double *__restrict__ gpart, GateArgs ga, NodeCols ncl) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    xtu_anch_bf16_tile(Ahi, Alo, lda, U, ldu, kdim, Za, Wa, W, beta, V, Bst, d, codes, c, active, q, ldp, store_b,
+                       gpart, ga, ncl, blockIdx.x, blockIdx.y, gridDim.x, red);
+}
+
+// Grouped launches of the BF16 split form (register tile, 8 waves): members as
+// in the FP32 / FP64 groups, A given as its BF16 pair.
+struct XwBfMember {
+    const __bf16 *hi, *lo;
+    const float *B;
+    float *U;
+    const int *cols;
+    int64_t lda, ldb, ldu, kdim;
+    int gx, tile0;
+};
+
+struct XtuBfMember {
+    const __bf16 *hi, *lo;
+    const float *U, *W, *c;
+    float *Wout, *beta, *V, *Bst;
+    const uint8_t *codes;
+    const int *active, *cols;
+    double *gpart;
+    int64_t lda, ldu, kdim, ldp;
+    int store_b, gx, tile0;
+    DevParams<float> q;
+    GateArgs ga;
+};
+
+struct AnchBfMember {
+    const __bf16 *hi, *lo;
+    const float *U;
+    const double *Za, *Wa, *c;
+    double *W, *beta, *V, *Bst;
+    float *d;
+    const uint8_t *codes;
+    const int *active, *cols;
+    double *gpart;
+    int64_t lda, ldu, kdim, ldp;
+    int store_b, gx, tile0;
+    DevParams<double> q;
+    GateArgs ga;
+};
+
+__global__ __launch_bounds__(64 * kWavesBf16) void k_gemm_xw_bf16_grp(Group<XwBfMember> g) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    const int b = blockIdx.x;
+    const XwBfMember &d = g.m[group_member(g, b)];
+    const int loc = b - d.tile0;
+    xw_bf16_tile(d.hi, d.lo, d.lda, d.B, d.ldb, d.U, d.ldu, d.kdim, NodeCols{d.cols}, 0, loc % d.gx, loc / d.gx, 0, 1,
+                 red);
+}
+
+__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_bf16_grp(Group<XtuBfMember> g) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    const int b = blockIdx.x;
+    const XtuBfMember &d = g.m[group_member(g, b)];
+    const int loc = b - d.tile0;
+    xtu_bf16_tile(d.hi, d.lo, d.lda, d.U, d.ldu, d.kdim, d.W, d.Wout, d.beta, d.V, d.Bst, d.codes, d.c, d.active, d.q,
+                  d.ldp, d.store_b, d.gpart, d.ga, NodeCols{d.cols}, loc % d.gx, loc / d.gx, d.gx, red);
+}
+
+__global__ __launch_bounds__(64 * kWavesBf16) void k_admm_xtu_anch_bf16_grp(Group<AnchBfMember> g) {
+    __shared__ float red[kWavesBf16 * Red<32, 32>::WS];
+    const int b = blockIdx.x;
+    const AnchBfMember &d = g.m[group_member(g, b)];
+    const int loc = b - d.tile0;
+    xtu_anch_bf16_tile(d.hi, d.lo, d.lda, d.U, d.ldu, d.kdim, d.Za, d.Wa, d.W, d.beta, d.V, d.Bst, d.d, d.codes, d.c,
+                       d.active, d.q, d.ldp, d.store_b, d.gpart, d.ga, NodeCols{d.cols}, loc % d.gx, loc / d.gx, d.gx,
+                       red);
+}
+
+static_assert(sizeof(Group<AnchBfMember>) <= 4096 && sizeof(Group<XtuBfMember>) <= 4096,
+              "a group travels in the kernel arguments");
 
 // ---------------------------------------------------------------------------
 // FP8 storage (anchored sweeps only).  The folded operand is stored as FP8 e4m3
@@ -3468,20 +3568,29 @@ void issue_block(l0l2_ctx *ctx, int kind, int64_t Kp, int n, double tol, double 
 // executor takes every block waiting when it becomes free, issues their starts,
 // then sweep t of all of them together, then their ends, on its own stream, and
 // hands each context its counters.  The sweeps whose contractions use the
-// 32 x 32 register tile (FP32 mode in both b-update forms and both phases, FP64
-// mode) go out as grouped launches, one per contraction kind, whose
+// 32 x 32 register tile (FP32 mode and the BF16 split form in both b-update
+// forms and both phases, FP64 mode) go out as grouped launches, one per
+// contraction kind, whose
 // workgroups are the tiles of every member; the other sweeps are issued for
 // their context alone, between them.  Instances join and leave between blocks
 // (continuous batching).  A member's tiles compute what its own launch would,
 // so results do not depend on what else runs.
 // ---------------------------------------------------------------------------
-enum GroupClass { GC_NONE, GC_F32, GC_F32_GRAM, GC_F64, GC_ANCH, GC_ANCH_GRAM };
+enum GroupClass { GC_NONE, GC_F32, GC_F32_GRAM, GC_F64, GC_ANCH, GC_ANCH_GRAM, GC_BF, GC_BF_GRAM, GC_BFA, GC_BFA_GRAM };
 
 GroupClass group_class(l0l2_ctx *ctx, int kind, const BlockPlan &bp) {
     const Instance &in = ctx->inst;
     if (kind == SK_F64) {
         const TileChoice &tc = tile_choice<double>(ctx, sweep64(ctx), bp.cols);
         return tc.xw == 0 && tc.xtu == 0 ? GC_F64 : GC_NONE;
+    }
+    if (in.prec == L0L2_BF16 && (kind == SK_BF16 || kind == SK_ANCH)) {
+        // the BF16 split form on the register tile (the single-term blocks need
+        // the LDS-staged tiles, so they are not taken here)
+        const TileChoice &tc = tile_choice_bf16(ctx, bp.cols);
+        if (tc.xtu != 0 || (!bp.gram && tc.xw != 0)) return GC_NONE;
+        if (kind == SK_BF16) return bp.gram ? GC_BF_GRAM : GC_BF;
+        return bp.gram ? GC_BFA_GRAM : GC_BFA;
     }
     if (in.prec != L0L2_FP32 || (kind != SK_F32 && kind != SK_ANCH)) return GC_NONE;
     const TileChoice &tc = tile_choice<float>(ctx, sweep32(ctx), bp.cols);
@@ -3524,6 +3633,15 @@ void go_xtu(const Group<XtuMember<T>> &g, int tiles, hipStream_t s) {
 }
 void go_anch(const Group<AnchMember> &g, int tiles, hipStream_t s) {
     hipLaunchKernelGGL(k_admm_xtu_anch_grp, dim3((unsigned)tiles), dim3(256), 0, s, g);
+}
+void go_xw_bf(const Group<XwBfMember> &g, int tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_gemm_xw_bf16_grp, dim3((unsigned)tiles), dim3(64 * kWavesBf16), 0, s, g);
+}
+void go_xtu_bf(const Group<XtuBfMember> &g, int tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_admm_xtu_bf16_grp, dim3((unsigned)tiles), dim3(64 * kWavesBf16), 0, s, g);
+}
+void go_anch_bf(const Group<AnchBfMember> &g, int tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_admm_xtu_anch_bf16_grp, dim3((unsigned)tiles), dim3(64 * kWavesBf16), 0, s, g);
 }
 
 template <class T>
@@ -3620,6 +3738,9 @@ GroupStats run_group(GroupExec &ex, std::vector<GroupReq *> &batch) {
     GroupBatch<XtuMember<float>> xtu32{{}, 0, &st.launches, &st.members, go_xtu<float>};
     GroupBatch<XtuMember<double>> xtu64{{}, 0, &st.launches, &st.members, go_xtu<double>};
     GroupBatch<AnchMember> anch{{}, 0, &st.launches, &st.members, go_anch};
+    GroupBatch<XwBfMember> xwbf{{}, 0, &st.launches, &st.members, go_xw_bf};
+    GroupBatch<XtuBfMember> xtubf{{}, 0, &st.launches, &st.members, go_xtu_bf};
+    GroupBatch<AnchBfMember> anchbf{{}, 0, &st.launches, &st.members, go_anch_bf};
     for (int t = 1; t <= nmax; ++t) {
         bool xtu_pending = false;
         for (size_t i = 0; i < m; ++i) {
@@ -3641,12 +3762,54 @@ GroupStats run_group(GroupExec &ex, std::vector<GroupReq *> &batch) {
                 // a member's contraction over n waits for its contraction over p:
                 // flush the pending contractions over p before an XTU group fills
                 auto before_xtu = [&] {
-                    if (xtu32.g.count == kGroupMax || xtu64.g.count == kGroupMax || anch.g.count == kGroupMax) {
+                    if (xtu32.g.count == kGroupMax || xtu64.g.count == kGroupMax || anch.g.count == kGroupMax ||
+                        xtubf.g.count == kGroupMax || anchbf.g.count == kGroupMax) {
                         xw32.flush(S);
                         xw64.flush(S);
+                        xwbf.flush(S);
                     }
                 };
-                if (cls[i] == GC_F64) {
+                if (cls[i] == GC_BF || cls[i] == GC_BF_GRAM || cls[i] == GC_BFA || cls[i] == GC_BFA_GRAM) {
+                    const Sweep<float> s32 = sweep32(ctx);
+                    const bool gram = cls[i] == GC_BF_GRAM || cls[i] == GC_BFA_GRAM;
+                    const bool anchd = cls[i] == GC_BFA || cls[i] == GC_BFA_GRAM;
+                    // the contraction over n (over p with G): A, its range, the node
+                    // operand read and the one written
+                    const __bf16 *hi = gram ? in.Ghi.as<__bf16>() : in.Xh.as<__bf16>();
+                    const __bf16 *lo = gram ? in.Glo.as<__bf16>() : in.XhLo.as<__bf16>();
+                    const int64_t lda = gram ? in.ldgb : in.ldw, ldu = gram ? in.ldp : in.ldu;
+                    const int64_t kdim = gram ? in.pp : in.np;
+                    const float *U = gram ? gram_in(ctx, t) : s32.U;
+                    float *wout = gram ? gram_out(ctx, t) : s32.W;
+                    if (!gram) {
+                        XwBfMember x{};
+                        x.hi = in.XhR.as<__bf16>(); x.lo = in.XhRLo.as<__bf16>(); x.lda = in.ldwr;
+                        x.B = s32.W; x.ldb = in.ldp; x.U = s32.U; x.ldu = in.ldu; x.kdim = in.pp; x.cols = cols;
+                        x.gx = (int)(in.np / 32);
+                        xwbf.add(x, x.gx * gy, S);
+                    }
+                    before_xtu();
+                    if (anchd) {
+                        const Sweep<double> s64 = sweep64(ctx);
+                        AnchBfMember a{};
+                        a.hi = hi; a.lo = lo; a.lda = lda; a.U = U; a.ldu = ldu; a.kdim = kdim;
+                        a.Za = ws.Za.as<double>(); a.Wa = ws.Wa.as<double>();
+                        a.W = s64.W; a.beta = s64.beta; a.V = s64.V; a.Bst = s64.B; a.d = wout; a.c = s64.c;
+                        a.codes = ws.codes.as<uint8_t>(); a.active = ws.active.as<int>(); a.cols = cols;
+                        a.gpart = gate ? ws.gpart.as<double>() : nullptr; a.ldp = in.ldp; a.store_b = last ? 1 : 0;
+                        a.gx = gxp; a.q = dev_params<double>(in.mp); a.ga = gate_args(in);
+                        anchbf.add(a, gxp * gy, S);
+                    } else {
+                        XtuBfMember x{};
+                        x.hi = hi; x.lo = lo; x.lda = lda; x.U = U; x.ldu = ldu; x.kdim = kdim;
+                        x.W = gram ? gram_in(ctx, t) : s32.W; x.Wout = wout;
+                        x.beta = s32.beta; x.V = s32.V; x.Bst = s32.B; x.c = s32.c;
+                        x.codes = ws.codes.as<uint8_t>(); x.active = ws.active.as<int>(); x.cols = cols;
+                        x.gpart = gate ? ws.gpart.as<double>() : nullptr; x.ldp = in.ldp; x.store_b = last ? 1 : 0;
+                        x.gx = gxp; x.q = dev_params<float>(in.mp); x.ga = gate_args(in);
+                        xtubf.add(x, gxp * gy, S);
+                    }
+                } else if (cls[i] == GC_F64) {
                     const Sweep<double> sw = sweep64(ctx);
                     xw64.add(xw_member<double>(sw, in, cols, ncols, nt), nt, S);
                     XtuMember<double> x{};
@@ -3703,10 +3866,13 @@ GroupStats run_group(GroupExec &ex, std::vector<GroupReq *> &batch) {
         }
         xw32.flush(S);
         xw64.flush(S);
+        xwbf.flush(S);
         if (xtu_pending) {
             xtu32.flush(S);
             xtu64.flush(S);
             anch.flush(S);
+            xtubf.flush(S);
+            anchbf.flush(S);
         }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess)

@@ -154,9 +154,9 @@ struct l0l2_server {
         if (rc == L0L2_OK)
             rc = l0l2_set_data(ctx, r.X.data(), r.y.data(), r.n, r.p, r.l0, r.l2, r.M, r.rho, r.prec, 0);
         // attached once its precompute is done (the executor waits briefly for
-        // every attached context); BF16 and FP8 sweeps have no grouped kernels:
-        // those instances keep their own streams rather than queue behind it
-        if (rc == L0L2_OK && batching.load() && (r.prec == L0L2_FP32 || r.prec == L0L2_FP64)) {
+        // every attached context); FP8 sweeps have no grouped kernels: those
+        // instances keep their own streams rather than queue behind it
+        if (rc == L0L2_OK && batching.load() && r.prec != L0L2_FP8) {
             ctx->group = exec;
             l0l2::group_exec_attach(exec, 1);
         }

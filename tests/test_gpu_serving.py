@@ -91,10 +91,11 @@ def _serve(insts, precs, batching, max_concurrent, **kw):
     return res, st
 
 
-@pytest.mark.parametrize("precisions", [("fp32", "fp64")])
+@pytest.mark.parametrize("precisions", [("fp32", "fp64"), ("bf16",)])
 def test_batching_across_instances_at_n_p_1000(instances, precisions):
     """Three n = p = 1000 instances (the benchmark's configuration with three
-    seeds) in FP32 and FP64 mode, six requests at once: their blocks share
+    seeds) in FP32 and FP64 mode (six requests at once), and in BF16 mode
+    (three requests, the split-form register-tile kernels): their blocks share
     launches (more than one instance per grouped launch on average) and every
     result equals, bit for bit, the instance solved alone with batching off
     (its own captured blocks on its own stream); the seed-0 instance's certified
