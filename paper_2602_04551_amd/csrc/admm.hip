@@ -1136,18 +1136,25 @@ __device__ __forceinline__ void lds_tile_bf16(const __bf16 *__restrict__ Ahi, co
     L0L2_GLOADB(va1, vb1, last < 1 ? last : 1)
     L0L2_SSTOREB(0, va0, vb0)
     __syncthreads();
-    for (int64_t c = 0; c < nch; c += 2) {
+    // pairs of chunks with no branch inside the body: a branch between a load
+    // and its use lets the compiler sink the load past it, which cuts that
+    // load's head start from two chunks of work to one
+    int64_t c = 0;
+    for (; c + 1 < nch; c += 2) {
         L0L2_GLOADB(va0, vb0, c + 2 < last ? c + 2 : last)
         L0L2_COMPUTEB(0)
         __builtin_amdgcn_sched_barrier(0);
         L0L2_SSTOREB(1, va1, vb1)
         __syncthreads();
-        if (c + 1 >= nch) break;
         L0L2_GLOADB(va1, vb1, c + 3 < last ? c + 3 : last)
         L0L2_COMPUTEB(1)
         __builtin_amdgcn_sched_barrier(0);
         L0L2_SSTOREB(0, va0, vb0)
         __syncthreads();
+    }
+    if (c < nch) {
+        // odd count: the last chunk is in stage 0
+        L0L2_COMPUTEB(0)
     }
 #undef L0L2_GLOADB
 #undef L0L2_SSTOREB
@@ -1360,20 +1367,27 @@ __device__ __forceinline__ void lds_tile_bf16s(const __bf16 *__restrict__ A, int
     L0L2_GLOADS(va1, vb1, last < 1 ? last : 1)
     L0L2_SSTORES(0, va0, vb0)
     __syncthreads();
-    for (int64_t c = 0; c < nch; c += 2) {
+    // pairs of chunks with no branch inside the body (a branch between a load
+    // and its use lets the compiler sink the load past it, which cuts that
+    // load's head start from two chunks of work to one)
+    int64_t c = 0;
+    for (; c + 1 < nch; c += 2) {
         // chunk c in LDS stage 0, chunk c + 1 in register set 1
         L0L2_GLOADS(va0, vb0, c + 2 < last ? c + 2 : last)
         L0L2_COMPUTES(0)
         __builtin_amdgcn_sched_barrier(0);
         L0L2_SSTORES(1, va1, vb1)
         __syncthreads();
-        if (c + 1 >= nch) break;
         // chunk c + 1 in LDS stage 1, chunk c + 2 in register set 0
         L0L2_GLOADS(va1, vb1, c + 3 < last ? c + 3 : last)
         L0L2_COMPUTES(1)
         __builtin_amdgcn_sched_barrier(0);
         L0L2_SSTORES(0, va0, vb0)
         __syncthreads();
+    }
+    if (c < nch) {
+        // odd count: the last chunk is in stage 0
+        L0L2_COMPUTES(0)
     }
 #undef L0L2_GLOADS
 #undef L0L2_SSTORES
