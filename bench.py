@@ -78,6 +78,8 @@ def parse():
                     help="write profiles/hbm_traffic.json from two rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE) "
                          "of a --copy-calibrate run of the headline, then exit")
     ap.add_argument("--traffic-workload", default="c3")
+    ap.add_argument("--bf16-rows", type=int, default=128, choices=[128, 256],
+                    help="rows of the single-term BF16 sweep's largest tile")
     ap.add_argument("--traffic-families", default="",
                     help="comma-separated sweep families to summarise (default: every family found)")
     ap.add_argument("--copy-calibrate", action="store_true",
@@ -769,6 +771,7 @@ def main():
     root = fp64_root(inst)
     print(json.dumps({"root_sweeps": root[3], "root_ub": root[2]}), file=sys.stderr, flush=True)
     mixed = Path(inst, "bf16", codes, root)
+    mixed.ctx.set_bf16_tile_rows(args.bf16_rows)
     dt, its, prof = run_path(mixed, args.steps, args.warmup)
     ms_per_step = 1e3 * dt / args.steps
     value = K * args.steps / dt
@@ -780,7 +783,7 @@ def main():
            "config": {"workload": wl.format(K=K), "n": n, "p": p, "K": K, "node_tol": 1e-6, "check_every": 10,
                       "rho": 1.0, "root_warm_start": f"FP64 root relaxation to a 1e-9 gap ({root[3]} sweeps), "
                                                      "shared by every precision",
-                      "b_update": b_update_info(mixed.ctx)},
+                      "b_update": b_update_info(mixed.ctx), "bf16_tile_rows": args.bf16_rows},
            "roofline": roof,
            "roofline_hbm": sweep_bytes_roofline(prof, n, p, "bf16"),
            "kernels": kernels,

@@ -466,6 +466,15 @@ int l0l2_cancel(l0l2_ctx *ctx);
  * L0L2_E_INVALID for other values. */
 int l0l2_set_bf16_terms(l0l2_ctx *ctx, int terms);
 
+/* Rows of the single-term sweep's largest LDS-staged tile (the Gram form's
+ * 128-node tile): 128 (default) keeps the 128 x 128 tile; 256, where the padded
+ * p is a multiple of 256, takes a 256 x 128 tile (one workgroup per compute
+ * unit, each wave a 128 x 64 block: fewer operand bytes staged per MFMA, but
+ * one wave per SIMD; slower at n = p = 5000).  The results are
+ * those of the same contraction in another tile order: bounds agree to the
+ * node tolerance, not bit for bit.  Returns L0L2_E_INVALID for other values. */
+int l0l2_set_bf16_tile_rows(l0l2_ctx *ctx, int rows);
+
 /* Opt-in timing of the library's kernels with HIP events recorded on the
  * context stream around each launch (adds one event pair per launch).
  * l0l2_profile_enable clears the counters and switches timing on (1) or off (0).

@@ -95,6 +95,7 @@ SIGNATURES = {
     "l0l2_bnb_path": (_i, [_vp, C.POINTER(l0l2_bnb_opts), _i, _vp, C.POINTER(l0l2_bnb_result)]),
     "l0l2_set_bupdate_form": (_i, [_vp, _i]),
     "l0l2_set_bf16_terms": (_i, [_vp, _i]),
+    "l0l2_set_bf16_tile_rows": (_i, [_vp, _i]),
     "l0l2_bupdate_form": (_i, [_vp, C.POINTER(_i), C.POINTER(_d), C.POINTER(_d)]),
     "l0l2_cancel": (_i, [_vp]),
     "l0l2_profile_enable": (_i, [_vp, _i]),
@@ -373,6 +374,10 @@ class Context:
     def set_bf16_terms(self, terms=1):
         """BF16 Gram-form sweeps: 1 single-term anchored blocks (default), 3 split form in every sweep."""
         self._check(lib.l0l2_set_bf16_terms(self._h, int(terms)))
+
+    def set_bf16_tile_rows(self, rows=128):
+        """Rows of the single-term BF16 sweep's largest LDS-staged tile: 128 (default) or 256."""
+        self._check(lib.l0l2_set_bf16_tile_rows(self._h, int(rows)))
 
     def set_tiles(self, xw_shape=-1, xtu_shape=-1):
         self._check(lib.l0l2_set_tiles(self._h, int(xw_shape), int(xtu_shape)))

@@ -1401,8 +1401,11 @@ __device__ __forceinline__ void lds_tile_bf16s(const __bf16 *__restrict__ A, int
 // d = bf16(W_new - w_a) to Dout.  The product's rounding error scales with |d|,
 // which vanishes as the iterates settle, so the single BF16 term costs the
 // fixed point nothing that the anchor does not already fix.
+// The 256-row tile (WM = 8) keeps one workgroup per compute unit (its LDS
+// stages and accumulators need the whole budget) and reports the gap-estimate
+// sums per 128-row half, the granularity the 128-row tiles report.
 template <int WM, int WN, int MODE>
-__global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16s_lds(
+__global__ __launch_bounds__(256, (WM > 4 ? 1 : 2)) void k_admm_xtu_bf16s_lds(
     const __bf16 *__restrict__ A, int64_t lda, const __bf16 *__restrict__ Din, __bf16 *__restrict__ Dout,
     int64_t kdim, const float *W32, float *W32out, float *__restrict__ beta32, float *__restrict__ V32,
     float *__restrict__ B32, const float *__restrict__ Za32, const float *__restrict__ Wa32,
@@ -1424,6 +1427,9 @@ __global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16s_lds(
     constexpr int PN = L::TN / NP;
     float *buf = reinterpret_cast<float *>(smem);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // estimate sums per 128-row part of the tile (one part for tiles up to 128 rows)
+    constexpr int NH = L::TM > 128 ? L::TM / 128 : 1, HP = E::H / NH;
+    const int64_t ntile = (int64_t)gridDim.x * NH;
     for (int pass = 0; pass < NP; ++pass) {
         const int c0 = pass * PN;
         __syncthreads();
@@ -1431,7 +1437,7 @@ __global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16s_lds(
         __syncthreads();
         for (int t = 0; t < PN / 4; ++t) {
             const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
-            double e[5] = {0, 0, 0, 0, 0};
+            double e[NH][5] = {};
             if (MODE == 2) {
                 EpiIn<double> ei[E::H];
                 double za[E::H], wa[E::H];
@@ -1452,7 +1458,7 @@ __global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16s_lds(
                                                           beta64, V64, B64, q64, store_b, est, ga, ev);
                     Dout[o] = (__bf16)(float)(wn - wa[h]);
 #pragma unroll
-                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
+                    for (int u = 0; u < 5; ++u) e[h / HP][u] += ev[u];
                 }
             } else {
                 EpiIn<float> ei[E::H];
@@ -1474,13 +1480,17 @@ __global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16s_lds(
                                                         V32, B32, q32, store_b, est, ga, ev);
                     Dout[o] = (__bf16)(wn - wa[h]);
 #pragma unroll
-                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
+                    for (int u = 0; u < 5; ++u) e[h / HP][u] += ev[u];
                 }
             }
             if (est) {
-                wave_sum5(e);
-                if (lane == 0 && slot >= 0)
-                    for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
+#pragma unroll
+                for (int hh = 0; hh < NH; ++hh) {
+                    wave_sum5(e[hh]);
+                    if (lane == 0 && slot >= 0)
+                        for (int u = 0; u < 5; ++u)
+                            gpart[((int64_t)slot * ntile + (int64_t)blockIdx.x * NH + hh) * 5 + u] = e[hh][u];
+                }
             }
         }
     }
@@ -3133,6 +3143,11 @@ void launch_xtu_bf16s(int v, l0l2_ctx *ctx, int mode, int64_t Kp, int store_b, d
     if (v == 1) {
         if (mode == 2) L0L2_XTUS(2, 2, 2);
         else L0L2_XTUS(2, 2, 1);
+    } else if (ctx->bf16_rows == 256 && in.pp % 256 == 0) {
+        // 256 x 128 tile: the grid's rows halve (the estimate stays per 128 rows)
+        g.x = (unsigned)(in.pp / 256);
+        if (mode == 2) L0L2_XTUS(8, 4, 2);
+        else L0L2_XTUS(8, 4, 1);
     } else {
         if (mode == 2) L0L2_XTUS(4, 4, 2);
         else L0L2_XTUS(4, 4, 1);

@@ -490,6 +490,17 @@ int l0l2_set_bf16_terms(l0l2_ctx *ctx, int terms) {
     });
 }
 
+int l0l2_set_bf16_tile_rows(l0l2_ctx *ctx, int rows) {
+    return guarded(ctx, [&] {
+        if (rows != 128 && rows != 256) l0l2::fail(L0L2_E_INVALID, "rows is 128 or 256");
+        if (ctx->bf16_rows != rows) {
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            l0l2::drop_graphs(ctx);
+        }
+        ctx->bf16_rows = rows;
+    });
+}
+
 int l0l2_bupdate_form(l0l2_ctx *ctx, int *form, double *ms_folded, double *ms_gram) {
     return guarded(ctx, [&] {
         need_data(ctx);

@@ -244,6 +244,7 @@ struct l0l2_ctx {
     int force_xw = -1, force_xtu = -1;   // fixed tile shapes (-1: autotune)
     int bform = 0;                       // b-update form: 0 auto, 1 folded operand (two contractions), 2 Gram
     int bf16_terms = 1;                  // BF16 Gram sweeps: 1 single-term anchored blocks, 3 split every sweep
+    int bf16_rows = 128;                 // rows of the single-term sweep's largest LDS-staged tile (128 or 256)
     bool use_graphs = true;              // replay captured blocks of sweeps
     std::string noalloc_err;             // why the allocation-free scratch is unavailable (empty: it is)
     std::atomic<int> cancel{0};          // set by l0l2_cancel (any thread), taken by the next block boundary

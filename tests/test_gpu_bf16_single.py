@@ -46,13 +46,14 @@ def random_nodes(p, K, seed, base_beta, base_v):
     return codes, beta, v
 
 
-def solve(inst, terms, shape, codes, beta0, v0, tol, check_every, profile=False):
+def solve(inst, terms, shape, codes, beta0, v0, tol, check_every, profile=False, rows=128):
     from paper_2602_04551_amd.binding import Context
     ctx = Context(0)
     ctx.set_data(inst.X, inst.y, inst.lambda0, inst.lambda2, inst.M, precision="bf16")
     ctx.set_bupdate_form("gram")
     ctx.set_tiles(shape, shape)
     ctx.set_bf16_terms(terms)
+    ctx.set_bf16_tile_rows(rows)
     outs = []
     for prof in ((False, True) if profile else (False,)):
         ctx.profile_enable(prof)
@@ -99,6 +100,37 @@ def test_single_term_blocks_at_the_node_tolerance_and_graph_replay(torch_cuda, c
         assert graph["lb"][k] <= ref["primal"] + 1e-12
 
 
+@pytest.fixture(scope="module")
+def p512(orc):
+    """n = 400, p = 500: padded p = 512, a multiple of the 256-row tile."""
+    inst = datagen.make_instance(400, 500, rho=0.4, k=8, snr=4.0, seed=21, lambda0=0.01, lambda2=0.01)
+    o = orc.Oracle.from_instance(inst)
+    root = o.node_admm(None, tol=1e-7, max_iter=20000)
+    return inst, o, root
+
+
+@pytest.mark.parametrize("check_every", [10, 7])
+def test_wide_tile_matches_the_128_row_tile_and_the_oracle(torch_cuda, p512, check_every):
+    """The 256 x 128 single-term tile against the 128 x 128 one (the same
+    contraction in another order) and against the oracle, through both phases
+    to a 1e-9 gap; graph replay and eager issue give identical bits."""
+    inst, o, root = p512
+    K = 256
+    codes, beta0, v0 = random_nodes(inst.p, K, 5, root["beta"], root["v"])
+    wide, wide_eager = solve(inst, 1, 2, codes, beta0, v0, 1e-9, check_every, profile=True, rows=256)
+    narrow = solve(inst, 1, 2, codes, beta0, v0, 1e-9, check_every, rows=128)[0]
+    for k in ("lb", "primal", "iters", "status", "beta", "v"):
+        assert np.array_equal(wide[k], wide_eager[k]), k
+    for r in (wide, narrow):
+        assert (r["status"] == 0).all()
+        assert np.all(r["lb"] <= r["primal"])
+    pr = np.abs(narrow["primal"])
+    assert np.max(np.abs(wide["lb"] - narrow["lb"]) / pr) < 2e-8
+    for k in range(0, K, 32):
+        ref = o.node_admm(codes[k], beta0[k], v0[k], tol=1e-9, max_iter=6000, check_every=check_every)
+        assert abs(wide["lb"][k] - ref["lb"]) <= 1e-8 * abs(ref["primal"]), k
+
+
 def test_terms_switch_rejects_other_values(torch_cuda, c1):
     from paper_2602_04551_amd.binding import Context, L0L2Error
     inst, _, _ = c1
@@ -107,4 +139,7 @@ def test_terms_switch_rejects_other_values(torch_cuda, c1):
     for bad in (0, 2, 4):
         with pytest.raises(L0L2Error):
             ctx.set_bf16_terms(bad)
+    for bad in (0, 64, 512):
+        with pytest.raises(L0L2Error):
+            ctx.set_bf16_tile_rows(bad)
     ctx.close()
