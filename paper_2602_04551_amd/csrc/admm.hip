@@ -1435,53 +1435,55 @@ __global__ __launch_bounds__(256, (WM > 4 ? 1 : 2)) void k_admm_xtu_bf16s_lds(
         __syncthreads();
         acc_stage<float, WM, WN>(acc, buf, c0, PN);
         __syncthreads();
-        for (int t = 0; t < PN / 4; ++t) {
-            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
+        // the node-state operands of the next D rows are in flight while a row
+        // is updated (a ring of D rows), so their latency overlaps that work
+        constexpr int T = PN / 4, D = 2;
+        static_assert(T % D == 0, "rows per wave in groups of D");
+        typedef typename std::conditional<MODE == 2, double, float>::type ST;
+        struct Row {
+            EpiIn<ST> ei[E::H];
+            ST za[E::H], wa[E::H];
+            int slot;
+        };
+        auto load_row = [&](Row &R, int t) {
+            const int nl = c0 + w + 4 * t;
+            R.slot = col_slot(ncl, n0 + nl);
+            if constexpr (MODE == 2)
+                epi_load_row<double, E::H>(R.ei, R.slot, n0 + nl, m0, ldp, W64, V64, codes, c64, active);
+            else
+                epi_load_row<float, E::H>(R.ei, R.slot, n0 + nl, m0, ldp, W32, V32, codes, c32, active);
+#pragma unroll
+            for (int h = 0; h < E::H; ++h) {
+                const int64_t o = col_row(R.slot, n0 + nl) * ldp + m0 + lane + 64 * h;
+                if constexpr (MODE == 2) {
+                    R.za[h] = Za[o];
+                    R.wa[h] = Wa[o];
+                } else {
+                    R.za[h] = Za32[o];
+                    R.wa[h] = Wa32[o];
+                }
+            }
+        };
+        auto update_row = [&](const Row &R, int t) {
+            const int nl = c0 + w + 4 * t, slot = R.slot;
             double e[NH][5] = {};
-            if (MODE == 2) {
-                EpiIn<double> ei[E::H];
-                double za[E::H], wa[E::H];
-                epi_load_row<double, E::H>(ei, slot, n0 + nl, m0, ldp, W64, V64, codes, c64, active);
 #pragma unroll
-                for (int h = 0; h < E::H; ++h) {
-                    const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
-                    za[h] = Za[o];
-                    wa[h] = Wa[o];
+            for (int h = 0; h < E::H; ++h) {
+                if (!R.ei[h].on) continue;
+                const int m = lane + 64 * h;
+                const int64_t o = (int64_t)slot * ldp + m0 + m;
+                double ev[5] = {0, 0, 0, 0, 0};
+                if constexpr (MODE == 2) {
+                    const double wn = admm_update<double>(R.za[h] + (double)buf[(nl - c0) * E::LD + m], R.ei[h], o,
+                                                          W64, beta64, V64, B64, q64, store_b, est, ga, ev);
+                    Dout[o] = (__bf16)(float)(wn - R.wa[h]);
+                } else {
+                    const float wn = admm_update<float>(R.za[h] + buf[(nl - c0) * E::LD + m], R.ei[h], o, W32out,
+                                                        beta32, V32, B32, q32, store_b, est, ga, ev);
+                    Dout[o] = (__bf16)(wn - R.wa[h]);
                 }
 #pragma unroll
-                for (int h = 0; h < E::H; ++h) {
-                    if (!ei[h].on) continue;
-                    const int m = lane + 64 * h;
-                    const int64_t o = (int64_t)slot * ldp + m0 + m;
-                    double ev[5] = {0, 0, 0, 0, 0};
-                    const double wn = admm_update<double>(za[h] + (double)buf[(nl - c0) * E::LD + m], ei[h], o, W64,
-                                                          beta64, V64, B64, q64, store_b, est, ga, ev);
-                    Dout[o] = (__bf16)(float)(wn - wa[h]);
-#pragma unroll
-                    for (int u = 0; u < 5; ++u) e[h / HP][u] += ev[u];
-                }
-            } else {
-                EpiIn<float> ei[E::H];
-                float za[E::H], wa[E::H];
-                epi_load_row<float, E::H>(ei, slot, n0 + nl, m0, ldp, W32, V32, codes, c32, active);
-#pragma unroll
-                for (int h = 0; h < E::H; ++h) {
-                    const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
-                    za[h] = Za32[o];
-                    wa[h] = Wa32[o];
-                }
-#pragma unroll
-                for (int h = 0; h < E::H; ++h) {
-                    if (!ei[h].on) continue;
-                    const int m = lane + 64 * h;
-                    const int64_t o = (int64_t)slot * ldp + m0 + m;
-                    double ev[5] = {0, 0, 0, 0, 0};
-                    const float wn = admm_update<float>(za[h] + buf[(nl - c0) * E::LD + m], ei[h], o, W32out, beta32,
-                                                        V32, B32, q32, store_b, est, ga, ev);
-                    Dout[o] = (__bf16)(wn - wa[h]);
-#pragma unroll
-                    for (int u = 0; u < 5; ++u) e[h / HP][u] += ev[u];
-                }
+                for (int u = 0; u < 5; ++u) e[h / HP][u] += ev[u];
             }
             if (est) {
 #pragma unroll
@@ -1491,6 +1493,16 @@ __global__ __launch_bounds__(256, (WM > 4 ? 1 : 2)) void k_admm_xtu_bf16s_lds(
                         for (int u = 0; u < 5; ++u)
                             gpart[((int64_t)slot * ntile + (int64_t)blockIdx.x * NH + hh) * 5 + u] = e[hh][u];
                 }
+            }
+        };
+        Row ring[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) load_row(ring[d], d);
+        for (int t = 0; t < T; t += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                update_row(ring[d], t + d);
+                if (t + d + D < T) load_row(ring[d], t + d + D);
             }
         }
     }
