@@ -775,6 +775,22 @@ __device__ __forceinline__ void epi_load_row(EpiIn<T> (&ei)[H], int slot, int64_
     for (int h = 0; h < H; ++h) epi_load<T>(ei[h], slot, col, m0 + lane + 64 * h, ldp, W, V, codes, c, active);
 }
 
+// The node rows of a wave's epilogue pass, t = 0 .. T - 1 (T even): the
+// operands of row t + 1 are loaded (load(row, t + 1)) before row t is updated
+// (update(row, t)), so their latency overlaps that row's work instead of being
+// paid row by row.
+template <class Row, class Load, class Update>
+__device__ __forceinline__ void rows_pipelined(int T, Load &&load, Update &&update) {
+    Row ra, rb;
+    load(ra, 0);
+    for (int t = 0; t < T; t += 2) {
+        load(rb, t + 1);
+        update(ra, t);
+        if (t + 2 < T) load(ra, t + 2);
+        update(rb, t + 1);
+    }
+}
+
 // Contraction over p (U = Xh W^T) with an LDS-staged tile.  With gridDim.z = S
 // > 1 the contraction range is cut into S equal slices (kdim / S a multiple of
 // 16) and slice z writes its partial product to U + z pstride; k_splitk_sum adds
@@ -1235,58 +1251,61 @@ __global__ __launch_bounds__(256, 2) void k_admm_xtu_bf16_lds(
         __syncthreads();
         acc_stage<float, WM, WN>(acc, buf, c0, PN);
         __syncthreads();
-        for (int t = 0; t < PN / 4; ++t) {
-            const int nl = c0 + w + 4 * t, slot = col_slot(ncl, n0 + nl);
-            double e[5] = {0, 0, 0, 0, 0};
-            if (ANCH == 1) {
-                EpiIn<double> ei[E::H];
-                double za[E::H], wa[E::H];
-                epi_load_row<double, E::H>(ei, slot, n0 + nl, m0, ldp, W64, V64, codes, c64, active);
+        typedef typename std::conditional<ANCH == 1, double, float>::type ST;
+        struct Row {
+            EpiIn<ST> ei[E::H];
+            double za[ANCH == 1 ? E::H : 1], wa[ANCH == 1 ? E::H : 1];
+            int slot;
+        };
+        auto load = [&](Row &R, int t) {
+            const int nl = c0 + w + 4 * t;
+            R.slot = col_slot(ncl, n0 + nl);
+            if constexpr (ANCH == 1) {
+                epi_load_row<double, E::H>(R.ei, R.slot, n0 + nl, m0, ldp, W64, V64, codes, c64, active);
 #pragma unroll
                 for (int h = 0; h < E::H; ++h) {
-                    const int64_t o = col_row(slot, n0 + nl) * ldp + m0 + lane + 64 * h;
-                    za[h] = Za[o];
-                    wa[h] = Wa[o];
-                }
-#pragma unroll
-                for (int h = 0; h < E::H; ++h) {
-                    if (!ei[h].on) continue;
-                    const int m = lane + 64 * h;
-                    const int64_t o = (int64_t)slot * ldp + m0 + m;
-                    double ev[5] = {0, 0, 0, 0, 0};
-                    const double wn = admm_update<double>(za[h] + (double)buf[(nl - c0) * E::LD + m], ei[h], o, W64,
-                                                          beta64, V64, B64, q64, store_b, est, ga, ev);
-                    W32out[o] = (float)(wn - wa[h]);
-#pragma unroll
-                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
+                    const int64_t o = col_row(R.slot, n0 + nl) * ldp + m0 + lane + 64 * h;
+                    R.za[h] = Za[o];
+                    R.wa[h] = Wa[o];
                 }
             } else {
-                EpiIn<float> ei[E::H];
-                epi_load_row<float, E::H>(ei, slot, n0 + nl, m0, ldp, W32, V32, codes, c32, active);
+                epi_load_row<float, E::H>(R.ei, R.slot, n0 + nl, m0, ldp, W32, V32, codes, c32, active);
+            }
+        };
+        auto update = [&](const Row &R, int t) {
+            const int nl = c0 + w + 4 * t, slot = R.slot;
+            double e[5] = {0, 0, 0, 0, 0};
 #pragma unroll
-                for (int h = 0; h < E::H; ++h) {
-                    if (!ei[h].on) continue;
-                    const int m = lane + 64 * h;
-                    const int64_t o = (int64_t)slot * ldp + m0 + m;
-                    double ev[5] = {0, 0, 0, 0, 0};
+            for (int h = 0; h < E::H; ++h) {
+                if (!R.ei[h].on) continue;
+                const int m = lane + 64 * h;
+                const int64_t o = (int64_t)slot * ldp + m0 + m;
+                double ev[5] = {0, 0, 0, 0, 0};
+                if constexpr (ANCH == 1) {
+                    const double wn = admm_update<double>(R.za[h] + (double)buf[(nl - c0) * E::LD + m], R.ei[h], o,
+                                                          W64, beta64, V64, B64, q64, store_b, est, ga, ev);
+                    W32out[o] = (float)(wn - R.wa[h]);
+                } else {
                     const float qv = buf[(nl - c0) * E::LD + m];
-                    const float wn = admm_update<float>(qv, ei[h], o, W32out, beta32, V32, B32, q32, store_b, est,
+                    const float wn = admm_update<float>(qv, R.ei[h], o, W32out, beta32, V32, B32, q32, store_b, est,
                                                         ga, ev);
                     if (ANCH == 2) {
                         Za32[o] = qv;
-                        Wa32[o] = ei[h].w;
-                        Dout[o] = (__bf16)(wn - ei[h].w);
+                        Wa32[o] = R.ei[h].w;
+                        Dout[o] = (__bf16)(wn - R.ei[h].w);
                     }
-#pragma unroll
-                    for (int u = 0; u < 5; ++u) e[u] += ev[u];
                 }
+#pragma unroll
+                for (int u = 0; u < 5; ++u) e[u] += ev[u];
             }
             if (est) {
                 wave_sum5(e);
                 if (lane == 0 && slot >= 0)
                     for (int u = 0; u < 5; ++u) gpart[((int64_t)slot * gridDim.x + blockIdx.x) * 5 + u] = e[u];
             }
-        }
+        };
+        static_assert((PN / 4) % 2 == 0, "rows per wave in pairs");
+        rows_pipelined<Row>(PN / 4, load, update);
     }
 }
 
@@ -1435,10 +1454,6 @@ __global__ __launch_bounds__(256, (WM > 4 ? 1 : 2)) void k_admm_xtu_bf16s_lds(
         __syncthreads();
         acc_stage<float, WM, WN>(acc, buf, c0, PN);
         __syncthreads();
-        // the node-state operands of the next D rows are in flight while a row
-        // is updated (a ring of D rows), so their latency overlaps that work
-        constexpr int T = PN / 4, D = 2;
-        static_assert(T % D == 0, "rows per wave in groups of D");
         typedef typename std::conditional<MODE == 2, double, float>::type ST;
         struct Row {
             EpiIn<ST> ei[E::H];
@@ -1495,16 +1510,8 @@ __global__ __launch_bounds__(256, (WM > 4 ? 1 : 2)) void k_admm_xtu_bf16s_lds(
                 }
             }
         };
-        Row ring[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) load_row(ring[d], d);
-        for (int t = 0; t < T; t += D) {
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                update_row(ring[d], t + d);
-                if (t + d + D < T) load_row(ring[d], t + d + D);
-            }
-        }
+        static_assert((PN / 4) % 2 == 0, "rows per wave in pairs");
+        rows_pipelined<Row>(PN / 4, load_row, update_row);
     }
 }
 
