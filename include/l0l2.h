@@ -336,10 +336,12 @@ typedef struct {
 
 /* Create a server on `device`.  hbm_budget_bytes bounds the summed footprints
  * of the instances running at once (0 = 80% of the free device memory now);
- * at most max_concurrent instances run at once, each on its own context and
- * HIP stream.  opts (copied; its trace buffer is ignored) applies to every
- * request.  Requests are admitted in arrival order as workers and budget free
- * up ("continuous batching": arrivals join while others are on the GPU). */
+ * at most max_concurrent instances run at once, each with its own context and
+ * HIP stream for its branch and bound, their blocks of ADMM sweeps batched
+ * into shared launches by the server's executor (l0l2_server_set_batching).
+ * opts (copied; its trace buffer is ignored) applies to every request.
+ * Requests are admitted in arrival order as workers and budget free up
+ * (arrivals join while others are on the GPU). */
 int l0l2_server_create(int device, size_t hbm_budget_bytes, int max_concurrent, const l0l2_bnb_opts *opts,
                        l0l2_server **out);
 /* Queue one instance (host X column-major n x p, host y; copied before return).
