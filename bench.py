@@ -734,6 +734,30 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_bandwidth(nbytes=2 << 30, reps=5):
+    """Device-to-device copy rate measured here (read + write bytes per second,
+    best of `reps`), beside the 8 TB/s published HBM peak the rooflines use."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * nbytes / best / 1e9
+    return {"GB_per_s": round(gbs, 1), "fraction_of_8000": round(gbs / 8000.0, 3),
+            "what": f"{nbytes >> 20} MiB device copy, read plus write bytes over the best of {reps} event-timed copies"}
+
+
 def main():
     args = parse()
     if args.traffic_summary:
@@ -789,7 +813,10 @@ def main():
            "kernels": kernels,
            "batch_detail": batch_detail(mixed),
            "set_data_s": {"bf16": round(mixed.set_data_s, 4)}}
+    held, peak = mixed.ctx.memory_stats()
+    out["hbm_high_water_gb"] = {"bf16": round(peak / 1e9, 3)}
     mixed.close()
+    out["hbm_copy_measured"] = copy_bandwidth()
     print(json.dumps({"bf16": out["value"]}), file=sys.stderr, flush=True)
     if not args.only_mixed:
         for prec, steps_o in (("fp32", max(2, args.steps // 2)), ("fp64", max(2, args.steps // 4))):
@@ -801,6 +828,7 @@ def main():
                                    "roofline": roof_o, "kernels": kernels_o, "batch_detail": batch_detail(path),
                                    "b_update": b_update_info(path.ctx)}
             out["set_data_s"][prec] = round(path.set_data_s, 4)
+            out["hbm_high_water_gb"][prec] = round(path.ctx.memory_stats()[1] / 1e9, 3)
             path.close()
             print(json.dumps({prec: out[prec + "_path"]["value"]}), file=sys.stderr, flush=True)
         out["mixed_vs_fp64"] = round(out["value"] / out["fp64_path"]["value"], 3)
@@ -836,10 +864,19 @@ def main():
                                               "status": rh["status"],
                                               "same_support": [int(s) for s in rh["support"]] == tt[prec]["support"]}
             ctx.close()
+        gold = os.path.join(ROOT, "tests", "golden", "fullsize_c2_bnb.json")
+        oracle_ttco = None
+        if os.path.exists(gold):
+            with open(gold) as f:
+                g = json.load(f)
+            oracle_ttco = {"seconds": g.get("cpu_seconds"), "nodes": g.get("nodes_solved"),
+                           "what": "the single-threaded CPU oracle's depth-first branch and bound (K = 1) to "
+                                   "certification on the same instance, timed when it wrote "
+                                   "tests/golden/fullsize_c2_bnb.json (another host), same certified support"}
         out["ttco_n1000"] = {"workload": "n=p=1000 Toeplitz rho=0.5 k=10 SNR=5 lambda0=0.005 lambda2=0.01, "
                                          "best-first branch and bound with batches of 256 to certification "
                                          "(gap 0, eps_prune 2e-6), after one untimed solve",
-                             "runs": tt,
+                             "runs": tt, "oracle_cpu": oracle_ttco,
                              "mixed_vs_fp64": round(tt["fp64"]["seconds"] / tt["bf16"]["seconds"], 3)}
         print(json.dumps({"ttco": {k: v["seconds"] for k, v in tt.items()}}), file=sys.stderr, flush=True)
     if not args.no_highdim:
