@@ -4213,8 +4213,9 @@ void decide_form(l0l2_ctx *ctx, int64_t Kp) {
 // form) while the batch converges, then anchored sweeps (FP64 state, the
 // reduced products act on the movement since each block's FP64 anchor) from the
 // FP32 iterates.  The plain reduced sweeps stop for the batch once every active
-// node's gap is below switch_tol (50 tol_node for FP32, 200 tol_node for BF16:
-// the measured floors are about 1e-6..5e-6 and 1e-4), or the number of nodes
+// node's gap is below switch_tol (50 tol_node for FP32 and the BF16 single-term
+// blocks, 200 tol_node for the BF16 split form: the measured floors are about
+// 1e-6..5e-6 and 1e-4), or the number of nodes
 // above it has not dropped for 5 checks, or half the sweep budget is spent.
 // FP8 storage has no plain phase (its floor is far above any useful gap): its
 // sweeps are anchored from the start.  Bounds are FP64 throughout; the final
@@ -4228,7 +4229,9 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     init_batch<float>(ctx, s32, K, Kp);
     const int m = std::max(1, o.check_every);
     const bool bf16 = in.prec == L0L2_BF16;
-    const double switch_tol = (bf16 ? 200.0 : 50.0) * o.tol_node;
+    // the BF16 split form's floor is about 1e-4; single-term blocks are anchored
+    // on the FP32 state, whose floor is the FP32 one
+    const double switch_tol = (bf16 && !bf16_single(ctx, Kp) ? 200.0 : 50.0) * o.tol_node;
     bool fp64 = false;
     if (in.prec == L0L2_FP8) {
         // FP8 storage: anchored sweeps from the start, on the FP64 state
