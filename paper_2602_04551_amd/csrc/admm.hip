@@ -4242,9 +4242,14 @@ void solve_mixed(l0l2_ctx *ctx, int K, const l0l2_admm_opts &o) {
     }
     int cnt[3], best_above = 1 << 30, flat = 0;
     int64_t active = K;
+    // single-term blocks before the switch run two check intervals per block:
+    // their gap sits above the FP32 floor, so the checks mostly steer the
+    // switch, and each block's first sweep is the split-form one that renews
+    // the anchor
+    const bool long_blocks = bf16 && bf16_single(ctx, Kp);
     for (int t = 0; t < o.max_iter;) {
         check_cancel(ctx);
-        const int n = std::min(m, o.max_iter - t);
+        const int n = std::min(!fp64 && long_blocks ? 2 * m : m, o.max_iter - t);
         const int kind = fp64 ? SK_ANCH : (bf16 ? SK_BF16 : SK_F32);
         run_block(ctx, kind, Kp, n, o.tol_node, switch_tol, active, t + n >= o.max_iter, cnt);
         t += n;
