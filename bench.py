@@ -65,6 +65,10 @@ def parse():
     ap.add_argument("--serve-solo", type=int, default=4, help="draws timed alone to set the arrival rate")
     ap.add_argument("--serve-interarrival", type=float, default=0.0, help="mean inter-arrival time (0: measured)")
     ap.add_argument("--serve-batching", choices=["on", "off", "both"], default="on")
+    ap.add_argument("--serve-oracle", action="store_true",
+                    help="CPU oracle time to certify the smallest draws of the serving stream (no GPU)")
+    ap.add_argument("--serve-oracle-count", type=int, default=8)
+    ap.add_argument("--serve-oracle-nodes", type=int, default=20000, help="node cap of each oracle run")
     ap.add_argument("--highdim", action="store_true",
                     help="n = 1000, p = 50000 node batches of 256 and 1024: FP8, BF16, FP32 vs FP64")
     ap.add_argument("--node-parallel", action="store_true",
@@ -333,8 +337,10 @@ def traffic_summary(fetch_csv, write_csv, workload, last=50, families=None):
     out = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = load(path, counter)
+        # the calibration copy is the first copy dispatched (later copies, such as
+        # the measured copy rate's, move other amounts)
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        ref = max(copies) * 1024.0 if copies else None
+        ref = copies[0] * 1024.0 if copies else None
         scale = (256.0 * 2 ** 20) / ref if ref else 1.0
         for fam, pats in FAMILIES.items():
             if families and fam not in families:
@@ -734,6 +740,37 @@ def serve_main(args):
     print(json.dumps(out), flush=True)
 
 
+def _serve_oracle_one(args):
+    import oracle
+    i, inst, max_nodes = args
+    t0 = time.perf_counter()
+    r = oracle.Oracle.from_instance(inst).bnb(tol_node=1e-6, max_iter=2000, max_iter_root=10000,
+                                               max_nodes=max_nodes, trace_cap=0)
+    return {"draw": i, "n": inst.n, "p": inst.p, "seconds": round(time.perf_counter() - t0, 2),
+            "status": int(r["status"]), "nodes": int(r["nodes_solved"]), "certified": r["certified"],
+            "support": [int(j) for j in r["support"]]}
+
+
+def serve_oracle_main(args):
+    """CPU baseline of the serving stream: the single-threaded oracle's branch
+    and bound on the smallest draws (by n p) of the 64-instance stream, one
+    process per instance, with a node cap (a capped run is censored)."""
+    import multiprocessing as mp
+    from paper_2602_04551_amd import datagen
+    rng = np.random.default_rng(0)
+    small = []
+    for i in range(args.serve_requests):
+        inst = datagen.serving_instance(rng, seed=1000 + i)
+        small = sorted(small + [(i, inst)], key=lambda d: d[1].n * d[1].p)[:args.serve_oracle_count]
+    workers = max(1, min(len(small), os.cpu_count() or 1, 16))
+    with mp.get_context("fork").Pool(workers) as pool:
+        rows = pool.map(_serve_oracle_one, [(i, inst, args.serve_oracle_nodes) for i, inst in small])
+    out = {"metric": "CPU oracle time to certified optimum, smallest draws of the serving stream",
+           "config": {"draws": args.serve_requests, "smallest": len(small), "node_cap": args.serve_oracle_nodes,
+                      "workers": workers, "cpu_model": cpu_model()}, "runs": rows}
+    print(json.dumps(out), flush=True)
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=5):
     """Device-to-device copy rate measured here (read + write bytes per second,
     best of `reps`), beside the 8 TB/s published HBM peak the rooflines use."""
@@ -777,6 +814,8 @@ def main():
         return node_parallel_main(args)
     if args.heuristic_study:
         return heuristic_main(args)
+    if args.serve_oracle:
+        return serve_oracle_main(args)
     import torch
     from paper_2602_04551_amd import datagen
 
