@@ -2328,6 +2328,7 @@ struct GateFin {
     double yy, tol;
     int64_t K, ntile;
     int budget;   // > 0: nodes at their sweep budget go to the exact check whatever the estimate
+    int skip;     // 1: no node goes to the exact check (the estimate alone steers the switch)
 };
 
 // Gap estimate per node (one wave each) from the per-tile sums of the last
@@ -2354,7 +2355,7 @@ __global__ __launch_bounds__(256) void k_gate(const double *__restrict__ gpart, 
         const double D = -0.5 * rr + (gf.yy - e[0]) - e[2];
         const double Pl = 0.5 * rr - e[3] + e[4];
         const bool spent = gf.budget > 0 && *sweep_no - start[k] >= gf.budget;
-        const bool far = !spent && Pl > 0.0 && (Pl - D) > 2.0 * gf.tol * Pl;
+        const bool far = !spent && (gf.skip || (Pl > 0.0 && (Pl - D) > 2.0 * gf.tol * Pl));
         needs[k] = far ? 0 : 1;
         gest[k] = Pl > 0.0 ? (Pl - D) / Pl : INFINITY;
         if (!far) clist[atomicAdd(&gate[0], 1)] = (int)k;
@@ -3585,7 +3586,10 @@ void block_end(l0l2_ctx *ctx, int kind, const BlockPlan &bp, int64_t Kp, int n, 
             rows = kBfTM[tile_choice_bf16(ctx, cols).xtu];
         else if (kind == SK_ANCH && in.prec == L0L2_FP8) rows = kF8TM[tile_choice_fp8(ctx, cols).xtu];
         else rows = kTileTM[tile_choice<float>(ctx, sweep32(ctx), cols).xtu];
-        GateFin gf{in.yy, tol, Kp, in.pp / rows, budget};
+        // single-term blocks before the switch: their gaps sit above the FP32
+        // floor, so an exact check there would almost never retire a node
+        const int skip = kind == SK_BF16 && bf16_single(ctx, cols) ? 1 : 0;
+        GateFin gf{in.yy, tol, Kp, in.pp / rows, budget, skip};
         prof_begin(ctx, PROF_CHECK);
         hipLaunchKernelGGL(k_gate, dim3((unsigned)((Kp + 3) / 4)), dim3(256), 0, s, ws.gpart.as<double>(),
                            ws.active.as<int>(), ws.needs.as<int>(), ws.gest.as<double>(), ws.clist.as<int>(),
