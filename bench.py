@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--serve-oracle", action="store_true",
                     help="CPU oracle time to certify the smallest draws of the serving stream (no GPU)")
     ap.add_argument("--serve-oracle-count", type=int, default=8)
-    ap.add_argument("--serve-oracle-nodes", type=int, default=20000, help="node cap of each oracle run")
+    ap.add_argument("--serve-oracle-nodes", type=int, default=2000, help="node cap of each oracle run")
     ap.add_argument("--highdim", action="store_true",
                     help="n = 1000, p = 50000 node batches of 256 and 1024: FP8, BF16, FP32 vs FP64")
     ap.add_argument("--node-parallel", action="store_true",
@@ -763,8 +763,12 @@ def serve_oracle_main(args):
         inst = datagen.serving_instance(rng, seed=1000 + i)
         small = sorted(small + [(i, inst)], key=lambda d: d[1].n * d[1].p)[:args.serve_oracle_count]
     workers = max(1, min(len(small), os.cpu_count() or 1, 16))
+    rows = []
     with mp.get_context("fork").Pool(workers) as pool:
-        rows = pool.map(_serve_oracle_one, [(i, inst, args.serve_oracle_nodes) for i, inst in small])
+        for row in pool.imap_unordered(_serve_oracle_one, [(i, inst, args.serve_oracle_nodes) for i, inst in small]):
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    rows.sort(key=lambda r: r["draw"])
     out = {"metric": "CPU oracle time to certified optimum, smallest draws of the serving stream",
            "config": {"draws": args.serve_requests, "smallest": len(small), "node_cap": args.serve_oracle_nodes,
                       "workers": workers, "cpu_model": cpu_model()}, "runs": rows}
