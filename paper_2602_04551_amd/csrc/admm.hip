@@ -2110,32 +2110,36 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // First kernel of the gap check: with the original X (row-major copy, FP64)
 // and the node iterates b (grid z = 0) and beta (z = 1) of type T, forms the
-// 32 x 16 BN tile of X b^T (X beta^T) for the nodes of the check list and, in
-// the epilogue, r = y - X b (stored in R) with the per-(node, row tile) sums of
-// ||r||^2, y^T r, |y|^T |r| (z = 0) or ||y - X beta||^2 (z = 1) in
-// rpart[(node * ntr + tile) * 4 + {0, 1, 2 | 3}].  BN = 4 (64 nodes per
-// workgroup) reads each X panel half as often as BN = 2, for large batches.
-template <class T, int BN>
-__global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR, int64_t ldx,
-                                                  const T *__restrict__ B, const T *__restrict__ beta, int64_t ldb,
-                                                  int64_t kdim, const double *__restrict__ y, double *__restrict__ R,
-                                                  int64_t ldr, double *__restrict__ rpart, NodeCols ncl) {
-    constexpr int WAVES = 8, TN = 16 * BN;
-    __shared__ double red[WAVES * Red<32, TN>::WS];
+// 16 BM x 16 BN tile of X b^T (X beta^T) for the nodes of the check list and,
+// in the epilogue, r = y - X b (stored in R) with the per-(node, 32-row tile)
+// sums of ||r||^2, y^T r, |y|^T |r| (z = 0) or ||y - X beta||^2 (z = 1) in
+// rpart[(node * ntr + tile) * 4 + {0, 1, 2 | 3}], ntr = rows / 32.  Wider node
+// tiles read each X panel fewer times, for large batches.
+template <class T, int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_check_xr(const double *__restrict__ XR, int64_t ldx,
+                                                         const T *__restrict__ B, const T *__restrict__ beta,
+                                                         int64_t ldb, int64_t kdim, const double *__restrict__ y,
+                                                         double *__restrict__ R, int64_t ldr,
+                                                         double *__restrict__ rpart, NodeCols ncl) {
+    constexpr int TM = 16 * BM, TN = 16 * BN;
+    static_assert(TM == 32 || TM == 64, "row tiles of 32 or 64");
+    __shared__ double red[WAVES * Red<TM, TN>::WS];
     const bool with_b = blockIdx.z == 0;
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * TN;
-    constexpr int E = 32 * TN / (64 * WAVES);
+    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    constexpr int E = TM * TN / (64 * WAVES);
+    static_assert(E * 64 * WAVES == TM * TN, "tile elements per thread");
     int sb[BN], se[E];
-    if (!tile_slots<32, BN, E, WAVES>(ncl, n0, sb, se)) return;
-    nt_tile<double, T, double, 2, BN, WAVES>(XR, ldx, with_b ? B : beta, ldb, kdim, m0, n0, sb, red);
-    const int64_t ntr = gridDim.x;
+    if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
+    nt_tile<double, T, double, BM, BN, WAVES>(XR, ldx, with_b ? B : beta, ldb, kdim, m0, n0, sb, red);
+    const int64_t ntr = (int64_t)gridDim.x * (TM / 32);
 #pragma unroll
     for (int t = 0; t < E; ++t) {
-        const int idx = threadIdx.x + t * 64 * WAVES, n = idx >> 5, m = idx & 31;
+        // 32 consecutive lanes hold 32 rows of one node: one 32-row tile
+        const int idx = threadIdx.x + t * 64 * WAVES, n = idx / TM, m = idx % TM;
         const bool live = se[t] >= 0;
         const int64_t node = se[t], i = m0 + m;
         const double yi = y[i];
-        const double rv = yi - sum_waves<double, 32, TN, WAVES>(red, n, m);
+        const double rv = yi - sum_waves<double, TM, TN, WAVES>(red, n, m);
         double e0, e1 = 0.0, e2 = 0.0;
         if (with_b) {
             if (live) R[node * ldr + i] = rv;
@@ -2150,8 +2154,8 @@ __global__ __launch_bounds__(512) void k_check_xr(const double *__restrict__ XR,
             e1 += __shfl_xor(e1, off);
             e2 += __shfl_xor(e2, off);
         }
-        if (m == 0 && live) {
-            double *d = rpart + (node * ntr + blockIdx.x) * 4;
+        if ((m & 31) == 0 && live) {
+            double *d = rpart + (node * ntr + (i >> 5)) * 4;
             if (with_b) {
                 d[0] = e0;
                 d[1] = e1;
@@ -2170,30 +2174,30 @@ struct DualArgs {
 };
 
 // g = X^T r per (node, coordinate) with the per-tile sums of the upper bounds
-// of nu_i(|g_i|) and of psi_i(beta_i):  part[(k * ntile + tile) * 3 + {0,1,2}] =
-// sum nu+, sum |nu+|, sum psi.
-constexpr int kWavesDual = 8;
-
-template <class T, int BN>
-__global__ __launch_bounds__(64 * kWavesDual) void k_dual_xtr(
+// of nu_i(|g_i|) and of psi_i(beta_i) over 32-coordinate tiles:
+// part[(k * ntile + tile) * 3 + {0,1,2}] = sum nu+, sum |nu+|, sum psi,
+// ntile = padded p / 32.  The output tile is 16 BM coordinates x 16 BN nodes.
+template <class T, int BM, int BN, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_dual_xtr(
     const double *__restrict__ A, int64_t lda, const double *__restrict__ R, int64_t ldr, int64_t kdim,
     const uint8_t *__restrict__ codes, const T *__restrict__ beta, const double *__restrict__ colnrm,
     const double *__restrict__ rpart, int64_t ntr, const int *__restrict__ active, double *__restrict__ part,
     int64_t ldp, DualArgs da, NodeCols ncl) {
-    constexpr int TN = 16 * BN;
-    __shared__ double red[kWavesDual * Red<32, TN>::WS];
+    constexpr int TM = 16 * BM, TN = 16 * BN;
+    __shared__ double red[WAVES * Red<TM, TN>::WS];
     const int tid = threadIdx.x;
-    const int64_t m0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * TN;
-    constexpr int E = 32 * TN / (64 * kWavesDual);
-    // TPN consecutive threads per node (16 for 32 nodes, 8 for 64): thread t
-    // takes node t / TPN and coordinates CPT (t % TPN) ... CPT (t % TPN) + CPT - 1
-    constexpr int TPN = 64 * kWavesDual / TN, CPT = 32 / TPN;
-    static_assert(TPN * CPT == 32 && TPN <= 64, "threads per node");
+    const int64_t m0 = (int64_t)blockIdx.x * TM, n0 = (int64_t)blockIdx.y * TN;
+    constexpr int E = TM * TN / (64 * WAVES);
+    // TPN consecutive threads per node; thread t takes node t / TPN and the CPT
+    // coordinates from CPT (t % TPN), all in one 32-coordinate tile (TPH
+    // threads per tile)
+    constexpr int TPN = 64 * WAVES / TN, CPT = TM / TPN, TPH = TPN / (TM / 32);
+    static_assert(TPN * CPT == TM && TPN <= 64 && TPH >= 1 && CPT <= 32, "threads per node");
     int sb[BN], se[E];
     const int n = tid / TPN, jl = (tid % TPN) * CPT;
     const int slot = col_slot(ncl, n0 + n);
-    if (!tile_slots<32, BN, E, kWavesDual>(ncl, n0, sb, se)) return;
-    nt_tile<double, double, double, 2, BN, kWavesDual>(A, lda, R, ldr, kdim, m0, n0, sb, red);
+    if (!tile_slots<TM, BN, E, WAVES>(ncl, n0, sb, se)) return;
+    nt_tile<double, double, double, BM, BN, WAVES>(A, lda, R, ldr, kdim, m0, n0, sb, red);
     const bool live = slot >= 0;
     const int64_t node = col_row(slot, n0 + n);   // rows read for an idle column are valid and unused
     // ||r||^2 of the node from the row-tile sums of the first check kernel
@@ -2207,7 +2211,7 @@ __global__ __launch_bounds__(64 * kWavesDual) void k_dual_xtr(
         for (int e = 0; e < CPT; ++e) {
             int64_t j = m0 + jl + e;
             if (j >= da.p) continue;
-            double g = sum_waves<double, 32, TN, kWavesDual>(red, n, jl + e);
+            double g = sum_waves<double, TM, TN, WAVES>(red, n, jl + e);
             uint8_t code = codes[node * ldp + j];
             double ej = 2.0 * da.gamma_n * colnrm[j] * nr;
             double val = nu_upper(fabs(g), ej, code, da.l0, da.l2, da.M, da.two_M_l2, da.four_l2, da.l2_M2,
@@ -2217,14 +2221,14 @@ __global__ __launch_bounds__(64 * kWavesDual) void k_dual_xtr(
             spsi += psi_val((double)beta[node * ldp + j], code, da.l0, da.l2, da.s, da.free_quad, da.psi_lin);
         }
     }
-    for (int off = 1; off < TPN; off <<= 1) {
+    for (int off = 1; off < TPH; off <<= 1) {
         snu += __shfl_xor(snu, off);
         sanu += __shfl_xor(sanu, off);
         spsi += __shfl_xor(spsi, off);
     }
-    if (tid % TPN == 0 && act) {
-        int64_t ntile = gridDim.x;
-        double *pp = part + (node * ntile + blockIdx.x) * 3;
+    if (tid % TPH == 0 && act) {
+        const int64_t ntile = (int64_t)gridDim.x * (TM / 32);
+        double *pp = part + (node * ntile + ((m0 + jl) >> 5)) * 3;
         pp[0] = snu;
         pp[1] = sanu;
         pp[2] = spsi;
@@ -3405,29 +3409,29 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     const int64_t ntr = np / 32;
     NodeCols ncl{nullptr};
     if (mode == 0) ncl = gated ? NodeCols{ws.clist.as<int>()} : active_cols(ctx);
-    // 64 nodes per workgroup once the batch leaves at least 4 workgroups per CU
-    // per product; below that, 32 (more, shorter workgroups)
+    // Tile of the two FP64 products: 32 x 32 (8 waves) by default; once the
+    // batch leaves at least 4 workgroups per CU per product at 64 nodes per
+    // workgroup, 64 x 64 (4 waves), which reads each X panel half as often per
+    // node as 32 x 64 and a quarter as often as 32 x 32.
     const bool wide = Kp % 64 == 0 && std::min(ntr, pp / 32) * (Kp / 64) >= 1024;
-    const int TN = wide ? 64 : 32;
-    dim3 g1((unsigned)ntr, (unsigned)(Kp / TN), mode == 0 ? 2u : 1u);
-    dim3 g2((unsigned)(pp / 32), (unsigned)(Kp / TN));
-    prof_begin(ctx, PROF_CHECK);
-    if (wide)
-        hipLaunchKernelGGL((k_check_xr<T, 4>), g1, dim3(512), 0, s, in.X64R.as<double>(), in.ldxr, B, beta, in.ldp,
-                           pp, in.y64.as<double>(), ws.R.as<double>(), in.ldu64, ws.rpart.as<double>(), ncl);
-    else
-        hipLaunchKernelGGL((k_check_xr<T, 2>), g1, dim3(512), 0, s, in.X64R.as<double>(), in.ldxr, B, beta, in.ldp,
-                           pp, in.y64.as<double>(), ws.R.as<double>(), in.ldu64, ws.rpart.as<double>(), ncl);
     DualArgs da = dual_args(in);
     const T *bd = mode == 0 ? beta : B;
+    auto launch = [&](auto bm, auto bn, auto wv) {
+        constexpr int BM = decltype(bm)::value, BN = decltype(bn)::value, WV = decltype(wv)::value;
+        const dim3 g1((unsigned)(np / (16 * BM)), (unsigned)(Kp / (16 * BN)), mode == 0 ? 2u : 1u);
+        const dim3 g2((unsigned)(pp / (16 * BM)), (unsigned)(Kp / (16 * BN)));
+        hipLaunchKernelGGL((k_check_xr<T, BM, BN, WV>), g1, dim3(64 * WV), 0, s, in.X64R.as<double>(), in.ldxr, B,
+                           beta, in.ldp, pp, in.y64.as<double>(), ws.R.as<double>(), in.ldu64,
+                           ws.rpart.as<double>(), ncl);
+        hipLaunchKernelGGL((k_dual_xtr<T, BM, BN, WV>), g2, dim3(64 * WV), 0, s, in.X64.as<double>(), in.ldx,
+                           ws.R.as<double>(), in.ldu64, np, ws.codes.as<uint8_t>(), bd, in.colnrm.as<double>(),
+                           ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), in.ldp, da, ncl);
+    };
+    prof_begin(ctx, PROF_CHECK);
     if (wide)
-        hipLaunchKernelGGL((k_dual_xtr<T, 4>), g2, dim3(64 * kWavesDual), 0, s, in.X64.as<double>(), in.ldx,
-                           ws.R.as<double>(), in.ldu64, np, ws.codes.as<uint8_t>(), bd, in.colnrm.as<double>(),
-                           ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), in.ldp, da, ncl);
+        launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
     else
-        hipLaunchKernelGGL((k_dual_xtr<T, 2>), g2, dim3(64 * kWavesDual), 0, s, in.X64.as<double>(), in.ldx,
-                           ws.R.as<double>(), in.ldu64, np, ws.codes.as<uint8_t>(), bd, in.colnrm.as<double>(),
-                           ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), in.ldp, da, ncl);
+        launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{}, std::integral_constant<int, 8>{});
     FinArgs fa;
     const double u = 1.1102230246251565e-16;
     fa.gamma_n2 = ((double)in.n + 2.0) * u / (1.0 - ((double)in.n + 2.0) * u);
