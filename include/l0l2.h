@@ -394,7 +394,7 @@ int l0l2_server_batching_stats(l0l2_server *srv, int64_t *rounds, int64_t *block
 /* Tile shapes of the two sweep contractions (output rows x nodes / waves):
  * register tiles whose waves split the contraction range, 0 = 32x32/4,
  * 1 = 32x32/8, 2 = 32x32/16 (8 in FP64), 3 = 16x32/8, 4 = 32x16/8, 5 = 16x16/4,
- * 6 = 64x32/8, 7 = 32x64/8, 8 = 64x32/4; LDS-staged tiles (4 waves), 9 = 64x64,
+ * 6 = 64x32/8, 7 = 32x64/8, 8 = 64x64/4; LDS-staged tiles (4 waves), 9 = 64x64,
  * 10 = 128x64, 11 = 128x128; for the contraction over p only (xw_shape), the
  * range cut into slices whose partial products are then added in slice order
  * (more workgroups when n x nodes is small and p long): 12, 13, 17 = 128x128

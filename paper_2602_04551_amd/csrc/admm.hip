@@ -2448,7 +2448,7 @@ template <> constexpr int prof_xtu<double>() { return PROF_ADMM_XTU_F64; }
 // register tile (4 waves) in 4 slices.
 constexpr int kShapes = 12, kShapesXw = 18;
 constexpr int kTileTM[kShapesXw] = {32, 32, 32, 16, 32, 16, 64, 32, 64, 64, 128, 128, 128, 128, 16, 16, 32, 128};
-constexpr int kTileTN[kShapesXw] = {32, 32, 32, 32, 16, 16, 32, 64, 32, 64, 64, 128, 128, 128, 16, 16, 32, 128};
+constexpr int kTileTN[kShapesXw] = {32, 32, 32, 32, 16, 16, 32, 64, 64, 64, 64, 128, 128, 128, 16, 16, 32, 128};
 constexpr int kTileW[kShapesXw] = {4, 8, 16, 8, 8, 4, 8, 8, 4, 4, 4, 4, 4, 4, 4, 4, 4, 4};
 constexpr int kSplit[kShapesXw] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 2, 4, 4, 8, 4, 8};
 constexpr int kMaxSplit = 8;
@@ -2521,7 +2521,7 @@ void launch_xw(int v, hipStream_t s, const TA *A, int64_t lda, const TB *B, int6
         case 5: L0L2_XW(1, 1, 4); break;
         case 6: L0L2_XW(4, 2, 8); break;
         case 7: L0L2_XW(2, 4, 8); break;
-        default: L0L2_XW(4, 2, 4); break;
+        default: L0L2_XW(4, 4, 4); break;
     }
 #undef L0L2_XW
 #undef L0L2_XWL
@@ -2560,7 +2560,7 @@ void launch_xtu(int v, hipStream_t s, const Sweep<T> &sw, int64_t np, int64_t pp
         case 5: L0L2_XTU(1, 1, 4); break;
         case 6: L0L2_XTU(4, 2, 8); break;
         case 7: L0L2_XTU(2, 4, 8); break;
-        default: L0L2_XTU(4, 2, 4); break;
+        default: L0L2_XTU(4, 4, 4); break;
     }
 #undef L0L2_XTU
 #undef L0L2_XTUL
@@ -2597,7 +2597,7 @@ void launch_xtu_anch(int v, hipStream_t s, const Sweep<float> &s32, const Sweep<
         case 5: L0L2_XTUA(1, 1, 4); break;
         case 6: L0L2_XTUA(4, 2, 8); break;
         case 7: L0L2_XTUA(2, 4, 8); break;
-        default: L0L2_XTUA(4, 2, 4); break;
+        default: L0L2_XTUA(4, 4, 4); break;
     }
 #undef L0L2_XTUA
 #undef L0L2_XTUAL
