@@ -775,19 +775,21 @@ __device__ __forceinline__ void epi_load_row(EpiIn<T> (&ei)[H], int slot, int64_
     for (int h = 0; h < H; ++h) epi_load<T>(ei[h], slot, col, m0 + lane + 64 * h, ldp, W, V, codes, c, active);
 }
 
-// The node rows of a wave's epilogue pass, t = 0 .. T - 1 (T even): the
-// operands of row t + 1 are loaded (load(row, t + 1)) before row t is updated
-// (update(row, t)), so their latency overlaps that row's work instead of being
-// paid row by row.
-template <class Row, class Load, class Update>
+// The node rows of a wave's epilogue pass, t = 0 .. T - 1 (T a multiple of D):
+// the operands of rows t + 1 .. t + D - 1 are loaded (load(row, t')) before row
+// t is updated (update(row, t)), so their latency overlaps D - 1 rows of work
+// instead of being paid row by row.  The D rows sit in a ring of registers
+// indexed with compile-time constants.
+template <class Row, int D = 2, class Load, class Update>
 __device__ __forceinline__ void rows_pipelined(int T, Load &&load, Update &&update) {
-    Row ra, rb;
-    load(ra, 0);
-    for (int t = 0; t < T; t += 2) {
-        load(rb, t + 1);
-        update(ra, t);
-        if (t + 2 < T) load(ra, t + 2);
-        update(rb, t + 1);
+    Row ring[D];
+    sfor<D - 1>([&](auto i) { load(ring[decltype(i)::value], decltype(i)::value); });
+    for (int t = 0; t < T; t += D) {
+        sfor<D>([&](auto i) {
+            constexpr int k = decltype(i)::value, nxt = (k + D - 1) % D;
+            if (t + k + D - 1 < T) load(ring[nxt], t + k + D - 1);
+            update(ring[k], t + k);
+        });
     }
 }
 
@@ -1510,8 +1512,8 @@ __global__ __launch_bounds__(256, (WM > 4 ? 1 : 2)) void k_admm_xtu_bf16s_lds(
                 }
             }
         };
-        static_assert((PN / 4) % 2 == 0, "rows per wave in pairs");
-        rows_pipelined<Row>(PN / 4, load_row, update_row);
+        static_assert((PN / 4) % 4 == 0, "rows per wave in fours");
+        rows_pipelined<Row, 4>(PN / 4, load_row, update_row);
     }
 }
 
