@@ -3411,29 +3411,37 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     const int64_t ntr = np / 32;
     NodeCols ncl{nullptr};
     if (mode == 0) ncl = gated ? NodeCols{ws.clist.as<int>()} : active_cols(ctx);
-    // Tile of the two FP64 products: 32 x 32 (8 waves) by default; once the
-    // batch leaves at least 4 workgroups per CU per product at 64 nodes per
-    // workgroup, 64 x 64 (4 waves), which reads each X panel half as often per
-    // node as 32 x 64 and a quarter as often as 32 x 32.
-    const bool wide = Kp % 64 == 0 && std::min(ntr, pp / 32) * (Kp / 64) >= 1024;
+    // Tile of each FP64 product: 32 x 32 (8 waves) by default; once its grid
+    // has at least 4 workgroups per CU at 64 nodes per workgroup, 64 x 64 (4
+    // waves), which reads each panel of X a quarter as often per node.  The two
+    // kernels choose separately (rows n of the first, p of the second): the
+    // partial sums keep their 32-row and 32-coordinate layout either way.
+    const bool wide_xr = Kp % 64 == 0 && ntr * (Kp / 64) >= 1024;
+    const bool wide_xtr = Kp % 64 == 0 && (pp / 32) * (Kp / 64) >= 1024;
     DualArgs da = dual_args(in);
     const T *bd = mode == 0 ? beta : B;
-    auto launch = [&](auto bm, auto bn, auto wv) {
+    auto launch_xr = [&](auto bm, auto bn, auto wv) {
         constexpr int BM = decltype(bm)::value, BN = decltype(bn)::value, WV = decltype(wv)::value;
-        const dim3 g1((unsigned)(np / (16 * BM)), (unsigned)(Kp / (16 * BN)), mode == 0 ? 2u : 1u);
-        const dim3 g2((unsigned)(pp / (16 * BM)), (unsigned)(Kp / (16 * BN)));
-        hipLaunchKernelGGL((k_check_xr<T, BM, BN, WV>), g1, dim3(64 * WV), 0, s, in.X64R.as<double>(), in.ldxr, B,
+        const dim3 g((unsigned)(np / (16 * BM)), (unsigned)(Kp / (16 * BN)), mode == 0 ? 2u : 1u);
+        hipLaunchKernelGGL((k_check_xr<T, BM, BN, WV>), g, dim3(64 * WV), 0, s, in.X64R.as<double>(), in.ldxr, B,
                            beta, in.ldp, pp, in.y64.as<double>(), ws.R.as<double>(), in.ldu64,
                            ws.rpart.as<double>(), ncl);
-        hipLaunchKernelGGL((k_dual_xtr<T, BM, BN, WV>), g2, dim3(64 * WV), 0, s, in.X64.as<double>(), in.ldx,
+    };
+    auto launch_xtr = [&](auto bm, auto bn, auto wv) {
+        constexpr int BM = decltype(bm)::value, BN = decltype(bn)::value, WV = decltype(wv)::value;
+        const dim3 g((unsigned)(pp / (16 * BM)), (unsigned)(Kp / (16 * BN)));
+        hipLaunchKernelGGL((k_dual_xtr<T, BM, BN, WV>), g, dim3(64 * WV), 0, s, in.X64.as<double>(), in.ldx,
                            ws.R.as<double>(), in.ldu64, np, ws.codes.as<uint8_t>(), bd, in.colnrm.as<double>(),
                            ws.rpart.as<double>(), ntr, ws.active.as<int>(), ws.part.as<double>(), in.ldp, da, ncl);
     };
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    using I8 = std::integral_constant<int, 8>;
     prof_begin(ctx, PROF_CHECK);
-    if (wide)
-        launch(std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{}, std::integral_constant<int, 4>{});
-    else
-        launch(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{}, std::integral_constant<int, 8>{});
+    if (wide_xr) launch_xr(I4{}, I4{}, I4{});
+    else launch_xr(I2{}, I2{}, I8{});
+    if (wide_xtr) launch_xtr(I4{}, I4{}, I4{});
+    else launch_xtr(I2{}, I2{}, I8{});
     FinArgs fa;
     const double u = 1.1102230246251565e-16;
     fa.gamma_n2 = ((double)in.n + 2.0) * u / (1.0 - ((double)in.n + 2.0) * u);
