@@ -3416,8 +3416,8 @@ void check_once(l0l2_ctx *ctx, const T *B, const T *beta, int64_t Kp, double tol
     // waves), which reads each panel of X a quarter as often per node.  The two
     // kernels choose separately (rows n of the first, p of the second): the
     // partial sums keep their 32-row and 32-coordinate layout either way.
-    const bool wide_xr = Kp % 64 == 0 && ntr * (Kp / 64) >= 1024;
-    const bool wide_xtr = Kp % 64 == 0 && (pp / 32) * (Kp / 64) >= 1024;
+    const bool wide_xr = Kp % 64 == 0 && np % 64 == 0 && ntr * (Kp / 64) >= 1024;
+    const bool wide_xtr = Kp % 64 == 0 && pp % 64 == 0 && (pp / 32) * (Kp / 64) >= 1024;
     DualArgs da = dual_args(in);
     const T *bd = mode == 0 ? beta : B;
     auto launch_xr = [&](auto bm, auto bn, auto wv) {
