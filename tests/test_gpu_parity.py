@@ -136,6 +136,18 @@ def test_lds_tiles_fp32_and_anchored_match(torch_cuda, cases, shape):
     """The LDS-staged tiles in FP32 mode (plain and anchored sweeps, with the gap
     estimate's epilogue) give the same node solves as the register tiles, to
     FP32 rounding of the summation order."""
+    _fp32_shape_matches(cases, shape)
+
+
+@pytest.mark.parametrize("shape", [6, 7, 8])
+def test_large_register_tiles_fp32_and_anchored_match(torch_cuda, cases, shape):
+    """The 64 x 32, 32 x 64 and 64 x 64 register tiles in FP32 mode (both
+    contractions, plain and anchored sweeps) give the same node solves as the
+    32 x 32 register tile, to FP32 rounding of the summation order."""
+    _fp32_shape_matches(cases, shape)
+
+
+def _fp32_shape_matches(cases, shape):
     inst, o, root = cases["wide"]
     K = 128
     codes, beta0, v0 = random_nodes(inst.p, K, 13, root["beta"], root["v"])
